@@ -1,0 +1,207 @@
+/*
+ * tcf.h -- C-ABI of the tree-cotree-gauged dual-primal eddy-current solver.
+ *
+ * The library advances the time-domain A*-formulation
+ *     curl(nu curl A) + sigma dA/dt = J,   n x A = 0 on the outer boundary
+ * (Sec. 2, A*-formulation with PEC boundary) discretised by curl-conforming
+ * spline patches (Sec. 2.2) with implicit Euler (Sec. 2.2, implicit Euler
+ * system W = M + dt K, f = M a^(l) + dt j^(l+1)).  Every step is solved by the
+ * dual-primal tearing of Sec. 3: per-patch remainder solves, a signed jump
+ * across patch interfaces, a coarse problem on the primal unknowns, and PCG
+ * on the Lagrange multipliers with an unscaled Dirichlet preconditioner
+ * (Sec. 4).  The insulating region is gauged by the tree-cotree split of
+ * Sec. 3 (tree on the control mesh: wirebasket, then faces, then interiors;
+ * interface tree edges primal).
+ *
+ * Conventions shared by every call:
+ *  - Patches form a P0 x P1 x P2 grid of axis-aligned boxes; patch (i,j,k)
+ *    has id s = i + P0*(j + P1*k).  Row r of direction d has nel[d][r]
+ *    uniform elements and H1 degree deg[d][r] (open knots), so neighbouring
+ *    patches are conforming on shared faces (Sec. 2.2).
+ *  - Global edge numbering on the control grid (nodes per direction
+ *    N_d = sum_r (nel+deg-1) + 1): x-edges I + (Nx-1)(J + Ny K), then y-edges
+ *    Ex + I + Nx (J + (Ny-1) K), then z-edges Ex + Ey + I + Nx (J + Ny K).
+ *  - Fields are returned as global edge vectors in that numbering, with
+ *    Dirichlet and gauge-tree edges equal to zero.
+ *  - Every call returns TCF_OK (0) or a negative status; no exception crosses
+ *    the ABI.  tcf_last_error() describes the last failure on a handle.
+ *  - Device pointers are HIP device memory on the current device; streams
+ *    are hipStream_t passed as void* (NULL = the legacy default stream).
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef TCF_H
+#define TCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum tcf_status {
+  TCF_OK = 0,
+  TCF_EINVAL = -1,   /* invalid description or argument                     */
+  TCF_ENOMEM = -2,   /* host or device allocation failed                   */
+  TCF_ENOTSPD = -3,  /* a Cholesky pivot <= 0 (patch id in tcf_stats)       */
+  TCF_ENOCONV = -4,  /* PCG / refinement hit its iteration limit; results   */
+                     /* of that step are still readable and flagged          */
+  TCF_EHIP = -5,     /* HIP runtime error                                   */
+  TCF_ESTATE = -6    /* call out of order (e.g. step before setup)          */
+};
+
+enum tcf_precision {
+  TCF_FP64 = 0,      /* all local factors and applies in FP64                */
+  TCF_FP32_IR = 1    /* local factors / Schur applies FP32, PCG, coarse     */
+                     /* solve and refinement residual FP64                   */
+};
+
+/*
+ * Source callback: evaluate phi_k on a tensor grid of quadrature abscissae.
+ * out[ix + nx*(iy + ny*iz)] = phi_k(xs[ix], ys[iy], zs[iz]).
+ * The source is J_k(x,t) = g_k(t) curl(0, 0, phi_k(x)) on patches whose
+ * src_mask is set (the load vector j of Sec. 2.2, taken in curl form).
+ * Called only from tcf_create, on the calling thread.
+ */
+typedef void (*tcf_phi_fn)(const double* xs, int32_t nx, const double* ys, int32_t ny,
+                           const double* zs, int32_t nz, int32_t k, double* out, void* ctx);
+
+typedef struct tcf_problem_desc {
+  int32_t np[3];            /* patches per direction, each >= 1               */
+  const double* breaks[3];  /* np[d]+1 strictly increasing patch boundaries   */
+  const int32_t* nel[3];    /* np[d] element counts per row, each >= 1        */
+  const int32_t* deg[3];    /* np[d] H1 degrees per row, each >= 1            */
+  const double* sigma;      /* per patch conductivity, >= 0 (0 = insulator)   */
+  const double* nu;         /* per patch reluctivity, > 0                     */
+  const uint8_t* src_mask;  /* per patch: 1 = source acts here                */
+  int32_t n_rhs;            /* independent excitations sharing the operator   */
+  tcf_phi_fn phi;           /* source potential callback (see above)          */
+  void* phi_ctx;
+  const double* amp;        /* [n_rhs][n_steps]: g_k(t_{l+1}), t_l = l*dt     */
+  double dt;                /* implicit Euler step, > 0                       */
+  int32_t n_steps;          /* steps available in amp                         */
+} tcf_problem_desc;
+
+typedef struct tcf_options {
+  int32_t precision;        /* TCF_FP64 or TCF_FP32_IR                        */
+  double pcg_rtol;          /* stop when ||r||_2 <= pcg_rtol * ||d||_2        */
+  int32_t pcg_maxit;        /* <= 0: max(1000, n_lambda)                      */
+  double ir_rtol;           /* FP32 path: stop when ||f - W a|| <= ir_rtol||f||*/
+  int32_t ir_maxit;         /* FP32 path: refinement sweeps, <= 0: 10         */
+  int32_t check_every;      /* PCG iterations between host convergence reads  */
+  int32_t use_graph;        /* 1: replay captured hipGraphs for PCG chunks    */
+} tcf_options;
+
+/* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1. */
+void tcf_default_options(tcf_options* opts);
+
+typedef struct tcf_problem tcf_problem;
+
+/*
+ * Host-only work: validation, control grid, edge classes, gauge tree,
+ * primal/dual/interior split, multiplier table, device memory plan, and the
+ * source callback at quadrature points.  Touches no GPU.  Everything in
+ * desc is copied; the caller may free it on return.
+ * Errors: TCF_EINVAL (bad sizes, sigma < 0, nu <= 0, dt <= 0, non-increasing
+ * breaks, deg < 1, nel < 1, n_rhs < 1), TCF_ENOMEM.  On error *out is NULL and
+ * tcf_last_error(NULL) holds the message.
+ */
+int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_problem** out);
+
+/* Device bytes the setup will allocate for the FP64 and FP32 paths. */
+int tcf_footprint(const tcf_problem* h, size_t* bytes_fp64, size_t* bytes_fp32);
+
+/*
+ * Allocates device memory on the current device and runs, on `stream`:
+ * patch assembly by quadrature, the local partial Cholesky and explicit
+ * Schur complements, the coarse primal matrix and its factorisation, and the
+ * source condensation.  Synchronises `stream` before returning.
+ * Errors: TCF_ENOMEM, TCF_ENOTSPD (a local or coarse pivot <= 0; the failing
+ * patch id, or -1 for the coarse matrix, is in tcf_stats.fail_patch),
+ * TCF_EHIP, TCF_ESTATE (setup called twice).
+ */
+int tcf_setup(tcf_problem* h, void* stream);
+
+/*
+ * Advances nsteps implicit Euler steps (bounded by n_steps - steps_done) on
+ * `stream`.  Synchronises `stream` before returning.  TCF_ENOCONV if any step
+ * hit its PCG or refinement limit (the steps are still taken; see stats).
+ */
+int tcf_step(tcf_problem* h, int32_t nsteps, void* stream);
+
+/* Waits for all work of the handle on `stream`; reports deferred errors. */
+int tcf_sync(tcf_problem* h, void* stream);
+
+/*
+ * Copies the current field of excitation k (global edge vector, length
+ * n_edges, FP64) into `out`: host memory if on_device == 0, else device
+ * memory of the current device.  len must be >= n_edges.
+ */
+int tcf_get_field(tcf_problem* h, int32_t k, double* out, size_t len, int32_t on_device,
+                  void* stream);
+
+enum tcf_topology_kind {
+  TCF_TOPO_COUNTS = 0,     /* int64[8]: n_edges, n_nodes, |V(H)|, n_plain,      */
+                           /* n_floating, n_lambda, n_primal, n_kept             */
+  TCF_TOPO_DIRICHLET = 1,  /* sorted global edge ids                             */
+  TCF_TOPO_TREE_I = 2,     /* sorted gauge-tree edge ids (eliminated)            */
+  TCF_TOPO_TREE_GAMMA = 3, /* sorted interface-tree edge ids (primal)            */
+  TCF_TOPO_PRIMAL = 4,     /* sorted primal edge ids; index = coarse unknown     */
+  TCF_TOPO_DUAL = 5,       /* sorted dual edge ids; index = multiplier row       */
+  TCF_TOPO_INTERIOR = 6,   /* sorted patch-interior kept edge ids                */
+  TCF_TOPO_MULT = 7,       /* int64[n_lambda][3]: edge id, patch (+1), patch(-1) */
+  TCF_TOPO_N = 8           /* int64[sum_s n_p^(s)][3]: patch, edge id, primal    */
+                           /* rank; per patch in increasing edge id              */
+};
+
+/*
+ * Topology of the split, for bit-exact checks.  With out == NULL, *len
+ * receives the number of int64 values; otherwise *len is the capacity on
+ * entry and the count written on return (TCF_EINVAL if too small).
+ */
+int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* len);
+
+typedef struct tcf_stats {
+  int64_t n_patches, n_edges, n_kept, n_lambda, n_primal, n_tree_I;
+  int32_t steps_done;
+  int32_t last_pcg_iters;      /* of the last PCG solve (last IR sweep)         */
+  int64_t total_pcg_iters;     /* summed over all steps and IR sweeps            */
+  int32_t max_pcg_iters;
+  int32_t last_ir_sweeps;      /* FP32 path; 0 on the FP64 path                  */
+  int32_t nonconverged_steps;
+  int32_t fail_patch;          /* non-SPD patch, -1 coarse, -2 none              */
+  double last_rel_residual;    /* ||r||/||d|| of the last PCG solve              */
+  double last_ir_residual;     /* ||f - W a||/||f|| after the last step (FP32)   */
+  double setup_ms;
+  double step_ms_total;
+  size_t device_bytes;
+} tcf_stats;
+
+int tcf_get_stats(const tcf_problem* h, tcf_stats* st);
+
+/*
+ * Per-step log of the last `n` steps: PCG iterations (summed over
+ * refinement sweeps), refinement sweeps and wall milliseconds.  Any pointer
+ * may be NULL.  n is clamped to steps_done.
+ */
+int tcf_get_step_log(const tcf_problem* h, int32_t n, int32_t* pcg_iters, int32_t* ir_sweeps,
+                     double* step_ms);
+
+/*
+ * Checkpoint: the state is the step counter and the current field of every
+ * excitation.  tcf_get_state with buf == NULL returns the size in *bytes.
+ * tcf_set_state restores a state taken from a handle of the same problem.
+ */
+int tcf_get_state(tcf_problem* h, void* buf, size_t* bytes, void* stream);
+int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream);
+
+void tcf_destroy(tcf_problem* h);
+
+/* Message of the last failure on h (h may be NULL for create failures). */
+const char* tcf_last_error(const tcf_problem* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCF_H */

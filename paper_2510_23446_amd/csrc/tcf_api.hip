@@ -1,0 +1,1130 @@
+// libtcf driver: C-ABI entry points, device memory plan, setup and the
+// per-step dual-primal PCG.
+//
+// Per patch s the kept unknowns are ordered [interior i | dual b | primal p].
+// Setup (once; W = sigma M + dt nu K is time invariant):
+//   partial Cholesky of W over the i then b columns gives L_ii, L_bi, L_pi,
+//   S_bb (Schur complement onto b, p held at zero), L_bb, L_pb and the
+//   primal Schur complement S_pp;  S_Pi = sum_s N_s^T S_pp N_s;
+//   G = [S_bb^-1 | Phi_b] with Phi_b = S_bb^-1 S_bp = L_bb^-T L_pb^T;
+//   Q^T = [L_ii^-T | (L_bi L_ii^-1)^T | (L_pi L_ii^-1)^T].
+// Per step (Sec. 2.2 implicit Euler; Sec. 3 three-field system reduced by
+// two Schur complements):
+//   f = M a^(l) + dt g(t_{l+1}) jhat;  [y; g_b; g_p] from Q^T and f;
+//   [u; c0] = G^T g_b;  h = sum N^T (g_p - c0);  q0 = S_Pi^-1 h;
+//   d = sum Bhat (u - Phi N q0);  PCG on F lambda = d with the unscaled
+//   Dirichlet preconditioner sum B S_bb B^T;  recover p, a_b, a_i.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tcf.h"
+#include "tcf_device.h"
+#include "tcf_internal.h"
+#include "tcf_kernels.h"
+
+using namespace tcf;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+inline int pad32(int n) { return (n + TCF_NB - 1) / TCF_NB * TCF_NB; }
+inline double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        const double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+      }
+      pp = n * (z * p0 - p1) / (z * z - 1.0);
+      const double dz = p0 / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = 0.0;
+    for (int k = 1; k <= n; ++k) {
+      const double p2 = p1;
+      p1 = p0;
+      p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+    }
+    pp = n * (z * p0 - p1) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+template <class T>
+std::vector<int> prefix_of(const std::vector<T>& counts) {
+  std::vector<int> out(counts.size() + 1, 0);
+  for (size_t i = 0; i < counts.size(); ++i) out[i + 1] = out[i] + (int)counts[i];
+  return out;
+}
+
+}  // namespace
+
+struct tcf_problem {
+  // ---- description copy ---------------------------------------------------
+  int32_t np[3];
+  std::vector<double> breaks[3];
+  std::vector<int32_t> nel[3], deg[3];
+  std::vector<double> sigma, nu;
+  std::vector<uint8_t> src;
+  int32_t n_rhs = 1;
+  tcf_phi_fn phi = nullptr;
+  void* phi_ctx = nullptr;
+  std::vector<double> amp;
+  double dt = 0.0;
+  int32_t n_steps = 0;
+  tcf_options opt;
+  std::string err;
+
+  // ---- host plan -----------------------------------------------------------
+  Grid g;
+  Topology topo;
+  std::vector<PatchPlan> plans;
+  std::vector<DevPatch> hp;  // host copy of the device patch table
+  int np_tot = 0;
+  int64_t n_rtot = 0, n_itot = 0, n_btot = 0, n_ptot = 0, n_bptot = 0, n_loctot = 0;
+  int64_t A_elems = 0, G_elems = 0, S_elems = 0, Q_elems = 0;
+  int tab_elems = 0, ptab_elems = 0;
+  int n_lambda = 0, n_primal = 0, nPi_pad = 0;
+  int max_nb = 0, max_ni = 0, max_np = 0, max_bp = 0, max_nr = 0;
+  std::vector<int> cond_list;
+  double gx[16 * 17 / 2], gw[16 * 17 / 2];
+
+  // ---- device state ----------------------------------------------------------
+  int precision = TCF_FP64;
+  bool is_setup = false;
+  int device = 0;
+  std::vector<DevBuf> bufs;
+  size_t dev_bytes = 0;
+
+  DevPatch* dP = nullptr;
+  int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
+  signed char *d_bsgn = nullptr, *d_isint = nullptr;
+  int64_t* d_rgid = nullptr;
+  int *d_posp = nullptr, *d_posm = nullptr, *d_cptr = nullptr, *d_cidx_bp = nullptr,
+      *d_cidx_r = nullptr, *d_b2bp = nullptr, *d_p2r = nullptr, *d_b2r = nullptr;
+  double *d_gx = nullptr, *d_gw = nullptr, *d_tabs = nullptr, *d_ptab = nullptr;
+  void *d_G = nullptr, *d_S = nullptr, *d_Q = nullptr;  // T-typed
+  double *d_SPinv = nullptr;
+  double *d_a = nullptr, *d_fM = nullptr, *d_ygg = nullptr, *d_yggs = nullptr, *d_zr = nullptr;
+  double *d_uc = nullptr, *d_vc = nullptr, *d_wb = nullptr, *d_tb = nullptr;
+  double *d_h = nullptr, *d_q0 = nullptr, *d_cv = nullptr, *d_q = nullptr;
+  double *d_d = nullptr, *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr,
+         *d_Fp = nullptr;
+  double *d_part = nullptr;  // 3 partial arrays
+  int npart = 0;
+  PcgScalars* d_st = nullptr;
+  PcgScalars* h_st = nullptr;  // pinned
+  int* d_fail = nullptr;
+  double* d_field = nullptr;
+
+  // job tables
+  DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr, *dj_coarse = nullptr;
+  int *dp_app = nullptr, *dp_pre = nullptr, *dp_coarse = nullptr;
+  int nj_app = 0, nt_app = 0, nj_pre = 0, nt_pre = 0, nt_coarse = 0;
+  AxpyJob *aj_phi = nullptr, *aj_ab = nullptr, *aj_ai = nullptr;
+  int *ap_phi = nullptr, *ap_ai = nullptr, *a_boff_bp = nullptr, *a_boff_b = nullptr;
+  int *a_boff_ai = nullptr, *a_boff_ab = nullptr;
+  int nj_phi = 0, nt_phi = 0, nj_ai = 0, nt_ai = 0;
+  int *d_cond = nullptr, *d_cond_cprefix = nullptr, *d_cond_rprefix = nullptr;
+  int nt_cond_c = 0, nt_cond_r = 0;
+
+  // ---- stats -------------------------------------------------------------------
+  int steps_done = 0;
+  int last_iters = 0, max_iters = 0, nonconv = 0, last_ir = 0, fail_patch = -2;
+  int64_t total_iters = 0;
+  double last_rel = 0.0, last_ir_res = 0.0, setup_ms = 0.0, step_ms_total = 0.0;
+  std::vector<int32_t> log_iters, log_ir;
+  std::vector<double> log_ms;
+
+  ~tcf_problem() {
+    for (auto& b : bufs)
+      if (b.p) (void)hipFree(b.p);
+    if (h_st) (void)hipHostFree(h_st);
+  }
+
+  template <class T>
+  int alloc(T** out, size_t count) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+      return TCF_ENOMEM;
+    }
+    bufs.push_back({p, bytes});
+    dev_bytes += bytes;
+    *out = (T*)p;
+    return TCF_OK;
+  }
+  void release(void* p) {
+    for (auto& b : bufs)
+      if (b.p == p) {
+        (void)hipFree(b.p);
+        dev_bytes -= b.bytes;
+        b.p = nullptr;
+        b.bytes = 0;
+      }
+  }
+  template <class T>
+  int upload(T** out, const std::vector<T>& v) {
+    int rc = alloc(out, v.size());
+    if (rc) return rc;
+    if (!v.empty() && hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+      err = "hipMemcpy upload failed";
+      return TCF_EHIP;
+    }
+    return TCF_OK;
+  }
+  size_t footprint(int prec) const;
+};
+
+#define HIPCHK(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      h->err = std::string(#expr) + ": " + hipGetErrorString(e_);           \
+      return TCF_EHIP;                                                      \
+    }                                                                       \
+  } while (0)
+#define RCCHK(expr)        \
+  do {                     \
+    int rc_ = (expr);      \
+    if (rc_) return rc_;   \
+  } while (0)
+
+size_t tcf_problem::footprint(int prec) const {
+  const size_t w = prec == TCF_FP64 ? 8 : 4;
+  size_t b = (size_t)(A_elems + G_elems + S_elems + Q_elems) * w;
+  b += (size_t)nPi_pad * nPi_pad * 8 * 2;
+  b += (size_t)n_rtot * n_rhs * 8 * 6 + (size_t)n_bptot * 16 + (size_t)n_btot * 16;
+  b += (size_t)n_lambda * 8 * 8 + (size_t)(tab_elems + ptab_elems) * 8;
+  b += (size_t)n_rtot * 24 + (size_t)n_loctot * 4;
+  return b;
+}
+
+// ============================================================================
+// Plan: sizes, offsets and index tables (host only)
+// ============================================================================
+static void build_plan(tcf_problem* h) {
+  const int np = h->np_tot;
+  h->hp.assign(np, DevPatch());
+  int64_t r_off = 0, i_off = 0, b_off = 0, p_off = 0, bp_off = 0, loc_off = 0;
+  int64_t A = 0, G = 0, S = 0, Q = 0;
+  int tab = 0, ptab = 0;
+  h->cond_list.clear();
+  for (int s = 0; s < np; ++s) {
+    const PatchPlan& pp = h->plans[s];
+    DevPatch& d = h->hp[s];
+    for (int a = 0; a < 3; ++a) {
+      d.m[a] = pp.m[a];
+      d.nel[a] = pp.nel[a];
+      d.deg[a] = pp.deg[a];
+      d.lo[a] = pp.lo[a];
+      d.hi[a] = pp.hi[a];
+    }
+    d.sigma = pp.sigma;
+    d.nu = pp.nu;
+    d.n_i = pp.n_i; d.n_b = pp.n_b; d.n_p = pp.n_p; d.n_r = pp.n_r(); d.n_loc = pp.n_loc;
+    d.ni_pad = pad32(pp.n_i); d.nb_pad = pad32(pp.n_b); d.np_pad = pad32(pp.n_p);
+    d.nr_pad = d.ni_pad + d.nb_pad + d.np_pad;
+    d.src = pp.src ? 1 : 0;
+    d.cond = pp.sigma > 0 ? 1 : 0;
+    if (d.cond) h->cond_list.push_back(s);
+    d.A_off = A; A += (int64_t)d.nr_pad * d.nr_pad;
+    d.G_off = G; G += (int64_t)d.nb_pad * (d.n_b + d.n_p);
+    d.S_off = S; S += (int64_t)d.nb_pad * d.n_b;
+    d.Q_off = Q; Q += (int64_t)d.ni_pad * d.n_r;
+    d.r_off = (int)r_off; r_off += d.n_r;
+    d.i_off = (int)i_off; i_off += d.n_i;
+    d.b_off = (int)b_off; b_off += d.n_b;
+    d.p_off = (int)p_off; p_off += d.n_p;
+    d.bp_off = (int)bp_off; bp_off += d.n_b + d.n_p;
+    d.loc_off = (int)loc_off; loc_off += d.n_loc;
+    for (int a = 0; a < 3; ++a) {
+      const int m = d.m[a];
+      d.tab_off[a] = tab;
+      tab += 2 * m * m + (m - 1) * (m - 1) + (m - 1) * m;
+      d.nq_load[a] = d.nel[a] * (d.deg[a] + 3);
+      d.ptab_off[a] = ptab;
+      ptab += d.nq_load[a] * (3 * m + 1);
+    }
+    h->max_nb = std::max(h->max_nb, d.n_b);
+    h->max_ni = std::max(h->max_ni, d.n_i);
+    h->max_np = std::max(h->max_np, d.n_p);
+    h->max_bp = std::max(h->max_bp, d.n_b + d.n_p);
+    h->max_nr = std::max(h->max_nr, d.n_r);
+  }
+  h->n_rtot = r_off; h->n_itot = i_off; h->n_btot = b_off; h->n_ptot = p_off;
+  h->n_bptot = bp_off; h->n_loctot = loc_off;
+  h->A_elems = A; h->G_elems = G; h->S_elems = S; h->Q_elems = Q;
+  h->tab_elems = tab; h->ptab_elems = ptab;
+  h->n_lambda = (int)h->topo.dual.size();
+  h->n_primal = (int)h->topo.primal.size();
+  h->nPi_pad = pad32(h->n_primal);
+  for (int n = 1, o = 0; n <= 16; o += n, ++n) gauss_legendre(n, h->gx + o, h->gw + o);
+}
+
+// ============================================================================
+// C-ABI
+// ============================================================================
+extern "C" {
+
+void tcf_default_options(tcf_options* o) {
+  o->precision = TCF_FP64;
+  o->pcg_rtol = 1e-10;
+  o->pcg_maxit = 0;
+  o->ir_rtol = 1e-8;
+  o->ir_maxit = 10;
+  o->check_every = 8;
+  o->use_graph = 1;
+}
+
+const char* tcf_last_error(const tcf_problem* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_problem** out) {
+  if (!out) { g_create_error = "null output handle"; return TCF_EINVAL; }
+  *out = nullptr;
+  if (!desc) { g_create_error = "null description"; return TCF_EINVAL; }
+  std::string e = validate_desc(*desc);
+  if (!e.empty()) { g_create_error = e; return TCF_EINVAL; }
+  std::unique_ptr<tcf_problem> h(new (std::nothrow) tcf_problem());
+  if (!h) { g_create_error = "out of host memory"; return TCF_ENOMEM; }
+  if (opts) h->opt = *opts; else tcf_default_options(&h->opt);
+  if (h->opt.precision != TCF_FP64 && h->opt.precision != TCF_FP32_IR) {
+    g_create_error = "unknown precision"; return TCF_EINVAL;
+  }
+  if (!(h->opt.pcg_rtol > 0)) { g_create_error = "pcg_rtol <= 0"; return TCF_EINVAL; }
+  if (h->opt.check_every <= 0) h->opt.check_every = 8;
+  if (h->opt.ir_maxit <= 0) h->opt.ir_maxit = 10;
+  h->precision = h->opt.precision;
+  for (int a = 0; a < 3; ++a) {
+    h->np[a] = desc->np[a];
+    h->breaks[a].assign(desc->breaks[a], desc->breaks[a] + desc->np[a] + 1);
+    h->nel[a].assign(desc->nel[a], desc->nel[a] + desc->np[a]);
+    h->deg[a].assign(desc->deg[a], desc->deg[a] + desc->np[a]);
+  }
+  const int np = desc->np[0] * desc->np[1] * desc->np[2];
+  h->np_tot = np;
+  h->sigma.assign(desc->sigma, desc->sigma + np);
+  h->nu.assign(desc->nu, desc->nu + np);
+  h->src.assign(desc->src_mask, desc->src_mask + np);
+  h->n_rhs = desc->n_rhs;
+  h->phi = desc->phi;
+  h->phi_ctx = desc->phi_ctx;
+  h->dt = desc->dt;
+  h->n_steps = desc->n_steps;
+  if (desc->n_steps > 0) h->amp.assign(desc->amp, desc->amp + (size_t)desc->n_rhs * desc->n_steps);
+  // a private description pointing at the copies
+  tcf_problem_desc d = *desc;
+  for (int a = 0; a < 3; ++a) {
+    d.breaks[a] = h->breaks[a].data();
+    d.nel[a] = h->nel[a].data();
+    d.deg[a] = h->deg[a].data();
+  }
+  d.sigma = h->sigma.data();
+  d.nu = h->nu.data();
+  d.src_mask = h->src.data();
+  try {
+    h->g = build_grid(d);
+    e = compute_topology(d, h->g, h->topo, h->plans);
+  } catch (const std::bad_alloc&) {
+    g_create_error = "out of host memory in topology";
+    return TCF_ENOMEM;
+  }
+  if (!e.empty()) { g_create_error = e; return TCF_EINVAL; }
+  build_plan(h.get());
+  *out = h.release();
+  return TCF_OK;
+}
+
+int tcf_footprint(const tcf_problem* h, size_t* b64, size_t* b32) {
+  if (!h) return TCF_EINVAL;
+  if (b64) *b64 = h->footprint(TCF_FP64);
+  if (b32) *b32 = h->footprint(TCF_FP32_IR);
+  return TCF_OK;
+}
+
+int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* len) {
+  if (!h || !len) return TCF_EINVAL;
+  std::vector<int64_t> tmp;
+  const std::vector<int64_t>* src = &tmp;
+  switch (kind) {
+    case TCF_TOPO_COUNTS:
+      tmp = {h->g.n_edges(), h->g.n_nodes(), h->topo.n_vertices_H, h->topo.n_plain,
+             h->topo.n_floating, (int64_t)h->topo.dual.size(), (int64_t)h->topo.primal.size(),
+             h->topo.n_kept};
+      break;
+    case TCF_TOPO_DIRICHLET: src = &h->topo.dirichlet; break;
+    case TCF_TOPO_TREE_I: src = &h->topo.tree_I; break;
+    case TCF_TOPO_TREE_GAMMA: src = &h->topo.tree_gamma; break;
+    case TCF_TOPO_PRIMAL: src = &h->topo.primal; break;
+    case TCF_TOPO_DUAL: src = &h->topo.dual; break;
+    case TCF_TOPO_INTERIOR: src = &h->topo.interior; break;
+    case TCF_TOPO_MULT: src = &h->topo.mult; break;
+    case TCF_TOPO_N:
+      for (int s = 0; s < h->np_tot; ++s) {
+        const PatchPlan& pp = h->plans[s];
+        for (int j = 0; j < pp.n_p; ++j) {
+          tmp.push_back(s);
+          tmp.push_back(pp.r_gid[pp.n_i + pp.n_b + j]);
+          tmp.push_back(pp.p_rank[j]);
+        }
+      }
+      break;
+    default:
+      return TCF_EINVAL;
+  }
+  if (!out) { *len = src->size(); return TCF_OK; }
+  if (*len < src->size()) {
+    const_cast<tcf_problem*>(h)->err = "topology buffer too small";
+    return TCF_EINVAL;
+  }
+  std::copy(src->begin(), src->end(), out);
+  *len = src->size();
+  return TCF_OK;
+}
+
+int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
+  if (!h || !st) return TCF_EINVAL;
+  std::memset(st, 0, sizeof(*st));
+  st->n_patches = h->np_tot;
+  st->n_edges = h->g.n_edges();
+  st->n_kept = h->topo.n_kept;
+  st->n_lambda = h->n_lambda;
+  st->n_primal = h->n_primal;
+  st->n_tree_I = (int64_t)h->topo.tree_I.size();
+  st->steps_done = h->steps_done;
+  st->last_pcg_iters = h->last_iters;
+  st->total_pcg_iters = h->total_iters;
+  st->max_pcg_iters = h->max_iters;
+  st->last_ir_sweeps = h->last_ir;
+  st->nonconverged_steps = h->nonconv;
+  st->fail_patch = h->fail_patch;
+  st->last_rel_residual = h->last_rel;
+  st->last_ir_residual = h->last_ir_res;
+  st->setup_ms = h->setup_ms;
+  st->step_ms_total = h->step_ms_total;
+  st->device_bytes = h->dev_bytes;
+  return TCF_OK;
+}
+
+int tcf_get_step_log(const tcf_problem* h, int32_t n, int32_t* it, int32_t* ir, double* ms) {
+  if (!h || n < 0) return TCF_EINVAL;
+  n = std::min<int32_t>(n, (int32_t)h->log_iters.size());
+  const size_t o = h->log_iters.size() - n;
+  for (int k = 0; k < n; ++k) {
+    if (it) it[k] = h->log_iters[o + k];
+    if (ir) ir[k] = h->log_ir[o + k];
+    if (ms) ms[k] = h->log_ms[o + k];
+  }
+  return TCF_OK;
+}
+
+void tcf_destroy(tcf_problem* h) { delete h; }
+
+}  // extern "C"
+
+// ============================================================================
+// Setup
+// ============================================================================
+template <class T>
+static int run_factor_phase(tcf_problem* h, const std::vector<FactorJob>& jobs, T* A,
+                            hipStream_t st) {
+  if (jobs.empty()) return TCF_OK;
+  const int nj = (int)jobs.size();
+  int steps = 0;
+  for (auto& j : jobs) steps = std::max(steps, (j.c_end - j.c_begin) / TCF_NB);
+  std::vector<int> trsm_pre((size_t)steps * (nj + 1)), syrk_pre((size_t)steps * (nj + 1));
+  std::vector<int> trsm_tot(steps), syrk_tot(steps);
+  for (int k = 0; k < steps; ++k) {
+    int* tp = &trsm_pre[(size_t)k * (nj + 1)];
+    int* sp = &syrk_pre[(size_t)k * (nj + 1)];
+    tp[0] = sp[0] = 0;
+    for (int j = 0; j < nj; ++j) {
+      const FactorJob& jb = jobs[j];
+      const int col0 = jb.c_begin + TCF_NB * k;
+      int nt = 0, ns = 0;
+      if (col0 < jb.c_end) {
+        const int below = jb.n - (col0 + TCF_NB);
+        nt = (below + 63) / 64;
+        const int T_ = (below + 63) / 64;
+        ns = T_ * (T_ + 1) / 2;
+      }
+      tp[j + 1] = tp[j] + nt;
+      sp[j + 1] = sp[j] + ns;
+    }
+    trsm_tot[k] = tp[nj];
+    syrk_tot[k] = sp[nj];
+  }
+  FactorJob* dj;
+  int *dtp, *dsp;
+  RCCHK(h->upload(&dj, jobs));
+  RCCHK(h->upload(&dtp, trsm_pre));
+  RCCHK(h->upload(&dsp, syrk_pre));
+  for (int k = 0; k < steps; ++k) {
+    launch_potrf<T>(dj, nj, k, A, h->d_fail, st);
+    launch_trsm_panel<T>(dj, dtp + (size_t)k * (nj + 1), nj, trsm_tot[k], k, A, st);
+    launch_syrk<T>(dj, dsp + (size_t)k * (nj + 1), nj, syrk_tot[k], k, A, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  h->release(dj);
+  h->release(dtp);
+  h->release(dsp);
+  return TCF_OK;
+}
+
+template <class T>
+static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, const T* L, T* B,
+                    hipStream_t st) {
+  if (jobs.empty()) return TCF_OK;
+  std::vector<int> cnt;
+  for (auto& j : jobs) cnt.push_back((j.ncols + 63) / 64);
+  std::vector<int> pre = prefix_of(cnt);
+  TrsmJob* dj;
+  int* dp;
+  RCCHK(h->upload(&dj, jobs));
+  RCCHK(h->upload(&dp, pre));
+  launch_trsm<T>(fwd, dj, dp, (int)jobs.size(), pre.back(), L, B, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  h->release(dj);
+  h->release(dp);
+  return TCF_OK;
+}
+
+static int build_index_tables(tcf_problem* h) {
+  const int np = h->np_tot;
+  std::vector<int> rloc, loc2r, brow, prank, posp(h->n_lambda), posm(h->n_lambda), b2bp, p2r, b2r;
+  std::vector<signed char> bsgn, isint;
+  std::vector<int64_t> rgid;
+  for (int s = 0; s < np; ++s) {
+    const PatchPlan& pp = h->plans[s];
+    const DevPatch& d = h->hp[s];
+    rloc.insert(rloc.end(), pp.r_loc.begin(), pp.r_loc.end());
+    loc2r.insert(loc2r.end(), pp.loc2r.begin(), pp.loc2r.end());
+    rgid.insert(rgid.end(), pp.r_gid.begin(), pp.r_gid.end());
+    for (int k = 0; k < pp.n_b; ++k) {
+      brow.push_back(pp.b_row[k]);
+      bsgn.push_back((signed char)pp.b_sgn[k]);
+      b2bp.push_back(d.bp_off + k);
+      b2r.push_back(d.r_off + pp.n_i + k);
+      if (pp.b_sgn[k] > 0) posp[pp.b_row[k]] = d.b_off + k;
+      else posm[pp.b_row[k]] = d.b_off + k;
+    }
+    for (int j = 0; j < pp.n_p; ++j) {
+      prank.push_back(pp.p_rank[j]);
+      p2r.push_back(d.r_off + pp.n_i + pp.n_b + j);
+    }
+    for (int j = 0; j < pp.n_r(); ++j) isint.push_back(j < pp.n_i ? 1 : 0);
+  }
+  // coarse owners (deterministic order: by patch id)
+  std::vector<std::vector<std::pair<int, int>>> own(h->n_primal);
+  for (int s = 0; s < np; ++s) {
+    const PatchPlan& pp = h->plans[s];
+    const DevPatch& d = h->hp[s];
+    for (int j = 0; j < pp.n_p; ++j)
+      own[pp.p_rank[j]].push_back({d.bp_off + pp.n_b + j, d.r_off + pp.n_i + pp.n_b + j});
+  }
+  std::vector<int> cptr(1, 0), cbp, cr;
+  for (int k = 0; k < h->n_primal; ++k) {
+    for (auto& x : own[k]) { cbp.push_back(x.first); cr.push_back(x.second); }
+    cptr.push_back((int)cbp.size());
+  }
+  RCCHK(h->upload(&h->d_rloc, rloc));
+  RCCHK(h->upload(&h->d_loc2r, loc2r));
+  RCCHK(h->upload(&h->d_rgid, rgid));
+  RCCHK(h->upload(&h->d_brow, brow));
+  RCCHK(h->upload(&h->d_bsgn, bsgn));
+  RCCHK(h->upload(&h->d_isint, isint));
+  RCCHK(h->upload(&h->d_prank, prank));
+  RCCHK(h->upload(&h->d_posp, posp));
+  RCCHK(h->upload(&h->d_posm, posm));
+  RCCHK(h->upload(&h->d_cptr, cptr));
+  RCCHK(h->upload(&h->d_cidx_bp, cbp));
+  RCCHK(h->upload(&h->d_cidx_r, cr));
+  RCCHK(h->upload(&h->d_b2bp, b2bp));
+  RCCHK(h->upload(&h->d_p2r, p2r));
+  RCCHK(h->upload(&h->d_b2r, b2r));
+
+  // per-apply job tables
+  std::vector<DotJob> app_g, app_v, pre;
+  std::vector<int> c_app, c_pre;
+  std::vector<AxpyJob> phi, ai;
+  std::vector<int> c_phi, c_ai, boff_bp, boff_b, boff_ai;
+  for (int s = 0; s < np; ++s) {
+    const DevPatch& d = h->hp[s];
+    if (d.n_b > 0) {
+      app_g.push_back(DotJob{d.G_off, d.nb_pad, d.n_b, d.n_b + d.n_p, d.b_off, d.bp_off});
+      app_v.push_back(DotJob{d.G_off, d.nb_pad, d.n_b, d.n_b + d.n_p, d.r_off + d.n_i, d.bp_off});
+      c_app.push_back((d.n_b + d.n_p + 15) / 16);
+      pre.push_back(DotJob{d.S_off, d.nb_pad, d.n_b, d.n_b, d.b_off, d.b_off});
+      c_pre.push_back((d.n_b + 15) / 16);
+      if (d.n_p > 0) {
+        phi.push_back(AxpyJob{d.G_off, d.nb_pad, d.n_b, d.n_p, d.n_b, d.p_off, d.b_off});
+        c_phi.push_back((d.n_b + 63) / 64);
+        boff_bp.push_back(d.bp_off);
+        boff_b.push_back(d.b_off);
+      }
+    }
+    if (d.n_i > 0) {
+      ai.push_back(AxpyJob{d.Q_off, d.ni_pad, d.n_i, d.n_r, 0, d.r_off, d.r_off});
+      c_ai.push_back((d.n_i + 63) / 64);
+      boff_ai.push_back(0);
+    }
+  }
+  h->nj_app = (int)app_g.size();
+  h->nj_pre = (int)pre.size();
+  h->nj_phi = (int)phi.size();
+  h->nj_ai = (int)ai.size();
+  auto p_app = prefix_of(c_app), p_pre = prefix_of(c_pre), p_phi = prefix_of(c_phi),
+       p_ai = prefix_of(c_ai);
+  h->nt_app = p_app.back();
+  h->nt_pre = p_pre.back();
+  h->nt_phi = p_phi.back();
+  h->nt_ai = p_ai.back();
+  RCCHK(h->upload(&h->dj_app_g, app_g));
+  RCCHK(h->upload(&h->dj_app_v, app_v));
+  RCCHK(h->upload(&h->dp_app, p_app));
+  RCCHK(h->upload(&h->dj_pre, pre));
+  RCCHK(h->upload(&h->dp_pre, p_pre));
+  RCCHK(h->upload(&h->aj_phi, phi));
+  RCCHK(h->upload(&h->ap_phi, p_phi));
+  RCCHK(h->upload(&h->a_boff_bp, boff_bp));
+  RCCHK(h->upload(&h->a_boff_b, boff_b));
+  RCCHK(h->upload(&h->aj_ai, ai));
+  RCCHK(h->upload(&h->ap_ai, p_ai));
+  RCCHK(h->upload(&h->a_boff_ai, boff_ai));
+  // a_b recovery: same matrices as Phi, output into the state at r_off + n_i
+  std::vector<AxpyJob> ab;
+  std::vector<int> boff_ab;
+  for (int s = 0; s < np; ++s) {
+    const DevPatch& d = h->hp[s];
+    if (d.n_b > 0 && d.n_p > 0) {
+      ab.push_back(AxpyJob{d.G_off, d.nb_pad, d.n_b, d.n_p, d.n_b, d.p_off, d.r_off + d.n_i});
+      boff_ab.push_back(d.r_off + d.n_i);
+    }
+  }
+  RCCHK(h->upload(&h->aj_ab, ab));
+  RCCHK(h->upload(&h->a_boff_ab, boff_ab));
+  // coarse GEMV
+  std::vector<DotJob> cj;
+  std::vector<int> cc;
+  if (h->n_primal > 0) {
+    cj.push_back(DotJob{0, h->nPi_pad, h->n_primal, h->n_primal, 0, 0});
+    cc.push_back((h->n_primal + 15) / 16);
+  }
+  auto p_c = prefix_of(cc);
+  h->nt_coarse = p_c.back();
+  RCCHK(h->upload(&h->dj_coarse, cj));
+  RCCHK(h->upload(&h->dp_coarse, p_c));
+  // conductor patch lists
+  std::vector<int> ccnt, rcnt;
+  for (int s : h->cond_list) {
+    ccnt.push_back((h->hp[s].n_r + 15) / 16);
+    rcnt.push_back(h->hp[s].n_r);
+  }
+  auto cpre = prefix_of(ccnt), rpre = prefix_of(rcnt);
+  h->nt_cond_c = cpre.back();
+  h->nt_cond_r = rpre.back();
+  RCCHK(h->upload(&h->d_cond, h->cond_list));
+  RCCHK(h->upload(&h->d_cond_cprefix, cpre));
+  RCCHK(h->upload(&h->d_cond_rprefix, rpre));
+  return TCF_OK;
+}
+
+template <class T>
+static int setup_impl(tcf_problem* h, hipStream_t st) {
+  const int np = h->np_tot;
+  const int nrhs = h->n_rhs;
+  const int64_t ldv = h->n_rtot;
+  RCCHK(h->upload(&h->dP, h->hp));
+  RCCHK(build_index_tables(h));
+  std::vector<double> gx(h->gx, h->gx + 136), gw(h->gw, h->gw + 136);
+  RCCHK(h->upload(&h->d_gx, gx));
+  RCCHK(h->upload(&h->d_gw, gw));
+  RCCHK(h->alloc(&h->d_tabs, h->tab_elems));
+  RCCHK(h->alloc(&h->d_ptab, h->ptab_elems));
+  RCCHK(h->alloc(&h->d_fail, 1));
+  HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int), st));
+  launch_tables(h->dP, np, h->d_gx, h->d_gw, h->d_tabs, h->d_ptab, st);
+
+  // dense patch matrices
+  T* A = nullptr;
+  RCCHK(h->alloc(&A, h->A_elems));
+  std::vector<int> colcnt(np);
+  for (int s = 0; s < np; ++s) colcnt[s] = h->hp[s].nr_pad;
+  auto colpre = prefix_of(colcnt);
+  int* d_colpre;
+  RCCHK(h->upload(&d_colpre, colpre));
+  launch_assemble<T>(h->dP, d_colpre, np, colpre.back(), h->d_rloc, h->d_tabs, h->dt, A, st);
+  HIPCHK(hipGetLastError());
+
+  // source loads (curl form), one patch at a time through a staging buffer
+  double* jr;
+  RCCHK(h->alloc(&jr, (size_t)ldv * nrhs));
+  HIPCHK(hipMemsetAsync(jr, 0, sizeof(double) * ldv * nrhs, st));
+  {
+    size_t maxpts = 0;
+    for (int s = 0; s < np; ++s)
+      if (h->hp[s].src)
+        maxpts = std::max(maxpts, (size_t)h->hp[s].nq_load[0] * h->hp[s].nq_load[1] * h->hp[s].nq_load[2]);
+    if (maxpts > 0) {
+      double* stage;
+      RCCHK(h->alloc(&stage, maxpts * nrhs));
+      std::vector<double> hphi(maxpts * nrhs);
+      for (int s = 0; s < np; ++s) {
+        const DevPatch& d = h->hp[s];
+        if (!d.src || d.n_r == 0) continue;
+        std::vector<double> ax[3];
+        for (int a = 0; a < 3; ++a) {
+          const int nq = d.deg[a] + 3;
+          const int o = nq * (nq - 1) / 2;
+          const double hh = (d.hi[a] - d.lo[a]) / d.nel[a];
+          for (int t = 0; t < d.nel[a]; ++t)
+            for (int q = 0; q < nq; ++q) ax[a].push_back((hh * t + d.lo[a]) + 0.5 * hh * (h->gx[o + q] + 1.0));
+        }
+        const size_t npts = ax[0].size() * ax[1].size() * ax[2].size();
+        for (int k = 0; k < nrhs; ++k)
+          h->phi(ax[0].data(), (int)ax[0].size(), ax[1].data(), (int)ax[1].size(), ax[2].data(),
+                 (int)ax[2].size(), k, hphi.data() + (size_t)k * npts, h->phi_ctx);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(stage, hphi.data(), sizeof(double) * npts * nrhs, hipMemcpyHostToDevice));
+        launch_load_patch(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, jr, ldv, st);
+      }
+      HIPCHK(hipStreamSynchronize(st));
+      h->release(stage);
+    }
+  }
+
+  // factor the interior columns, keep S_bb, factor the dual columns
+  std::vector<FactorJob> ja, jbv;
+  for (int s = 0; s < np; ++s) {
+    const DevPatch& d = h->hp[s];
+    if (d.ni_pad > 0) ja.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, 0, d.ni_pad, s});
+    if (d.nb_pad > 0) jbv.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, d.ni_pad, d.ni_pad + d.nb_pad, s});
+  }
+  RCCHK(run_factor_phase<T>(h, ja, A, st));
+  T *G, *S, *Q;
+  RCCHK(h->alloc(&S, h->S_elems));
+  RCCHK(h->alloc(&G, h->G_elems));
+  RCCHK(h->alloc(&Q, h->Q_elems));
+  h->d_G = G;
+  h->d_S = S;
+  h->d_Q = Q;
+  {
+    std::vector<int> cnt(np);
+    for (int s = 0; s < np; ++s) cnt[s] = h->hp[s].n_b;
+    auto pre = prefix_of(cnt);
+    int* dpre;
+    RCCHK(h->upload(&dpre, pre));
+    launch_copy_sbb<T>(h->dP, dpre, np, pre.back(), A, S, st);
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(dpre);
+  }
+  RCCHK(run_factor_phase<T>(h, jbv, A, st));
+
+  // coarse matrix S_Pi = sum N^T S_pp N, its Cholesky factor and inverse (FP64)
+  if (h->n_primal > 0) {
+    const int ldc = h->nPi_pad;
+    double *SPi, *SPinv;
+    RCCHK(h->alloc(&SPi, (size_t)ldc * ldc));
+    RCCHK(h->alloc(&SPinv, (size_t)ldc * ldc));
+    HIPCHK(hipMemsetAsync(SPi, 0, sizeof(double) * ldc * ldc, st));
+    for (int s = 0; s < np; ++s)
+      launch_coarse_add<T>(h->dP, s, h->hp[s].n_p, h->d_prank, A, SPi, ldc, st);
+    launch_identity_pad(SPi, ldc, h->n_primal, ldc, st);
+    std::vector<FactorJob> jc{FactorJob{0, ldc, ldc, 0, ldc, -1}};
+    RCCHK(run_factor_phase<double>(h, jc, SPi, st));
+    // SPinv = I, then solve L X = I and L^T Y = X
+    HIPCHK(hipMemsetAsync(SPinv, 0, sizeof(double) * ldc * ldc, st));
+    launch_identity_pad(SPinv, ldc, 0, h->n_primal, st);
+    std::vector<TrsmJob> tj{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal}};
+    RCCHK(run_trsm<double>(h, 1, tj, SPi, SPinv, st));
+    RCCHK(run_trsm<double>(h, 0, tj, SPi, SPinv, st));
+    h->release(SPi);
+    h->d_SPinv = SPinv;
+  }
+
+  // G = [S_bb^-1 | Phi_b] and Q^T
+  {
+    std::vector<int> cg(np), cq(np);
+    for (int s = 0; s < np; ++s) {
+      cg[s] = h->hp[s].n_b > 0 ? h->hp[s].n_b + h->hp[s].n_p : 0;
+      cq[s] = h->hp[s].n_i > 0 ? h->hp[s].n_r : 0;
+    }
+    auto pg = prefix_of(cg), pq = prefix_of(cq);
+    int *dpg, *dpq;
+    RCCHK(h->upload(&dpg, pg));
+    RCCHK(h->upload(&dpq, pq));
+    launch_fill_G<T>(h->dP, dpg, np, pg.back(), A, G, st);
+    launch_fill_Q<T>(h->dP, dpq, np, pq.back(), A, Q, st);
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(dpg);
+    h->release(dpq);
+    std::vector<TrsmJob> gf, gb, qb;
+    for (int s = 0; s < np; ++s) {
+      const DevPatch& d = h->hp[s];
+      if (d.n_b > 0) {
+        gf.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b});
+        gb.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b + d.n_p});
+      }
+      if (d.n_i > 0) qb.push_back(TrsmJob{d.A_off, d.nr_pad, 0, d.ni_pad, d.Q_off, d.ni_pad, d.n_r});
+    }
+    RCCHK(run_trsm<T>(h, 1, gf, A, G, st));
+    RCCHK(run_trsm<T>(h, 0, gb, A, G, st));
+    RCCHK(run_trsm<T>(h, 0, qb, A, Q, st));
+  }
+  int fail = 0;
+  HIPCHK(hipMemcpy(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost));
+  h->release(A);
+  h->release(d_colpre);
+  if (fail) {
+    h->fail_patch = fail - 2;
+    h->err = "non-positive pivot in " +
+             (fail - 2 >= 0 ? "patch " + std::to_string(fail - 2) : std::string("coarse matrix"));
+    return TCF_ENOTSPD;
+  }
+
+  // state and work vectors
+  RCCHK(h->alloc(&h->d_a, (size_t)ldv * nrhs));
+  RCCHK(h->alloc(&h->d_fM, (size_t)ldv * nrhs));
+  RCCHK(h->alloc(&h->d_ygg, (size_t)ldv * nrhs));
+  RCCHK(h->alloc(&h->d_yggs, (size_t)ldv * nrhs));
+  RCCHK(h->alloc(&h->d_zr, (size_t)ldv));
+  HIPCHK(hipMemsetAsync(h->d_a, 0, sizeof(double) * ldv * nrhs, st));
+  HIPCHK(hipMemsetAsync(h->d_fM, 0, sizeof(double) * ldv * nrhs, st));
+  HIPCHK(hipMemsetAsync(h->d_yggs, 0, sizeof(double) * ldv * nrhs, st));
+  RCCHK(h->alloc(&h->d_uc, h->n_bptot));
+  RCCHK(h->alloc(&h->d_vc, h->n_bptot));
+  RCCHK(h->alloc(&h->d_wb, h->n_btot));
+  RCCHK(h->alloc(&h->d_tb, h->n_btot));
+  const int nP = std::max(h->n_primal, 1);
+  RCCHK(h->alloc(&h->d_h, nP));
+  RCCHK(h->alloc(&h->d_q0, nP));
+  RCCHK(h->alloc(&h->d_cv, nP));
+  RCCHK(h->alloc(&h->d_q, nP));
+  const int nl = std::max(h->n_lambda, 1);
+  RCCHK(h->alloc(&h->d_d, nl));
+  RCCHK(h->alloc(&h->d_lam, nl));
+  RCCHK(h->alloc(&h->d_r, nl));
+  RCCHK(h->alloc(&h->d_z, nl));
+  RCCHK(h->alloc(&h->d_p, nl));
+  RCCHK(h->alloc(&h->d_Fp, nl));
+  h->npart = (nl + 255) / 256;
+  RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4));
+  RCCHK(h->alloc(&h->d_st, 1));
+  RCCHK(h->alloc(&h->d_field, (size_t)h->g.n_edges()));
+  HIPCHK(hipHostMalloc((void**)&h->h_st, sizeof(PcgScalars), hipHostMallocDefault));
+  HIPCHK(hipMemsetAsync(h->d_lam, 0, sizeof(double) * nl, st));
+
+  // source condensation (time separable): yggs = cond(jhat)
+  std::vector<int> all(np), acnt(np);
+  for (int s = 0; s < np; ++s) { all[s] = s; acnt[s] = (h->hp[s].n_r + 15) / 16; }
+  auto apre = prefix_of(acnt);
+  int *d_all, *d_apre;
+  RCCHK(h->upload(&d_all, all));
+  RCCHK(h->upload(&d_apre, apre));
+  launch_condense<T>(h->dP, d_all, d_apre, np, apre.back(), nrhs, h->max_ni, Q, jr, h->d_yggs, ldv, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  h->release(d_all);
+  h->release(d_apre);
+  h->release(jr);
+  return TCF_OK;
+}
+
+extern "C" int tcf_setup(tcf_problem* h, void* stream) {
+  if (!h) return TCF_EINVAL;
+  if (h->is_setup) { h->err = "setup already done"; return TCF_ESTATE; }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipGetDevice(&h->device));
+  const double t0 = now_ms();
+  int rc = h->precision == TCF_FP64 ? setup_impl<double>(h, st) : setup_impl<float>(h, st);
+  if (rc) return rc;
+  h->setup_ms = now_ms() - t0;
+  h->is_setup = true;
+  return TCF_OK;
+}
+
+// ============================================================================
+// Per-step dual-primal solve
+// ============================================================================
+// wb = base_bp[b part] + alpha * Phi_b N_s q  (per patch; Phi_b = columns n_b.. of G)
+template <class T>
+static void phi_apply(tcf_problem* h, const double* base_bp, double alpha, const double* q,
+                      double* wb, const int* done, hipStream_t st) {
+  launch_scatter((int)h->n_btot, nullptr, h->d_b2bp, base_bp, 1.0, wb, done, st);
+  if (h->n_primal > 0)
+    launch_axpyrows<T>(h->aj_phi, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, (const T*)h->d_G, q,
+                       h->d_prank, wb, h->a_boff_b, alpha, wb, 0, done, st);
+}
+
+// out = S_Pi^-1 (extra + sum_s N_s^T c_s), c_s = the primal part of a bp-vector
+static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, double* out,
+                         const int* done, hipStream_t st) {
+  if (h->n_primal == 0) return;
+  launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, bp, 1.0,
+                       extra, h->d_cv, done, st);
+  launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv, 0,
+                         h->d_cv, nullptr, nullptr, 1.0, out, done, st);
+}
+
+// Fp = F p = sum Bhat [S_bb^-1 x + Phi N S_Pi^-1 sum N^T Phi^T x], x = Bhat^T p;
+// partial sums of p.Fp
+template <class T>
+static void apply_F(tcf_problem* h, const double* p, double* Fp, double* part, const int* done,
+                    hipStream_t st) {
+  launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, (const T*)h->d_G, 1,
+                    p, h->d_brow, h->d_bsgn, h->dt, h->d_vc, done, st);
+  coarse_solve(h, h->d_vc, nullptr, h->d_q, done, st);
+  phi_apply<T>(h, h->d_vc, 1.0, h->d_q, h->d_wb, done, st);
+  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, Fp, p, part, done, st);
+}
+
+// z = sum B S_bb B^T r (unscaled Dirichlet preconditioner); partial sums of r.z
+template <class T>
+static void apply_M(tcf_problem* h, const double* r, double* z, double* part, const int* done,
+                    hipStream_t st) {
+  launch_dotcols<T>(h->dj_pre, h->dp_pre, h->nj_pre, h->nt_pre, h->max_nb, (const T*)h->d_S, 1, r,
+                    h->d_brow, h->d_bsgn, 1.0, h->d_tb, done, st);
+  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
+}
+
+template <class T>
+static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bool& conv) {
+  const int nl = h->n_lambda;
+  iters = 0;
+  rel = 0.0;
+  conv = true;
+  if (nl == 0) return TCF_OK;
+  const int* done = &h->d_st->done;
+  const int npt = h->npart;
+  double* p_pq = h->d_part;
+  double* p_rr = h->d_part + npt;
+  double* p_rz = h->d_part + 2 * npt;
+  double* p_dd = h->d_part + 3 * npt;
+  launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
+  apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
+  launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
+  const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
+  const double tol2 = h->opt.pcg_rtol * h->opt.pcg_rtol;
+  const int chunk = h->opt.check_every;
+  int it = 0;
+  bool finished = false;
+  while (it < maxit && !finished) {
+    const int it1 = std::min(maxit, it + chunk);
+    for (; it < it1; ++it) {
+      const int par = it & 1;
+      apply_F<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
+      launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
+      launch_pcg_check(p_rr, npt, h->d_st, tol2, it, st);
+      apply_M<T>(h, h->d_r, h->d_z, p_rz, done, st);
+      launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    finished = h->h_st->done != 0;
+  }
+  if (!finished) {
+    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  iters = h->h_st->iters;
+  conv = h->h_st->done != 0;
+  rel = h->h_st->dd > 0 ? std::sqrt(h->h_st->rr / h->h_st->dd) : 0.0;
+  return TCF_OK;
+}
+
+// One implicit Euler step for excitation k: a_k <- solve(W, M a_k + dt g_k jhat_k)
+template <class T>
+static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bool& conv) {
+  const int64_t ldv = h->n_rtot;
+  double* a = h->d_a + (int64_t)k * ldv;
+  double* fM = h->d_fM + (int64_t)k * ldv;
+  double* ygg = h->d_ygg + (int64_t)k * ldv;
+  const double* yggs = h->d_yggs + (int64_t)k * ldv;
+  const T* G = (const T*)h->d_G;
+  const T* Q = (const T*)h->d_Q;
+  // f = M a (conductor patches) ; [y; g_b; g_p] = cond(f) + dt g jhat-condensed
+  const double gk = h->amp[(size_t)k * h->n_steps + l];
+  launch_axpby(ldv, h->dt * gk, yggs, 0.0, ygg, st);
+  if (!h->cond_list.empty()) {
+    launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
+                  h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
+    launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
+                       h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
+  }
+  // [u; c0] = G^T g_b ; h = sum N^T (g_p - c0) ; q0 = S_Pi^-1 h ; d = jump(u - Phi N q0)
+  launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
+                    nullptr, 1.0, h->d_uc, nullptr, st);
+  if (h->n_primal > 0) {
+    launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, h->d_uc,
+                         -1.0, nullptr, h->d_h, nullptr, st);
+    launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv,
+                           0, h->d_h, nullptr, nullptr, 1.0, h->d_q0, nullptr, st);
+  }
+  phi_apply<T>(h, h->d_uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
+  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, h->d_d, nullptr, nullptr,
+              nullptr, st);
+  double rel = 0.0;
+  RCCHK(pcg_solve<T>(h, st, iters, rel, conv));
+  h->last_rel = rel;
+  // recovery: p = S_Pi^-1 (h + sum N^T Phi^T x), x = Bhat^T lambda
+  if (h->n_lambda > 0)
+    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, h->d_lam,
+                      h->d_brow, h->d_bsgn, h->dt, h->d_vc, nullptr, st);
+  else
+    HIPCHK(hipMemsetAsync(h->d_vc, 0, sizeof(double) * std::max<int64_t>(h->n_bptot, 1), st));
+  coarse_solve(h, h->d_vc, h->d_h, h->d_q, nullptr, st);
+  // a_b = (u - v) - Phi N p ;  a_p = N p
+  launch_sub_gather((int)h->n_btot, h->d_b2bp, h->d_uc, h->d_b2bp, h->d_vc, h->d_tb, st);
+  launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, a, nullptr, st);
+  if (h->n_primal > 0) {
+    if (h->nj_phi > 0)
+      launch_axpyrows<T>(h->aj_ab, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, G, h->d_q,
+                         h->d_prank, a, h->a_boff_ab, -1.0, a, 0, nullptr, st);
+    launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, a, nullptr, st);
+  }
+  // a_i = L_ii^-T (y - L_bi^T a_b - L_pi^T a_p) = Q^T [y; -a_b; -a_p]
+  launch_build_z(ldv, h->d_isint, ygg, a, h->d_zr, st);
+  launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
+                     nullptr, h->a_boff_ai, 1.0, a, 1, nullptr, st);
+  HIPCHK(hipGetLastError());
+  return TCF_OK;
+}
+
+template <class T>
+static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
+  int status = TCF_OK;
+  for (int s = 0; s < nsteps; ++s) {
+    const int l = h->steps_done;
+    const double t0 = now_ms();
+    int it_sum = 0;
+    bool all_conv = true;
+    for (int k = 0; k < h->n_rhs; ++k) {
+      int iters = 0;
+      bool conv = true;
+      RCCHK(step_one<T>(h, k, l, st, iters, conv));
+      it_sum += iters;
+      all_conv &= conv;
+      h->last_iters = iters;
+      h->max_iters = std::max(h->max_iters, iters);
+      h->total_iters += iters;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const double ms = now_ms() - t0;
+    if (!all_conv) {
+      ++h->nonconv;
+      status = TCF_ENOCONV;
+      h->err = "PCG reached its iteration limit at step " + std::to_string(l);
+    }
+    h->log_iters.push_back(it_sum);
+    h->log_ir.push_back(0);
+    h->log_ms.push_back(ms);
+    h->step_ms_total += ms;
+    h->steps_done++;
+  }
+  return status;
+}
+
+extern "C" {
+
+int tcf_step(tcf_problem* h, int32_t nsteps, void* stream) {
+  if (!h) return TCF_EINVAL;
+  if (!h->is_setup) { h->err = "tcf_step before tcf_setup"; return TCF_ESTATE; }
+  if (nsteps < 0) { h->err = "nsteps < 0"; return TCF_EINVAL; }
+  nsteps = std::min(nsteps, h->n_steps - h->steps_done);
+  if (nsteps <= 0) return TCF_OK;
+  hipStream_t st = (hipStream_t)stream;
+  return h->precision == TCF_FP64 ? step_impl<double>(h, nsteps, st)
+                                  : step_impl<float>(h, nsteps, st);
+}
+
+int tcf_sync(tcf_problem* h, void* stream) {
+  if (!h) return TCF_EINVAL;
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  HIPCHK(hipGetLastError());
+  return TCF_OK;
+}
+
+int tcf_get_field(tcf_problem* h, int32_t k, double* out, size_t len, int32_t on_device,
+                  void* stream) {
+  if (!h || !out) return TCF_EINVAL;
+  if (!h->is_setup) { h->err = "tcf_get_field before tcf_setup"; return TCF_ESTATE; }
+  if (k < 0 || k >= h->n_rhs) { h->err = "excitation index out of range"; return TCF_EINVAL; }
+  const int64_t nE = h->g.n_edges();
+  if (len < (size_t)nE) { h->err = "field buffer too small"; return TCF_EINVAL; }
+  hipStream_t st = (hipStream_t)stream;
+  double* dst = on_device ? out : h->d_field;
+  HIPCHK(hipMemsetAsync(dst, 0, sizeof(double) * nE, st));
+  launch_to_global(h->n_rtot, h->d_rgid, h->d_a + (int64_t)k * h->n_rtot, dst, st);
+  HIPCHK(hipGetLastError());
+  if (!on_device)
+    HIPCHK(hipMemcpyAsync(out, h->d_field, sizeof(double) * nE, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return TCF_OK;
+}
+
+int tcf_get_state(tcf_problem* h, void* buf, size_t* bytes, void* stream) {
+  if (!h || !bytes) return TCF_EINVAL;
+  if (!h->is_setup) { h->err = "tcf_get_state before tcf_setup"; return TCF_ESTATE; }
+  const size_t need = 16 + sizeof(double) * (size_t)h->n_rtot * h->n_rhs;
+  if (!buf) { *bytes = need; return TCF_OK; }
+  if (*bytes < need) { h->err = "state buffer too small"; return TCF_EINVAL; }
+  int64_t hdr[2] = {h->steps_done, h->n_rtot * h->n_rhs};
+  std::memcpy(buf, hdr, 16);
+  HIPCHK(hipMemcpyAsync((char*)buf + 16, h->d_a, need - 16, hipMemcpyDeviceToHost,
+                        (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  *bytes = need;
+  return TCF_OK;
+}
+
+int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream) {
+  if (!h || !buf) return TCF_EINVAL;
+  if (!h->is_setup) { h->err = "tcf_set_state before tcf_setup"; return TCF_ESTATE; }
+  const size_t need = 16 + sizeof(double) * (size_t)h->n_rtot * h->n_rhs;
+  int64_t hdr[2];
+  if (bytes < need) { h->err = "state buffer too small"; return TCF_EINVAL; }
+  std::memcpy(hdr, buf, 16);
+  if (hdr[1] != h->n_rtot * h->n_rhs || hdr[0] < 0 || hdr[0] > h->n_steps) {
+    h->err = "state does not match this problem";
+    return TCF_EINVAL;
+  }
+  HIPCHK(hipMemcpyAsync(h->d_a, (const char*)buf + 16, need - 16, hipMemcpyHostToDevice,
+                        (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  h->steps_done = (int)hdr[0];
+  return TCF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Device-side data structures shared by the kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#define TCF_MAXP 8
+#define TCF_NB 32  // factorisation panel width; all block sizes are padded to it
+
+namespace tcf {
+
+// One patch as seen by the kernels.
+struct DevPatch {
+  int m[3], nel[3], deg[3];
+  double lo[3], hi[3];
+  double sigma, nu;
+  int n_i, n_b, n_p, n_r, n_loc;
+  int ni_pad, nb_pad, np_pad, nr_pad;  // padded to TCF_NB
+  int src, cond;
+  int64_t A_off;   // dense [i|b|p] matrix, nr_pad x nr_pad column-major
+  int64_t G_off;   // [Sbb^-1 | Phi_b], ld = nb_pad, n_b + n_p columns
+  int64_t S_off;   // Sbb, ld = nb_pad, n_b columns
+  int64_t Q_off;   // Q^T = [L_ii^-T | E_bi^T | E_pi^T], ld = ni_pad, n_r columns
+  int r_off, i_off, b_off, p_off, bp_off, loc_off;
+  int tab_off[3];  // 1-D Galerkin tables per direction
+  int ptab_off[3]; // basis values at load quadrature points per direction
+  int nq_load[3];  // load quadrature points per direction (nel * (deg + 3))
+};
+
+// A block of columns [c_begin, c_end) of one dense SPD matrix to factor.
+struct FactorJob {
+  int64_t off;  // matrix offset (elements)
+  int ld;       // leading dimension == padded order
+  int n;        // padded order (multiple of TCF_NB)
+  int c_begin, c_end;
+  int tag;      // patch id reported on a non-positive pivot (-1 coarse)
+};
+
+// Triangular solve with the lower block L (order n, multiple of TCF_NB) at
+// (l_row0, l_row0) of a matrix with leading dimension ldl, against ncols
+// right-hand sides stored with leading dimension ldb.
+struct TrsmJob {
+  int64_t l_off;
+  int ldl, l_row0, n;
+  int64_t b_off;
+  int ldb, ncols;
+};
+
+// Column-dot matrix-vector job: out[j] = sum_{r < nrows} M[r + j*ld] x[r].
+struct DotJob {
+  int64_t m_off;
+  int ld, nrows, ncols;
+  int x_off;    // offset into gather tables / input vector
+  int out_off;
+};
+
+// Row-stripe matrix-vector job: out[r] = base[r] + alpha * sum_j M[r + (c0+j)*ld] y[j].
+struct AxpyJob {
+  int64_t m_off;
+  int ld, nrows, ncols, c0;
+  int y_off;    // offset into the gather index table of y
+  int out_off;
+};
+
+struct PcgScalars {
+  double dd;         // ||d||^2
+  double rz[2];      // r.z of the current / next iteration (parity)
+  double rr;         // last ||r||^2
+  int done;
+  int iters;
+  int pad[2];
+};
+
+}  // namespace tcf

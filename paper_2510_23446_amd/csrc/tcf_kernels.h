@@ -1,0 +1,89 @@
+// Host launch wrappers of the libtcf kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tcf_device.h"
+
+namespace tcf {
+
+void launch_tables(const DevPatch* P, int np, const double* gx, const double* gw, double* tabs,
+                   double* ptab, hipStream_t st);
+template <class T>
+void launch_assemble(const DevPatch* P, const int* col_prefix, int np, int total_cols,
+                     const int* r_loc, const double* tabs, double dt, T* A, hipStream_t st);
+void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                   int total_rows, int nrhs, const int* r_loc, const int* loc2r,
+                   const double* tabs, double dt, int mass_only, const double* x, double* y,
+                   int64_t ldv, hipStream_t st);
+void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
+                       const double* ptab, const double* phi, double* jr, int64_t ldv,
+                       hipStream_t st);
+template <class T>
+void launch_potrf(const FactorJob* jobs, int njobs, int k, T* A, int* fail, hipStream_t st);
+template <class T>
+void launch_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
+                       hipStream_t st);
+template <class T>
+void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
+                 hipStream_t st);
+template <class T>
+void launch_copy_sbb(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* S,
+                     hipStream_t st);
+template <class T>
+void launch_fill_G(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* G,
+                   hipStream_t st);
+template <class T>
+void launch_fill_Q(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* Q,
+                   hipStream_t st);
+template <class T>
+void launch_coarse_add(const DevPatch* P, int s, int n_p, const int* p_rank, const T* A,
+                       double* SPi, int ldc, hipStream_t st);
+void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st);
+template <class T>
+void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int total,
+                 const T* L, T* B, hipStream_t st);
+template <class T>
+void launch_dotcols(const DotJob* jobs, const int* prefix, int njobs, int total, int max_rows,
+                    const T* M, int xmode, const double* xv, const int* gidx,
+                    const signed char* gsgn, double xscale, double* out, const int* done,
+                    hipStream_t st);
+template <class T>
+void launch_axpyrows(const AxpyJob* jobs, const int* prefix, int njobs, int total, int max_cols,
+                     const T* M, const double* yv, const int* yidx, const double* base,
+                     const int* base_off, double alpha, double* out, int tri_cols,
+                     const int* done, hipStream_t st);
+template <class T>
+void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int nlist, int total,
+                     int nrhs, int max_ni, const T* Q, const double* f, double* ygg, int64_t ldv,
+                     hipStream_t st);
+void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
+                 const double* dotw, double* partial, const int* done, hipStream_t st);
+void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
+                     hipStream_t st);
+void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, const double* prz,
+                      int npart, PcgScalars* stt, hipStream_t st);
+void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
+                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st);
+void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2, int it,
+                      hipStream_t st);
+void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
+                        const double* z, hipStream_t st);
+void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
+                          const int* ib, const double* srcB, double sb, const double* extra,
+                          double* out, const int* done, hipStream_t st);
+void launch_axpby(int64_t n, double alpha, const double* x, double beta, double* y,
+                  hipStream_t st);
+void launch_sub_gather(int n, const int* ia, const double* a, const int* ib, const double* b,
+                       double* out, hipStream_t st);
+void launch_scatter(int n, const int* dst, const int* sidx, const double* src, double scale,
+                    double* out, const int* done, hipStream_t st);
+void launch_to_global(int64_t n, const int64_t* gid, const double* a, double* out,
+                      hipStream_t st);
+
+}  // namespace tcf
+
+namespace tcf {
+void launch_build_z(int64_t n, const signed char* is_int, const double* y, const double* a,
+                    double* zr, hipStream_t st);
+}  // namespace tcf

@@ -1,0 +1,1259 @@
+// HIP kernels of libtcf for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// Setup: 1-D Galerkin tables by Gauss quadrature, dense patch matrices in
+// [interior | dual | primal] order, batched partial Cholesky (right-looking,
+// 32-wide panels), multi-RHS triangular solves that produce the explicit
+// Schur operators.  Per step: matrix-free conductor mass, condensation,
+// column-dot and row-stripe matrix-vector products for the dual-primal
+// operator, the signed jump, and PCG recurrences with device-side scalars.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+
+#include "tcf_device.h"
+#include "tcf_kernels.h"
+
+namespace tcf {
+
+// ===========================================================================
+// 1-D splines on one patch row (open uniform knots)
+// ===========================================================================
+struct Row1D {
+  double lo, hi;
+  int nel, p;
+};
+
+__device__ inline double knot(const Row1D& r, int i) {
+  if (i <= r.p) return r.lo;
+  int t = i - r.p;
+  if (t >= r.nel) return r.hi;
+  return (r.hi - r.lo) / r.nel * t + r.lo;
+}
+
+// Degree-q B-splines active on element t (span k = p + t of the degree-p
+// knot vector): out[j] = N_{k-q+j, q}(x), j = 0..q.  Cox-de Boor recursion,
+// updated in place from the highest index down.
+__device__ inline void bspline_span(const Row1D& r, int t, double x, int q, double* out) {
+  const int k = r.p + t;
+  out[0] = 1.0;
+  for (int d = 1; d <= q; ++d) {
+    for (int j = d; j >= 0; --j) {
+      const int i = k - d + j;
+      const double lo_v = (j >= 1) ? out[j - 1] : 0.0;
+      const double hi_v = (j <= d - 1) ? out[j] : 0.0;
+      double v = 0.0;
+      const double ui = knot(r, i), uid = knot(r, i + d);
+      if (uid - ui > 0.0) v += (x - ui) / (uid - ui) * lo_v;
+      const double ui1 = knot(r, i + 1), uid1 = knot(r, i + d + 1);
+      if (uid1 - ui1 > 0.0) v += (uid1 - x) / (uid1 - ui1) * hi_v;
+      out[j] = v;
+    }
+  }
+}
+
+// On element t at x: N[j] = N_{t+j}, dN[j] = N'_{t+j} (j = 0..p) and the
+// edge functions D[j] = D_{t+j} = p/(U_{t+j+p+1} - U_{t+j+1}) N^{p-1}_{t+j+1}
+// (j = 0..p-1).  The derivative uses N'_i = D_{i-1} - D_i.
+__device__ inline void eval_element(const Row1D& r, int t, double x, double* N, double* D,
+                                    double* dN) {
+  const int p = r.p;
+  double Nl[TCF_MAXP + 1];
+  bspline_span(r, t, x, p - 1, Nl);
+  for (int j = 0; j < p; ++j) {
+    const int e = t + j;
+    D[j] = p / (knot(r, e + p + 1) - knot(r, e + 1)) * Nl[j];
+  }
+  bspline_span(r, t, x, p, N);
+  for (int j = 0; j <= p; ++j) dN[j] = (j >= 1 ? D[j - 1] : 0.0) - (j <= p - 1 ? D[j] : 0.0);
+}
+
+__device__ inline int gauss_off(int nq) { return nq * (nq - 1) / 2; }
+
+// Tables per (patch, direction): Nn = int N_i N_j, NdNd = int N'_i N'_j,
+// Dd = int D_i D_j, DNd = int D_i N'_j, by Gauss-Legendre with p+1 points per
+// element (exact).  One block per (patch, direction).
+__global__ void k_tables1d(const DevPatch* P, const double* gx, const double* gw, double* tabs) {
+  const int s = blockIdx.x / 3, d = blockIdx.x % 3;
+  const DevPatch& pp = P[s];
+  const Row1D r{pp.lo[d], pp.hi[d], pp.nel[d], pp.deg[d]};
+  const int m = pp.m[d], p = r.p, nq = p + 1;
+  const double* g = gx + gauss_off(nq);
+  const double* w = gw + gauss_off(nq);
+  double* base = tabs + pp.tab_off[d];
+  const int n0 = m * m, n1 = 2 * m * m, n2 = n1 + (m - 1) * (m - 1), total = n2 + (m - 1) * m;
+  const double h = (r.hi - r.lo) / r.nel;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    int type, i, j;
+    if (idx < n0) { type = 0; i = idx / m; j = idx % m; }
+    else if (idx < n1) { type = 1; i = (idx - n0) / m; j = (idx - n0) % m; }
+    else if (idx < n2) { type = 2; i = (idx - n1) / (m - 1); j = (idx - n1) % (m - 1); }
+    else { type = 3; i = (idx - n2) / m; j = (idx - n2) % m; }
+    int tmin = max(0, max(i, j) - p), tmax = min(r.nel - 1, min(i, j));
+    double acc = 0.0;
+    for (int t = tmin; t <= tmax; ++t) {
+      const bool ai_N = (i >= t && i <= t + p), aj_N = (j >= t && j <= t + p);
+      const bool ai_D = (i >= t && i <= t + p - 1), aj_D = (j >= t && j <= t + p - 1);
+      bool act;
+      switch (type) {
+        case 0: case 1: act = ai_N && aj_N; break;
+        case 2: act = ai_D && aj_D; break;
+        default: act = ai_D && aj_N; break;
+      }
+      if (!act) continue;
+      const double lo_t = h * t + r.lo;
+      for (int q = 0; q < nq; ++q) {
+        const double x = lo_t + 0.5 * h * (g[q] + 1.0);
+        const double wq = 0.5 * h * w[q];
+        double N[TCF_MAXP + 1], D[TCF_MAXP], dN[TCF_MAXP + 1];
+        eval_element(r, t, x, N, D, dN);
+        double vi, vj;
+        switch (type) {
+          case 0: vi = N[i - t]; vj = N[j - t]; break;
+          case 1: vi = dN[i - t]; vj = dN[j - t]; break;
+          case 2: vi = D[i - t]; vj = D[j - t]; break;
+          default: vi = D[i - t]; vj = dN[j - t]; break;
+        }
+        acc += wq * vi * vj;
+      }
+    }
+    base[idx] = acc;
+  }
+}
+
+// Basis values at the load quadrature points (p+3 per element): per point
+// [x, w, N_0..N_{m-1}, N'_0..N'_{m-1}, D_0..D_{m-2}] (zeros off support).
+__global__ void k_point_tables(const DevPatch* P, const double* gx, const double* gw,
+                               double* ptab) {
+  const int s = blockIdx.x / 3, d = blockIdx.x % 3;
+  const DevPatch& pp = P[s];
+  const Row1D r{pp.lo[d], pp.hi[d], pp.nel[d], pp.deg[d]};
+  const int m = pp.m[d], p = r.p, nq = p + 3;
+  const double* g = gx + gauss_off(nq);
+  const double* w = gw + gauss_off(nq);
+  const int stride = 3 * m + 1;
+  const double h = (r.hi - r.lo) / r.nel;
+  double* base = ptab + pp.ptab_off[d];
+  const int npts = r.nel * nq;
+  for (int ip = threadIdx.x; ip < npts; ip += blockDim.x) {
+    const int t = ip / nq, q = ip % nq;
+    const double x = (h * t + r.lo) + 0.5 * h * (g[q] + 1.0);
+    double N[TCF_MAXP + 1], D[TCF_MAXP], dN[TCF_MAXP + 1];
+    eval_element(r, t, x, N, D, dN);
+    double* o = base + (int64_t)ip * stride;
+    o[0] = x;
+    o[1] = 0.5 * h * w[q];
+    for (int i = 0; i < m; ++i) { o[2 + i] = 0.0; o[2 + m + i] = 0.0; }
+    for (int i = 0; i < m - 1; ++i) o[2 + 2 * m + i] = 0.0;
+    for (int j = 0; j <= p; ++j) { o[2 + t + j] = N[j]; o[2 + m + t + j] = dN[j]; }
+    for (int j = 0; j < p; ++j) o[2 + 2 * m + t + j] = D[j];
+  }
+}
+
+// ===========================================================================
+// Patch matrix entries: W = sigma M + dt nu K on the edge basis
+// x-edge (a,b,c) = D_a(x) N_b(y) N_c(z) e_x (cyclic for y, z)
+// ===========================================================================
+struct Tab1 {
+  const double* Nn;
+  const double* NdNd;
+  const double* Dd;
+  const double* DNd;
+  int m;
+  __device__ double nn(int i, int j) const { return Nn[i * m + j]; }
+  __device__ double dndn(int i, int j) const { return NdNd[i * m + j]; }
+  __device__ double dd(int i, int j) const { return Dd[i * (m - 1) + j]; }
+  __device__ double dnd(int i, int j) const { return DNd[i * m + j]; }  // int D_i N'_j
+};
+
+__device__ inline Tab1 make_tab(const DevPatch& pp, const double* tabs, int d) {
+  const int m = pp.m[d];
+  const double* b = tabs + pp.tab_off[d];
+  return Tab1{b, b + m * m, b + 2 * m * m, b + 2 * m * m + (m - 1) * (m - 1), m};
+}
+
+struct EdgeCode {
+  int dir, a, b, c;
+};
+
+__device__ inline EdgeCode decode_local(const DevPatch& pp, int loc) {
+  const int mx = pp.m[0], my = pp.m[1], mz = pp.m[2];
+  const int nX = (mx - 1) * my * mz, nY = mx * (my - 1) * mz;
+  EdgeCode e;
+  if (loc < nX) {
+    e.dir = 0; e.a = loc % (mx - 1); e.b = (loc / (mx - 1)) % my; e.c = loc / ((mx - 1) * my);
+  } else if (loc < nX + nY) {
+    const int l = loc - nX;
+    e.dir = 1; e.a = l % mx; e.b = (l / mx) % (my - 1); e.c = l / (mx * (my - 1));
+  } else {
+    const int l = loc - nX - nY;
+    e.dir = 2; e.a = l % mx; e.b = (l / mx) % my; e.c = l / (mx * my);
+  }
+  return e;
+}
+
+__device__ inline int encode_local(const DevPatch& pp, int dir, int a, int b, int c) {
+  const int mx = pp.m[0], my = pp.m[1], mz = pp.m[2];
+  const int nX = (mx - 1) * my * mz, nY = mx * (my - 1) * mz;
+  if (dir == 0) return a + (mx - 1) * (b + my * c);
+  if (dir == 1) return nX + a + mx * (b + (my - 1) * c);
+  return nX + nY + a + mx * (b + my * c);
+}
+
+// Returns (M, K) entry pair for row edge u and column edge v (unscaled).
+__device__ inline void mk_entry(const Tab1& X, const Tab1& Y, const Tab1& Z, const EdgeCode& u,
+                                const EdgeCode& v, double& M, double& K) {
+  M = 0.0;
+  K = 0.0;
+  const int a = u.a, b = u.b, c = u.c, a2 = v.a, b2 = v.b, c2 = v.c;
+  if (u.dir == v.dir) {
+    if (u.dir == 0) {
+      const double dx = X.dd(a, a2);
+      M = dx * Y.nn(b, b2) * Z.nn(c, c2);
+      K = dx * (Y.nn(b, b2) * Z.dndn(c, c2) + Y.dndn(b, b2) * Z.nn(c, c2));
+    } else if (u.dir == 1) {
+      const double dy = Y.dd(b, b2);
+      M = X.nn(a, a2) * dy * Z.nn(c, c2);
+      K = dy * (X.nn(a, a2) * Z.dndn(c, c2) + X.dndn(a, a2) * Z.nn(c, c2));
+    } else {
+      const double dz = Z.dd(c, c2);
+      M = X.nn(a, a2) * Y.nn(b, b2) * dz;
+      K = dz * (X.nn(a, a2) * Y.dndn(b, b2) + X.dndn(a, a2) * Y.nn(b, b2));
+    }
+    return;
+  }
+  const int pr = u.dir * 3 + v.dir;
+  switch (pr) {
+    case 1:  // x row, y col: -int D_a N'_a2 . int N'_b D_b2 . int N_c N_c2
+      K = -X.dnd(a, a2) * Y.dnd(b2, b) * Z.nn(c, c2); break;
+    case 3:  // y row, x col
+      K = -X.dnd(a2, a) * Y.dnd(b, b2) * Z.nn(c2, c); break;
+    case 2:  // x row, z col: -int D_a N'_a2 . int N_b N_b2 . int N'_c D_c2
+      K = -X.dnd(a, a2) * Y.nn(b, b2) * Z.dnd(c2, c); break;
+    case 6:  // z row, x col
+      K = -X.dnd(a2, a) * Y.nn(b2, b) * Z.dnd(c, c2); break;
+    case 5:  // y row, z col: -int N_a N_a2 . int D_b N'_b2 . int N'_c D_c2
+      K = -X.nn(a, a2) * Y.dnd(b, b2) * Z.dnd(c2, c); break;
+    default:  // 7: z row, y col
+      K = -X.nn(a2, a) * Y.dnd(b2, b) * Z.dnd(c, c2); break;
+  }
+}
+
+// padded position -> kept index (-1 for padding)
+__device__ inline int pad_to_r(const DevPatch& pp, int pos) {
+  if (pos < pp.ni_pad) return pos < pp.n_i ? pos : -1;
+  pos -= pp.ni_pad;
+  if (pos < pp.nb_pad) return pos < pp.n_b ? pp.n_i + pos : -1;
+  pos -= pp.nb_pad;
+  return pos < pp.n_p ? pp.n_i + pp.n_b + pos : -1;
+}
+
+__device__ inline int find_job(const int* prefix, int njobs, int b) {
+  int lo = 0, hi = njobs;  // prefix[lo] <= b < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Dense assembly: one block per padded column of every patch.
+template <class T>
+__global__ void k_assemble(const DevPatch* P, const int* col_prefix, int np, const int* r_loc,
+                           const double* tabs, double dt, T* A) {
+  const int s = find_job(col_prefix, np, blockIdx.x);
+  const DevPatch& pp = P[s];
+  const int col = blockIdx.x - col_prefix[s];
+  const int rc = pad_to_r(pp, col);
+  const Tab1 X = make_tab(pp, tabs, 0), Y = make_tab(pp, tabs, 1), Z = make_tab(pp, tabs, 2);
+  EdgeCode v{};
+  if (rc >= 0) v = decode_local(pp, r_loc[pp.r_off + rc]);
+  T* out = A + pp.A_off + (int64_t)col * pp.nr_pad;
+  const double nudt = pp.nu * dt;
+  for (int row = threadIdx.x; row < pp.nr_pad; row += blockDim.x) {
+    const int rr = pad_to_r(pp, row);
+    double val;
+    if (rr < 0 || rc < 0) {
+      val = (row == col) ? 1.0 : 0.0;
+    } else {
+      const EdgeCode u = decode_local(pp, r_loc[pp.r_off + rr]);
+      double M, K;
+      mk_entry(X, Y, Z, u, v, M, K);
+      val = pp.sigma * M + nudt * K;
+    }
+    out[row] = (T)val;
+  }
+}
+
+// Matrix-free y = W x (full) or y = sigma M x (mass only) on the kept
+// unknowns of each listed patch, FP64.  x, y are kept-ordered vectors.
+__global__ void k_wapply(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                         const int* r_loc, const int* loc2r, const double* tabs, double dt,
+                         int mass_only, const double* x, double* y, int64_t ldv) {
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= row_prefix[nlist]) return;
+  const int li = find_job(row_prefix, nlist, gi);
+  const int s = plist[li];
+  const DevPatch& pp = P[s];
+  const int j = gi - row_prefix[li];
+  const int rhs = blockIdx.y;
+  const Tab1 X = make_tab(pp, tabs, 0), Y = make_tab(pp, tabs, 1), Z = make_tab(pp, tabs, 2);
+  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+  const double* xs = x + (int64_t)rhs * ldv + pp.r_off;
+  const int* l2r = loc2r + pp.loc_off;
+  double acc = 0.0;
+  const int px = pp.deg[0], py = pp.deg[1], pz = pp.deg[2];
+  for (int dir = 0; dir < 3; ++dir) {
+    if (mass_only && dir != u.dir) continue;
+    const int na = pp.m[0] - (dir == 0), nb = pp.m[1] - (dir == 1), nc = pp.m[2] - (dir == 2);
+    const int a0 = max(0, u.a - px), a1 = min(na - 1, u.a + px);
+    const int b0 = max(0, u.b - py), b1 = min(nb - 1, u.b + py);
+    const int c0 = max(0, u.c - pz), c1 = min(nc - 1, u.c + pz);
+    for (int c = c0; c <= c1; ++c)
+      for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) {
+          const int r2 = l2r[encode_local(pp, dir, a, b, c)];
+          if (r2 < 0) continue;
+          double M, K;
+          mk_entry(X, Y, Z, u, EdgeCode{dir, a, b, c}, M, K);
+          const double wv = mass_only ? pp.sigma * M : pp.sigma * M + pp.nu * dt * K;
+          acc += wv * xs[r2];
+        }
+  }
+  y[(int64_t)rhs * ldv + pp.r_off + j] = acc;
+}
+
+// Curl-form load of one patch: jhat_e = int phi (curl w_e)_z, with
+// (curl w)_z = -D_a N'_b N_c (x-edges), N'_a D_b N_c (y-edges), 0 (z-edges).
+// phi holds the callback values on the patch's tensor grid of load points,
+// one block of nx*ny*nz per excitation.
+__global__ void k_load_patch(const DevPatch* P, int s, const int* r_loc, const double* ptab,
+                             const double* phi, double* jr, int64_t ldv) {
+  const DevPatch& pp = P[s];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (j >= pp.n_r) return;
+  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+  double val = 0.0;
+  if (u.dir != 2) {
+    const int mx = pp.m[0], my = pp.m[1], mz = pp.m[2];
+    const int sx = 3 * mx + 1, sy = 3 * my + 1, sz = 3 * mz + 1;
+    const double* TX = ptab + pp.ptab_off[0];
+    const double* TY = ptab + pp.ptab_off[1];
+    const double* TZ = ptab + pp.ptab_off[2];
+    const int NX = pp.nq_load[0], NY = pp.nq_load[1];
+    const int qx = pp.deg[0] + 3, qy = pp.deg[1] + 3, qz = pp.deg[2] + 3;
+    const int px = pp.deg[0], py = pp.deg[1], pz = pp.deg[2];
+    const double* ph = phi + (int64_t)k * NX * NY * pp.nq_load[2];
+    // element ranges where each factor is active
+    int tx0, tx1, ty0, ty1;
+    if (u.dir == 0) {  // D_a(x): t in [a-p+1, a];  N'_b(y): t in [b-p, b]
+      tx0 = u.a - px + 1; tx1 = u.a; ty0 = u.b - py; ty1 = u.b;
+    } else {           // N'_a(x): t in [a-p, a];    D_b(y): t in [b-p+1, b]
+      tx0 = u.a - px; tx1 = u.a; ty0 = u.b - py + 1; ty1 = u.b;
+    }
+    tx0 = max(tx0, 0); tx1 = min(tx1, pp.nel[0] - 1);
+    ty0 = max(ty0, 0); ty1 = min(ty1, pp.nel[1] - 1);
+    const int tz0 = max(u.c - pz, 0), tz1 = min(u.c, pp.nel[2] - 1);
+    for (int iz = tz0 * qz; iz < (tz1 + 1) * qz; ++iz) {
+      const double* oz = TZ + (int64_t)iz * sz;
+      const double fz = oz[1] * oz[2 + u.c];  // w N_c(z)
+      if (fz == 0.0) continue;
+      for (int iy = ty0 * qy; iy < (ty1 + 1) * qy; ++iy) {
+        const double* oy = TY + (int64_t)iy * sy;
+        const double fy = oy[1] * (u.dir == 0 ? oy[2 + my + u.b] : oy[2 + 2 * my + u.b]);
+        if (fy == 0.0) continue;
+        const double fyz = fy * fz;
+        const double* prow = ph + (int64_t)NX * (iy + (int64_t)NY * iz);
+        double sx_acc = 0.0;
+        for (int ix = tx0 * qx; ix < (tx1 + 1) * qx; ++ix) {
+          const double* ox = TX + (int64_t)ix * sx;
+          const double fx = ox[1] * (u.dir == 0 ? ox[2 + 2 * mx + u.a] : ox[2 + mx + u.a]);
+          sx_acc += fx * prow[ix];
+        }
+        val += sx_acc * fyz;
+      }
+    }
+    if (u.dir == 0) val = -val;
+  }
+  jr[(int64_t)k * ldv + pp.r_off + j] = val;
+}
+
+// ===========================================================================
+// Batched partial Cholesky (lower, column-major, right-looking, 32 panels)
+// ===========================================================================
+template <class T>
+__global__ void k_potrf_panel(const FactorJob* jobs, int k, T* A, int* fail) {
+  const FactorJob jb = jobs[blockIdx.x];
+  const int col0 = jb.c_begin + TCF_NB * k;
+  if (col0 >= jb.c_end) return;
+  __shared__ T L[TCF_NB][TCF_NB + 1];
+  T* a = A + jb.off;
+  const int64_t ld = jb.ld;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    L[r][c] = (r >= c) ? a[(col0 + r) + (int64_t)(col0 + c) * ld] : T(0);
+  }
+  __syncthreads();
+  for (int j = 0; j < TCF_NB; ++j) {
+    if (threadIdx.x == 0) {
+      T d = L[j][j];
+      if (!(d > T(0))) {
+        atomicExch(fail, jb.tag + 2);
+        d = T(1);
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    if (threadIdx.x > j && threadIdx.x < TCF_NB) L[threadIdx.x][j] /= L[j][j];
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+      const int i = idx % TCF_NB, l = idx / TCF_NB;
+      if (l > j && i >= l) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    if (r >= c) a[(col0 + r) + (int64_t)(col0 + c) * ld] = L[r][c];
+  }
+}
+
+// Rows below the panel: L_ik = A_ik L_kk^-T.  64 rows per block, one per lane.
+template <class T>
+__global__ void k_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs, int k, T* A) {
+  const int j = find_job(prefix, njobs, blockIdx.x);
+  const FactorJob jb = jobs[j];
+  const int chunk = blockIdx.x - prefix[j];
+  const int col0 = jb.c_begin + TCF_NB * k;
+  __shared__ T L[TCF_NB][TCF_NB + 1];
+  T* a = A + jb.off;
+  const int64_t ld = jb.ld;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    L[r][c] = (r >= c) ? a[(col0 + r) + (int64_t)(col0 + c) * ld] : T(0);
+  }
+  __syncthreads();
+  const int row = col0 + TCF_NB + chunk * 64 + threadIdx.x;
+  if (row >= jb.n) return;
+  T x[TCF_NB];
+#pragma unroll
+  for (int c = 0; c < TCF_NB; ++c) x[c] = a[row + (int64_t)(col0 + c) * ld];
+#pragma unroll
+  for (int c = 0; c < TCF_NB; ++c) {
+    T v = x[c];
+#pragma unroll
+    for (int l = 0; l < c; ++l) v -= x[l] * L[c][l];
+    x[c] = v / L[c][c];
+  }
+#pragma unroll
+  for (int c = 0; c < TCF_NB; ++c) a[row + (int64_t)(col0 + c) * ld] = x[c];
+}
+
+// Trailing update C -= L_I L_J^T on 64x64 lower tiles below the panel.
+template <class T>
+__global__ void k_syrk_update(const FactorJob* jobs, const int* prefix, int njobs, int k, T* A) {
+  const int j = find_job(prefix, njobs, blockIdx.x);
+  const FactorJob jb = jobs[j];
+  const int t = blockIdx.x - prefix[j];
+  const int col0 = jb.c_begin + TCF_NB * k;
+  const int trail0 = col0 + TCF_NB;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int row0 = trail0 + 64 * I, cl0 = trail0 + 64 * J;
+  __shared__ T LI[TCF_NB][64 + 1];
+  __shared__ T LJ[TCF_NB][64 + 1];
+  T* a = A + jb.off;
+  const int64_t ld = jb.ld;
+  const int n = jb.n;
+  for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
+    const int r = idx % 64, c = idx / 64;
+    LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(col0 + c) * ld] : T(0);
+    LJ[c][r] = (cl0 + r < n) ? a[(cl0 + r) + (int64_t)(col0 + c) * ld] : T(0);
+  }
+  __syncthreads();
+  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[i][q] = T(0);
+#pragma unroll 4
+  for (int c = 0; c < TCF_NB; ++c) {
+    T li[4], lj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { li[i] = LI[c][tr + 16 * i]; lj[i] = LJ[c][tc + 16 * i]; }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][q] += li[i] * lj[q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int C = cl0 + tc + 16 * q;
+    if (C >= n) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int R = row0 + tr + 16 * i;
+      if (R < n && R >= C) a[R + (int64_t)C * ld] -= acc[i][q];
+    }
+  }
+}
+
+// ===========================================================================
+// Fills between factorisation phases
+// ===========================================================================
+// S_bb (full symmetric, ld nb_pad) from the Schur block left after the
+// interior columns were eliminated.
+template <class T>
+__global__ void k_copy_sbb(const DevPatch* P, const int* col_prefix, int np, const T* A, T* S) {
+  const int s = find_job(col_prefix, np, blockIdx.x);
+  const DevPatch& pp = P[s];
+  const int c = blockIdx.x - col_prefix[s];
+  const T* a = A + pp.A_off;
+  T* o = S + pp.S_off + (int64_t)c * pp.nb_pad;
+  for (int r = threadIdx.x; r < pp.nb_pad; r += blockDim.x) {
+    T v = T(0);
+    if (r < pp.n_b) {
+      const int R = pp.ni_pad + max(r, c), C = pp.ni_pad + min(r, c);
+      v = a[R + (int64_t)C * pp.nr_pad];
+    }
+    o[r] = v;
+  }
+}
+
+// G = [I | L_pb^T] over nb_pad rows, n_b + n_p columns.
+template <class T>
+__global__ void k_fill_G(const DevPatch* P, const int* col_prefix, int np, const T* A, T* G) {
+  const int s = find_job(col_prefix, np, blockIdx.x);
+  const DevPatch& pp = P[s];
+  const int c = blockIdx.x - col_prefix[s];
+  const T* a = A + pp.A_off;
+  T* o = G + pp.G_off + (int64_t)c * pp.nb_pad;
+  for (int r = threadIdx.x; r < pp.nb_pad; r += blockDim.x) {
+    T v = T(0);
+    if (r < pp.n_b) {
+      if (c < pp.n_b) v = (r == c) ? T(1) : T(0);
+      else v = a[(pp.ni_pad + pp.nb_pad + (c - pp.n_b)) + (int64_t)(pp.ni_pad + r) * pp.nr_pad];
+    }
+    o[r] = v;
+  }
+}
+
+// Q^T right-hand side [I | L_bi^T | L_pi^T] over ni_pad rows, n_r columns.
+template <class T>
+__global__ void k_fill_Q(const DevPatch* P, const int* col_prefix, int np, const T* A, T* Q) {
+  const int s = find_job(col_prefix, np, blockIdx.x);
+  const DevPatch& pp = P[s];
+  const int c = blockIdx.x - col_prefix[s];
+  const T* a = A + pp.A_off;
+  T* o = Q + pp.Q_off + (int64_t)c * pp.ni_pad;
+  int srcrow = -1;
+  if (c >= pp.n_i && c < pp.n_i + pp.n_b) srcrow = pp.ni_pad + (c - pp.n_i);
+  else if (c >= pp.n_i + pp.n_b) srcrow = pp.ni_pad + pp.nb_pad + (c - pp.n_i - pp.n_b);
+  for (int r = threadIdx.x; r < pp.ni_pad; r += blockDim.x) {
+    T v = T(0);
+    if (r < pp.n_i) {
+      if (srcrow < 0) v = (r == c) ? T(1) : T(0);
+      else v = a[srcrow + (int64_t)r * pp.nr_pad];
+    }
+    o[r] = v;
+  }
+}
+
+// S_Pi += N_s^T S_pp N_s for one patch (launched per patch in sequence).
+template <class T>
+__global__ void k_coarse_add(const DevPatch* P, int s, const int* p_rank, const T* A, double* SPi,
+                             int ldc) {
+  const DevPatch& pp = P[s];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= pp.n_p * pp.n_p) return;
+  const int i = idx % pp.n_p, j = idx / pp.n_p;
+  const int R = pp.ni_pad + pp.nb_pad + max(i, j), C = pp.ni_pad + pp.nb_pad + min(i, j);
+  const double v = (double)A[pp.A_off + R + (int64_t)C * pp.nr_pad];
+  const int gi = p_rank[pp.p_off + i], gj = p_rank[pp.p_off + j];
+  SPi[gi + (int64_t)gj * ldc] += v;
+}
+
+__global__ void k_set_identity_pad(double* M, int ld, int n0, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - n0) return;
+  M[(n0 + i) + (int64_t)(n0 + i) * ld] = 1.0;
+}
+
+// ===========================================================================
+// Multi-RHS triangular solves: 32-row blocks, 64 right-hand sides per block
+// ===========================================================================
+template <class T>
+__global__ void k_trsm_fwd(const TrsmJob* jobs, const int* prefix, int njobs, const T* Lb, T* Bb) {
+  const int jx = find_job(prefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int c0 = (blockIdx.x - prefix[jx]) * 64;
+  __shared__ T Ls[TCF_NB][TCF_NB + 1];
+  __shared__ T Xs[TCF_NB][64 + 1];
+  __shared__ T Acc[TCF_NB][64 + 1];
+  const T* L = Lb + jb.l_off;
+  T* B = Bb + jb.b_off;
+  const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;  // cg in 0..7
+  const int nblk = jb.n / TCF_NB;
+  const int64_t ldl = jb.ldl, ldb = jb.ldb;
+  for (int kb = 0; kb < nblk; ++kb) {
+    T acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = c0 + cg + 8 * q;
+      acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
+    }
+    for (int jblk = 0; jblk < kb; ++jblk) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+        const int r = idx % TCF_NB, c = idx / TCF_NB;
+        Ls[r][c] = L[(jb.l_row0 + kb * TCF_NB + r) + (int64_t)(jb.l_row0 + jblk * TCF_NB + c) * ldl];
+      }
+      for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
+        const int r = idx % TCF_NB, c = idx / TCF_NB;
+        const int col = c0 + c;
+        Xs[r][c] = (col < jb.ncols) ? B[(jblk * TCF_NB + r) + col * ldb] : T(0);
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int l = 0; l < TCF_NB; ++l) {
+        const T lv = Ls[tr][l];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] -= lv * Xs[l][cg + 8 * q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Acc[tr][cg + 8 * q] = acc[q];
+    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+      const int r = idx % TCF_NB, c = idx / TCF_NB;
+      Ls[r][c] = L[(jb.l_row0 + kb * TCF_NB + r) + (int64_t)(jb.l_row0 + kb * TCF_NB + c) * ldl];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int c = threadIdx.x;
+      for (int r = 0; r < TCF_NB; ++r) {
+        T v = Acc[r][c];
+        for (int l = 0; l < r; ++l) v -= Ls[r][l] * Acc[l][c];
+        Acc[r][c] = v / Ls[r][r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = c0 + cg + 8 * q;
+      if (col < jb.ncols) B[(kb * TCF_NB + tr) + col * ldb] = Acc[tr][cg + 8 * q];
+    }
+  }
+}
+
+// Solve L^T X = B (backward substitution with the transposed lower block).
+template <class T>
+__global__ void k_trsm_bwd(const TrsmJob* jobs, const int* prefix, int njobs, const T* Lb, T* Bb) {
+  const int jx = find_job(prefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int c0 = (blockIdx.x - prefix[jx]) * 64;
+  __shared__ T Ls[TCF_NB][TCF_NB + 1];
+  __shared__ T Xs[TCF_NB][64 + 1];
+  __shared__ T Acc[TCF_NB][64 + 1];
+  const T* L = Lb + jb.l_off;
+  T* B = Bb + jb.b_off;
+  const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;
+  const int nblk = jb.n / TCF_NB;
+  const int64_t ldl = jb.ldl, ldb = jb.ldb;
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    T acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = c0 + cg + 8 * q;
+      acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
+    }
+    for (int jblk = kb + 1; jblk < nblk; ++jblk) {
+      __syncthreads();
+      // Ls[l][r] = L[jblk*NB + l, kb*NB + r]
+      for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+        const int l = idx % TCF_NB, r = idx / TCF_NB;
+        Ls[l][r] = L[(jb.l_row0 + jblk * TCF_NB + l) + (int64_t)(jb.l_row0 + kb * TCF_NB + r) * ldl];
+      }
+      for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
+        const int r = idx % TCF_NB, c = idx / TCF_NB;
+        const int col = c0 + c;
+        Xs[r][c] = (col < jb.ncols) ? B[(jblk * TCF_NB + r) + col * ldb] : T(0);
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int l = 0; l < TCF_NB; ++l) {
+        const T lv = Ls[l][tr];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] -= lv * Xs[l][cg + 8 * q];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Acc[tr][cg + 8 * q] = acc[q];
+    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
+      const int l = idx % TCF_NB, r = idx / TCF_NB;
+      Ls[l][r] = L[(jb.l_row0 + kb * TCF_NB + l) + (int64_t)(jb.l_row0 + kb * TCF_NB + r) * ldl];
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int c = threadIdx.x;
+      for (int r = TCF_NB - 1; r >= 0; --r) {
+        T v = Acc[r][c];
+        for (int l = r + 1; l < TCF_NB; ++l) v -= Ls[l][r] * Acc[l][c];
+        Acc[r][c] = v / Ls[r][r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = c0 + cg + 8 * q;
+      if (col < jb.ncols) B[(kb * TCF_NB + tr) + col * ldb] = Acc[tr][cg + 8 * q];
+    }
+  }
+}
+
+// ===========================================================================
+// Per-step matrix-vector products (FP64 vectors, T-typed matrices)
+// ===========================================================================
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Column dots over jobs, 16 columns per block (4 waves x 4 columns); the
+// input vector is staged through LDS in chunks of TCF_XCH entries.
+// xmode 0: x[r] = xv[x_off + r]; xmode 1: x[r] = xscale * sgn * xv[gidx].
+#define TCF_XCH 4096
+template <class T>
+__global__ void __launch_bounds__(256) k_dotcols(const DotJob* jobs, const int* prefix, int njobs,
+                                                 const T* Mb, int xmode, const double* xv,
+                                                 const int* gidx, const signed char* gsgn,
+                                                 double xscale, double* out, const int* done) {
+  if (done && *done) return;
+  const int jx = find_job(prefix, njobs, blockIdx.x);
+  const DotJob jb = jobs[jx];
+  const int cblk = (blockIdx.x - prefix[jx]) * 16;
+  __shared__ double xs[TCF_XCH];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const T* M = Mb + jb.m_off;
+  const int64_t ld = jb.ld;
+  const int cA = cblk + wave * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  bool valid[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) valid[q] = (cA + q) < jb.ncols;
+  for (int r0 = 0; r0 < jb.nrows; r0 += TCF_XCH) {
+    const int rn = min(TCF_XCH, jb.nrows - r0);
+    if (r0 > 0) __syncthreads();
+    for (int r = threadIdx.x; r < rn; r += blockDim.x) {
+      const int R = r0 + r;
+      xs[r] = (xmode == 0) ? xv[jb.x_off + R]
+                           : xscale * (double)gsgn[jb.x_off + R] * xv[gidx[jb.x_off + R]];
+    }
+    __syncthreads();
+    for (int r = lane; r < rn; r += 64) {
+      const double x = xs[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (valid[q]) acc[q] += (double)M[(r0 + r) + (cA + q) * ld] * x;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0 && valid[q]) out[jb.out_off + cA + q] = v;
+  }
+}
+
+// Row stripes: out[r] = base[base_off + r] + alpha * sum_j M[r + (c0+j) ld] y[j],
+// 64 rows per block, 4 waves splitting the columns, LDS reduction; y is
+// staged through LDS in chunks.  y[j] = yv[yidx[y_off + j]] (yidx != null)
+// or yv[y_off + j].  tri != 0: M[r, c0 + j] = 0 for j < r (upper-triangular
+// leading block), so each stripe starts at its own first row.
+template <class T>
+__global__ void __launch_bounds__(256) k_axpyrows(const AxpyJob* jobs, const int* prefix,
+                                                  int njobs, const T* Mb, const double* yv,
+                                                  const int* yidx, const double* base,
+                                                  const int* base_off, double alpha, double* out,
+                                                  int tri, const int* done) {
+  if (done && *done) return;
+  const int jx = find_job(prefix, njobs, blockIdx.x);
+  const AxpyJob jb = jobs[jx];
+  const int r0 = (blockIdx.x - prefix[jx]) * 64;
+  __shared__ double ys[TCF_XCH];
+  __shared__ double red[4][64];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int r = r0 + lane;
+  const T* M = Mb + jb.m_off;
+  const int64_t ld = jb.ld;
+  double acc = 0.0;
+  const int jstart = tri ? r0 : 0;
+  for (int j0 = jstart; j0 < jb.ncols; j0 += TCF_XCH) {
+    const int jn = min(TCF_XCH, jb.ncols - j0);
+    if (j0 > jstart) __syncthreads();
+    for (int j = threadIdx.x; j < jn; j += blockDim.x)
+      ys[j] = yidx ? yv[yidx[jb.y_off + j0 + j]] : yv[jb.y_off + j0 + j];
+    __syncthreads();
+    if (r < jb.nrows) {
+      const T* Mc = M + r + (int64_t)(jb.c0 + j0) * ld;
+      for (int j = wave; j < jn; j += 4) acc += (double)Mc[(int64_t)j * ld] * ys[j];
+    }
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && r < jb.nrows) {
+    const double s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    const double b = base ? base[base_off[jx] + r] : 0.0;
+    out[jb.out_off + r] = b + alpha * s;
+  }
+}
+
+// Condensation of a kept-ordered right-hand side f (conductor patches):
+// ygg[j] += (j < n_i) ? (Q^T[:,j] . f_i) : (f[j] - Q^T[:,j] . f_i),
+// where Q^T[:, j] has nonzeros only in rows <= j for j < n_i.
+template <class T>
+__global__ void __launch_bounds__(256) k_condense(const DevPatch* P, const int* plist,
+                                                  const int* prefix, int nlist, const T* Q,
+                                                  const double* f, double* ygg, int64_t ldv) {
+  const int li = find_job(prefix, nlist, blockIdx.x);
+  const DevPatch& pp = P[plist[li]];
+  const int rhs = blockIdx.y;
+  const int cblk = (blockIdx.x - prefix[li]) * 16;
+  __shared__ double xs[TCF_XCH];
+  const double* fr = f + (int64_t)rhs * ldv + pp.r_off;
+  double* yr = ygg + (int64_t)rhs * ldv + pp.r_off;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const T* M = Q + pp.Q_off;
+  const int64_t ld = pp.ni_pad;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int nrq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = cblk + wave * 4 + q;
+    nrq[q] = (col >= pp.n_r) ? 0 : ((col < pp.n_i) ? col + 1 : pp.n_i);
+  }
+  for (int r0 = 0; r0 < pp.n_i; r0 += TCF_XCH) {
+    const int rn = min(TCF_XCH, pp.n_i - r0);
+    if (r0 > 0) __syncthreads();
+    for (int r = threadIdx.x; r < rn; r += blockDim.x) xs[r] = fr[r0 + r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = cblk + wave * 4 + q;
+      const int lim = min(rn, nrq[q] - r0);
+      for (int r = lane; r < lim; r += 64) acc[q] += (double)M[(r0 + r) + col * ld] * xs[r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = cblk + wave * 4 + q;
+    const double v = wave_sum(acc[q]);
+    if (lane == 0 && col < pp.n_r) yr[col] += (col < pp.n_i) ? v : (fr[col] - v);
+  }
+}
+
+// ===========================================================================
+// Small vector kernels
+// ===========================================================================
+__device__ inline double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) r += sh[w];
+  }
+  return r;  // valid in thread 0
+}
+
+// y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i]
+__global__ void __launch_bounds__(256) k_jump(int n, const int* pos_p, const int* pos_m,
+                                              const double* w, double scale, double* y,
+                                              const double* dotw, double* partial,
+                                              const int* done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (i < n) {
+    const double v = scale * (w[pos_p[i]] - w[pos_m[i]]);
+    y[i] = v;
+    if (dotw) d = v * dotw[i];
+  }
+  if (partial) {
+    const double s = block_sum256(d, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+__device__ inline double sum_partials(const double* p, int n, double* sh) {
+  // every block reduces the same partials in the same order (deterministic)
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
+  __shared__ double s2[4];
+  v = wave_sum(v);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  if (lane == 0) s2[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / 64); ++w) r += s2[w];
+    sh[0] = r;
+  }
+  __syncthreads();
+  return sh[0];
+}
+
+// lambda = 0, r = d, partial = d.d
+__global__ void __launch_bounds__(256) k_pcg_init(int n, const double* d, double* lam, double* r,
+                                                  double* partial) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    lam[i] = 0.0;
+    r[i] = d[i];
+    v = d[i] * d[i];
+  }
+  const double s = block_sum256(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// p = z; rz[0] = sum partial_rz; dd = sum partial_dd; done = (dd == 0)
+__global__ void __launch_bounds__(256) k_pcg_init2(int n, const double* z, double* p,
+                                                   const double* part_dd, const double* part_rz,
+                                                   int npart, PcgScalars* st) {
+  __shared__ double sh[1];
+  const double dd = sum_partials(part_dd, npart, sh);
+  __syncthreads();
+  const double rz = sum_partials(part_rz, npart, sh);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->dd = dd;
+    st->rz[0] = rz;
+    st->rz[1] = 0.0;
+    st->rr = dd;
+    st->done = (dd == 0.0) ? 1 : 0;
+    st->iters = 0;
+  }
+}
+
+// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r
+__global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq, int npart,
+                                                    PcgScalars* st, int par, double* lam,
+                                                    double* r, const double* p, const double* Fp,
+                                                    double* part_rr) {
+  if (st->done) return;
+  __shared__ double sh[1];
+  __shared__ double sh4[4];
+  const double pq = sum_partials(part_pq, npart, sh);
+  const double alpha = st->rz[par] / pq;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    lam[i] += alpha * p[i];
+    const double ri = r[i] - alpha * Fp[i];
+    r[i] = ri;
+    v = ri * ri;
+  }
+  const double s = block_sum256(v, sh4);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_pcg_check(const double* part_rr, int npart,
+                                                   PcgScalars* st, double tol2, int it) {
+  if (st->done) return;
+  __shared__ double sh[1];
+  const double rr = sum_partials(part_rr, npart, sh);
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    st->iters = it + 1;
+    if (rr <= tol2 * st->dd) st->done = 1;
+  }
+}
+
+// beta = (r.z)_new / rz[par]; p = z + beta p; rz[par^1] = (r.z)_new
+__global__ void __launch_bounds__(256) k_pcg_pupdate(int n, const double* part_rz, int npart,
+                                                     PcgScalars* st, int par, double* p,
+                                                     const double* z) {
+  if (st->done) return;
+  __shared__ double sh[1];
+  const double rz_new = sum_partials(part_rz, npart, sh);
+  const double beta = rz_new / st->rz[par];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = z[i] + beta * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[par ^ 1] = rz_new;
+}
+
+// out[k] = extra[k] + sa * sum srcA[ia[t]] + sb * sum srcB[ib[t]] over owners t of k
+__global__ void __launch_bounds__(256) k_coarse_gather(int n, const int* ptr, const int* ia,
+                                                       const double* srcA, double sa,
+                                                       const int* ib, const double* srcB,
+                                                       double sb, const double* extra,
+                                                       double* out, const int* done) {
+  if (done && *done) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double v = extra ? extra[k] : 0.0;
+  for (int t = ptr[k]; t < ptr[k + 1]; ++t) {
+    if (srcA) v += sa * srcA[ia[t]];
+    if (srcB) v += sb * srcB[ib[t]];
+  }
+  out[k] = v;
+}
+
+// y = alpha * x + beta * y over n entries
+__global__ void k_axpby(int64_t n, double alpha, const double* x, double beta, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = alpha * x[i] + (beta == 0.0 ? 0.0 : beta * y[i]);
+}
+
+// out[i] = a[ia[i]] - b[ib[i]] (index maps), used for t = u - v on b-vectors
+__global__ void k_sub_gather(int n, const int* ia, const double* a, const int* ib,
+                             const double* b, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[ia[i]] - b[ib[i]];
+}
+
+// out[dst ? dst[i] : i] = scale * src[sidx ? sidx[i] : i]
+__global__ void k_scatter(int n, const int* dst, const int* sidx, const double* src, double scale,
+                          double* out, const int* done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[dst ? dst[i] : i] = scale * src[sidx ? sidx[i] : i];
+}
+
+// global field: out[gid[i]] = a[i] (zero elsewhere beforehand)
+__global__ void k_to_global(int64_t n, const int64_t* gid, const double* a, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[gid[i]] = a[i];
+}
+
+// ===========================================================================
+// Host launch wrappers
+// ===========================================================================
+#define TCF_GRID(n, b) dim3((unsigned)(((n) + (b)-1) / (b)))
+
+void launch_tables(const DevPatch* P, int np, const double* gx, const double* gw, double* tabs,
+                   double* ptab, hipStream_t st) {
+  hipLaunchKernelGGL(k_tables1d, dim3(3 * np), dim3(256), 0, st, P, gx, gw, tabs);
+  hipLaunchKernelGGL(k_point_tables, dim3(3 * np), dim3(256), 0, st, P, gx, gw, ptab);
+}
+
+template <class T>
+void launch_assemble(const DevPatch* P, const int* col_prefix, int np, int total_cols,
+                     const int* r_loc, const double* tabs, double dt, T* A, hipStream_t st) {
+  if (total_cols == 0) return;
+  hipLaunchKernelGGL(k_assemble<T>, dim3(total_cols), dim3(256), 0, st, P, col_prefix, np, r_loc,
+                     tabs, dt, A);
+}
+
+void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                   int total_rows, int nrhs, const int* r_loc, const int* loc2r,
+                   const double* tabs, double dt, int mass_only, const double* x, double* y,
+                   int64_t ldv, hipStream_t st) {
+  if (total_rows == 0) return;
+  hipLaunchKernelGGL(k_wapply, dim3((total_rows + 127) / 128, nrhs), dim3(128), 0, st, P, plist,
+                     row_prefix, nlist, r_loc, loc2r, tabs, dt, mass_only, x, y, ldv);
+}
+
+void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
+                       const double* ptab, const double* phi, double* jr, int64_t ldv,
+                       hipStream_t st) {
+  if (n_r == 0) return;
+  hipLaunchKernelGGL(k_load_patch, dim3((n_r + 127) / 128, nrhs), dim3(128), 0, st, P, s, r_loc,
+                     ptab, phi, jr, ldv);
+}
+
+template <class T>
+void launch_potrf(const FactorJob* jobs, int njobs, int k, T* A, int* fail, hipStream_t st) {
+  hipLaunchKernelGGL(k_potrf_panel<T>, dim3(njobs), dim3(256), 0, st, jobs, k, A, fail);
+}
+template <class T>
+void launch_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
+                       hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_trsm_panel<T>, dim3(total), dim3(64), 0, st, jobs, prefix, njobs, k, A);
+}
+template <class T>
+void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
+                 hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_syrk_update<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, k, A);
+}
+template <class T>
+void launch_copy_sbb(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* S,
+                     hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_copy_sbb<T>, dim3(total), dim3(256), 0, st, P, prefix, np, A, S);
+}
+template <class T>
+void launch_fill_G(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* G,
+                   hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_fill_G<T>, dim3(total), dim3(256), 0, st, P, prefix, np, A, G);
+}
+template <class T>
+void launch_fill_Q(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* Q,
+                   hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_fill_Q<T>, dim3(total), dim3(256), 0, st, P, prefix, np, A, Q);
+}
+template <class T>
+void launch_coarse_add(const DevPatch* P, int s, int n_p, const int* p_rank, const T* A,
+                       double* SPi, int ldc, hipStream_t st) {
+  if (n_p == 0) return;
+  hipLaunchKernelGGL(k_coarse_add<T>, TCF_GRID(n_p * n_p, 256), dim3(256), 0, st, P, s, p_rank, A,
+                     SPi, ldc);
+}
+void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st) {
+  if (n <= n0) return;
+  hipLaunchKernelGGL(k_set_identity_pad, TCF_GRID(n - n0, 256), dim3(256), 0, st, M, ld, n0, n);
+}
+template <class T>
+void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int total,
+                 const T* L, T* B, hipStream_t st) {
+  if (total == 0) return;
+  if (fwd)
+    hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, L, B);
+  else
+    hipLaunchKernelGGL(k_trsm_bwd<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, L, B);
+}
+template <class T>
+void launch_dotcols(const DotJob* jobs, const int* prefix, int njobs, int total, int max_rows,
+                    const T* M, int xmode, const double* xv, const int* gidx,
+                    const signed char* gsgn, double xscale, double* out, const int* done,
+                    hipStream_t st) {
+  if (total == 0) return;
+  (void)max_rows;
+  hipLaunchKernelGGL(k_dotcols<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, xmode, xv,
+                     gidx, gsgn, xscale, out, done);
+}
+template <class T>
+void launch_axpyrows(const AxpyJob* jobs, const int* prefix, int njobs, int total, int max_cols,
+                     const T* M, const double* yv, const int* yidx, const double* base,
+                     const int* base_off, double alpha, double* out, int tri_cols,
+                     const int* done, hipStream_t st) {
+  if (total == 0) return;
+  (void)max_cols;
+  hipLaunchKernelGGL(k_axpyrows<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, yv, yidx,
+                     base, base_off, alpha, out, tri_cols, done);
+}
+template <class T>
+void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int nlist, int total,
+                     int nrhs, int max_ni, const T* Q, const double* f, double* ygg, int64_t ldv,
+                     hipStream_t st) {
+  if (total == 0) return;
+  (void)max_ni;
+  hipLaunchKernelGGL(k_condense<T>, dim3(total, nrhs), dim3(256), 0, st, P, plist, prefix, nlist, Q,
+                     f, ygg, ldv);
+}
+
+void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
+                 const double* dotw, double* partial, const int* done, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_jump, TCF_GRID(n, 256), dim3(256), 0, st, n, pp, pm, w, scale, y, dotw,
+                     partial, done);
+}
+void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, d, lam, r, partial);
+}
+void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, const double* prz,
+                      int npart, PcgScalars* stt, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_init2, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, z, p, pdd, prz,
+                     npart, stt);
+}
+void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
+                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, ppq, npart, stt,
+                     par, lam, r, p, Fp, prr);
+}
+void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2, int it,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, st, prr, npart, stt, tol2, it);
+}
+void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
+                        const double* z, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_pupdate, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, prz, npart, stt,
+                     par, p, z);
+}
+void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
+                          const int* ib, const double* srcB, double sb, const double* extra,
+                          double* out, const int* done, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_coarse_gather, TCF_GRID(n, 256), dim3(256), 0, st, n, ptr, ia, srcA, sa, ib,
+                     srcB, sb, extra, out, done);
+}
+void launch_axpby(int64_t n, double alpha, const double* x, double beta, double* y,
+                  hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_axpby, TCF_GRID(n, 256), dim3(256), 0, st, n, alpha, x, beta, y);
+}
+void launch_sub_gather(int n, const int* ia, const double* a, const int* ib, const double* b,
+                       double* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_sub_gather, TCF_GRID(n, 256), dim3(256), 0, st, n, ia, a, ib, b, out);
+}
+void launch_scatter(int n, const int* dst, const int* sidx, const double* src, double scale,
+                    double* out, const int* done, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scatter, TCF_GRID(n, 256), dim3(256), 0, st, n, dst, sidx, src, scale, out,
+                     done);
+}
+void launch_to_global(int64_t n, const int64_t* gid, const double* a, double* out,
+                      hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_to_global, TCF_GRID(n, 256), dim3(256), 0, st, n, gid, a, out);
+}
+
+#define TCF_INST(T)                                                                              \
+  template void launch_assemble<T>(const DevPatch*, const int*, int, int, const int*,            \
+                                   const double*, double, T*, hipStream_t);                      \
+  template void launch_potrf<T>(const FactorJob*, int, int, T*, int*, hipStream_t);              \
+  template void launch_trsm_panel<T>(const FactorJob*, const int*, int, int, int, T*,            \
+                                     hipStream_t);                                               \
+  template void launch_syrk<T>(const FactorJob*, const int*, int, int, int, T*, hipStream_t);    \
+  template void launch_copy_sbb<T>(const DevPatch*, const int*, int, int, const T*, T*,          \
+                                   hipStream_t);                                                 \
+  template void launch_fill_G<T>(const DevPatch*, const int*, int, int, const T*, T*,            \
+                                 hipStream_t);                                                   \
+  template void launch_fill_Q<T>(const DevPatch*, const int*, int, int, const T*, T*,            \
+                                 hipStream_t);                                                   \
+  template void launch_coarse_add<T>(const DevPatch*, int, int, const int*, const T*, double*,   \
+                                     int, hipStream_t);                                          \
+  template void launch_trsm<T>(int, const TrsmJob*, const int*, int, int, const T*, T*,          \
+                               hipStream_t);                                                     \
+  template void launch_dotcols<T>(const DotJob*, const int*, int, int, int, const T*, int,       \
+                                  const double*, const int*, const signed char*, double,         \
+                                  double*, const int*, hipStream_t);                             \
+  template void launch_axpyrows<T>(const AxpyJob*, const int*, int, int, int, const T*,          \
+                                   const double*, const int*, const double*, const int*, double, \
+                                   double*, int, const int*, hipStream_t);                       \
+  template void launch_condense<T>(const DevPatch*, const int*, const int*, int, int, int, int,  \
+                                   const T*, const double*, double*, int64_t, hipStream_t);
+
+TCF_INST(double)
+TCF_INST(float)
+
+}  // namespace tcf
+
+namespace tcf {
+// zr[i] = is_int[i] ? y[i] : -a[i]  (right-hand side of the interior recovery)
+__global__ void k_build_z(int64_t n, const signed char* is_int, const double* y, const double* a,
+                          double* zr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) zr[i] = is_int[i] ? y[i] : -a[i];
+}
+void launch_build_z(int64_t n, const signed char* is_int, const double* y, const double* a,
+                    double* zr, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_build_z, TCF_GRID(n, 256), dim3(256), 0, st, n, is_int, y, a, zr);
+}
+}  // namespace tcf
