@@ -1,0 +1,217 @@
+"""Benchmark: implicit-Euler time steps per second of the dual-primal solve.
+
+One step = condensation of the new right-hand side, the dual right-hand
+side, PCG on the multipliers (each iteration: signed gather, local Schur
+applies, coarse solve, jump, unscaled Dirichlet preconditioner, recurrences)
+and recovery of the field, for every patch, on one GPU.  Inputs are resident
+on the device (assembled and factored by tcf_setup) before timing starts.
+
+Prints one JSON line.  Besides time-steps/s it reports PCG applies/s, p50/p99
+step latency, the field error against the CPU oracle on the first steps,
+a roofline entry for the dominant kernel (its algorithmic bytes per launch
+divided by its HIP-event-timed average launch duration) and the oracle's
+own time-steps/s on the host cores (a baseline, not the target).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "plain", "mixed", "largest"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir"])
+    ap.add_argument("--profile-steps", type=int, default=3,
+                    help="steps after the timed run with per-kernel HIP-event timing")
+    ap.add_argument("--check-steps", type=int, default=2,
+                    help="steps compared against the oracle after the timed run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    return ap.parse_args()
+
+
+def make_problem(name, n_steps):
+    import workloads as W
+    if name == "uneven":
+        return W.uneven_fp64(seed=1, n_steps=n_steps)
+    if name == "plain":
+        return W.plain_fp64().with_steps(n_steps) if n_steps <= 20 else \
+            W.make_uniform((2, 2, 2), 4, 2, sigma=W.plain_fp64().sigma, n_steps=n_steps,
+                           name="cube8_p2_n4_fp64")
+    if name == "mixed":
+        return W.floating_mixed(n_steps=n_steps)
+    return W.largest_multirhs(n_steps=n_steps)
+
+
+def cpu_baseline(prob, budget_s):
+    """Time the oracle's per-step solve on a bounded sample of the same
+    problem: the full-size problem, as many steps as fit in the budget (at
+    least one), after its one-time assembly and factorisation."""
+    from oracle import solve as osolve
+    import scipy.sparse.linalg as spla
+    from oracle.assemble import assemble_global
+    from oracle.gauge import compute_topology
+    from oracle.grid import build_grid
+
+    t0 = time.perf_counter()
+    g = build_grid(prob)
+    sysm = assemble_global(prob, g, keep_patches=False)
+    topo = compute_topology(prob, g)
+    Wg, K = osolve.gauged_matrix(sysm, topo, prob.dt)
+    t1 = time.perf_counter()
+    lu = spla.splu(Wg)
+    t2 = time.perf_counter()
+    a = np.zeros((g.n_edges, prob.n_rhs))
+    steps = 0
+    ts = time.perf_counter()
+    while steps < prob.n_steps:
+        f = sysm.M @ a + prob.dt * sysm.jhat * prob.amp[:, steps][None, :]
+        a = np.zeros_like(a)
+        a[K] = lu.solve(np.ascontiguousarray(f[K]))
+        steps += 1
+        if time.perf_counter() - ts > budget_s:
+            break
+    t3 = time.perf_counter()
+    per_step = (t3 - ts) / steps
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": 1.0 / per_step, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+        "sample": (f"full-size problem, {steps} implicit-Euler steps with one SuperLU "
+                   f"factorisation of the {len(K)}-unknown gauged system (factor {t2 - t1:.1f} s, "
+                   f"assembly+gauge {t1 - t0:.1f} s, not in value); SuperLU is single-threaded, "
+                   f"{cores} cores visible"),
+        "factor_s": t2 - t1, "assembly_s": t1 - t0, "steps_timed": steps,
+    }, [a]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    from paper_2510_23446_amd import tcf
+
+    n_steps = args.warmup + args.steps + args.profile_steps
+    prob = make_problem(args.workload, max(n_steps, args.check_steps))
+    prec = args.precision or prob.precision
+    p = tcf.Problem(prob, precision=prec)
+    counts = p.counts()
+    t0 = time.perf_counter()
+    p.tcf_setup()
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] {prob.name}: setup {setup_s:.2f} s, counts {counts}", file=sys.stderr, flush=True)
+
+    # warmup
+    if args.warmup:
+        p.tcf_step(args.warmup)
+    st0 = p.tcf_get_stats()
+    p.tcf_sync()
+    t0 = time.perf_counter()
+    p.tcf_step(args.steps)
+    p.tcf_sync()
+    t1 = time.perf_counter()
+    st1 = p.tcf_get_stats()
+    wall = t1 - t0
+    iters, _, ms = p.tcf_get_step_log(args.steps)
+    applies = int(st1["total_pcg_iters"] - st0["total_pcg_iters"])
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s; PCG iterations {applies}",
+          file=sys.stderr, flush=True)
+    # per-kernel durations: HIP events around every launch of each kernel
+    # group, on the launch stream, over the next steps (stream launches; the
+    # timed run above replays captured graphs, which take no events)
+    p.tcf_profile_enable(True)
+    p.tcf_step(args.profile_steps)
+    p.tcf_sync()
+    prof = p.tcf_profile_get()
+    p.tcf_profile_enable(False)
+
+    # dominant kernel by measured time
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot_ms, nl, alg_bytes = prof[dom]
+    avg_s = tot_ms / 1e3 / max(nl, 1)
+    achieved = alg_bytes / avg_s / 1e9 if nl else 0.0
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        tj = json.load(open(args.traffic))
+        if tj.get("kernel_group") == dom:
+            traffic = tj.get("hbm_bytes_per_launch")
+    breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
+                     "avg_us": round(v[0] * 1e3 / max(v[1], 1), 2),
+                     "alg_MB_per_launch": round(v[2] / 1e6, 3),
+                     "alg_GBs": round(v[2] / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1) if v[1] else 0.0}
+                 for k, v in prof.items()}
+
+    # field error against the oracle on the first steps (separate handle)
+    rel_err = None
+    if args.check_steps > 0:
+        from oracle import solve as osolve
+        small = prob.with_steps(args.check_steps)
+        ref = osolve.run(small)
+        q = tcf.Problem(small, precision=prec)
+        q.tcf_setup()
+        rel_err = 0.0
+        for l in range(args.check_steps):
+            q.tcf_step(1)
+            for k in range(small.n_rhs):
+                a = q.tcf_get_field(k)
+                r = ref.fields[l][:, k]
+                rel_err = max(rel_err, float(np.linalg.norm(a - r) / np.linalg.norm(r)))
+        q.tcf_destroy()
+        print(f"[bench] field rel err vs oracle over {args.check_steps} steps: {rel_err:.2e}",
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, _ = cpu_baseline(prob, args.cpu_budget_s)
+        print(f"[bench] oracle {cpu['value']:.3f} steps/s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "time-steps/sec",
+        "value": args.steps / wall,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32-factors+f64-pcg",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "patches": prob.n_patches, "n_rhs": prob.n_rhs,
+                   "dt": prob.dt, "pcg_rtol": prob.pcg_rtol, "precision": prec,
+                   "n_edges": counts["n_edges"], "gauged_dofs": counts["n_kept"],
+                   "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"]},
+        "pcg_applies_per_s": applies / wall,
+        "pcg_iters_per_step": applies / args.steps,
+        "p50_step_ms": float(np.percentile(ms, 50)),
+        "p99_step_ms": float(np.percentile(ms, 99)),
+        "setup_s": setup_s,
+        "rel_error_vs_oracle": rel_err,
+        "rel_error_steps": args.check_steps,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernels": breakdown,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -61,7 +61,8 @@ enum tcf_precision {
  * out[ix + nx*(iy + ny*iz)] = phi_k(xs[ix], ys[iy], zs[iz]).
  * The source is J_k(x,t) = g_k(t) curl(0, 0, phi_k(x)) on patches whose
  * src_mask is set (the load vector j of Sec. 2.2, taken in curl form).
- * Called only from tcf_create, on the calling thread.
+ * Called from tcf_setup on the calling thread, once per (source patch, k);
+ * phi and phi_ctx must stay valid until tcf_setup returns.
  */
 typedef void (*tcf_phi_fn)(const double* xs, int32_t nx, const double* ys, int32_t ny,
                            const double* zs, int32_t nz, int32_t k, double* out, void* ctx);
@@ -99,9 +100,9 @@ typedef struct tcf_problem tcf_problem;
 
 /*
  * Host-only work: validation, control grid, edge classes, gauge tree,
- * primal/dual/interior split, multiplier table, device memory plan, and the
- * source callback at quadrature points.  Touches no GPU.  Everything in
- * desc is copied; the caller may free it on return.
+ * primal/dual/interior split, multiplier table and device memory plan.
+ * Touches no GPU.  Every array in desc is copied and may be freed on
+ * return; the phi callback and its context are kept until tcf_setup.
  * Errors: TCF_EINVAL (bad sizes, sigma < 0, nu <= 0, dt <= 0, non-increasing
  * breaks, deg < 1, nel < 1, n_rhs < 1), TCF_ENOMEM.  On error *out is NULL and
  * tcf_last_error(NULL) holds the message.
@@ -194,6 +195,28 @@ int tcf_get_step_log(const tcf_problem* h, int32_t n, int32_t* pcg_iters, int32_
  */
 int tcf_get_state(tcf_problem* h, void* buf, size_t* bytes, void* stream);
 int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream);
+
+/*
+ * Kernel timing for measurement.  While enabled, every launch of the
+ * per-step kernel groups below is bracketed by HIP events on its launch
+ * stream; launches issued after the PCG converged (which exit at once) are
+ * not counted.  tcf_profile_get returns, for group g, the summed event time
+ * in milliseconds, the number of launches and the algorithmic bytes one
+ * launch must move (each matrix entry read once, symmetric matrices as one
+ * triangle, plus its vectors).  Enabling resets the counters.
+ */
+enum tcf_kernel_group {
+  TCF_KG_APPLY = 0,    /* [S_bb^-1 | Phi_b]^T x over all patches (F apply)   */
+  TCF_KG_PRECOND = 1,  /* S_bb x over all patches (Dirichlet preconditioner) */
+  TCF_KG_PHI = 2,      /* Phi_b N q over all patches                         */
+  TCF_KG_COARSE = 3,   /* S_Pi^-1 c                                          */
+  TCF_KG_CONDENSE = 4, /* per-step condensation of conductor patches         */
+  TCF_KG_RECOVER = 5,  /* interior recovery of all patches                   */
+  TCF_KG_COUNT = 6
+};
+int tcf_profile_enable(tcf_problem* h, int32_t on);
+int tcf_profile_get(const tcf_problem* h, int32_t group, double* total_ms, int64_t* launches,
+                    double* alg_bytes_per_launch);
 
 void tcf_destroy(tcf_problem* h);
 

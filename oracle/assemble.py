@@ -150,8 +150,13 @@ def assemble_patch(prob, grid: Grid, s: int) -> PatchMatrices:
                     m, np.arange(lo[0], lo[0] + span[0]), np.arange(lo[1], lo[1] + span[1]),
                     np.arange(lo[2], lo[2] + span[2]), d)
             col += width
-        Ke = nu * np.einsum("eq,eqic,eqjc->eij", wq, C, C)
-        Me = sig * np.einsum("eq,eqic,eqjc->eij", wq, V, V)
+        # element matrices: sum over points q and components c of
+        # w_q curl w_i(q)_c curl w_j(q)_c, as a batched product per element
+        Cq = C.transpose(0, 1, 3, 2).reshape(E, nq3 * 3, nl)
+        Vq = V.transpose(0, 1, 3, 2).reshape(E, nq3 * 3, nl)
+        wr = np.repeat(wq, 3, axis=1)[:, :, None]
+        Ke = nu * np.matmul((Cq * wr).transpose(0, 2, 1), Cq)
+        Me = sig * np.matmul((Vq * wr).transpose(0, 2, 1), Vq)
         Mr.append(np.repeat(idx[:, :, None], nl, axis=2).ravel())
         Mc.append(np.repeat(idx[:, None, :], nl, axis=1).ravel())
         Mv.append(Me.ravel())
@@ -215,19 +220,27 @@ class GlobalSystem:
 
 
 def assemble_global(prob, grid: Grid | None = None, keep_patches=True) -> GlobalSystem:
+    """Sum the local patch matrices into the global conforming matrices
+    through each patch's local-to-global edge map (one COO build)."""
     grid = grid or build_grid(prob)
     nE = grid.n_edges
-    Mg = sp.csr_matrix((nE, nE))
-    Kg = sp.csr_matrix((nE, nE))
+    rows, cols, mv, kv = [], [], [], []
     jg = np.zeros((nE, prob.n_rhs))
     pats = []
     for s in range(prob.n_patches):
         pm = assemble_patch(prob, grid, s)
-        R = sp.csr_matrix((np.ones(len(pm.gid)), (pm.gid, np.arange(len(pm.gid)))),
-                          shape=(nE, len(pm.gid)))
-        Mg = Mg + R @ pm.M @ R.T
-        Kg = Kg + R @ pm.K @ R.T
+        Mc = pm.M.tocoo()
+        Kc = pm.K.tocoo()
+        assert np.array_equal(Mc.row, Kc.row) and np.array_equal(Mc.col, Kc.col)
+        rows.append(pm.gid[Mc.row])
+        cols.append(pm.gid[Mc.col])
+        mv.append(Mc.data)
+        kv.append(Kc.data)
         np.add.at(jg, pm.gid, pm.jhat)
         if keep_patches:
             pats.append(pm)
-    return GlobalSystem(grid=grid, M=Mg.tocsr(), K=Kg.tocsr(), jhat=jg, patches=pats)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    Mg = sp.csr_matrix((np.concatenate(mv), (r, c)), shape=(nE, nE))
+    Kg = sp.csr_matrix((np.concatenate(kv), (r, c)), shape=(nE, nE))
+    return GlobalSystem(grid=grid, M=Mg, K=Kg, jhat=jg, patches=pats)

@@ -142,6 +142,8 @@ struct tcf_problem {
   PcgScalars* h_st = nullptr;  // pinned
   int* d_fail = nullptr;
   double* d_field = nullptr;
+  hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+  hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
 
   // job tables
   DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr, *dj_coarse = nullptr;
@@ -154,6 +156,41 @@ struct tcf_problem {
   int *d_cond = nullptr, *d_cond_cprefix = nullptr, *d_cond_rprefix = nullptr;
   int nt_cond_c = 0, nt_cond_r = 0;
 
+  // ---- kernel timing -------------------------------------------------------------
+  struct Pend { int g, it; hipEvent_t a, b; };
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pend> pend;
+  double prof_ms[TCF_KG_COUNT] = {0};
+  int64_t prof_n[TCF_KG_COUNT] = {0};
+  double prof_bytes[TCF_KG_COUNT] = {0};
+  int cur_it = -1;  // PCG iteration of the launches being issued (-1: outside PCG)
+  hipEvent_t ev_get() {
+    if (ev_pool.empty()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      return e;
+    }
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  // drop_from: PCG launches with iteration >= drop_from are discarded
+  void prof_flush(int drop_from) {
+    for (auto& p : pend) {
+      if (!(p.it >= 0 && p.it >= drop_from)) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+          prof_ms[p.g] += ms;
+          prof_n[p.g]++;
+        }
+      }
+      ev_pool.push_back(p.a);
+      ev_pool.push_back(p.b);
+    }
+    pend.clear();
+  }
+
   // ---- stats -------------------------------------------------------------------
   int steps_done = 0;
   int last_iters = 0, max_iters = 0, nonconv = 0, last_ir = 0, fail_patch = -2;
@@ -163,6 +200,10 @@ struct tcf_problem {
   std::vector<double> log_ms;
 
   ~tcf_problem() {
+    if (pcg_graph) (void)hipGraphExecDestroy(pcg_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    for (auto& p : pend) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto& b : bufs)
       if (b.p) (void)hipFree(b.p);
     if (h_st) (void)hipHostFree(h_st);
@@ -216,6 +257,44 @@ struct tcf_problem {
     int rc_ = (expr);      \
     if (rc_) return rc_;   \
   } while (0)
+
+template <class F>
+static inline void timed(tcf_problem* h, int g, hipStream_t st, F&& f) {
+  if (!h->prof_on) {
+    f();
+    return;
+  }
+  hipEvent_t a = h->ev_get(), b = h->ev_get();
+  (void)hipEventRecord(a, st);
+  f();
+  (void)hipEventRecord(b, st);
+  h->pend.push_back({g, h->cur_it, a, b});
+}
+
+// Algorithmic bytes of one launch of each kernel group (see tcf.h).
+static void compute_alg_bytes(tcf_problem* h) {
+  const double w = h->precision == TCF_FP64 ? 8.0 : 4.0;
+  double app = 0, pre = 0, phi = 0, cond = 0, rec = 0;
+  for (int s = 0; s < h->np_tot; ++s) {
+    const DevPatch& d = h->hp[s];
+    const double nb = d.n_b, np_ = d.n_p, ni = d.n_i;
+    if (d.n_b > 0) {
+      app += (nb * (nb + 1) / 2 + nb * np_) * w + (2 * nb + np_) * 8;
+      pre += nb * (nb + 1) / 2 * w + 2 * nb * 8;
+      if (d.n_p > 0) phi += nb * np_ * w + (np_ + 2 * nb) * 8;
+    }
+    const double qb = (ni * (ni + 1) / 2 + ni * (nb + np_)) * w;
+    if (d.cond) cond += qb + (2 * (ni + nb + np_)) * 8;
+    rec += qb + (d.n_r + ni) * 8;
+  }
+  const double nP = h->n_primal;
+  h->prof_bytes[TCF_KG_APPLY] = app;
+  h->prof_bytes[TCF_KG_PRECOND] = pre;
+  h->prof_bytes[TCF_KG_PHI] = phi;
+  h->prof_bytes[TCF_KG_COARSE] = nP * (nP + 1) / 2 * 8 + 2 * nP * 8;
+  h->prof_bytes[TCF_KG_CONDENSE] = cond;
+  h->prof_bytes[TCF_KG_RECOVER] = rec;
+}
 
 size_t tcf_problem::footprint(int prec) const {
   const size_t w = prec == TCF_FP64 ? 8 : 4;
@@ -449,6 +528,24 @@ int tcf_get_step_log(const tcf_problem* h, int32_t n, int32_t* it, int32_t* ir, 
 
 void tcf_destroy(tcf_problem* h) { delete h; }
 
+int tcf_profile_enable(tcf_problem* h, int32_t on) {
+  if (!h) return TCF_EINVAL;
+  h->prof_flush(INT32_MAX);
+  h->prof_on = on != 0;
+  for (int g = 0; g < TCF_KG_COUNT; ++g) { h->prof_ms[g] = 0; h->prof_n[g] = 0; }
+  compute_alg_bytes(h);
+  return TCF_OK;
+}
+
+int tcf_profile_get(const tcf_problem* h, int32_t g, double* total_ms, int64_t* launches,
+                    double* alg_bytes) {
+  if (!h || g < 0 || g >= TCF_KG_COUNT) return TCF_EINVAL;
+  if (total_ms) *total_ms = h->prof_ms[g];
+  if (launches) *launches = h->prof_n[g];
+  if (alg_bytes) *alg_bytes = h->prof_bytes[g];
+  return TCF_OK;
+}
+
 }  // extern "C"
 
 // ============================================================================
@@ -520,8 +617,11 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
   return TCF_OK;
 }
 
+static constexpr int kDotCpb = 32;  // columns per block of k_dotcols
+
 static int build_index_tables(tcf_problem* h) {
   const int np = h->np_tot;
+  const int rows_per_stripe = 64 * (h->precision == TCF_FP64 ? 2 : 4);
   std::vector<int> rloc, loc2r, brow, prank, posp(h->n_lambda), posm(h->n_lambda), b2bp, p2r, b2r;
   std::vector<signed char> bsgn, isint;
   std::vector<int64_t> rgid;
@@ -584,19 +684,19 @@ static int build_index_tables(tcf_problem* h) {
     if (d.n_b > 0) {
       app_g.push_back(DotJob{d.G_off, d.nb_pad, d.n_b, d.n_b + d.n_p, d.b_off, d.bp_off});
       app_v.push_back(DotJob{d.G_off, d.nb_pad, d.n_b, d.n_b + d.n_p, d.r_off + d.n_i, d.bp_off});
-      c_app.push_back((d.n_b + d.n_p + 15) / 16);
+      c_app.push_back((d.n_b + d.n_p + kDotCpb - 1) / kDotCpb);
       pre.push_back(DotJob{d.S_off, d.nb_pad, d.n_b, d.n_b, d.b_off, d.b_off});
-      c_pre.push_back((d.n_b + 15) / 16);
+      c_pre.push_back((d.n_b + kDotCpb - 1) / kDotCpb);
       if (d.n_p > 0) {
         phi.push_back(AxpyJob{d.G_off, d.nb_pad, d.n_b, d.n_p, d.n_b, d.p_off, d.b_off});
-        c_phi.push_back((d.n_b + 63) / 64);
+        c_phi.push_back((d.n_b + rows_per_stripe - 1) / rows_per_stripe);
         boff_bp.push_back(d.bp_off);
         boff_b.push_back(d.b_off);
       }
     }
     if (d.n_i > 0) {
       ai.push_back(AxpyJob{d.Q_off, d.ni_pad, d.n_i, d.n_r, 0, d.r_off, d.r_off});
-      c_ai.push_back((d.n_i + 63) / 64);
+      c_ai.push_back((d.n_i + rows_per_stripe - 1) / rows_per_stripe);
       boff_ai.push_back(0);
     }
   }
@@ -639,7 +739,7 @@ static int build_index_tables(tcf_problem* h) {
   std::vector<int> cc;
   if (h->n_primal > 0) {
     cj.push_back(DotJob{0, h->nPi_pad, h->n_primal, h->n_primal, 0, 0});
-    cc.push_back((h->n_primal + 15) / 16);
+    cc.push_back((h->n_primal + kDotCpb - 1) / kDotCpb);
   }
   auto p_c = prefix_of(cc);
   h->nt_coarse = p_c.back();
@@ -883,8 +983,10 @@ static void phi_apply(tcf_problem* h, const double* base_bp, double alpha, const
                       double* wb, const int* done, hipStream_t st) {
   launch_scatter((int)h->n_btot, nullptr, h->d_b2bp, base_bp, 1.0, wb, done, st);
   if (h->n_primal > 0)
-    launch_axpyrows<T>(h->aj_phi, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, (const T*)h->d_G, q,
-                       h->d_prank, wb, h->a_boff_b, alpha, wb, 0, done, st);
+    timed(h, TCF_KG_PHI, st, [&] {
+      launch_axpyrows<T>(h->aj_phi, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, (const T*)h->d_G,
+                         q, h->d_prank, wb, h->a_boff_b, alpha, wb, 0, done, st);
+    });
 }
 
 // out = S_Pi^-1 (extra + sum_s N_s^T c_s), c_s = the primal part of a bp-vector
@@ -893,8 +995,10 @@ static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, 
   if (h->n_primal == 0) return;
   launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, bp, 1.0,
                        extra, h->d_cv, done, st);
-  launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv, 0,
-                         h->d_cv, nullptr, nullptr, 1.0, out, done, st);
+  timed(h, TCF_KG_COARSE, st, [&] {
+    launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv,
+                           0, h->d_cv, nullptr, nullptr, 1.0, out, done, st);
+  });
 }
 
 // Fp = F p = sum Bhat [S_bb^-1 x + Phi N S_Pi^-1 sum N^T Phi^T x], x = Bhat^T p;
@@ -902,8 +1006,10 @@ static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, 
 template <class T>
 static void apply_F(tcf_problem* h, const double* p, double* Fp, double* part, const int* done,
                     hipStream_t st) {
-  launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, (const T*)h->d_G, 1,
-                    p, h->d_brow, h->d_bsgn, h->dt, h->d_vc, done, st);
+  timed(h, TCF_KG_APPLY, st, [&] {
+    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, (const T*)h->d_G,
+                      1, p, h->d_brow, h->d_bsgn, h->dt, h->d_vc, done, st);
+  });
   coarse_solve(h, h->d_vc, nullptr, h->d_q, done, st);
   phi_apply<T>(h, h->d_vc, 1.0, h->d_q, h->d_wb, done, st);
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, Fp, p, part, done, st);
@@ -913,9 +1019,47 @@ static void apply_F(tcf_problem* h, const double* p, double* Fp, double* part, c
 template <class T>
 static void apply_M(tcf_problem* h, const double* r, double* z, double* part, const int* done,
                     hipStream_t st) {
-  launch_dotcols<T>(h->dj_pre, h->dp_pre, h->nj_pre, h->nt_pre, h->max_nb, (const T*)h->d_S, 1, r,
-                    h->d_brow, h->d_bsgn, 1.0, h->d_tb, done, st);
+  timed(h, TCF_KG_PRECOND, st, [&] {
+    launch_dotcols<T>(h->dj_pre, h->dp_pre, h->nj_pre, h->nt_pre, h->max_nb, (const T*)h->d_S, 1,
+                      r, h->d_brow, h->d_bsgn, 1.0, h->d_tb, done, st);
+  });
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
+}
+
+// One PCG iteration with the given parity (launch sequence only).
+template <class T>
+static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
+  const int nl = h->n_lambda, npt = h->npart;
+  const int* done = &h->d_st->done;
+  double* p_pq = h->d_part;
+  double* p_rr = h->d_part + npt;
+  double* p_rz = h->d_part + 2 * npt;
+  const double tol2 = h->opt.pcg_rtol * h->opt.pcg_rtol;
+  apply_F<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
+  launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
+  launch_pcg_check(p_rr, npt, h->d_st, tol2, st);
+  apply_M<T>(h, h->d_r, h->d_z, p_rz, done, st);
+  launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
+}
+
+// Captures two iterations (parity 0, 1) into a graph replayed per chunk.
+template <class T>
+static int build_pcg_graph(tcf_problem* h) {
+  if (h->pcg_graph) return TCF_OK;
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  pcg_iteration<T>(h, 0, h->cap_stream);
+  pcg_iteration<T>(h, 1, h->cap_stream);
+  HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(&h->pcg_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->pcg_graph = nullptr;
+    h->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+    return TCF_EHIP;
+  }
+  return TCF_OK;
 }
 
 template <class T>
@@ -925,41 +1069,39 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bo
   rel = 0.0;
   conv = true;
   if (nl == 0) return TCF_OK;
-  const int* done = &h->d_st->done;
   const int npt = h->npart;
-  double* p_pq = h->d_part;
-  double* p_rr = h->d_part + npt;
   double* p_rz = h->d_part + 2 * npt;
   double* p_dd = h->d_part + 3 * npt;
   launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
   apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
   launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
-  const double tol2 = h->opt.pcg_rtol * h->opt.pcg_rtol;
-  const int chunk = h->opt.check_every;
+  const bool graph = h->opt.use_graph && !h->prof_on;
+  if (graph) RCCHK(build_pcg_graph<T>(h));
+  const int chunk = std::max(2, h->opt.check_every / 2 * 2);
   int it = 0;
   bool finished = false;
   while (it < maxit && !finished) {
     const int it1 = std::min(maxit, it + chunk);
-    for (; it < it1; ++it) {
-      const int par = it & 1;
-      apply_F<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
-      launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
-      launch_pcg_check(p_rr, npt, h->d_st, tol2, it, st);
-      apply_M<T>(h, h->d_r, h->d_z, p_rz, done, st);
-      launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
+    while (it < it1) {
+      if (graph && it + 2 <= it1 && (it & 1) == 0) {
+        HIPCHK(hipGraphLaunch(h->pcg_graph, st));
+        it += 2;
+      } else {
+        h->cur_it = it;
+        pcg_iteration<T>(h, it & 1, st);
+        ++it;
+      }
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     finished = h->h_st->done != 0;
+    if (h->prof_on) h->prof_flush(finished ? h->h_st->iters : INT32_MAX);
   }
-  if (!finished) {
-    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-  }
+  h->cur_it = -1;
   iters = h->h_st->iters;
-  conv = h->h_st->done != 0;
+  conv = finished;
   rel = h->h_st->dd > 0 ? std::sqrt(h->h_st->rr / h->h_st->dd) : 0.0;
   return TCF_OK;
 }
@@ -980,8 +1122,10 @@ static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bo
   if (!h->cond_list.empty()) {
     launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
                   h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
-    launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
-                       h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
+    timed(h, TCF_KG_CONDENSE, st, [&] {
+      launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
+                         h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
+    });
   }
   // [u; c0] = G^T g_b ; h = sum N^T (g_p - c0) ; q0 = S_Pi^-1 h ; d = jump(u - Phi N q0)
   launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
@@ -1016,8 +1160,10 @@ static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bo
   }
   // a_i = L_ii^-T (y - L_bi^T a_b - L_pi^T a_p) = Q^T [y; -a_b; -a_p]
   launch_build_z(ldv, h->d_isint, ygg, a, h->d_zr, st);
-  launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
-                     nullptr, h->a_boff_ai, 1.0, a, 1, nullptr, st);
+  timed(h, TCF_KG_RECOVER, st, [&] {
+    launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
+                       nullptr, h->a_boff_ai, 1.0, a, 1, nullptr, st);
+  });
   HIPCHK(hipGetLastError());
   return TCF_OK;
 }
@@ -1041,6 +1187,7 @@ static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
       h->total_iters += iters;
     }
     HIPCHK(hipStreamSynchronize(st));
+    if (h->prof_on) h->prof_flush(INT32_MAX);
     const double ms = now_ms() - t0;
     if (!all_conv) {
       ++h->nonconv;

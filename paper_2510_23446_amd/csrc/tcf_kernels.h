@@ -65,7 +65,7 @@ void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, cons
                       int npart, PcgScalars* stt, hipStream_t st);
 void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
                        double* r, const double* p, const double* Fp, double* prr, hipStream_t st);
-void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2, int it,
+void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
                       hipStream_t st);
 void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
                         const double* z, hipStream_t st);

@@ -724,55 +724,90 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Column dots over jobs, 16 columns per block (4 waves x 4 columns); the
-// input vector is staged through LDS in chunks of TCF_XCH entries.
+// Column dots over jobs: out[j] = sum_r M[r + j ld] x[r].  A block of 4
+// waves covers TCF_DOT_CPB columns, each wave TCF_DOT_CPW columns at once;
+// each lane reads 16 bytes (2 doubles / 4 floats) of a column per load, so a
+// wave load covers 128 / 256 rows.  Columns are zero beyond nrows up to the
+// padded leading dimension, and x is staged through LDS (zero padded) in
+// chunks of TCF_XCH entries.
 // xmode 0: x[r] = xv[x_off + r]; xmode 1: x[r] = xscale * sgn * xv[gidx].
 #define TCF_XCH 4096
+#define TCF_DOT_CPW 8
+#define TCF_DOT_CPB (4 * TCF_DOT_CPW)
+template <class T> struct Vec16;
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+
+template <class T>
+__device__ inline void vdot(const typename Vec16<T>::type& v, const double* x, double& acc);
+template <>
+__device__ inline void vdot<double>(const double2& v, const double* x, double& acc) {
+  acc += v.x * x[0] + v.y * x[1];
+}
+template <>
+__device__ inline void vdot<float>(const float4& v, const double* x, double& acc) {
+  acc += (double)v.x * x[0] + (double)v.y * x[1] + (double)v.z * x[2] + (double)v.w * x[3];
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) k_dotcols(const DotJob* jobs, const int* prefix, int njobs,
                                                  const T* Mb, int xmode, const double* xv,
                                                  const int* gidx, const signed char* gsgn,
                                                  double xscale, double* out, const int* done) {
   if (done && *done) return;
+  typedef typename Vec16<T>::type VT;
+  constexpr int V = Vec16<T>::n;
   const int jx = find_job(prefix, njobs, blockIdx.x);
   const DotJob jb = jobs[jx];
-  const int cblk = (blockIdx.x - prefix[jx]) * 16;
+  const int cblk = (blockIdx.x - prefix[jx]) * TCF_DOT_CPB;
   __shared__ double xs[TCF_XCH];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const T* M = Mb + jb.m_off;
   const int64_t ld = jb.ld;
-  const int cA = cblk + wave * 4;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  bool valid[4];
+  const int cA = cblk + wave * TCF_DOT_CPW;
+  double acc[TCF_DOT_CPW];
+  const VT* colp[TCF_DOT_CPW];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) valid[q] = (cA + q) < jb.ncols;
-  for (int r0 = 0; r0 < jb.nrows; r0 += TCF_XCH) {
-    const int rn = min(TCF_XCH, jb.nrows - r0);
+  for (int q = 0; q < TCF_DOT_CPW; ++q) {
+    acc[q] = 0.0;
+    const int c = min(cA + q, jb.ncols - 1);
+    colp[q] = reinterpret_cast<const VT*>(M + (int64_t)c * ld);
+  }
+  const int nrv = (jb.nrows + V - 1) / V * V;
+  for (int r0 = 0; r0 < nrv; r0 += TCF_XCH) {
+    const int rn = min(TCF_XCH, nrv - r0);
     if (r0 > 0) __syncthreads();
     for (int r = threadIdx.x; r < rn; r += blockDim.x) {
       const int R = r0 + r;
-      xs[r] = (xmode == 0) ? xv[jb.x_off + R]
-                           : xscale * (double)gsgn[jb.x_off + R] * xv[gidx[jb.x_off + R]];
+      double v = 0.0;
+      if (R < jb.nrows)
+        v = (xmode == 0) ? xv[jb.x_off + R]
+                         : xscale * (double)gsgn[jb.x_off + R] * xv[gidx[jb.x_off + R]];
+      xs[r] = v;
     }
     __syncthreads();
-    for (int r = lane; r < rn; r += 64) {
-      const double x = xs[r];
+    if (cA < jb.ncols) {
+      for (int r = lane * V; r < rn; r += 64 * V) {
+        VT v[TCF_DOT_CPW];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (valid[q]) acc[q] += (double)M[(r0 + r) + (cA + q) * ld] * x;
+        for (int q = 0; q < TCF_DOT_CPW; ++q) v[q] = colp[q][(r0 + r) / V];
+#pragma unroll
+        for (int q = 0; q < TCF_DOT_CPW; ++q) vdot<T>(v[q], xs + r, acc[q]);
+      }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < TCF_DOT_CPW; ++q) {
     const double v = wave_sum(acc[q]);
-    if (lane == 0 && valid[q]) out[jb.out_off + cA + q] = v;
+    if (lane == 0 && cA + q < jb.ncols) out[jb.out_off + cA + q] = v;
   }
 }
 
-// Row stripes: out[r] = base[base_off + r] + alpha * sum_j M[r + (c0+j) ld] y[j],
-// 64 rows per block, 4 waves splitting the columns, LDS reduction; y is
-// staged through LDS in chunks.  y[j] = yv[yidx[y_off + j]] (yidx != null)
-// or yv[y_off + j].  tri != 0: M[r, c0 + j] = 0 for j < r (upper-triangular
+// Row stripes: out[r] = base[base_off + r] + alpha * sum_j M[r + (c0+j) ld] y[j].
+// A block covers 64*V rows (each lane V consecutive rows, one 16-byte load
+// per column); 4 waves split the columns (8 in flight each) and reduce in
+// LDS.  y is staged through LDS in chunks.  y[j] = yv[yidx[y_off + j]] or
+// yv[y_off + j].  tri != 0: M[r, c0 + j] = 0 for j < r (upper-triangular
 // leading block), so each stripe starts at its own first row.
 template <class T>
 __global__ void __launch_bounds__(256) k_axpyrows(const AxpyJob* jobs, const int* prefix,
@@ -781,16 +816,20 @@ __global__ void __launch_bounds__(256) k_axpyrows(const AxpyJob* jobs, const int
                                                   const int* base_off, double alpha, double* out,
                                                   int tri, const int* done) {
   if (done && *done) return;
+  typedef typename Vec16<T>::type VT;
+  constexpr int V = Vec16<T>::n;
   const int jx = find_job(prefix, njobs, blockIdx.x);
   const AxpyJob jb = jobs[jx];
-  const int r0 = (blockIdx.x - prefix[jx]) * 64;
+  const int r0 = (blockIdx.x - prefix[jx]) * 64 * V;
   __shared__ double ys[TCF_XCH];
-  __shared__ double red[4][64];
+  __shared__ double red[4][64 * 4];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int r = r0 + lane;
+  const int r = r0 + lane * V;
   const T* M = Mb + jb.m_off;
   const int64_t ld = jb.ld;
-  double acc = 0.0;
+  double acc[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) acc[k] = 0.0;
   const int jstart = tri ? r0 : 0;
   for (int j0 = jstart; j0 < jb.ncols; j0 += TCF_XCH) {
     const int jn = min(TCF_XCH, jb.ncols - j0);
@@ -800,15 +839,38 @@ __global__ void __launch_bounds__(256) k_axpyrows(const AxpyJob* jobs, const int
     __syncthreads();
     if (r < jb.nrows) {
       const T* Mc = M + r + (int64_t)(jb.c0 + j0) * ld;
-      for (int j = wave; j < jn; j += 4) acc += (double)Mc[(int64_t)j * ld] * ys[j];
+      int j = wave;
+      for (; j + 4 * 7 < jn; j += 4 * 8) {
+        VT v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = *reinterpret_cast<const VT*>(Mc + (int64_t)(j + 4 * u) * ld);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double yj = ys[j + 4 * u];
+          const T* e = reinterpret_cast<const T*>(&v[u]);
+#pragma unroll
+          for (int k = 0; k < V; ++k) acc[k] += (double)e[k] * yj;
+        }
+      }
+      for (; j < jn; j += 4) {
+        const VT v = *reinterpret_cast<const VT*>(Mc + (int64_t)j * ld);
+        const T* e = reinterpret_cast<const T*>(&v);
+        const double yj = ys[j];
+#pragma unroll
+        for (int k = 0; k < V; ++k) acc[k] += (double)e[k] * yj;
+      }
     }
   }
-  red[wave][lane] = acc;
+#pragma unroll
+  for (int k = 0; k < V; ++k) red[wave][lane * V + k] = acc[k];
   __syncthreads();
-  if (wave == 0 && r < jb.nrows) {
-    const double s = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    const double b = base ? base[base_off[jx] + r] : 0.0;
-    out[jb.out_off + r] = b + alpha * s;
+  for (int t = threadIdx.x; t < 64 * V; t += blockDim.x) {
+    const int R = r0 + t;
+    if (R < jb.nrows) {
+      const double s = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+      const double b = base ? base[base_off[jx] + R] : 0.0;
+      out[jb.out_off + R] = b + alpha * s;
+    }
   }
 }
 
@@ -967,13 +1029,13 @@ __global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq
 }
 
 __global__ void __launch_bounds__(256) k_pcg_check(const double* part_rr, int npart,
-                                                   PcgScalars* st, double tol2, int it) {
+                                                   PcgScalars* st, double tol2) {
   if (st->done) return;
   __shared__ double sh[1];
   const double rr = sum_partials(part_rr, npart, sh);
   if (threadIdx.x == 0) {
     st->rr = rr;
-    st->iters = it + 1;
+    st->iters += 1;
     if (rr <= tol2 * st->dd) st->done = 1;
   }
 }
@@ -1175,9 +1237,9 @@ void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int
   hipLaunchKernelGGL(k_pcg_update, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, ppq, npart, stt,
                      par, lam, r, p, Fp, prr);
 }
-void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2, int it,
+void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
                       hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, st, prr, npart, stt, tol2, it);
+  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, st, prr, npart, stt, tol2);
 }
 void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
                         const double* z, hipStream_t st) {

@@ -23,7 +23,9 @@ TCF_FP64, TCF_FP32_IR = 0, 1
 
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
            "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_stats",
-           "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_destroy"]
+           "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
+           "tcf_profile_get", "tcf_destroy"]
+KERNEL_GROUPS = ["apply", "precond", "phi", "coarse", "condense", "recover"]
 
 PHI_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), C.c_int32,
                      C.POINTER(C.c_double), C.c_int32, C.c_int32, C.POINTER(C.c_double),
@@ -91,6 +93,9 @@ def lib():
                                    C.POINTER(C.c_double)]
     L.tcf_get_state.argtypes = [P, P, C.POINTER(C.c_size_t), P]
     L.tcf_set_state.argtypes = [P, P, C.c_size_t, P]
+    L.tcf_profile_enable.argtypes = [P, C.c_int32]
+    L.tcf_profile_get.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_double)]
     L.tcf_destroy.argtypes = [P]
     L.tcf_destroy.restype = None
     for n in EXPORTS:
@@ -256,6 +261,18 @@ class Problem:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         return self._check(lib().tcf_set_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size,
                                                self._stream(stream)))
+
+    def tcf_profile_enable(self, on=True):
+        return self._check(lib().tcf_profile_enable(self.h, int(bool(on))))
+
+    def tcf_profile_get(self):
+        """{group: (total_ms, launches, algorithmic bytes per launch)}"""
+        out = {}
+        for g, name in enumerate(KERNEL_GROUPS):
+            ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+            self._check(lib().tcf_profile_get(self.h, g, C.byref(ms), C.byref(n), C.byref(b)))
+            out[name] = (ms.value, n.value, b.value)
+        return out
 
     def tcf_destroy(self):
         if getattr(self, "h", None):
