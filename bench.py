@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="uneven", choices=["uneven", "plain", "mixed", "largest"])
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir", "fp32_full_ir"])
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="steps after the timed run with per-kernel HIP-event timing")
     ap.add_argument("--check-steps", type=int, default=2,

@@ -51,9 +51,14 @@ enum tcf_status {
 };
 
 enum tcf_precision {
-  TCF_FP64 = 0,      /* all local factors and applies in FP64                */
-  TCF_FP32_IR = 1    /* local factors / Schur applies FP32, PCG, coarse     */
-                     /* solve and refinement residual FP64                   */
+  TCF_FP64 = 0,         /* local factors and Schur operators in FP64          */
+  TCF_FP32_IR = 1,      /* local factors in FP64, the explicit Schur operators */
+                        /* (S_bb^-1, Phi_b, S_bb, condensation) stored and     */
+                        /* applied in FP32; PCG, coarse solve and refinement   */
+                        /* residual in FP64                                    */
+  TCF_FP32_FULL_IR = 2  /* as TCF_FP32_IR but the local factorisation is FP32 */
+                        /* too (converges only where the local blocks are well */
+                        /* conditioned, e.g. conductors)                       */
 };
 
 /*
@@ -87,8 +92,11 @@ typedef struct tcf_options {
   int32_t precision;        /* TCF_FP64 or TCF_FP32_IR                        */
   double pcg_rtol;          /* stop when ||r||_2 <= pcg_rtol * ||d||_2        */
   int32_t pcg_maxit;        /* <= 0: max(1000, n_lambda)                      */
-  double ir_rtol;           /* FP32 path: stop when ||f - W a|| <= ir_rtol||f||*/
-  int32_t ir_maxit;         /* FP32 path: refinement sweeps, <= 0: 10         */
+  double ir_rtol;           /* FP32 paths: refine (>= 1 correction) until the  */
+                            /* estimated field error (last correction times    */
+                            /* the observed contraction) <= ir_rtol ||a||      */
+  int32_t ir_maxit;         /* FP32 path: solves per step incl. the first,    */
+                            /* <= 0: 10                                        */
   int32_t check_every;      /* PCG iterations between host convergence reads  */
   int32_t use_graph;        /* 1: replay captured hipGraphs for PCG chunks    */
 } tcf_options;
@@ -172,7 +180,8 @@ typedef struct tcf_stats {
   int32_t nonconverged_steps;
   int32_t fail_patch;          /* non-SPD patch, -1 coarse, -2 none              */
   double last_rel_residual;    /* ||r||/||d|| of the last PCG solve              */
-  double last_ir_residual;     /* ||f - W a||/||f|| after the last step (FP32)   */
+  double last_ir_residual;     /* assembled ||f - W a||/||f|| after the last     */
+                               /* step (FP32 path; FP64 operator, matrix-free)   */
   double setup_ms;
   double step_ms_total;
   size_t device_bytes;

@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -117,6 +118,9 @@ struct tcf_problem {
 
   // ---- device state ----------------------------------------------------------
   int precision = TCF_FP64;
+  double pcg_tol = 1e-10;  // effective PCG tolerance (FP32 path: at least 1e-7, refined after)
+  bool trace = false;      // TCF_TRACE=1: refinement sweeps on stderr
+  bool fp64_ir = false;    // TCF_FP64_IR=1: refine the FP64 path too (diagnostic)
   bool is_setup = false;
   int device = 0;
   std::vector<DevBuf> bufs;
@@ -126,12 +130,19 @@ struct tcf_problem {
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
   signed char *d_bsgn = nullptr, *d_isint = nullptr;
   int64_t* d_rgid = nullptr;
+  int *d_posp_r = nullptr, *d_posm_r = nullptr;  // multiplier -> kept-order position of its copies
   int *d_posp = nullptr, *d_posm = nullptr, *d_cptr = nullptr, *d_cidx_bp = nullptr,
       *d_cidx_r = nullptr, *d_b2bp = nullptr, *d_p2r = nullptr, *d_b2r = nullptr;
   double *d_gx = nullptr, *d_gw = nullptr, *d_tabs = nullptr, *d_ptab = nullptr;
   void *d_G = nullptr, *d_S = nullptr, *d_Q = nullptr;  // T-typed
   double *d_SPinv = nullptr;
   double *d_a = nullptr, *d_fM = nullptr, *d_ygg = nullptr, *d_yggs = nullptr, *d_zr = nullptr;
+  double *d_jr = nullptr, *d_floc = nullptr, *d_res = nullptr, *d_delta = nullptr;
+  int *d_kptr = nullptr, *d_kidx = nullptr;  // kept global unknown -> its local copies
+  int n_kept_i = 0;
+  double *d_nrm_part = nullptr, *d_nrm = nullptr, *h_nrm = nullptr;  // norms (pinned host copy)
+  int *d_all = nullptr, *d_all_cprefix = nullptr, *d_all_rprefix = nullptr;
+  int nt_all_c = 0, nt_all_r = 0;
   double *d_uc = nullptr, *d_vc = nullptr, *d_wb = nullptr, *d_tb = nullptr;
   double *d_h = nullptr, *d_q0 = nullptr, *d_cv = nullptr, *d_q = nullptr;
   double *d_d = nullptr, *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr,
@@ -207,6 +218,7 @@ struct tcf_problem {
     for (auto& b : bufs)
       if (b.p) (void)hipFree(b.p);
     if (h_st) (void)hipHostFree(h_st);
+    if (h_nrm) (void)hipHostFree(h_nrm);
   }
 
   template <class T>
@@ -273,7 +285,7 @@ static inline void timed(tcf_problem* h, int g, hipStream_t st, F&& f) {
 
 // Algorithmic bytes of one launch of each kernel group (see tcf.h).
 static void compute_alg_bytes(tcf_problem* h) {
-  const double w = h->precision == TCF_FP64 ? 8.0 : 4.0;
+  const double w = h->precision == TCF_FP64 ? 8.0 : 4.0;  // operator storage
   double app = 0, pre = 0, phi = 0, cond = 0, rec = 0;
   for (int s = 0; s < h->np_tot; ++s) {
     const DevPatch& d = h->hp[s];
@@ -396,13 +408,21 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   std::unique_ptr<tcf_problem> h(new (std::nothrow) tcf_problem());
   if (!h) { g_create_error = "out of host memory"; return TCF_ENOMEM; }
   if (opts) h->opt = *opts; else tcf_default_options(&h->opt);
-  if (h->opt.precision != TCF_FP64 && h->opt.precision != TCF_FP32_IR) {
+  if (h->opt.precision != TCF_FP64 && h->opt.precision != TCF_FP32_IR &&
+      h->opt.precision != TCF_FP32_FULL_IR) {
     g_create_error = "unknown precision"; return TCF_EINVAL;
   }
   if (!(h->opt.pcg_rtol > 0)) { g_create_error = "pcg_rtol <= 0"; return TCF_EINVAL; }
   if (h->opt.check_every <= 0) h->opt.check_every = 8;
   if (h->opt.ir_maxit <= 0) h->opt.ir_maxit = 10;
   h->precision = h->opt.precision;
+  h->pcg_tol = h->precision == TCF_FP64 ? h->opt.pcg_rtol : std::max(h->opt.pcg_rtol, 1e-7);
+  {
+    const char* tr = std::getenv("TCF_TRACE");
+    h->trace = tr && tr[0] == '1';
+    const char* fi = std::getenv("TCF_FP64_IR");
+    h->fp64_ir = fi && fi[0] == '1';
+  }
   for (int a = 0; a < 3; ++a) {
     h->np[a] = desc->np[a];
     h->breaks[a].assign(desc->breaks[a], desc->breaks[a] + desc->np[a] + 1);
@@ -623,6 +643,7 @@ static int build_index_tables(tcf_problem* h) {
   const int np = h->np_tot;
   const int rows_per_stripe = 64 * (h->precision == TCF_FP64 ? 2 : 4);
   std::vector<int> rloc, loc2r, brow, prank, posp(h->n_lambda), posm(h->n_lambda), b2bp, p2r, b2r;
+  std::vector<int> posp_r(h->n_lambda), posm_r(h->n_lambda);
   std::vector<signed char> bsgn, isint;
   std::vector<int64_t> rgid;
   for (int s = 0; s < np; ++s) {
@@ -636,8 +657,13 @@ static int build_index_tables(tcf_problem* h) {
       bsgn.push_back((signed char)pp.b_sgn[k]);
       b2bp.push_back(d.bp_off + k);
       b2r.push_back(d.r_off + pp.n_i + k);
-      if (pp.b_sgn[k] > 0) posp[pp.b_row[k]] = d.b_off + k;
-      else posm[pp.b_row[k]] = d.b_off + k;
+      if (pp.b_sgn[k] > 0) {
+        posp[pp.b_row[k]] = d.b_off + k;
+        posp_r[pp.b_row[k]] = d.r_off + pp.n_i + k;
+      } else {
+        posm[pp.b_row[k]] = d.b_off + k;
+        posm_r[pp.b_row[k]] = d.r_off + pp.n_i + k;
+      }
     }
     for (int j = 0; j < pp.n_p; ++j) {
       prank.push_back(pp.p_rank[j]);
@@ -667,6 +693,8 @@ static int build_index_tables(tcf_problem* h) {
   RCCHK(h->upload(&h->d_prank, prank));
   RCCHK(h->upload(&h->d_posp, posp));
   RCCHK(h->upload(&h->d_posm, posm));
+  RCCHK(h->upload(&h->d_posp_r, posp_r));
+  RCCHK(h->upload(&h->d_posm_r, posm_r));
   RCCHK(h->upload(&h->d_cptr, cptr));
   RCCHK(h->upload(&h->d_cidx_bp, cbp));
   RCCHK(h->upload(&h->d_cidx_r, cr));
@@ -955,9 +983,58 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   launch_condense<T>(h->dP, d_all, d_apre, np, apre.back(), nrhs, h->max_ni, Q, jr, h->d_yggs, ldv, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
-  h->release(d_all);
-  h->release(d_apre);
-  h->release(jr);
+  h->d_all = d_all;
+  h->d_all_cprefix = d_apre;
+  h->nt_all_c = apre.back();
+  {
+    std::vector<int> rc(np);
+    for (int s = 0; s < np; ++s) rc[s] = h->hp[s].n_r;
+    auto rp = prefix_of(rc);
+    h->nt_all_r = rp.back();
+    RCCHK(h->upload(&h->d_all_rprefix, rp));
+  }
+  h->d_jr = jr;
+  // refinement work vectors and the kept-unknown -> local-copies map
+  RCCHK(h->alloc(&h->d_floc, (size_t)ldv));
+  RCCHK(h->alloc(&h->d_res, (size_t)ldv));
+  RCCHK(h->alloc(&h->d_delta, (size_t)ldv));
+  {
+    std::vector<std::vector<int>> copies;
+    std::vector<int64_t> kept_ids;
+    std::vector<int> where(h->g.n_edges(), -1);
+    for (int s = 0; s < np; ++s) {
+      const PatchPlan& pp = h->plans[s];
+      for (int j = 0; j < pp.n_r(); ++j) {
+        const int64_t e = pp.r_gid[j];
+        if (where[e] < 0) { where[e] = (int)copies.size(); copies.emplace_back(); }
+        copies[where[e]].push_back(h->hp[s].r_off + j);
+      }
+    }
+    std::vector<int> kp(1, 0), ki;
+    for (auto& c : copies) { ki.insert(ki.end(), c.begin(), c.end()); kp.push_back((int)ki.size()); }
+    h->n_kept_i = (int)copies.size();
+    RCCHK(h->upload(&h->d_kptr, kp));
+    RCCHK(h->upload(&h->d_kidx, ki));
+    RCCHK(h->alloc(&h->d_nrm_part, (size_t)(h->n_kept_i + 255) / 256 + 1));
+    RCCHK(h->alloc(&h->d_nrm, 4));
+    HIPCHK(hipHostMalloc((void**)&h->h_nrm, 4 * sizeof(double), hipHostMallocDefault));
+  }
+  return TCF_OK;
+}
+
+// FP32_IR: the Schur operators were built in FP64; keep FP32 copies only.
+static int demote_operators(tcf_problem* h, hipStream_t st) {
+  void** bufs[3] = {&h->d_G, &h->d_S, &h->d_Q};
+  const int64_t counts[3] = {h->G_elems, h->S_elems, h->Q_elems};
+  for (int i = 0; i < 3; ++i) {
+    float* f = nullptr;
+    RCCHK(h->alloc(&f, (size_t)counts[i]));
+    launch_to_float(counts[i], (const double*)*bufs[i], f, st);
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(*bufs[i]);
+    *bufs[i] = f;
+  }
+  HIPCHK(hipGetLastError());
   return TCF_OK;
 }
 
@@ -967,7 +1044,13 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipGetDevice(&h->device));
   const double t0 = now_ms();
-  int rc = h->precision == TCF_FP64 ? setup_impl<double>(h, st) : setup_impl<float>(h, st);
+  int rc;
+  if (h->precision == TCF_FP32_FULL_IR) {
+    rc = setup_impl<float>(h, st);
+  } else {
+    rc = setup_impl<double>(h, st);
+    if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
+  }
   if (rc) return rc;
   h->setup_ms = now_ms() - t0;
   h->is_setup = true;
@@ -1034,7 +1117,7 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
   double* p_pq = h->d_part;
   double* p_rr = h->d_part + npt;
   double* p_rz = h->d_part + 2 * npt;
-  const double tol2 = h->opt.pcg_rtol * h->opt.pcg_rtol;
+  const double tol2 = h->pcg_tol * h->pcg_tol;
   apply_F<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
   launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
   launch_pcg_check(p_rr, npt, h->d_st, tol2, st);
@@ -1106,26 +1189,38 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bo
   return TCF_OK;
 }
 
-// One implicit Euler step for excitation k: a_k <- solve(W, M a_k + dt g_k jhat_k)
+// Dual-primal solve of W x = f for one excitation, the right-hand side
+// given per patch (kept order).  rhs == nullptr selects the time-step form
+// f = M a_k + dt g_k(t_{l+1}) jhat_k, whose source part was condensed at
+// setup; otherwise f = rhs (all patches condensed).  The solution is
+// written to x_out (kept order).  If base != nullptr, x_out is a correction
+// to base and the interface constraint is Bhat (base + x) = 0, i.e. the dual
+// right-hand side becomes d + Bhat base.
 template <class T>
-static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bool& conv) {
+static int solve_local(tcf_problem* h, int k, int l, const double* rhs, double* x_out,
+                       hipStream_t st, int& iters, bool& conv, const double* base = nullptr) {
   const int64_t ldv = h->n_rtot;
-  double* a = h->d_a + (int64_t)k * ldv;
-  double* fM = h->d_fM + (int64_t)k * ldv;
   double* ygg = h->d_ygg + (int64_t)k * ldv;
-  const double* yggs = h->d_yggs + (int64_t)k * ldv;
   const T* G = (const T*)h->d_G;
   const T* Q = (const T*)h->d_Q;
-  // f = M a (conductor patches) ; [y; g_b; g_p] = cond(f) + dt g jhat-condensed
-  const double gk = h->amp[(size_t)k * h->n_steps + l];
-  launch_axpby(ldv, h->dt * gk, yggs, 0.0, ygg, st);
-  if (!h->cond_list.empty()) {
-    launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
-                  h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
-    timed(h, TCF_KG_CONDENSE, st, [&] {
-      launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
-                         h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
-    });
+  if (!rhs) {
+    double* a = h->d_a + (int64_t)k * ldv;
+    double* fM = h->d_fM + (int64_t)k * ldv;
+    const double* yggs = h->d_yggs + (int64_t)k * ldv;
+    const double gk = h->amp[(size_t)k * h->n_steps + l];
+    launch_axpby(ldv, h->dt * gk, yggs, 0.0, ygg, st);
+    if (!h->cond_list.empty()) {
+      launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
+                    h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
+      timed(h, TCF_KG_CONDENSE, st, [&] {
+        launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
+                           h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
+      });
+    }
+  } else {
+    launch_axpby(ldv, 0.0, rhs, 0.0, ygg, st);
+    launch_condense<T>(h->dP, h->d_all, h->d_all_cprefix, h->np_tot, h->nt_all_c, 1, h->max_ni, Q,
+                       rhs, ygg, ldv, st);
   }
   // [u; c0] = G^T g_b ; h = sum N^T (g_p - c0) ; q0 = S_Pi^-1 h ; d = jump(u - Phi N q0)
   launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
@@ -1139,6 +1234,17 @@ static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bo
   phi_apply<T>(h, h->d_uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, h->d_d, nullptr, nullptr,
               nullptr, st);
+  auto trace_vec = [&](const char* what, const double* v, int n) {
+    std::vector<double> hv(n);
+    (void)hipMemcpyAsync(hv.data(), v, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+    (void)hipStreamSynchronize(st);
+    double s2 = 0;
+    for (double x : hv) s2 += x * x;
+    std::fprintf(stderr, "[tcf]   %s %.3e\n", what, std::sqrt(s2));
+  };
+  if (base && h->trace) trace_vec("|d(r)|", h->d_d, h->n_lambda);
+  if (base) launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, h->d_d, st);
+  if (base && h->trace) trace_vec("|d(r)+Bhat a|", h->d_d, h->n_lambda);
   double rel = 0.0;
   RCCHK(pcg_solve<T>(h, st, iters, rel, conv));
   h->last_rel = rel;
@@ -1149,22 +1255,129 @@ static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, bo
   else
     HIPCHK(hipMemsetAsync(h->d_vc, 0, sizeof(double) * std::max<int64_t>(h->n_bptot, 1), st));
   coarse_solve(h, h->d_vc, h->d_h, h->d_q, nullptr, st);
-  // a_b = (u - v) - Phi N p ;  a_p = N p
+  // x_b = (u - v) - Phi N p ;  x_p = N p
   launch_sub_gather((int)h->n_btot, h->d_b2bp, h->d_uc, h->d_b2bp, h->d_vc, h->d_tb, st);
-  launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, a, nullptr, st);
+  launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, x_out, nullptr, st);
   if (h->n_primal > 0) {
     if (h->nj_phi > 0)
       launch_axpyrows<T>(h->aj_ab, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, G, h->d_q,
-                         h->d_prank, a, h->a_boff_ab, -1.0, a, 0, nullptr, st);
-    launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, a, nullptr, st);
+                         h->d_prank, x_out, h->a_boff_ab, -1.0, x_out, 0, nullptr, st);
+    launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, x_out, nullptr, st);
   }
-  // a_i = L_ii^-T (y - L_bi^T a_b - L_pi^T a_p) = Q^T [y; -a_b; -a_p]
-  launch_build_z(ldv, h->d_isint, ygg, a, h->d_zr, st);
+  // x_i = L_ii^-T (y - L_bi^T x_b - L_pi^T x_p) = Q^T [y; -x_b; -x_p]
+  launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr, st);
   timed(h, TCF_KG_RECOVER, st, [&] {
     launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
-                       nullptr, h->a_boff_ai, 1.0, a, 1, nullptr, st);
+                       nullptr, h->a_boff_ai, 1.0, x_out, 1, nullptr, st);
   });
+  if (h->trace && h->n_lambda > 0) {
+    HIPCHK(hipMemsetAsync(h->d_Fp, 0, sizeof(double) * h->n_lambda, st));
+    launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, x_out, h->dt, h->d_Fp, st);
+    trace_vec("|Bhat x|", h->d_Fp, h->n_lambda);
+    if (base) {
+      launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, h->d_Fp, st);
+      trace_vec("|Bhat (base + x)|", h->d_Fp, h->n_lambda);
+    }
+  }
   HIPCHK(hipGetLastError());
+  return TCF_OK;
+}
+
+// Squared global norm of a kept-ordered vector into h_nrm[slot] (syncs):
+// assembled (sum of local copies) for residuals, first copy for fields.
+static int asm_norm2(tcf_problem* h, const double* x, int first_copy, int slot, hipStream_t st) {
+  launch_asm_norm2(h->n_kept_i, h->d_kptr, h->d_kidx, x, first_copy, h->d_nrm_part,
+                   h->d_nrm + slot, st);
+  HIPCHK(hipMemcpyAsync(h->h_nrm + slot, h->d_nrm + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return TCF_OK;
+}
+
+// One implicit Euler step for excitation k.  FP64: one dual-primal solve.
+// FP32 operators: refinement a <- a + solve(f - W a) with the residual of
+// the FP64 operator (matrix-free per patch, double-double row sums),
+// assembled and split evenly over interface copies, the correction also
+// closing the interface jump left in a.  At least one correction; stop when
+// the estimated remaining error (last correction times the observed
+// contraction, relative to the field) is <= ir_rtol.  The final assembled
+// residual ||f - W a|| / ||f|| is reported in the stats.
+template <class T>
+static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, int& sweeps,
+                    bool& conv) {
+  const int64_t ldv = h->n_rtot;
+  double* a = h->d_a + (int64_t)k * ldv;
+  iters = 0;
+  sweeps = 0;
+  conv = true;
+  if (h->precision == TCF_FP64 && !h->fp64_ir) {
+    RCCHK(solve_local<T>(h, k, l, nullptr, a, st, iters, conv));
+    return TCF_OK;
+  }
+  // f = M a^(l) + dt g jhat (local, FP64)
+  double* fM = h->d_fM + (int64_t)k * ldv;
+  const double gk = h->amp[(size_t)k * h->n_steps + l];
+  if (!h->cond_list.empty())
+    launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
+                  h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
+  HIPCHK(hipMemcpyAsync(h->d_floc, fM, sizeof(double) * ldv, hipMemcpyDeviceToDevice, st));
+  launch_axpby(ldv, h->dt * gk, h->d_jr + (int64_t)k * ldv, 1.0, h->d_floc, st);
+  RCCHK(asm_norm2(h, h->d_floc, 0, 0, st));
+  const double fn = std::sqrt(h->h_nrm[0]);
+  int it = 0;
+  bool c = true;
+  RCCHK(solve_local<T>(h, k, l, nullptr, a, st, it, c));
+  iters += it;
+  conv &= c;
+  sweeps = 1;
+  double rn = 0.0, dn = 0.0, an = 0.0, rel_prev = 0.0, est = 1.0;
+  for (;;) {
+    launch_residual(h->dP, h->d_all, h->d_all_rprefix, h->np_tot, h->nt_all_r, h->d_rloc,
+                    h->d_loc2r, h->d_tabs, h->dt, h->d_floc, a, h->d_res, st);
+    RCCHK(asm_norm2(h, h->d_res, 0, 1, st));
+    rn = std::sqrt(h->h_nrm[1]);
+    if (fn == 0.0 || rn == 0.0) break;
+    if (sweeps >= 2 && est <= h->opt.ir_rtol) break;
+    if (sweeps >= h->opt.ir_maxit) { conv = false; break; }
+    // the correction sees the assembled residual split evenly over copies, so
+    // its dual right-hand side is as small as the true residual and the PCG
+    // tolerance also resolves the interface jump carried over from a
+    launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, h->d_res, st);
+    RCCHK(solve_local<T>(h, k, l, h->d_res, h->d_delta, st, it, c, a));
+    iters += it;
+    conv &= c;
+    launch_axpby(ldv, 1.0, h->d_delta, 1.0, a, st);
+    RCCHK(asm_norm2(h, h->d_delta, 1, 2, st));
+    RCCHK(asm_norm2(h, a, 1, 3, st));
+    dn = std::sqrt(h->h_nrm[2]);
+    an = std::sqrt(h->h_nrm[3]);
+    {
+      // error left after this correction ~ its size times the contraction
+      // of one inexact solve: the first correction's relative size
+      // estimates that contraction, later ones use the observed ratio
+      const double rel = an > 0 ? dn / an : 0.0;
+      const double ratio = rel_prev > 0 ? rel / rel_prev : rel;
+      est = rel * std::min(1.0, ratio);
+      rel_prev = rel;
+    }
+    if (h->trace) {
+      double jn = 0.0;
+      if (h->n_lambda > 0) {
+        std::vector<double> jv(h->n_lambda);
+        HIPCHK(hipMemsetAsync(h->d_Fp, 0, sizeof(double) * h->n_lambda, st));
+        launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, a, 1.0, h->d_Fp, st);
+        HIPCHK(hipMemcpyAsync(jv.data(), h->d_Fp, sizeof(double) * h->n_lambda,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (double v : jv) jn += v * v;
+      }
+      std::fprintf(stderr,
+                   "[tcf] step %d rhs %d sweep %d: |r|/|f| %.3e  |da|/|a| %.3e  |Ba|/|a| %.3e  pcg %d%s\n",
+                   l, k, sweeps, rn / fn, dn / std::max(an, 1e-300), std::sqrt(jn) / std::max(an, 1e-300),
+                   it, c ? "" : " (not converged)");
+    }
+    ++sweeps;
+  }
+  h->last_ir_res = fn > 0 ? rn / fn : 0.0;
   return TCF_OK;
 }
 
@@ -1174,15 +1387,17 @@ static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
   for (int s = 0; s < nsteps; ++s) {
     const int l = h->steps_done;
     const double t0 = now_ms();
-    int it_sum = 0;
+    int it_sum = 0, ir_sum = 0;
     bool all_conv = true;
     for (int k = 0; k < h->n_rhs; ++k) {
-      int iters = 0;
+      int iters = 0, sweeps = 0;
       bool conv = true;
-      RCCHK(step_one<T>(h, k, l, st, iters, conv));
+      RCCHK(step_one<T>(h, k, l, st, iters, sweeps, conv));
       it_sum += iters;
+      ir_sum += sweeps;
       all_conv &= conv;
       h->last_iters = iters;
+      h->last_ir = sweeps;
       h->max_iters = std::max(h->max_iters, iters);
       h->total_iters += iters;
     }
@@ -1192,10 +1407,10 @@ static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
     if (!all_conv) {
       ++h->nonconv;
       status = TCF_ENOCONV;
-      h->err = "PCG reached its iteration limit at step " + std::to_string(l);
+      h->err = "PCG or refinement reached its iteration limit at step " + std::to_string(l);
     }
     h->log_iters.push_back(it_sum);
-    h->log_ir.push_back(0);
+    h->log_ir.push_back(ir_sum);
     h->log_ms.push_back(ms);
     h->step_ms_total += ms;
     h->steps_done++;
@@ -1213,7 +1428,7 @@ int tcf_step(tcf_problem* h, int32_t nsteps, void* stream) {
   if (nsteps <= 0) return TCF_OK;
   hipStream_t st = (hipStream_t)stream;
   return h->precision == TCF_FP64 ? step_impl<double>(h, nsteps, st)
-                                  : step_impl<float>(h, nsteps, st);
+                                  : step_impl<float>(h, nsteps, st);  // FP32 operators
 }
 
 int tcf_sync(tcf_problem* h, void* stream) {

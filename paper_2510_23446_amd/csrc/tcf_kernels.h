@@ -87,3 +87,23 @@ namespace tcf {
 void launch_build_z(int64_t n, const signed char* is_int, const double* y, const double* a,
                     double* zr, hipStream_t st);
 }  // namespace tcf
+namespace tcf {
+void launch_asm_norm2(int n, const int* ptr, const int* idx, const double* x, int first_copy,
+                      double* partial, double* out, hipStream_t st);
+void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t st);
+}  // namespace tcf
+namespace tcf {
+void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st);
+}  // namespace tcf
+namespace tcf {
+void launch_residual(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                     int total_rows, const int* r_loc, const int* loc2r, const double* tabs,
+                     double dt, const double* f, const double* x, double* r, hipStream_t st);
+}  // namespace tcf
+namespace tcf {
+void launch_jump_add(int n, const int* pp, const int* pm, const double* a, double scale, double* y,
+                     hipStream_t st);
+}  // namespace tcf
+namespace tcf {
+void launch_assemble_split(int n, const int* ptr, const int* idx, double* x, hipStream_t st);
+}  // namespace tcf

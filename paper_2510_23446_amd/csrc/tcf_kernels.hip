@@ -1319,3 +1319,150 @@ void launch_build_z(int64_t n, const signed char* is_int, const double* y, const
   hipLaunchKernelGGL(k_build_z, TCF_GRID(n, 256), dim3(256), 0, st, n, is_int, y, a, zr);
 }
 }  // namespace tcf
+
+namespace tcf {
+// Assembled squared norm: the global value of kept unknown k is the sum of
+// its local copies x[idx[ptr[k] .. ptr[k+1]]]; partial[block] = sum of squares.
+// first_copy != 0: the value is the first copy only (vectors whose copies
+// agree, such as fields), otherwise the sum of copies (assembled residuals).
+__global__ void __launch_bounds__(256) k_asm_norm2(int n, const int* ptr, const int* idx,
+                                                   const double* x, int first_copy,
+                                                   double* partial) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (k < n) {
+    const int t1 = first_copy ? ptr[k] + 1 : ptr[k + 1];
+    for (int t = ptr[k]; t < t1; ++t) v += x[idx[t]];
+    v = v * v;
+  }
+  const double s = block_sum256(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+__global__ void __launch_bounds__(256) k_sum_partials(const double* partial, int npart,
+                                                      double* out) {
+  __shared__ double sh[1];
+  const double s = sum_partials(partial, npart, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+// out = a - b (elementwise)
+__global__ void k_sub(int64_t n, const double* a, const double* b, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+void launch_asm_norm2(int n, const int* ptr, const int* idx, const double* x, int first_copy,
+                      double* partial, double* out, hipStream_t st) {
+  const int nb = (n + 255) / 256;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_asm_norm2, dim3(nb), dim3(256), 0, st, n, ptr, idx, x, first_copy, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, nb, out);
+}
+void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_sub, TCF_GRID(n, 256), dim3(256), 0, st, n, a, b, out);
+}
+}  // namespace tcf
+
+namespace tcf {
+__global__ void k_to_float(int64_t n, const double* a, float* b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_to_float, TCF_GRID(n, 256), dim3(256), 0, st, n, a, b);
+}
+}  // namespace tcf
+
+namespace tcf {
+// Residual r = f - W x on the kept unknowns of every listed patch, with the
+// row sums accumulated in double-double (exact products by FMA, error-free
+// additions), so that the rounding of a sum with heavy cancellation does not
+// leak into the near-kernel of the gauged operator.
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__global__ void k_residual(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                           const int* r_loc, const int* loc2r, const double* tabs, double dt,
+                           const double* f, const double* x, double* r) {
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= row_prefix[nlist]) return;
+  const int li = find_job(row_prefix, nlist, gi);
+  const DevPatch& pp = P[plist[li]];
+  const int j = gi - row_prefix[li];
+  const Tab1 X = make_tab(pp, tabs, 0), Y = make_tab(pp, tabs, 1), Z = make_tab(pp, tabs, 2);
+  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+  const double* xs = x + pp.r_off;
+  const int* l2r = loc2r + pp.loc_off;
+  double hi = 0.0, lo = 0.0;
+  const int px = pp.deg[0], py = pp.deg[1], pz = pp.deg[2];
+  const double nudt = pp.nu * dt;
+  for (int dir = 0; dir < 3; ++dir) {
+    const int na = pp.m[0] - (dir == 0), nb = pp.m[1] - (dir == 1), nc = pp.m[2] - (dir == 2);
+    const int a0 = max(0, u.a - px), a1 = min(na - 1, u.a + px);
+    const int b0 = max(0, u.b - py), b1 = min(nb - 1, u.b + py);
+    const int c0 = max(0, u.c - pz), c1 = min(nc - 1, u.c + pz);
+    for (int c = c0; c <= c1; ++c)
+      for (int b = b0; b <= b1; ++b)
+        for (int a = a0; a <= a1; ++a) {
+          const int r2 = l2r[encode_local(pp, dir, a, b, c)];
+          if (r2 < 0) continue;
+          double M, K;
+          mk_entry(X, Y, Z, u, EdgeCode{dir, a, b, c}, M, K);
+          const double w = pp.sigma * M + nudt * K;
+          const double p = w * xs[r2];
+          const double pe = fma(w, xs[r2], -p);
+          double s, e;
+          two_sum(hi, p, s, e);
+          hi = s;
+          lo += e + pe;
+        }
+  }
+  // r = f - (hi + lo)
+  double s, e;
+  two_sum(f[pp.r_off + j], -hi, s, e);
+  r[pp.r_off + j] = s + (e - lo);
+}
+void launch_residual(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
+                     int total_rows, const int* r_loc, const int* loc2r, const double* tabs,
+                     double dt, const double* f, const double* x, double* r, hipStream_t st) {
+  if (total_rows == 0) return;
+  hipLaunchKernelGGL(k_residual, dim3((total_rows + 127) / 128), dim3(128), 0, st, P, plist,
+                     row_prefix, nlist, r_loc, loc2r, tabs, dt, f, x, r);
+}
+}  // namespace tcf
+
+namespace tcf {
+// y[i] += scale * (a[pp[i]] - a[pm[i]])  (jump of a kept-ordered vector)
+__global__ void k_jump_add(int n, const int* pos_p, const int* pos_m, const double* a, double scale,
+                           double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += scale * (a[pos_p[i]] - a[pos_m[i]]);
+}
+void launch_jump_add(int n, const int* pp, const int* pm, const double* a, double scale, double* y,
+                     hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_jump_add, TCF_GRID(n, 256), dim3(256), 0, st, n, pp, pm, a, scale, y);
+}
+}  // namespace tcf
+
+namespace tcf {
+// Replace every local copy of kept unknown k by (sum of its copies) / count,
+// i.e. assemble a residual and split it evenly over the patches sharing k.
+__global__ void k_assemble_split(int n, const int* ptr, const int* idx, double* x) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int t0 = ptr[k], t1 = ptr[k + 1];
+  if (t1 - t0 < 2) return;
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) v += x[idx[t]];
+  v /= (double)(t1 - t0);
+  for (int t = t0; t < t1; ++t) x[idx[t]] = v;
+}
+void launch_assemble_split(int n, const int* ptr, const int* idx, double* x, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_assemble_split, TCF_GRID(n, 256), dim3(256), 0, st, n, ptr, idx, x);
+}
+}  // namespace tcf

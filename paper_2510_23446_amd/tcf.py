@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtcf.so")
 
 TCF_OK, TCF_EINVAL, TCF_ENOMEM, TCF_ENOTSPD, TCF_ENOCONV, TCF_EHIP, TCF_ESTATE = 0, -1, -2, -3, -4, -5, -6
-TCF_FP64, TCF_FP32_IR = 0, 1
+TCF_FP64, TCF_FP32_IR, TCF_FP32_FULL_IR = 0, 1, 2
+PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32_FULL_IR}
 (TCF_TOPO_COUNTS, TCF_TOPO_DIRICHLET, TCF_TOPO_TREE_I, TCF_TOPO_TREE_GAMMA, TCF_TOPO_PRIMAL,
  TCF_TOPO_DUAL, TCF_TOPO_INTERIOR, TCF_TOPO_MULT, TCF_TOPO_N) = range(9)
 
@@ -171,7 +172,7 @@ class Problem:
         self._desc = d
         prec = precision if precision is not None else prob.precision
         o = default_options(
-            precision=TCF_FP64 if prec in ("fp64", TCF_FP64) else TCF_FP32_IR,
+            precision=PRECISIONS[prec] if isinstance(prec, str) else int(prec),
             pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
             pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
             check_every=int(check_every), use_graph=int(use_graph))

@@ -33,7 +33,7 @@ def _run_and_compare(prob, tol, rtol=None, steps=None, every=1):
                 err = np.linalg.norm(a - r) / np.linalg.norm(r)
                 worst = max(worst, err)
     st = p.tcf_get_stats()
-    print(f"[parity] {prob.name} worst rel err {worst:.3e} last iters {st['last_pcg_iters']}", flush=True)
+    print(f"[parity] {prob.name} {prob.precision} worst rel err {worst:.3e} last iters {st['last_pcg_iters']} ir {st['last_ir_sweeps']} ir_res {st['last_ir_residual']:.2e}", flush=True)
     assert worst <= tol, worst
     return worst, st
 
@@ -55,4 +55,34 @@ def test_plain_fp64_all_steps():
 
 def test_uneven_reduced_seeded():
     prob = W.uneven_fp64(seed=1, n_steps=3, P=(3, 3, 3))
+    _run_and_compare(prob, 1e-9)
+
+
+# ---- FP32 factors + FP64 refinement ------------------------------------------
+@pytest.mark.parametrize("mode", ["fp32_ir", "fp32_full_ir"])
+@pytest.mark.parametrize("name", ["cond_bottom_p2", "floating_p2", "checker", "all_insulator"])
+def test_tiny_fp32_ir(name, mode):
+    P, n, p, sig = CASES[name]
+    prob = tiny(P, n, p, sig)
+    prob.precision = mode
+    worst, st = _run_and_compare(prob, 1e-8)
+    assert st["nonconverged_steps"] == 0
+
+
+def test_plain_fp32_ir():
+    prob = W.plain_fp64()
+    prob.precision = "fp32_ir"
+    worst, st = _run_and_compare(prob, 1e-8)
+    assert st["last_ir_sweeps"] >= 1 and st["nonconverged_steps"] == 0
+
+
+@pytest.mark.parametrize("mode", ["fp32_ir", "fp32_full_ir"])
+def test_floating_reduced_fp32_ir(mode):
+    """The floating-conductor layout (central 2x2x2 block) at n=4."""
+    prob = W.floating_mixed(n=4, p=3, n_steps=3, precision=mode)
+    _run_and_compare(prob, 1e-8)
+
+
+def test_floating_reduced_fp64():
+    prob = W.floating_mixed(n=4, p=3, n_steps=3, precision="fp64")
     _run_and_compare(prob, 1e-9)
