@@ -246,6 +246,29 @@ def poisson_arrivals(n_req: int, rate: float, seed: int = 33) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=n_req))
 
 
+def subproblem(prob: Problem, lo=(0, 0, 0), P=(2, 2, 2)) -> Problem:
+    """The same problem restricted to the block of P patch rows starting at
+    lo in each direction (same rows, materials, source and time grid)."""
+    lo = tuple(int(v) for v in lo)
+    P = tuple(min(int(P[d]), int(prob.np[d]) - lo[d]) for d in range(3))
+    ids = []
+    for k in range(P[2]):
+        for j in range(P[1]):
+            for i in range(P[0]):
+                ids.append((lo[0] + i) + prob.np[0] * ((lo[1] + j) + prob.np[1] * (lo[2] + k)))
+    ids = np.array(ids)
+    q = Problem(**{k: getattr(prob, k) for k in prob.__dataclass_fields__})
+    q.name = f"{prob.name}_sub{P[0]}x{P[1]}x{P[2]}"
+    q.np = P
+    q.breaks = [np.asarray(prob.breaks[d][lo[d]:lo[d] + P[d] + 1]) for d in range(3)]
+    q.nel = [np.asarray(prob.nel[d][lo[d]:lo[d] + P[d]]) for d in range(3)]
+    q.deg = [np.asarray(prob.deg[d][lo[d]:lo[d] + P[d]]) for d in range(3)]
+    q.sigma = np.asarray(prob.sigma)[ids]
+    q.nu = np.asarray(prob.nu)[ids]
+    q.src_mask = np.asarray(prob.src_mask)[ids]
+    return q
+
+
 WORKLOADS = {
     "plain": plain_fp64,
     "uneven": uneven_fp64,
