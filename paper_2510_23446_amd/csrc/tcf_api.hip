@@ -153,6 +153,16 @@ struct tcf_problem {
   PcgScalars* h_st = nullptr;  // pinned
   int* d_fail = nullptr;
   double* d_field = nullptr;
+  // tile storage of the per-iteration operators (lower triangles of the
+  // symmetric ones): apply = S_bb^-1 and Phi_b tiles, pre = S_bb tiles (T),
+  // coarse = S_Pi^-1 tiles (FP64)
+  void *d_tA = nullptr, *d_tB = nullptr;
+  double* d_tC = nullptr;
+  TileJob *tj_apply = nullptr, *tj_phi = nullptr, *tj_pre = nullptr, *tj_coarse = nullptr;
+  int n_tapply = 0, n_tphi = 0, n_tpre = 0, n_tcoarse = 0;
+  double* d_acc = nullptr;  // vc | q | tb accumulators of the tile path
+  int *d_posp_bp = nullptr, *d_posm_bp = nullptr;
+  bool use_tiles = true;
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
 
@@ -420,6 +430,8 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   {
     const char* tr = std::getenv("TCF_TRACE");
     h->trace = tr && tr[0] == '1';
+    const char* nt = std::getenv("TCF_NO_TILES");
+    h->use_tiles = !(nt && nt[0] == '1');
     const char* fi = std::getenv("TCF_FP64_IR");
     h->fp64_ir = fi && fi[0] == '1';
   }
@@ -644,6 +656,7 @@ static int build_index_tables(tcf_problem* h) {
   const int rows_per_stripe = 64 * (h->precision == TCF_FP64 ? 2 : 4);
   std::vector<int> rloc, loc2r, brow, prank, posp(h->n_lambda), posm(h->n_lambda), b2bp, p2r, b2r;
   std::vector<int> posp_r(h->n_lambda), posm_r(h->n_lambda);
+  std::vector<int> posp_bp(h->n_lambda), posm_bp(h->n_lambda);
   std::vector<signed char> bsgn, isint;
   std::vector<int64_t> rgid;
   for (int s = 0; s < np; ++s) {
@@ -660,7 +673,9 @@ static int build_index_tables(tcf_problem* h) {
       if (pp.b_sgn[k] > 0) {
         posp[pp.b_row[k]] = d.b_off + k;
         posp_r[pp.b_row[k]] = d.r_off + pp.n_i + k;
+        posp_bp[pp.b_row[k]] = d.bp_off + k;
       } else {
+        posm_bp[pp.b_row[k]] = d.bp_off + k;
         posm[pp.b_row[k]] = d.b_off + k;
         posm_r[pp.b_row[k]] = d.r_off + pp.n_i + k;
       }
@@ -694,6 +709,8 @@ static int build_index_tables(tcf_problem* h) {
   RCCHK(h->upload(&h->d_posp, posp));
   RCCHK(h->upload(&h->d_posm, posm));
   RCCHK(h->upload(&h->d_posp_r, posp_r));
+  RCCHK(h->upload(&h->d_posp_bp, posp_bp));
+  RCCHK(h->upload(&h->d_posm_bp, posm_bp));
   RCCHK(h->upload(&h->d_posm_r, posm_r));
   RCCHK(h->upload(&h->d_cptr, cptr));
   RCCHK(h->upload(&h->d_cidx_bp, cbp));
@@ -1022,6 +1039,78 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   return TCF_OK;
 }
 
+// Tile copies of the per-iteration operators: lower 64x64 tiles of S_bb^-1
+// (with the Phi_b tiles), of S_bb and of S_Pi^-1, plus the job lists.
+template <class T>
+static int build_tiles(tcf_problem* h, hipStream_t st) {
+  std::vector<PackJob> pa, pb, pc;
+  std::vector<TileJob> ja, jphi, jpre, jc;
+  int64_t oa = 0, ob = 0, oc = 0;
+  const int64_t TT = 64 * 64;
+  for (int s = 0; s < h->np_tot; ++s) {
+    const DevPatch& d = h->hp[s];
+    if (d.n_b == 0) continue;
+    const int Tb = (d.n_b + 63) / 64, Tp = (d.n_p + 63) / 64;
+    for (int J = 0; J < Tb; ++J)
+      for (int I = J; I < Tb; ++I) {
+        const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_b - 64 * J);
+        pa.push_back(PackJob{d.G_off, oa, d.nb_pad, 64 * I, 64 * J, nr, nc, 0});
+        ja.push_back(TileJob{oa, d.b_off + 64 * I, d.b_off + 64 * J, d.bp_off + 64 * I,
+                             d.bp_off + 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
+        oa += TT;
+        pb.push_back(PackJob{d.S_off, ob, d.nb_pad, 64 * I, 64 * J, nr, nc, 0});
+        jpre.push_back(TileJob{ob, d.b_off + 64 * I, d.b_off + 64 * J, d.b_off + 64 * I,
+                               d.b_off + 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
+        ob += TT;
+      }
+    for (int K = 0; K < Tp; ++K)
+      for (int I = 0; I < Tb; ++I) {
+        const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_p - 64 * K);
+        pa.push_back(PackJob{d.G_off, oa, d.nb_pad, 64 * I, d.n_b + 64 * K, nr, nc, 0});
+        ja.push_back(TileJob{oa, d.b_off + 64 * I, 0, 0, d.bp_off + d.n_b + 64 * K, nr, nc, 2, 0});
+        jphi.push_back(TileJob{oa, 0, d.p_off + 64 * K, d.bp_off + 64 * I, 0, nr, nc, 1, 0});
+        oa += TT;
+      }
+  }
+  const int nP = h->n_primal;
+  const int Tc = (nP + 63) / 64;
+  for (int J = 0; J < Tc; ++J)
+    for (int I = J; I < Tc; ++I) {
+      const int nr = std::min(64, nP - 64 * I), nc = std::min(64, nP - 64 * J);
+      pc.push_back(PackJob{0, oc, h->nPi_pad, 64 * I, 64 * J, nr, nc, 0});
+      jc.push_back(TileJob{oc, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
+      oc += TT;
+    }
+  T *tA, *tB;
+  RCCHK(h->alloc(&tA, (size_t)oa));
+  RCCHK(h->alloc(&tB, (size_t)ob));
+  RCCHK(h->alloc(&h->d_tC, (size_t)oc));
+  h->d_tA = tA;
+  h->d_tB = tB;
+  PackJob *dpa, *dpb, *dpc;
+  RCCHK(h->upload(&dpa, pa));
+  RCCHK(h->upload(&dpb, pb));
+  RCCHK(h->upload(&dpc, pc));
+  launch_pack_tiles<T, T>(dpa, (int)pa.size(), (const T*)h->d_G, tA, st);
+  launch_pack_tiles<T, T>(dpb, (int)pb.size(), (const T*)h->d_S, tB, st);
+  if (nP > 0) launch_pack_tiles<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_tC, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  h->release(dpa);
+  h->release(dpb);
+  h->release(dpc);
+  RCCHK(h->upload(&h->tj_apply, ja));
+  RCCHK(h->upload(&h->tj_phi, jphi));
+  RCCHK(h->upload(&h->tj_pre, jpre));
+  RCCHK(h->upload(&h->tj_coarse, jc));
+  h->n_tapply = (int)ja.size();
+  h->n_tphi = (int)jphi.size();
+  h->n_tpre = (int)jpre.size();
+  h->n_tcoarse = (int)jc.size();
+  RCCHK(h->alloc(&h->d_acc, (size_t)(h->n_bptot + std::max(nP, 1) + h->n_btot)));
+  return TCF_OK;
+}
+
 // FP32_IR: the Schur operators were built in FP64; keep FP32 copies only.
 static int demote_operators(tcf_problem* h, hipStream_t st) {
   void** bufs[3] = {&h->d_G, &h->d_S, &h->d_Q};
@@ -1051,6 +1140,8 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
     rc = setup_impl<double>(h, st);
     if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
   }
+  if (!rc && h->use_tiles)
+    rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
   if (rc) return rc;
   h->setup_ms = now_ms() - t0;
   h->is_setup = true;
@@ -1109,9 +1200,61 @@ static void apply_M(tcf_problem* h, const double* r, double* z, double* part, co
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
 }
 
+// Tile-path operators: accumulators vc | q | tb are zeroed, then each tile
+// adds its share with FP64 atomics.
+template <class T>
+static void apply_F_tiles(tcf_problem* h, const double* p, double* Fp, double* part,
+                          const int* done, hipStream_t st) {
+  double* vc = h->d_acc;
+  double* q = h->d_acc + h->n_bptot;
+  timed(h, TCF_KG_APPLY, st, [&] {
+    launch_tiles<T>(h->tj_apply, h->n_tapply, (const T*)h->d_tA, 1, p, h->d_brow, h->d_bsgn,
+                    h->dt, vc, done, st);
+  });
+  if (h->n_primal > 0) {
+    launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, vc, 1.0,
+                         nullptr, h->d_cv, done, st);
+    timed(h, TCF_KG_COARSE, st, [&] {
+      launch_tiles<double>(h->tj_coarse, h->n_tcoarse, h->d_tC, 0, h->d_cv, nullptr, nullptr,
+                           1.0, q, done, st);
+    });
+    timed(h, TCF_KG_PHI, st, [&] {
+      launch_tiles<T>(h->tj_phi, h->n_tphi, (const T*)h->d_tA, 2, q, h->d_prank, nullptr, 1.0,
+                      vc, done, st);
+    });
+  }
+  launch_jump(h->n_lambda, h->d_posp_bp, h->d_posm_bp, vc, h->dt, Fp, p, part, done, st);
+}
+
+template <class T>
+static void apply_M_tiles(tcf_problem* h, const double* r, double* z, double* part,
+                          const int* done, hipStream_t st) {
+  double* tb = h->d_acc + h->n_bptot + std::max(h->n_primal, 1);
+  timed(h, TCF_KG_PRECOND, st, [&] {
+    launch_tiles<T>(h->tj_pre, h->n_tpre, (const T*)h->d_tB, 1, r, h->d_brow, h->d_bsgn, 1.0, tb,
+                    done, st);
+  });
+  launch_jump(h->n_lambda, h->d_posp, h->d_posm, tb, 1.0, z, r, part, done, st);
+}
+
 // One PCG iteration with the given parity (launch sequence only).
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
+  if (h->use_tiles) {
+    const int nl = h->n_lambda, npt = h->npart;
+    const int* done = &h->d_st->done;
+    double* p_pq = h->d_part;
+    double* p_rr = h->d_part + npt;
+    double* p_rz = h->d_part + 2 * npt;
+    const double tol2 = h->pcg_tol * h->pcg_tol;
+    launch_zero(h->n_bptot + std::max(h->n_primal, 1) + h->n_btot, h->d_acc, st);
+    apply_F_tiles<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
+    launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
+    launch_pcg_check(p_rr, npt, h->d_st, tol2, st);
+    apply_M_tiles<T>(h, h->d_r, h->d_z, p_rz, done, st);
+    launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
+    return;
+  }
   const int nl = h->n_lambda, npt = h->npart;
   const int* done = &h->d_st->done;
   double* p_pq = h->d_part;

@@ -63,6 +63,26 @@ struct AxpyJob {
   int out_off;
 };
 
+// One 64x64 tile of an operator stored tile by tile (column-major inside the
+// tile, zero beyond nr x nc).  N part: y[yr_off + r] += sum_c A[r,c] x[xc_off + c];
+// T part: y[yc_off + c] += sum_r A[r,c] x[xr_off + r].  flags bit 0 = N, bit 1 = T.
+struct TileJob {
+  int64_t m_off;
+  int xr_off, xc_off;
+  int yr_off, yc_off;
+  int nr, nc;
+  int flags;
+  int pad;
+};
+
+// Copy a block of a column-major source into one zero-padded 64x64 tile.
+struct PackJob {
+  int64_t src_off;
+  int64_t dst_off;
+  int ld, row0, col0, nr, nc;
+  int pad;
+};
+
 struct PcgScalars {
   double dd;         // ||d||^2
   double rz[2];      // r.z of the current / next iteration (parity)

@@ -107,3 +107,12 @@ void launch_jump_add(int n, const int* pp, const int* pm, const double* a, doubl
 namespace tcf {
 void launch_assemble_split(int n, const int* ptr, const int* idx, double* x, hipStream_t st);
 }  // namespace tcf
+namespace tcf {
+template <class TS, class TD>
+void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st);
+template <class T>
+void launch_tiles(const TileJob* jobs, int njobs, const T* M, int xmode, const double* xv,
+                  const int* gidx, const signed char* gsgn, double scale, double* y,
+                  const int* done, hipStream_t st);
+void launch_zero(int64_t n, double* a, hipStream_t st);
+}  // namespace tcf

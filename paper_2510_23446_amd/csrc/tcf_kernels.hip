@@ -1466,3 +1466,124 @@ void launch_assemble_split(int n, const int* ptr, const int* idx, double* x, hip
   hipLaunchKernelGGL(k_assemble_split, TCF_GRID(n, 256), dim3(256), 0, st, n, ptr, idx, x);
 }
 }  // namespace tcf
+
+namespace tcf {
+// ===========================================================================
+// Tile storage and tile GEMV
+// ===========================================================================
+template <class TS, class TD>
+__global__ void k_pack_tiles(const PackJob* jobs, const TS* src, TD* dst) {
+  const PackJob jb = jobs[blockIdx.x];
+  TD* o = dst + jb.dst_off;
+  const TS* s = src + jb.src_off;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += blockDim.x) {
+    const int r = idx % 64, c = idx / 64;
+    TD v = TD(0);
+    if (r < jb.nr && c < jb.nc) v = (TD)s[(int64_t)(jb.row0 + r) + (int64_t)(jb.col0 + c) * jb.ld];
+    o[idx] = v;
+  }
+}
+
+// Input value of a tile side: xmode 0 direct xv[off + i]; 1 signed gather
+// scale * sgn[off + i] * xv[gidx[off + i]]; 2 plain gather xv[gidx[off + i]].
+__device__ inline double tile_x(int xmode, const double* xv, const int* gidx,
+                                const signed char* gsgn, double scale, int off) {
+  if (xmode == 0) return xv[off];
+  if (xmode == 1) return scale * (double)gsgn[off] * xv[gidx[off]];
+  return xv[gidx[off]];
+}
+
+// One block (256 threads) per tile.  Thread t covers column t/4 and 16
+// consecutive rows of it; the T part is reduced across the 4 threads of a
+// column, the N part through an LDS transpose.  Results are added to y with
+// FP64 atomics (each tile of a symmetric operator serves A_IJ and A_IJ^T).
+template <class T>
+__global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb, int xmode,
+                                               const double* xv, const int* gidx,
+                                               const signed char* gsgn, double scale,
+                                               double* y, const int* done) {
+  if (done && *done) return;
+  const TileJob jb = jobs[blockIdx.x];
+  __shared__ double xr[64], xc[64];
+  __shared__ double P[64][65];
+  const int t = threadIdx.x;
+  const bool doN = jb.flags & 1, doT = jb.flags & 2;
+  const int c = t >> 2, g = t & 3;
+  typedef typename Vec16<T>::type VT;
+  constexpr int V = Vec16<T>::n;
+  // matrix loads first: they do not depend on the gathered inputs
+  const VT* col = reinterpret_cast<const VT*>(Mb + jb.m_off + (int64_t)c * 64 + g * 16);
+  VT raw[16 / V];
+#pragma unroll
+  for (int k = 0; k < 16 / V; ++k) raw[k] = col[k];
+  if (t < 64) {
+    xr[t] = (doT && t < jb.nr) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xr_off + t) : 0.0;
+  } else if (t < 128) {
+    const int cc = t - 64;
+    xc[cc] = (doN && cc < jb.nc) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xc_off + cc) : 0.0;
+  }
+  __syncthreads();
+  double a[16];
+#pragma unroll
+  for (int k = 0; k < 16 / V; ++k) {
+    const T* e = reinterpret_cast<const T*>(&raw[k]);
+#pragma unroll
+    for (int q = 0; q < V; ++q) a[k * V + q] = (double)e[q];
+  }
+  // T part: column sums
+  if (doT) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += a[k] * xr[g * 16 + k];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (g == 0 && c < jb.nc) atomicAdd(y + jb.yc_off + c, s);
+  }
+  if (doN) {
+    const double xcv = xc[c];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) P[g * 16 + k][c] = a[k] * xcv;
+    __syncthreads();
+    const int r = t >> 2, q = t & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += P[r][q * 16 + k];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (q == 0 && r < jb.nr) atomicAdd(y + jb.yr_off + r, s);
+  }
+}
+
+__global__ void k_zero(int64_t n, double* a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+template <class TS, class TD>
+void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st) {
+  if (njobs == 0) return;
+  hipLaunchKernelGGL((k_pack_tiles<TS, TD>), dim3(njobs), dim3(256), 0, st, jobs, src, dst);
+}
+template <class T>
+void launch_tiles(const TileJob* jobs, int njobs, const T* M, int xmode, const double* xv,
+                  const int* gidx, const signed char* gsgn, double scale, double* y,
+                  const int* done, hipStream_t st) {
+  if (njobs == 0) return;
+  hipLaunchKernelGGL(k_tiles<T>, dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx, gsgn,
+                     scale, y, done);
+}
+void launch_zero(int64_t n, double* a, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero, TCF_GRID(n, 256), dim3(256), 0, st, n, a);
+}
+template void launch_pack_tiles<double, double>(const PackJob*, int, const double*, double*,
+                                                hipStream_t);
+template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,
+                                              hipStream_t);
+template void launch_tiles<double>(const TileJob*, int, const double*, int, const double*,
+                                   const int*, const signed char*, double, double*, const int*,
+                                   hipStream_t);
+template void launch_tiles<float>(const TileJob*, int, const float*, int, const double*,
+                                  const int*, const signed char*, double, double*, const int*,
+                                  hipStream_t);
+}  // namespace tcf
