@@ -33,7 +33,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "plain", "mixed", "largest"])
+    ap.add_argument("--workload", default="uneven",
+                    choices=["uneven", "plain", "mixed", "largest", "serving"])
+    ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
+    ap.add_argument("--rate-x", type=float, default=2.0,
+                    help="serving: arrival rate as a multiple of the solo FP64 capacity")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir", "fp32_full_ir"])
     ap.add_argument("--profile-steps", type=int, default=3,
                     help="steps after the timed run with per-kernel HIP-event timing")
@@ -113,12 +118,75 @@ def cpu_baseline(prob, budget_s, full_kept):
     }
 
 
+def serving(args):
+    """Stream of independent simulations: FP32-refined requests admitted by
+    memory into the server (continuous batching over HIP streams) vs the same
+    requests in FP64 one after another."""
+    import workloads as W
+    from paper_2510_23446_amd import tcf
+
+    reqs = W.serving_requests(n_req=args.requests, seed=3, n_steps=50)
+    steps_total = sum(r.n_steps for r in reqs)
+    # plain FP64, per problem, sequential
+    t0 = time.perf_counter()
+    seq_steps = []
+    for i, r in enumerate(reqs):
+        p = tcf.Problem(r, precision="fp64")
+        p.tcf_setup()
+        p.tcf_step(r.n_steps)
+        _, _, ms = p.tcf_get_step_log(r.n_steps)
+        seq_steps.extend(ms.tolist())
+        p.tcf_destroy()
+        if i % 8 == 7:
+            print(f"[bench] sequential fp64 {i + 1}/{len(reqs)}", file=sys.stderr, flush=True)
+    seq_wall = time.perf_counter() - t0
+    solo_rate = len(reqs) / seq_wall
+    # served, FP32 operators + FP64 refinement, Poisson arrivals
+    rate = args.rate_x * solo_rate
+    arrivals = W.poisson_arrivals(len(reqs), rate, seed=33)
+    srv = tcf.Server(max_bytes=200 << 30, max_slots=args.slots)
+    t0 = time.perf_counter()
+    ids = []
+    for i, (r, ta) in enumerate(zip(reqs, arrivals)):
+        dt = ta - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        ids.append(srv.tcf_server_submit(r, precision="fp32_ir"))
+    for i in ids:
+        rc = srv.tcf_server_wait(i)
+        if rc != tcf.TCF_OK:
+            print(f"[bench] request {i} ({reqs[i].name}) failed: {srv.tcf_server_error(i)}",
+                  file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    st = srv.tcf_server_stats()
+    srv.tcf_server_destroy()
+    out = {
+        "metric": "time-steps/sec", "value": steps_total / wall, "unit": "time-steps/s",
+        "n_gpus": 1, "steps": steps_total, "warmup": 0, "ms_per_step": wall / steps_total * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-operators+f64-pcg", "data": "synthetic",
+        "config": {"workload": f"serving_{len(reqs)}req_k234_seed3", "requests": len(reqs),
+                   "arrival_rate_per_s": rate, "arrival_seed": 33, "slots": args.slots,
+                   "precision": "fp32_ir"},
+        "p50_step_ms": st["p50_step_ms"], "p99_step_ms": st["p99_step_ms"],
+        "p50_queue_ms": st["p50_queue_ms"], "p99_queue_ms": st["p99_queue_ms"],
+        "completed": st["completed"], "failed": st["failed"], "peak_bytes": st["peak_bytes"],
+        "fp64_sequential": {"steps_per_s": steps_total / seq_wall, "wall_s": seq_wall,
+                            "p50_step_ms": float(np.percentile(seq_steps, 50)),
+                            "p99_step_ms": float(np.percentile(seq_steps, 99))},
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "serving":
+        serving(args)
+        return
     from paper_2510_23446_amd import tcf
 
     n_steps = args.warmup + args.steps + args.profile_steps

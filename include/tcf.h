@@ -229,6 +229,57 @@ int tcf_profile_get(const tcf_problem* h, int32_t group, double* total_ms, int64
 
 void tcf_destroy(tcf_problem* h);
 
+/*
+ * Serving: a stream of independent simulations admitted by device memory.
+ *
+ * tcf_server_submit does the host work of tcf_create on the calling thread
+ * and queues the request with its device footprint (tcf_footprint for the
+ * requested precision).  A dispatcher admits queued requests in arrival
+ * order whenever a slot is free and the footprint fits in max_bytes next to
+ * the running ones; each admitted request runs setup and all n_steps steps
+ * on its own worker thread and HIP stream (default priority) on the device
+ * that was current at tcf_server_create, so the work of running requests
+ * overlaps on the GPU.  When a request finishes, its fields are copied to
+ * host memory and its device memory is released, which may admit the next.
+ * The phi callback of a request must stay valid until the request is DONE
+ * or FAILED (it is called from the worker thread during setup).
+ * A request whose footprint exceeds max_bytes fails with TCF_ENOMEM.
+ */
+typedef struct tcf_server tcf_server;
+
+enum tcf_request_state {
+  TCF_REQ_QUEUED = 0,
+  TCF_REQ_RUNNING = 1,
+  TCF_REQ_DONE = 2,
+  TCF_REQ_FAILED = 3
+};
+
+typedef struct tcf_server_report {
+  int32_t submitted, admitted, completed, failed, running, queued;
+  int64_t steps;             /* steps completed over all requests              */
+  double p50_step_ms;        /* over all steps of all completed requests       */
+  double p99_step_ms;
+  double p50_queue_ms;       /* submit -> admission                            */
+  double p99_queue_ms;
+  double busy_ms;            /* first admission -> last completion             */
+  size_t peak_bytes;         /* peak admitted footprint                        */
+} tcf_server_report;
+
+int tcf_server_create(size_t max_bytes, int32_t max_slots, tcf_server** out);
+int tcf_server_submit(tcf_server* srv, const tcf_problem_desc* desc, const tcf_options* opts,
+                      int32_t* req_id);
+int tcf_server_poll(tcf_server* srv, int32_t req_id, int32_t* state);
+/* Blocks until the request is DONE or FAILED; returns its final status. */
+int tcf_server_wait(tcf_server* srv, int32_t req_id);
+/* Final field of excitation k (host copy), length n_edges; stats may be NULL. */
+int tcf_server_fetch(tcf_server* srv, int32_t req_id, int32_t k, double* out, size_t len,
+                     tcf_stats* stats);
+int tcf_server_stats(tcf_server* srv, tcf_server_report* st);
+/* Failure message of a FAILED request (empty otherwise); owned by the server. */
+const char* tcf_server_error(tcf_server* srv, int32_t req_id);
+/* Waits for every request, joins the threads and frees everything. */
+void tcf_server_destroy(tcf_server* srv);
+
 /* Message of the last failure on h (h may be NULL for create failures). */
 const char* tcf_last_error(const tcf_problem* h);
 

@@ -19,8 +19,9 @@ LIB = os.path.join(HERE, "libtcf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TCF_OFFLOAD_ARCH", "gfx950")
 
-COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wno-unused-result",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
+CXX_FLAGS = ["-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics"]
 
@@ -28,14 +29,15 @@ SOURCES = [
     ("tcf_topology.cpp", False),
     ("tcf_kernels.hip", True),
     ("tcf_api.hip", True),
+    ("tcf_serve.cpp", False),
 ]
 
 
 def _compile(src, is_hip, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + COMMON + (HIP_FLAGS if is_hip else []) + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if is_hip:
-        cmd[1:1] = ["-x", "hip"]
+    cmd = [HIPCC] + COMMON + (HIP_FLAGS if is_hip else CXX_FLAGS) + ["-c", os.path.join(CSRC, src),
+                                                                   "-o", obj]
+    cmd[1:1] = ["-x", "hip"] if is_hip else ["-x", "c++"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,7 +54,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda a: _compile(a[0], a[1], verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,11 @@ using namespace tcf;
 namespace {
 
 thread_local std::string g_create_error;
+
+// Serialises stream capture against device allocation and release in this
+// process: hipFree synchronises the device and would invalidate a capture in
+// progress on another thread (several handles run concurrently when serving).
+std::mutex g_capture_mu;
 
 inline int pad32(int n) { return (n + TCF_NB - 1) / TCF_NB * TCF_NB; }
 inline double now_ms() {
@@ -165,6 +171,7 @@ struct tcf_problem {
   bool use_tiles = true;
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
+  bool graph_failed = false;          // capture refused: stream launches instead
 
   // job tables
   DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr, *dj_coarse = nullptr;
@@ -221,6 +228,7 @@ struct tcf_problem {
   std::vector<double> log_ms;
 
   ~tcf_problem() {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
     if (pcg_graph) (void)hipGraphExecDestroy(pcg_graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& p : pend) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
@@ -235,7 +243,12 @@ struct tcf_problem {
   int alloc(T** out, size_t count) {
     void* p = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    hipError_t e;
+    {
+      std::lock_guard<std::mutex> lk(g_capture_mu);
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess) {
       err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
       return TCF_ENOMEM;
     }
@@ -247,6 +260,7 @@ struct tcf_problem {
   void release(void* p) {
     for (auto& b : bufs)
       if (b.p == p) {
+        std::lock_guard<std::mutex> lk(g_capture_mu);
         (void)hipFree(b.p);
         dev_bytes -= b.bytes;
         b.p = nullptr;
@@ -257,7 +271,12 @@ struct tcf_problem {
   int upload(T** out, const std::vector<T>& v) {
     int rc = alloc(out, v.size());
     if (rc) return rc;
-    if (!v.empty() && hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+    hipError_t e = hipSuccess;
+    if (!v.empty()) {
+      std::lock_guard<std::mutex> lk(g_capture_mu);
+      e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
       err = "hipMemcpy upload failed";
       return TCF_EHIP;
     }
@@ -861,7 +880,8 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
           h->phi(ax[0].data(), (int)ax[0].size(), ax[1].data(), (int)ax[1].size(), ax[2].data(),
                  (int)ax[2].size(), k, hphi.data() + (size_t)k * npts, h->phi_ctx);
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(stage, hphi.data(), sizeof(double) * npts * nrhs, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(stage, hphi.data(), sizeof(double) * npts * nrhs,
+                              hipMemcpyHostToDevice, st));
         launch_load_patch(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, jr, ldv, st);
       }
       HIPCHK(hipStreamSynchronize(st));
@@ -948,7 +968,8 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     RCCHK(run_trsm<T>(h, 0, qb, A, Q, st));
   }
   int fail = 0;
-  HIPCHK(hipMemcpy(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
   h->release(A);
   h->release(d_colpre);
   if (fail) {
@@ -987,7 +1008,10 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4));
   RCCHK(h->alloc(&h->d_st, 1));
   RCCHK(h->alloc(&h->d_field, (size_t)h->g.n_edges()));
-  HIPCHK(hipHostMalloc((void**)&h->h_st, sizeof(PcgScalars), hipHostMallocDefault));
+  {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    HIPCHK(hipHostMalloc((void**)&h->h_st, sizeof(PcgScalars), hipHostMallocDefault));
+  }
   HIPCHK(hipMemsetAsync(h->d_lam, 0, sizeof(double) * nl, st));
 
   // source condensation (time separable): yggs = cond(jhat)
@@ -1034,7 +1058,10 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     RCCHK(h->upload(&h->d_kidx, ki));
     RCCHK(h->alloc(&h->d_nrm_part, (size_t)(h->n_kept_i + 255) / 256 + 1));
     RCCHK(h->alloc(&h->d_nrm, 4));
-    HIPCHK(hipHostMalloc((void**)&h->h_nrm, 4 * sizeof(double), hipHostMallocDefault));
+    {
+      std::lock_guard<std::mutex> lk(g_capture_mu);
+      HIPCHK(hipHostMalloc((void**)&h->h_nrm, 4 * sizeof(double), hipHostMallocDefault));
+    }
   }
   return TCF_OK;
 }
@@ -1269,21 +1296,31 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
 }
 
 // Captures two iterations (parity 0, 1) into a graph replayed per chunk.
+// If capture or instantiation fails, the handle falls back to stream
+// launches (same kernels) instead of failing.
 template <class T>
 static int build_pcg_graph(tcf_problem* h) {
-  if (h->pcg_graph) return TCF_OK;
-  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  if (h->pcg_graph || h->graph_failed) return TCF_OK;
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    h->graph_failed = true;
+    return TCF_OK;
+  }
   hipGraph_t g = nullptr;
-  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    h->graph_failed = true;
+    (void)hipGetLastError();
+    return TCF_OK;
+  }
   pcg_iteration<T>(h, 0, h->cap_stream);
   pcg_iteration<T>(h, 1, h->cap_stream);
-  HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
-  hipError_t e = hipGraphInstantiate(&h->pcg_graph, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (e == hipSuccess) e = hipGraphInstantiate(&h->pcg_graph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     h->pcg_graph = nullptr;
-    h->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
-    return TCF_EHIP;
+    h->graph_failed = true;
+    (void)hipGetLastError();
   }
   return TCF_OK;
 }
@@ -1302,8 +1339,8 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bo
   apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
   launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
-  const bool graph = h->opt.use_graph && !h->prof_on;
-  if (graph) RCCHK(build_pcg_graph<T>(h));
+  if (h->opt.use_graph && !h->prof_on) RCCHK(build_pcg_graph<T>(h));
+  const bool graph = h->opt.use_graph && !h->prof_on && h->pcg_graph;
   const int chunk = std::max(2, h->opt.check_every / 2 * 2);
   int it = 0;
   bool finished = false;

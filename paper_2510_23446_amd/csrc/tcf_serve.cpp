@@ -1,0 +1,263 @@
+// Serving loop of libtcf: admission by device footprint, one worker thread
+// and HIP stream per running request, results kept on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/tcf.h"
+
+namespace {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  int id = 0;
+  tcf_problem* h = nullptr;
+  size_t footprint = 0;
+  int state = TCF_REQ_QUEUED;
+  int status = TCF_OK;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  std::vector<std::vector<double>> fields;
+  tcf_stats stats{};
+  std::vector<double> step_ms;
+  std::string err;
+};
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (double)(v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - (double)i;
+  return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+struct tcf_server {
+  size_t max_bytes = 0;
+  int max_slots = 1;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<int> queue;
+  std::vector<std::unique_ptr<Request>> reqs;
+  size_t used = 0, peak = 0;
+  int running = 0;
+  bool stopping = false;
+  double t_first_admit = -1, t_last_done = -1;
+  std::thread dispatcher;
+  std::vector<std::thread> workers;
+
+  void run_request(Request* r);
+  void dispatch_loop();
+};
+
+void tcf_server::run_request(Request* r) {
+  (void)hipSetDevice(device);
+  hipStream_t st = nullptr;
+  int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? TCF_OK : TCF_EHIP;
+  if (rc == TCF_OK) rc = tcf_setup(r->h, st);
+  if (rc == TCF_OK) {
+    rc = tcf_step(r->h, 1 << 30, st);
+    if (rc == TCF_ENOCONV) rc = TCF_OK;  // flagged in the stats, results kept
+  }
+  if (rc == TCF_OK) {
+    tcf_get_stats(r->h, &r->stats);
+    const int n = r->stats.steps_done;
+    r->step_ms.resize(n);
+    tcf_get_step_log(r->h, n, nullptr, nullptr, r->step_ms.data());
+    int64_t cnt[8];
+    size_t len = 8;
+    tcf_get_topology(r->h, TCF_TOPO_COUNTS, cnt, &len);
+    // number of excitations: fetch until the library refuses the index
+    for (int k = 0;; ++k) {
+      std::vector<double> f((size_t)cnt[0]);
+      if (tcf_get_field(r->h, k, f.data(), f.size(), 0, st) != TCF_OK) break;
+      r->fields.push_back(std::move(f));
+    }
+  } else {
+    r->err = std::string("status ") + std::to_string(rc) + ": " + tcf_last_error(r->h);
+  }
+  tcf_destroy(r->h);  // releases the request's device memory
+  r->h = nullptr;
+  if (st) (void)hipStreamDestroy(st);
+  std::lock_guard<std::mutex> lk(mu);
+  r->status = rc;
+  r->state = rc == TCF_OK ? TCF_REQ_DONE : TCF_REQ_FAILED;
+  r->t_done = now_ms();
+  t_last_done = r->t_done;
+  used -= r->footprint;
+  --running;
+  cv.notify_all();
+}
+
+void tcf_server::dispatch_loop() {
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    cv.wait(lk, [&] {
+      if (stopping && queue.empty()) return true;
+      if (queue.empty()) return false;
+      const Request* r = reqs[queue.front()].get();
+      return running < max_slots && (running == 0 || used + r->footprint <= max_bytes);
+    });
+    if (queue.empty()) {
+      if (stopping) break;
+      continue;
+    }
+    Request* r = reqs[queue.front()].get();
+    queue.pop_front();
+    r->state = TCF_REQ_RUNNING;
+    r->t_admit = now_ms();
+    if (t_first_admit < 0) t_first_admit = r->t_admit;
+    used += r->footprint;
+    peak = std::max(peak, used);
+    ++running;
+    workers.emplace_back([this, r] { run_request(r); });
+  }
+}
+
+extern "C" {
+
+int tcf_server_create(size_t max_bytes, int32_t max_slots, tcf_server** out) {
+  if (!out || max_slots < 1 || max_bytes == 0) return TCF_EINVAL;
+  auto* s = new (std::nothrow) tcf_server();
+  if (!s) return TCF_ENOMEM;
+  s->max_bytes = max_bytes;
+  s->max_slots = max_slots;
+  if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
+  s->dispatcher = std::thread([s] { s->dispatch_loop(); });
+  *out = s;
+  return TCF_OK;
+}
+
+int tcf_server_submit(tcf_server* srv, const tcf_problem_desc* desc, const tcf_options* opts,
+                      int32_t* req_id) {
+  if (!srv || !desc || !req_id) return TCF_EINVAL;
+  tcf_problem* h = nullptr;
+  int rc = tcf_create(desc, opts, &h);
+  if (rc != TCF_OK) return rc;
+  size_t b64 = 0, b32 = 0;
+  tcf_footprint(h, &b64, &b32);
+  const int prec = opts ? opts->precision : TCF_FP64;
+  auto r = std::make_unique<Request>();
+  r->h = h;
+  r->footprint = prec == TCF_FP64 ? b64 : b32;
+  r->t_submit = now_ms();
+  std::lock_guard<std::mutex> lk(srv->mu);
+  r->id = (int)srv->reqs.size();
+  *req_id = r->id;
+  if (r->footprint > srv->max_bytes) {
+    r->state = TCF_REQ_FAILED;
+    r->status = TCF_ENOMEM;
+    r->err = "request footprint exceeds the server memory budget";
+    tcf_destroy(r->h);
+    r->h = nullptr;
+    srv->reqs.push_back(std::move(r));
+    return TCF_ENOMEM;
+  }
+  srv->queue.push_back(r->id);
+  srv->reqs.push_back(std::move(r));
+  srv->cv.notify_all();
+  return TCF_OK;
+}
+
+int tcf_server_poll(tcf_server* srv, int32_t id, int32_t* state) {
+  if (!srv || !state) return TCF_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (id < 0 || id >= (int)srv->reqs.size()) return TCF_EINVAL;
+  *state = srv->reqs[id]->state;
+  return TCF_OK;
+}
+
+int tcf_server_wait(tcf_server* srv, int32_t id) {
+  if (!srv) return TCF_EINVAL;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (id < 0 || id >= (int)srv->reqs.size()) return TCF_EINVAL;
+  Request* r = srv->reqs[id].get();
+  srv->cv.wait(lk, [&] { return r->state == TCF_REQ_DONE || r->state == TCF_REQ_FAILED; });
+  return r->status;
+}
+
+int tcf_server_fetch(tcf_server* srv, int32_t id, int32_t k, double* out, size_t len,
+                     tcf_stats* stats) {
+  if (!srv) return TCF_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (id < 0 || id >= (int)srv->reqs.size()) return TCF_EINVAL;
+  Request* r = srv->reqs[id].get();
+  if (r->state != TCF_REQ_DONE) return r->state == TCF_REQ_FAILED ? r->status : TCF_ESTATE;
+  if (stats) *stats = r->stats;
+  if (out) {
+    if (k < 0 || k >= (int)r->fields.size()) return TCF_EINVAL;
+    if (len < r->fields[k].size()) return TCF_EINVAL;
+    std::memcpy(out, r->fields[k].data(), r->fields[k].size() * sizeof(double));
+  }
+  return TCF_OK;
+}
+
+int tcf_server_stats(tcf_server* srv, tcf_server_report* st) {
+  if (!srv || !st) return TCF_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  std::memset(st, 0, sizeof(*st));
+  std::vector<double> steps, waits;
+  for (auto& r : srv->reqs) {
+    ++st->submitted;
+    if (r->state != TCF_REQ_QUEUED && r->t_admit > 0) {
+      ++st->admitted;
+      waits.push_back(r->t_admit - r->t_submit);
+    }
+    if (r->state == TCF_REQ_DONE) {
+      ++st->completed;
+      steps.insert(steps.end(), r->step_ms.begin(), r->step_ms.end());
+      st->steps += (int64_t)r->step_ms.size();
+    }
+    if (r->state == TCF_REQ_FAILED) ++st->failed;
+    if (r->state == TCF_REQ_RUNNING) ++st->running;
+    if (r->state == TCF_REQ_QUEUED) ++st->queued;
+  }
+  st->p50_step_ms = percentile(steps, 0.50);
+  st->p99_step_ms = percentile(steps, 0.99);
+  st->p50_queue_ms = percentile(waits, 0.50);
+  st->p99_queue_ms = percentile(waits, 0.99);
+  st->busy_ms = (srv->t_first_admit >= 0 && srv->t_last_done >= 0)
+                    ? srv->t_last_done - srv->t_first_admit
+                    : 0.0;
+  st->peak_bytes = srv->peak;
+  return TCF_OK;
+}
+
+const char* tcf_server_error(tcf_server* srv, int32_t id) {
+  if (!srv) return "";
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (id < 0 || id >= (int)srv->reqs.size()) return "";
+  return srv->reqs[id]->err.c_str();
+}
+
+void tcf_server_destroy(tcf_server* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stopping = true;
+    srv->cv.notify_all();
+  }
+  if (srv->dispatcher.joinable()) srv->dispatcher.join();
+  for (auto& w : srv->workers)
+    if (w.joinable()) w.join();
+  for (auto& r : srv->reqs)
+    if (r->h) tcf_destroy(r->h);
+  delete srv;
+}
+
+}  // extern "C"

@@ -25,7 +25,10 @@ PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
            "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
-           "tcf_profile_get", "tcf_destroy"]
+           "tcf_profile_get", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
+           "tcf_server_poll", "tcf_server_wait", "tcf_server_fetch", "tcf_server_stats",
+           "tcf_server_error", "tcf_server_destroy"]
+TCF_REQ_QUEUED, TCF_REQ_RUNNING, TCF_REQ_DONE, TCF_REQ_FAILED = range(4)
 KERNEL_GROUPS = ["apply", "precond", "phi", "coarse", "condense", "recover"]
 
 PHI_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double), C.c_int32,
@@ -66,6 +69,14 @@ class tcf_stats(C.Structure):
                 ("step_ms_total", C.c_double), ("device_bytes", C.c_size_t)]
 
 
+class tcf_server_report(C.Structure):
+    _fields_ = [("submitted", C.c_int32), ("admitted", C.c_int32), ("completed", C.c_int32),
+                ("failed", C.c_int32), ("running", C.c_int32), ("queued", C.c_int32),
+                ("steps", C.c_int64), ("p50_step_ms", C.c_double), ("p99_step_ms", C.c_double),
+                ("p50_queue_ms", C.c_double), ("p99_queue_ms", C.c_double),
+                ("busy_ms", C.c_double), ("peak_bytes", C.c_size_t)]
+
+
 _lib = None
 
 
@@ -99,8 +110,20 @@ def lib():
                                   C.POINTER(C.c_double)]
     L.tcf_destroy.argtypes = [P]
     L.tcf_destroy.restype = None
+    L.tcf_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(P)]
+    L.tcf_server_submit.argtypes = [P, C.POINTER(tcf_problem_desc), C.POINTER(tcf_options),
+                                    C.POINTER(C.c_int32)]
+    L.tcf_server_poll.argtypes = [P, C.c_int32, C.POINTER(C.c_int32)]
+    L.tcf_server_wait.argtypes = [P, C.c_int32]
+    L.tcf_server_fetch.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, C.POINTER(tcf_stats)]
+    L.tcf_server_stats.argtypes = [P, C.POINTER(tcf_server_report)]
+    L.tcf_server_error.argtypes = [P, C.c_int32]
+    L.tcf_server_error.restype = C.c_char_p
+    L.tcf_server_destroy.argtypes = [P]
+    L.tcf_server_destroy.restype = None
     for n in EXPORTS:
-        if n not in ("tcf_default_options", "tcf_last_error", "tcf_destroy"):
+        if n not in ("tcf_default_options", "tcf_last_error", "tcf_destroy", "tcf_server_destroy",
+                     "tcf_server_error"):
             getattr(L, n).restype = C.c_int
     _lib = L
     return L
@@ -122,6 +145,118 @@ def default_options(**kw) -> tcf_options:
     for k, v in kw.items():
         setattr(o, k, v)
     return o
+
+
+def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
+            use_graph=1):
+    """(desc, options, keep-alive list) for a workloads.Problem."""
+    keep = []
+    d = tcf_problem_desc()
+    for a in range(3):
+        d.np[a] = int(prob.np[a])
+        br = np.ascontiguousarray(prob.breaks[a], dtype=np.float64)
+        ne = np.ascontiguousarray(prob.nel[a], dtype=np.int32)
+        dg = np.ascontiguousarray(prob.deg[a], dtype=np.int32)
+        keep += [br, ne, dg]
+        d.breaks[a] = _dptr(br, C.c_double)
+        d.nel[a] = _dptr(ne, C.c_int32)
+        d.deg[a] = _dptr(dg, C.c_int32)
+    sig = np.ascontiguousarray(prob.sigma, dtype=np.float64)
+    nu = np.ascontiguousarray(prob.nu, dtype=np.float64)
+    src = np.ascontiguousarray(prob.src_mask, dtype=np.uint8)
+    amp = np.ascontiguousarray(prob.amp, dtype=np.float64)
+    keep += [sig, nu, src, amp]
+    d.sigma = _dptr(sig, C.c_double)
+    d.nu = _dptr(nu, C.c_double)
+    d.src_mask = _dptr(src, C.c_uint8)
+    d.n_rhs = int(amp.shape[0])
+    phi = prob.phi
+
+    def _cb(xs, nx, ys, ny, zs, nz, k, out, ctx):
+        x = np.ctypeslib.as_array(xs, shape=(nx,))
+        y = np.ctypeslib.as_array(ys, shape=(ny,))
+        z = np.ctypeslib.as_array(zs, shape=(nz,))
+        v = np.asarray(phi(x, y, z, int(k)), dtype=np.float64).reshape(nx, ny, nz)
+        o = np.ctypeslib.as_array(out, shape=(nx * ny * nz,))
+        o[:] = v.ravel(order="F")
+
+    cb = PHI_FN(_cb)
+    keep.append(cb)
+    d.phi = cb
+    d.phi_ctx = None
+    d.amp = _dptr(amp, C.c_double)
+    d.dt = float(prob.dt)
+    d.n_steps = int(amp.shape[1])
+    prec = precision if precision is not None else prob.precision
+    o = default_options(
+        precision=PRECISIONS[prec] if isinstance(prec, str) else int(prec),
+        pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
+        pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
+        check_every=int(check_every), use_graph=int(use_graph))
+    return d, o, keep
+
+
+class Server:
+    """Owns one tcf_server (admission by device memory, overlapping requests)."""
+
+    def __init__(self, max_bytes, max_slots):
+        self.s = C.c_void_p()
+        rc = lib().tcf_server_create(int(max_bytes), int(max_slots), C.byref(self.s))
+        if rc != TCF_OK:
+            raise TcfError(rc, "tcf_server_create failed")
+        self._keep = {}
+
+    def tcf_server_submit(self, prob, **kw):
+        d, o, keep = marshal(prob, **kw)
+        rid = C.c_int32()
+        rc = lib().tcf_server_submit(self.s, C.byref(d), C.byref(o), C.byref(rid))
+        self._keep[rid.value] = (d, o, keep, prob)
+        if rc != TCF_OK:
+            raise TcfError(rc, lib().tcf_last_error(None).decode())
+        return rid.value
+
+    def tcf_server_poll(self, rid):
+        st = C.c_int32()
+        rc = lib().tcf_server_poll(self.s, int(rid), C.byref(st))
+        if rc != TCF_OK:
+            raise TcfError(rc, "poll")
+        return st.value
+
+    def tcf_server_wait(self, rid):
+        return lib().tcf_server_wait(self.s, int(rid))
+
+    def tcf_server_fetch(self, rid, k=0, n_edges=None):
+        st = tcf_stats()
+        rc = lib().tcf_server_fetch(self.s, int(rid), 0, None, 0, C.byref(st))
+        if rc != TCF_OK:
+            raise TcfError(rc, "fetch")
+        n = int(st.n_edges)
+        out = np.zeros(n, dtype=np.float64)
+        rc = lib().tcf_server_fetch(self.s, int(rid), int(k), out.ctypes.data_as(C.c_void_p), n,
+                                    None)
+        if rc != TCF_OK:
+            raise TcfError(rc, "fetch")
+        return out, {f: getattr(st, f) for f, _ in tcf_stats._fields_}
+
+    def tcf_server_error(self, rid):
+        return lib().tcf_server_error(self.s, int(rid)).decode()
+
+    def tcf_server_stats(self):
+        s = tcf_server_report()
+        lib().tcf_server_stats(self.s, C.byref(s))
+        return {f: getattr(s, f) for f, _ in tcf_server_report._fields_}
+
+    def tcf_server_destroy(self):
+        if getattr(self, "s", None):
+            lib().tcf_server_destroy(self.s)
+            self.s = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.tcf_server_destroy()
+        except Exception:
+            pass
 
 
 class Problem:
