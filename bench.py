@@ -46,8 +46,29 @@ def parse():
                     help="steps compared against the oracle after the timed run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
+                                                      "apply_tiles_uneven_fp64_traffic.json"),
+                    help="JSON with the counter-measured HBM bytes per launch of a kernel")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every PCG iteration on the stream instead of replaying graphs")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="launch the plain copy kernel of this size once (counter reference)")
     return ap.parse_args()
+
+
+def kernel_digest(marker):
+    """sha256 of a kernel's source text (from the line starting with marker to
+    the closing brace in column 0): counters taken for another text are stale."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_23446_amd", "csrc", "tcf_kernels.hip")
+    lines = open(path).read().splitlines()
+    i = next((n for n, l in enumerate(lines) if l.startswith(marker)), None)
+    if i is None:
+        return None
+    j = i
+    while j < len(lines) and not lines[j].startswith("}"):
+        j += 1
+    return hashlib.sha256("\n".join(lines[i:j + 1]).encode()).hexdigest()
 
 
 def make_problem(name, n_steps):
@@ -94,8 +115,9 @@ def cpu_baseline(prob, budget_s, full_kept):
     a = np.zeros((g.n_edges, sub.n_rhs))
     steps = 0
     ts = time.perf_counter()
-    while steps < sub.n_steps:
-        f = sysm.M @ a + sub.dt * sysm.jhat * sub.amp[:, steps][None, :]
+    # the amplitude sequence repeats until the budget is spent
+    while steps < 1_000_000:
+        f = sysm.M @ a + sub.dt * sysm.jhat * sub.amp[:, steps % sub.n_steps][None, :]
         a = np.zeros_like(a)
         a[K] = lu.solve(np.ascontiguousarray(f[K]))
         steps += 1
@@ -110,7 +132,8 @@ def cpu_baseline(prob, budget_s, full_kept):
         "sample": (f"{sub.name}: first 2x2x2 patches of the same seeded workload, "
                    f"{len(K)} gauged unknowns (full problem {full_kept}); assembly+gauge "
                    f"{t1 - t0:.1f} s and one SuperLU factorisation {t2 - t1:.1f} s (not in value), "
-                   f"then {steps} implicit-Euler solves at {sub_rate:.2f} steps/s; value = that rate "
+                   f"then {steps} implicit-Euler solves (amplitudes repeated after "
+                   f"{sub.n_steps}) at {sub_rate:.2f} steps/s; value = that rate "
                    f"x sample/full unknowns (linear scaling); SuperLU runs on 1 core, "
                    f"{cores} cores visible"),
         "sample_steps_per_s": sub_rate, "sample_unknowns": len(K), "factor_s": t2 - t1,
@@ -189,10 +212,12 @@ def main():
         return
     from paper_2510_23446_amd import tcf
 
+    if args.copy_probe_mb:
+        tcf.tcf_copy_probe(args.copy_probe_mb << 20)
     n_steps = args.warmup + args.steps + args.profile_steps
     prob = make_problem(args.workload, max(n_steps, args.check_steps))
     prec = args.precision or prob.precision
-    p = tcf.Problem(prob, precision=prec)
+    p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1)
     counts = p.counts()
     t0 = time.perf_counter()
     p.tcf_setup()
@@ -231,7 +256,9 @@ def main():
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         tj = json.load(open(args.traffic))
-        if tj.get("kernel_group") == dom:
+        same_kernel = tj.get("kernel_source_sha256") == kernel_digest("template <class T, int Group>")
+        if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
+                and prec == "fp64"):
             traffic = tj.get("hbm_bytes_per_launch")
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                      "avg_us": round(v[0] * 1e3 / max(v[1], 1), 2),
@@ -285,7 +312,8 @@ def main():
         "config": {"workload": prob.name, "patches": prob.n_patches, "n_rhs": prob.n_rhs,
                    "dt": prob.dt, "pcg_rtol": prob.pcg_rtol, "precision": prec,
                    "n_edges": counts["n_edges"], "gauged_dofs": counts["n_kept"],
-                   "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"]},
+                   "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"],
+                   "graphs": not args.no_graph},
         "pcg_applies_per_s": applies / wall,
         "pcg_iters_per_step": applies / args.steps,
         "p50_step_ms": float(np.percentile(ms, 50)),

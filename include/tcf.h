@@ -227,6 +227,14 @@ int tcf_profile_enable(tcf_problem* h, int32_t on);
 int tcf_profile_get(const tcf_problem* h, int32_t group, double* total_ms, int64_t* launches,
                     double* alg_bytes_per_launch);
 
+/*
+ * Measurement reference: one launch of a plain streaming copy that reads and
+ * writes `bytes` (rounded down to 32) through device buffers it allocates
+ * and frees.  Traffic counters of the library's kernels are scaled by what
+ * the same counters report for this launch.
+ */
+int tcf_copy_probe(size_t bytes, void* stream);
+
 void tcf_destroy(tcf_problem* h);
 
 /*

@@ -305,10 +305,16 @@ static inline void timed(tcf_problem* h, int g, hipStream_t st, F&& f) {
     f();
     return;
   }
+  // every timed group is exactly one kernel launch; the events ride on it
   hipEvent_t a = h->ev_get(), b = h->ev_get();
-  (void)hipEventRecord(a, st);
+  set_launch_events(a, b);
   f();
-  (void)hipEventRecord(b, st);
+  if (launch_events_pending()) {  // nothing was launched
+    set_launch_events(nullptr, nullptr);
+    h->ev_pool.push_back(a);
+    h->ev_pool.push_back(b);
+    return;
+  }
   h->pend.push_back({g, h->cur_it, a, b});
 }
 
@@ -586,6 +592,29 @@ int tcf_profile_enable(tcf_problem* h, int32_t on) {
   for (int g = 0; g < TCF_KG_COUNT; ++g) { h->prof_ms[g] = 0; h->prof_n[g] = 0; }
   compute_alg_bytes(h);
   return TCF_OK;
+}
+
+int tcf_copy_probe(size_t bytes, void* stream) {
+  const size_t n32 = bytes / 32;
+  if (n32 == 0) return TCF_EINVAL;
+  void *a = nullptr, *b = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    if (hipMalloc(&a, n32 * 32) != hipSuccess) return TCF_ENOMEM;
+    if (hipMalloc(&b, n32 * 32) != hipSuccess) {
+      (void)hipFree(a);
+      return TCF_ENOMEM;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc = TCF_OK;
+  if (hipMemsetAsync(a, 0, n32 * 32, st) != hipSuccess) rc = TCF_EHIP;
+  if (rc == TCF_OK) launch_copy_probe((int64_t)n32, a, b, st);
+  if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) rc = TCF_EHIP;
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  return rc;
 }
 
 int tcf_profile_get(const tcf_problem* h, int32_t g, double* total_ms, int64_t* launches,
@@ -1235,18 +1264,18 @@ static void apply_F_tiles(tcf_problem* h, const double* p, double* Fp, double* p
   double* vc = h->d_acc;
   double* q = h->d_acc + h->n_bptot;
   timed(h, TCF_KG_APPLY, st, [&] {
-    launch_tiles<T>(h->tj_apply, h->n_tapply, (const T*)h->d_tA, 1, p, h->d_brow, h->d_bsgn,
+    launch_tiles<T>(0, h->tj_apply, h->n_tapply, (const T*)h->d_tA, 1, p, h->d_brow, h->d_bsgn,
                     h->dt, vc, done, st);
   });
   if (h->n_primal > 0) {
     launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, vc, 1.0,
                          nullptr, h->d_cv, done, st);
     timed(h, TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(h->tj_coarse, h->n_tcoarse, h->d_tC, 0, h->d_cv, nullptr, nullptr,
+      launch_tiles<double>(3, h->tj_coarse, h->n_tcoarse, h->d_tC, 0, h->d_cv, nullptr, nullptr,
                            1.0, q, done, st);
     });
     timed(h, TCF_KG_PHI, st, [&] {
-      launch_tiles<T>(h->tj_phi, h->n_tphi, (const T*)h->d_tA, 2, q, h->d_prank, nullptr, 1.0,
+      launch_tiles<T>(1, h->tj_phi, h->n_tphi, (const T*)h->d_tA, 2, q, h->d_prank, nullptr, 1.0,
                       vc, done, st);
     });
   }
@@ -1258,7 +1287,7 @@ static void apply_M_tiles(tcf_problem* h, const double* r, double* z, double* pa
                           const int* done, hipStream_t st) {
   double* tb = h->d_acc + h->n_bptot + std::max(h->n_primal, 1);
   timed(h, TCF_KG_PRECOND, st, [&] {
-    launch_tiles<T>(h->tj_pre, h->n_tpre, (const T*)h->d_tB, 1, r, h->d_brow, h->d_bsgn, 1.0, tb,
+    launch_tiles<T>(2, h->tj_pre, h->n_tpre, (const T*)h->d_tB, 1, r, h->d_brow, h->d_bsgn, 1.0, tb,
                     done, st);
   });
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, tb, 1.0, z, r, part, done, st);

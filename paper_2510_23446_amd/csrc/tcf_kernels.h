@@ -111,8 +111,12 @@ namespace tcf {
 template <class TS, class TD>
 void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st);
 template <class T>
-void launch_tiles(const TileJob* jobs, int njobs, const T* M, int xmode, const double* xv,
-                  const int* gidx, const signed char* gsgn, double scale, double* y,
-                  const int* done, hipStream_t st);
+void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, int xmode,
+                  const double* xv, const int* gidx, const signed char* gsgn, double scale,
+                  double* y, const int* done, hipStream_t st);
+// Timing events for the next launch (of a timed kernel) issued by this thread.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
+void launch_copy_probe(int64_t n32, const void* a, void* b, hipStream_t st);
 void launch_zero(int64_t n, double* a, hipStream_t st);
 }  // namespace tcf

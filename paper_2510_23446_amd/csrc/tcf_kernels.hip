@@ -6,6 +6,7 @@
 // Schur operators.  Per step: matrix-free conductor mass, condensation,
 // column-dot and row-stripe matrix-vector products for the dual-primal
 // operator, the signed jump, and PCG recurrences with device-side scalars.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -1187,6 +1188,28 @@ void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int
   else
     hipLaunchKernelGGL(k_trsm_bwd<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, L, B);
 }
+// Optional timing events for the next timed launch of this thread: attached
+// to the dispatch packet itself (hipExtLaunchKernelGGL), so their interval
+// is the kernel's own execution, without the queue latency that separate
+// marker packets would add.
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev_start = start;
+  t_ev_stop = stop;
+}
+bool launch_events_pending() { return t_ev_start != nullptr; }
+
+#define TCF_TIMED_LAUNCH(kernel, grid, block, shm, st, ...)                               \
+  do {                                                                                  \
+    if (t_ev_start) {                                                                   \
+      hipExtLaunchKernelGGL(kernel, grid, block, shm, st, t_ev_start, t_ev_stop, 0u,     \
+                            __VA_ARGS__);                                               \
+      t_ev_start = t_ev_stop = nullptr;                                                 \
+    } else {                                                                            \
+      hipLaunchKernelGGL(kernel, grid, block, shm, st, __VA_ARGS__);                    \
+    }                                                                                   \
+  } while (0)
+
 template <class T>
 void launch_dotcols(const DotJob* jobs, const int* prefix, int njobs, int total, int max_rows,
                     const T* M, int xmode, const double* xv, const int* gidx,
@@ -1194,7 +1217,7 @@ void launch_dotcols(const DotJob* jobs, const int* prefix, int njobs, int total,
                     hipStream_t st) {
   if (total == 0) return;
   (void)max_rows;
-  hipLaunchKernelGGL(k_dotcols<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, xmode, xv,
+  TCF_TIMED_LAUNCH(k_dotcols<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, xmode, xv,
                      gidx, gsgn, xscale, out, done);
 }
 template <class T>
@@ -1204,7 +1227,7 @@ void launch_axpyrows(const AxpyJob* jobs, const int* prefix, int njobs, int tota
                      const int* done, hipStream_t st) {
   if (total == 0) return;
   (void)max_cols;
-  hipLaunchKernelGGL(k_axpyrows<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, yv, yidx,
+  TCF_TIMED_LAUNCH(k_axpyrows<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, M, yv, yidx,
                      base, base_off, alpha, out, tri_cols, done);
 }
 template <class T>
@@ -1213,7 +1236,7 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
                      hipStream_t st) {
   if (total == 0) return;
   (void)max_ni;
-  hipLaunchKernelGGL(k_condense<T>, dim3(total, nrhs), dim3(256), 0, st, P, plist, prefix, nlist, Q,
+  TCF_TIMED_LAUNCH(k_condense<T>, dim3(total, nrhs), dim3(256), 0, st, P, plist, prefix, nlist, Q,
                      f, ygg, ldv);
 }
 
@@ -1497,7 +1520,7 @@ __device__ inline double tile_x(int xmode, const double* xv, const int* gidx,
 // consecutive rows of it; the T part is reduced across the 4 threads of a
 // column, the N part through an LDS transpose.  Results are added to y with
 // FP64 atomics (each tile of a symmetric operator serves A_IJ and A_IJ^T).
-template <class T>
+template <class T, int Group>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb, int xmode,
                                                const double* xv, const int* gidx,
                                                const signed char* gsgn, double scale,
@@ -1564,13 +1587,42 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
   if (njobs == 0) return;
   hipLaunchKernelGGL((k_pack_tiles<TS, TD>), dim3(njobs), dim3(256), 0, st, jobs, src, dst);
 }
+// group only names the kernel instance (apply / phi / precond / coarse) so
+// that traces attribute each operator separately
 template <class T>
-void launch_tiles(const TileJob* jobs, int njobs, const T* M, int xmode, const double* xv,
-                  const int* gidx, const signed char* gsgn, double scale, double* y,
-                  const int* done, hipStream_t st) {
+void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, int xmode,
+                  const double* xv, const int* gidx, const signed char* gsgn, double scale,
+                  double* y, const int* done, hipStream_t st) {
   if (njobs == 0) return;
-  hipLaunchKernelGGL(k_tiles<T>, dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx, gsgn,
-                     scale, y, done);
+  switch (group) {
+    case 0:
+      TCF_TIMED_LAUNCH((k_tiles<T, 0>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
+                         gsgn, scale, y, done);
+      break;
+    case 1:
+      TCF_TIMED_LAUNCH((k_tiles<T, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
+                         gsgn, scale, y, done);
+      break;
+    case 2:
+      TCF_TIMED_LAUNCH((k_tiles<T, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
+                         gsgn, scale, y, done);
+      break;
+    default:
+      TCF_TIMED_LAUNCH((k_tiles<T, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
+                         gsgn, scale, y, done);
+      break;
+  }
+}
+
+// Plain streaming copy (measurement reference for traffic counters).
+__global__ void k_copy_probe(int64_t n, const double4* a, double4* b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+void launch_copy_probe(int64_t n32, const void* a, void* b, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_probe, dim3(8192), dim3(256), 0, st, n32, (const double4*)a,
+                     (double4*)b);
 }
 void launch_zero(int64_t n, double* a, hipStream_t st) {
   if (n == 0) return;
@@ -1580,10 +1632,10 @@ template void launch_pack_tiles<double, double>(const PackJob*, int, const doubl
                                                 hipStream_t);
 template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,
                                               hipStream_t);
-template void launch_tiles<double>(const TileJob*, int, const double*, int, const double*,
+template void launch_tiles<double>(int, const TileJob*, int, const double*, int, const double*,
                                    const int*, const signed char*, double, double*, const int*,
                                    hipStream_t);
-template void launch_tiles<float>(const TileJob*, int, const float*, int, const double*,
+template void launch_tiles<float>(int, const TileJob*, int, const float*, int, const double*,
                                   const int*, const signed char*, double, double*, const int*,
                                   hipStream_t);
 }  // namespace tcf

@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
            "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
-           "tcf_profile_get", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
+           "tcf_profile_get", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
            "tcf_server_poll", "tcf_server_wait", "tcf_server_fetch", "tcf_server_stats",
            "tcf_server_error", "tcf_server_destroy"]
 TCF_REQ_QUEUED, TCF_REQ_RUNNING, TCF_REQ_DONE, TCF_REQ_FAILED = range(4)
@@ -108,6 +108,7 @@ def lib():
     L.tcf_profile_enable.argtypes = [P, C.c_int32]
     L.tcf_profile_get.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double)]
+    L.tcf_copy_probe.argtypes = [C.c_size_t, P]
     L.tcf_destroy.argtypes = [P]
     L.tcf_destroy.restype = None
     L.tcf_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(P)]
@@ -194,6 +195,13 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
         check_every=int(check_every), use_graph=int(use_graph))
     return d, o, keep
+
+
+def tcf_copy_probe(nbytes, stream=None):
+    """One launch of the plain copy kernel (traffic-counter reference)."""
+    rc = lib().tcf_copy_probe(int(nbytes), Problem._stream(stream))
+    if rc != TCF_OK:
+        raise TcfError(rc, "tcf_copy_probe")
 
 
 class Server:
