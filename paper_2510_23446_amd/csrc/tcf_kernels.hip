@@ -1516,29 +1516,50 @@ __device__ inline double tile_x(int xmode, const double* xv, const int* gidx,
   return xv[gidx[off]];
 }
 
-// One block (256 threads) per tile.  Thread t covers column t/4 and 16
-// consecutive rows of it; the T part is reduced across the 4 threads of a
-// column, the N part through an LDS transpose.  Results are added to y with
-// FP64 atomics (each tile of a symmetric operator serves A_IJ and A_IJ^T).
+// One block (256 threads) per 64x64 tile (column-major, zero-padded).
+// Loads are coalesced: load k of thread t reads the 16-byte chunk k*256 + t,
+// i.e. V = 16/sizeof(T) consecutive rows (V*(t % RPC) ..) of column
+// k*(256/RPC) + t/RPC, RPC = 64/V chunks per column, so each wave reads
+// 1 KiB contiguous per instruction.  N part (row sums): each thread sums its
+// columns, then threads with equal t % RPC are combined by lane shuffles and
+// one LDS row per wave.  T part (column sums): per-thread partials over its
+// V rows go through LDS and are summed by 4 threads per column.  Results are
+// added to y with FP64 atomics (a tile of a symmetric operator serves A_IJ
+// and A_IJ^T).
+template <class T>
+struct TileVec;
+template <>
+struct TileVec<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+template <>
+struct TileVec<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+
 template <class T, int Group>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb, int xmode,
                                                const double* xv, const int* gidx,
                                                const signed char* gsgn, double scale,
                                                double* y, const int* done) {
+  typedef typename TileVec<T>::v VT;
+  constexpr int V = TileVec<T>::n;   // rows per chunk
+  constexpr int RPC = 64 / V;        // chunks per column
+  constexpr int L = 64 * 64 / V / 256;  // loads per thread
+  constexpr int CPL = 256 / RPC;     // columns advanced per load
+  const TileJob jb = jobs[blockIdx.x];  // issued together with the flag read
   if (done && *done) return;
-  const TileJob jb = jobs[blockIdx.x];
   __shared__ double xr[64], xc[64];
-  __shared__ double P[64][65];
+  __shared__ double Tp[64][RPC + 1];
+  __shared__ double Np[4][64];
   const int t = threadIdx.x;
   const bool doN = jb.flags & 1, doT = jb.flags & 2;
-  const int c = t >> 2, g = t & 3;
-  typedef typename Vec16<T>::type VT;
-  constexpr int V = Vec16<T>::n;
-  // matrix loads first: they do not depend on the gathered inputs
-  const VT* col = reinterpret_cast<const VT*>(Mb + jb.m_off + (int64_t)c * 64 + g * 16);
-  VT raw[16 / V];
+  const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
+  VT raw[L];
 #pragma unroll
-  for (int k = 0; k < 16 / V; ++k) raw[k] = col[k];
+  for (int k = 0; k < L; ++k) raw[k] = __builtin_nontemporal_load(base + k * 256 + t);
   if (t < 64) {
     xr[t] = (doT && t < jb.nr) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xr_off + t) : 0.0;
   } else if (t < 128) {
@@ -1546,34 +1567,50 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
     xc[cc] = (doN && cc < jb.nc) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xc_off + cc) : 0.0;
   }
   __syncthreads();
-  double a[16];
+  const int lr = t % RPC, h = t / RPC;
+  const int r0 = V * lr;
+  double xrv[V], n[V];
 #pragma unroll
-  for (int k = 0; k < 16 / V; ++k) {
-    const T* e = reinterpret_cast<const T*>(&raw[k]);
-#pragma unroll
-    for (int q = 0; q < V; ++q) a[k * V + q] = (double)e[q];
+  for (int v = 0; v < V; ++v) {
+    xrv[v] = xr[r0 + v];
+    n[v] = 0.0;
   }
-  // T part: column sums
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int cc = k * CPL + h;
+    const double xcv = xc[cc];
+    double tp = 0.0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double a = (double)raw[k][v];
+      n[v] += a * xcv;
+      tp += a * xrv[v];
+    }
+    Tp[cc][lr] = tp;
+  }
+  // rows r0.. are shared by the lanes of a wave with equal t % RPC
+#pragma unroll
+  for (int m = RPC; m < 64; m <<= 1)
+#pragma unroll
+    for (int v = 0; v < V; ++v) n[v] += __shfl_xor(n[v], m, 64);
+  const int w = t >> 6;
+  if ((t & 63) < RPC) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) Np[w][r0 + v] = n[v];
+  }
+  __syncthreads();
   if (doT) {
-    double s = 0.0;
+    const int cc = t >> 2, q = t & 3;
+    double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s += a[k] * xr[g * 16 + k];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (g == 0 && c < jb.nc) atomicAdd(y + jb.yc_off + c, s);
+    for (int k = 0; k < RPC / 4; ++k) sum += Tp[cc][q * (RPC / 4) + k];
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    if (q == 0 && cc < jb.nc) atomicAdd(y + jb.yc_off + cc, sum);
   }
-  if (doN) {
-    const double xcv = xc[c];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) P[g * 16 + k][c] = a[k] * xcv;
-    __syncthreads();
-    const int r = t >> 2, q = t & 3;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) s += P[r][q * 16 + k];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (q == 0 && r < jb.nr) atomicAdd(y + jb.yr_off + r, s);
+  if (doN && t < 64) {
+    const double sum = (Np[0][t] + Np[1][t]) + (Np[2][t] + Np[3][t]);
+    if (t < jb.nr) atomicAdd(y + jb.yr_off + t, sum);
   }
 }
 
