@@ -166,7 +166,9 @@ struct tcf_problem {
   double* d_tC = nullptr;
   TileJob *tj_apply = nullptr, *tj_phi = nullptr, *tj_pre = nullptr, *tj_coarse = nullptr;
   int n_tapply = 0, n_tphi = 0, n_tpre = 0, n_tcoarse = 0;
-  double* d_acc = nullptr;  // vc | q | tb accumulators of the tile path
+  double* d_acc = nullptr;  // vc | cv | q | tb accumulators of the tile path
+  int* d_cmap = nullptr;    // local primal entry -> position of its coarse unknown in d_acc
+  int64_t n_acc = 0;
   int *d_posp_bp = nullptr, *d_posm_bp = nullptr;
   bool use_tiles = true;
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
@@ -1097,12 +1099,48 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
 
 // Tile copies of the per-iteration operators: lower 64x64 tiles of S_bb^-1
 // (with the Phi_b tiles), of S_bb and of S_Pi^-1, plus the job lists.
+// A tile job and its packing: a block whose last tile row is ragged (nr < nc)
+// is stored transposed, so that only the nc <= 64 stored columns of 64 rows
+// are read; the roles of rows and columns (N and T parts, their inputs,
+// outputs and output maps) swap with it.
+static void add_tile(std::vector<PackJob>& pk, std::vector<TileJob>& tj, int64_t& off,
+                     int64_t src_off, int ld, int row0, int col0, TileJob jb) {
+  const bool trans = jb.nr < jb.nc;
+  pk.push_back(PackJob{src_off, off, ld, row0, col0, jb.nr, jb.nc, trans ? 1 : 0});
+  if (trans) {
+    const int f = jb.flags;
+    jb = TileJob{jb.m_off, jb.xc_off, jb.xr_off, jb.yc_off, jb.yr_off, jb.nc, jb.nr,
+                 ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1), 0};
+  }
+  jb.m_off = off;
+  tj.push_back(jb);
+  off += 64 * (int64_t)jb.nc;
+}
+
+// Phi tiles are read by two job lists (the apply's T part and the coarse
+// correction's N part): one packing, two jobs with the same orientation.
+static void add_phi_tile(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
+                         std::vector<TileJob>& jphi, int64_t& off, int64_t src_off, int ld,
+                         int row0, int col0, TileJob japp, TileJob jphi_) {
+  const int64_t off0 = off;
+  add_tile(pk, ja, off, src_off, ld, row0, col0, japp);
+  const bool trans = jphi_.nr < jphi_.nc;
+  if (trans) {
+    const int f = jphi_.flags;
+    jphi_ = TileJob{0, jphi_.xc_off, jphi_.xr_off, jphi_.yc_off, jphi_.yr_off, jphi_.nc, jphi_.nr,
+                    ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1), 0};
+  }
+  jphi_.m_off = off0;
+  jphi.push_back(jphi_);
+}
+
+// Tile copies of the per-iteration operators: lower tiles of S_bb^-1 (with
+// the Phi_b tiles), of S_bb and of S_Pi^-1, plus the job lists.
 template <class T>
 static int build_tiles(tcf_problem* h, hipStream_t st) {
   std::vector<PackJob> pa, pb, pc;
   std::vector<TileJob> ja, jphi, jpre, jc;
   int64_t oa = 0, ob = 0, oc = 0;
-  const int64_t TT = 64 * 64;
   for (int s = 0; s < h->np_tot; ++s) {
     const DevPatch& d = h->hp[s];
     if (d.n_b == 0) continue;
@@ -1110,22 +1148,20 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int J = 0; J < Tb; ++J)
       for (int I = J; I < Tb; ++I) {
         const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_b - 64 * J);
-        pa.push_back(PackJob{d.G_off, oa, d.nb_pad, 64 * I, 64 * J, nr, nc, 0});
-        ja.push_back(TileJob{oa, d.b_off + 64 * I, d.b_off + 64 * J, d.bp_off + 64 * I,
-                             d.bp_off + 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
-        oa += TT;
-        pb.push_back(PackJob{d.S_off, ob, d.nb_pad, 64 * I, 64 * J, nr, nc, 0});
-        jpre.push_back(TileJob{ob, d.b_off + 64 * I, d.b_off + 64 * J, d.b_off + 64 * I,
-                               d.b_off + 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
-        ob += TT;
+        const int fl = 1 | (I != J ? 2 : 0);
+        add_tile(pa, ja, oa, d.G_off, d.nb_pad, 64 * I, 64 * J,
+                 TileJob{0, d.b_off + 64 * I, d.b_off + 64 * J, d.bp_off + 64 * I,
+                         d.bp_off + 64 * J, nr, nc, fl, 0});
+        add_tile(pb, jpre, ob, d.S_off, d.nb_pad, 64 * I, 64 * J,
+                 TileJob{0, d.b_off + 64 * I, d.b_off + 64 * J, d.b_off + 64 * I,
+                         d.b_off + 64 * J, nr, nc, fl, 0});
       }
     for (int K = 0; K < Tp; ++K)
       for (int I = 0; I < Tb; ++I) {
         const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_p - 64 * K);
-        pa.push_back(PackJob{d.G_off, oa, d.nb_pad, 64 * I, d.n_b + 64 * K, nr, nc, 0});
-        ja.push_back(TileJob{oa, d.b_off + 64 * I, 0, 0, d.bp_off + d.n_b + 64 * K, nr, nc, 2, 0});
-        jphi.push_back(TileJob{oa, 0, d.p_off + 64 * K, d.bp_off + 64 * I, 0, nr, nc, 1, 0});
-        oa += TT;
+        add_phi_tile(pa, ja, jphi, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K,
+                     TileJob{0, d.b_off + 64 * I, 0, 0, d.p_off + 64 * K, nr, nc, 2 | 4, 0},
+                     TileJob{0, 0, d.p_off + 64 * K, d.bp_off + 64 * I, 0, nr, nc, 1, 0});
       }
   }
   const int nP = h->n_primal;
@@ -1133,9 +1169,8 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
   for (int J = 0; J < Tc; ++J)
     for (int I = J; I < Tc; ++I) {
       const int nr = std::min(64, nP - 64 * I), nc = std::min(64, nP - 64 * J);
-      pc.push_back(PackJob{0, oc, h->nPi_pad, 64 * I, 64 * J, nr, nc, 0});
-      jc.push_back(TileJob{oc, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
-      oc += TT;
+      add_tile(pc, jc, oc, 0, h->nPi_pad, 64 * I, 64 * J,
+               TileJob{0, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
     }
   T *tA, *tB;
   RCCHK(h->alloc(&tA, (size_t)oa));
@@ -1163,7 +1198,14 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
   h->n_tphi = (int)jphi.size();
   h->n_tpre = (int)jpre.size();
   h->n_tcoarse = (int)jc.size();
-  RCCHK(h->alloc(&h->d_acc, (size_t)(h->n_bptot + std::max(nP, 1) + h->n_btot)));
+  // c = Phi_b^T x goes straight into the coarse vector: cv = sum_s N_s^T c_s
+  std::vector<int> cmap((size_t)std::max<int64_t>(h->n_ptot, 1), 0);
+  for (int s = 0; s < h->np_tot; ++s)
+    for (int j = 0; j < h->hp[s].n_p; ++j)
+      cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->plans[s].p_rank[j];
+  RCCHK(h->upload(&h->d_cmap, cmap));
+  h->n_acc = h->n_bptot + 2 * std::max(nP, 1) + h->n_btot;
+  RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
   return TCF_OK;
 }
 
@@ -1256,58 +1298,50 @@ static void apply_M(tcf_problem* h, const double* r, double* z, double* part, co
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
 }
 
-// Tile-path operators: accumulators vc | q | tb are zeroed, then each tile
-// adds its share with FP64 atomics.
-template <class T>
-static void apply_F_tiles(tcf_problem* h, const double* p, double* Fp, double* part,
-                          const int* done, hipStream_t st) {
-  double* vc = h->d_acc;
-  double* q = h->d_acc + h->n_bptot;
-  timed(h, TCF_KG_APPLY, st, [&] {
-    launch_tiles<T>(0, h->tj_apply, h->n_tapply, (const T*)h->d_tA, 1, p, h->d_brow, h->d_bsgn,
-                    h->dt, vc, done, st);
-  });
-  if (h->n_primal > 0) {
-    launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, vc, 1.0,
-                         nullptr, h->d_cv, done, st);
-    timed(h, TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(3, h->tj_coarse, h->n_tcoarse, h->d_tC, 0, h->d_cv, nullptr, nullptr,
-                           1.0, q, done, st);
-    });
-    timed(h, TCF_KG_PHI, st, [&] {
-      launch_tiles<T>(1, h->tj_phi, h->n_tphi, (const T*)h->d_tA, 2, q, h->d_prank, nullptr, 1.0,
-                      vc, done, st);
-    });
-  }
-  launch_jump(h->n_lambda, h->d_posp_bp, h->d_posm_bp, vc, h->dt, Fp, p, part, done, st);
-}
-
-template <class T>
-static void apply_M_tiles(tcf_problem* h, const double* r, double* z, double* part,
-                          const int* done, hipStream_t st) {
-  double* tb = h->d_acc + h->n_bptot + std::max(h->n_primal, 1);
-  timed(h, TCF_KG_PRECOND, st, [&] {
-    launch_tiles<T>(2, h->tj_pre, h->n_tpre, (const T*)h->d_tB, 1, r, h->d_brow, h->d_bsgn, 1.0, tb,
-                    done, st);
-  });
-  launch_jump(h->n_lambda, h->d_posp, h->d_posm, tb, 1.0, z, r, part, done, st);
-}
-
 // One PCG iteration with the given parity (launch sequence only).
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
   if (h->use_tiles) {
+    // Tile path, 8 launches.  Accumulators d_acc = [vc | cv | q | tb]: vc
+    // gets [S_bb^-1 x; .] and Phi_b N q, cv = sum_s N_s^T Phi_b^T x_s, q the
+    // coarse solution, tb = S_bb B^T r.  Each is cleared by a kernel that
+    // runs after its last reader (tb by the first jump, the rest by the
+    // update), and once before the first iteration of a solve.
     const int nl = h->n_lambda, npt = h->npart;
     const int* done = &h->d_st->done;
     double* p_pq = h->d_part;
     double* p_rr = h->d_part + npt;
     double* p_rz = h->d_part + 2 * npt;
     const double tol2 = h->pcg_tol * h->pcg_tol;
-    launch_zero(h->n_bptot + std::max(h->n_primal, 1) + h->n_btot, h->d_acc, st);
-    apply_F_tiles<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
-    launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
-    launch_pcg_check(p_rr, npt, h->d_st, tol2, st);
-    apply_M_tiles<T>(h, h->d_r, h->d_z, p_rz, done, st);
+    const int64_t nPm = std::max(h->n_primal, 1);
+    double* vc = h->d_acc;
+    double* cv = vc + h->n_bptot;
+    double* q = cv + nPm;
+    double* tb = q + nPm;
+    timed(h, TCF_KG_APPLY, st, [&] {
+      launch_tiles<T>(0, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, h->d_brow,
+                      h->d_bsgn, h->dt, vc, h->d_cmap, done, st);
+    });
+    if (h->n_primal > 0) {
+      timed(h, TCF_KG_COARSE, st, [&] {
+        launch_tiles<double>(3, h->tj_coarse, h->n_tcoarse, h->d_tC, cv, nullptr, nullptr, 1.0,
+                             q, nullptr, done, st);
+      });
+      timed(h, TCF_KG_PHI, st, [&] {
+        launch_tiles<T>(1, h->tj_phi, h->n_tphi, (const T*)h->d_tA, q, h->d_prank, nullptr,
+                        1.0, vc, nullptr, done, st);
+      });
+    }
+    launch_jump(nl, h->d_posp_bp, h->d_posm_bp, vc, h->dt, h->d_Fp, h->d_p, p_pq, done, st, tb,
+                h->n_btot);
+    launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st,
+                      vc, h->n_bptot + 2 * nPm);
+    timed(h, TCF_KG_PRECOND, st, [&] {
+      launch_tiles<T>(2, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, h->d_brow, h->d_bsgn,
+                      1.0, tb, nullptr, done, st);
+    });
+    launch_jump_check(nl, h->d_posp, h->d_posm, tb, h->d_z, h->d_r, p_rz, p_rr, npt, h->d_st,
+                      tol2, st);
     launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
     return;
   }
@@ -1367,6 +1401,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bo
   launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
   apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
   launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
+  if (h->use_tiles) launch_zero(h->n_acc, h->d_acc, st);
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
   if (h->opt.use_graph && !h->prof_on) RCCHK(build_pcg_graph<T>(h));
   const bool graph = h->opt.use_graph && !h->prof_on && h->pcg_graph;

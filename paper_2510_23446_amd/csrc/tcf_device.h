@@ -63,9 +63,11 @@ struct AxpyJob {
   int out_off;
 };
 
-// One 64x64 tile of an operator stored tile by tile (column-major inside the
-// tile, zero beyond nr x nc).  N part: y[yr_off + r] += sum_c A[r,c] x[xc_off + c];
-// T part: y[yc_off + c] += sum_r A[r,c] x[xr_off + r].  flags bit 0 = N, bit 1 = T.
+// One tile of an operator stored tile by tile: nc columns of 64 rows each
+// (column-major, zero beyond row nr).  N part: y[yr_off + r] += sum_c A[r,c]
+// x[xc_off + c]; T part: y[yc_off + c] += sum_r A[r,c] x[xr_off + r].
+// flags bit 0 = N, bit 1 = T, bit 2 = T output at y[ymap[yc_off + c]],
+// bit 3 = N output at y[ymap[yr_off + r]].
 struct TileJob {
   int64_t m_off;
   int xr_off, xc_off;
@@ -75,12 +77,15 @@ struct TileJob {
   int pad;
 };
 
-// Copy a block of a column-major source into one zero-padded 64x64 tile.
+// Copy the nr x nc block at (row0, col0) of a column-major source into a tile
+// of 64-row columns (rows beyond the block are zero).  trans = 0: nc stored
+// columns, tile(r, c) = block(r, c); trans = 1: nr stored columns,
+// tile(c, r) = block(r, c).
 struct PackJob {
   int64_t src_off;
   int64_t dst_off;
   int ld, row0, col0, nr, nc;
-  int pad;
+  int trans;
 };
 
 struct PcgScalars {

@@ -934,14 +934,16 @@ __device__ inline double block_sum256(double v, double* sh) {
   return r;  // valid in thread 0
 }
 
-// y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i]
+// y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i];
+// also clears zero[0 .. nzero) (an accumulator not in use at this point)
 __global__ void __launch_bounds__(256) k_jump(int n, const int* pos_p, const int* pos_m,
                                               const double* w, double scale, double* y,
                                               const double* dotw, double* partial,
-                                              const int* done) {
+                                              const int* done, double* zero, int64_t nzero) {
   if (done && *done) return;
   __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
   double d = 0.0;
   if (i < n) {
     const double v = scale * (w[pos_p[i]] - w[pos_m[i]]);
@@ -1007,26 +1009,67 @@ __global__ void __launch_bounds__(256) k_pcg_init2(int n, const double* z, doubl
   }
 }
 
-// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r
+// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r;
+// also clears zero[0 .. nzero) (accumulators consumed earlier in the iteration)
 __global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq, int npart,
                                                     PcgScalars* st, int par, double* lam,
                                                     double* r, const double* p, const double* Fp,
-                                                    double* part_rr) {
+                                                    double* part_rr, double* zero,
+                                                    int64_t nzero) {
   if (st->done) return;
   __shared__ double sh[1];
   __shared__ double sh4[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double pi = 0.0, fi = 0.0, ri = 0.0, li = 0.0;
+  if (i < n) {  // independent of the reduction: in flight while it runs
+    pi = p[i];
+    fi = Fp[i];
+    ri = r[i];
+    li = lam[i];
+  }
+  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
   const double pq = sum_partials(part_pq, npart, sh);
   const double alpha = st->rz[par] / pq;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double v = 0.0;
   if (i < n) {
-    lam[i] += alpha * p[i];
-    const double ri = r[i] - alpha * Fp[i];
+    lam[i] = li + alpha * pi;
+    ri -= alpha * fi;
     r[i] = ri;
     v = ri * ri;
   }
   const double s = block_sum256(v, sh4);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// z = jump(w); partial[block] = z.r.  Block 0 also sums the ||r||^2 partials
+// and records ||r||^2, the iteration count and the convergence flag.  Other
+// blocks may see the flag set by block 0 and stop early: their z and r.z
+// are then never used (a converged iteration leaves lambda as it is).
+__global__ void __launch_bounds__(256) k_jump_check(int n, const int* pos_p, const int* pos_m,
+                                                    const double* w, double* z, const double* r,
+                                                    double* part_rz, const double* part_rr,
+                                                    int npart, PcgScalars* st, double tol2) {
+  if (st->done) return;
+  __shared__ double sh[4];
+  __shared__ double sh1[1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double d = 0.0;
+  if (i < n) {
+    const double v = w[pos_p[i]] - w[pos_m[i]];
+    z[i] = v;
+    d = v * r[i];
+  }
+  const double s = block_sum256(d, sh);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s;
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    const double rr = sum_partials(part_rr, npart, sh1);
+    if (threadIdx.x == 0) {
+      st->rr = rr;
+      st->iters += 1;
+      if (rr <= tol2 * st->dd) st->done = 1;
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256) k_pcg_check(const double* part_rr, int npart,
@@ -1241,10 +1284,17 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
 }
 
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
-                 const double* dotw, double* partial, const int* done, hipStream_t st) {
+                 const double* dotw, double* partial, const int* done, hipStream_t st,
+                 double* zero, int64_t nzero) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_jump, TCF_GRID(n, 256), dim3(256), 0, st, n, pp, pm, w, scale, y, dotw,
-                     partial, done);
+                     partial, done, zero, nzero);
+}
+void launch_jump_check(int n, const int* pp, const int* pm, const double* w, double* z,
+                       const double* r, double* part_rz, const double* part_rr, int npart,
+                       PcgScalars* stt, double tol2, hipStream_t st) {
+  hipLaunchKernelGGL(k_jump_check, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, w, z, r,
+                     part_rz, part_rr, npart, stt, tol2);
 }
 void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
                      hipStream_t st) {
@@ -1256,9 +1306,10 @@ void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, cons
                      npart, stt);
 }
 void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
-                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st) {
+                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st,
+                       double* zero, int64_t nzero) {
   hipLaunchKernelGGL(k_pcg_update, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, ppq, npart, stt,
-                     par, lam, r, p, Fp, prr);
+                     par, lam, r, p, Fp, prr, zero, nzero);
 }
 void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
                       hipStream_t st) {
@@ -1499,24 +1550,21 @@ __global__ void k_pack_tiles(const PackJob* jobs, const TS* src, TD* dst) {
   const PackJob jb = jobs[blockIdx.x];
   TD* o = dst + jb.dst_off;
   const TS* s = src + jb.src_off;
-  for (int idx = threadIdx.x; idx < 64 * 64; idx += blockDim.x) {
+  const int ncs = jb.trans ? jb.nr : jb.nc;  // stored columns
+  const int nrs = jb.trans ? jb.nc : jb.nr;  // filled rows
+  for (int idx = threadIdx.x; idx < 64 * ncs; idx += blockDim.x) {
     const int r = idx % 64, c = idx / 64;
     TD v = TD(0);
-    if (r < jb.nr && c < jb.nc) v = (TD)s[(int64_t)(jb.row0 + r) + (int64_t)(jb.col0 + c) * jb.ld];
+    if (r < nrs) {
+      const int br = jb.trans ? c : r, bc = jb.trans ? r : c;
+      v = (TD)s[(int64_t)(jb.row0 + br) + (int64_t)(jb.col0 + bc) * jb.ld];
+    }
     o[idx] = v;
   }
 }
 
-// Input value of a tile side: xmode 0 direct xv[off + i]; 1 signed gather
-// scale * sgn[off + i] * xv[gidx[off + i]]; 2 plain gather xv[gidx[off + i]].
-__device__ inline double tile_x(int xmode, const double* xv, const int* gidx,
-                                const signed char* gsgn, double scale, int off) {
-  if (xmode == 0) return xv[off];
-  if (xmode == 1) return scale * (double)gsgn[off] * xv[gidx[off]];
-  return xv[gidx[off]];
-}
 
-// One block (256 threads) per 64x64 tile (column-major, zero-padded).
+// One block (256 threads) per tile (nc <= 64 columns of 64 rows, zero-padded).
 // Loads are coalesced: load k of thread t reads the 16-byte chunk k*256 + t,
 // i.e. V = 16/sizeof(T) consecutive rows (V*(t % RPC) ..) of column
 // k*(256/RPC) + t/RPC, RPC = 64/V chunks per column, so each wave reads
@@ -1539,35 +1587,65 @@ struct TileVec<float> {
   static constexpr int n = 4;
 };
 
+// Group (the operator) fixes the input mode: 0 (F apply) and 2 (Dirichlet
+// preconditioner) take the signed gather scale * gsgn[i] * xv[gidx[i]],
+// 1 (Phi_b N q) the plain gather xv[gidx[i]], 3 (coarse) reads xv[i].
 template <class T, int Group>
-__global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb, int xmode,
+__global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
                                                const double* xv, const int* gidx,
                                                const signed char* gsgn, double scale,
-                                               double* y, const int* done) {
+                                               double* y, const int* ymap, const int* done) {
+  constexpr int XM = Group == 3 ? 0 : (Group == 1 ? 2 : 1);
   typedef typename TileVec<T>::v VT;
   constexpr int V = TileVec<T>::n;   // rows per chunk
   constexpr int RPC = 64 / V;        // chunks per column
   constexpr int L = 64 * 64 / V / 256;  // loads per thread
   constexpr int CPL = 256 / RPC;     // columns advanced per load
-  const TileJob jb = jobs[blockIdx.x];  // issued together with the flag read
-  if (done && *done) return;
-  __shared__ double xr[64], xc[64];
+  const TileJob jb = jobs[blockIdx.x];
+  // the test reads a job field (never negative) so that the descriptor load
+  // is issued together with the flag read instead of after it
+  if ((done ? *done : 0) | (jb.nc < 0) | (jb.m_off < 0)) return;
+  __shared__ double xs[256];  // [0, 64) row-side inputs, [64, 128) column side, rest unused
   __shared__ double Tp[64][RPC + 1];
   __shared__ double Np[4][64];
+  const double* xr = xs;
+  const double* xc = xs + 64;
   const int t = threadIdx.x;
   const bool doN = jb.flags & 1, doT = jb.flags & 2;
   const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
+  // inputs, step 1: gather indices (threads 0..63 the row side, 64..127 the
+  // column side).  Issued before the matrix loads: memory counters retire in
+  // order, so an index load issued after them would wait for the whole tile.
+  const bool side_r = t < 64;
+  const int tt = side_r ? t : t - 64;
+  const bool xon = t < 128 && (side_r ? (doT && tt < jb.nr) : (doN && tt < jb.nc));
+  // lanes without an input read entry 0 (which every table has): no branch
+  // around the loads, whose results are only used after the matrix loads
+  const int xo = xon ? (side_r ? jb.xr_off : jb.xc_off) + tt : 0;
+  int gi = xo, sgi = 1;
+  if (XM != 0) gi = gidx[xo];
+  if (XM == 1) sgi = gsgn[xo];
+  // keep the index loads ahead of the matrix loads (straight-line code, so
+  // this pins the order the scheduler emits)
+  __builtin_amdgcn_sched_barrier(0);
   VT raw[L];
+  const int h = t / RPC, lr = t % RPC;
+  // only the nc stored columns exist: a lane past them reads its row chunk
+  // of column 0 instead and drops the value (no branch around the loads,
+  // which would serialise them)
 #pragma unroll
-  for (int k = 0; k < L; ++k) raw[k] = __builtin_nontemporal_load(base + k * 256 + t);
-  if (t < 64) {
-    xr[t] = (doT && t < jb.nr) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xr_off + t) : 0.0;
-  } else if (t < 128) {
-    const int cc = t - 64;
-    xc[cc] = (doN && cc < jb.nc) ? tile_x(xmode, xv, gidx, gsgn, scale, jb.xc_off + cc) : 0.0;
+  for (int k = 0; k < L; ++k) {
+    const bool ok = k * CPL + h < jb.nc;
+    const VT v = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
+    raw[k] = ok ? v : VT(0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // inputs, step 2: values, all 256 lanes (no branch): slot t of xs
+  {
+    const double xg = xv[gi];
+    xs[t] = xon ? (XM == 1 ? scale * (double)sgi : 1.0) * xg : 0.0;
   }
   __syncthreads();
-  const int lr = t % RPC, h = t / RPC;
   const int r0 = V * lr;
   double xrv[V], n[V];
 #pragma unroll
@@ -1606,11 +1684,14 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
     for (int k = 0; k < RPC / 4; ++k) sum += Tp[cc][q * (RPC / 4) + k];
     sum += __shfl_xor(sum, 1, 64);
     sum += __shfl_xor(sum, 2, 64);
-    if (q == 0 && cc < jb.nc) atomicAdd(y + jb.yc_off + cc, sum);
+    if (q == 0 && cc < jb.nc) {
+      const int yi = (jb.flags & 4) ? ymap[jb.yc_off + cc] : jb.yc_off + cc;
+      atomicAdd(y + yi, sum);
+    }
   }
   if (doN && t < 64) {
     const double sum = (Np[0][t] + Np[1][t]) + (Np[2][t] + Np[3][t]);
-    if (t < jb.nr) atomicAdd(y + jb.yr_off + t, sum);
+    if (t < jb.nr) atomicAdd(y + ((jb.flags & 8) ? ymap[jb.yr_off + t] : jb.yr_off + t), sum);
   }
 }
 
@@ -1627,26 +1708,26 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
 // group only names the kernel instance (apply / phi / precond / coarse) so
 // that traces attribute each operator separately
 template <class T>
-void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, int xmode,
-                  const double* xv, const int* gidx, const signed char* gsgn, double scale,
-                  double* y, const int* done, hipStream_t st) {
+void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, const double* xv,
+                  const int* gidx, const signed char* gsgn, double scale, double* y,
+                  const int* ymap, const int* done, hipStream_t st) {
   if (njobs == 0) return;
   switch (group) {
     case 0:
-      TCF_TIMED_LAUNCH((k_tiles<T, 0>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
-                         gsgn, scale, y, done);
+      TCF_TIMED_LAUNCH((k_tiles<T, 0>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
+                       scale, y, ymap, done);
       break;
     case 1:
-      TCF_TIMED_LAUNCH((k_tiles<T, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
-                         gsgn, scale, y, done);
+      TCF_TIMED_LAUNCH((k_tiles<T, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
+                       scale, y, ymap, done);
       break;
     case 2:
-      TCF_TIMED_LAUNCH((k_tiles<T, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
-                         gsgn, scale, y, done);
+      TCF_TIMED_LAUNCH((k_tiles<T, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
+                       scale, y, ymap, done);
       break;
     default:
-      TCF_TIMED_LAUNCH((k_tiles<T, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xmode, xv, gidx,
-                         gsgn, scale, y, done);
+      TCF_TIMED_LAUNCH((k_tiles<T, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
+                       scale, y, ymap, done);
       break;
   }
 }
@@ -1669,10 +1750,10 @@ template void launch_pack_tiles<double, double>(const PackJob*, int, const doubl
                                                 hipStream_t);
 template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,
                                               hipStream_t);
-template void launch_tiles<double>(int, const TileJob*, int, const double*, int, const double*,
+template void launch_tiles<double>(int, const TileJob*, int, const double*, const double*,
                                    const int*, const signed char*, double, double*, const int*,
-                                   hipStream_t);
-template void launch_tiles<float>(int, const TileJob*, int, const float*, int, const double*,
+                                   const int*, hipStream_t);
+template void launch_tiles<float>(int, const TileJob*, int, const float*, const double*,
                                   const int*, const signed char*, double, double*, const int*,
-                                  hipStream_t);
+                                  const int*, hipStream_t);
 }  // namespace tcf
