@@ -1110,7 +1110,8 @@ static void add_tile(std::vector<PackJob>& pk, std::vector<TileJob>& tj, int64_t
   if (trans) {
     const int f = jb.flags;
     jb = TileJob{jb.m_off, jb.xc_off, jb.xr_off, jb.yc_off, jb.yr_off, jb.nc, jb.nr,
-                 ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1), 0};
+                 ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1) | (f & ~15),
+                 0};
   }
   jb.m_off = off;
   tj.push_back(jb);
@@ -1128,7 +1129,8 @@ static void add_phi_tile(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
   if (trans) {
     const int f = jphi_.flags;
     jphi_ = TileJob{0, jphi_.xc_off, jphi_.xr_off, jphi_.yc_off, jphi_.yr_off, jphi_.nc, jphi_.nr,
-                    ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1), 0};
+                    ((f & 1) << 1) | ((f & 2) >> 1) | ((f & 4) << 1) | ((f & 8) >> 1) | (f & ~15),
+                    0};
   }
   jphi_.m_off = off0;
   jphi.push_back(jphi_);
@@ -1148,7 +1150,8 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int J = 0; J < Tb; ++J)
       for (int I = J; I < Tb; ++I) {
         const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_b - 64 * J);
-        const int fl = 1 | (I != J ? 2 : 0);
+        // N (+T off the diagonal) and the quadratic form x^T A x (bits 4, 5)
+        const int fl = 1 | (I != J ? 2 | 32 : 0) | 16;
         add_tile(pa, ja, oa, d.G_off, d.nb_pad, 64 * I, 64 * J,
                  TileJob{0, d.b_off + 64 * I, d.b_off + 64 * J, d.bp_off + 64 * I,
                          d.bp_off + 64 * J, nr, nc, fl, 0});
@@ -1170,7 +1173,8 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int I = J; I < Tc; ++I) {
       const int nr = std::min(64, nP - 64 * I), nc = std::min(64, nP - 64 * J);
       add_tile(pc, jc, oc, 0, h->nPi_pad, 64 * I, 64 * J,
-               TileJob{0, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 : 0), 0});
+               TileJob{0, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 | 32 : 0) | 16,
+                       0});
     }
   T *tA, *tB;
   RCCHK(h->alloc(&tA, (size_t)oa));
@@ -1204,7 +1208,8 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int j = 0; j < h->hp[s].n_p; ++j)
       cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->plans[s].p_rank[j];
   RCCHK(h->upload(&h->d_cmap, cmap));
-  h->n_acc = h->n_bptot + 2 * std::max(nP, 1) + h->n_btot;
+  // [vc | cv | q | slots of p.Fp | tb | slots of r.z]
+  h->n_acc = h->n_bptot + 2 * std::max(nP, 1) + 2 * TCF_QSLOTS + h->n_btot;
   RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
   return TCF_OK;
 }
@@ -1302,47 +1307,46 @@ static void apply_M(tcf_problem* h, const double* r, double* z, double* part, co
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
   if (h->use_tiles) {
-    // Tile path, 8 launches.  Accumulators d_acc = [vc | cv | q | tb]: vc
-    // gets [S_bb^-1 x; .] and Phi_b N q, cv = sum_s N_s^T Phi_b^T x_s, q the
-    // coarse solution, tb = S_bb B^T r.  Each is cleared by a kernel that
-    // runs after its last reader (tb by the first jump, the rest by the
-    // update), and once before the first iteration of a solve.
+    // Tile path, 6 launches.  Accumulators d_acc = [vc | cv | q | pq slots |
+    // tb | rz slots]: vc gets [S_bb^-1 x; .] and Phi_b N q, cv = sum_s N_s^T
+    // Phi_b^T x_s, q the coarse solution, tb = S_bb B^T r; the slots collect
+    // p.Fp = x^T S_bb^-1 x + cv^T S_Pi^-1 cv and r.z = (B^T r)^T S_bb (B^T r)
+    // from the tile kernels.  The update clears [tb | rz slots], the search
+    // direction update clears [vc .. pq slots]; both are cleared once before
+    // the first iteration of a solve.
     const int nl = h->n_lambda, npt = h->npart;
     const int* done = &h->d_st->done;
-    double* p_pq = h->d_part;
     double* p_rr = h->d_part + npt;
-    double* p_rz = h->d_part + 2 * npt;
     const double tol2 = h->pcg_tol * h->pcg_tol;
     const int64_t nPm = std::max(h->n_primal, 1);
     double* vc = h->d_acc;
     double* cv = vc + h->n_bptot;
     double* q = cv + nPm;
-    double* tb = q + nPm;
+    double* pq_slots = q + nPm;
+    double* tb = pq_slots + TCF_QSLOTS;
+    double* rz_slots = tb + h->n_btot;
     timed(h, TCF_KG_APPLY, st, [&] {
       launch_tiles<T>(0, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, h->d_brow,
-                      h->d_bsgn, h->dt, vc, h->d_cmap, done, st);
+                      h->d_bsgn, h->dt, vc, h->d_cmap, pq_slots, done, st);
     });
     if (h->n_primal > 0) {
       timed(h, TCF_KG_COARSE, st, [&] {
         launch_tiles<double>(3, h->tj_coarse, h->n_tcoarse, h->d_tC, cv, nullptr, nullptr, 1.0,
-                             q, nullptr, done, st);
+                             q, nullptr, pq_slots, done, st);
       });
       timed(h, TCF_KG_PHI, st, [&] {
         launch_tiles<T>(1, h->tj_phi, h->n_tphi, (const T*)h->d_tA, q, h->d_prank, nullptr,
-                        1.0, vc, nullptr, done, st);
+                        1.0, vc, nullptr, nullptr, done, st);
       });
     }
-    launch_jump(nl, h->d_posp_bp, h->d_posm_bp, vc, h->dt, h->d_Fp, h->d_p, p_pq, done, st, tb,
-                h->n_btot);
-    launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st,
-                      vc, h->n_bptot + 2 * nPm);
+    launch_pcg_update_t(nl, h->d_posp_bp, h->d_posm_bp, vc, h->dt, pq_slots, h->d_st, par,
+                        h->d_lam, h->d_r, h->d_p, p_rr, tb, h->n_btot + TCF_QSLOTS, st);
     timed(h, TCF_KG_PRECOND, st, [&] {
       launch_tiles<T>(2, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, h->d_brow, h->d_bsgn,
-                      1.0, tb, nullptr, done, st);
+                      1.0, tb, nullptr, rz_slots, done, st);
     });
-    launch_jump_check(nl, h->d_posp, h->d_posm, tb, h->d_z, h->d_r, p_rz, p_rr, npt, h->d_st,
-                      tol2, st);
-    launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
+    launch_pcg_pupdate_t(nl, h->d_posp, h->d_posm, tb, rz_slots, p_rr, npt, h->d_st, par, tol2,
+                         h->d_p, vc, h->n_bptot + 2 * nPm + TCF_QSLOTS, st);
     return;
   }
   const int nl = h->n_lambda, npt = h->npart;

@@ -7,6 +7,7 @@
 
 #define TCF_MAXP 8
 #define TCF_NB 32  // factorisation panel width; all block sizes are padded to it
+#define TCF_QSLOTS 1024  // slots of a tile-accumulated quadratic form (atomic spread)
 
 namespace tcf {
 

@@ -58,18 +58,13 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
                      int nrhs, int max_ni, const T* Q, const double* f, double* ygg, int64_t ldv,
                      hipStream_t st);
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
-                 const double* dotw, double* partial, const int* done, hipStream_t st,
-                 double* zero = nullptr, int64_t nzero = 0);
-void launch_jump_check(int n, const int* pp, const int* pm, const double* w, double* z,
-                       const double* r, double* part_rz, const double* part_rr, int npart,
-                       PcgScalars* stt, double tol2, hipStream_t st);
+                 const double* dotw, double* partial, const int* done, hipStream_t st);
 void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
                      hipStream_t st);
 void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, const double* prz,
                       int npart, PcgScalars* stt, hipStream_t st);
 void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
-                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st,
-                       double* zero = nullptr, int64_t nzero = 0);
+                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st);
 void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
                       hipStream_t st);
 void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
@@ -120,7 +115,15 @@ template <class T>
 // (plain gather), 3 coarse (direct inputs)
 void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, const double* xv,
                   const int* gidx, const signed char* gsgn, double scale, double* y,
-                  const int* ymap, const int* done, hipStream_t st);
+                  const int* ymap, double* qslot, const int* done, hipStream_t st);
+void launch_pcg_update_t(int n, const int* pp, const int* pm, const double* w, double dt,
+                         const double* pq_slots, PcgScalars* stt, int par, double* lam, double* r,
+                         const double* p, double* part_rr, double* zero, int64_t nzero,
+                         hipStream_t st);
+void launch_pcg_pupdate_t(int n, const int* pp, const int* pm, const double* tb,
+                          const double* rz_slots, const double* part_rr, int npart,
+                          PcgScalars* stt, int par, double tol2, double* p, double* zero,
+                          int64_t nzero, hipStream_t st);
 // Timing events for the next launch (of a timed kernel) issued by this thread.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();

@@ -934,16 +934,14 @@ __device__ inline double block_sum256(double v, double* sh) {
   return r;  // valid in thread 0
 }
 
-// y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i];
-// also clears zero[0 .. nzero) (an accumulator not in use at this point)
+// y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i]
 __global__ void __launch_bounds__(256) k_jump(int n, const int* pos_p, const int* pos_m,
                                               const double* w, double scale, double* y,
                                               const double* dotw, double* partial,
-                                              const int* done, double* zero, int64_t nzero) {
+                                              const int* done) {
   if (done && *done) return;
   __shared__ double sh[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
   double d = 0.0;
   if (i < n) {
     const double v = scale * (w[pos_p[i]] - w[pos_m[i]]);
@@ -1009,13 +1007,11 @@ __global__ void __launch_bounds__(256) k_pcg_init2(int n, const double* z, doubl
   }
 }
 
-// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r;
-// also clears zero[0 .. nzero) (accumulators consumed earlier in the iteration)
+// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r
 __global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq, int npart,
                                                     PcgScalars* st, int par, double* lam,
                                                     double* r, const double* p, const double* Fp,
-                                                    double* part_rr, double* zero,
-                                                    int64_t nzero) {
+                                                    double* part_rr) {
   if (st->done) return;
   __shared__ double sh[1];
   __shared__ double sh4[4];
@@ -1027,7 +1023,6 @@ __global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq
     ri = r[i];
     li = lam[i];
   }
-  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
   const double pq = sum_partials(part_pq, npart, sh);
   const double alpha = st->rz[par] / pq;
   double v = 0.0;
@@ -1041,36 +1036,95 @@ __global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq
   if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
 }
 
-// z = jump(w); partial[block] = z.r.  Block 0 also sums the ||r||^2 partials
-// and records ||r||^2, the iteration count and the convergence flag.  Other
-// blocks may see the flag set by block 0 and stop early: their z and r.z
-// are then never used (a converged iteration leaves lambda as it is).
-__global__ void __launch_bounds__(256) k_jump_check(int n, const int* pos_p, const int* pos_m,
-                                                    const double* w, double* z, const double* r,
-                                                    double* part_rz, const double* part_rr,
-                                                    int npart, PcgScalars* st, double tol2) {
+// Sum of the TCF_QSLOTS quadratic-form slots (256-thread blocks), the same
+// fixed order in every block.
+__device__ inline double sum_slots(const double* slots, double* sh) {
+  __shared__ double s4[4];
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < TCF_QSLOTS / 256; ++k) v += slots[k * 256 + threadIdx.x];
+  v = block_sum256(v, s4);
+  if (threadIdx.x == 0) sh[0] = v;
+  __syncthreads();
+  return sh[0];
+}
+
+// Tile-path update.  p.Fp comes from the quadratic-form slots of the F apply
+// (x^T S_bb^-1 x + cv^T S_Pi^-1 cv, x = Bhat^T p), Fp = dt (w[pp] - w[pm])
+// is formed on the fly from the accumulated w; alpha = rz[par] / p.Fp;
+// lambda += alpha p; r -= alpha Fp; partial[block] = r.r.  Also clears
+// zero[0 .. nzero) (the preconditioner accumulator and its slots).
+__global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, const int* pos_m,
+                                                      const double* w, double dt,
+                                                      const double* pq_slots, PcgScalars* st,
+                                                      int par, double* lam, double* r,
+                                                      const double* p, double* part_rr,
+                                                      double* zero, int64_t nzero) {
   if (st->done) return;
-  __shared__ double sh[4];
+  __shared__ double sh[1];
+  __shared__ double sh4[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = 0, b = 0;
+  double pi = 0.0, ri = 0.0, li = 0.0;
+  if (i < n) {
+    a = pos_p[i];
+    b = pos_m[i];
+    pi = p[i];
+    ri = r[i];
+    li = lam[i];
+  }
+  const double pq = sum_slots(pq_slots, sh);
+  const double alpha = st->rz[par] / pq;
+  double v = 0.0;
+  if (i < n) {
+    const double fi = dt * (w[a] - w[b]);
+    lam[i] = li + alpha * pi;
+    ri -= alpha * fi;
+    r[i] = ri;
+    v = ri * ri;
+  }
+  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
+  const double s = block_sum256(v, sh4);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// Tile-path search direction.  r.z comes from the preconditioner's
+// quadratic-form slots, z = tb[pp] - tb[pm] is formed on the fly; beta =
+// (r.z) / rz[par]; p = z + beta p.  Block 0 records rz[par ^ 1], sums the
+// ||r||^2 partials and sets the iteration count and convergence flag (other
+// blocks may then stop early: p is not used after convergence).  Also
+// clears zero[0 .. nzero) (the F-apply accumulators and their slots).
+__global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, const int* pos_m,
+                                                       const double* tb, const double* rz_slots,
+                                                       const double* part_rr, int npart,
+                                                       PcgScalars* st, int par, double tol2,
+                                                       double* p, double* zero, int64_t nzero) {
+  if (st->done) return;
+  __shared__ double sh[1];
   __shared__ double sh1[1];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double d = 0.0;
+  int a = 0, b = 0;
+  double pi = 0.0;
   if (i < n) {
-    const double v = w[pos_p[i]] - w[pos_m[i]];
-    z[i] = v;
-    d = v * r[i];
+    a = pos_p[i];
+    b = pos_m[i];
+    pi = p[i];
   }
-  const double s = block_sum256(d, sh);
-  if (threadIdx.x == 0) part_rz[blockIdx.x] = s;
+  const double rz_new = sum_slots(rz_slots, sh);
+  const double beta = rz_new / st->rz[par];
+  if (i < n) p[i] = (tb[a] - tb[b]) + beta * pi;
+  for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
   if (blockIdx.x == 0) {
-    __syncthreads();
     const double rr = sum_partials(part_rr, npart, sh1);
     if (threadIdx.x == 0) {
+      st->rz[par ^ 1] = rz_new;
       st->rr = rr;
       st->iters += 1;
       if (rr <= tol2 * st->dd) st->done = 1;
     }
   }
 }
+
 
 __global__ void __launch_bounds__(256) k_pcg_check(const double* part_rr, int npart,
                                                    PcgScalars* st, double tol2) {
@@ -1284,17 +1338,24 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
 }
 
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
-                 const double* dotw, double* partial, const int* done, hipStream_t st,
-                 double* zero, int64_t nzero) {
+                 const double* dotw, double* partial, const int* done, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_jump, TCF_GRID(n, 256), dim3(256), 0, st, n, pp, pm, w, scale, y, dotw,
-                     partial, done, zero, nzero);
+                     partial, done);
 }
-void launch_jump_check(int n, const int* pp, const int* pm, const double* w, double* z,
-                       const double* r, double* part_rz, const double* part_rr, int npart,
-                       PcgScalars* stt, double tol2, hipStream_t st) {
-  hipLaunchKernelGGL(k_jump_check, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, w, z, r,
-                     part_rz, part_rr, npart, stt, tol2);
+void launch_pcg_update_t(int n, const int* pp, const int* pm, const double* w, double dt,
+                         const double* pq_slots, PcgScalars* stt, int par, double* lam, double* r,
+                         const double* p, double* part_rr, double* zero, int64_t nzero,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_update_t, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, w, dt,
+                     pq_slots, stt, par, lam, r, p, part_rr, zero, nzero);
+}
+void launch_pcg_pupdate_t(int n, const int* pp, const int* pm, const double* tb,
+                          const double* rz_slots, const double* part_rr, int npart,
+                          PcgScalars* stt, int par, double tol2, double* p, double* zero,
+                          int64_t nzero, hipStream_t st) {
+  hipLaunchKernelGGL(k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, tb,
+                     rz_slots, part_rr, npart, stt, par, tol2, p, zero, nzero);
 }
 void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
                      hipStream_t st) {
@@ -1306,10 +1367,9 @@ void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, cons
                      npart, stt);
 }
 void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
-                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st,
-                       double* zero, int64_t nzero) {
+                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st) {
   hipLaunchKernelGGL(k_pcg_update, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, ppq, npart, stt,
-                     par, lam, r, p, Fp, prr, zero, nzero);
+                     par, lam, r, p, Fp, prr);
 }
 void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
                       hipStream_t st) {
@@ -1594,7 +1654,8 @@ template <class T, int Group>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
                                                const double* xv, const int* gidx,
                                                const signed char* gsgn, double scale,
-                                               double* y, const int* ymap, const int* done) {
+                                               double* y, const int* ymap, double* qslot,
+                                               const int* done) {
   constexpr int XM = Group == 3 ? 0 : (Group == 1 ? 2 : 1);
   typedef typename TileVec<T>::v VT;
   constexpr int V = TileVec<T>::n;   // rows per chunk
@@ -1611,14 +1672,14 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   const double* xr = xs;
   const double* xc = xs + 64;
   const int t = threadIdx.x;
-  const bool doN = jb.flags & 1, doT = jb.flags & 2;
+  const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = jb.flags & 16;
   const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
   // inputs, step 1: gather indices (threads 0..63 the row side, 64..127 the
   // column side).  Issued before the matrix loads: memory counters retire in
   // order, so an index load issued after them would wait for the whole tile.
   const bool side_r = t < 64;
   const int tt = side_r ? t : t - 64;
-  const bool xon = t < 128 && (side_r ? (doT && tt < jb.nr) : (doN && tt < jb.nc));
+  const bool xon = t < 128 && (side_r ? ((doT || qf) && tt < jb.nr) : (doN && tt < jb.nc));
   // lanes without an input read entry 0 (which every table has): no branch
   // around the loads, whose results are only used after the matrix loads
   const int xo = xon ? (side_r ? jb.xr_off : jb.xc_off) + tt : 0;
@@ -1689,9 +1750,13 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
       atomicAdd(y + yi, sum);
     }
   }
-  if (doN && t < 64) {
+  if (doN && t < 64) {  // wave 0
     const double sum = (Np[0][t] + Np[1][t]) + (Np[2][t] + Np[3][t]);
     if (t < jb.nr) atomicAdd(y + ((jb.flags & 8) ? ymap[jb.yr_off + t] : jb.yr_off + t), sum);
+    if (qf) {  // this tile's share of x^T A x (rows past nr carry zeros)
+      const double v = wave_sum(xr[t] * sum);
+      if (t == 0) atomicAdd(qslot + (blockIdx.x & (TCF_QSLOTS - 1)), (jb.flags & 32) ? 2.0 * v : v);
+    }
   }
 }
 
@@ -1710,24 +1775,24 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
 template <class T>
 void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, const double* xv,
                   const int* gidx, const signed char* gsgn, double scale, double* y,
-                  const int* ymap, const int* done, hipStream_t st) {
+                  const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
   switch (group) {
     case 0:
       TCF_TIMED_LAUNCH((k_tiles<T, 0>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, done);
+                       scale, y, ymap, qslot, done);
       break;
     case 1:
       TCF_TIMED_LAUNCH((k_tiles<T, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, done);
+                       scale, y, ymap, qslot, done);
       break;
     case 2:
       TCF_TIMED_LAUNCH((k_tiles<T, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, done);
+                       scale, y, ymap, qslot, done);
       break;
     default:
       TCF_TIMED_LAUNCH((k_tiles<T, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, done);
+                       scale, y, ymap, qslot, done);
       break;
   }
 }
@@ -1752,8 +1817,8 @@ template void launch_pack_tiles<float, float>(const PackJob*, int, const float*,
                                               hipStream_t);
 template void launch_tiles<double>(int, const TileJob*, int, const double*, const double*,
                                    const int*, const signed char*, double, double*, const int*,
-                                   const int*, hipStream_t);
+                                   double*, const int*, hipStream_t);
 template void launch_tiles<float>(int, const TileJob*, int, const float*, const double*,
                                   const int*, const signed char*, double, double*, const int*,
-                                  const int*, hipStream_t);
+                                  double*, const int*, hipStream_t);
 }  // namespace tcf
