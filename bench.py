@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="uneven",
-                    choices=["uneven", "plain", "mixed", "largest", "serving"])
+                    choices=["uneven", "plain", "mixed", "largest", "multirhs", "serving"])
+    ap.add_argument("--rhs-batch", type=int, default=0,
+                    help="excitations per batched PCG (0: automatic, up to 4)")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--rate-x", type=float, default=2.0,
                     help="serving: arrival rate as a multiple of the solo FP64 capacity")
@@ -81,6 +83,10 @@ def make_problem(name, n_steps):
                            name="cube8_p2_n4_fp64")
     if name == "mixed":
         return W.floating_mixed(n_steps=n_steps)
+    if name == "multirhs":
+        # the 256-patch checkerboard with its 32 excitations at n = 4 (the
+        # full n = 12 case needs a dense coarse inverse beyond one GPU)
+        return W.largest_multirhs(n=4, n_steps=n_steps)
     return W.largest_multirhs(n_steps=n_steps)
 
 
@@ -217,7 +223,8 @@ def main():
     n_steps = args.warmup + args.steps + args.profile_steps
     prob = make_problem(args.workload, max(n_steps, args.check_steps))
     prec = args.precision or prob.precision
-    p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1)
+    p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
+                    rhs_batch=args.rhs_batch)
     counts = p.counts()
     t0 = time.perf_counter()
     p.tcf_setup()
@@ -277,7 +284,7 @@ def main():
         check_name = small.name
         print(f"[bench] oracle check on {small.name}", file=sys.stderr, flush=True)
         ref = osolve.run(small)
-        q = tcf.Problem(small, precision=prec)
+        q = tcf.Problem(small, precision=prec, rhs_batch=args.rhs_batch)
         q.tcf_setup()
         rel_err = 0.0
         for l in range(args.check_steps):
@@ -313,7 +320,8 @@ def main():
                    "dt": prob.dt, "pcg_rtol": prob.pcg_rtol, "precision": prec,
                    "n_edges": counts["n_edges"], "gauged_dofs": counts["n_kept"],
                    "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"],
-                   "graphs": not args.no_graph},
+                   "graphs": not args.no_graph, "rhs_batch": args.rhs_batch or "auto"},
+        "rhs_steps_per_s": args.steps * prob.n_rhs / wall,
         "pcg_applies_per_s": applies / wall,
         "pcg_iters_per_step": applies / args.steps,
         "p50_step_ms": float(np.percentile(ms, 50)),

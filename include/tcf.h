@@ -89,7 +89,7 @@ typedef struct tcf_problem_desc {
 } tcf_problem_desc;
 
 typedef struct tcf_options {
-  int32_t precision;        /* TCF_FP64 or TCF_FP32_IR                        */
+  int32_t precision;        /* TCF_FP64, TCF_FP32_IR or TCF_FP32_FULL_IR      */
   double pcg_rtol;          /* stop when ||r||_2 <= pcg_rtol * ||d||_2        */
   int32_t pcg_maxit;        /* <= 0: max(1000, n_lambda)                      */
   double ir_rtol;           /* FP32 paths: refine (>= 1 correction) until the  */
@@ -99,9 +99,14 @@ typedef struct tcf_options {
                             /* <= 0: 10                                        */
   int32_t check_every;      /* PCG iterations between host convergence reads  */
   int32_t use_graph;        /* 1: replay captured hipGraphs for PCG chunks    */
+  int32_t rhs_batch;        /* excitations solved together (one PCG over      */
+                            /* several columns, each operator tile read once  */
+                            /* per iteration for all of them): 1..4, <= 0:    */
+                            /* min(n_rhs, 4)                                  */
 } tcf_options;
 
-/* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1. */
+/* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
+ * rhs_batch 0 (automatic). */
 void tcf_default_options(tcf_options* opts);
 
 typedef struct tcf_problem tcf_problem;

@@ -171,6 +171,8 @@ struct tcf_problem {
   int64_t n_acc = 0;
   int *d_posp_bp = nullptr, *d_posm_bp = nullptr;
   bool use_tiles = true;
+  int rb = 1;  // excitations per PCG (columns of every PCG vector and accumulator)
+  bool bp_gaps = false;  // some patch has primal but no dual unknowns
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
   bool graph_failed = false;          // capture refused: stream launches instead
@@ -195,6 +197,9 @@ struct tcf_problem {
   int64_t prof_n[TCF_KG_COUNT] = {0};
   double prof_bytes[TCF_KG_COUNT] = {0};
   int cur_it = -1;  // PCG iteration of the launches being issued (-1: outside PCG)
+  int cur_sweep = 0;  // refinement sweep of the solve being issued (0: first solve)
+#define TCF_PRED_KINDS 8
+  int pred_iters[TCF_PRED_KINDS] = {0};  // iterations of the last solve of each sweep
   hipEvent_t ev_get() {
     if (ev_pool.empty()) {
       hipEvent_t e;
@@ -349,8 +354,9 @@ size_t tcf_problem::footprint(int prec) const {
   const size_t w = prec == TCF_FP64 ? 8 : 4;
   size_t b = (size_t)(A_elems + G_elems + S_elems + Q_elems) * w;
   b += (size_t)nPi_pad * nPi_pad * 8 * 2;
-  b += (size_t)n_rtot * n_rhs * 8 * 6 + (size_t)n_bptot * 16 + (size_t)n_btot * 16;
-  b += (size_t)n_lambda * 8 * 8 + (size_t)(tab_elems + ptab_elems) * 8;
+  b += (size_t)n_rtot * n_rhs * 8 * 6 + (size_t)n_rtot * rb * 8 * 3;
+  b += ((size_t)n_bptot * 16 + (size_t)n_btot * 16 + (size_t)n_lambda * 8 * 8) * rb;
+  b += (size_t)rb * (n_bptot + n_btot + 2 * TCF_QSLOTS) * 8 + (size_t)(tab_elems + ptab_elems) * 8;
   b += (size_t)n_rtot * 24 + (size_t)n_loctot * 4;
   return b;
 }
@@ -430,6 +436,7 @@ void tcf_default_options(tcf_options* o) {
   o->ir_maxit = 10;
   o->check_every = 8;
   o->use_graph = 1;
+  o->rhs_batch = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -474,6 +481,9 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   h->nu.assign(desc->nu, desc->nu + np);
   h->src.assign(desc->src_mask, desc->src_mask + np);
   h->n_rhs = desc->n_rhs;
+  // excitations per batched PCG (the tile path only)
+  h->rb = h->use_tiles ? std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 4) : 4)
+                       : 1;
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
   h->dt = desc->dt;
@@ -796,6 +806,11 @@ static int build_index_tables(tcf_problem* h) {
     }
   }
   h->nj_app = (int)app_g.size();
+  // a patch with primal but no dual unknowns has no column-dot job, so its
+  // entries of the b+p vectors (c = Phi_b^T x = 0) must be cleared first
+  h->bp_gaps = false;
+  for (int s = 0; s < np; ++s)
+    if (h->hp[s].n_b == 0 && h->hp[s].n_p > 0) h->bp_gaps = true;
   h->nj_pre = (int)pre.size();
   h->nj_phi = (int)phi.size();
   h->nj_ai = (int)ai.size();
@@ -1019,29 +1034,30 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   HIPCHK(hipMemsetAsync(h->d_a, 0, sizeof(double) * ldv * nrhs, st));
   HIPCHK(hipMemsetAsync(h->d_fM, 0, sizeof(double) * ldv * nrhs, st));
   HIPCHK(hipMemsetAsync(h->d_yggs, 0, sizeof(double) * ldv * nrhs, st));
-  RCCHK(h->alloc(&h->d_uc, h->n_bptot));
+  const int rb = h->rb;
+  RCCHK(h->alloc(&h->d_uc, (size_t)h->n_bptot * rb));
   RCCHK(h->alloc(&h->d_vc, h->n_bptot));
   RCCHK(h->alloc(&h->d_wb, h->n_btot));
   RCCHK(h->alloc(&h->d_tb, h->n_btot));
   const int nP = std::max(h->n_primal, 1);
-  RCCHK(h->alloc(&h->d_h, nP));
+  RCCHK(h->alloc(&h->d_h, (size_t)nP * rb));
   RCCHK(h->alloc(&h->d_q0, nP));
   RCCHK(h->alloc(&h->d_cv, nP));
   RCCHK(h->alloc(&h->d_q, nP));
   const int nl = std::max(h->n_lambda, 1);
-  RCCHK(h->alloc(&h->d_d, nl));
-  RCCHK(h->alloc(&h->d_lam, nl));
-  RCCHK(h->alloc(&h->d_r, nl));
-  RCCHK(h->alloc(&h->d_z, nl));
-  RCCHK(h->alloc(&h->d_p, nl));
-  RCCHK(h->alloc(&h->d_Fp, nl));
+  RCCHK(h->alloc(&h->d_d, (size_t)nl * rb));
+  RCCHK(h->alloc(&h->d_lam, (size_t)nl * rb));
+  RCCHK(h->alloc(&h->d_r, (size_t)nl * rb));
+  RCCHK(h->alloc(&h->d_z, (size_t)nl * rb));
+  RCCHK(h->alloc(&h->d_p, (size_t)nl * rb));
+  RCCHK(h->alloc(&h->d_Fp, (size_t)nl * rb));
   h->npart = (nl + 255) / 256;
-  RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4));
-  RCCHK(h->alloc(&h->d_st, 1));
+  RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4 * rb));
+  RCCHK(h->alloc(&h->d_st, (size_t)rb + 1));  // per column, plus the all-done flag
   RCCHK(h->alloc(&h->d_field, (size_t)h->g.n_edges()));
   {
     std::lock_guard<std::mutex> lk(g_capture_mu);
-    HIPCHK(hipHostMalloc((void**)&h->h_st, sizeof(PcgScalars), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->h_st, sizeof(PcgScalars) * (rb + 1), hipHostMallocDefault));
   }
   HIPCHK(hipMemsetAsync(h->d_lam, 0, sizeof(double) * nl, st));
 
@@ -1067,9 +1083,9 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   }
   h->d_jr = jr;
   // refinement work vectors and the kept-unknown -> local-copies map
-  RCCHK(h->alloc(&h->d_floc, (size_t)ldv));
-  RCCHK(h->alloc(&h->d_res, (size_t)ldv));
-  RCCHK(h->alloc(&h->d_delta, (size_t)ldv));
+  RCCHK(h->alloc(&h->d_floc, (size_t)ldv * rb));
+  RCCHK(h->alloc(&h->d_res, (size_t)ldv * rb));
+  RCCHK(h->alloc(&h->d_delta, (size_t)ldv * rb));
   {
     std::vector<std::vector<int>> copies;
     std::vector<int64_t> kept_ids;
@@ -1208,8 +1224,9 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int j = 0; j < h->hp[s].n_p; ++j)
       cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->plans[s].p_rank[j];
   RCCHK(h->upload(&h->d_cmap, cmap));
-  // [vc | cv | q | slots of p.Fp | tb | slots of r.z]
-  h->n_acc = h->n_bptot + 2 * std::max(nP, 1) + 2 * TCF_QSLOTS + h->n_btot;
+  // per column j of rb: [vc | cv] (stride n_bptot + n_Pi), then q, p.Fp
+  // slots, tb, r.z slots, each block rb columns wide
+  h->n_acc = (int64_t)h->rb * (h->n_bptot + 2 * std::max(nP, 1) + 2 * TCF_QSLOTS + h->n_btot);
   RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
   return TCF_OK;
 }
@@ -1283,6 +1300,7 @@ static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, 
 template <class T>
 static void apply_F(tcf_problem* h, const double* p, double* Fp, double* part, const int* done,
                     hipStream_t st) {
+  if (h->bp_gaps) launch_zero(h->n_bptot, h->d_vc, st);
   timed(h, TCF_KG_APPLY, st, [&] {
     launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, (const T*)h->d_G,
                       1, p, h->d_brow, h->d_bsgn, h->dt, h->d_vc, done, st);
@@ -1303,50 +1321,66 @@ static void apply_M(tcf_problem* h, const double* r, double* z, double* part, co
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
 }
 
+// Views into the tile path's accumulator block (see pcg_iteration).
+struct TileAcc {
+  double *vc, *q, *pq, *tb, *rz;
+  int lf, npm;              // column strides of [vc | cv] and of q
+  int64_t n_head, n_tail;   // [vc .. p.Fp slots] and [tb .. r.z slots] lengths
+};
+static TileAcc tile_acc(tcf_problem* h) {
+  TileAcc a;
+  const int R = h->rb;
+  a.npm = std::max(h->n_primal, 1);
+  a.lf = (int)h->n_bptot + a.npm;
+  a.vc = h->d_acc;
+  a.q = a.vc + (int64_t)a.lf * R;
+  a.pq = a.q + (int64_t)a.npm * R;
+  a.tb = a.pq + (int64_t)TCF_QSLOTS * R;
+  a.rz = a.tb + h->n_btot * R;
+  a.n_head = (int64_t)(a.lf + a.npm + TCF_QSLOTS) * R;
+  a.n_tail = (h->n_btot + TCF_QSLOTS) * R;
+  return a;
+}
+
 // One PCG iteration with the given parity (launch sequence only).
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
   if (h->use_tiles) {
-    // Tile path, 6 launches.  Accumulators d_acc = [vc | cv | q | pq slots |
-    // tb | rz slots]: vc gets [S_bb^-1 x; .] and Phi_b N q, cv = sum_s N_s^T
-    // Phi_b^T x_s, q the coarse solution, tb = S_bb B^T r; the slots collect
-    // p.Fp = x^T S_bb^-1 x + cv^T S_Pi^-1 cv and r.z = (B^T r)^T S_bb (B^T r)
-    // from the tile kernels.  The update clears [tb | rz slots], the search
-    // direction update clears [vc .. pq slots]; both are cleared once before
-    // the first iteration of a solve.
-    const int nl = h->n_lambda, npt = h->npart;
-    const int* done = &h->d_st->done;
-    double* p_rr = h->d_part + npt;
+    // Tile path, 6 launches, rb columns (excitations) at once.  Accumulators
+    // (each block rb columns wide): [vc | cv] per column (vc gets S_bb^-1 x
+    // and Phi_b N q, cv = sum_s N_s^T Phi_b^T x_s), q the coarse solution,
+    // slots of p.Fp = x^T S_bb^-1 x + cv^T S_Pi^-1 cv, tb = S_bb B^T r, slots
+    // of r.z = (B^T r)^T S_bb (B^T r).  The update clears [tb, r.z slots],
+    // the search-direction update clears [vc .. p.Fp slots]; all are cleared
+    // once before a solve.
+    const TileAcc a = tile_acc(h);
+    const int R = h->rb, nl = h->n_lambda, npt = h->npart;
+    PcgScalars* stv = h->d_st;
+    const int* alldone = &h->d_st[R].done;
+    double* p_rr = h->d_part;
     const double tol2 = h->pcg_tol * h->pcg_tol;
-    const int64_t nPm = std::max(h->n_primal, 1);
-    double* vc = h->d_acc;
-    double* cv = vc + h->n_bptot;
-    double* q = cv + nPm;
-    double* pq_slots = q + nPm;
-    double* tb = pq_slots + TCF_QSLOTS;
-    double* rz_slots = tb + h->n_btot;
     timed(h, TCF_KG_APPLY, st, [&] {
-      launch_tiles<T>(0, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, h->d_brow,
-                      h->d_bsgn, h->dt, vc, h->d_cmap, pq_slots, done, st);
+      launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, nl, h->d_brow,
+                      h->d_bsgn, h->dt, a.vc, a.lf, h->d_cmap, a.pq, alldone, st);
     });
     if (h->n_primal > 0) {
       timed(h, TCF_KG_COARSE, st, [&] {
-        launch_tiles<double>(3, h->tj_coarse, h->n_tcoarse, h->d_tC, cv, nullptr, nullptr, 1.0,
-                             q, nullptr, pq_slots, done, st);
+        launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, a.vc + h->n_bptot, a.lf,
+                             nullptr, nullptr, 1.0, a.q, a.npm, nullptr, a.pq, alldone, st);
       });
       timed(h, TCF_KG_PHI, st, [&] {
-        launch_tiles<T>(1, h->tj_phi, h->n_tphi, (const T*)h->d_tA, q, h->d_prank, nullptr,
-                        1.0, vc, nullptr, nullptr, done, st);
+        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.npm, h->d_prank,
+                        nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, alldone, st);
       });
     }
-    launch_pcg_update_t(nl, h->d_posp_bp, h->d_posm_bp, vc, h->dt, pq_slots, h->d_st, par,
-                        h->d_lam, h->d_r, h->d_p, p_rr, tb, h->n_btot + TCF_QSLOTS, st);
+    launch_pcg_update_t(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, a.pq, stv, par,
+                        h->d_lam, h->d_r, h->d_p, p_rr, npt, a.tb, a.n_tail, st);
     timed(h, TCF_KG_PRECOND, st, [&] {
-      launch_tiles<T>(2, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, h->d_brow, h->d_bsgn,
-                      1.0, tb, nullptr, rz_slots, done, st);
+      launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
+                      h->d_bsgn, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, alldone, st);
     });
-    launch_pcg_pupdate_t(nl, h->d_posp, h->d_posm, tb, rz_slots, p_rr, npt, h->d_st, par, tol2,
-                         h->d_p, vc, h->n_bptot + 2 * nPm + TCF_QSLOTS, st);
+    launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, a.rz, p_rr, npt, stv,
+                         par, tol2, h->d_p, a.vc, a.n_head, st);
     return;
   }
   const int nl = h->n_lambda, npt = h->npart;
@@ -1392,28 +1426,58 @@ static int build_pcg_graph(tcf_problem* h) {
   return TCF_OK;
 }
 
+// PCG on the multipliers for the rb columns of d (columns past the active
+// excitations hold zeros and are converged from the start).  Per column:
+// iteration count and whether it converged within maxit.
 template <class T>
-static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bool& conv) {
-  const int nl = h->n_lambda;
-  iters = 0;
-  rel = 0.0;
-  conv = true;
+static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
+  const int nl = h->n_lambda, R = h->rb;
+  for (int j = 0; j < R; ++j) {
+    iters[j] = 0;
+    conv[j] = true;
+  }
+  h->last_rel = 0.0;
   if (nl == 0) return TCF_OK;
   const int npt = h->npart;
-  double* p_rz = h->d_part + 2 * npt;
-  double* p_dd = h->d_part + 3 * npt;
-  launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
-  apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
-  launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
-  if (h->use_tiles) launch_zero(h->n_acc, h->d_acc, st);
+  if (h->use_tiles) {
+    const TileAcc a = tile_acc(h);
+    double* p_dd = h->d_part + (int64_t)npt * R;
+    launch_zero(h->n_acc, h->d_acc, st);
+    launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
+    launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
+                    h->d_bsgn, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
+    launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, a.rz, p_dd, npt,
+                       h->d_st, h->d_p, st);
+  } else {
+    double* p_rz = h->d_part + 2 * npt;
+    double* p_dd = h->d_part + 3 * npt;
+    launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
+    apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
+    launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
+  }
+  // flag the host reads: the all-columns flag on the tile path
+  const int fl = h->use_tiles ? R : 0;
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
   if (h->opt.use_graph && !h->prof_on) RCCHK(build_pcg_graph<T>(h));
   const bool graph = h->opt.use_graph && !h->prof_on && h->pcg_graph;
   const int chunk = std::max(2, h->opt.check_every / 2 * 2);
+  // Host reads of the convergence flag stall the stream.  Solves of the
+  // same kind (same refinement sweep) take nearly the same number of
+  // iterations from step to step: the first read comes a few iterations
+  // before the previous count, later ones every min(chunk, 4) iterations.
+  const int kind = std::min(h->cur_sweep, TCF_PRED_KINDS - 1);
+  const int pred = h->pred_iters[kind];
+  int seg = pred > chunk + 6 ? (pred - 6) / 2 * 2 : chunk;
   int it = 0;
   bool finished = false;
+  auto max_iters = [&] {
+    int m = 0;
+    for (int j = 0; j < R; ++j) m = std::max(m, h->h_st[j].iters);
+    return m;
+  };
   while (it < maxit && !finished) {
-    const int it1 = std::min(maxit, it + chunk);
+    const int it1 = std::min(maxit, it + seg);
+    seg = std::min(chunk, 4);
     while (it < it1) {
       if (graph && it + 2 <= it1 && (it & 1) == 0) {
         HIPCHK(hipGraphLaunch(h->pcg_graph, st));
@@ -1425,32 +1489,45 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int& iters, double& rel, bo
       }
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, sizeof(PcgScalars) * (fl + 1), hipMemcpyDeviceToHost,
+                          st));
     HIPCHK(hipStreamSynchronize(st));
-    finished = h->h_st->done != 0;
-    if (h->prof_on) h->prof_flush(finished ? h->h_st->iters : INT32_MAX);
+    finished = h->h_st[fl].done != 0;
+    if (h->prof_on) h->prof_flush(finished ? max_iters() : INT32_MAX);
   }
   h->cur_it = -1;
-  iters = h->h_st->iters;
-  conv = finished;
-  rel = h->h_st->dd > 0 ? std::sqrt(h->h_st->rr / h->h_st->dd) : 0.0;
+  const int ncol = h->use_tiles ? R : 1;
+  double rel = 0.0;
+  for (int j = 0; j < ncol; ++j) {
+    iters[j] = h->h_st[j].iters;
+    conv[j] = h->h_st[j].done != 0;
+    if (h->h_st[j].dd > 0) rel = std::max(rel, std::sqrt(h->h_st[j].rr / h->h_st[j].dd));
+  }
+  if (finished) h->pred_iters[kind] = max_iters();
+  h->last_rel = rel;
   return TCF_OK;
 }
 
-// Dual-primal solve of W x = f for one excitation, the right-hand side
-// given per patch (kept order).  rhs == nullptr selects the time-step form
-// f = M a_k + dt g_k(t_{l+1}) jhat_k, whose source part was condensed at
-// setup; otherwise f = rhs (all patches condensed).  The solution is
-// written to x_out (kept order).  If base != nullptr, x_out is a correction
-// to base and the interface constraint is Bhat (base + x) = 0, i.e. the dual
-// right-hand side becomes d + Bhat base.
+// Dual-primal solve of W x = f, split around the (batched) PCG.  The
+// right-hand side is given per patch (kept order): rhs == nullptr selects
+// the time-step form f = M a_k + dt g_k(t_{l+1}) jhat_k of excitation k,
+// whose source part was condensed at setup; otherwise f = rhs (all patches
+// condensed).  If base != nullptr the solution is a correction to base and
+// the interface constraint is Bhat (base + x) = 0, i.e. the dual right-hand
+// side becomes d + Bhat base.  Column j of the PCG vectors carries it.
+//
+// solve_pre: [u; c0] = G^T g_b, h = sum N^T (g_p - c0), q0 = S_Pi^-1 h,
+// d = jump(u - Phi N q0) into column j.
 template <class T>
-static int solve_local(tcf_problem* h, int k, int l, const double* rhs, double* x_out,
-                       hipStream_t st, int& iters, bool& conv, const double* base = nullptr) {
+static void solve_pre(tcf_problem* h, int k, int l, const double* rhs, const double* base, int j,
+                      hipStream_t st) {
   const int64_t ldv = h->n_rtot;
   double* ygg = h->d_ygg + (int64_t)k * ldv;
   const T* G = (const T*)h->d_G;
   const T* Q = (const T*)h->d_Q;
+  double* uc = h->d_uc + (int64_t)j * h->n_bptot;
+  double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
+  double* dv = h->d_d + (int64_t)j * h->n_lambda;
   if (!rhs) {
     double* a = h->d_a + (int64_t)k * ldv;
     double* fM = h->d_fM + (int64_t)k * ldv;
@@ -1470,41 +1547,39 @@ static int solve_local(tcf_problem* h, int k, int l, const double* rhs, double* 
     launch_condense<T>(h->dP, h->d_all, h->d_all_cprefix, h->np_tot, h->nt_all_c, 1, h->max_ni, Q,
                        rhs, ygg, ldv, st);
   }
-  // [u; c0] = G^T g_b ; h = sum N^T (g_p - c0) ; q0 = S_Pi^-1 h ; d = jump(u - Phi N q0)
+  if (h->bp_gaps) launch_zero(h->n_bptot, uc, st);
   launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
-                    nullptr, 1.0, h->d_uc, nullptr, st);
+                    nullptr, 1.0, uc, nullptr, st);
   if (h->n_primal > 0) {
-    launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, h->d_uc,
-                         -1.0, nullptr, h->d_h, nullptr, st);
+    launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, uc, -1.0,
+                         nullptr, hv, nullptr, st);
     launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv,
-                           0, h->d_h, nullptr, nullptr, 1.0, h->d_q0, nullptr, st);
+                           0, hv, nullptr, nullptr, 1.0, h->d_q0, nullptr, st);
   }
-  phi_apply<T>(h, h->d_uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
-  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, h->d_d, nullptr, nullptr,
-              nullptr, st);
-  auto trace_vec = [&](const char* what, const double* v, int n) {
-    std::vector<double> hv(n);
-    (void)hipMemcpyAsync(hv.data(), v, sizeof(double) * n, hipMemcpyDeviceToHost, st);
-    (void)hipStreamSynchronize(st);
-    double s2 = 0;
-    for (double x : hv) s2 += x * x;
-    std::fprintf(stderr, "[tcf]   %s %.3e\n", what, std::sqrt(s2));
-  };
-  if (base && h->trace) trace_vec("|d(r)|", h->d_d, h->n_lambda);
-  if (base) launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, h->d_d, st);
-  if (base && h->trace) trace_vec("|d(r)+Bhat a|", h->d_d, h->n_lambda);
-  double rel = 0.0;
-  RCCHK(pcg_solve<T>(h, st, iters, rel, conv));
-  h->last_rel = rel;
-  // recovery: p = S_Pi^-1 (h + sum N^T Phi^T x), x = Bhat^T lambda
+  phi_apply<T>(h, uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
+  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, dv, nullptr, nullptr, nullptr,
+              st);
+  if (base) launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, dv, st);
+}
+
+// solve_post (column j, lambda from the PCG): p = S_Pi^-1 (h + sum N^T Phi^T
+// x) with x = Bhat^T lambda; x_b = (u - v) - Phi N p; x_p = N p; x_i from
+// Q^T [y; -x_b; -x_p].  Writes the solution to x_out (kept order).
+template <class T>
+static void solve_post(tcf_problem* h, int k, int j, double* x_out, hipStream_t st) {
+  const int64_t ldv = h->n_rtot;
+  double* ygg = h->d_ygg + (int64_t)k * ldv;
+  const T* G = (const T*)h->d_G;
+  const T* Q = (const T*)h->d_Q;
+  const double* uc = h->d_uc + (int64_t)j * h->n_bptot;
+  const double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
+  const double* lam = h->d_lam + (int64_t)j * h->n_lambda;
+  if (h->n_lambda == 0 || h->bp_gaps) launch_zero(std::max<int64_t>(h->n_bptot, 1), h->d_vc, st);
   if (h->n_lambda > 0)
-    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, h->d_lam,
+    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, lam,
                       h->d_brow, h->d_bsgn, h->dt, h->d_vc, nullptr, st);
-  else
-    HIPCHK(hipMemsetAsync(h->d_vc, 0, sizeof(double) * std::max<int64_t>(h->n_bptot, 1), st));
-  coarse_solve(h, h->d_vc, h->d_h, h->d_q, nullptr, st);
-  // x_b = (u - v) - Phi N p ;  x_p = N p
-  launch_sub_gather((int)h->n_btot, h->d_b2bp, h->d_uc, h->d_b2bp, h->d_vc, h->d_tb, st);
+  coarse_solve(h, h->d_vc, hv, h->d_q, nullptr, st);
+  launch_sub_gather((int)h->n_btot, h->d_b2bp, uc, h->d_b2bp, h->d_vc, h->d_tb, st);
   launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, x_out, nullptr, st);
   if (h->n_primal > 0) {
     if (h->nj_phi > 0)
@@ -1512,23 +1587,25 @@ static int solve_local(tcf_problem* h, int k, int l, const double* rhs, double* 
                          h->d_prank, x_out, h->a_boff_ab, -1.0, x_out, 0, nullptr, st);
     launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, x_out, nullptr, st);
   }
-  // x_i = L_ii^-T (y - L_bi^T x_b - L_pi^T x_p) = Q^T [y; -x_b; -x_p]
   launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr, st);
   timed(h, TCF_KG_RECOVER, st, [&] {
     launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
                        nullptr, h->a_boff_ai, 1.0, x_out, 1, nullptr, st);
   });
-  if (h->trace && h->n_lambda > 0) {
-    HIPCHK(hipMemsetAsync(h->d_Fp, 0, sizeof(double) * h->n_lambda, st));
-    launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, x_out, h->dt, h->d_Fp, st);
-    trace_vec("|Bhat x|", h->d_Fp, h->n_lambda);
-    if (base) {
-      launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, h->d_Fp, st);
-      trace_vec("|Bhat (base + x)|", h->d_Fp, h->n_lambda);
-    }
-  }
-  HIPCHK(hipGetLastError());
-  return TCF_OK;
+}
+
+// Relative interface jump ||Bhat x|| (diagnostics with TCF_TRACE=1; syncs).
+static double jump_norm(tcf_problem* h, const double* x, hipStream_t st) {
+  if (h->n_lambda == 0) return 0.0;
+  std::vector<double> jv(h->n_lambda);
+  launch_zero(h->n_lambda, h->d_Fp, st);
+  launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, x, 1.0, h->d_Fp, st);
+  (void)hipMemcpyAsync(jv.data(), h->d_Fp, sizeof(double) * h->n_lambda, hipMemcpyDeviceToHost,
+                       st);
+  (void)hipStreamSynchronize(st);
+  double s2 = 0.0;
+  for (double v : jv) s2 += v * v;
+  return std::sqrt(s2);
 }
 
 // Squared global norm of a kept-ordered vector into h_nrm[slot] (syncs):
@@ -1541,113 +1618,169 @@ static int asm_norm2(tcf_problem* h, const double* x, int first_copy, int slot, 
   return TCF_OK;
 }
 
-// One implicit Euler step for excitation k.  FP64: one dual-primal solve.
-// FP32 operators: refinement a <- a + solve(f - W a) with the residual of
-// the FP64 operator (matrix-free per patch, double-double row sums),
-// assembled and split evenly over interface copies, the correction also
-// closing the interface jump left in a.  At least one correction; stop when
-// the estimated remaining error (last correction times the observed
-// contraction, relative to the field) is <= ir_rtol.  The final assembled
-// residual ||f - W a|| / ||f|| is reported in the stats.
+// One implicit Euler step for excitations k0 .. k0 + nc - 1 (nc <= rb), one
+// PCG column each.  FP64: one dual-primal solve.  FP32 operators:
+// refinement a <- a + solve(f - W a) with the residual of the FP64 operator
+// (matrix-free per patch, double-double row sums), assembled and split
+// evenly over interface copies, the correction also closing the interface
+// jump left in a.  At least one correction; an excitation stops when its
+// estimated remaining error (last correction times the observed
+// contraction, relative to the field) is <= ir_rtol, and then sits out
+// (zero right-hand side) while the others continue.  The final assembled
+// residual ||f - W a|| / ||f|| is reported in the stats (largest over the
+// batch).  Per excitation: PCG iterations summed over its solves, sweeps.
 template <class T>
-static int step_one(tcf_problem* h, int k, int l, hipStream_t st, int& iters, int& sweeps,
-                    bool& conv) {
+static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int* iters,
+                      int* sweeps, bool* conv) {
   const int64_t ldv = h->n_rtot;
-  double* a = h->d_a + (int64_t)k * ldv;
-  iters = 0;
-  sweeps = 0;
-  conv = true;
-  if (h->precision == TCF_FP64 && !h->fp64_ir) {
-    RCCHK(solve_local<T>(h, k, l, nullptr, a, st, iters, conv));
-    return TCF_OK;
+  const int R = h->rb, nl = h->n_lambda;
+  std::vector<int> it(R);
+  std::vector<char> cv(R);
+  bool cvb[4];
+  for (int j = 0; j < nc; ++j) {
+    iters[j] = 0;
+    sweeps[j] = 0;
+    conv[j] = true;
   }
-  // f = M a^(l) + dt g jhat (local, FP64)
-  double* fM = h->d_fM + (int64_t)k * ldv;
-  const double gk = h->amp[(size_t)k * h->n_steps + l];
-  if (!h->cond_list.empty())
-    launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
-                  h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
-  HIPCHK(hipMemcpyAsync(h->d_floc, fM, sizeof(double) * ldv, hipMemcpyDeviceToDevice, st));
-  launch_axpby(ldv, h->dt * gk, h->d_jr + (int64_t)k * ldv, 1.0, h->d_floc, st);
-  RCCHK(asm_norm2(h, h->d_floc, 0, 0, st));
-  const double fn = std::sqrt(h->h_nrm[0]);
-  int it = 0;
-  bool c = true;
-  RCCHK(solve_local<T>(h, k, l, nullptr, a, st, it, c));
-  iters += it;
-  conv &= c;
-  sweeps = 1;
-  double rn = 0.0, dn = 0.0, an = 0.0, rel_prev = 0.0, est = 1.0;
-  for (;;) {
-    launch_residual(h->dP, h->d_all, h->d_all_rprefix, h->np_tot, h->nt_all_r, h->d_rloc,
-                    h->d_loc2r, h->d_tabs, h->dt, h->d_floc, a, h->d_res, st);
-    RCCHK(asm_norm2(h, h->d_res, 0, 1, st));
-    rn = std::sqrt(h->h_nrm[1]);
-    if (fn == 0.0 || rn == 0.0) break;
-    if (sweeps >= 2 && est <= h->opt.ir_rtol) break;
-    if (sweeps >= h->opt.ir_maxit) { conv = false; break; }
+  auto zero_idle = [&](const std::vector<char>& active) {
+    for (int j = 0; j < R; ++j)
+      if (j >= nc || !active[j]) launch_zero(nl, h->d_d + (int64_t)j * nl, st);
+  };
+  auto collect = [&](const std::vector<char>& active) {
+    for (int j = 0; j < nc; ++j)
+      if (active[j]) {
+        iters[j] += it[j];
+        conv[j] = conv[j] && cv[j];
+      }
+  };
+  auto run_pcg = [&]() -> int {
+    int itv[4];
+    RCCHK(pcg_solve<T>(h, st, itv, cvb));
+    for (int j = 0; j < R; ++j) {
+      it[j] = itv[j];
+      cv[j] = cvb[j];
+    }
+    return TCF_OK;
+  };
+  std::vector<char> all(R, 0);
+  for (int j = 0; j < nc; ++j) all[j] = 1;
+  // first solve: the time-step right-hand side of every excitation
+  h->cur_sweep = 0;
+  for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, l, nullptr, nullptr, j, st);
+  zero_idle(all);
+  RCCHK(run_pcg());
+  for (int j = 0; j < nc; ++j) solve_post<T>(h, k0 + j, j, h->d_a + (int64_t)(k0 + j) * ldv, st);
+  collect(all);
+  for (int j = 0; j < nc; ++j) sweeps[j] = 1;
+  if (h->precision == TCF_FP64 && !h->fp64_ir) return TCF_OK;
+
+  // refinement: f = M a^(l) + dt g jhat per excitation (local, FP64)
+  std::vector<double> fn(nc), rel_prev(nc, 0.0), est(nc, 1.0), rn(nc, 0.0);
+  for (int j = 0; j < nc; ++j) {
+    const int k = k0 + j;
+    double* a = h->d_a + (int64_t)k * ldv;
+    double* fM = h->d_fM + (int64_t)k * ldv;
+    double* floc = h->d_floc + (int64_t)j * ldv;
+    const double gk = h->amp[(size_t)k * h->n_steps + l];
+    // fM still holds M a^(l) from the first solve's condensation (conductor
+    // patches) and zeros elsewhere
+    (void)a;
+    HIPCHK(hipMemcpyAsync(floc, fM, sizeof(double) * ldv, hipMemcpyDeviceToDevice, st));
+    launch_axpby(ldv, h->dt * gk, h->d_jr + (int64_t)k * ldv, 1.0, floc, st);
+    RCCHK(asm_norm2(h, floc, 0, 0, st));
+    fn[j] = std::sqrt(h->h_nrm[0]);
+  }
+  std::vector<char> active(R, 0), settled(nc, 0);
+  for (int sweep = 1;; ++sweep) {
+    int n_active = 0;
+    for (int j = 0; j < nc; ++j) {
+      active[j] = 0;
+      if (settled[j]) continue;
+      const int k = k0 + j;
+      double* a = h->d_a + (int64_t)k * ldv;
+      double* res = h->d_res + (int64_t)j * ldv;
+      launch_residual(h->dP, h->d_all, h->d_all_rprefix, h->np_tot, h->nt_all_r, h->d_rloc,
+                      h->d_loc2r, h->d_tabs, h->dt, h->d_floc + (int64_t)j * ldv, a, res, st);
+      RCCHK(asm_norm2(h, res, 0, 1, st));
+      rn[j] = std::sqrt(h->h_nrm[1]);
+      bool act = !(fn[j] == 0.0 || rn[j] == 0.0) && !(sweeps[j] >= 2 && est[j] <= h->opt.ir_rtol);
+      if (act && sweeps[j] >= h->opt.ir_maxit) {
+        conv[j] = false;
+        act = false;
+      }
+      active[j] = act ? 1 : 0;
+      settled[j] = act ? 0 : 1;
+      n_active += act ? 1 : 0;
+    }
+    if (n_active == 0) break;
     // the correction sees the assembled residual split evenly over copies, so
     // its dual right-hand side is as small as the true residual and the PCG
     // tolerance also resolves the interface jump carried over from a
-    launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, h->d_res, st);
-    RCCHK(solve_local<T>(h, k, l, h->d_res, h->d_delta, st, it, c, a));
-    iters += it;
-    conv &= c;
-    launch_axpby(ldv, 1.0, h->d_delta, 1.0, a, st);
-    RCCHK(asm_norm2(h, h->d_delta, 1, 2, st));
-    RCCHK(asm_norm2(h, a, 1, 3, st));
-    dn = std::sqrt(h->h_nrm[2]);
-    an = std::sqrt(h->h_nrm[3]);
-    {
+    h->cur_sweep = sweep;
+    for (int j = 0; j < nc; ++j) {
+      if (!active[j]) continue;
+      double* res = h->d_res + (int64_t)j * ldv;
+      launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, res, st);
+      solve_pre<T>(h, k0 + j, l, res, h->d_a + (int64_t)(k0 + j) * ldv, j, st);
+    }
+    zero_idle(active);
+    RCCHK(run_pcg());
+    for (int j = 0; j < nc; ++j) {
+      if (!active[j]) continue;
+      const int k = k0 + j;
+      double* a = h->d_a + (int64_t)k * ldv;
+      double* delta = h->d_delta + (int64_t)j * ldv;
+      solve_post<T>(h, k, j, delta, st);
+      launch_axpby(ldv, 1.0, delta, 1.0, a, st);
+      RCCHK(asm_norm2(h, delta, 1, 2, st));
+      RCCHK(asm_norm2(h, a, 1, 3, st));
+      const double dn = std::sqrt(h->h_nrm[2]), an = std::sqrt(h->h_nrm[3]);
       // error left after this correction ~ its size times the contraction
       // of one inexact solve: the first correction's relative size
       // estimates that contraction, later ones use the observed ratio
       const double rel = an > 0 ? dn / an : 0.0;
-      const double ratio = rel_prev > 0 ? rel / rel_prev : rel;
-      est = rel * std::min(1.0, ratio);
-      rel_prev = rel;
+      const double ratio = rel_prev[j] > 0 ? rel / rel_prev[j] : rel;
+      est[j] = rel * std::min(1.0, ratio);
+      rel_prev[j] = rel;
+      ++sweeps[j];
+      if (h->trace)
+        std::fprintf(stderr,
+                     "[tcf] step %d rhs %d sweep %d: |r|/|f| %.3e  |da|/|a| %.3e  |Ba|/|a| %.3e  "
+                     "pcg %d%s\n",
+                     l, k, sweeps[j] - 1, rn[j] / fn[j], dn / std::max(an, 1e-300),
+                     jump_norm(h, a, st) / std::max(an, 1e-300), it[j],
+                     cv[j] ? "" : " (not converged)");
     }
-    if (h->trace) {
-      double jn = 0.0;
-      if (h->n_lambda > 0) {
-        std::vector<double> jv(h->n_lambda);
-        HIPCHK(hipMemsetAsync(h->d_Fp, 0, sizeof(double) * h->n_lambda, st));
-        launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, a, 1.0, h->d_Fp, st);
-        HIPCHK(hipMemcpyAsync(jv.data(), h->d_Fp, sizeof(double) * h->n_lambda,
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        for (double v : jv) jn += v * v;
-      }
-      std::fprintf(stderr,
-                   "[tcf] step %d rhs %d sweep %d: |r|/|f| %.3e  |da|/|a| %.3e  |Ba|/|a| %.3e  pcg %d%s\n",
-                   l, k, sweeps, rn / fn, dn / std::max(an, 1e-300), std::sqrt(jn) / std::max(an, 1e-300),
-                   it, c ? "" : " (not converged)");
-    }
-    ++sweeps;
+    collect(active);
   }
-  h->last_ir_res = fn > 0 ? rn / fn : 0.0;
+  double worst = 0.0;
+  for (int j = 0; j < nc; ++j) worst = std::max(worst, fn[j] > 0 ? rn[j] / fn[j] : 0.0);
+  h->last_ir_res = worst;
   return TCF_OK;
 }
 
 template <class T>
 static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
   int status = TCF_OK;
+  int iters[4], sweeps[4];
+  bool conv[4];
   for (int s = 0; s < nsteps; ++s) {
     const int l = h->steps_done;
     const double t0 = now_ms();
     int it_sum = 0, ir_sum = 0;
     bool all_conv = true;
-    for (int k = 0; k < h->n_rhs; ++k) {
-      int iters = 0, sweeps = 0;
-      bool conv = true;
-      RCCHK(step_one<T>(h, k, l, st, iters, sweeps, conv));
-      it_sum += iters;
-      ir_sum += sweeps;
-      all_conv &= conv;
-      h->last_iters = iters;
-      h->last_ir = sweeps;
-      h->max_iters = std::max(h->max_iters, iters);
-      h->total_iters += iters;
+    for (int k0 = 0; k0 < h->n_rhs; k0 += h->rb) {
+      const int nc = std::min(h->rb, h->n_rhs - k0);
+      RCCHK(step_batch<T>(h, k0, nc, l, st, iters, sweeps, conv));
+      for (int j = 0; j < nc; ++j) {
+        it_sum += iters[j];
+        ir_sum += sweeps[j];
+        all_conv &= conv[j];
+        h->last_iters = iters[j];
+        h->last_ir = sweeps[j];
+        h->max_iters = std::max(h->max_iters, iters[j]);
+        h->total_iters += iters[j];
+      }
     }
     HIPCHK(hipStreamSynchronize(st));
     if (h->prof_on) h->prof_flush(INT32_MAX);

@@ -1049,79 +1049,177 @@ __device__ inline double sum_slots(const double* slots, double* sh) {
   return sh[0];
 }
 
-// Tile-path update.  p.Fp comes from the quadratic-form slots of the F apply
-// (x^T S_bb^-1 x + cv^T S_Pi^-1 cv, x = Bhat^T p), Fp = dt (w[pp] - w[pm])
-// is formed on the fly from the accumulated w; alpha = rz[par] / p.Fp;
-// lambda += alpha p; r -= alpha Fp; partial[block] = r.r.  Also clears
-// zero[0 .. nzero) (the preconditioner accumulator and its slots).
+// ---- tile-path PCG on R right-hand sides at once ---------------------------
+// Vectors are column-major (column j of an n-vector at j * n); st[0 .. R)
+// hold each column's scalars, st[R].done is set when every column is done.
+// A converged column is frozen (its lambda and r no longer change).
+
+// lambda = 0, r = d, partial[j * npart + block] = d_j.d_j
+template <int R>
+__global__ void __launch_bounds__(256) k_pcg_init_t(int n, const double* d, double* lam,
+                                                    double* r, double* part_dd, int npart) {
+  __shared__ double sh4[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    double v = 0.0;
+    if (i < n) {
+      v = d[(int64_t)j * n + i];
+      lam[(int64_t)j * n + i] = 0.0;
+      r[(int64_t)j * n + i] = v;
+    }
+    const double s = block_sum256(v * v, sh4);
+    if (threadIdx.x == 0) part_dd[j * npart + blockIdx.x] = s;
+    __syncthreads();
+  }
+}
+
+// z0 = tb[pp] - tb[pm] (tb = S_bb B^T r0 from the preconditioner tiles),
+// p = z0; block 0: dd, r.z (the preconditioner's quadratic-form slots),
+// iteration counts and flags.
+template <int R>
+__global__ void __launch_bounds__(256) k_pcg_init2_t(int n, const int* pos_p, const int* pos_m,
+                                                     const double* tb, int tld,
+                                                     const double* rz_slots,
+                                                     const double* part_dd, int npart,
+                                                     PcgScalars* st, double* p) {
+  __shared__ double sh[1];
+  __shared__ double sh1[1];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int a = pos_p[i], b = pos_m[i];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      p[(int64_t)j * n + i] = tb[(int64_t)j * tld + a] - tb[(int64_t)j * tld + b];
+  }
+  if (blockIdx.x == 0) {
+    int all = 1;
+    for (int j = 0; j < R; ++j) {
+      const double dd = sum_partials(part_dd + j * npart, npart, sh1);
+      const double rz = sum_slots(rz_slots + j * TCF_QSLOTS, sh);
+      if (threadIdx.x == 0) {
+        st[j].dd = dd;
+        st[j].rz[0] = rz;
+        st[j].rz[1] = 0.0;
+        st[j].rr = dd;
+        st[j].done = dd == 0.0 ? 1 : 0;
+        st[j].iters = 0;
+      }
+      all &= dd == 0.0 ? 1 : 0;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) st[R].done = all;
+  }
+}
+
+// p.Fp from the F apply's quadratic-form slots (x^T S_bb^-1 x + cv^T S_Pi^-1
+// cv, x = Bhat^T p); Fp = dt (w[pp] - w[pm]) formed on the fly from the
+// accumulated w; alpha = rz[par] / p.Fp; lambda += alpha p; r -= alpha Fp;
+// ||r||^2 partials.  Also clears zero[0 .. nzero) (the preconditioner
+// accumulator and its slots).
+template <int R>
 __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, const int* pos_m,
-                                                      const double* w, double dt,
+                                                      const double* w, int wld, double dt,
                                                       const double* pq_slots, PcgScalars* st,
                                                       int par, double* lam, double* r,
                                                       const double* p, double* part_rr,
-                                                      double* zero, int64_t nzero) {
-  if (st->done) return;
+                                                      int npart, double* zero, int64_t nzero) {
+  if (st[R].done) return;
   __shared__ double sh[1];
   __shared__ double sh4[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int a = 0, b = 0;
-  double pi = 0.0, ri = 0.0, li = 0.0;
+  double pi[R], ri[R], li[R];
   if (i < n) {
     a = pos_p[i];
     b = pos_m[i];
-    pi = p[i];
-    ri = r[i];
-    li = lam[i];
   }
-  const double pq = sum_slots(pq_slots, sh);
-  const double alpha = st->rz[par] / pq;
-  double v = 0.0;
-  if (i < n) {
-    const double fi = dt * (w[a] - w[b]);
-    lam[i] = li + alpha * pi;
-    ri -= alpha * fi;
-    r[i] = ri;
-    v = ri * ri;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
+    ri[j] = i < n ? r[(int64_t)j * n + i] : 0.0;
+    li[j] = i < n ? lam[(int64_t)j * n + i] : 0.0;
   }
   for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
-  const double s = block_sum256(v, sh4);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const double pq = sum_slots(pq_slots + j * TCF_QSLOTS, sh);
+    const bool live = !st[j].done;
+    double v = 0.0;
+    if (i < n) {
+      if (live) {
+        const double alpha = st[j].rz[par] / pq;
+        const double fi = dt * (w[(int64_t)j * wld + a] - w[(int64_t)j * wld + b]);
+        lam[(int64_t)j * n + i] = li[j] + alpha * pi[j];
+        ri[j] -= alpha * fi;
+        r[(int64_t)j * n + i] = ri[j];
+      }
+      v = ri[j] * ri[j];
+    }
+    const double s = block_sum256(v, sh4);
+    if (threadIdx.x == 0) part_rr[j * npart + blockIdx.x] = s;
+    __syncthreads();
+  }
 }
 
-// Tile-path search direction.  r.z comes from the preconditioner's
-// quadratic-form slots, z = tb[pp] - tb[pm] is formed on the fly; beta =
-// (r.z) / rz[par]; p = z + beta p.  Block 0 records rz[par ^ 1], sums the
-// ||r||^2 partials and sets the iteration count and convergence flag (other
-// blocks may then stop early: p is not used after convergence).  Also
-// clears zero[0 .. nzero) (the F-apply accumulators and their slots).
+// r.z from the preconditioner's quadratic-form slots, z = tb[pp] - tb[pm]
+// on the fly; beta = (r.z) / rz[par]; p = z + beta p.  Block 0 records
+// rz[par ^ 1], sums the ||r||^2 partials and sets each column's iteration
+// count and flag and the all-done flag (other blocks may then stop early: p
+// is not used after convergence).  Also clears zero[0 .. nzero) (the F-apply
+// accumulators and their slots).
+template <int R>
 __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, const int* pos_m,
-                                                       const double* tb, const double* rz_slots,
+                                                       const double* tb, int tld,
+                                                       const double* rz_slots,
                                                        const double* part_rr, int npart,
                                                        PcgScalars* st, int par, double tol2,
                                                        double* p, double* zero, int64_t nzero) {
-  if (st->done) return;
+  if (st[R].done) return;
   __shared__ double sh[1];
   __shared__ double sh1[1];
+  __shared__ double rzs[R];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int a = 0, b = 0;
-  double pi = 0.0;
+  double pi[R];
   if (i < n) {
     a = pos_p[i];
     b = pos_m[i];
-    pi = p[i];
   }
-  const double rz_new = sum_slots(rz_slots, sh);
-  const double beta = rz_new / st->rz[par];
-  if (i < n) p[i] = (tb[a] - tb[b]) + beta * pi;
+#pragma unroll
+  for (int j = 0; j < R; ++j) pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
   for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
-  if (blockIdx.x == 0) {
-    const double rr = sum_partials(part_rr, npart, sh1);
-    if (threadIdx.x == 0) {
-      st->rz[par ^ 1] = rz_new;
-      st->rr = rr;
-      st->iters += 1;
-      if (rr <= tol2 * st->dd) st->done = 1;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const double rz_new = sum_slots(rz_slots + j * TCF_QSLOTS, sh);
+    if (threadIdx.x == 0) rzs[j] = rz_new;
+    if (i < n && !st[j].done) {
+      const double beta = rz_new / st[j].rz[par];
+      p[(int64_t)j * n + i] =
+          (tb[(int64_t)j * tld + a] - tb[(int64_t)j * tld + b]) + beta * pi[j];
     }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    int all = 1;  // meaningful in thread 0, which writes every flag itself
+    for (int j = 0; j < R; ++j) {
+      const double rr = sum_partials(part_rr + j * npart, npart, sh1);
+      if (threadIdx.x == 0) {
+        int dn = st[j].done;
+        if (!dn) {
+          st[j].rz[par ^ 1] = rzs[j];
+          st[j].rr = rr;
+          st[j].iters += 1;
+          if (rr <= tol2 * st[j].dd) {
+            st[j].done = 1;
+            dn = 1;
+          }
+        }
+        all &= dn;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) st[R].done = all;
   }
 }
 
@@ -1343,19 +1441,36 @@ void launch_jump(int n, const int* pp, const int* pm, const double* w, double sc
   hipLaunchKernelGGL(k_jump, TCF_GRID(n, 256), dim3(256), 0, st, n, pp, pm, w, scale, y, dotw,
                      partial, done);
 }
-void launch_pcg_update_t(int n, const int* pp, const int* pm, const double* w, double dt,
-                         const double* pq_slots, PcgScalars* stt, int par, double* lam, double* r,
-                         const double* p, double* part_rr, double* zero, int64_t nzero,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_update_t, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, w, dt,
-                     pq_slots, stt, par, lam, r, p, part_rr, zero, nzero);
+#define TCF_R_DISPATCH(R, KERNEL, GRID, ...)                                          \
+  switch (R) {                                                                       \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+  }
+void launch_pcg_init_t(int R, int n, const double* d, double* lam, double* r, double* part_dd,
+                       int npart, hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_init_t, TCF_GRID(max(n, 1), 256), n, d, lam, r, part_dd, npart);
 }
-void launch_pcg_pupdate_t(int n, const int* pp, const int* pm, const double* tb,
+void launch_pcg_init2_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
+                        const double* rz_slots, const double* part_dd, int npart,
+                        PcgScalars* stt, double* p, hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_init2_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, rz_slots,
+                 part_dd, npart, stt, p);
+}
+void launch_pcg_update_t(int R, int n, const int* pp, const int* pm, const double* w, int wld,
+                         double dt, const double* pq_slots, PcgScalars* stt, int par,
+                         double* lam, double* r, const double* p, double* part_rr, int npart,
+                         double* zero, int64_t nzero, hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_update_t, TCF_GRID(max(n, 1), 256), n, pp, pm, w, wld, dt, pq_slots,
+                 stt, par, lam, r, p, part_rr, npart, zero, nzero);
+}
+void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
                           const double* rz_slots, const double* part_rr, int npart,
                           PcgScalars* stt, int par, double tol2, double* p, double* zero,
                           int64_t nzero, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, pp, pm, tb,
-                     rz_slots, part_rr, npart, stt, par, tol2, p, zero, nzero);
+  TCF_R_DISPATCH(R, k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, rz_slots,
+                 part_rr, npart, stt, par, tol2, p, zero, nzero);
 }
 void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
                      hipStream_t st) {
@@ -1650,27 +1765,36 @@ struct TileVec<float> {
 // Group (the operator) fixes the input mode: 0 (F apply) and 2 (Dirichlet
 // preconditioner) take the signed gather scale * gsgn[i] * xv[gidx[i]],
 // 1 (Phi_b N q) the plain gather xv[gidx[i]], 3 (coarse) reads xv[i].
-template <class T, int Group>
+template <class T, int Group, int R>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
-                                               const double* xv, const int* gidx,
+                                               const double* xv, int xld, const int* gidx,
                                                const signed char* gsgn, double scale,
-                                               double* y, const int* ymap, double* qslot,
-                                               const int* done) {
+                                               double* y, int yld, const int* ymap,
+                                               double* qslot, const int* done) {
   constexpr int XM = Group == 3 ? 0 : (Group == 1 ? 2 : 1);
+  // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b % 8); give
+  // each XCD a contiguous run of jobs, so that the tiles of a patch, which
+  // share inputs and outputs, stay within one L2.
+  const int nb = gridDim.x, per = nb >> 3, rem = nb & 7;
+  const int xcd = blockIdx.x & 7, kk = blockIdx.x >> 3;
+  const int job = xcd < rem ? xcd * (per + 1) + kk : rem * (per + 1) + (xcd - rem) * per + kk;
   typedef typename TileVec<T>::v VT;
   constexpr int V = TileVec<T>::n;   // rows per chunk
   constexpr int RPC = 64 / V;        // chunks per column
   constexpr int L = 64 * 64 / V / 256;  // loads per thread
   constexpr int CPL = 256 / RPC;     // columns advanced per load
-  const TileJob jb = jobs[blockIdx.x];
+  // column-sum partials per column and RHS: with several RHS, FP64 tiles
+  // first combine lane pairs so the LDS array stays 16 wide
+  constexpr int PRE = (R > 1 && RPC > 16) ? RPC / 16 : 1;
+  constexpr int TPW = RPC / PRE;
+  const TileJob jb = jobs[job];
   // the test reads a job field (never negative) so that the descriptor load
   // is issued together with the flag read instead of after it
   if ((done ? *done : 0) | (jb.nc < 0) | (jb.m_off < 0)) return;
-  __shared__ double xs[256];  // [0, 64) row-side inputs, [64, 128) column side, rest unused
-  __shared__ double Tp[64][RPC + 1];
-  __shared__ double Np[4][64];
-  const double* xr = xs;
-  const double* xc = xs + 64;
+  // inputs of RHS j: xs[j][0, 64) row side, xs[j][64, 128) column side
+  __shared__ double xs[R][256];
+  __shared__ double Tp[R][64][TPW + 1];
+  __shared__ double Np[R][4][64];
   const int t = threadIdx.x;
   const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = jb.flags & 16;
   const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
@@ -1692,70 +1816,94 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   VT raw[L];
   const int h = t / RPC, lr = t % RPC;
   // only the nc stored columns exist: a lane past them reads its row chunk
-  // of column 0 instead and drops the value (no branch around the loads,
-  // which would serialise them)
+  // of column 0 instead (no branch around the loads, which would serialise
+  // them).  That value needs no masking: the column's input is zero, so it
+  // adds nothing to the row sums, and its column sum is never written.
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     const bool ok = k * CPL + h < jb.nc;
-    const VT v = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
-    raw[k] = ok ? v : VT(0);
+    raw[k] = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
   }
   __builtin_amdgcn_sched_barrier(0);
-  // inputs, step 2: values, all 256 lanes (no branch): slot t of xs
+  // inputs, step 2: values, all 256 lanes (no branch): slot t of xs[j]
   {
-    const double xg = xv[gi];
-    xs[t] = xon ? (XM == 1 ? scale * (double)sgi : 1.0) * xg : 0.0;
+    const double f = XM == 1 ? scale * (double)sgi : 1.0;
+    // indices are non-negative: an unsigned index needs no sign extension,
+    // which the compiler would otherwise hoist right behind the index load
+    const unsigned gu = (unsigned)gi;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const double xg = xv[(size_t)j * (unsigned)xld + gu];
+      xs[j][t] = xon ? f * xg : 0.0;
+    }
   }
   __syncthreads();
   const int r0 = V * lr;
-  double xrv[V], n[V];
+  double xrv[R][V], n[R][V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) {
-    xrv[v] = xr[r0 + v];
-    n[v] = 0.0;
-  }
+  for (int j = 0; j < R; ++j)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      xrv[j][v] = xs[j][r0 + v];
+      n[j][v] = 0.0;
+    }
 #pragma unroll
   for (int k = 0; k < L; ++k) {
     const int cc = k * CPL + h;
-    const double xcv = xc[cc];
-    double tp = 0.0;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const double a = (double)raw[k][v];
-      n[v] += a * xcv;
-      tp += a * xrv[v];
+    for (int j = 0; j < R; ++j) {
+      const double xcv = xs[j][64 + cc];
+      double tp = 0.0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double a = (double)raw[k][v];
+        n[j][v] += a * xcv;
+        tp += a * xrv[j][v];
+      }
+      if (PRE == 2) tp += __shfl_xor(tp, 1, 64);
+      if (lr % PRE == 0) Tp[j][cc][lr / PRE] = tp;
     }
-    Tp[cc][lr] = tp;
   }
   // rows r0.. are shared by the lanes of a wave with equal t % RPC
 #pragma unroll
   for (int m = RPC; m < 64; m <<= 1)
 #pragma unroll
-    for (int v = 0; v < V; ++v) n[v] += __shfl_xor(n[v], m, 64);
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+      for (int v = 0; v < V; ++v) n[j][v] += __shfl_xor(n[j][v], m, 64);
   const int w = t >> 6;
   if ((t & 63) < RPC) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) Np[w][r0 + v] = n[v];
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+      for (int v = 0; v < V; ++v) Np[j][w][r0 + v] = n[j][v];
   }
   __syncthreads();
   if (doT) {
     const int cc = t >> 2, q = t & 3;
-    double sum = 0.0;
+    const int yi = (cc < jb.nc) ? ((jb.flags & 4) ? ymap[jb.yc_off + cc] : jb.yc_off + cc) : 0;
 #pragma unroll
-    for (int k = 0; k < RPC / 4; ++k) sum += Tp[cc][q * (RPC / 4) + k];
-    sum += __shfl_xor(sum, 1, 64);
-    sum += __shfl_xor(sum, 2, 64);
-    if (q == 0 && cc < jb.nc) {
-      const int yi = (jb.flags & 4) ? ymap[jb.yc_off + cc] : jb.yc_off + cc;
-      atomicAdd(y + yi, sum);
+    for (int j = 0; j < R; ++j) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < TPW / 4; ++k) sum += Tp[j][cc][q * (TPW / 4) + k];
+      sum += __shfl_xor(sum, 1, 64);
+      sum += __shfl_xor(sum, 2, 64);
+      if (q == 0 && cc < jb.nc) atomicAdd(y + (int64_t)j * yld + yi, sum);
     }
   }
   if (doN && t < 64) {  // wave 0
-    const double sum = (Np[0][t] + Np[1][t]) + (Np[2][t] + Np[3][t]);
-    if (t < jb.nr) atomicAdd(y + ((jb.flags & 8) ? ymap[jb.yr_off + t] : jb.yr_off + t), sum);
-    if (qf) {  // this tile's share of x^T A x (rows past nr carry zeros)
-      const double v = wave_sum(xr[t] * sum);
-      if (t == 0) atomicAdd(qslot + (blockIdx.x & (TCF_QSLOTS - 1)), (jb.flags & 32) ? 2.0 * v : v);
+    const int yi = (t < jb.nr) ? ((jb.flags & 8) ? ymap[jb.yr_off + t] : jb.yr_off + t) : 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const double sum = (Np[j][0][t] + Np[j][1][t]) + (Np[j][2][t] + Np[j][3][t]);
+      if (t < jb.nr) atomicAdd(y + (int64_t)j * yld + yi, sum);
+      if (qf) {  // this tile's share of x^T A x (rows past nr carry zeros)
+        const double v = wave_sum(xs[j][t] * sum);
+        if (t == 0)
+          atomicAdd(qslot + j * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
+                    (jb.flags & 32) ? 2.0 * v : v);
+      }
     }
   }
 }
@@ -1772,27 +1920,51 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
 }
 // group only names the kernel instance (apply / phi / precond / coarse) so
 // that traces attribute each operator separately
+template <class T, int G>
+static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
+                           int xld, const int* gidx, const signed char* gsgn, double scale,
+                           double* y, int yld, const int* ymap, double* qslot, const int* done,
+                           hipStream_t st) {
+  switch (R) {
+    case 1:
+      TCF_TIMED_LAUNCH((k_tiles<T, G, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx,
+                       gsgn, scale, y, yld, ymap, qslot, done);
+      break;
+    case 2:
+      TCF_TIMED_LAUNCH((k_tiles<T, G, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx,
+                       gsgn, scale, y, yld, ymap, qslot, done);
+      break;
+    case 3:
+      TCF_TIMED_LAUNCH((k_tiles<T, G, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx,
+                       gsgn, scale, y, yld, ymap, qslot, done);
+      break;
+    default:
+      TCF_TIMED_LAUNCH((k_tiles<T, G, 4>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx,
+                       gsgn, scale, y, yld, ymap, qslot, done);
+      break;
+  }
+}
 template <class T>
-void launch_tiles(int group, const TileJob* jobs, int njobs, const T* M, const double* xv,
-                  const int* gidx, const signed char* gsgn, double scale, double* y,
-                  const int* ymap, double* qslot, const int* done, hipStream_t st) {
+void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
+                  int xld, const int* gidx, const signed char* gsgn, double scale, double* y,
+                  int yld, const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
   switch (group) {
     case 0:
-      TCF_TIMED_LAUNCH((k_tiles<T, 0>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, qslot, done);
+      launch_tiles_g<T, 0>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
+                           done, st);
       break;
     case 1:
-      TCF_TIMED_LAUNCH((k_tiles<T, 1>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, qslot, done);
+      launch_tiles_g<T, 1>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
+                           done, st);
       break;
     case 2:
-      TCF_TIMED_LAUNCH((k_tiles<T, 2>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, qslot, done);
+      launch_tiles_g<T, 2>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
+                           done, st);
       break;
     default:
-      TCF_TIMED_LAUNCH((k_tiles<T, 3>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, gidx, gsgn,
-                       scale, y, ymap, qslot, done);
+      launch_tiles_g<T, 3>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
+                           done, st);
       break;
   }
 }
@@ -1815,10 +1987,10 @@ template void launch_pack_tiles<double, double>(const PackJob*, int, const doubl
                                                 hipStream_t);
 template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,
                                               hipStream_t);
-template void launch_tiles<double>(int, const TileJob*, int, const double*, const double*,
-                                   const int*, const signed char*, double, double*, const int*,
-                                   double*, const int*, hipStream_t);
-template void launch_tiles<float>(int, const TileJob*, int, const float*, const double*,
-                                  const int*, const signed char*, double, double*, const int*,
+template void launch_tiles<double>(int, int, const TileJob*, int, const double*, const double*,
+                                   int, const int*, const signed char*, double, double*, int,
+                                   const int*, double*, const int*, hipStream_t);
+template void launch_tiles<float>(int, int, const TileJob*, int, const float*, const double*, int,
+                                  const int*, const signed char*, double, double*, int, const int*,
                                   double*, const int*, hipStream_t);
 }  // namespace tcf

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtcf.so")
+# TCF_LIB names another build of the same library (e.g. a variant under test)
+LIB_PATH = os.environ.get("TCF_LIB", os.path.join(HERE, "libtcf.so"))
 
 TCF_OK, TCF_EINVAL, TCF_ENOMEM, TCF_ENOTSPD, TCF_ENOCONV, TCF_EHIP, TCF_ESTATE = 0, -1, -2, -3, -4, -5, -6
 TCF_FP64, TCF_FP32_IR, TCF_FP32_FULL_IR = 0, 1, 2
@@ -55,7 +56,7 @@ class tcf_problem_desc(C.Structure):
 class tcf_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("ir_rtol", C.c_double), ("ir_maxit", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("rhs_batch", C.c_int32)]
 
 
 class tcf_stats(C.Structure):
@@ -149,7 +150,7 @@ def default_options(**kw) -> tcf_options:
 
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
-            use_graph=1):
+            use_graph=1, rhs_batch=0):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -193,7 +194,7 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         precision=PRECISIONS[prec] if isinstance(prec, str) else int(prec),
         pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
         pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
-        check_every=int(check_every), use_graph=int(use_graph))
+        check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch))
     return d, o, keep
 
 
@@ -273,52 +274,12 @@ class Problem:
     again by tcf_setup)."""
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
-                 check_every=8, use_graph=1):
+                 check_every=8, use_graph=1, rhs_batch=0):
         L = lib()
         self.prob = prob
-        self._keep = []
-        d = tcf_problem_desc()
-        for a in range(3):
-            d.np[a] = int(prob.np[a])
-            br = np.ascontiguousarray(prob.breaks[a], dtype=np.float64)
-            ne = np.ascontiguousarray(prob.nel[a], dtype=np.int32)
-            dg = np.ascontiguousarray(prob.deg[a], dtype=np.int32)
-            self._keep += [br, ne, dg]
-            d.breaks[a] = _dptr(br, C.c_double)
-            d.nel[a] = _dptr(ne, C.c_int32)
-            d.deg[a] = _dptr(dg, C.c_int32)
-        sig = np.ascontiguousarray(prob.sigma, dtype=np.float64)
-        nu = np.ascontiguousarray(prob.nu, dtype=np.float64)
-        src = np.ascontiguousarray(prob.src_mask, dtype=np.uint8)
-        amp = np.ascontiguousarray(prob.amp, dtype=np.float64)
-        self._keep += [sig, nu, src, amp]
-        d.sigma = _dptr(sig, C.c_double)
-        d.nu = _dptr(nu, C.c_double)
-        d.src_mask = _dptr(src, C.c_uint8)
-        d.n_rhs = int(amp.shape[0])
-        phi = prob.phi
-
-        def _cb(xs, nx, ys, ny, zs, nz, k, out, ctx):
-            x = np.ctypeslib.as_array(xs, shape=(nx,))
-            y = np.ctypeslib.as_array(ys, shape=(ny,))
-            z = np.ctypeslib.as_array(zs, shape=(nz,))
-            v = np.asarray(phi(x, y, z, int(k)), dtype=np.float64).reshape(nx, ny, nz)
-            o = np.ctypeslib.as_array(out, shape=(nx * ny * nz,))
-            o[:] = v.ravel(order="F")
-
-        self._cb = PHI_FN(_cb)
-        d.phi = self._cb
-        d.phi_ctx = None
-        d.amp = _dptr(amp, C.c_double)
-        d.dt = float(prob.dt)
-        d.n_steps = int(amp.shape[1])
+        d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
+                                   use_graph, rhs_batch)
         self._desc = d
-        prec = precision if precision is not None else prob.precision
-        o = default_options(
-            precision=PRECISIONS[prec] if isinstance(prec, str) else int(prec),
-            pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
-            pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
-            check_every=int(check_every), use_graph=int(use_graph))
         self.opts = o
         h = C.c_void_p()
         rc = L.tcf_create(C.byref(d), C.byref(o), C.byref(h))

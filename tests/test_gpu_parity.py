@@ -16,10 +16,37 @@ from tests.test_oracle_gauge import CASES, tiny
 pytestmark = pytest.mark.gpu
 
 
-def _run_and_compare(prob, tol, rtol=None, steps=None, every=1):
+_ORACLE = {}
+
+
+def _problem_key(prob, steps):
+    """Identity of a problem's inputs (names are not unique: every tiny case
+    is called "tiny")."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (list(prob.breaks) + list(prob.nel) + list(prob.deg)
+              + [prob.sigma, prob.nu, prob.src_mask, prob.amp]):
+        h.update(np.ascontiguousarray(a).tobytes())
+    xs = np.linspace(0.05, 0.95, 4)
+    for k in range(prob.n_rhs):
+        for v in prob.phi(xs, xs, xs, k):
+            h.update(np.ascontiguousarray(v, dtype=np.float64).tobytes())
+    h.update(repr((tuple(prob.np), prob.dt, steps)).encode())
+    return h.hexdigest()
+
+
+def _oracle(prob, steps):
+    """Oracle run, reused by cases with the same inputs (e.g. precisions)."""
+    key = _problem_key(prob, steps)
+    if key not in _ORACLE:
+        _ORACLE[key] = solve.run(prob, n_steps=steps)
+    return _ORACLE[key]
+
+
+def _run_and_compare(prob, tol, rtol=None, steps=None, every=1, **opts):
     steps = prob.n_steps if steps is None else steps
-    ref = solve.run(prob, n_steps=steps)
-    p = tcf.Problem(prob, pcg_rtol=rtol)
+    ref = _oracle(prob, steps)
+    p = tcf.Problem(prob, pcg_rtol=rtol, **opts)
     print(f"[parity] {prob.name} steps={steps} counts={p.counts()}", flush=True)
     p.tcf_setup()
     worst = 0.0
@@ -86,6 +113,17 @@ def test_floating_reduced_fp32_ir(mode):
 def test_floating_reduced_fp64():
     prob = W.floating_mixed(n=4, p=3, n_steps=3, precision="fp64")
     _run_and_compare(prob, 1e-9)
+
+
+@pytest.mark.parametrize("batch", [4, 3, 1])
+@pytest.mark.parametrize("mode", ["fp32_ir", "fp64"])
+def test_largest_reduced_multirhs(mode, batch):
+    """Checkerboard box at reduced size: 4x4x2 patches, n=4, the first 4 of the
+    32 excitations; every excitation compared at every step.  batch = columns
+    of one PCG (3: a full batch and a partial one with idle columns)."""
+    prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=3, precision=mode)
+    worst, st = _run_and_compare(prob, 1e-9 if mode == "fp64" else 1e-8, rhs_batch=batch)
+    assert st["nonconverged_steps"] == 0
 
 
 # ---- full size: step residual of the oracle's assembled system ----------------
