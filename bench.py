@@ -37,6 +37,11 @@ def parse():
                     choices=["uneven", "plain", "mixed", "largest", "multirhs", "serving"])
     ap.add_argument("--rhs-batch", type=int, default=0,
                     help="excitations per batched PCG (0: automatic, up to 4)")
+    ap.add_argument("--pcg-warm", type=int, default=0, choices=[0, 1, 2],
+                    help="timed run: first solve of a step from the previous (1) or "
+                         "extrapolated (2) multipliers; 0 = from zero")
+    ap.add_argument("--no-warm-leg", action="store_true",
+                    help="skip the extra leg that reports the extrapolated warm start")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--rate-x", type=float, default=2.0,
                     help="serving: arrival rate as a multiple of the solo FP64 capacity")
@@ -224,7 +229,7 @@ def main():
     prob = make_problem(args.workload, max(n_steps, args.check_steps))
     prec = args.precision or prob.precision
     p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
-                    rhs_batch=args.rhs_batch)
+                    rhs_batch=args.rhs_batch, pcg_warm=args.pcg_warm)
     counts = p.counts()
     t0 = time.perf_counter()
     p.tcf_setup()
@@ -297,6 +302,28 @@ def main():
         print(f"[bench] field rel err vs oracle over {args.check_steps} steps: {rel_err:.2e}",
               file=sys.stderr, flush=True)
 
+    # the same timed run with the first solve of each step started from the
+    # extrapolated multipliers of the last two steps (same stopping test)
+    warm = None
+    if not args.no_warm_leg and args.pcg_warm == 0:
+        pw = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
+                         rhs_batch=args.rhs_batch, pcg_warm=2)
+        pw.tcf_setup()
+        if args.warmup:
+            pw.tcf_step(args.warmup)
+        w0 = pw.tcf_get_stats()
+        pw.tcf_sync()
+        tw0 = time.perf_counter()
+        pw.tcf_step(args.steps)
+        pw.tcf_sync()
+        tw = time.perf_counter() - tw0
+        w1 = pw.tcf_get_stats()
+        warm = {"value": args.steps / tw, "unit": "time-steps/s", "pcg_warm": 2,
+                "pcg_iters_per_step": (w1["total_pcg_iters"] - w0["total_pcg_iters"]) / args.steps}
+        pw.tcf_destroy()
+        print(f"[bench] warm-start leg {warm['value']:.2f} steps/s, "
+              f"{warm['pcg_iters_per_step']:.1f} iterations per step", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] oracle baseline on a sub-sample", file=sys.stderr, flush=True)
@@ -320,7 +347,8 @@ def main():
                    "dt": prob.dt, "pcg_rtol": prob.pcg_rtol, "precision": prec,
                    "n_edges": counts["n_edges"], "gauged_dofs": counts["n_kept"],
                    "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"],
-                   "graphs": not args.no_graph, "rhs_batch": args.rhs_batch or "auto"},
+                   "graphs": not args.no_graph, "rhs_batch": args.rhs_batch or "auto",
+                   "pcg_warm": args.pcg_warm},
         "rhs_steps_per_s": args.steps * prob.n_rhs / wall,
         "pcg_applies_per_s": applies / wall,
         "pcg_iters_per_step": applies / args.steps,
@@ -333,6 +361,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": breakdown,
+        "warm_start": warm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

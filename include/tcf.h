@@ -103,10 +103,14 @@ typedef struct tcf_options {
                             /* several columns, each operator tile read once  */
                             /* per iteration for all of them): 1..4, <= 0:    */
                             /* min(n_rhs, 4)                                  */
+  int32_t pcg_warm;         /* first solve of a step starts from: 0 lambda =  */
+                            /* 0; 1 the previous step's lambda; 2 the linear  */
+                            /* extrapolation of the last two (the stopping    */
+                            /* test stays ||r|| <= rtol ||d||)                 */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
- * rhs_batch 0 (automatic). */
+ * rhs_batch 0 (automatic), pcg_warm 0. */
 void tcf_default_options(tcf_options* opts);
 
 typedef struct tcf_problem tcf_problem;

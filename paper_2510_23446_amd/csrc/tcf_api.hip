@@ -173,6 +173,11 @@ struct tcf_problem {
   bool use_tiles = true;
   int rb = 1;  // excitations per PCG (columns of every PCG vector and accumulator)
   bool bp_gaps = false;  // some patch has primal but no dual unknowns
+  // warm starts: lambda of the first solve of the last two steps per
+  // excitation ([k][0] latest, [k][1] the one before) and how many are stored
+  double* d_lamh = nullptr;
+  std::vector<int> lamh_n;
+  bool warm_init = false;  // the next pcg_solve starts from the lambda columns as set
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
   bool graph_failed = false;          // capture refused: stream launches instead
@@ -437,6 +442,7 @@ void tcf_default_options(tcf_options* o) {
   o->check_every = 8;
   o->use_graph = 1;
   o->rhs_batch = 0;
+  o->pcg_warm = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -459,6 +465,7 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   if (!(h->opt.pcg_rtol > 0)) { g_create_error = "pcg_rtol <= 0"; return TCF_EINVAL; }
   if (h->opt.check_every <= 0) h->opt.check_every = 8;
   if (h->opt.ir_maxit <= 0) h->opt.ir_maxit = 10;
+  if (h->opt.pcg_warm < 0 || h->opt.pcg_warm > 2) { g_create_error = "pcg_warm not in 0..2"; return TCF_EINVAL; }
   h->precision = h->opt.precision;
   h->pcg_tol = h->precision == TCF_FP64 ? h->opt.pcg_rtol : std::max(h->opt.pcg_rtol, 1e-7);
   {
@@ -1054,6 +1061,10 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   h->npart = (nl + 255) / 256;
   RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4 * rb));
   RCCHK(h->alloc(&h->d_st, (size_t)rb + 1));  // per column, plus the all-done flag
+  if (h->opt.pcg_warm > 0 && h->use_tiles) {
+    RCCHK(h->alloc(&h->d_lamh, (size_t)nl * 2 * h->n_rhs));
+    h->lamh_n.assign(h->n_rhs, 0);
+  }
   RCCHK(h->alloc(&h->d_field, (size_t)h->g.n_edges()));
   {
     std::lock_guard<std::mutex> lk(g_capture_mu);
@@ -1443,7 +1454,23 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     const TileAcc a = tile_acc(h);
     double* p_dd = h->d_part + (int64_t)npt * R;
     launch_zero(h->n_acc, h->d_acc, st);
-    launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
+    if (h->warm_init) {
+      // r0 = d - F lambda0: one F apply on the lambda columns as set
+      launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_lam, nl, h->d_brow,
+                      h->d_bsgn, h->dt, a.vc, a.lf, h->d_cmap, a.pq, nullptr, st);
+      if (h->n_primal > 0) {
+        launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, a.vc + h->n_bptot, a.lf,
+                             nullptr, nullptr, 1.0, a.q, a.npm, nullptr, a.pq, nullptr, st);
+        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.npm, h->d_prank,
+                        nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, nullptr, st);
+      }
+      launch_pcg_init_w(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, h->d_d, h->d_r,
+                        p_dd, npt, st);
+      launch_zero(a.n_head, a.vc, st);
+      h->warm_init = false;
+    } else {
+      launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
+    }
     launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
                     h->d_bsgn, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
     launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, a.rz, p_dd, npt,
@@ -1668,7 +1695,37 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   h->cur_sweep = 0;
   for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, l, nullptr, nullptr, j, st);
   zero_idle(all);
+  if (h->d_lamh) {
+    // lambda0 per column from the excitation's history (zero without one)
+    for (int j = 0; j < R; ++j) {
+      double* lam = h->d_lam + (int64_t)j * nl;
+      const int k = k0 + j;
+      const int nh = j < nc ? h->lamh_n[k] : 0;
+      const double* h1 = h->d_lamh + ((int64_t)k * 2 + 0) * nl;
+      const double* h2 = h->d_lamh + ((int64_t)k * 2 + 1) * nl;
+      if (nh == 0)
+        launch_zero(nl, lam, st);
+      else if (nh == 1 || h->opt.pcg_warm == 1)
+        launch_axpby(nl, 1.0, h1, 0.0, lam, st);
+      else {
+        launch_axpby(nl, 1.0, h2, 0.0, lam, st);
+        launch_axpby(nl, 2.0, h1, -1.0, lam, st);  // 2 h1 - h2
+      }
+    }
+    h->warm_init = true;
+  }
   RCCHK(run_pcg());
+  if (h->d_lamh) {
+    for (int j = 0; j < nc; ++j) {
+      const int k = k0 + j;
+      double* h1 = h->d_lamh + ((int64_t)k * 2 + 0) * nl;
+      double* h2 = h->d_lamh + ((int64_t)k * 2 + 1) * nl;
+      HIPCHK(hipMemcpyAsync(h2, h1, sizeof(double) * nl, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(h1, h->d_lam + (int64_t)j * nl, sizeof(double) * nl,
+                            hipMemcpyDeviceToDevice, st));
+      h->lamh_n[k] = std::min(h->lamh_n[k] + 1, 2);
+    }
+  }
   for (int j = 0; j < nc; ++j) solve_post<T>(h, k0 + j, j, h->d_a + (int64_t)(k0 + j) * ldv, st);
   collect(all);
   for (int j = 0; j < nc; ++j) sweeps[j] = 1;
@@ -1867,6 +1924,7 @@ int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream) {
                         (hipStream_t)stream));
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   h->steps_done = (int)hdr[0];
+  std::fill(h->lamh_n.begin(), h->lamh_n.end(), 0);  // warm-start history no longer applies
   return TCF_OK;
 }
 

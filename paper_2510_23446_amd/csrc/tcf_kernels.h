@@ -122,6 +122,9 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
 // is the all-columns flag.
 void launch_pcg_init_t(int R, int n, const double* d, double* lam, double* r, double* part_dd,
                        int npart, hipStream_t st);
+void launch_pcg_init_w(int R, int n, const int* pp, const int* pm, const double* w, int wld,
+                       double dt, const double* d, double* r, double* part_dd, int npart,
+                       hipStream_t st);
 void launch_pcg_init2_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
                         const double* rz_slots, const double* part_dd, int npart,
                         PcgScalars* stt, double* p, hipStream_t st);

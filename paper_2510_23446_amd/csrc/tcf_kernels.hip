@@ -1074,6 +1074,34 @@ __global__ void __launch_bounds__(256) k_pcg_init_t(int n, const double* d, doub
   }
 }
 
+// Warm start: r0 = d - F lambda0, with F lambda0 = dt (w[pp] - w[pm]) from
+// the accumulated w of one F apply on lambda0 (lambda is left as it is);
+// partial[j * npart + block] = d_j.d_j (the stopping test stays relative to d).
+template <int R>
+__global__ void __launch_bounds__(256) k_pcg_init_w(int n, const int* pos_p, const int* pos_m,
+                                                    const double* w, int wld, double dt,
+                                                    const double* d, double* r, double* part_dd,
+                                                    int npart) {
+  __shared__ double sh4[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int a = 0, b = 0;
+  if (i < n) {
+    a = pos_p[i];
+    b = pos_m[i];
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    double v = 0.0;
+    if (i < n) {
+      v = d[(int64_t)j * n + i];
+      r[(int64_t)j * n + i] = v - dt * (w[(int64_t)j * wld + a] - w[(int64_t)j * wld + b]);
+    }
+    const double s = block_sum256(v * v, sh4);
+    if (threadIdx.x == 0) part_dd[j * npart + blockIdx.x] = s;
+    __syncthreads();
+  }
+}
+
 // z0 = tb[pp] - tb[pm] (tb = S_bb B^T r0 from the preconditioner tiles),
 // p = z0; block 0: dd, r.z (the preconditioner's quadratic-form slots),
 // iteration counts and flags.
@@ -1451,6 +1479,12 @@ void launch_jump(int n, const int* pp, const int* pm, const double* w, double sc
 void launch_pcg_init_t(int R, int n, const double* d, double* lam, double* r, double* part_dd,
                        int npart, hipStream_t st) {
   TCF_R_DISPATCH(R, k_pcg_init_t, TCF_GRID(max(n, 1), 256), n, d, lam, r, part_dd, npart);
+}
+void launch_pcg_init_w(int R, int n, const int* pp, const int* pm, const double* w, int wld,
+                       double dt, const double* d, double* r, double* part_dd, int npart,
+                       hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_init_w, TCF_GRID(max(n, 1), 256), n, pp, pm, w, wld, dt, d, r, part_dd,
+                 npart);
 }
 void launch_pcg_init2_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
                         const double* rz_slots, const double* part_dd, int npart,

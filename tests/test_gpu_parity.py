@@ -197,3 +197,34 @@ def test_uneven_full_size_residual():
     assert st["nonconverged_steps"] == 0
     assert zmax == 0.0
     assert max(res) <= RES_TOL
+
+
+# ---- warm starts (first solve of a step from the previous multipliers) -------
+@pytest.mark.parametrize("warm", [1, 2])
+def test_warm_start_plain_all_steps(warm):
+    """Same stopping test (||r|| <= rtol ||d||), so the field matches the oracle
+    to the same bar; the iteration count drops once there is a history."""
+    prob = W.plain_fp64()
+    worst, st = _run_and_compare(prob, 1e-9, pcg_warm=warm)
+    cold = tcf.Problem(prob)
+    cold.tcf_setup()
+    cold.tcf_step(prob.n_steps)
+    it_cold, _, _ = cold.tcf_get_step_log(prob.n_steps)
+    warm_p = tcf.Problem(prob, pcg_warm=warm)
+    warm_p.tcf_setup()
+    warm_p.tcf_step(prob.n_steps)
+    it_warm, _, _ = warm_p.tcf_get_step_log(prob.n_steps)
+    print(f"[parity] warm {warm}: iterations cold {list(it_cold)} warm {list(it_warm)}", flush=True)
+    assert it_warm[0] == it_cold[0]  # no history at the first step
+    assert sum(it_warm[3:]) < sum(it_cold[3:])
+
+
+def test_warm_start_uneven_reduced():
+    prob = W.uneven_fp64(seed=1, n_steps=3, P=(3, 3, 3))
+    _run_and_compare(prob, 1e-9, pcg_warm=2)
+
+
+def test_warm_start_fp32_ir_multirhs():
+    prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=3, precision="fp32_ir")
+    worst, st = _run_and_compare(prob, 1e-8, pcg_warm=2, rhs_batch=3)
+    assert st["nonconverged_steps"] == 0

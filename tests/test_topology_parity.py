@@ -104,3 +104,13 @@ def test_invalid_descriptions():
     bad.breaks = [np.array([0.0, 0.5, 0.4]), prob.breaks[1], prob.breaks[2]]
     with pytest.raises(tcf.TcfError):
         tcf.Problem(bad)
+
+
+def test_invalid_options():
+    prob = W.plain_fp64()
+    for kw in ({"pcg_warm": 3}, {"pcg_warm": -1}, {"pcg_rtol": 0.0}, {"precision": 7}):
+        with pytest.raises(tcf.TcfError) as e:
+            tcf.Problem(prob, **kw)
+        assert e.value.code == tcf.TCF_EINVAL, kw
+    # accepted: batch widths beyond 4 or n_rhs are clamped
+    tcf.Problem(prob, rhs_batch=9, pcg_warm=2)
