@@ -1152,7 +1152,8 @@ __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, c
                                                       int par, double* lam, double* r,
                                                       const double* p, double* part_rr,
                                                       int npart, double* zero, int64_t nzero) {
-  if (st[R].done) return;
+  // no early exit on the all-done flag: that read would sit in front of every
+  // other load; the per-column flags below already guard all updates
   __shared__ double sh[1];
   __shared__ double sh4[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1203,7 +1204,7 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, 
                                                        const double* part_rr, int npart,
                                                        PcgScalars* st, int par, double tol2,
                                                        double* p, double* zero, int64_t nzero) {
-  if (st[R].done) return;
+  // no early exit on the all-done flag (see k_pcg_update_t)
   __shared__ double sh[1];
   __shared__ double sh1[1];
   __shared__ double rzs[R];

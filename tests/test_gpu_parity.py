@@ -228,3 +228,12 @@ def test_warm_start_fp32_ir_multirhs():
     prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=3, precision="fp32_ir")
     worst, st = _run_and_compare(prob, 1e-8, pcg_warm=2, rhs_batch=3)
     assert st["nonconverged_steps"] == 0
+
+
+def test_column_dot_path_plain(monkeypatch):
+    """The operators applied from the dense per-patch blocks instead of tiles
+    (TCF_NO_TILES=1, read when the handle is created): same field."""
+    monkeypatch.setenv("TCF_NO_TILES", "1")
+    prob = W.plain_fp64().with_steps(5)
+    worst, st = _run_and_compare(prob, 1e-9)
+    assert st["nonconverged_steps"] == 0
