@@ -268,7 +268,7 @@ def main():
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         tj = json.load(open(args.traffic))
-        same_kernel = tj.get("kernel_source_sha256") == kernel_digest("template <class T, int Group>")
+        same_kernel = tj.get("kernel_source_sha256") == kernel_digest("template <class T, int Group, int R>")
         if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
                 and prec == "fp64"):
             traffic = tj.get("hbm_bytes_per_launch")
