@@ -107,10 +107,14 @@ typedef struct tcf_options {
                             /* 0; 1 the previous step's lambda; 2 the linear  */
                             /* extrapolation of the last two (the stopping    */
                             /* test stays ||r|| <= rtol ||d||)                 */
+  int32_t precond_scaling;  /* Dirichlet preconditioner: 0 unscaled (as      */
+                            /* published), 1 stiffness-scaled: each copy of a */
+                            /* dual unknown weighted by the other copy's share*/
+                            /* of the two local diagonal entries              */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
- * rhs_batch 0 (automatic), pcg_warm 0. */
+ * rhs_batch 0 (automatic), pcg_warm 0, precond_scaling 0. */
 void tcf_default_options(tcf_options* opts);
 
 typedef struct tcf_problem tcf_problem;

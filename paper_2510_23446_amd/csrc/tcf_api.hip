@@ -178,6 +178,11 @@ struct tcf_problem {
   double* d_lamh = nullptr;
   std::vector<int> lamh_n;
   bool warm_init = false;  // the next pcg_solve starts from the lambda columns as set
+  // signed gathers of the tile path: Bhat's +-1 per b entry (F apply) and the
+  // preconditioner's (the same, or D Bhat when scaled); weights of the two
+  // copies in the preconditioner's jump (null: unscaled)
+  double *d_bsgn_d = nullptr, *d_pre_w = nullptr, *d_zwp = nullptr, *d_zwm = nullptr;
+  std::vector<int> h_posp, h_posm;  // b-space copies of each multiplier (host)
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
   bool graph_failed = false;          // capture refused: stream launches instead
@@ -443,6 +448,7 @@ void tcf_default_options(tcf_options* o) {
   o->use_graph = 1;
   o->rhs_batch = 0;
   o->pcg_warm = 0;
+  o->precond_scaling = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -466,6 +472,10 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   if (h->opt.check_every <= 0) h->opt.check_every = 8;
   if (h->opt.ir_maxit <= 0) h->opt.ir_maxit = 10;
   if (h->opt.pcg_warm < 0 || h->opt.pcg_warm > 2) { g_create_error = "pcg_warm not in 0..2"; return TCF_EINVAL; }
+  if (h->opt.precond_scaling < 0 || h->opt.precond_scaling > 1) {
+    g_create_error = "precond_scaling not in 0..1";
+    return TCF_EINVAL;
+  }
   h->precision = h->opt.precision;
   h->pcg_tol = h->precision == TCF_FP64 ? h->opt.pcg_rtol : std::max(h->opt.pcg_rtol, 1e-7);
   {
@@ -774,6 +784,13 @@ static int build_index_tables(tcf_problem* h) {
   RCCHK(h->upload(&h->d_isint, isint));
   RCCHK(h->upload(&h->d_prank, prank));
   RCCHK(h->upload(&h->d_posp, posp));
+  h->h_posp = posp;
+  h->h_posm = posm;
+  {
+    std::vector<double> sd(bsgn.begin(), bsgn.end());
+    RCCHK(h->upload(&h->d_bsgn_d, sd));
+    h->d_pre_w = h->d_bsgn_d;
+  }
   RCCHK(h->upload(&h->d_posm, posm));
   RCCHK(h->upload(&h->d_posp_r, posp_r));
   RCCHK(h->upload(&h->d_posp_bp, posp_bp));
@@ -948,6 +965,34 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     const DevPatch& d = h->hp[s];
     if (d.ni_pad > 0) ja.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, 0, d.ni_pad, s});
     if (d.nb_pad > 0) jbv.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, d.ni_pad, d.ni_pad + d.nb_pad, s});
+  }
+  if (h->opt.precond_scaling == 1 && h->n_lambda > 0 && h->use_tiles) {
+    // stiffness scaling: the copy of a dual unknown in patch s is weighted
+    // by the other copy's share k_other / (k_s + k_other) of the two local
+    // diagonal entries (taken before factorisation)
+    double* kd;
+    RCCHK(h->alloc(&kd, (size_t)h->n_btot));
+    launch_bdiag<T>(h->dP, np, A, kd, st);
+    std::vector<double> k(h->n_btot);
+    HIPCHK(hipMemcpyAsync(k.data(), kd, sizeof(double) * h->n_btot, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(kd);
+    std::vector<double> bw(h->n_btot, 0.0), wp(h->n_lambda), wm(h->n_lambda);
+    for (int m = 0; m < h->n_lambda; ++m) {
+      const int ep = h->h_posp[m], em = h->h_posm[m];
+      const double kp = k[ep], km = k[em];
+      if (!(kp > 0 && km > 0)) {
+        h->err = "non-positive diagonal entry at a dual unknown";
+        return TCF_ENOTSPD;
+      }
+      wp[m] = km / (kp + km);
+      wm[m] = kp / (kp + km);
+      bw[ep] = wp[m];    // sign +1
+      bw[em] = -wm[m];   // sign -1
+    }
+    RCCHK(h->upload(&h->d_pre_w, bw));
+    RCCHK(h->upload(&h->d_zwp, wp));
+    RCCHK(h->upload(&h->d_zwm, wm));
   }
   RCCHK(run_factor_phase<T>(h, ja, A, st));
   T *G, *S, *Q;
@@ -1372,7 +1417,7 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
     const double tol2 = h->pcg_tol * h->pcg_tol;
     timed(h, TCF_KG_APPLY, st, [&] {
       launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, nl, h->d_brow,
-                      h->d_bsgn, h->dt, a.vc, a.lf, h->d_cmap, a.pq, alldone, st);
+                      h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, alldone, st);
     });
     if (h->n_primal > 0) {
       timed(h, TCF_KG_COARSE, st, [&] {
@@ -1388,10 +1433,10 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
                         h->d_lam, h->d_r, h->d_p, p_rr, npt, a.tb, a.n_tail, st);
     timed(h, TCF_KG_PRECOND, st, [&] {
       launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
-                      h->d_bsgn, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, alldone, st);
+                      h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, alldone, st);
     });
-    launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, a.rz, p_rr, npt, stv,
-                         par, tol2, h->d_p, a.vc, a.n_head, st);
+    launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
+                         a.rz, p_rr, npt, stv, par, tol2, h->d_p, a.vc, a.n_head, st);
     return;
   }
   const int nl = h->n_lambda, npt = h->npart;
@@ -1457,7 +1502,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     if (h->warm_init) {
       // r0 = d - F lambda0: one F apply on the lambda columns as set
       launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_lam, nl, h->d_brow,
-                      h->d_bsgn, h->dt, a.vc, a.lf, h->d_cmap, a.pq, nullptr, st);
+                      h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, nullptr, st);
       if (h->n_primal > 0) {
         launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, a.vc + h->n_bptot, a.lf,
                              nullptr, nullptr, 1.0, a.q, a.npm, nullptr, a.pq, nullptr, st);
@@ -1472,9 +1517,9 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
       launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
     }
     launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
-                    h->d_bsgn, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
-    launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, a.rz, p_dd, npt,
-                       h->d_st, h->d_p, st);
+                    h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
+    launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
+                       a.rz, p_dd, npt, h->d_st, h->d_p, st);
   } else {
     double* p_rz = h->d_part + 2 * npt;
     double* p_dd = h->d_part + 3 * npt;

@@ -116,8 +116,10 @@ template <class T>
 // R (1..4) right-hand sides at once: inputs xv[j * xld + i], outputs
 // y[j * yld + i], quadratic-form slots qslot[j * TCF_QSLOTS + k].
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
-                  int xld, const int* gidx, const signed char* gsgn, double scale, double* y,
+                  int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st);
+template <class T>
+void launch_bdiag(const DevPatch* P, int np, const T* A, double* out, hipStream_t st);
 // Tile-path PCG on R (1..4) right-hand sides, column-major vectors; st[R].done
 // is the all-columns flag.
 void launch_pcg_init_t(int R, int n, const double* d, double* lam, double* r, double* part_dd,
@@ -126,16 +128,17 @@ void launch_pcg_init_w(int R, int n, const int* pp, const int* pm, const double*
                        double dt, const double* d, double* r, double* part_dd, int npart,
                        hipStream_t st);
 void launch_pcg_init2_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
-                        const double* rz_slots, const double* part_dd, int npart,
-                        PcgScalars* stt, double* p, hipStream_t st);
+                        const double* wp, const double* wm, const double* rz_slots,
+                        const double* part_dd, int npart, PcgScalars* stt, double* p,
+                        hipStream_t st);
 void launch_pcg_update_t(int R, int n, const int* pp, const int* pm, const double* w, int wld,
                          double dt, const double* pq_slots, PcgScalars* stt, int par,
                          double* lam, double* r, const double* p, double* part_rr, int npart,
                          double* zero, int64_t nzero, hipStream_t st);
 void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
-                          const double* rz_slots, const double* part_rr, int npart,
-                          PcgScalars* stt, int par, double tol2, double* p, double* zero,
-                          int64_t nzero, hipStream_t st);
+                          const double* wp, const double* wm, const double* rz_slots,
+                          const double* part_rr, int npart, PcgScalars* stt, int par,
+                          double tol2, double* p, double* zero, int64_t nzero, hipStream_t st);
 // Timing events for the next launch (of a timed kernel) issued by this thread.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();

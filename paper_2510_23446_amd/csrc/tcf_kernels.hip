@@ -1102,12 +1102,14 @@ __global__ void __launch_bounds__(256) k_pcg_init_w(int n, const int* pos_p, con
   }
 }
 
-// z0 = tb[pp] - tb[pm] (tb = S_bb B^T r0 from the preconditioner tiles),
+// z0 = wp tb[pp] - wm tb[pm] (tb = S_bb (D B)^T r0 from the preconditioner
+// tiles; wp = wm = 1 unscaled, else the scaling weights of the two copies),
 // p = z0; block 0: dd, r.z (the preconditioner's quadratic-form slots),
 // iteration counts and flags.
 template <int R>
 __global__ void __launch_bounds__(256) k_pcg_init2_t(int n, const int* pos_p, const int* pos_m,
                                                      const double* tb, int tld,
+                                                     const double* wp, const double* wm,
                                                      const double* rz_slots,
                                                      const double* part_dd, int npart,
                                                      PcgScalars* st, double* p) {
@@ -1116,9 +1118,10 @@ __global__ void __launch_bounds__(256) k_pcg_init2_t(int n, const int* pos_p, co
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const int a = pos_p[i], b = pos_m[i];
+    const double ca = wp ? wp[i] : 1.0, cb = wm ? wm[i] : 1.0;
 #pragma unroll
     for (int j = 0; j < R; ++j)
-      p[(int64_t)j * n + i] = tb[(int64_t)j * tld + a] - tb[(int64_t)j * tld + b];
+      p[(int64_t)j * n + i] = ca * tb[(int64_t)j * tld + a] - cb * tb[(int64_t)j * tld + b];
   }
   if (blockIdx.x == 0) {
     int all = 1;
@@ -1191,8 +1194,8 @@ __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, c
   }
 }
 
-// r.z from the preconditioner's quadratic-form slots, z = tb[pp] - tb[pm]
-// on the fly; beta = (r.z) / rz[par]; p = z + beta p.  Block 0 records
+// r.z from the preconditioner's quadratic-form slots, z = wp tb[pp] -
+// wm tb[pm] on the fly (weights as in k_pcg_init2_t); beta = (r.z) / rz[par]; p = z + beta p.  Block 0 records
 // rz[par ^ 1], sums the ||r||^2 partials and sets each column's iteration
 // count and flag and the all-done flag (other blocks may then stop early: p
 // is not used after convergence).  Also clears zero[0 .. nzero) (the F-apply
@@ -1200,6 +1203,7 @@ __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, c
 template <int R>
 __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, const int* pos_m,
                                                        const double* tb, int tld,
+                                                       const double* wp, const double* wm,
                                                        const double* rz_slots,
                                                        const double* part_rr, int npart,
                                                        PcgScalars* st, int par, double tol2,
@@ -1210,10 +1214,12 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, 
   __shared__ double rzs[R];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int a = 0, b = 0;
-  double pi[R];
+  double pi[R], ca = 1.0, cb = 1.0;
   if (i < n) {
     a = pos_p[i];
     b = pos_m[i];
+    if (wp) ca = wp[i];
+    if (wm) cb = wm[i];
   }
 #pragma unroll
   for (int j = 0; j < R; ++j) pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
@@ -1225,7 +1231,7 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, 
     if (i < n && !st[j].done) {
       const double beta = rz_new / st[j].rz[par];
       p[(int64_t)j * n + i] =
-          (tb[(int64_t)j * tld + a] - tb[(int64_t)j * tld + b]) + beta * pi[j];
+          (ca * tb[(int64_t)j * tld + a] - cb * tb[(int64_t)j * tld + b]) + beta * pi[j];
     }
     __syncthreads();
   }
@@ -1488,10 +1494,11 @@ void launch_pcg_init_w(int R, int n, const int* pp, const int* pm, const double*
                  npart);
 }
 void launch_pcg_init2_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
-                        const double* rz_slots, const double* part_dd, int npart,
-                        PcgScalars* stt, double* p, hipStream_t st) {
-  TCF_R_DISPATCH(R, k_pcg_init2_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, rz_slots,
-                 part_dd, npart, stt, p);
+                        const double* wp, const double* wm, const double* rz_slots,
+                        const double* part_dd, int npart, PcgScalars* stt, double* p,
+                        hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_init2_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, wp, wm,
+                 rz_slots, part_dd, npart, stt, p);
 }
 void launch_pcg_update_t(int R, int n, const int* pp, const int* pm, const double* w, int wld,
                          double dt, const double* pq_slots, PcgScalars* stt, int par,
@@ -1501,11 +1508,11 @@ void launch_pcg_update_t(int R, int n, const int* pp, const int* pm, const doubl
                  stt, par, lam, r, p, part_rr, npart, zero, nzero);
 }
 void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const double* tb, int tld,
-                          const double* rz_slots, const double* part_rr, int npart,
-                          PcgScalars* stt, int par, double tol2, double* p, double* zero,
-                          int64_t nzero, hipStream_t st) {
-  TCF_R_DISPATCH(R, k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, rz_slots,
-                 part_rr, npart, stt, par, tol2, p, zero, nzero);
+                          const double* wp, const double* wm, const double* rz_slots,
+                          const double* part_rr, int npart, PcgScalars* stt, int par,
+                          double tol2, double* p, double* zero, int64_t nzero, hipStream_t st) {
+  TCF_R_DISPATCH(R, k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, wp, wm,
+                 rz_slots, part_rr, npart, stt, par, tol2, p, zero, nzero);
 }
 void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
                      hipStream_t st) {
@@ -1798,12 +1805,13 @@ struct TileVec<float> {
 };
 
 // Group (the operator) fixes the input mode: 0 (F apply) and 2 (Dirichlet
-// preconditioner) take the signed gather scale * gsgn[i] * xv[gidx[i]],
+// preconditioner) take the signed gather scale * gsw[i] * xv[gidx[i]] (gsw:
+// the +-1 entries of Bhat, or for a scaled preconditioner those of D Bhat),
 // 1 (Phi_b N q) the plain gather xv[gidx[i]], 3 (coarse) reads xv[i].
 template <class T, int Group, int R>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
                                                const double* xv, int xld, const int* gidx,
-                                               const signed char* gsgn, double scale,
+                                               const double* gsw, double scale,
                                                double* y, int yld, const int* ymap,
                                                double* qslot, const int* done) {
   constexpr int XM = Group == 3 ? 0 : (Group == 1 ? 2 : 1);
@@ -1842,9 +1850,10 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   // lanes without an input read entry 0 (which every table has): no branch
   // around the loads, whose results are only used after the matrix loads
   const int xo = xon ? (side_r ? jb.xr_off : jb.xc_off) + tt : 0;
-  int gi = xo, sgi = 1;
+  int gi = xo;
+  double sw = 1.0;
   if (XM != 0) gi = gidx[xo];
-  if (XM == 1) sgi = gsgn[xo];
+  if (XM == 1) sw = gsw[xo];
   // keep the index loads ahead of the matrix loads (straight-line code, so
   // this pins the order the scheduler emits)
   __builtin_amdgcn_sched_barrier(0);
@@ -1862,7 +1871,7 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   __builtin_amdgcn_sched_barrier(0);
   // inputs, step 2: values, all 256 lanes (no branch): slot t of xs[j]
   {
-    const double f = XM == 1 ? scale * (double)sgi : 1.0;
+    const double f = XM == 1 ? scale * sw : 1.0;
     // indices are non-negative: an unsigned index needs no sign extension,
     // which the compiler would otherwise hoist right behind the index load
     const unsigned gu = (unsigned)gi;
@@ -1957,7 +1966,7 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
 // that traces attribute each operator separately
 template <class T, int G>
 static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
-                           int xld, const int* gidx, const signed char* gsgn, double scale,
+                           int xld, const int* gidx, const double* gsgn, double scale,
                            double* y, int yld, const int* ymap, double* qslot, const int* done,
                            hipStream_t st) {
   switch (R) {
@@ -1981,7 +1990,7 @@ static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, co
 }
 template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
-                  int xld, const int* gidx, const signed char* gsgn, double scale, double* y,
+                  int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
   switch (group) {
@@ -2004,6 +2013,25 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
   }
 }
 
+// Diagonal of each patch's dual block, read from the assembled [i|b|p]
+// matrix before it is factored: out[b_off + k] = A[(ni_pad + k), (ni_pad + k)].
+template <class T>
+__global__ void k_bdiag(const DevPatch* P, int np, const T* A, double* out) {
+  const int s = blockIdx.x;
+  if (s >= np) return;
+  const DevPatch& d = P[s];
+  const T* a = A + d.A_off;
+  for (int k = threadIdx.x; k < d.n_b; k += blockDim.x)
+    out[d.b_off + k] = (double)a[(int64_t)(d.ni_pad + k) * (d.nr_pad + 1)];
+}
+template <class T>
+void launch_bdiag(const DevPatch* P, int np, const T* A, double* out, hipStream_t st) {
+  if (np == 0) return;
+  hipLaunchKernelGGL(k_bdiag<T>, dim3(np), dim3(256), 0, st, P, np, A, out);
+}
+template void launch_bdiag<double>(const DevPatch*, int, const double*, double*, hipStream_t);
+template void launch_bdiag<float>(const DevPatch*, int, const float*, double*, hipStream_t);
+
 // Plain streaming copy (measurement reference for traffic counters).
 __global__ void k_copy_probe(int64_t n, const double4* a, double4* b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -2023,9 +2051,9 @@ template void launch_pack_tiles<double, double>(const PackJob*, int, const doubl
 template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,
                                               hipStream_t);
 template void launch_tiles<double>(int, int, const TileJob*, int, const double*, const double*,
-                                   int, const int*, const signed char*, double, double*, int,
+                                   int, const int*, const double*, double, double*, int,
                                    const int*, double*, const int*, hipStream_t);
 template void launch_tiles<float>(int, int, const TileJob*, int, const float*, const double*, int,
-                                  const int*, const signed char*, double, double*, int, const int*,
+                                  const int*, const double*, double, double*, int, const int*,
                                   double*, const int*, hipStream_t);
 }  // namespace tcf

@@ -56,7 +56,8 @@ class tcf_problem_desc(C.Structure):
 class tcf_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("ir_rtol", C.c_double), ("ir_maxit", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32)]
+                ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32),
+                ("precond_scaling", C.c_int32)]
 
 
 class tcf_stats(C.Structure):
@@ -150,7 +151,7 @@ def default_options(**kw) -> tcf_options:
 
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
-            use_graph=1, rhs_batch=0, pcg_warm=0):
+            use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -195,7 +196,7 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
         pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
         check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch),
-        pcg_warm=int(pcg_warm))
+        pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling))
     return d, o, keep
 
 
@@ -275,11 +276,11 @@ class Problem:
     again by tcf_setup)."""
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
-                 check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0):
+                 check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
-                                   use_graph, rhs_batch, pcg_warm)
+                                   use_graph, rhs_batch, pcg_warm, precond_scaling)
         self._desc = d
         self.opts = o
         h = C.c_void_p()

@@ -237,3 +237,28 @@ def test_column_dot_path_plain(monkeypatch):
     prob = W.plain_fp64().with_steps(5)
     worst, st = _run_and_compare(prob, 1e-9)
     assert st["nonconverged_steps"] == 0
+
+
+# ---- stiffness-scaled Dirichlet preconditioner (same solution, fewer iterations)
+@pytest.mark.parametrize("case", ["uneven", "floating_fp32_ir", "largest_batched", "plain_warm"])
+def test_scaled_preconditioner(case):
+    if case == "uneven":
+        prob, tol, kw = W.uneven_fp64(seed=1, n_steps=3, P=(3, 3, 3)), 1e-9, {}
+    elif case == "floating_fp32_ir":
+        prob, tol, kw = W.floating_mixed(n=4, p=3, n_steps=3, precision="fp32_ir"), 1e-8, {}
+    elif case == "largest_batched":
+        prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=3, precision="fp64")
+        tol, kw = 1e-9, {"rhs_batch": 4}
+    else:
+        prob, tol, kw = W.plain_fp64(), 1e-9, {"pcg_warm": 2}
+    worst, st = _run_and_compare(prob, tol, precond_scaling=1, **kw)
+    assert st["nonconverged_steps"] == 0
+    plain = tcf.Problem(prob, **kw)
+    plain.tcf_setup()
+    plain.tcf_step(prob.n_steps)
+    it_u, _, _ = plain.tcf_get_step_log(prob.n_steps)
+    scaled = tcf.Problem(prob, precond_scaling=1, **kw)
+    scaled.tcf_setup()
+    scaled.tcf_step(prob.n_steps)
+    it_s, _, _ = scaled.tcf_get_step_log(prob.n_steps)
+    print(f"[parity] scaled {case}: iterations unscaled {list(it_u)} scaled {list(it_s)}", flush=True)
