@@ -1,0 +1,104 @@
+"""The rest of the C-ABI on the GPU: checkpoint and resume, call order and
+limit errors, kernel-group timing, the copy probe and request states."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import solve
+from paper_2510_23446_amd import tcf
+
+pytestmark = pytest.mark.gpu
+
+
+def _field(p, k=0):
+    return np.array(p.tcf_get_field(k), copy=True)
+
+
+def test_checkpoint_resume_matches_uninterrupted_run():
+    """tcf_get_state after 5 of 10 steps, tcf_set_state on a fresh handle and
+    5 more steps: same field as 10 steps in one go, and as the oracle."""
+    prob = W.plain_fp64().with_steps(10)
+    a = tcf.Problem(prob)
+    a.tcf_setup()
+    a.tcf_step(5)
+    state = a.tcf_get_state()
+    a.tcf_step(5)
+    straight = _field(a)
+    b = tcf.Problem(prob)
+    b.tcf_setup()
+    b.tcf_set_state(state)
+    assert b.tcf_get_stats()["steps_done"] == 5
+    b.tcf_step(5)
+    resumed = _field(b)
+    ref = solve.run(prob).fields[-1][:, 0]
+    d = np.linalg.norm(resumed - straight) / np.linalg.norm(straight)
+    e = np.linalg.norm(resumed - ref) / np.linalg.norm(ref)
+    print(f"[api] resumed vs straight {d:.2e}, vs oracle {e:.2e}", flush=True)
+    # the tile products accumulate with atomics (rounding order varies from run
+    # to run) and each step's PCG is exact only to its stopping tolerance, so
+    # two runs agree to the solver tolerance, not bitwise
+    assert d <= 1e-9
+    assert e <= 1e-9
+    with pytest.raises(tcf.TcfError) as err:
+        b.tcf_set_state(state[:-8])
+    assert err.value.code == tcf.TCF_EINVAL
+
+
+def test_call_order_and_limits():
+    prob = W.plain_fp64().with_steps(3)
+    p = tcf.Problem(prob)
+    with pytest.raises(tcf.TcfError) as e:
+        p.tcf_step(1)
+    assert e.value.code == tcf.TCF_ESTATE
+    with pytest.raises(tcf.TcfError) as e:
+        p.tcf_get_field(0)
+    assert e.value.code == tcf.TCF_ESTATE
+    p.tcf_setup()
+    with pytest.raises(tcf.TcfError) as e:
+        p.tcf_setup()
+    assert e.value.code == tcf.TCF_ESTATE
+    with pytest.raises(tcf.TcfError) as e:
+        p.tcf_get_field(1)  # one excitation only
+    assert e.value.code == tcf.TCF_EINVAL
+    # an iteration limit far below convergence: flagged, results still readable
+    q = tcf.Problem(prob, pcg_maxit=3)
+    q.tcf_setup()
+    assert q.tcf_step(1, allow_noconv=True) == tcf.TCF_ENOCONV
+    st = q.tcf_get_stats()
+    assert st["nonconverged_steps"] == 1
+    assert np.all(np.isfinite(_field(q)))
+    # steps beyond n_steps are not taken
+    p.tcf_step(10)
+    assert p.tcf_get_stats()["steps_done"] == 3
+
+
+def test_kernel_group_timing_and_copy_probe():
+    prob = W.plain_fp64().with_steps(2)
+    p = tcf.Problem(prob)
+    p.tcf_setup()
+    p.tcf_profile_enable(True)
+    p.tcf_step(2)
+    p.tcf_sync()
+    prof = p.tcf_profile_get()
+    p.tcf_profile_enable(False)
+    it = int(p.tcf_get_stats()["total_pcg_iters"])
+    for g in ("apply", "precond", "phi", "coarse"):
+        ms, n, b = prof[g]
+        assert n > 0 and ms > 0 and b > 0, (g, prof[g])
+        assert n <= it + 2  # post-convergence launches are not counted
+    tcf.tcf_copy_probe(64 << 20)
+
+
+def test_server_request_states():
+    reqs = W.serving_requests(n_req=3, seed=3, n_steps=3, ks=(2,), nrange=(3, 4))
+    srv = tcf.Server(max_bytes=64 << 30, max_slots=1)
+    ids = [srv.tcf_server_submit(r, precision="fp64") for r in reqs]
+    states = [srv.tcf_server_poll(i) for i in ids]
+    assert all(s in (tcf.TCF_REQ_QUEUED, tcf.TCF_REQ_RUNNING, tcf.TCF_REQ_DONE) for s in states)
+    for i in ids:
+        assert srv.tcf_server_wait(i) == tcf.TCF_OK
+        assert srv.tcf_server_poll(i) == tcf.TCF_REQ_DONE
+        assert srv.tcf_server_error(i) == ""
+    with pytest.raises(tcf.TcfError):
+        srv.tcf_server_poll(len(ids) + 5)
+    srv.tcf_server_destroy()
