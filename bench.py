@@ -362,6 +362,10 @@ def main():
         "p50_step_ms": float(np.percentile(ms, 50)),
         "p99_step_ms": float(np.percentile(ms, 99)),
         "setup_s": setup_s,
+        # setup factorisations on the FP64/FP32 vector units (on this GPU the
+        # FP64 and FP32 matrix-core peaks equal the vector peaks)
+        "setup_tflops": p.tcf_get_stats()["setup_flops"] / setup_s / 1e12,
+        "setup_frac_of_fp64_peak": p.tcf_get_stats()["setup_flops"] / setup_s / 78.6e12,
         "rel_error_vs_oracle": rel_err,
         "rel_error_steps": args.check_steps,
         "rel_error_sample": check_name,

@@ -198,6 +198,15 @@ typedef struct tcf_stats {
   double setup_ms;
   double step_ms_total;
   size_t device_bytes;
+  double setup_flops;          /* algorithmic flops of the setup factorisations: */
+                               /* per patch n_i^3/3 + n_i^2 (n_b + n_p) +        */
+                               /* n_i (n_b + n_p)^2 (interior elimination),      */
+                               /* n_b^3/3 + n_b^2 n_p + n_b n_p^2 (dual block),  */
+                               /* n_b^3/3 + n_b^2 (n_b + n_p) (S_bb^-1, Phi_b),  */
+                               /* n_i^3/3 + n_i^2 (n_b + n_p) (Q^T); coarse      */
+                               /* 5 n_Pi^3/3 (Cholesky, triangular inverse, and  */
+                               /* one full triangular solve); triangular         */
+                               /* right-hand sides counted by their nonzeros     */
 } tcf_stats;
 
 int tcf_get_stats(const tcf_problem* h, tcf_stats* st);

@@ -597,6 +597,19 @@ int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
   st->setup_ms = h->setup_ms;
   st->step_ms_total = h->step_ms_total;
   st->device_bytes = h->dev_bytes;
+  {
+    double f = 0.0;
+    for (int s = 0; s < h->np_tot; ++s) {
+      const double ni = h->hp[s].n_i, nb = h->hp[s].n_b, np_ = h->hp[s].n_p;
+      const double nbp = nb + np_;
+      f += ni * ni * ni / 3 + ni * ni * nbp + ni * nbp * nbp;  // interior elimination
+      f += nb * nb * nb / 3 + nb * nb * np_ + nb * np_ * np_;  // dual block
+      f += nb * nb * nb / 3 + nb * nb * (nb + np_);             // S_bb^-1 and Phi_b
+      f += ni * ni * ni / 3 + ni * ni * nbp;                    // Q^T
+    }
+    const double nP = h->n_primal;
+    st->setup_flops = f + 5 * nP * nP * nP / 3;  // coarse Cholesky and inverse
+  }
   return TCF_OK;
 }
 
@@ -1029,9 +1042,10 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     // SPinv = I, then solve L X = I and L^T Y = X
     HIPCHK(hipMemsetAsync(SPinv, 0, sizeof(double) * ldc * ldc, st));
     launch_identity_pad(SPinv, ldc, 0, h->n_primal, st);
-    std::vector<TrsmJob> tj{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal}};
+    std::vector<TrsmJob> tj{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal, h->n_primal, 0}};
+    std::vector<TrsmJob> tjb{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal, 0, 0}};
     RCCHK(run_trsm<double>(h, 1, tj, SPi, SPinv, st));
-    RCCHK(run_trsm<double>(h, 0, tj, SPi, SPinv, st));
+    RCCHK(run_trsm<double>(h, 0, tjb, SPi, SPinv, st));
     h->release(SPi);
     h->d_SPinv = SPinv;
   }
@@ -1056,10 +1070,13 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     for (int s = 0; s < np; ++s) {
       const DevPatch& d = h->hp[s];
       if (d.n_b > 0) {
-        gf.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b});
-        gb.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b + d.n_p});
+        gf.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b,
+                             d.n_b, 0});
+        gb.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad,
+                             d.n_b + d.n_p, 0, 0});
       }
-      if (d.n_i > 0) qb.push_back(TrsmJob{d.A_off, d.nr_pad, 0, d.ni_pad, d.Q_off, d.ni_pad, d.n_r});
+      if (d.n_i > 0)
+        qb.push_back(TrsmJob{d.A_off, d.nr_pad, 0, d.ni_pad, d.Q_off, d.ni_pad, d.n_r, d.n_i, 0});
     }
     RCCHK(run_trsm<T>(h, 1, gf, A, G, st));
     RCCHK(run_trsm<T>(h, 0, gb, A, G, st));

@@ -40,12 +40,16 @@ struct FactorJob {
 
 // Triangular solve with the lower block L (order n, multiple of TCF_NB) at
 // (l_row0, l_row0) of a matrix with leading dimension ldl, against ncols
-// right-hand sides stored with leading dimension ldb.
+// right-hand sides stored with leading dimension ldb.  The first tri
+// right-hand sides are the identity columns (the solution is then
+// triangular there and its zero rows are skipped).
 struct TrsmJob {
   int64_t l_off;
   int ldl, l_row0, n;
   int64_t b_off;
   int ldb, ncols;
+  int tri;
+  int pad;
 };
 
 // Column-dot matrix-vector job: out[j] = sum_{r < nrows} M[r + j*ld] x[r].

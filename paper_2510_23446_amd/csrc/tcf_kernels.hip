@@ -600,14 +600,17 @@ __global__ void k_trsm_fwd(const TrsmJob* jobs, const int* prefix, int njobs, co
   const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;  // cg in 0..7
   const int nblk = jb.n / TCF_NB;
   const int64_t ldl = jb.ldl, ldb = jb.ldb;
-  for (int kb = 0; kb < nblk; ++kb) {
+  // identity right-hand sides: L^-1 I is lower triangular, so the rows above
+  // this column block stay zero and contribute nothing
+  const int kmin = (c0 + 64 <= jb.tri) ? c0 / TCF_NB : 0;
+  for (int kb = kmin; kb < nblk; ++kb) {
     T acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int col = c0 + cg + 8 * q;
       acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
     }
-    for (int jblk = 0; jblk < kb; ++jblk) {
+    for (int jblk = kmin; jblk < kb; ++jblk) {
       __syncthreads();
       for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
         const int r = idx % TCF_NB, c = idx / TCF_NB;
@@ -665,14 +668,17 @@ __global__ void k_trsm_bwd(const TrsmJob* jobs, const int* prefix, int njobs, co
   const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;
   const int nblk = jb.n / TCF_NB;
   const int64_t ldl = jb.ldl, ldb = jb.ldb;
-  for (int kb = nblk - 1; kb >= 0; --kb) {
+  // identity right-hand sides: L^-T I is upper triangular, so the rows below
+  // this column block stay zero and contribute nothing
+  const int kmax = (c0 + 64 <= jb.tri) ? min(nblk - 1, (c0 + 63) / TCF_NB) : nblk - 1;
+  for (int kb = kmax; kb >= 0; --kb) {
     T acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int col = c0 + cg + 8 * q;
       acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
     }
-    for (int jblk = kb + 1; jblk < nblk; ++jblk) {
+    for (int jblk = kb + 1; jblk <= kmax; ++jblk) {
       __syncthreads();
       // Ls[l][r] = L[jblk*NB + l, kb*NB + r]
       for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {

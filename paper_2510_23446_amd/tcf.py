@@ -68,7 +68,8 @@ class tcf_stats(C.Structure):
                 ("last_ir_sweeps", C.c_int32), ("nonconverged_steps", C.c_int32),
                 ("fail_patch", C.c_int32), ("last_rel_residual", C.c_double),
                 ("last_ir_residual", C.c_double), ("setup_ms", C.c_double),
-                ("step_ms_total", C.c_double), ("device_bytes", C.c_size_t)]
+                ("step_ms_total", C.c_double), ("device_bytes", C.c_size_t),
+                ("setup_flops", C.c_double)]
 
 
 class tcf_server_report(C.Structure):
