@@ -1787,6 +1787,34 @@ __global__ void k_pack_tiles(const PackJob* jobs, const TS* src, TD* dst) {
 }
 
 
+// Lane exchanges inside a wave without the LDS crossbar: DPP moves of the two
+// 32-bit halves of a double.  CTRL is a DPP control word: quad_perm 0xB1 (lane
+// i takes lane i^1 of its quad), 0x4E (i^2), row_ror 0x120 + n (rotate by n
+// within each row of 16 lanes).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+// sum over the 4 lanes of a quad, in every lane of it
+__device__ inline double quad_sum(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  return v;
+}
+// sum over the 64 lanes of a wave, in every lane: rotations within rows of
+// 16 lanes, then two exchanges across rows
+__device__ inline double wave_sum_dpp(double v) {
+  v += dpp_f64<0x128>(v);
+  v += dpp_f64<0x124>(v);
+  v += dpp_f64<0x122>(v);
+  v += dpp_f64<0x121>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 // One block (256 threads) per tile (nc <= 64 columns of 64 rows, zero-padded).
 // Loads are coalesced: load k of thread t reads the 16-byte chunk k*256 + t,
 // i.e. V = 16/sizeof(T) consecutive rows (V*(t % RPC) ..) of column
@@ -1910,7 +1938,7 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
         n[j][v] += a * xcv;
         tp += a * xrv[j][v];
       }
-      if (PRE == 2) tp += __shfl_xor(tp, 1, 64);
+      if (PRE == 2) tp += dpp_f64<0xB1>(tp);
       if (lr % PRE == 0) Tp[j][cc][lr / PRE] = tp;
     }
   }
@@ -1937,8 +1965,7 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
       double sum = 0.0;
 #pragma unroll
       for (int k = 0; k < TPW / 4; ++k) sum += Tp[j][cc][q * (TPW / 4) + k];
-      sum += __shfl_xor(sum, 1, 64);
-      sum += __shfl_xor(sum, 2, 64);
+      sum = quad_sum(sum);
       if (q == 0 && cc < jb.nc) atomicAdd(y + (int64_t)j * yld + yi, sum);
     }
   }
@@ -1949,7 +1976,7 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
       const double sum = (Np[j][0][t] + Np[j][1][t]) + (Np[j][2][t] + Np[j][3][t]);
       if (t < jb.nr) atomicAdd(y + (int64_t)j * yld + yi, sum);
       if (qf) {  // this tile's share of x^T A x (rows past nr carry zeros)
-        const double v = wave_sum(xs[j][t] * sum);
+        const double v = wave_sum_dpp(xs[j][t] * sum);
         if (t == 0)
           atomicAdd(qslot + j * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
                     (jb.flags & 32) ? 2.0 * v : v);
