@@ -1803,16 +1803,31 @@ __device__ inline double quad_sum(double v) {
   v += dpp_f64<0x4E>(v);
   return v;
 }
+// v plus the value of lane ^ 32 (resp. ^ 16), in every lane, through the
+// permlane swaps: swapping a register with itself leaves (own, partner) in
+// one half of the wave and (partner, own) in the other, so the two results
+// add up to the pair sum everywhere (the same value: addition commutes)
+__device__ inline double xor32_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ inline double xor16_sum(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
 // sum over the 64 lanes of a wave, in every lane: rotations within rows of
-// 16 lanes, then two exchanges across rows
+// 16 lanes, then the two exchanges across rows
 __device__ inline double wave_sum_dpp(double v) {
   v += dpp_f64<0x128>(v);
   v += dpp_f64<0x124>(v);
   v += dpp_f64<0x122>(v);
   v += dpp_f64<0x121>(v);
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
+  v = xor16_sum(v);
+  return xor32_sum(v);
 }
 
 // One block (256 threads) per tile (nc <= 64 columns of 64 rows, zero-padded).
@@ -1944,11 +1959,12 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   }
   // rows r0.. are shared by the lanes of a wave with equal t % RPC
 #pragma unroll
-  for (int m = RPC; m < 64; m <<= 1)
+  for (int j = 0; j < R; ++j)
 #pragma unroll
-    for (int j = 0; j < R; ++j)
-#pragma unroll
-      for (int v = 0; v < V; ++v) n[j][v] += __shfl_xor(n[j][v], m, 64);
+    for (int v = 0; v < V; ++v) {
+      if (RPC == 16) n[j][v] = xor16_sum(n[j][v]);
+      n[j][v] = xor32_sum(n[j][v]);
+    }
   const int w = t >> 6;
   if ((t & 63) < RPC) {
 #pragma unroll
