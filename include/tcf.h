@@ -72,6 +72,18 @@ enum tcf_precision {
 typedef void (*tcf_phi_fn)(const double* xs, int32_t nx, const double* ys, int32_t ny,
                            const double* zs, int32_t nz, int32_t k, double* out, void* ctx);
 
+/*
+ * Vector callback: evaluate a vector field of excitation k at the points of a
+ * tensor grid inside patch s (id as in tcf_problem_desc):
+ *   out[c + 3*(ix + nx*(iy + ny*iz))] = F_c(xs[ix], ys[iy], zs[iz]),  c = 0, 1, 2.
+ * The patch id lets the field depend on the patch's material (a manufactured
+ * source does: the same potential gives a different J in a conductor and in
+ * an insulator).  Called from tcf_setup on the calling thread; the function
+ * and vec_ctx must stay valid until tcf_setup returns.
+ */
+typedef void (*tcf_vec_fn)(int32_t s, const double* xs, int32_t nx, const double* ys, int32_t ny,
+                           const double* zs, int32_t nz, int32_t k, double* out, void* ctx);
+
 typedef struct tcf_problem_desc {
   int32_t np[3];            /* patches per direction, each >= 1               */
   const double* breaks[3];  /* np[d]+1 strictly increasing patch boundaries   */
@@ -86,6 +98,23 @@ typedef struct tcf_problem_desc {
   const double* amp;        /* [n_rhs][n_steps]: g_k(t_{l+1}), t_l = l*dt     */
   double dt;                /* implicit Euler step, > 0                       */
   int32_t n_steps;          /* steps available in amp                         */
+  /* Optional fields (NULL = absent; zero-initialise the struct).  With them a
+   * problem whose boundary data was homogenised by a lifting (Sec. 2.1: the
+   * inhomogeneous n x A = g becomes n x A = 0 with a modified source and
+   * initial value) can be posed directly.                                  */
+  tcf_vec_fn jvol;          /* volume source: J_k(x,t) gains g_k(t) jvol_k(x) */
+                            /* on patches whose src_mask is set, loaded as    */
+                            /* the integral of J . w_e (the load vector of    */
+                            /* Sec. 2.2) on p_d + 3 Gauss points; may be used */
+                            /* with or without phi                             */
+  tcf_vec_fn ainit;         /* initial potential A_k(x, 0) (Sec. 2.1).  The   */
+                            /* first step's M a^(0) is taken as the integral  */
+                            /* of sigma A_k(x,0) . w_e, i.e. a^(0) is the      */
+                            /* sigma-weighted L2 projection of the initial    */
+                            /* value; evaluated on conductor patches only.    */
+                            /* It is added at step 0 on top of M times the    */
+                            /* held field (zero unless a state was restored)  */
+  void* vec_ctx;            /* passed to jvol and ainit                       */
 } tcf_problem_desc;
 
 typedef struct tcf_options {

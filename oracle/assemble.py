@@ -18,6 +18,12 @@ The source is J = g(t) curl Psi with Psi = (0, 0, phi).  The load uses the
 curl form int Psi . curl w_e (equal to int J . w_e whenever n x Psi = 0 on
 the boundary of the source region) on a rule of p_d + 3 points; the curl
 form makes the load annihilate discrete gradients exactly.
+
+A problem may instead (or also) give the source as a vector field J (the
+``jvol`` callback), loaded as written in Sec. 2.2: int J . w_e, on the same
+p_d + 3 point rule.  An initial potential A(x, 0) (Sec. 2.1, ``ainit``)
+enters the first step through int sigma A(x,0) . w_e, which is M a^(0) for
+the sigma-weighted L2 projection a^(0) of the initial value.
 """
 from __future__ import annotations
 
@@ -64,7 +70,8 @@ class PatchMatrices:
     gid: np.ndarray      # local edge -> global edge id
     M: sp.csr_matrix     # sigma-weighted mass (local numbering)
     K: sp.csr_matrix     # nu-weighted curl-curl (local numbering)
-    jhat: np.ndarray     # (n_local, n_rhs) curl-form load, zero if no source
+    jhat: np.ndarray     # (n_local, n_rhs) source load, zero if no source
+    m0: np.ndarray       # (n_local, n_rhs) initial load int sigma A(x,0) . w, zero if none
 
 
 def patch_rows(prob, s):
@@ -167,8 +174,51 @@ def assemble_patch(prob, grid: Grid, s: int) -> PatchMatrices:
     Kloc = sp.csr_matrix((np.concatenate(Kv), (r_, c_)), shape=(nloc, nloc))
     jloc = np.zeros((nloc, prob.n_rhs))
     if prob.src_mask[s]:
-        jloc = assemble_patch_load(prob, s, m)
-    return PatchMatrices(gid=gid, M=Mloc, K=Kloc, jhat=jloc)
+        if prob.phi is not None:
+            jloc = jloc + assemble_patch_load(prob, s, m)
+        if getattr(prob, "jvol", None) is not None:
+            jloc = jloc + assemble_patch_vec_load(prob, s, m, prob.jvol)
+    m0loc = np.zeros((nloc, prob.n_rhs))
+    if getattr(prob, "ainit", None) is not None and sig > 0:
+        m0loc = sig * assemble_patch_vec_load(prob, s, m, prob.ainit)
+    return PatchMatrices(gid=gid, M=Mloc, K=Kloc, jhat=jloc, m0=m0loc)
+
+
+def assemble_patch_vec_load(prob, s, m, fn):
+    """Volume-form load int F . w_e over patch s, one column per RHS.
+
+    F = fn(s, xs, ys, zs, k) on the tensor grid of load points, shape
+    (nx, ny, nz, 3).  An edge of direction d pairs with component d only:
+    x-edges take F_x D_a(x) N_b(y) N_c(z), y-edges F_y N_a D_b N_c, z-edges
+    F_z N_a N_b D_c.  Gauss rule with p_d + 3 points per element and direction.
+    """
+    rows = patch_rows(prob, s)
+    tabs = [_row_tables(r[0][0], r[0][1], r[1], r[2], r[2] + 3) for r in rows]
+    (x, wx, Nx, _, Dx), (y, wy, Ny, _, Dy), (zz, wz, Nz, _, Dz) = tabs
+    (nx, px), (ny, py), (nz, pz) = [(r[1], r[2]) for r in rows]
+    mx, my, mz = m
+    nloc = (mx - 1) * my * mz + mx * (my - 1) * mz + mx * my * (mz - 1)
+    out = np.zeros((nloc, prob.n_rhs))
+    qx, qy, qz = x.shape[1], y.shape[1], zz.shape[1]
+    for k in range(prob.n_rhs):
+        F = np.asarray(fn(s, x.ravel(), y.ravel(), zz.ravel(), k), dtype=np.float64)
+        F = F.reshape(nx, qx, ny, qy, nz, qz, 3)
+        for ez in range(nz):
+            for ey in range(ny):
+                for ex in range(nx):
+                    wgt = wx[ex][:, None, None] * wy[ey][None, :, None] * wz[ez][None, None, :]
+                    f = F[ex, :, ey, :, ez, :, :] * wgt[..., None]
+                    for d, (fa, fb, fc) in enumerate(((Dx[ex], Ny[ey], Nz[ez]),
+                                                      (Nx[ex], Dy[ey], Nz[ez]),
+                                                      (Nx[ex], Ny[ey], Dz[ez]))):
+                        v = np.einsum("xyz,xa,yb,zc->cba", f[..., d], fa, fb, fc).ravel()
+                        span = [px + 1, py + 1, pz + 1]
+                        span[d] -= 1
+                        idx = _local_index_blocks(m, np.arange(ex, ex + span[0]),
+                                                  np.arange(ey, ey + span[1]),
+                                                  np.arange(ez, ez + span[2]), d)
+                        np.add.at(out[:, k], idx, v)
+    return out
 
 
 def assemble_patch_load(prob, s, m):
@@ -214,6 +264,7 @@ class GlobalSystem:
     K: sp.csr_matrix       # sum over patches of nu curl-curl
     jhat: np.ndarray       # (n_edges, n_rhs)
     patches: list          # PatchMatrices per patch
+    m0: np.ndarray = None  # (n_edges, n_rhs) initial load, zeros if no initial value
 
     def W(self, dt):
         return (self.M + dt * self.K).tocsr()
@@ -226,6 +277,7 @@ def assemble_global(prob, grid: Grid | None = None, keep_patches=True) -> Global
     nE = grid.n_edges
     rows, cols, mv, kv = [], [], [], []
     jg = np.zeros((nE, prob.n_rhs))
+    m0 = np.zeros((nE, prob.n_rhs))
     pats = []
     for s in range(prob.n_patches):
         pm = assemble_patch(prob, grid, s)
@@ -237,10 +289,11 @@ def assemble_global(prob, grid: Grid | None = None, keep_patches=True) -> Global
         mv.append(Mc.data)
         kv.append(Kc.data)
         np.add.at(jg, pm.gid, pm.jhat)
+        np.add.at(m0, pm.gid, pm.m0)
         if keep_patches:
             pats.append(pm)
     r = np.concatenate(rows)
     c = np.concatenate(cols)
     Mg = sp.csr_matrix((np.concatenate(mv), (r, c)), shape=(nE, nE))
     Kg = sp.csr_matrix((np.concatenate(kv), (r, c)), shape=(nE, nE))
-    return GlobalSystem(grid=grid, M=Mg, K=Kg, jhat=jg, patches=pats)
+    return GlobalSystem(grid=grid, M=Mg, K=Kg, jhat=jg, patches=pats, m0=m0)

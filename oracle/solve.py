@@ -10,7 +10,9 @@ the eliminated edges at zero.  The oracle solves exactly that:
 
     W_g a_K^(l+1) = (M a^(l) + dt g(t_{l+1}) jhat)_K,   a^(0) = 0,
 
-with one sparse LU factorisation of W_g reused for every step.
+with one sparse LU factorisation of W_g reused for every step.  With an
+initial value A(x, 0) (Sec. 2.1) the first step's M a^(0) is the load
+int sigma A(x,0) . w_e (a^(0) = its sigma-weighted L2 projection).
 """
 from __future__ import annotations
 
@@ -57,6 +59,8 @@ def run(prob, n_steps=None, keep_fields=True) -> OracleRun:
     for l in range(steps):
         ts = time.perf_counter()
         f = sys.M @ a + prob.dt * sys.jhat * prob.amp[:, l][None, :]
+        if l == 0 and sys.m0 is not None:
+            f = f + sys.m0
         a = np.zeros((nE, prob.n_rhs))
         a[K] = lu.solve(np.ascontiguousarray(f[K]))
         t_solve += time.perf_counter() - ts

@@ -102,6 +102,9 @@ struct tcf_problem {
   int32_t n_rhs = 1;
   tcf_phi_fn phi = nullptr;
   void* phi_ctx = nullptr;
+  tcf_vec_fn jvol = nullptr, ainit = nullptr;
+  void* vec_ctx = nullptr;
+  double* d_m0 = nullptr;  // initial load int sigma A(x,0) . w (kept local order), per excitation
   std::vector<double> amp;
   double dt = 0.0;
   int32_t n_steps = 0;
@@ -368,6 +371,7 @@ size_t tcf_problem::footprint(int prec) const {
   b += ((size_t)n_bptot * 16 + (size_t)n_btot * 16 + (size_t)n_lambda * 8 * 8) * rb;
   b += (size_t)rb * (n_bptot + n_btot + 2 * TCF_QSLOTS) * 8 + (size_t)(tab_elems + ptab_elems) * 8;
   b += (size_t)n_rtot * 24 + (size_t)n_loctot * 4;
+  if (ainit && !cond_list.empty()) b += (size_t)n_rtot * n_rhs * 8;  // initial load
   return b;
 }
 
@@ -503,6 +507,9 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
                        : 1;
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
+  h->jvol = desc->jvol;
+  h->ainit = desc->ainit;
+  h->vec_ctx = desc->vec_ctx;
   h->dt = desc->dt;
   h->n_steps = desc->n_steps;
   if (desc->n_steps > 0) h->amp.assign(desc->amp, desc->amp + (size_t)desc->n_rhs * desc->n_steps);
@@ -934,22 +941,43 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   launch_assemble<T>(h->dP, d_colpre, np, colpre.back(), h->d_rloc, h->d_tabs, h->dt, A, st);
   HIPCHK(hipGetLastError());
 
-  // source loads (curl form), one patch at a time through a staging buffer
+  // source loads, one patch at a time through a staging buffer: the curl
+  // form (phi) and/or the volume form (jvol) on source patches, and the
+  // initial load int sigma A(x,0) . w (ainit) on conductor patches
   double* jr;
   RCCHK(h->alloc(&jr, (size_t)ldv * nrhs));
   HIPCHK(hipMemsetAsync(jr, 0, sizeof(double) * ldv * nrhs, st));
+  const bool want_m0 = h->ainit && !h->cond_list.empty();
+  if (want_m0) {
+    RCCHK(h->alloc(&h->d_m0, (size_t)ldv * nrhs));
+    HIPCHK(hipMemsetAsync(h->d_m0, 0, sizeof(double) * ldv * nrhs, st));
+  }
   {
+    auto uses = [&](int s) {
+      const DevPatch& d = h->hp[s];
+      if (d.n_r == 0) return false;
+      return (d.src && (h->phi || h->jvol)) || (want_m0 && h->sigma[s] > 0);
+    };
     size_t maxpts = 0;
     for (int s = 0; s < np; ++s)
-      if (h->hp[s].src)
+      if (uses(s))
         maxpts = std::max(maxpts, (size_t)h->hp[s].nq_load[0] * h->hp[s].nq_load[1] * h->hp[s].nq_load[2]);
     if (maxpts > 0) {
       double* stage;
-      RCCHK(h->alloc(&stage, maxpts * nrhs));
-      std::vector<double> hphi(maxpts * nrhs);
+      RCCHK(h->alloc(&stage, 3 * maxpts * nrhs));
+      std::vector<double> hbuf(3 * maxpts * nrhs);
+      // the previous launch has read the stage before it is overwritten, and
+      // the copy has left the (pageable) host buffer before the next
+      // callback refills it
+      auto upload_stage = [&](size_t n) -> int {
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpyAsync(stage, hbuf.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return TCF_OK;
+      };
       for (int s = 0; s < np; ++s) {
+        if (!uses(s)) continue;
         const DevPatch& d = h->hp[s];
-        if (!d.src || d.n_r == 0) continue;
         std::vector<double> ax[3];
         for (int a = 0; a < 3; ++a) {
           const int nq = d.deg[a] + 3;
@@ -958,14 +986,31 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
           for (int t = 0; t < d.nel[a]; ++t)
             for (int q = 0; q < nq; ++q) ax[a].push_back((hh * t + d.lo[a]) + 0.5 * hh * (h->gx[o + q] + 1.0));
         }
-        const size_t npts = ax[0].size() * ax[1].size() * ax[2].size();
-        for (int k = 0; k < nrhs; ++k)
-          h->phi(ax[0].data(), (int)ax[0].size(), ax[1].data(), (int)ax[1].size(), ax[2].data(),
-                 (int)ax[2].size(), k, hphi.data() + (size_t)k * npts, h->phi_ctx);
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpyAsync(stage, hphi.data(), sizeof(double) * npts * nrhs,
-                              hipMemcpyHostToDevice, st));
-        launch_load_patch(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, jr, ldv, st);
+        const int nx = (int)ax[0].size(), ny = (int)ax[1].size(), nz = (int)ax[2].size();
+        const size_t npts = (size_t)nx * ny * nz;
+        if (d.src && h->phi) {
+          for (int k = 0; k < nrhs; ++k)
+            h->phi(ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
+                   hbuf.data() + (size_t)k * npts, h->phi_ctx);
+          RCCHK(upload_stage(npts * nrhs));
+          launch_load_patch(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, jr, ldv, st);
+        }
+        if (d.src && h->jvol) {
+          for (int k = 0; k < nrhs; ++k)
+            h->jvol(s, ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
+                    hbuf.data() + (size_t)k * 3 * npts, h->vec_ctx);
+          RCCHK(upload_stage(3 * npts * nrhs));
+          launch_load_vec(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, 1.0, jr, ldv, st);
+        }
+        if (want_m0 && h->sigma[s] > 0) {
+          for (int k = 0; k < nrhs; ++k)
+            h->ainit(s, ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
+                     hbuf.data() + (size_t)k * 3 * npts, h->vec_ctx);
+          RCCHK(upload_stage(3 * npts * nrhs));
+          launch_load_vec(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, h->sigma[s], h->d_m0,
+                          ldv, st);
+        }
+        HIPCHK(hipGetLastError());
       }
       HIPCHK(hipStreamSynchronize(st));
       h->release(stage);
@@ -1626,6 +1671,8 @@ static void solve_pre(tcf_problem* h, int k, int l, const double* rhs, const dou
     if (!h->cond_list.empty()) {
       launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
                     h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
+      // the initial value enters the first step as M a^(0) = int sigma A_0 . w
+      if (l == 0 && h->d_m0) launch_axpby(ldv, 1.0, h->d_m0 + (int64_t)k * ldv, 1.0, fM, st);
       timed(h, TCF_KG_CONDENSE, st, [&] {
         launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
                            h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);

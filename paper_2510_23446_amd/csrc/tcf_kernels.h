@@ -19,6 +19,9 @@ void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, i
 void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
                        const double* ptab, const double* phi, double* jr, int64_t ldv,
                        hipStream_t st);
+void launch_load_vec(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
+                     const double* ptab, const double* F, double scale, double* jr, int64_t ldv,
+                     hipStream_t st);
 template <class T>
 void launch_potrf(const FactorJob* jobs, int njobs, int k, T* A, int* fail, hipStream_t st);
 template <class T>

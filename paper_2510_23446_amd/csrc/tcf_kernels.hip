@@ -380,6 +380,55 @@ __global__ void k_load_patch(const DevPatch* P, int s, const int* r_loc, const d
   jr[(int64_t)k * ldv + pp.r_off + j] = val;
 }
 
+// Volume-form load of one patch (Sec. 2.2: the integral of F . w_e):
+// jr[k][r_off + j] += scale * sum over the load points of w F_dir(x) w_j,dir(x)
+// where edge j of direction dir is D in that direction and N in the other
+// two.  F holds the field at the load quadrature points (p_d + 3 per element
+// and direction), component fastest: F[k][c + 3 (ix + NX (iy + NY iz))].
+__global__ void k_load_vec(const DevPatch* P, int s, const int* r_loc, const double* ptab,
+                           const double* F, double scale, double* jr, int64_t ldv) {
+  const DevPatch& pp = P[s];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (j >= pp.n_r) return;
+  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+  const int id[3] = {u.a, u.b, u.c};
+  const double* T[3];
+  int stride[3], col[3], nq[3], t0[3], t1[3];
+  for (int a = 0; a < 3; ++a) {
+    const int m = pp.m[a], p = pp.deg[a];
+    const bool isD = a == u.dir;
+    T[a] = ptab + pp.ptab_off[a];
+    stride[a] = 3 * m + 1;
+    nq[a] = p + 3;
+    col[a] = isD ? 2 + 2 * m + id[a] : 2 + id[a];  // D_i or N_i column of the table
+    // elements where the factor is nonzero: D_i on [i-p+1, i], N_i on [i-p, i]
+    t0[a] = max(isD ? id[a] - p + 1 : id[a] - p, 0);
+    t1[a] = min(id[a], pp.nel[a] - 1);
+  }
+  const int NX = pp.nq_load[0], NY = pp.nq_load[1];
+  const double* f = F + (int64_t)k * 3 * NX * NY * pp.nq_load[2] + u.dir;
+  double val = 0.0;
+  for (int iz = t0[2] * nq[2]; iz < (t1[2] + 1) * nq[2]; ++iz) {
+    const double* oz = T[2] + (int64_t)iz * stride[2];
+    const double fz = oz[1] * oz[col[2]];
+    if (fz == 0.0) continue;
+    for (int iy = t0[1] * nq[1]; iy < (t1[1] + 1) * nq[1]; ++iy) {
+      const double* oy = T[1] + (int64_t)iy * stride[1];
+      const double fy = oy[1] * oy[col[1]];
+      if (fy == 0.0) continue;
+      const double* frow = f + 3 * (int64_t)NX * (iy + (int64_t)NY * iz);
+      double acc = 0.0;
+      for (int ix = t0[0] * nq[0]; ix < (t1[0] + 1) * nq[0]; ++ix) {
+        const double* ox = T[0] + (int64_t)ix * stride[0];
+        acc += ox[1] * ox[col[0]] * frow[3 * ix];
+      }
+      val += acc * fy * fz;
+    }
+  }
+  jr[(int64_t)k * ldv + pp.r_off + j] += scale * val;
+}
+
 // ===========================================================================
 // Batched partial Cholesky (lower, column-major, right-looking, 32 panels)
 // ===========================================================================
@@ -1368,6 +1417,14 @@ void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r
   if (n_r == 0) return;
   hipLaunchKernelGGL(k_load_patch, dim3((n_r + 127) / 128, nrhs), dim3(128), 0, st, P, s, r_loc,
                      ptab, phi, jr, ldv);
+}
+
+void launch_load_vec(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
+                     const double* ptab, const double* F, double scale, double* jr, int64_t ldv,
+                     hipStream_t st) {
+  if (n_r == 0) return;
+  hipLaunchKernelGGL(k_load_vec, dim3((n_r + 127) / 128, nrhs), dim3(128), 0, st, P, s, r_loc,
+                     ptab, F, scale, jr, ldv);
 }
 
 template <class T>

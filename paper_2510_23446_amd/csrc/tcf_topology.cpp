@@ -45,7 +45,7 @@ std::string validate_desc(const tcf_problem_desc& d) {
   if (d.n_steps > 0 && !d.amp) return "null amp";
   bool any_src = false;
   for (int64_t s = 0; s < np; ++s) any_src |= d.src_mask[s] != 0;
-  if (any_src && !d.phi) return "source mask set but phi is null";
+  if (any_src && !d.phi && !d.jvol) return "source mask set but neither phi nor jvol given";
   return "";
 }
 

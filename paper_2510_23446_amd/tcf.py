@@ -36,6 +36,10 @@ PHI_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_doubl
                      C.POINTER(C.c_double), C.c_int32, C.c_int32, C.POINTER(C.c_double),
                      C.c_void_p)
 
+VEC_FN = C.CFUNCTYPE(None, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                     C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                     C.POINTER(C.c_double), C.c_void_p)
+
 
 class tcf_problem_desc(C.Structure):
     _fields_ = [("np", C.c_int32 * 3),
@@ -50,7 +54,10 @@ class tcf_problem_desc(C.Structure):
                 ("phi_ctx", C.c_void_p),
                 ("amp", C.POINTER(C.c_double)),
                 ("dt", C.c_double),
-                ("n_steps", C.c_int32)]
+                ("n_steps", C.c_int32),
+                ("jvol", VEC_FN),
+                ("ainit", VEC_FN),
+                ("vec_ctx", C.c_void_p)]
 
 
 class tcf_options(C.Structure):
@@ -184,10 +191,29 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         o = np.ctypeslib.as_array(out, shape=(nx * ny * nz,))
         o[:] = v.ravel(order="F")
 
-    cb = PHI_FN(_cb)
-    keep.append(cb)
-    d.phi = cb
+    if phi is not None:
+        cb = PHI_FN(_cb)
+        keep.append(cb)
+        d.phi = cb
     d.phi_ctx = None
+
+    def _vec(fn):
+        def _cbv(s, xs, nx, ys, ny, zs, nz, k, out, ctx):
+            x = np.ctypeslib.as_array(xs, shape=(nx,))
+            y = np.ctypeslib.as_array(ys, shape=(ny,))
+            z = np.ctypeslib.as_array(zs, shape=(nz,))
+            v = np.asarray(fn(int(s), x, y, z, int(k)), dtype=np.float64).reshape(nx, ny, nz, 3)
+            o = np.ctypeslib.as_array(out, shape=(3 * nx * ny * nz,))
+            o[:] = v.transpose(2, 1, 0, 3).ravel()  # component fastest, then x, y, z
+        cbv = VEC_FN(_cbv)
+        keep.append(cbv)
+        return cbv
+
+    if getattr(prob, "jvol", None) is not None:
+        d.jvol = _vec(prob.jvol)
+    if getattr(prob, "ainit", None) is not None:
+        d.ainit = _vec(prob.ainit)
+    d.vec_ctx = None
     d.amp = _dptr(amp, C.c_double)
     d.dt = float(prob.dt)
     d.n_steps = int(amp.shape[1])

@@ -1,0 +1,79 @@
+"""The paper's experiment (Sec. 4) on the GPU path.
+
+* Parity: the fields of the manufactured problem match the oracle step by step.
+  This covers the volume source, the initial value entering the first step,
+  and both precisions.
+* Convergence: the errors of the GPU fields against the closed-form solution
+  fall like h^p.  The norms are the oracle's quadrature of the returned
+  global vectors.
+* The paper's timed configuration runs: p = 3, h = 2^-3 (8 elements per
+  patch and direction, 7260 patch unknowns) and n_t = 2^5.  Its wall time
+  and iteration counts are printed.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import errors
+from paper_2510_23446_amd import tcf
+from tests.test_gpu_parity import _run_and_compare
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,p,n_t", [(4, 2, 8), (3, 3, 4), (2, 1, 6)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32_ir", 1e-8)])
+def test_manufactured_parity(n, p, n_t, precision, tol):
+    prob = W.paper_manufactured(n=n, p=p, n_t=n_t, precision=precision)
+    _run_and_compare(prob, tol)
+
+
+def _gpu_errors(n, p, n_t, precision="fp64"):
+    prob = W.paper_manufactured(n=n, p=p, n_t=n_t, precision=precision)
+    h = tcf.Problem(prob)
+    t0 = time.perf_counter()
+    h.tcf_setup()
+    h.tcf_step(n_t - 1)
+    prev = h.tcf_get_field(0)
+    h.tcf_step(1)
+    now = h.tcf_get_field(0)
+    wall = time.perf_counter() - t0
+    st = h.tcf_get_stats()
+    cnt = h.counts()
+    h.tcf_destroy()
+    e = errors.field_errors(prob, now, prev, prob.extra["T"], prob.extra["B_exact"],
+                            prob.extra["E_exact"])
+    print(f"[mms] p={p} n={n} n_t={n_t} {precision}: eB {e['eB']:.3e} eE {e['eE']:.3e} "
+          f"mean PCG iters {st['total_pcg_iters'] / n_t:.1f} n_primal {cnt['n_primal']} "
+          f"n_lambda {cnt['n_lambda']} wall {wall:.3f}s", flush=True)
+    return e
+
+
+@pytest.mark.parametrize("p,ns,lo", [(2, (4, 8, 16), 3.5), (3, (2, 4, 8), 5.5)])
+def test_manufactured_convergence_in_h(p, ns, lo):
+    e = [_gpu_errors(n, p, 512) for n in ns]
+    for a, b in zip(e[:-1], e[1:]):
+        assert a["eB"] / b["eB"] >= lo, (a, b)
+
+
+def test_paper_timed_configuration():
+    prob = W.paper_manufactured(n=8, p=3, n_t=32)
+    h = tcf.Problem(prob)
+    cnt = h.counts()
+    t0 = time.perf_counter()
+    h.tcf_setup()
+    t1 = time.perf_counter()
+    h.tcf_step(31)
+    prev = h.tcf_get_field(0)
+    h.tcf_step(1)
+    now = h.tcf_get_field(0)
+    t2 = time.perf_counter()
+    st = h.tcf_get_stats()
+    h.tcf_destroy()
+    e = errors.field_errors(prob, now, prev, 1.0, prob.extra["B_exact"], prob.extra["E_exact"])
+    print(f"[mms] paper configuration p=3 h=2^-3 n_t=32: setup {t1 - t0:.3f}s steps {t2 - t1:.3f}s "
+          f"mean PCG iters {st['total_pcg_iters'] / 32:.1f} n_primal {cnt['n_primal']} "
+          f"eB {e['eB']:.3e} eE {e['eE']:.3e}", flush=True)
+    assert e["eB"] < 5e-3 and e["eE"] < 2e-2

@@ -29,8 +29,13 @@ def _problem_key(prob, steps):
         h.update(np.ascontiguousarray(a).tobytes())
     xs = np.linspace(0.05, 0.95, 4)
     for k in range(prob.n_rhs):
-        for v in prob.phi(xs, xs, xs, k):
-            h.update(np.ascontiguousarray(v, dtype=np.float64).tobytes())
+        if prob.phi is not None:
+            for v in prob.phi(xs, xs, xs, k):
+                h.update(np.ascontiguousarray(v, dtype=np.float64).tobytes())
+        for fn in (prob.jvol, prob.ainit):
+            if fn is not None:
+                for s in range(prob.n_patches):
+                    h.update(np.ascontiguousarray(fn(s, xs, xs, xs, k), dtype=np.float64).tobytes())
     h.update(repr((tuple(prob.np), prob.dt, steps)).encode())
     return h.hexdigest()
 

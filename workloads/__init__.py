@@ -38,7 +38,10 @@ class Problem:
     and has id s = i + P0 * (j + P1 * k).  Row r of direction d carries
     ``nel[d][r]`` uniform elements and H1 spline degree ``deg[d][r]``.
     The source is J_k(x, t) = g_k(t) curl(0, 0, phi_k(x)) on patches with
-    ``src_mask`` set; ``amp[k, l]`` is g_k(t_{l+1}).
+    ``src_mask`` set; ``amp[k, l]`` is g_k(t_{l+1}).  Optionally a volume
+    source ``jvol(s, xs, ys, zs, k) -> (nx, ny, nz, 3)`` adds g_k(t) times that
+    field on source patches, and ``ainit`` (same signature) gives the initial
+    potential A_k(x, 0) (used on conductor patches); ``phi`` may then be None.
     """
 
     name: str
@@ -59,6 +62,8 @@ class Problem:
     seed: Optional[int] = None
     note: str = ""
     extra: dict = field(default_factory=dict)
+    jvol: Optional[Callable] = None
+    ainit: Optional[Callable] = None
 
     @property
     def n_patches(self) -> int:
@@ -267,6 +272,108 @@ def subproblem(prob: Problem, lo=(0, 0, 0), P=(2, 2, 2)) -> Problem:
     q.nu = np.asarray(prob.nu)[ids]
     q.src_mask = np.asarray(prob.src_mask)[ids]
     return q
+
+
+# ---------------------------------------------------------------------------
+# The paper's manufactured solution (Sec. 4), homogenised by a lifting
+# ---------------------------------------------------------------------------
+def _trig(x, y, z):
+    return np.sin(x), np.cos(x), np.sin(y), np.cos(y), np.sin(z), np.cos(z)
+
+
+def _paper_field(x, y, z):
+    """The spatial factor F(x) of the Sec. 4 solution A = e^{-t} F, and its
+    Jacobian dF_i/dx_j; F = (sin x cos y cos z, -2 cos x sin y cos z,
+    cos x cos y sin z) is divergence-free and -Laplace(F) = 3 F."""
+    sx, cx, sy, cy, sz, cz = _trig(x, y, z)
+    F = np.stack([sx * cy * cz, -2.0 * cx * sy * cz, cx * cy * sz], axis=-1)
+    J = np.stack([
+        np.stack([cx * cy * cz, -sx * sy * cz, -sx * cy * sz], axis=-1),
+        np.stack([2.0 * sx * sy * cz, -2.0 * cx * cy * cz, 2.0 * cx * sy * sz], axis=-1),
+        np.stack([-sx * cy * sz, -cx * sy * sz, cx * cy * cz], axis=-1)], axis=-2)
+    return F, J
+
+
+def _bubble(x, y, z):
+    """b = 64 x(1-x) y(1-y) z(1-z) with its gradient and Hessian."""
+    X, Y, Z = 4 * x * (1 - x), 4 * y * (1 - y), 4 * z * (1 - z)
+    dX, dY, dZ = 4 * (1 - 2 * x), 4 * (1 - 2 * y), 4 * (1 - 2 * z)
+    d2 = -8.0
+    b = X * Y * Z
+    g = np.stack([dX * Y * Z, X * dY * Z, X * Y * dZ], axis=-1)
+    H = np.stack([
+        np.stack([d2 * Y * Z, dX * dY * Z, dX * Y * dZ], axis=-1),
+        np.stack([dX * dY * Z, X * d2 * Z, X * dY * dZ], axis=-1),
+        np.stack([dX * Y * dZ, X * dY * dZ, X * Y * d2], axis=-1)], axis=-2)
+    return b, g, H
+
+
+def manufactured_parts(x, y, z):
+    """U = b F (the homogenised potential's spatial factor), curl U and
+    curl curl U at points (broadcast arrays); returns three (..., 3) arrays.
+
+    curl(b F) = b curl F + grad b x F with curl F = (-3 cx sy sz, 0, 3 sx sy cz);
+    curl curl U = grad div U - Laplace U, div U = grad b . F, and
+    Laplace U_i = Laplace(b) F_i + 2 grad b . grad F_i - 3 b F_i.
+    """
+    x, y, z = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float), np.asarray(z, float))
+    F, JF = _paper_field(x, y, z)
+    b, g, H = _bubble(x, y, z)
+    sx, cx, sy, cy, sz, cz = _trig(x, y, z)
+    curlF = np.stack([-3.0 * cx * sy * sz, np.zeros_like(x), 3.0 * sx * sy * cz], axis=-1)
+    U = b[..., None] * F
+    curlU = b[..., None] * curlF + np.cross(g, F)
+    lap_b = H[..., 0, 0] + H[..., 1, 1] + H[..., 2, 2]
+    grad_div = np.einsum("...ij,...j->...i", H, F) + np.einsum("...j,...ji->...i", g, JF)
+    lap_U = lap_b[..., None] * F + 2.0 * np.einsum("...j,...ij->...i", g, JF) - 3.0 * b[..., None] * F
+    return U, curlU, grad_div - lap_U
+
+
+def paper_manufactured(n: int = 4, p: int = 2, n_t: int = 32, T: float = 1.0,
+                       precision: str = "fp64", pcg_rtol: float = 1e-10) -> Problem:
+    """The Sec. 4 experiment: (0,1)^3 cut at x = 0.5 into a conductor (x < 0.5,
+    sigma = 1) and an insulator (nu = 1 everywhere), exact potential
+    A = e^{-t} F(x), t in (0, T), n_t implicit Euler steps.
+
+    A has nonzero tangential trace on the boundary.  It is homogenised with
+    the lifting L = e^{-t} (1 - b) F, b = 64 x(1-x) y(1-y) z(1-z), which
+    carries the boundary data exactly: the unknown U = A - L = e^{-t} b F has
+    n x U = 0, source J = sigma dU/dt + curl nu curl U = e^{-t} (-sigma b F +
+    nu curl curl(b F)) in every patch, and initial value b F.  Because L is
+    known exactly, A_h - A = U_h - U: errors of U_h are errors of A_h.
+    ``n`` elements per direction per patch and H1 degree ``p`` (h = 1/n in
+    the patch parameter, as the paper counts it); g(t) = e^{-t}.
+    ``extra`` holds the closed forms B = curl U and E = -dU/dt for the errors.
+    """
+    P = (2, 1, 1)
+    sig = np.array([1.0, 0.0])
+    nu = np.array([1.0, 1.0])
+    dt = T / n_t
+
+    def jvol(s, xs, ys, zs, k):
+        X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+        U, _, ccU = manufactured_parts(X, Y, Z)
+        return -sig[s] * U + nu[s] * ccU
+
+    def ainit(s, xs, ys, zs, k):
+        X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+        return manufactured_parts(X, Y, Z)[0]
+
+    def B_exact(X, Y, Z, t):
+        return np.exp(-t) * manufactured_parts(X, Y, Z)[1]
+
+    def E_exact(X, Y, Z, t):
+        return np.exp(-t) * manufactured_parts(X, Y, Z)[0]
+
+    amp = np.exp(-dt * np.arange(1, n_t + 1))[None, :].astype(np.float64)
+    nel = [np.full(P[d], n, dtype=np.int32) for d in range(3)]
+    deg = [np.full(P[d], p, dtype=np.int32) for d in range(3)]
+    return Problem(
+        name=f"paper_cube2_p{p}_n{n}_nt{n_t}", np=P,
+        breaks=[np.array([0.0, 0.5, 1.0]), np.array([0.0, 1.0]), np.array([0.0, 1.0])],
+        nel=nel, deg=deg, sigma=sig, nu=nu, src_mask=np.ones(2, np.uint8), phi=None,
+        amp=amp, dt=dt, n_steps=n_t, pcg_rtol=pcg_rtol, precision=precision,
+        jvol=jvol, ainit=ainit, extra={"B_exact": B_exact, "E_exact": E_exact, "T": T})
 
 
 WORKLOADS = {
