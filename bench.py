@@ -42,6 +42,8 @@ def parse():
                          "extrapolated (2) multipliers; 0 = from zero")
     ap.add_argument("--no-warm-leg", action="store_true",
                     help="skip the extra legs (warm start, scaled preconditioner, both)")
+    ap.add_argument("--no-paper-leg", action="store_true",
+                    help="skip the end-to-end run of the paper's timed configuration")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--rate-x", type=float, default=2.0,
                     help="serving: arrival rate as a multiple of the solo FP64 capacity")
@@ -331,6 +333,33 @@ def main():
                   f"{legs[name]['pcg_iters_per_step']:.1f} iterations per step",
                   file=sys.stderr, flush=True)
 
+    # the paper's own timed configuration (Sec. 4: p = 3, h = 2^-3, i.e. 8
+    # elements per patch and direction and 7260 patch unknowns, n_t = 2^5 on
+    # its two-subdomain manufactured problem), end to end: create, setup and
+    # all 32 steps
+    paper = None
+    if not args.no_paper_leg:
+        import workloads as W
+        pp_prob = W.paper_manufactured(n=8, p=3, n_t=32)
+        tq0 = time.perf_counter()
+        pq = tcf.Problem(pp_prob)
+        tq1 = time.perf_counter()
+        pq.tcf_setup()
+        tq2 = time.perf_counter()
+        pq.tcf_step(32)
+        pq.tcf_sync()
+        tq3 = time.perf_counter()
+        sq = pq.tcf_get_stats()
+        pq.tcf_destroy()
+        paper = {"workload": pp_prob.name, "patch_unknowns": 7260, "create_s": tq1 - tq0,
+                 "setup_s": tq2 - tq1, "steps_s": tq3 - tq2, "total_s": tq3 - tq0,
+                 "pcg_iters_per_step": sq["total_pcg_iters"] / 32,
+                 "paper_total_s": 10.0,
+                 "paper_note": "about 10 s in total for this configuration, sequential "
+                               "Matlab on a laptop (Sec. 4): context, not a target"}
+        print(f"[bench] paper configuration end to end {paper['total_s']:.3f} s",
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] oracle baseline on a sub-sample", file=sys.stderr, flush=True)
@@ -373,6 +402,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": breakdown,
         "options_beyond_published": legs or None,
+        "paper_timed_configuration": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -77,3 +77,38 @@ def test_paper_timed_configuration():
           f"mean PCG iters {st['total_pcg_iters'] / 32:.1f} n_primal {cnt['n_primal']} "
           f"eB {e['eB']:.3e} eE {e['eE']:.3e}", flush=True)
     assert e["eB"] < 5e-3 and e["eE"] < 2e-2
+
+
+def _indicators(n, p, n_t):
+    prob = W.paper_manufactured(n=n, p=p, n_t=n_t)
+    h = tcf.Problem(prob)
+    cnt = h.counts()
+    h.tcf_setup()
+    h.tcf_step(n_t)
+    st = h.tcf_get_stats()
+    h.tcf_destroy()
+    return st["total_pcg_iters"] / n_t, cnt["n_primal"]
+
+
+def test_paper_scalability_indicators():
+    """Sec. 4's two scalability indicators on its experiment: the mean
+    number of PCG iterations per step (unscaled Dirichlet preconditioner)
+    against h and n_t, and the number of primal unknowns against h.  The
+    paper's plotted values are not available (parity unpinned); checked
+    here are the trends it states: both grow as h shrinks."""
+    rows = []
+    for p in (1, 2, 3):
+        its, prim = [], []
+        for n in (2, 4, 8, 16):
+            it, npr = _indicators(n, p, 32)
+            its.append(it)
+            prim.append(npr)
+            rows.append((p, n, 32, it, npr))
+        assert all(b > a for a, b in zip(prim[:-1], prim[1:])), prim
+        assert its[-1] > its[0], its
+    for n_t in (4, 8, 16, 64, 128):
+        it, npr = _indicators(8, 3, n_t)
+        rows.append((3, 8, n_t, it, npr))
+    for r in rows:
+        print(f"[mms-ind] p={r[0]} h=1/{r[1]} n_t={r[2]}: mean PCG iters {r[3]:.2f} n_primal {r[4]}",
+              flush=True)
