@@ -37,9 +37,10 @@ def parse():
                     choices=["uneven", "plain", "mixed", "largest", "multirhs", "serving"])
     ap.add_argument("--rhs-batch", type=int, default=0,
                     help="excitations per batched PCG (0: automatic, up to 4)")
-    ap.add_argument("--pcg-warm", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--pcg-warm", type=int, default=0, choices=[0, 1, 2, 3],
                     help="timed run: first solve of a step from the previous (1) or "
-                         "extrapolated (2) multipliers; 0 = from zero")
+                         "extrapolated (2) multipliers, or from the projection onto the "
+                         "span of earlier solutions (3); 0 = from zero")
     ap.add_argument("--no-warm-leg", action="store_true",
                     help="skip the extra legs (warm start, scaled preconditioner, both)")
     ap.add_argument("--no-paper-leg", action="store_true",
@@ -306,13 +307,18 @@ def main():
 
     # the same timed run with options beyond the published method: the first
     # solve of each step from the extrapolated multipliers of the last two
-    # steps, the stiffness-scaled Dirichlet preconditioner (the scaling the
-    # paper's outlook recommends), and both (same stopping test, same
-    # solution; the value above is the method as published)
+    # steps, or from the projection onto the span of earlier solutions (which
+    # deflates the initial error), the stiffness-scaled Dirichlet
+    # preconditioner (scaling and deflation are what the paper's outlook
+    # recommends), and combinations (same stopping test, same solution; the
+    # value above is the method as published)
     legs = {}
     if not args.no_warm_leg and args.pcg_warm == 0:
-        for name, kw in (("warm_start", {"pcg_warm": 2}), ("scaled_precond", {"precond_scaling": 1}),
-                         ("scaled_warm", {"pcg_warm": 2, "precond_scaling": 1})):
+        for name, kw in (("warm_start", {"pcg_warm": 2}),
+                         ("projection_start", {"pcg_warm": 3}),
+                         ("scaled_precond", {"precond_scaling": 1}),
+                         ("scaled_warm", {"pcg_warm": 2, "precond_scaling": 1}),
+                         ("scaled_projection", {"pcg_warm": 3, "precond_scaling": 1})):
             pw = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
                              rhs_batch=args.rhs_batch, **kw)
             pw.tcf_setup()

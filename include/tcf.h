@@ -134,8 +134,15 @@ typedef struct tcf_options {
                             /* min(n_rhs, 4)                                  */
   int32_t pcg_warm;         /* first solve of a step starts from: 0 lambda =  */
                             /* 0; 1 the previous step's lambda; 2 the linear  */
-                            /* extrapolation of the last two (the stopping    */
-                            /* test stays ||r|| <= rtol ||d||)                 */
+                            /* extrapolation of the last two; 3 the Galerkin  */
+                            /* projection onto the span of the excitation's   */
+                            /* newest 8 solutions (Fischer's projection for   */
+                            /* successive right-hand sides over a sliding     */
+                            /* window: it deflates the initial error; the     */
+                            /* F-orthonormal basis is rebuilt on the stream   */
+                            /* after each solve).  The stopping test stays    */
+                            /* ||r|| <= rtol ||d||.  3 keeps 4 x 8 n_lambda    */
+                            /* doubles per excitation                         */
   int32_t precond_scaling;  /* Dirichlet preconditioner: 0 unscaled (as      */
                             /* published), 1 stiffness-scaled: each copy of a */
                             /* dual unknown weighted by the other copy's share*/

@@ -180,6 +180,13 @@ struct tcf_problem {
   // excitation ([k][0] latest, [k][1] the one before) and how many are stored
   double* d_lamh = nullptr;
   std::vector<int> lamh_n;
+  // projection start (pcg_warm = 3): per excitation a ring of the newest
+  // kProjMax solutions H with F H beside them, and the F-orthonormal basis
+  // X, F X of their span rebuilt after every solve; work vectors and slots
+  static constexpr int kProjMax = 8;
+  double *d_ph = nullptr, *d_pfh = nullptr, *d_px = nullptr, *d_pfx = nullptr;
+  double *d_pv = nullptr, *d_pfv = nullptr, *d_pc = nullptr;
+  std::vector<int> proj_n, proj_head;
   bool warm_init = false;  // the next pcg_solve starts from the lambda columns as set
   // signed gathers of the tile path: Bhat's +-1 per b entry (F apply) and the
   // preconditioner's (the same, or D Bhat when scaled); weights of the two
@@ -475,7 +482,7 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   if (!(h->opt.pcg_rtol > 0)) { g_create_error = "pcg_rtol <= 0"; return TCF_EINVAL; }
   if (h->opt.check_every <= 0) h->opt.check_every = 8;
   if (h->opt.ir_maxit <= 0) h->opt.ir_maxit = 10;
-  if (h->opt.pcg_warm < 0 || h->opt.pcg_warm > 2) { g_create_error = "pcg_warm not in 0..2"; return TCF_EINVAL; }
+  if (h->opt.pcg_warm < 0 || h->opt.pcg_warm > 3) { g_create_error = "pcg_warm not in 0..3"; return TCF_EINVAL; }
   if (h->opt.precond_scaling < 0 || h->opt.precond_scaling > 1) {
     g_create_error = "precond_scaling not in 0..1";
     return TCF_EINVAL;
@@ -1168,9 +1175,21 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   h->npart = (nl + 255) / 256;
   RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4 * rb));
   RCCHK(h->alloc(&h->d_st, (size_t)rb + 1));  // per column, plus the all-done flag
-  if (h->opt.pcg_warm > 0 && h->use_tiles) {
+  if ((h->opt.pcg_warm == 1 || h->opt.pcg_warm == 2) && h->use_tiles) {
     RCCHK(h->alloc(&h->d_lamh, (size_t)nl * 2 * h->n_rhs));
     h->lamh_n.assign(h->n_rhs, 0);
+  }
+  if (h->opt.pcg_warm == 3 && h->use_tiles) {
+    const size_t kb = (size_t)tcf_problem::kProjMax * nl * h->n_rhs;
+    RCCHK(h->alloc(&h->d_ph, kb));
+    RCCHK(h->alloc(&h->d_pfh, kb));
+    RCCHK(h->alloc(&h->d_px, kb));
+    RCCHK(h->alloc(&h->d_pfx, kb));
+    RCCHK(h->alloc(&h->d_pv, (size_t)nl));
+    RCCHK(h->alloc(&h->d_pfv, (size_t)nl));
+    RCCHK(h->alloc(&h->d_pc, (size_t)tcf_problem::kProjMax + 4));
+    h->proj_n.assign(h->n_rhs, 0);
+    h->proj_head.assign(h->n_rhs, 0);
   }
   RCCHK(h->alloc(&h->d_field, (size_t)h->g.n_edges()));
   {
@@ -1765,6 +1784,54 @@ static int asm_norm2(tcf_problem* h, const double* x, int first_copy, int slot, 
 // (zero right-hand side) while the others continue.  The final assembled
 // residual ||f - W a|| / ||f|| is reported in the stats (largest over the
 // batch).  Per excitation: PCG iterations summed over its solves, sweeps.
+// Projection start (Fischer's method for successive right-hand sides, over
+// a sliding window): the newest kProjMax solutions of excitation k span X
+// (F-orthonormal, F X kept beside), and the first solve of a step starts
+// from the F-orthogonal projection of its solution onto that span,
+// lambda0 = X X^T d (X^T F X = I and F lambda = d).
+static void proj_start(tcf_problem* h, int k, int j, hipStream_t st) {
+  const int nl = h->n_lambda, nb = h->proj_n[k];
+  double* lam = h->d_lam + (int64_t)j * nl;
+  launch_zero(nl, lam, st);
+  if (nb == 0) return;
+  const double* X = h->d_px + (int64_t)k * tcf_problem::kProjMax * nl;
+  launch_rowdot(nl, nb, X, nl, h->d_d + (int64_t)j * nl, h->d_pc, nullptr, nullptr, 0, st);
+  launch_multiaxpy(nl, nb, h->d_pc, 1.0, X, nullptr, nl, lam, nullptr, st);
+}
+
+// After the solve: lambda (column j) and F lambda = d - r (the PCG's own
+// residual) enter the ring in place of the oldest pair, and the basis of the
+// window is rebuilt newest first: each raw pair gets two classical
+// Gram-Schmidt passes in the F inner product and is normalised; one that
+// lies in the span of the newer ones to the solver's accuracy is stored as
+// zero.  All on the stream, no host reads.
+static void proj_update(tcf_problem* h, int k, int j, hipStream_t st) {
+  const int nl = h->n_lambda, K = tcf_problem::kProjMax;
+  const int64_t off = (int64_t)k * K * nl;
+  double *H = h->d_ph + off, *FH = h->d_pfh + off, *X = h->d_px + off, *FX = h->d_pfx + off;
+  double *v = h->d_pv, *Fv = h->d_pfv, *c = h->d_pc;
+  const int slot = h->proj_head[k];
+  launch_copy_sub(nl, h->d_lam + (int64_t)j * nl, h->d_d + (int64_t)j * nl,
+                  h->d_r + (int64_t)j * nl, H + (int64_t)slot * nl, FH + (int64_t)slot * nl, st);
+  h->proj_head[k] = (slot + 1) % K;
+  const int cnt = std::min(h->proj_n[k] + 1, K);
+  for (int i = 0; i < cnt; ++i) {
+    const int src = ((slot - i) % K + K) % K;  // newest first
+    launch_copy_sub(nl, H + (int64_t)src * nl, FH + (int64_t)src * nl, nullptr, v, Fv, st);
+    // pass 1 (and lambda^T F lambda into c[K]), pass 2, then nu^2 into c[K+1]
+    launch_rowdot(nl, i, FX, nl, v, c, v, Fv, K, st);
+    launch_multiaxpy(nl, i, c, -1.0, X, FX, nl, v, Fv, st);
+    if (i > 0) {
+      launch_rowdot(nl, i, FX, nl, v, c, nullptr, nullptr, 0, st);
+      launch_multiaxpy(nl, i, c, -1.0, X, FX, nl, v, Fv, st);
+    }
+    launch_rowdot(nl, 0, nullptr, 0, nullptr, c, v, Fv, K + 1, st);
+    launch_store_dir(nl, c + K + 1, c + K, 1e-18, v, Fv, X + (int64_t)i * nl, FX + (int64_t)i * nl,
+                     st);
+  }
+  h->proj_n[k] = cnt;
+}
+
 template <class T>
 static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int* iters,
                       int* sweeps, bool* conv) {
@@ -1804,6 +1871,15 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   h->cur_sweep = 0;
   for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, l, nullptr, nullptr, j, st);
   zero_idle(all);
+  if (h->d_px) {
+    for (int j = 0; j < R; ++j) {
+      if (j < nc)
+        proj_start(h, k0 + j, j, st);
+      else
+        launch_zero(nl, h->d_lam + (int64_t)j * nl, st);
+    }
+    h->warm_init = true;
+  }
   if (h->d_lamh) {
     // lambda0 per column from the excitation's history (zero without one)
     for (int j = 0; j < R; ++j) {
@@ -1835,6 +1911,8 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
       h->lamh_n[k] = std::min(h->lamh_n[k] + 1, 2);
     }
   }
+  if (h->d_px)
+    for (int j = 0; j < nc; ++j) proj_update(h, k0 + j, j, st);
   for (int j = 0; j < nc; ++j) solve_post<T>(h, k0 + j, j, h->d_a + (int64_t)(k0 + j) * ldv, st);
   collect(all);
   for (int j = 0; j < nc; ++j) sweeps[j] = 1;
@@ -2034,6 +2112,8 @@ int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream) {
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   h->steps_done = (int)hdr[0];
   std::fill(h->lamh_n.begin(), h->lamh_n.end(), 0);  // warm-start history no longer applies
+  std::fill(h->proj_n.begin(), h->proj_n.end(), 0);
+  std::fill(h->proj_head.begin(), h->proj_head.end(), 0);
   return TCF_OK;
 }
 

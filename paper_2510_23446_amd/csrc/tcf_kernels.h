@@ -75,6 +75,14 @@ void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, in
 void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
                           const int* ib, const double* srcB, double sb, const double* extra,
                           double* out, const int* done, hipStream_t st);
+void launch_rowdot(int n, int nb, const double* rows, int64_t ld, const double* v, double* c,
+                   const double* a, const double* b, int extra, hipStream_t st);
+void launch_multiaxpy(int n, int nb, const double* c, double sgn, const double* X, const double* FX,
+                      int64_t ld, double* v, double* Fv, hipStream_t st);
+void launch_store_dir(int n, const double* nu2, const double* ref, double tol, const double* v,
+                      const double* Fv, double* x, double* fx, hipStream_t st);
+void launch_copy_sub(int n, const double* a, const double* b, const double* c, double* v,
+                     double* w, hipStream_t st);
 void launch_axpby(int64_t n, double alpha, const double* x, double beta, double* y,
                   hipStream_t st);
 void launch_sub_gather(int n, const int* ia, const double* a, const int* ib, const double* b,

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <algorithm>
 #include <climits>
 
 #include "tcf_device.h"
@@ -989,6 +990,68 @@ __device__ inline double block_sum256(double v, double* sh) {
   return r;  // valid in thread 0
 }
 
+// One block of 1024 threads per output: c[i] = sum_t rows[i ld + t] v[t] for
+// i < nb (block i), and with a != nullptr one more block writes
+// c[extra] = sum_t a[t] b[t].  Plain stores, no atomics.
+__global__ void __launch_bounds__(1024) k_rowdot(int n, int nb, const double* rows, int64_t ld,
+                                                 const double* v, double* c, const double* a,
+                                                 const double* b, int extra) {
+  __shared__ double sh[16];
+  const int i = blockIdx.x;
+  const double* x = i < nb ? rows + (int64_t)i * ld : a;
+  const double* y = i < nb ? v : b;
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < n; t += 1024) acc += x[t] * y[t];
+  acc = wave_sum(acc);
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += sh[w];
+    c[i < nb ? i : extra] = s;
+  }
+}
+
+// v[t] += sgn * sum_{i < nb} c[i] X[i ld + t]; with FX != nullptr also
+// Fv[t] += sgn * sum_{i < nb} c[i] FX[i ld + t]
+__global__ void __launch_bounds__(256) k_multiaxpy(int n, int nb, const double* c, double sgn,
+                                                   const double* X, const double* FX, int64_t ld,
+                                                   double* v, double* Fv) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    const double ci = c[i];
+    a += ci * X[(int64_t)i * ld + t];
+    if (FX) b += ci * FX[(int64_t)i * ld + t];
+  }
+  v[t] += sgn * a;
+  if (FX) Fv[t] += sgn * b;
+}
+
+// x = v / sqrt(nu2), fx = Fv / sqrt(nu2) when nu2 > tol * ref > 0, else zeros
+// (a direction that adds nothing beyond the span is stored as zero)
+__global__ void __launch_bounds__(256) k_store_dir(int n, const double* nu2, const double* ref,
+                                                   double tol, const double* v, const double* Fv,
+                                                   double* x, double* fx) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const double q = nu2[0], r = ref[0];
+  const bool keep = r > 0.0 && q > tol * r;
+  const double sc = keep ? 1.0 / sqrt(q) : 0.0;
+  x[t] = v[t] * sc;
+  fx[t] = Fv[t] * sc;
+}
+
+// v = a, w = b - c (copies of a ring slot, or F lambda = d - r)
+__global__ void __launch_bounds__(256) k_copy_sub(int n, const double* a, const double* b,
+                                                  const double* c, double* v, double* w) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  v[t] = a[t];
+  w[t] = c ? b[t] - c[t] : b[t];
+}
+
 // y[i] = scale * (w[pp[i]] - w[pm[i]]); partial[block] = sum y[i] * dotw[i]
 __global__ void __launch_bounds__(256) k_jump(int n, const int* pos_p, const int* pos_m,
                                               const double* w, double scale, double* y,
@@ -1606,6 +1669,29 @@ void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* sr
   if (n == 0) return;
   hipLaunchKernelGGL(k_coarse_gather, TCF_GRID(n, 256), dim3(256), 0, st, n, ptr, ia, srcA, sa, ib,
                      srcB, sb, extra, out, done);
+}
+void launch_rowdot(int n, int nb, const double* rows, int64_t ld, const double* v, double* c,
+                   const double* a, const double* b, int extra, hipStream_t st) {
+  const int nblk = nb + (a ? 1 : 0);
+  if (nblk == 0) return;
+  hipLaunchKernelGGL(k_rowdot, dim3(nblk), dim3(1024), 0, st, n, nb, rows, ld, v, c, a, b, extra);
+}
+void launch_multiaxpy(int n, int nb, const double* c, double sgn, const double* X, const double* FX,
+                      int64_t ld, double* v, double* Fv, hipStream_t st) {
+  if (n == 0 || nb == 0) return;
+  hipLaunchKernelGGL(k_multiaxpy, TCF_GRID(n, 256), dim3(256), 0, st, n, nb, c, sgn, X, FX, ld, v,
+                     Fv);
+}
+void launch_store_dir(int n, const double* nu2, const double* ref, double tol, const double* v,
+                      const double* Fv, double* x, double* fx, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_store_dir, TCF_GRID(n, 256), dim3(256), 0, st, n, nu2, ref, tol, v, Fv, x,
+                     fx);
+}
+void launch_copy_sub(int n, const double* a, const double* b, const double* c, double* v,
+                     double* w, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy_sub, TCF_GRID(n, 256), dim3(256), 0, st, n, a, b, c, v, w);
 }
 void launch_axpby(int64_t n, double alpha, const double* x, double beta, double* y,
                   hipStream_t st) {

@@ -205,10 +205,12 @@ def test_uneven_full_size_residual():
 
 
 # ---- warm starts (first solve of a step from the previous multipliers) -------
-@pytest.mark.parametrize("warm", [1, 2])
+@pytest.mark.parametrize("warm", [1, 2, 3])
 def test_warm_start_plain_all_steps(warm):
     """Same stopping test (||r|| <= rtol ||d||), so the field matches the oracle
-    to the same bar; the iteration count drops once there is a history."""
+    to the same bar; the iteration count drops once there is a history.
+    warm = 3 (projection onto the newest 8 solutions) slides its window from
+    step 9 of the 20 on."""
     prob = W.plain_fp64()
     worst, st = _run_and_compare(prob, 1e-9, pcg_warm=warm)
     cold = tcf.Problem(prob)
@@ -224,14 +226,17 @@ def test_warm_start_plain_all_steps(warm):
     assert sum(it_warm[3:]) < sum(it_cold[3:])
 
 
-def test_warm_start_uneven_reduced():
+@pytest.mark.parametrize("warm", [2, 3])
+def test_warm_start_uneven_reduced(warm):
     prob = W.uneven_fp64(seed=1, n_steps=3, P=(3, 3, 3))
-    _run_and_compare(prob, 1e-9, pcg_warm=2)
+    _run_and_compare(prob, 1e-9, pcg_warm=warm)
 
 
-def test_warm_start_fp32_ir_multirhs():
+@pytest.mark.parametrize("warm", [2, 3])
+def test_warm_start_fp32_ir_multirhs(warm):
+    """Batched columns (3 + 1 of 4 excitations), each with its own history."""
     prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=3, precision="fp32_ir")
-    worst, st = _run_and_compare(prob, 1e-8, pcg_warm=2, rhs_batch=3)
+    worst, st = _run_and_compare(prob, 1e-8, pcg_warm=warm, rhs_batch=3)
     assert st["nonconverged_steps"] == 0
 
 

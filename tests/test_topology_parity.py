@@ -108,7 +108,7 @@ def test_invalid_descriptions():
 
 def test_invalid_options():
     prob = W.plain_fp64()
-    for kw in ({"pcg_warm": 3}, {"pcg_warm": -1}, {"pcg_rtol": 0.0}, {"precision": 7},
+    for kw in ({"pcg_warm": 4}, {"pcg_warm": -1}, {"pcg_rtol": 0.0}, {"precision": 7},
                {"precond_scaling": 2}):
         with pytest.raises(tcf.TcfError) as e:
             tcf.Problem(prob, **kw)
