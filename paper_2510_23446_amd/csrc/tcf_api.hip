@@ -25,6 +25,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tcf.h"
@@ -745,9 +746,50 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
   int* dp;
   RCCHK(h->upload(&dj, jobs));
   RCCHK(h->upload(&dp, pre));
-  launch_trsm<T>(fwd, dj, dp, (int)jobs.size(), pre.back(), L, B, st);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
+  if constexpr (std::is_same<T, double>::value) {
+    // FP64 on the matrix cores: the inverses of the 32 x 32 diagonal blocks
+    // first, then the blocked solve
+    std::vector<int> dcnt;
+    for (auto& j : jobs) dcnt.push_back(j.n / TCF_NB);
+    std::vector<int> dpre = prefix_of(dcnt);
+    int* ddp;
+    double* D;
+    RCCHK(h->upload(&ddp, dpre));
+    RCCHK(h->alloc(&D, (size_t)dpre.back() * TCF_NB * TCF_NB));
+    launch_trsm_dinv(dj, ddp, (int)jobs.size(), dpre.back(), L, D, st);
+    // right-looking steps: per step the prefix over jobs of the tiles it
+    // updates (rows after kb forward, before kb backward)
+    const int nj = (int)jobs.size();
+    int steps = 0;
+    for (int c : dcnt) steps = std::max(steps, c);
+    std::vector<int> tab((size_t)steps * (nj + 1)), tot(steps);
+    for (int st_i = 0; st_i < steps; ++st_i) {
+      int acc = 0;
+      for (int x = 0; x < nj; ++x) {
+        tab[(size_t)st_i * (nj + 1) + x] = acc;
+        const int nb = dcnt[x], kb = fwd ? st_i : nb - 1 - st_i;
+        const int rows = (kb < 0 || kb >= nb) ? 0 : (fwd ? nb - kb - 1 : kb);
+        acc += rows * cnt[x];
+      }
+      tab[(size_t)st_i * (nj + 1) + nj] = acc;
+      tot[st_i] = acc;
+    }
+    int* dtab;
+    RCCHK(h->upload(&dtab, tab));
+    for (int st_i = 0; st_i < steps; ++st_i) {
+      launch_trsm_rl_diag(dj, dp, ddp, nj, pre.back(), st_i, fwd, D, B, st);
+      launch_trsm_rl_update(dj, dtab + (size_t)st_i * (nj + 1), nj, tot[st_i], st_i, fwd, L, B, st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(dtab);
+    h->release(D);
+    h->release(ddp);
+  } else {
+    launch_trsm<T>(fwd, dj, dp, (int)jobs.size(), pre.back(), L, B, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+  }
   h->release(dj);
   h->release(dp);
   return TCF_OK;

@@ -704,6 +704,164 @@ __global__ void k_trsm_fwd(const TrsmJob* jobs, const int* prefix, int njobs, co
   }
 }
 
+// ---------------------------------------------------------------------------
+// FP64 triangular solves on the matrix cores (v_mfma_f64_16x16x4).  Lane
+// layout of that instruction (checked by a probe on the device): lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; element e of the 4-wide
+// accumulator is C[l / 16 + 4 e][l % 16].
+// ---------------------------------------------------------------------------
+typedef double tcf_v4d __attribute__((ext_vector_type(4)));
+
+// Inverses of the 32 x 32 diagonal blocks of each job's lower factor:
+// D[(dprefix[job] + kb) * 1024 + r + 32 c] = (L_kb,kb)^-1 [r][c].  One block
+// of 64 threads per diagonal block; thread c < 32 forward-substitutes the
+// unit vector e_c.
+__global__ void __launch_bounds__(64) k_trsm_dinv(const TrsmJob* jobs, const int* dprefix,
+                                                  int njobs, const double* Lb, double* D) {
+  const int jx = find_job(dprefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int kb = blockIdx.x - dprefix[jx];
+  __shared__ double Ls[TCF_NB][TCF_NB + 1];
+  __shared__ double Ys[TCF_NB][TCF_NB + 1];
+  const double* L = Lb + jb.l_off;
+  const int64_t ldl = jb.ldl;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 64) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    Ls[r][c] = L[(jb.l_row0 + kb * TCF_NB + r) + (int64_t)(jb.l_row0 + kb * TCF_NB + c) * ldl];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < TCF_NB) {
+    for (int r = 0; r < TCF_NB; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      if (r >= c) {
+        for (int l = c; l < r; ++l) v -= Ls[r][l] * Ys[l][c];
+        v /= Ls[r][r];
+      }
+      Ys[r][c] = v;
+    }
+  }
+  __syncthreads();
+  double* out = D + (int64_t)blockIdx.x * TCF_NB * TCF_NB;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 64) {
+    const int r = idx % TCF_NB, cc = idx / TCF_NB;
+    out[idx] = Ys[r][cc];
+  }
+}
+
+// Solves L X = B (forward) or L^T X = B (backward) for a batch of jobs,
+// right-looking: step s handles row block kb of every job (kb = s forward,
+// nblk - 1 - s backward) in two launches, first
+// X_kb = D_kb B_kb (D_kb^T backward) for every column block of every job,
+// then B_j -= L_j,kb X_kb for the row blocks still to come (j > kb forward;
+// j < kb backward with L_kb,j^T), every tile of every job in parallel.  With
+// identity right-hand sides (column c0 + q of the identity, tri > 0) the
+// blocks that stay zero are skipped.
+__device__ inline int rl_kb(const TrsmJob& jb, int s, int fwd) {
+  const int nblk = jb.n / TCF_NB;
+  return fwd ? s : nblk - 1 - s;
+}
+__device__ inline bool rl_zero_block(const TrsmJob& jb, int kb, int c0, int fwd) {
+  if (c0 + 64 > jb.tri) return false;
+  if (fwd) return kb < c0 / TCF_NB;
+  return kb > (c0 + 63) / TCF_NB;
+}
+
+__global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix,
+                                                      const int* dprefix, int njobs, int s,
+                                                      int fwd, const double* D, double* Bb) {
+  const int jx = find_job(cprefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int nblk = jb.n / TCF_NB;
+  const int kb = rl_kb(jb, s, fwd);
+  const int c0 = (blockIdx.x - cprefix[jx]) * 64;
+  if (kb < 0 || kb >= nblk || rl_zero_block(jb, kb, c0, fwd)) return;
+  __shared__ double Ls[TCF_NB][TCF_NB + 1];
+  __shared__ double Xs[TCF_NB][64 + 1];
+  double* B = Bb + jb.b_off;
+  const int64_t ldb = jb.ldb;
+  const double* Dk = D + ((int64_t)dprefix[jx] + kb) * TCF_NB * TCF_NB;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256) Ls[idx % TCF_NB][idx / TCF_NB] = Dk[idx];
+  for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += 256) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : 0.0;
+  }
+  __syncthreads();
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  tcf_v4d x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
+    const double bv = Xs[k0 + lk][16 * w + li];
+    const double a0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
+    const double a1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
+    x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, x0, 0, 0, 0);
+    x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, x1, 0, 0, 0);
+  }
+  const int col = c0 + 16 * w + li;
+  if (col < jb.ncols) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = x0[e];
+      B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = x1[e];
+    }
+  }
+}
+
+// tprefix: row s of a (steps x (njobs + 1)) table, the prefix over jobs of
+// the tiles that step s updates (rows j > kb, or j < kb, times column blocks)
+__global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, const int* tprefix,
+                                                        int njobs, int s, int fwd,
+                                                        const double* Lb, double* Bb) {
+  const int jx = find_job(tprefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int ncb = (jb.ncols + 63) / 64;
+  const int t = blockIdx.x - tprefix[jx];
+  const int kb = rl_kb(jb, s, fwd);
+  const int j = fwd ? kb + 1 + t / ncb : t / ncb;
+  const int c0 = (t % ncb) * 64;
+  if (rl_zero_block(jb, kb, c0, fwd)) return;
+  __shared__ double Ls[TCF_NB][TCF_NB + 1];
+  __shared__ double Xs[TCF_NB][64 + 1];
+  const double* L = Lb + jb.l_off;
+  double* B = Bb + jb.b_off;
+  const int64_t ldl = jb.ldl, ldb = jb.ldb;
+  // L tile: forward L_j,kb (A[i][k] = Ls[i][k]); backward L_kb,j (A = Ls^T)
+  const int lr = fwd ? j : kb, lc = fwd ? kb : j;
+  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    Ls[r][c] = L[(jb.l_row0 + lr * TCF_NB + r) + (int64_t)(jb.l_row0 + lc * TCF_NB + c) * ldl];
+  }
+  for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += 256) {
+    const int r = idx % TCF_NB, c = idx / TCF_NB;
+    Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : 0.0;
+  }
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int col = c0 + 16 * w + li;
+  const bool colok = col < jb.ncols;
+  tcf_v4d a0, a1;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    a0[e] = colok ? B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
+    a1[e] = colok ? B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
+    const double bv = Xs[k0 + lk][16 * w + li];
+    const double v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
+    const double v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
+    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v0, bv, a0, 0, 0, 0);
+    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v1, bv, a1, 0, 0, 0);
+  }
+  if (colok) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = a0[e];
+      B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = a1[e];
+    }
+  }
+}
+
 // Solve L^T X = B (backward substitution with the transposed lower block).
 template <class T>
 __global__ void k_trsm_bwd(const TrsmJob* jobs, const int* prefix, int njobs, const T* Lb, T* Bb) {
@@ -1534,6 +1692,23 @@ void launch_coarse_add(const DevPatch* P, int s, int n_p, const int* p_rank, con
 void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st) {
   if (n <= n0) return;
   hipLaunchKernelGGL(k_set_identity_pad, TCF_GRID(n - n0, 256), dim3(256), 0, st, M, ld, n0, n);
+}
+void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total,
+                      const double* L, double* D, hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_trsm_dinv, dim3(total), dim3(64), 0, st, jobs, dprefix, njobs, L, D);
+}
+void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
+                         int total, int s, int fwd, const double* D, double* B, hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_trsm_rl_diag, dim3(total), dim3(256), 0, st, jobs, cprefix, dprefix, njobs,
+                     s, fwd, D, B);
+}
+void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
+                           int fwd, const double* L, double* B, hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_trsm_rl_update, dim3(total), dim3(256), 0, st, jobs, tprefix, njobs, s, fwd,
+                     L, B);
 }
 template <class T>
 void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int total,
