@@ -691,47 +691,66 @@ int tcf_profile_get(const tcf_problem* h, int32_t g, double* total_ms, int64_t* 
 template <class T>
 static int run_factor_phase(tcf_problem* h, const std::vector<FactorJob>& jobs, T* A,
                             hipStream_t st) {
+  // Blocked right-looking Cholesky of columns [c_begin, c_end) of every job:
+  // per panel of TCF_NB columns the diagonal block, the rows below it, and
+  // the update of the rest of its super-panel (SP panels); after the last
+  // panel of a super-panel one update of the whole trailing matrix with all
+  // of the super-panel's columns.
   if (jobs.empty()) return TCF_OK;
-  const int nj = (int)jobs.size();
+  const int nj = (int)jobs.size(), SP = syrk_super_panel();
   int steps = 0;
   for (auto& j : jobs) steps = std::max(steps, (j.c_end - j.c_begin) / TCF_NB);
-  std::vector<int> trsm_pre((size_t)steps * (nj + 1)), syrk_pre((size_t)steps * (nj + 1));
-  std::vector<int> trsm_tot(steps), syrk_tot(steps);
+  std::vector<int> trsm_pre((size_t)steps * (nj + 1)), loc_pre((size_t)steps * (nj + 1)),
+      wide_pre((size_t)steps * (nj + 1));
+  std::vector<int> trsm_tot(steps), loc_tot(steps), wide_tot(steps);
   for (int k = 0; k < steps; ++k) {
     int* tp = &trsm_pre[(size_t)k * (nj + 1)];
-    int* sp = &syrk_pre[(size_t)k * (nj + 1)];
-    tp[0] = sp[0] = 0;
+    int* lp = &loc_pre[(size_t)k * (nj + 1)];
+    int* wp = &wide_pre[(size_t)k * (nj + 1)];
+    tp[0] = lp[0] = wp[0] = 0;
     for (int j = 0; j < nj; ++j) {
       const FactorJob& jb = jobs[j];
       const int col0 = jb.c_begin + TCF_NB * k;
-      int nt = 0, ns = 0;
+      const int p0 = jb.c_begin + TCF_NB * SP * (k / SP);
+      const int p_end = std::min(p0 + TCF_NB * SP, jb.c_end);
+      int nt = 0, nl = 0, nw = 0;
       if (col0 < jb.c_end) {
-        const int below = jb.n - (col0 + TCF_NB);
-        nt = (below + 63) / 64;
-        const int T_ = (below + 63) / 64;
-        ns = T_ * (T_ + 1) / 2;
+        const int trail0 = col0 + TCF_NB;
+        nt = (jb.n - trail0 + 63) / 64;
+        if (p_end > trail0) nl = nt * ((p_end - trail0 + 63) / 64);
+      }
+      // the wide update once the job's super-panel is complete, i.e. after
+      // its last panel (the one ending at p_end)
+      if (col0 < jb.c_end && col0 + TCF_NB == p_end) {
+        const int T_ = (jb.n - p_end + 63) / 64;
+        nw = T_ * (T_ + 1) / 2;
       }
       tp[j + 1] = tp[j] + nt;
-      sp[j + 1] = sp[j] + ns;
+      lp[j + 1] = lp[j] + nl;
+      wp[j + 1] = wp[j] + nw;
     }
     trsm_tot[k] = tp[nj];
-    syrk_tot[k] = sp[nj];
+    loc_tot[k] = lp[nj];
+    wide_tot[k] = wp[nj];
   }
   FactorJob* dj;
-  int *dtp, *dsp;
+  int *dtp, *dlp, *dwp;
   RCCHK(h->upload(&dj, jobs));
   RCCHK(h->upload(&dtp, trsm_pre));
-  RCCHK(h->upload(&dsp, syrk_pre));
+  RCCHK(h->upload(&dlp, loc_pre));
+  RCCHK(h->upload(&dwp, wide_pre));
   for (int k = 0; k < steps; ++k) {
     launch_potrf<T>(dj, nj, k, A, h->d_fail, st);
     launch_trsm_panel<T>(dj, dtp + (size_t)k * (nj + 1), nj, trsm_tot[k], k, A, st);
-    launch_syrk<T>(dj, dsp + (size_t)k * (nj + 1), nj, syrk_tot[k], k, A, st);
+    launch_syrk<T>(dj, dlp + (size_t)k * (nj + 1), nj, loc_tot[k], k, 0, A, st);
+    launch_syrk<T>(dj, dwp + (size_t)k * (nj + 1), nj, wide_tot[k], k, 1, A, st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   h->release(dj);
   h->release(dtp);
-  h->release(dsp);
+  h->release(dlp);
+  h->release(dwp);
   return TCF_OK;
 }
 
@@ -757,18 +776,19 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
     RCCHK(h->upload(&ddp, dpre));
     RCCHK(h->alloc(&D, (size_t)dpre.back() * TCF_NB * TCF_NB));
     launch_trsm_dinv(dj, ddp, (int)jobs.size(), dpre.back(), L, D, st);
-    // right-looking steps: per step the prefix over jobs of the tiles it
-    // updates (rows after kb forward, before kb backward)
-    const int nj = (int)jobs.size();
+    // right-looking steps over panels of P row blocks: per step the prefix
+    // over jobs of the tiles it updates (row blocks after the panel forward,
+    // before it backward)
+    const int nj = (int)jobs.size(), P = trsm_rl_panel();
     int steps = 0;
-    for (int c : dcnt) steps = std::max(steps, c);
+    for (int c : dcnt) steps = std::max(steps, (c + P - 1) / P);
     std::vector<int> tab((size_t)steps * (nj + 1)), tot(steps);
     for (int st_i = 0; st_i < steps; ++st_i) {
       int acc = 0;
       for (int x = 0; x < nj; ++x) {
         tab[(size_t)st_i * (nj + 1) + x] = acc;
-        const int nb = dcnt[x], kb = fwd ? st_i : nb - 1 - st_i;
-        const int rows = (kb < 0 || kb >= nb) ? 0 : (fwd ? nb - kb - 1 : kb);
+        const int nb = dcnt[x];
+        const int rows = fwd ? std::max(0, nb - P * (st_i + 1)) : std::max(0, nb - P * (st_i + 1));
         acc += rows * cnt[x];
       }
       tab[(size_t)st_i * (nj + 1) + nj] = acc;
@@ -777,7 +797,7 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
     int* dtab;
     RCCHK(h->upload(&dtab, tab));
     for (int st_i = 0; st_i < steps; ++st_i) {
-      launch_trsm_rl_diag(dj, dp, ddp, nj, pre.back(), st_i, fwd, D, B, st);
+      launch_trsm_rl_diag(dj, dp, ddp, nj, pre.back(), st_i, fwd, L, D, B, st);
       launch_trsm_rl_update(dj, dtab + (size_t)st_i * (nj + 1), nj, tot[st_i], st_i, fwd, L, B, st);
     }
     HIPCHK(hipGetLastError());
@@ -990,9 +1010,9 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   launch_assemble<T>(h->dP, d_colpre, np, colpre.back(), h->d_rloc, h->d_tabs, h->dt, A, st);
   HIPCHK(hipGetLastError());
 
-  // source loads, one patch at a time through a staging buffer: the curl
-  // form (phi) and/or the volume form (jvol) on source patches, and the
-  // initial load int sigma A(x,0) . w (ainit) on conductor patches
+  // source loads: the curl form (phi) and/or the volume form (jvol) on
+  // source patches, and the initial load int sigma A(x,0) . w (ainit) on
+  // conductor patches
   double* jr;
   RCCHK(h->alloc(&jr, (size_t)ldv * nrhs));
   HIPCHK(hipMemsetAsync(jr, 0, sizeof(double) * ldv * nrhs, st));
@@ -1002,68 +1022,89 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     HIPCHK(hipMemsetAsync(h->d_m0, 0, sizeof(double) * ldv * nrhs, st));
   }
   {
-    auto uses = [&](int s) {
-      const DevPatch& d = h->hp[s];
-      if (d.n_r == 0) return false;
-      return (d.src && (h->phi || h->jvol)) || (want_m0 && h->sigma[s] > 0);
-    };
-    size_t maxpts = 0;
-    for (int s = 0; s < np; ++s)
-      if (uses(s))
-        maxpts = std::max(maxpts, (size_t)h->hp[s].nq_load[0] * h->hp[s].nq_load[1] * h->hp[s].nq_load[2]);
-    if (maxpts > 0) {
-      double* stage;
-      RCCHK(h->alloc(&stage, 3 * maxpts * nrhs));
-      std::vector<double> hbuf(3 * maxpts * nrhs);
-      // the previous launch has read the stage before it is overwritten, and
-      // the copy has left the (pageable) host buffer before the next
-      // callback refills it
-      auto upload_stage = [&](size_t n) -> int {
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpyAsync(stage, hbuf.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return TCF_OK;
-      };
-      for (int s = 0; s < np; ++s) {
-        if (!uses(s)) continue;
-        const DevPatch& d = h->hp[s];
-        std::vector<double> ax[3];
-        for (int a = 0; a < 3; ++a) {
-          const int nq = d.deg[a] + 3;
-          const int o = nq * (nq - 1) / 2;
-          const double hh = (d.hi[a] - d.lo[a]) / d.nel[a];
-          for (int t = 0; t < d.nel[a]; ++t)
-            for (int q = 0; q < nq; ++q) ax[a].push_back((hh * t + d.lo[a]) + 0.5 * hh * (h->gx[o + q] + 1.0));
-        }
-        const int nx = (int)ax[0].size(), ny = (int)ax[1].size(), nz = (int)ax[2].size();
-        const size_t npts = (size_t)nx * ny * nz;
-        if (d.src && h->phi) {
-          for (int k = 0; k < nrhs; ++k)
-            h->phi(ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
-                   hbuf.data() + (size_t)k * npts, h->phi_ctx);
-          RCCHK(upload_stage(npts * nrhs));
-          launch_load_patch(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, jr, ldv, st);
-        }
-        if (d.src && h->jvol) {
-          for (int k = 0; k < nrhs; ++k)
-            h->jvol(s, ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
-                    hbuf.data() + (size_t)k * 3 * npts, h->vec_ctx);
-          RCCHK(upload_stage(3 * npts * nrhs));
-          launch_load_vec(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, 1.0, jr, ldv, st);
-        }
-        if (want_m0 && h->sigma[s] > 0) {
-          for (int k = 0; k < nrhs; ++k)
-            h->ainit(s, ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k,
-                     hbuf.data() + (size_t)k * 3 * npts, h->vec_ctx);
-          RCCHK(upload_stage(3 * npts * nrhs));
-          launch_load_vec(h->dP, s, d.n_r, nrhs, h->d_rloc, h->d_ptab, stage, h->sigma[s], h->d_m0,
-                          ldv, st);
-        }
-        HIPCHK(hipGetLastError());
+    // Three passes (curl-form source, volume source, initial value), each
+    // over its patches in chunks: the callbacks fill a host buffer with the
+    // values at every patch's load points until the chunk budget is
+    // reached, one upload, one launch over every kept edge of the chunk.
+    const size_t budget = (size_t)16 << 20;  // doubles per chunk
+    double* stage = nullptr;
+    size_t stage_cap = 0;
+    std::vector<double> hbuf;
+    auto points = [&](const DevPatch& d, std::vector<double>* ax) {
+      for (int a = 0; a < 3; ++a) {
+        const int nq = d.deg[a] + 3;
+        const int o = nq * (nq - 1) / 2;
+        const double hh = (d.hi[a] - d.lo[a]) / d.nel[a];
+        ax[a].clear();
+        for (int t = 0; t < d.nel[a]; ++t)
+          for (int q = 0; q < nq; ++q) ax[a].push_back((hh * t + d.lo[a]) + 0.5 * hh * (h->gx[o + q] + 1.0));
       }
-      HIPCHK(hipStreamSynchronize(st));
-      h->release(stage);
+    };
+    for (int kind = 0; kind < 3; ++kind) {
+      const int ncomp = kind == 0 ? 1 : 3;
+      double* out = kind == 2 ? h->d_m0 : jr;
+      std::vector<int> pl;
+      for (int s = 0; s < np; ++s) {
+        const DevPatch& d = h->hp[s];
+        if (d.n_r == 0) continue;
+        if (kind == 0 && d.src && h->phi) pl.push_back(s);
+        if (kind == 1 && d.src && h->jvol) pl.push_back(s);
+        if (kind == 2 && want_m0 && h->sigma[s] > 0) pl.push_back(s);
+      }
+      size_t next = 0;
+      while (next < pl.size()) {
+        std::vector<LoadJob> jobs;
+        std::vector<int> cnt;
+        size_t used = 0;
+        while (next < pl.size()) {
+          const DevPatch& d = h->hp[pl[next]];
+          const size_t npts = (size_t)d.nq_load[0] * d.nq_load[1] * d.nq_load[2];
+          const size_t need = npts * ncomp * nrhs;
+          if (!jobs.empty() && used + need > budget) break;
+          jobs.push_back(LoadJob{(int64_t)used, pl[next], 0, kind == 2 ? h->sigma[pl[next]] : 1.0});
+          cnt.push_back((d.n_r + 127) / 128);
+          used += need;
+          ++next;
+        }
+        if (hbuf.size() < used) hbuf.resize(used);
+        std::vector<double> ax[3];
+        for (const LoadJob& jb : jobs) {
+          const DevPatch& d = h->hp[jb.s];
+          points(d, ax);
+          const int nx = (int)ax[0].size(), ny = (int)ax[1].size(), nz = (int)ax[2].size();
+          const size_t npts = (size_t)nx * ny * nz;
+          for (int k = 0; k < nrhs; ++k) {
+            double* o = hbuf.data() + jb.f_off + (size_t)k * ncomp * npts;
+            if (kind == 0)
+              h->phi(ax[0].data(), nx, ax[1].data(), ny, ax[2].data(), nz, k, o, h->phi_ctx);
+            else
+              (kind == 1 ? h->jvol : h->ainit)(jb.s, ax[0].data(), nx, ax[1].data(), ny,
+                                                ax[2].data(), nz, k, o, h->vec_ctx);
+          }
+        }
+        HIPCHK(hipStreamSynchronize(st));  // the previous chunk's launch has read the stage
+        if (stage_cap < used) {
+          if (stage) h->release(stage);
+          RCCHK(h->alloc(&stage, used));
+          stage_cap = used;
+        }
+        // the copy leaves the pageable host buffer before the next chunk refills it
+        HIPCHK(hipMemcpyAsync(stage, hbuf.data(), sizeof(double) * used, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        auto pre = prefix_of(cnt);
+        LoadJob* dj;
+        int* dp;
+        RCCHK(h->upload(&dj, jobs));
+        RCCHK(h->upload(&dp, pre));
+        launch_load_batch(h->dP, dj, dp, (int)jobs.size(), pre.back(), nrhs, h->d_rloc, h->d_ptab,
+                          stage, kind == 0 ? 0 : 1, out, ldv, st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        h->release(dj);
+        h->release(dp);
+      }
     }
+    if (stage) h->release(stage);
   }
 
   // factor the interior columns, keep S_bb, factor the dual columns

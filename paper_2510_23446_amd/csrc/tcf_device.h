@@ -30,6 +30,14 @@ struct DevPatch {
 };
 
 // A block of columns [c_begin, c_end) of one dense SPD matrix to factor.
+// One patch of a batched source load: field values at F + f_off, result
+// scaled by scale (1, or sigma for the initial-value load)
+struct LoadJob {
+  int64_t f_off;
+  int s, pad;
+  double scale;
+};
+
 struct FactorJob {
   int64_t off;  // matrix offset (elements)
   int ld;       // leading dimension == padded order

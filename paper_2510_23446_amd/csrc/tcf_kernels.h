@@ -16,20 +16,18 @@ void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, i
                    int total_rows, int nrhs, const int* r_loc, const int* loc2r,
                    const double* tabs, double dt, int mass_only, const double* x, double* y,
                    int64_t ldv, hipStream_t st);
-void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
-                       const double* ptab, const double* phi, double* jr, int64_t ldv,
-                       hipStream_t st);
-void launch_load_vec(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
-                     const double* ptab, const double* F, double scale, double* jr, int64_t ldv,
-                     hipStream_t st);
+void launch_load_batch(const DevPatch* P, const LoadJob* jobs, const int* prefix, int njobs,
+                       int total, int nrhs, const int* r_loc, const double* ptab, const double* F,
+                       int vec, double* out, int64_t ldv, hipStream_t st);
 template <class T>
 void launch_potrf(const FactorJob* jobs, int njobs, int k, T* A, int* fail, hipStream_t st);
 template <class T>
 void launch_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
                        hipStream_t st);
 template <class T>
-void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
-                 hipStream_t st);
+void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, int mode,
+                 T* A, hipStream_t st);
+int syrk_super_panel();
 template <class T>
 void launch_copy_sbb(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* S,
                      hipStream_t st);
@@ -45,8 +43,10 @@ void launch_coarse_add(const DevPatch* P, int s, int n_p, const int* p_rank, con
 void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st);
 void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total,
                       const double* L, double* D, hipStream_t st);
+int trsm_rl_panel();
 void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
-                         int total, int s, int fwd, const double* D, double* B, hipStream_t st);
+                         int total, int s, int fwd, const double* L, const double* D, double* B,
+                         hipStream_t st);
 void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
                            int fwd, const double* L, double* B, hipStream_t st);
 template <class T>

@@ -329,13 +329,12 @@ __global__ void k_wapply(const DevPatch* P, const int* plist, const int* row_pre
 // (curl w)_z = -D_a N'_b N_c (x-edges), N'_a D_b N_c (y-edges), 0 (z-edges).
 // phi holds the callback values on the patch's tensor grid of load points,
 // one block of nx*ny*nz per excitation.
-__global__ void k_load_patch(const DevPatch* P, int s, const int* r_loc, const double* ptab,
-                             const double* phi, double* jr, int64_t ldv) {
-  const DevPatch& pp = P[s];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (j >= pp.n_r) return;
-  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+// Curl-form load of local kept edge j of a patch: the integral of
+// phi (curl w_j)_z over the patch on the load points, phi given there
+// (x fastest).  (curl w)_z is -D_a N'_b N_c for x-edges, N'_a D_b N_c for
+// y-edges and 0 for z-edges.
+__device__ double load_curl_edge(const DevPatch& pp, const EdgeCode& u, const double* ptab,
+                                 const double* ph) {
   double val = 0.0;
   if (u.dir != 2) {
     const int mx = pp.m[0], my = pp.m[1], mz = pp.m[2];
@@ -346,7 +345,7 @@ __global__ void k_load_patch(const DevPatch* P, int s, const int* r_loc, const d
     const int NX = pp.nq_load[0], NY = pp.nq_load[1];
     const int qx = pp.deg[0] + 3, qy = pp.deg[1] + 3, qz = pp.deg[2] + 3;
     const int px = pp.deg[0], py = pp.deg[1], pz = pp.deg[2];
-    const double* ph = phi + (int64_t)k * NX * NY * pp.nq_load[2];
+    (void)mz;
     // element ranges where each factor is active
     int tx0, tx1, ty0, ty1;
     if (u.dir == 0) {  // D_a(x): t in [a-p+1, a];  N'_b(y): t in [b-p, b]
@@ -378,21 +377,16 @@ __global__ void k_load_patch(const DevPatch* P, int s, const int* r_loc, const d
     }
     if (u.dir == 0) val = -val;
   }
-  jr[(int64_t)k * ldv + pp.r_off + j] = val;
+  return val;
 }
 
-// Volume-form load of one patch (Sec. 2.2: the integral of F . w_e):
-// jr[k][r_off + j] += scale * sum over the load points of w F_dir(x) w_j,dir(x)
-// where edge j of direction dir is D in that direction and N in the other
-// two.  F holds the field at the load quadrature points (p_d + 3 per element
-// and direction), component fastest: F[k][c + 3 (ix + NX (iy + NY iz))].
-__global__ void k_load_vec(const DevPatch* P, int s, const int* r_loc, const double* ptab,
-                           const double* F, double scale, double* jr, int64_t ldv) {
-  const DevPatch& pp = P[s];
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  if (j >= pp.n_r) return;
-  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+// Volume-form load of local kept edge j of a patch (Sec. 2.2: the integral
+// of F . w_j): sum over the load points of w F_dir(x) w_j,dir(x), where an
+// edge of direction dir is D in that direction and N in the other two.  F
+// holds the field at the load points, component fastest:
+// F[c + 3 (ix + NX (iy + NY iz))].
+__device__ double load_vec_edge(const DevPatch& pp, const EdgeCode& u, const double* ptab,
+                                const double* F) {
   const int id[3] = {u.a, u.b, u.c};
   const double* T[3];
   int stride[3], col[3], nq[3], t0[3], t1[3];
@@ -408,7 +402,7 @@ __global__ void k_load_vec(const DevPatch* P, int s, const int* r_loc, const dou
     t1[a] = min(id[a], pp.nel[a] - 1);
   }
   const int NX = pp.nq_load[0], NY = pp.nq_load[1];
-  const double* f = F + (int64_t)k * 3 * NX * NY * pp.nq_load[2] + u.dir;
+  const double* f = F + u.dir;
   double val = 0.0;
   for (int iz = t0[2] * nq[2]; iz < (t1[2] + 1) * nq[2]; ++iz) {
     const double* oz = T[2] + (int64_t)iz * stride[2];
@@ -427,7 +421,28 @@ __global__ void k_load_vec(const DevPatch* P, int s, const int* r_loc, const dou
       val += acc * fy * fz;
     }
   }
-  jr[(int64_t)k * ldv + pp.r_off + j] += scale * val;
+  return val;
+}
+
+// Source loads of a batch of patches in one launch: job x covers patch
+// jobs[x].s with its field values at F + jobs[x].f_off (per excitation k,
+// F_k follows at k times the patch's point count, times 3 for vector
+// fields); out[k][r_off + j] += jobs[x].scale * load of kept edge j.
+// vec = 0: curl form (phi), 1: volume form (vector field).
+__global__ void k_load_batch(const DevPatch* P, const LoadJob* jobs, const int* prefix,
+                             int njobs, const int* r_loc, const double* ptab, const double* F,
+                             int vec, double* out, int64_t ldv) {
+  const int jx = find_job(prefix, njobs, blockIdx.x);
+  const LoadJob jb = jobs[jx];
+  const DevPatch& pp = P[jb.s];
+  const int j = (blockIdx.x - prefix[jx]) * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (j >= pp.n_r) return;
+  const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
+  const int64_t npts = (int64_t)pp.nq_load[0] * pp.nq_load[1] * pp.nq_load[2];
+  const double* f = F + jb.f_off + (int64_t)k * (vec ? 3 : 1) * npts;
+  const double v = vec ? load_vec_edge(pp, u, ptab, f) : load_curl_edge(pp, u, ptab, f);
+  out[(int64_t)k * ldv + pp.r_off + j] += jb.scale * v;
 }
 
 // ===========================================================================
@@ -501,50 +516,83 @@ __global__ void k_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs
   for (int c = 0; c < TCF_NB; ++c) a[row + (int64_t)(col0 + c) * ld] = x[c];
 }
 
-// Trailing update C -= L_I L_J^T on 64x64 lower tiles below the panel.
+// Trailing updates of the blocked Cholesky, C -= L_I L_J^T on 64 x 64 tiles
+// (entries on or below the diagonal).  Panels of TCF_NB columns are grouped
+// into super-panels of TCF_SP panels.
+// mode 0, after panel k: K = the panel's columns [col0, col0 + TCF_NB); rows
+//   from trail0 = col0 + TCF_NB to n, columns from trail0 to the end of the
+//   super-panel (what the next panels of the super-panel need), tiles
+//   enumerated as a rectangle.
+// mode 1, after the last panel of super-panel k / TCF_SP: K = all of its
+//   columns [p0, p_end); rows and columns from p_end to n (lower tiles):
+//   each trailing tile is read and written once per super-panel.
+#define TCF_SP 4
 template <class T>
-__global__ void k_syrk_update(const FactorJob* jobs, const int* prefix, int njobs, int k, T* A) {
+__global__ void k_syrk_blk(const FactorJob* jobs, const int* prefix, int njobs, int k, int mode,
+                           T* A) {
   const int j = find_job(prefix, njobs, blockIdx.x);
   const FactorJob jb = jobs[j];
   const int t = blockIdx.x - prefix[j];
-  const int col0 = jb.c_begin + TCF_NB * k;
-  const int trail0 = col0 + TCF_NB;
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int J = t - I * (I + 1) / 2;
-  const int row0 = trail0 + 64 * I, cl0 = trail0 + 64 * J;
+  const int n = jb.n;
+  const int sp = k / TCF_SP;
+  const int p0 = jb.c_begin + TCF_NB * TCF_SP * sp;
+  const int p_end = min(p0 + TCF_NB * TCF_SP, jb.c_end);
+  int k0, k1, row0, cl0, cmax;
+  if (mode == 0) {
+    const int col0 = jb.c_begin + TCF_NB * k;
+    const int trail0 = col0 + TCF_NB;
+    const int nJ = (p_end - trail0 + 63) / 64;
+    const int I = t / nJ, J = t % nJ;
+    k0 = col0;
+    k1 = col0 + TCF_NB;
+    row0 = trail0 + 64 * I;
+    cl0 = trail0 + 64 * J;
+    cmax = p_end;
+    if (row0 + 63 < cl0) return;  // wholly above the diagonal
+  } else {
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    k0 = p0;
+    k1 = p_end;
+    row0 = p_end + 64 * I;
+    cl0 = p_end + 64 * J;
+    cmax = n;
+  }
   __shared__ T LI[TCF_NB][64 + 1];
   __shared__ T LJ[TCF_NB][64 + 1];
   T* a = A + jb.off;
   const int64_t ld = jb.ld;
-  const int n = jb.n;
-  for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
-    const int r = idx % 64, c = idx / 64;
-    LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(col0 + c) * ld] : T(0);
-    LJ[c][r] = (cl0 + r < n) ? a[(cl0 + r) + (int64_t)(col0 + c) * ld] : T(0);
-  }
-  __syncthreads();
   const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
   T acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[i][q] = T(0);
+  for (int kc = k0; kc < k1; kc += TCF_NB) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
+      const int r = idx % 64, c = idx / 64;
+      LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(kc + c) * ld] : T(0);
+      LJ[c][r] = (cl0 + r < cmax) ? a[(cl0 + r) + (int64_t)(kc + c) * ld] : T(0);
+    }
+    __syncthreads();
 #pragma unroll 4
-  for (int c = 0; c < TCF_NB; ++c) {
-    T li[4], lj[4];
+    for (int c = 0; c < TCF_NB; ++c) {
+      T li[4], lj[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { li[i] = LI[c][tr + 16 * i]; lj[i] = LJ[c][tc + 16 * i]; }
+      for (int i = 0; i < 4; ++i) { li[i] = LI[c][tr + 16 * i]; lj[i] = LJ[c][tc + 16 * i]; }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][q] += li[i] * lj[q];
+        for (int q = 0; q < 4; ++q) acc[i][q] += li[i] * lj[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int C = cl0 + tc + 16 * q;
-    if (C >= n) continue;
+    if (C >= cmax) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int R = row0 + tr + 16 * i;
@@ -750,16 +798,20 @@ __global__ void __launch_bounds__(64) k_trsm_dinv(const TrsmJob* jobs, const int
 }
 
 // Solves L X = B (forward) or L^T X = B (backward) for a batch of jobs,
-// right-looking: step s handles row block kb of every job (kb = s forward,
-// nblk - 1 - s backward) in two launches, first
-// X_kb = D_kb B_kb (D_kb^T backward) for every column block of every job,
-// then B_j -= L_j,kb X_kb for the row blocks still to come (j > kb forward;
-// j < kb backward with L_kb,j^T), every tile of every job in parallel.  With
-// identity right-hand sides (column c0 + q of the identity, tri > 0) the
-// blocks that stay zero are skipped.
-__device__ inline int rl_kb(const TrsmJob& jb, int s, int fwd) {
+// right-looking over panels of TCF_RL_PANEL row blocks (32 rows each): step
+// s takes the panel of row blocks kb = P s + i, i < P (forward; backward
+// kb = nblk - 1 - P s - i) of every job in two launches.  The first, per
+// column block, solves the panel's blocks in order, X_kb = D_kb (B_kb -
+// sum of the panel's earlier blocks L_kb,kb' X_kb') (D_kb^T and L^T
+// backward).  The second subtracts the whole panel from every row block
+// after it (before it backward), B_j -= sum_i L_j,kb_i X_kb_i, each output
+// tile read and written once per panel, every tile of every job in
+// parallel.  With identity right-hand sides (tri > 0) the blocks that stay
+// zero are skipped.
+#define TCF_RL_PANEL 4
+__device__ inline int rl_kb(const TrsmJob& jb, int s, int i, int fwd) {
   const int nblk = jb.n / TCF_NB;
-  return fwd ? s : nblk - 1 - s;
+  return fwd ? TCF_RL_PANEL * s + i : nblk - 1 - TCF_RL_PANEL * s - i;
 }
 __device__ inline bool rl_zero_block(const TrsmJob& jb, int kb, int c0, int fwd) {
   if (c0 + 64 > jb.tri) return false;
@@ -767,66 +819,11 @@ __device__ inline bool rl_zero_block(const TrsmJob& jb, int kb, int c0, int fwd)
   return kb > (c0 + 63) / TCF_NB;
 }
 
-__global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix,
-                                                      const int* dprefix, int njobs, int s,
-                                                      int fwd, const double* D, double* Bb) {
-  const int jx = find_job(cprefix, njobs, blockIdx.x);
-  const TrsmJob jb = jobs[jx];
-  const int nblk = jb.n / TCF_NB;
-  const int kb = rl_kb(jb, s, fwd);
-  const int c0 = (blockIdx.x - cprefix[jx]) * 64;
-  if (kb < 0 || kb >= nblk || rl_zero_block(jb, kb, c0, fwd)) return;
-  __shared__ double Ls[TCF_NB][TCF_NB + 1];
-  __shared__ double Xs[TCF_NB][64 + 1];
-  double* B = Bb + jb.b_off;
-  const int64_t ldb = jb.ldb;
-  const double* Dk = D + ((int64_t)dprefix[jx] + kb) * TCF_NB * TCF_NB;
-  for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256) Ls[idx % TCF_NB][idx / TCF_NB] = Dk[idx];
-  for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += 256) {
-    const int r = idx % TCF_NB, c = idx / TCF_NB;
-    Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : 0.0;
-  }
-  __syncthreads();
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
-  tcf_v4d x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
-    const double bv = Xs[k0 + lk][16 * w + li];
-    const double a0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
-    const double a1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
-    x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, x0, 0, 0, 0);
-    x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, x1, 0, 0, 0);
-  }
-  const int col = c0 + 16 * w + li;
-  if (col < jb.ncols) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = x0[e];
-      B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = x1[e];
-    }
-  }
-}
-
-// tprefix: row s of a (steps x (njobs + 1)) table, the prefix over jobs of
-// the tiles that step s updates (rows j > kb, or j < kb, times column blocks)
-__global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, const int* tprefix,
-                                                        int njobs, int s, int fwd,
-                                                        const double* Lb, double* Bb) {
-  const int jx = find_job(tprefix, njobs, blockIdx.x);
-  const TrsmJob jb = jobs[jx];
-  const int ncb = (jb.ncols + 63) / 64;
-  const int t = blockIdx.x - tprefix[jx];
-  const int kb = rl_kb(jb, s, fwd);
-  const int j = fwd ? kb + 1 + t / ncb : t / ncb;
-  const int c0 = (t % ncb) * 64;
-  if (rl_zero_block(jb, kb, c0, fwd)) return;
-  __shared__ double Ls[TCF_NB][TCF_NB + 1];
-  __shared__ double Xs[TCF_NB][64 + 1];
-  const double* L = Lb + jb.l_off;
-  double* B = Bb + jb.b_off;
+// Stage the 32 x 32 block of L at row block lr, column block lc into Ls and
+// the 32 x 64 block of B at row block kb, columns c0.., into Xs.
+__device__ inline void rl_stage(const TrsmJob& jb, const double* L, const double* B, int lr, int lc,
+                                int kb, int c0, double (*Ls)[TCF_NB + 1], double (*Xs)[64 + 1]) {
   const int64_t ldl = jb.ldl, ldb = jb.ldb;
-  // L tile: forward L_j,kb (A[i][k] = Ls[i][k]); backward L_kb,j (A = Ls^T)
-  const int lr = fwd ? j : kb, lc = fwd ? kb : j;
   for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256) {
     const int r = idx % TCF_NB, c = idx / TCF_NB;
     Ls[r][c] = L[(jb.l_row0 + lr * TCF_NB + r) + (int64_t)(jb.l_row0 + lc * TCF_NB + c) * ldl];
@@ -835,16 +832,12 @@ __global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, con
     const int r = idx % TCF_NB, c = idx / TCF_NB;
     Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : 0.0;
   }
-  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
-  const int col = c0 + 16 * w + li;
-  const bool colok = col < jb.ncols;
-  tcf_v4d a0, a1;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    a0[e] = colok ? B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
-    a1[e] = colok ? B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
-  }
-  __syncthreads();
+}
+
+// acc -= A X with A = Ls (forward) or Ls^T (backward), X = Xs, for the
+// wave's 16 columns and both 16-row halves
+__device__ inline void rl_mfma_sub(const double (*Ls)[TCF_NB + 1], const double (*Xs)[64 + 1],
+                                   int fwd, int w, int li, int lk, tcf_v4d& a0, tcf_v4d& a1) {
 #pragma unroll
   for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
     const double bv = Xs[k0 + lk][16 * w + li];
@@ -853,12 +846,113 @@ __global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, con
     a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v0, bv, a0, 0, 0, 0);
     a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v1, bv, a1, 0, 0, 0);
   }
-  if (colok) {
+}
+
+__global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix,
+                                                      const int* dprefix, int njobs, int s,
+                                                      int fwd, const double* Lb, const double* D,
+                                                      double* Bb) {
+  const int jx = find_job(cprefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int nblk = jb.n / TCF_NB;
+  const int c0 = (blockIdx.x - cprefix[jx]) * 64;
+  __shared__ double Ls[TCF_NB][TCF_NB + 1];
+  __shared__ double Xs[TCF_NB][64 + 1];
+  const double* L = Lb + jb.l_off;
+  double* B = Bb + jb.b_off;
+  const int64_t ldb = jb.ldb;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int col = c0 + 16 * w + li;
+  const bool colok = col < jb.ncols;
+  for (int i = 0; i < TCF_RL_PANEL; ++i) {
+    const int kb = rl_kb(jb, s, i, fwd);
+    if (kb < 0 || kb >= nblk) break;
+    if (rl_zero_block(jb, kb, c0, fwd)) continue;
+    tcf_v4d a0, a1;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = a0[e];
-      B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = a1[e];
+      a0[e] = colok ? B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
+      a1[e] = colok ? B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
     }
+    // earlier blocks of this panel (already solved and stored by this block)
+    for (int q = 0; q < i; ++q) {
+      const int kq = rl_kb(jb, s, q, fwd);
+      if (rl_zero_block(jb, kq, c0, fwd)) continue;
+      __syncthreads();
+      rl_stage(jb, L, B, fwd ? kb : kq, fwd ? kq : kb, kq, c0, Ls, Xs);
+      __syncthreads();
+      rl_mfma_sub(Ls, Xs, fwd, w, li, lk, a0, a1);
+    }
+    // X_kb = D_kb acc (D_kb^T backward) through LDS
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Xs[lk + 4 * e][16 * w + li] = a0[e];
+      Xs[16 + lk + 4 * e][16 * w + li] = a1[e];
+    }
+    const double* Dk = D + ((int64_t)dprefix[jx] + kb) * TCF_NB * TCF_NB;
+    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256)
+      Ls[idx % TCF_NB][idx / TCF_NB] = Dk[idx];
+    __syncthreads();
+    tcf_v4d x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
+      const double bv = Xs[k0 + lk][16 * w + li];
+      const double v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
+      const double v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
+      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, bv, x0, 0, 0, 0);
+      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, bv, x1, 0, 0, 0);
+    }
+    if (colok) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = x0[e];
+        B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = x1[e];
+      }
+    }
+    __syncthreads();  // the stores are read back by the next block of the panel
+  }
+}
+
+// tprefix: row s of a (steps x (njobs + 1)) table, the prefix over jobs of
+// the tiles that step s updates (row blocks after the panel forward, before
+// it backward, times column blocks)
+__global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, const int* tprefix,
+                                                        int njobs, int s, int fwd,
+                                                        const double* Lb, double* Bb) {
+  const int jx = find_job(tprefix, njobs, blockIdx.x);
+  const TrsmJob jb = jobs[jx];
+  const int nblk = jb.n / TCF_NB;
+  const int ncb = (jb.ncols + 63) / 64;
+  const int t = blockIdx.x - tprefix[jx];
+  const int first = fwd ? TCF_RL_PANEL * (s + 1) : 0;  // first row block updated
+  const int j = first + t / ncb;
+  const int c0 = (t % ncb) * 64;
+  __shared__ double Ls[TCF_NB][TCF_NB + 1];
+  __shared__ double Xs[TCF_NB][64 + 1];
+  const double* L = Lb + jb.l_off;
+  double* B = Bb + jb.b_off;
+  const int64_t ldb = jb.ldb;
+  const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+  const int col = c0 + 16 * w + li;
+  const bool colok = col < jb.ncols;
+  tcf_v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  bool any = false;
+  for (int i = 0; i < TCF_RL_PANEL; ++i) {
+    const int kb = rl_kb(jb, s, i, fwd);
+    if (kb < 0 || kb >= nblk) break;
+    if (rl_zero_block(jb, kb, c0, fwd)) continue;
+    any = true;
+    __syncthreads();
+    rl_stage(jb, L, B, fwd ? j : kb, fwd ? kb : j, kb, c0, Ls, Xs);
+    __syncthreads();
+    rl_mfma_sub(Ls, Xs, fwd, w, li, lk, a0, a1);
+  }
+  if (!any || !colok) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] += a0[e];
+    B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] += a1[e];
   }
 }
 
@@ -1632,20 +1726,13 @@ void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, i
                      row_prefix, nlist, r_loc, loc2r, tabs, dt, mass_only, x, y, ldv);
 }
 
-void launch_load_patch(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
-                       const double* ptab, const double* phi, double* jr, int64_t ldv,
-                       hipStream_t st) {
-  if (n_r == 0) return;
-  hipLaunchKernelGGL(k_load_patch, dim3((n_r + 127) / 128, nrhs), dim3(128), 0, st, P, s, r_loc,
-                     ptab, phi, jr, ldv);
-}
 
-void launch_load_vec(const DevPatch* P, int s, int n_r, int nrhs, const int* r_loc,
-                     const double* ptab, const double* F, double scale, double* jr, int64_t ldv,
-                     hipStream_t st) {
-  if (n_r == 0) return;
-  hipLaunchKernelGGL(k_load_vec, dim3((n_r + 127) / 128, nrhs), dim3(128), 0, st, P, s, r_loc,
-                     ptab, F, scale, jr, ldv);
+void launch_load_batch(const DevPatch* P, const LoadJob* jobs, const int* prefix, int njobs,
+                       int total, int nrhs, const int* r_loc, const double* ptab, const double* F,
+                       int vec, double* out, int64_t ldv, hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_load_batch, dim3(total, nrhs), dim3(128), 0, st, P, jobs, prefix, njobs,
+                     r_loc, ptab, F, vec, out, ldv);
 }
 
 template <class T>
@@ -1659,11 +1746,12 @@ void launch_trsm_panel(const FactorJob* jobs, const int* prefix, int njobs, int 
   hipLaunchKernelGGL(k_trsm_panel<T>, dim3(total), dim3(64), 0, st, jobs, prefix, njobs, k, A);
 }
 template <class T>
-void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, T* A,
-                 hipStream_t st) {
+void launch_syrk(const FactorJob* jobs, const int* prefix, int njobs, int total, int k, int mode,
+                 T* A, hipStream_t st) {
   if (total == 0) return;
-  hipLaunchKernelGGL(k_syrk_update<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, k, A);
+  hipLaunchKernelGGL(k_syrk_blk<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, k, mode, A);
 }
+int syrk_super_panel() { return TCF_SP; }
 template <class T>
 void launch_copy_sbb(const DevPatch* P, const int* prefix, int np, int total, const T* A, T* S,
                      hipStream_t st) {
@@ -1698,11 +1786,13 @@ void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int to
   if (total == 0) return;
   hipLaunchKernelGGL(k_trsm_dinv, dim3(total), dim3(64), 0, st, jobs, dprefix, njobs, L, D);
 }
+int trsm_rl_panel() { return TCF_RL_PANEL; }
 void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
-                         int total, int s, int fwd, const double* D, double* B, hipStream_t st) {
+                         int total, int s, int fwd, const double* L, const double* D, double* B,
+                         hipStream_t st) {
   if (total == 0) return;
   hipLaunchKernelGGL(k_trsm_rl_diag, dim3(total), dim3(256), 0, st, jobs, cprefix, dprefix, njobs,
-                     s, fwd, D, B);
+                     s, fwd, L, D, B);
 }
 void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
                            int fwd, const double* L, double* B, hipStream_t st) {
@@ -1896,7 +1986,7 @@ void launch_to_global(int64_t n, const int64_t* gid, const double* a, double* ou
   template void launch_potrf<T>(const FactorJob*, int, int, T*, int*, hipStream_t);              \
   template void launch_trsm_panel<T>(const FactorJob*, const int*, int, int, int, T*,            \
                                      hipStream_t);                                               \
-  template void launch_syrk<T>(const FactorJob*, const int*, int, int, int, T*, hipStream_t);    \
+  template void launch_syrk<T>(const FactorJob*, const int*, int, int, int, int, T*, hipStream_t);    \
   template void launch_copy_sbb<T>(const DevPatch*, const int*, int, int, const T*, T*,          \
                                    hipStream_t);                                                 \
   template void launch_fill_G<T>(const DevPatch*, const int*, int, int, const T*, T*,            \

@@ -222,7 +222,9 @@ def test_warm_start_plain_all_steps(warm):
     warm_p.tcf_step(prob.n_steps)
     it_warm, _, _ = warm_p.tcf_get_step_log(prob.n_steps)
     print(f"[parity] warm {warm}: iterations cold {list(it_cold)} warm {list(it_warm)}", flush=True)
-    assert it_warm[0] == it_cold[0]  # no history at the first step
+    # no history at the first step: the same solve up to the rounding order of
+    # the atomically summed dot products (one iteration either way)
+    assert abs(int(it_warm[0]) - int(it_cold[0])) <= 1
     assert sum(it_warm[3:]) < sum(it_cold[3:])
 
 
