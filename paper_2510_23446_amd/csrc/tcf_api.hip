@@ -189,13 +189,14 @@ struct tcf_problem {
   double *d_pv = nullptr, *d_pfv = nullptr, *d_pc = nullptr;
   std::vector<int> proj_n, proj_head;
   bool warm_init = false;  // the next pcg_solve starts from the lambda columns as set
+  int graph_iters = 4;     // PCG iterations per replayed graph (even)
   // signed gathers of the tile path: Bhat's +-1 per b entry (F apply) and the
   // preconditioner's (the same, or D Bhat when scaled); weights of the two
   // copies in the preconditioner's jump (null: unscaled)
   double *d_bsgn_d = nullptr, *d_pre_w = nullptr, *d_zwp = nullptr, *d_zwm = nullptr;
   std::vector<int> h_posp, h_posm;  // b-space copies of each multiplier (host)
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
-  hipGraphExec_t pcg_graph = nullptr; // two PCG iterations (parity 0 then 1)
+  hipGraphExec_t pcg_graph = nullptr; // graph_iters PCG iterations (parity 0, 1, 0, ...)
   bool graph_failed = false;          // capture refused: stream launches instead
 
   // job tables
@@ -497,6 +498,8 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
     h->use_tiles = !(nt && nt[0] == '1');
     const char* fi = std::getenv("TCF_FP64_IR");
     h->fp64_ir = fi && fi[0] == '1';
+    const char* gi = std::getenv("TCF_GRAPH_ITERS");
+    if (gi) h->graph_iters = std::max(2, std::min(8, std::atoi(gi) / 2 * 2));
   }
   for (int a = 0; a < 3; ++a) {
     h->np[a] = desc->np[a];
@@ -1633,8 +1636,7 @@ static int build_pcg_graph(tcf_problem* h) {
     (void)hipGetLastError();
     return TCF_OK;
   }
-  pcg_iteration<T>(h, 0, h->cap_stream);
-  pcg_iteration<T>(h, 1, h->cap_stream);
+  for (int q = 0; q < h->graph_iters; ++q) pcg_iteration<T>(h, q & 1, h->cap_stream);
   hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
   if (e == hipSuccess) e = hipGraphInstantiate(&h->pcg_graph, g, nullptr, nullptr, 0);
   if (g) (void)hipGraphDestroy(g);
@@ -1703,7 +1705,8 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
   // before the previous count, later ones every min(chunk, 4) iterations.
   const int kind = std::min(h->cur_sweep, TCF_PRED_KINDS - 1);
   const int pred = h->pred_iters[kind];
-  int seg = pred > chunk + 6 ? (pred - 6) / 2 * 2 : chunk;
+  const int gi = h->graph_iters;
+  int seg = pred > chunk + 6 ? (pred - 6) / gi * gi : chunk;
   int it = 0;
   bool finished = false;
   auto max_iters = [&] {
@@ -1715,9 +1718,9 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     const int it1 = std::min(maxit, it + seg);
     seg = std::min(chunk, 4);
     while (it < it1) {
-      if (graph && it + 2 <= it1 && (it & 1) == 0) {
+      if (graph && it + h->graph_iters <= it1 && (it & 1) == 0) {
         HIPCHK(hipGraphLaunch(h->pcg_graph, st));
-        it += 2;
+        it += h->graph_iters;
       } else {
         h->cur_it = it;
         pcg_iteration<T>(h, it & 1, st);
