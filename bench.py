@@ -46,8 +46,9 @@ def parse():
     ap.add_argument("--no-paper-leg", action="store_true",
                     help="skip the end-to-end run of the paper's timed configuration")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
-    ap.add_argument("--rate-x", type=float, default=2.0,
-                    help="serving: arrival rate as a multiple of the solo FP64 capacity")
+    ap.add_argument("--rate-x", default="0.5,1,2",
+                    help="serving: arrival rates, comma-separated multiples of the solo FP64 "
+                         "capacity (the last one is the headline line)")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir", "fp32_full_ir"])
     ap.add_argument("--profile-steps", type=int, default=3,
@@ -140,6 +141,15 @@ def cpu_baseline(prob, budget_s, full_kept):
     t3 = time.perf_counter()
     sub_rate = steps / (t3 - ts)
     cores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": sub_rate * len(K) / full_kept, "unit": "time-steps/s", "cores": 1,
         "kind": "oracle",
@@ -152,6 +162,9 @@ def cpu_baseline(prob, budget_s, full_kept):
                    f"{cores} cores visible"),
         "sample_steps_per_s": sub_rate, "sample_unknowns": len(K), "factor_s": t2 - t1,
         "assembly_s": t1 - t0, "steps_timed": steps,
+        "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity": cores,
+                 "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+                 "direct_solve_threads": 1},
     }
 
 
@@ -178,25 +191,43 @@ def serving(args):
             print(f"[bench] sequential fp64 {i + 1}/{len(reqs)}", file=sys.stderr, flush=True)
     seq_wall = time.perf_counter() - t0
     solo_rate = len(reqs) / seq_wall
-    # served, FP32 operators + FP64 refinement, Poisson arrivals
-    rate = args.rate_x * solo_rate
-    arrivals = W.poisson_arrivals(len(reqs), rate, seed=33)
-    srv = tcf.Server(max_bytes=200 << 30, max_slots=args.slots)
-    t0 = time.perf_counter()
-    ids = []
-    for i, (r, ta) in enumerate(zip(reqs, arrivals)):
-        dt = ta - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        ids.append(srv.tcf_server_submit(r, precision="fp32_ir"))
-    for i in ids:
-        rc = srv.tcf_server_wait(i)
-        if rc != tcf.TCF_OK:
-            print(f"[bench] request {i} ({reqs[i].name}) failed: {srv.tcf_server_error(i)}",
-                  file=sys.stderr, flush=True)
-    wall = time.perf_counter() - t0
-    st = srv.tcf_server_stats()
-    srv.tcf_server_destroy()
+
+    # served, FP32 operators + FP64 refinement, Poisson arrivals at each
+    # multiple of the measured solo capacity (the last one is the headline)
+    def served(rate):
+        arrivals = W.poisson_arrivals(len(reqs), rate, seed=33)
+        srv = tcf.Server(max_bytes=200 << 30, max_slots=args.slots)
+        t0 = time.perf_counter()
+        ids = []
+        for i, (r, ta) in enumerate(zip(reqs, arrivals)):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(srv.tcf_server_submit(r, precision="fp32_ir"))
+        for i in ids:
+            rc = srv.tcf_server_wait(i)
+            if rc != tcf.TCF_OK:
+                print(f"[bench] request {i} ({reqs[i].name}) failed: {srv.tcf_server_error(i)}",
+                      file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        st = srv.tcf_server_stats()
+        srv.tcf_server_destroy()
+        return wall, st
+
+    per_rate = []
+    for x in [float(v) for v in args.rate_x.split(",")]:
+        rate = x * solo_rate
+        wall, st = served(rate)
+        per_rate.append({"rate_x": x, "arrival_rate_per_s": rate, "steps_per_s": steps_total / wall,
+                         "wall_s": wall, "p50_step_ms": st["p50_step_ms"],
+                         "p99_step_ms": st["p99_step_ms"], "p50_queue_ms": st["p50_queue_ms"],
+                         "p99_queue_ms": st["p99_queue_ms"], "completed": st["completed"],
+                         "failed": st["failed"], "peak_bytes": st["peak_bytes"]})
+        print(f"[bench] served at {x} x solo capacity: {steps_total / wall:.1f} steps/s",
+              file=sys.stderr, flush=True)
+    head = per_rate[-1]
+    wall, rate = head["wall_s"], head["arrival_rate_per_s"]
+    st = head
     out = {
         "metric": "time-steps/sec", "value": steps_total / wall, "unit": "time-steps/s",
         "n_gpus": 1, "steps": steps_total, "warmup": 0, "ms_per_step": wall / steps_total * 1e3,
@@ -208,6 +239,7 @@ def serving(args):
         "p50_step_ms": st["p50_step_ms"], "p99_step_ms": st["p99_step_ms"],
         "p50_queue_ms": st["p50_queue_ms"], "p99_queue_ms": st["p99_queue_ms"],
         "completed": st["completed"], "failed": st["failed"], "peak_bytes": st["peak_bytes"],
+        "rates": per_rate,
         "fp64_sequential": {"steps_per_s": steps_total / seq_wall, "wall_s": seq_wall,
                             "p50_step_ms": float(np.percentile(seq_steps, 50)),
                             "p99_step_ms": float(np.percentile(seq_steps, 99))},
