@@ -162,6 +162,11 @@ def cpu_baseline(prob, budget_s, full_kept):
                    f"{cores} cores visible"),
         "sample_steps_per_s": sub_rate, "sample_unknowns": len(K), "factor_s": t2 - t1,
         "assembly_s": t1 - t0, "steps_timed": steps,
+        # the same rate with assembly, gauge and factorisation spread over the
+        # workload's own number of steps (same linear scaling to full size)
+        "value_setup_amortised": (prob.n_steps / (prob.n_steps / sub_rate + (t2 - t0)))
+                                 * len(K) / full_kept,
+        "amortised_over_steps": int(prob.n_steps),
         "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity": cores,
                  "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
                  "direct_solve_threads": 1},
