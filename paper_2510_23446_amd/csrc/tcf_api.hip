@@ -1619,7 +1619,7 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
   launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
 }
 
-// Captures two iterations (parity 0, 1) into a graph replayed per chunk.
+// Captures graph_iters iterations (parity 0, 1, 0, ...) into a graph replayed per chunk.
 // If capture or instantiation fails, the handle falls back to stream
 // launches (same kernels) instead of failing.
 template <class T>

@@ -5,6 +5,8 @@ multiplier table (edge, +patch, -patch) and the primal assembly N must be
 identical, integer for integer.  tcf_create does host work only, so these
 run without a GPU.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -115,3 +117,34 @@ def test_invalid_options():
         assert e.value.code == tcf.TCF_EINVAL, kw
     # accepted: batch widths beyond 4 or n_rhs are clamped
     tcf.Problem(prob, rhs_batch=9, pcg_warm=2)
+    tcf.Problem(prob, pcg_warm=3, precond_scaling=1)
+
+
+def test_source_forms_validated():
+    """A source mask needs a curl-form potential or a volume field; a volume
+    field alone (the homogenised Sec. 4 problem) is accepted, and the host
+    plan of the manufactured problem matches the oracle's topology counts."""
+    import dataclasses
+    prob = W.paper_manufactured(n=3, p=2, n_t=2)
+    h = tcf.Problem(prob)
+    c = h.counts()
+    from oracle.gauge import compute_topology
+    from oracle.grid import build_grid
+    g = build_grid(prob)
+    topo = compute_topology(prob, g)
+    assert c["n_edges"] == g.n_edges
+    assert c["n_lambda"] == len(topo.dual) and c["n_primal"] == len(topo.primal)
+    bad = dataclasses.replace(prob, jvol=None, ainit=None)
+    with pytest.raises(tcf.TcfError) as e:
+        tcf.Problem(bad)
+    assert e.value.code == tcf.TCF_EINVAL
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout
