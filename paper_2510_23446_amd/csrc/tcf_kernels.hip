@@ -1207,16 +1207,40 @@ __global__ void __launch_bounds__(256) k_condense(const DevPatch* P, const int* 
     const int col = cblk + wave * 4 + q;
     nrq[q] = (col >= pp.n_r) ? 0 : ((col < pp.n_i) ? col + 1 : pp.n_i);
   }
+  // the wave's 4 columns and 4 row groups per pass: 16 independent loads in
+  // flight per lane (addresses clamped into the column, products masked,
+  // so no branch separates the loads); the pass count follows the longest
+  // of the 4 columns, so the zero part of triangular columns is not read
+  int colc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) colc[q] = min(cblk + wave * 4 + q, pp.n_r - 1);
   for (int r0 = 0; r0 < pp.n_i; r0 += TCF_XCH) {
     const int rn = min(TCF_XCH, pp.n_i - r0);
     if (r0 > 0) __syncthreads();
     for (int r = threadIdx.x; r < rn; r += blockDim.x) xs[r] = fr[r0 + r];
     __syncthreads();
+    int lim[4], lmax = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int col = cblk + wave * 4 + q;
-      const int lim = min(rn, nrq[q] - r0);
-      for (int r = lane; r < lim; r += 64) acc[q] += (double)M[(r0 + r) + col * ld] * xs[r];
+      lim[q] = max(0, min(rn, nrq[q] - r0));
+      lmax = max(lmax, lim[q]);
+    }
+    for (int base = 0; base < lmax; base += 256) {
+      double v[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int rr = min(base + 64 * u + lane, rn - 1);
+          v[q][u] = (double)M[(r0 + rr) + (int64_t)colc[q] * ld];
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int rr = base + 64 * u + lane;
+          if (rr < lim[q]) acc[q] += v[q][u] * xs[rr];
+        }
     }
   }
 #pragma unroll
