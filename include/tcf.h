@@ -219,6 +219,18 @@ enum tcf_topology_kind {
  */
 int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* len);
 
+/*
+ * Per-patch condition estimate of the local factorisation (after setup):
+ * (max_k L_kk / min_k L_kk)^2 over the factor's interior and dual rows, the
+ * ratio of the largest to the smallest Cholesky pivot of W_rr restricted to
+ * them.  It is a lower bound on that block's condition number and shows which
+ * patches can take FP32 factors (TCF_FP32_FULL_IR).  out == NULL returns the
+ * count (the number of patches) in *len; otherwise *len is the capacity on
+ * entry and the count on return.  Host memory.  TCF_ESTATE before
+ * tcf_setup, TCF_EINVAL for a small buffer.
+ */
+int tcf_get_cond_est(const tcf_problem* h, double* out, size_t* len);
+
 typedef struct tcf_stats {
   int64_t n_patches, n_edges, n_kept, n_lambda, n_primal, n_tree_I;
   int32_t steps_done;
@@ -243,6 +255,9 @@ typedef struct tcf_stats {
                                /* 5 n_Pi^3/3 (Cholesky, triangular inverse, and  */
                                /* one full triangular solve); triangular         */
                                /* right-hand sides counted by their nonzeros     */
+  double cond_est_max;         /* largest per-patch pivot ratio (see            */
+  int32_t cond_est_patch;      /* tcf_get_cond_est) and its patch; -1 before    */
+                               /* setup                                         */
 } tcf_stats;
 
 int tcf_get_stats(const tcf_problem* h, tcf_stats* st);

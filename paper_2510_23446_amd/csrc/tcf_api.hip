@@ -188,6 +188,7 @@ struct tcf_problem {
   double *d_ph = nullptr, *d_pfh = nullptr, *d_px = nullptr, *d_pfx = nullptr;
   double *d_pv = nullptr, *d_pfv = nullptr, *d_pc = nullptr;
   std::vector<int> proj_n, proj_head;
+  std::vector<double> cond_est;  // per patch, after setup
   bool warm_init = false;  // the next pcg_solve starts from the lambda columns as set
   int graph_iters = 4;     // PCG iterations per replayed graph (even)
   // signed gathers of the tile path: Bhat's +-1 per b entry (F apply) and the
@@ -628,6 +629,26 @@ int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
     const double nP = h->n_primal;
     st->setup_flops = f + 5 * nP * nP * nP / 3;  // coarse Cholesky and inverse
   }
+  st->cond_est_max = 0.0;
+  st->cond_est_patch = -1;
+  for (size_t s = 0; s < h->cond_est.size(); ++s)
+    if (h->cond_est[s] > st->cond_est_max) {
+      st->cond_est_max = h->cond_est[s];
+      st->cond_est_patch = (int32_t)s;
+    }
+  return TCF_OK;
+}
+
+int tcf_get_cond_est(const tcf_problem* h, double* out, size_t* len) {
+  if (!h || !len) return TCF_EINVAL;
+  if (h->cond_est.empty()) return TCF_ESTATE;
+  if (!out) {
+    *len = h->cond_est.size();
+    return TCF_OK;
+  }
+  if (*len < h->cond_est.size()) return TCF_EINVAL;
+  std::copy(h->cond_est.begin(), h->cond_est.end(), out);
+  *len = h->cond_est.size();
   return TCF_OK;
 }
 
@@ -1164,6 +1185,20 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     h->release(dpre);
   }
   RCCHK(run_factor_phase<T>(h, jbv, A, st));
+  {
+    // per-patch pivot-ratio condition estimate of the factored [i|b] block
+    double* dr;
+    RCCHK(h->alloc(&dr, (size_t)2 * np));
+    launch_diag_range<T>(h->dP, np, A, dr, st);
+    std::vector<double> r(2 * (size_t)np);
+    HIPCHK(hipMemcpyAsync(r.data(), dr, sizeof(double) * 2 * np, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    h->release(dr);
+    h->cond_est.assign(np, 1.0);
+    for (int s = 0; s < np; ++s)
+      if (h->hp[s].n_i + h->hp[s].n_b > 0 && r[2 * s] > 0)
+        h->cond_est[s] = (r[2 * s + 1] / r[2 * s]) * (r[2 * s + 1] / r[2 * s]);
+  }
 
   // coarse matrix S_Pi = sum N^T S_pp N, its Cholesky factor and inverse (FP64)
   if (h->n_primal > 0) {

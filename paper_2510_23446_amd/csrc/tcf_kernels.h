@@ -89,6 +89,8 @@ void launch_store_dir(int n, const double* nu2, const double* ref, double tol, c
                       const double* Fv, double* x, double* fx, hipStream_t st);
 void launch_copy_sub(int n, const double* a, const double* b, const double* c, double* v,
                      double* w, hipStream_t st);
+template <class T>
+void launch_diag_range(const DevPatch* P, int np, const T* A, double* out, hipStream_t st);
 void launch_axpby(int64_t n, double alpha, const double* x, double beta, double* y,
                   hipStream_t st);
 void launch_sub_gather(int n, const int* ia, const double* a, const int* ib, const double* b,

@@ -2494,6 +2494,47 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
   }
 }
 
+// Range of the Cholesky factor's diagonal over each patch's real interior
+// and dual rows (padding rows excluded): out[2 s] = min |L_kk|, out[2 s + 1]
+// = max |L_kk|.  (max / min)^2 is the ratio of the largest to the smallest
+// pivot, a lower bound on the condition number of the factored block.
+template <class T>
+__global__ void k_diag_range(const DevPatch* P, int np, const T* A, double* out) {
+  const int s = blockIdx.x;
+  if (s >= np) return;
+  const DevPatch& d = P[s];
+  const T* a = A + d.A_off;
+  __shared__ double smin[256], smax[256];
+  double lo = DBL_MAX, hi = 0.0;
+  for (int k = threadIdx.x; k < d.n_i + d.n_b; k += blockDim.x) {
+    const int row = k < d.n_i ? k : d.ni_pad + (k - d.n_i);
+    const double v = fabs((double)a[(int64_t)row * (d.nr_pad + 1)]);
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * s] = smin[0];
+    out[2 * s + 1] = smax[0];
+  }
+}
+template <class T>
+void launch_diag_range(const DevPatch* P, int np, const T* A, double* out, hipStream_t st) {
+  if (np == 0) return;
+  hipLaunchKernelGGL(k_diag_range<T>, dim3(np), dim3(256), 0, st, P, np, A, out);
+}
+template void launch_diag_range<double>(const DevPatch*, int, const double*, double*, hipStream_t);
+template void launch_diag_range<float>(const DevPatch*, int, const float*, double*, hipStream_t);
+
 // Diagonal of each patch's dual block, read from the assembled [i|b|p]
 // matrix before it is factored: out[b_off + k] = A[(ni_pad + k), (ni_pad + k)].
 template <class T>

@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32
  TCF_TOPO_DUAL, TCF_TOPO_INTERIOR, TCF_TOPO_MULT, TCF_TOPO_N) = range(9)
 
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
-           "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_stats",
+           "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
+           "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
            "tcf_profile_get", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
            "tcf_server_poll", "tcf_server_wait", "tcf_server_fetch", "tcf_server_stats",
@@ -76,7 +77,8 @@ class tcf_stats(C.Structure):
                 ("fail_patch", C.c_int32), ("last_rel_residual", C.c_double),
                 ("last_ir_residual", C.c_double), ("setup_ms", C.c_double),
                 ("step_ms_total", C.c_double), ("device_bytes", C.c_size_t),
-                ("setup_flops", C.c_double)]
+                ("setup_flops", C.c_double), ("cond_est_max", C.c_double),
+                ("cond_est_patch", C.c_int32)]
 
 
 class tcf_server_report(C.Structure):
@@ -368,6 +370,15 @@ class Problem:
         out = np.zeros(max(n.value, 1), dtype=np.int64)
         n2 = C.c_size_t(out.size)
         self._check(lib().tcf_get_topology(self.h, int(kind), _dptr(out, C.c_int64), C.byref(n2)))
+        return out[:n2.value]
+
+    def tcf_get_cond_est(self):
+        """Per-patch pivot-ratio condition estimates (after setup)."""
+        n = C.c_size_t()
+        self._check(lib().tcf_get_cond_est(self.h, None, C.byref(n)))
+        out = np.zeros(max(n.value, 1), dtype=np.float64)
+        n2 = C.c_size_t(out.size)
+        self._check(lib().tcf_get_cond_est(self.h, _dptr(out, C.c_double), C.byref(n2)))
         return out[:n2.value]
 
     def tcf_get_stats(self):

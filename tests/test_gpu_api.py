@@ -102,3 +102,35 @@ def test_server_request_states():
     with pytest.raises(tcf.TcfError):
         srv.tcf_server_poll(len(ids) + 5)
     srv.tcf_server_destroy()
+
+
+@pytest.mark.parametrize("case", ["plain", "floating"])
+def test_condition_estimates(case):
+    """Per-patch pivot ratios of the library's local factorisation against
+    numpy's Cholesky of the oracle's local [interior | dual] block (same
+    order: each class by edge id)."""
+    from oracle import solve
+    from tests.feti_ref import DenseFETI
+    prob = W.plain_fp64().with_steps(1) if case == "plain" else \
+        W.floating_mixed(n=3, p=2, n_steps=1, precision="fp64")
+    h = tcf.Problem(prob)
+    with pytest.raises(tcf.TcfError):
+        h.tcf_get_cond_est()  # before setup
+    h.tcf_setup()
+    got = h.tcf_get_cond_est()
+    st = h.tcf_get_stats()
+    h.tcf_destroy()
+    ref = solve.run(prob, n_steps=1)
+    fe = DenseFETI(prob, ref.sys, ref.topo)
+    want = np.ones(prob.n_patches)
+    for s, d in enumerate(fe.pat):
+        ib = np.concatenate([d["i"], d["b"]])
+        if len(ib) == 0:
+            continue
+        L = np.linalg.cholesky(d["W"][np.ix_(ib, ib)])
+        g = np.abs(np.diag(L))
+        want[s] = (g.max() / g.min()) ** 2
+    print(f"[cond] {prob.name}: max {got.max():.3e} at patch {int(np.argmax(got))}", flush=True)
+    assert np.allclose(got, want, rtol=1e-9, atol=0)
+    assert st["cond_est_patch"] == int(np.argmax(got))
+    assert abs(st["cond_est_max"] - got.max()) <= 1e-12 * got.max()
