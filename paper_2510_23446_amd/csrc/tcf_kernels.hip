@@ -12,9 +12,13 @@
 #include <cfloat>
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "tcf_device.h"
 #include "tcf_kernels.h"
+
+// 4-wide FP64 accumulator of v_mfma_f64_16x16x4
+typedef double tcf_v4d __attribute__((ext_vector_type(4)));
 
 namespace tcf {
 
@@ -564,6 +568,50 @@ __global__ void k_syrk_blk(const FactorJob* jobs, const int* prefix, int njobs, 
   __shared__ T LJ[TCF_NB][64 + 1];
   T* a = A + jb.off;
   const int64_t ld = jb.ld;
+  if constexpr (std::is_same<T, double>::value) {
+    // FP64 on the matrix cores: wave w owns rows 32 (w & 1) .. + 32 and
+    // columns 32 (w >> 1) .. + 32 of the tile as 2 x 2 subtiles of 16 x 16.
+    // The operands are swapped (A from LJ, B from LI), so the accumulator
+    // holds C^T: element e of lane l is C[rb + l % 16][cb + l / 16 + 4 e],
+    // i.e. lanes run along rows and the update of C stays coalesced.
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
+    const int rb = 32 * (w & 1), cb = 32 * (w >> 1);
+    tcf_v4d acc4[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc4[u][v] = tcf_v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kc = k0; kc < k1; kc += TCF_NB) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
+        const int r = idx % 64, c = idx / 64;
+        LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(kc + c) * ld] : 0.0;
+        LJ[c][r] = (cl0 + r < cmax) ? a[(cl0 + r) + (int64_t)(kc + c) * ld] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k4 = 0; k4 < TCF_NB; k4 += 4) {
+        const double b0 = LI[k4 + lk][rb + li], b1 = LI[k4 + lk][rb + 16 + li];
+        const double a0 = LJ[k4 + lk][cb + li], a1 = LJ[k4 + lk][cb + 16 + li];
+        acc4[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc4[0][0], 0, 0, 0);
+        acc4[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc4[0][1], 0, 0, 0);
+        acc4[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc4[1][0], 0, 0, 0);
+        acc4[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc4[1][1], 0, 0, 0);
+      }
+    }
+    // acc4[u][v]: rows rb + 16 u + li, columns cb + 16 v + lk + 4 e
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int R = row0 + rb + 16 * u + li;
+          const int C = cl0 + cb + 16 * v + lk + 4 * e;
+          if (R < n && C < cmax && R >= C) a[R + (int64_t)C * ld] -= acc4[u][v][e];
+        }
+    return;
+  }
   const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
   T acc[4][4];
 #pragma unroll
@@ -758,7 +806,6 @@ __global__ void k_trsm_fwd(const TrsmJob* jobs, const int* prefix, int njobs, co
 // holds A[l % 16][l / 16] and B[l / 16][l % 16]; element e of the 4-wide
 // accumulator is C[l / 16 + 4 e][l % 16].
 // ---------------------------------------------------------------------------
-typedef double tcf_v4d __attribute__((ext_vector_type(4)));
 
 // Inverses of the 32 x 32 diagonal blocks of each job's lower factor:
 // D[(dprefix[job] + kb) * 1024 + r + 32 c] = (L_kb,kb)^-1 [r][c].  One block
