@@ -789,14 +789,14 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
   int* dp;
   RCCHK(h->upload(&dj, jobs));
   RCCHK(h->upload(&dp, pre));
-  if constexpr (std::is_same<T, double>::value) {
-    // FP64 on the matrix cores: the inverses of the 32 x 32 diagonal blocks
+  {
+    // on the matrix cores: the inverses of the 32 x 32 diagonal blocks
     // first, then the blocked solve
     std::vector<int> dcnt;
     for (auto& j : jobs) dcnt.push_back(j.n / TCF_NB);
     std::vector<int> dpre = prefix_of(dcnt);
     int* ddp;
-    double* D;
+    T* D;
     RCCHK(h->upload(&ddp, dpre));
     RCCHK(h->alloc(&D, (size_t)dpre.back() * TCF_NB * TCF_NB));
     launch_trsm_dinv(dj, ddp, (int)jobs.size(), dpre.back(), L, D, st);
@@ -812,7 +812,7 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
       for (int x = 0; x < nj; ++x) {
         tab[(size_t)st_i * (nj + 1) + x] = acc;
         const int nb = dcnt[x];
-        const int rows = fwd ? std::max(0, nb - P * (st_i + 1)) : std::max(0, nb - P * (st_i + 1));
+        const int rows = std::max(0, nb - P * (st_i + 1));  // same count both ways
         acc += rows * cnt[x];
       }
       tab[(size_t)st_i * (nj + 1) + nj] = acc;
@@ -829,10 +829,6 @@ static int run_trsm(tcf_problem* h, int fwd, const std::vector<TrsmJob>& jobs, c
     h->release(dtab);
     h->release(D);
     h->release(ddp);
-  } else {
-    launch_trsm<T>(fwd, dj, dp, (int)jobs.size(), pre.back(), L, B, st);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
   }
   h->release(dj);
   h->release(dp);

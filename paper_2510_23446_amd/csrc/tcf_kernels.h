@@ -41,17 +41,16 @@ template <class T>
 void launch_coarse_add(const DevPatch* P, int s, int n_p, const int* p_rank, const T* A,
                        double* SPi, int ldc, hipStream_t st);
 void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st);
-void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total,
-                      const double* L, double* D, hipStream_t st);
-int trsm_rl_panel();
-void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
-                         int total, int s, int fwd, const double* L, const double* D, double* B,
-                         hipStream_t st);
-void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
-                           int fwd, const double* L, double* B, hipStream_t st);
 template <class T>
-void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int total,
-                 const T* L, T* B, hipStream_t st);
+void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total, const T* L,
+                      T* D, hipStream_t st);
+int trsm_rl_panel();
+template <class T>
+void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
+                         int total, int s, int fwd, const T* L, const T* D, T* B, hipStream_t st);
+template <class T>
+void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
+                           int fwd, const T* L, T* B, hipStream_t st);
 template <class T>
 void launch_dotcols(const DotJob* jobs, const int* prefix, int njobs, int total, int max_rows,
                     const T* M, int xmode, const double* xv, const int* gidx,

@@ -19,6 +19,32 @@
 
 // 4-wide FP64 accumulator of v_mfma_f64_16x16x4
 typedef double tcf_v4d __attribute__((ext_vector_type(4)));
+typedef float tcf_v4f __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 matrix-core product per element type, FP32 accumulating
+// in FP32 and FP64 in FP64.  Both take A[l % 16][l / 16] and
+// B[l / 16][l % 16] from lane l; they differ in where the 16 x 16 result
+// lands (checked by probes on the device): element e of lane l is
+// C[row(l / 16, e)][l % 16] with row = l/16 + 4 e for FP64 and
+// 4 (l/16) + e for FP32.
+template <class T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+  typedef tcf_v4d acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int e) { return lk + 4 * e; }
+};
+template <>
+struct Mfma16<float> {
+  typedef tcf_v4f acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int e) { return 4 * lk + e; }
+};
 
 namespace tcf {
 
@@ -568,38 +594,40 @@ __global__ void k_syrk_blk(const FactorJob* jobs, const int* prefix, int njobs, 
   __shared__ T LJ[TCF_NB][64 + 1];
   T* a = A + jb.off;
   const int64_t ld = jb.ld;
-  if constexpr (std::is_same<T, double>::value) {
-    // FP64 on the matrix cores: wave w owns rows 32 (w & 1) .. + 32 and
-    // columns 32 (w >> 1) .. + 32 of the tile as 2 x 2 subtiles of 16 x 16.
-    // The operands are swapped (A from LJ, B from LI), so the accumulator
-    // holds C^T: element e of lane l is C[rb + l % 16][cb + l / 16 + 4 e],
-    // i.e. lanes run along rows and the update of C stays coalesced.
+  {
+    // On the matrix cores (Mfma16<T>: FP64 in FP64, FP32 accumulating in
+    // FP32): wave w owns rows 32 (w & 1) .. + 32 and columns
+    // 32 (w >> 1) .. + 32 of the tile as 2 x 2 subtiles of 16 x 16.  The
+    // operands are swapped (A from LJ, B from LI), so the accumulator holds
+    // C^T: element e of lane l is C[rb + l % 16][cb + row(l / 16, e)], i.e.
+    // lanes run along rows and the update of C stays coalesced.
+    typedef Mfma16<T> M;
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
     const int rb = 32 * (w & 1), cb = 32 * (w >> 1);
-    tcf_v4d acc4[2][2];
+    typename M::acc acc4[2][2];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int v = 0; v < 2; ++v) acc4[u][v] = tcf_v4d{0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < 2; ++v) acc4[u][v] = typename M::acc{T(0), T(0), T(0), T(0)};
     for (int kc = k0; kc < k1; kc += TCF_NB) {
       __syncthreads();
       for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
         const int r = idx % 64, c = idx / 64;
-        LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(kc + c) * ld] : 0.0;
-        LJ[c][r] = (cl0 + r < cmax) ? a[(cl0 + r) + (int64_t)(kc + c) * ld] : 0.0;
+        LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(kc + c) * ld] : T(0);
+        LJ[c][r] = (cl0 + r < cmax) ? a[(cl0 + r) + (int64_t)(kc + c) * ld] : T(0);
       }
       __syncthreads();
 #pragma unroll
       for (int k4 = 0; k4 < TCF_NB; k4 += 4) {
-        const double b0 = LI[k4 + lk][rb + li], b1 = LI[k4 + lk][rb + 16 + li];
-        const double a0 = LJ[k4 + lk][cb + li], a1 = LJ[k4 + lk][cb + 16 + li];
-        acc4[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc4[0][0], 0, 0, 0);
-        acc4[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc4[0][1], 0, 0, 0);
-        acc4[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc4[1][0], 0, 0, 0);
-        acc4[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc4[1][1], 0, 0, 0);
+        const T b0 = LI[k4 + lk][rb + li], b1 = LI[k4 + lk][rb + 16 + li];
+        const T a0 = LJ[k4 + lk][cb + li], a1 = LJ[k4 + lk][cb + 16 + li];
+        acc4[0][0] = M::mma(a0, b0, acc4[0][0]);
+        acc4[0][1] = M::mma(a1, b0, acc4[0][1]);
+        acc4[1][0] = M::mma(a0, b1, acc4[1][0]);
+        acc4[1][1] = M::mma(a1, b1, acc4[1][1]);
       }
     }
-    // acc4[u][v]: rows rb + 16 u + li, columns cb + 16 v + lk + 4 e
+    // acc4[u][v]: rows rb + 16 u + li, columns cb + 16 v + row(lk, e)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -607,45 +635,9 @@ __global__ void k_syrk_blk(const FactorJob* jobs, const int* prefix, int njobs, 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int R = row0 + rb + 16 * u + li;
-          const int C = cl0 + cb + 16 * v + lk + 4 * e;
+          const int C = cl0 + cb + 16 * v + M::row(lk, e);
           if (R < n && C < cmax && R >= C) a[R + (int64_t)C * ld] -= acc4[u][v][e];
         }
-    return;
-  }
-  const int tr = threadIdx.x % 16, tc = threadIdx.x / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[i][q] = T(0);
-  for (int kc = k0; kc < k1; kc += TCF_NB) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
-      const int r = idx % 64, c = idx / 64;
-      LI[c][r] = (row0 + r < n) ? a[(row0 + r) + (int64_t)(kc + c) * ld] : T(0);
-      LJ[c][r] = (cl0 + r < cmax) ? a[(cl0 + r) + (int64_t)(kc + c) * ld] : T(0);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int c = 0; c < TCF_NB; ++c) {
-      T li[4], lj[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) { li[i] = LI[c][tr + 16 * i]; lj[i] = LJ[c][tc + 16 * i]; }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[i][q] += li[i] * lj[q];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int C = cl0 + tc + 16 * q;
-    if (C >= cmax) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int R = row0 + tr + 16 * i;
-      if (R < n && R >= C) a[R + (int64_t)C * ld] -= acc[i][q];
-    }
   }
 }
 
@@ -730,95 +722,25 @@ __global__ void k_set_identity_pad(double* M, int ld, int n0, int n) {
   M[(n0 + i) + (int64_t)(n0 + i) * ld] = 1.0;
 }
 
-// ===========================================================================
-// Multi-RHS triangular solves: 32-row blocks, 64 right-hand sides per block
-// ===========================================================================
-template <class T>
-__global__ void k_trsm_fwd(const TrsmJob* jobs, const int* prefix, int njobs, const T* Lb, T* Bb) {
-  const int jx = find_job(prefix, njobs, blockIdx.x);
-  const TrsmJob jb = jobs[jx];
-  const int c0 = (blockIdx.x - prefix[jx]) * 64;
-  __shared__ T Ls[TCF_NB][TCF_NB + 1];
-  __shared__ T Xs[TCF_NB][64 + 1];
-  __shared__ T Acc[TCF_NB][64 + 1];
-  const T* L = Lb + jb.l_off;
-  T* B = Bb + jb.b_off;
-  const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;  // cg in 0..7
-  const int nblk = jb.n / TCF_NB;
-  const int64_t ldl = jb.ldl, ldb = jb.ldb;
-  // identity right-hand sides: L^-1 I is lower triangular, so the rows above
-  // this column block stay zero and contribute nothing
-  const int kmin = (c0 + 64 <= jb.tri) ? c0 / TCF_NB : 0;
-  for (int kb = kmin; kb < nblk; ++kb) {
-    T acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int col = c0 + cg + 8 * q;
-      acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
-    }
-    for (int jblk = kmin; jblk < kb; ++jblk) {
-      __syncthreads();
-      for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
-        const int r = idx % TCF_NB, c = idx / TCF_NB;
-        Ls[r][c] = L[(jb.l_row0 + kb * TCF_NB + r) + (int64_t)(jb.l_row0 + jblk * TCF_NB + c) * ldl];
-      }
-      for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
-        const int r = idx % TCF_NB, c = idx / TCF_NB;
-        const int col = c0 + c;
-        Xs[r][c] = (col < jb.ncols) ? B[(jblk * TCF_NB + r) + col * ldb] : T(0);
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int l = 0; l < TCF_NB; ++l) {
-        const T lv = Ls[tr][l];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] -= lv * Xs[l][cg + 8 * q];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Acc[tr][cg + 8 * q] = acc[q];
-    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
-      const int r = idx % TCF_NB, c = idx / TCF_NB;
-      Ls[r][c] = L[(jb.l_row0 + kb * TCF_NB + r) + (int64_t)(jb.l_row0 + kb * TCF_NB + c) * ldl];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int c = threadIdx.x;
-      for (int r = 0; r < TCF_NB; ++r) {
-        T v = Acc[r][c];
-        for (int l = 0; l < r; ++l) v -= Ls[r][l] * Acc[l][c];
-        Acc[r][c] = v / Ls[r][r];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int col = c0 + cg + 8 * q;
-      if (col < jb.ncols) B[(kb * TCF_NB + tr) + col * ldb] = Acc[tr][cg + 8 * q];
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
-// FP64 triangular solves on the matrix cores (v_mfma_f64_16x16x4).  Lane
-// layout of that instruction (checked by a probe on the device): lane l
-// holds A[l % 16][l / 16] and B[l / 16][l % 16]; element e of the 4-wide
-// accumulator is C[l / 16 + 4 e][l % 16].
+// Triangular solves on the matrix cores: FP64 in FP64, FP32 accumulating
+// in FP32 (Mfma16<T> holds the instruction and its lane layout).
 // ---------------------------------------------------------------------------
 
 // Inverses of the 32 x 32 diagonal blocks of each job's lower factor:
 // D[(dprefix[job] + kb) * 1024 + r + 32 c] = (L_kb,kb)^-1 [r][c].  One block
 // of 64 threads per diagonal block; thread c < 32 forward-substitutes the
 // unit vector e_c.
+template <class T>
 __global__ void __launch_bounds__(64) k_trsm_dinv(const TrsmJob* jobs, const int* dprefix,
-                                                  int njobs, const double* Lb, double* D) {
+                                                  int njobs, const T* Lb, T* D) {
   const int jx = find_job(dprefix, njobs, blockIdx.x);
   const TrsmJob jb = jobs[jx];
   const int kb = blockIdx.x - dprefix[jx];
-  __shared__ double Ls[TCF_NB][TCF_NB + 1];
-  __shared__ double Ys[TCF_NB][TCF_NB + 1];
-  const double* L = Lb + jb.l_off;
+  __shared__ T Ls[TCF_NB][TCF_NB + 1];
+  __shared__ T Ys[TCF_NB][TCF_NB + 1];
+  const T* L = Lb + jb.l_off;
   const int64_t ldl = jb.ldl;
   for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 64) {
     const int r = idx % TCF_NB, c = idx / TCF_NB;
@@ -828,7 +750,7 @@ __global__ void __launch_bounds__(64) k_trsm_dinv(const TrsmJob* jobs, const int
   const int c = threadIdx.x;
   if (c < TCF_NB) {
     for (int r = 0; r < TCF_NB; ++r) {
-      double v = (r == c) ? 1.0 : 0.0;
+      T v = (r == c) ? T(1) : T(0);
       if (r >= c) {
         for (int l = c; l < r; ++l) v -= Ls[r][l] * Ys[l][c];
         v /= Ls[r][r];
@@ -837,7 +759,7 @@ __global__ void __launch_bounds__(64) k_trsm_dinv(const TrsmJob* jobs, const int
     }
   }
   __syncthreads();
-  double* out = D + (int64_t)blockIdx.x * TCF_NB * TCF_NB;
+  T* out = D + (int64_t)blockIdx.x * TCF_NB * TCF_NB;
   for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 64) {
     const int r = idx % TCF_NB, cc = idx / TCF_NB;
     out[idx] = Ys[r][cc];
@@ -868,8 +790,9 @@ __device__ inline bool rl_zero_block(const TrsmJob& jb, int kb, int c0, int fwd)
 
 // Stage the 32 x 32 block of L at row block lr, column block lc into Ls and
 // the 32 x 64 block of B at row block kb, columns c0.., into Xs.
-__device__ inline void rl_stage(const TrsmJob& jb, const double* L, const double* B, int lr, int lc,
-                                int kb, int c0, double (*Ls)[TCF_NB + 1], double (*Xs)[64 + 1]) {
+template <class T>
+__device__ inline void rl_stage(const TrsmJob& jb, const T* L, const T* B, int lr, int lc, int kb,
+                                int c0, T (*Ls)[TCF_NB + 1], T (*Xs)[64 + 1]) {
   const int64_t ldl = jb.ldl, ldb = jb.ldb;
   for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256) {
     const int r = idx % TCF_NB, c = idx / TCF_NB;
@@ -877,36 +800,39 @@ __device__ inline void rl_stage(const TrsmJob& jb, const double* L, const double
   }
   for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += 256) {
     const int r = idx % TCF_NB, c = idx / TCF_NB;
-    Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : 0.0;
+    Xs[r][c] = (c0 + c < jb.ncols) ? B[(kb * TCF_NB + r) + (int64_t)(c0 + c) * ldb] : T(0);
   }
 }
 
 // acc -= A X with A = Ls (forward) or Ls^T (backward), X = Xs, for the
 // wave's 16 columns and both 16-row halves
-__device__ inline void rl_mfma_sub(const double (*Ls)[TCF_NB + 1], const double (*Xs)[64 + 1],
-                                   int fwd, int w, int li, int lk, tcf_v4d& a0, tcf_v4d& a1) {
+template <class T>
+__device__ inline void rl_mfma_sub(const T (*Ls)[TCF_NB + 1], const T (*Xs)[64 + 1], int fwd, int w,
+                                   int li, int lk, typename Mfma16<T>::acc& a0,
+                                   typename Mfma16<T>::acc& a1) {
 #pragma unroll
   for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
-    const double bv = Xs[k0 + lk][16 * w + li];
-    const double v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
-    const double v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
-    a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v0, bv, a0, 0, 0, 0);
-    a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(-v1, bv, a1, 0, 0, 0);
+    const T bv = Xs[k0 + lk][16 * w + li];
+    const T v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
+    const T v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
+    a0 = Mfma16<T>::mma(-v0, bv, a0);
+    a1 = Mfma16<T>::mma(-v1, bv, a1);
   }
 }
 
+template <class T>
 __global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix,
                                                       const int* dprefix, int njobs, int s,
-                                                      int fwd, const double* Lb, const double* D,
-                                                      double* Bb) {
+                                                      int fwd, const T* Lb, const T* D, T* Bb) {
+  typedef Mfma16<T> M;
   const int jx = find_job(cprefix, njobs, blockIdx.x);
   const TrsmJob jb = jobs[jx];
   const int nblk = jb.n / TCF_NB;
   const int c0 = (blockIdx.x - cprefix[jx]) * 64;
-  __shared__ double Ls[TCF_NB][TCF_NB + 1];
-  __shared__ double Xs[TCF_NB][64 + 1];
-  const double* L = Lb + jb.l_off;
-  double* B = Bb + jb.b_off;
+  __shared__ T Ls[TCF_NB][TCF_NB + 1];
+  __shared__ T Xs[TCF_NB][64 + 1];
+  const T* L = Lb + jb.l_off;
+  T* B = Bb + jb.b_off;
   const int64_t ldb = jb.ldb;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
   const int col = c0 + 16 * w + li;
@@ -915,11 +841,11 @@ __global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const
     const int kb = rl_kb(jb, s, i, fwd);
     if (kb < 0 || kb >= nblk) break;
     if (rl_zero_block(jb, kb, c0, fwd)) continue;
-    tcf_v4d a0, a1;
+    typename M::acc a0, a1;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      a0[e] = colok ? B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
-      a1[e] = colok ? B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] : 0.0;
+      a0[e] = colok ? B[(kb * TCF_NB + M::row(lk, e)) + (int64_t)col * ldb] : T(0);
+      a1[e] = colok ? B[(kb * TCF_NB + 16 + M::row(lk, e)) + (int64_t)col * ldb] : T(0);
     }
     // earlier blocks of this panel (already solved and stored by this block)
     for (int q = 0; q < i; ++q) {
@@ -934,27 +860,27 @@ __global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      Xs[lk + 4 * e][16 * w + li] = a0[e];
-      Xs[16 + lk + 4 * e][16 * w + li] = a1[e];
+      Xs[M::row(lk, e)][16 * w + li] = a0[e];
+      Xs[16 + M::row(lk, e)][16 * w + li] = a1[e];
     }
-    const double* Dk = D + ((int64_t)dprefix[jx] + kb) * TCF_NB * TCF_NB;
+    const T* Dk = D + ((int64_t)dprefix[jx] + kb) * TCF_NB * TCF_NB;
     for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += 256)
       Ls[idx % TCF_NB][idx / TCF_NB] = Dk[idx];
     __syncthreads();
-    tcf_v4d x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+    typename M::acc x0 = {T(0), T(0), T(0), T(0)}, x1 = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int k0 = 0; k0 < TCF_NB; k0 += 4) {
-      const double bv = Xs[k0 + lk][16 * w + li];
-      const double v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
-      const double v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
-      x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, bv, x0, 0, 0, 0);
-      x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, bv, x1, 0, 0, 0);
+      const T bv = Xs[k0 + lk][16 * w + li];
+      const T v0 = fwd ? Ls[li][k0 + lk] : Ls[k0 + lk][li];
+      const T v1 = fwd ? Ls[16 + li][k0 + lk] : Ls[k0 + lk][16 + li];
+      x0 = M::mma(v0, bv, x0);
+      x1 = M::mma(v1, bv, x1);
     }
     if (colok) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        B[(kb * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] = x0[e];
-        B[(kb * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] = x1[e];
+        B[(kb * TCF_NB + M::row(lk, e)) + (int64_t)col * ldb] = x0[e];
+        B[(kb * TCF_NB + 16 + M::row(lk, e)) + (int64_t)col * ldb] = x1[e];
       }
     }
     __syncthreads();  // the stores are read back by the next block of the panel
@@ -964,9 +890,11 @@ __global__ void __launch_bounds__(256) k_trsm_rl_diag(const TrsmJob* jobs, const
 // tprefix: row s of a (steps x (njobs + 1)) table, the prefix over jobs of
 // the tiles that step s updates (row blocks after the panel forward, before
 // it backward, times column blocks)
+template <class T>
 __global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, const int* tprefix,
-                                                        int njobs, int s, int fwd,
-                                                        const double* Lb, double* Bb) {
+                                                        int njobs, int s, int fwd, const T* Lb,
+                                                        T* Bb) {
+  typedef Mfma16<T> M;
   const int jx = find_job(tprefix, njobs, blockIdx.x);
   const TrsmJob jb = jobs[jx];
   const int nblk = jb.n / TCF_NB;
@@ -975,15 +903,15 @@ __global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, con
   const int first = fwd ? TCF_RL_PANEL * (s + 1) : 0;  // first row block updated
   const int j = first + t / ncb;
   const int c0 = (t % ncb) * 64;
-  __shared__ double Ls[TCF_NB][TCF_NB + 1];
-  __shared__ double Xs[TCF_NB][64 + 1];
-  const double* L = Lb + jb.l_off;
-  double* B = Bb + jb.b_off;
+  __shared__ T Ls[TCF_NB][TCF_NB + 1];
+  __shared__ T Xs[TCF_NB][64 + 1];
+  const T* L = Lb + jb.l_off;
+  T* B = Bb + jb.b_off;
   const int64_t ldb = jb.ldb;
   const int w = threadIdx.x / 64, lane = threadIdx.x % 64, li = lane % 16, lk = lane / 16;
   const int col = c0 + 16 * w + li;
   const bool colok = col < jb.ncols;
-  tcf_v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  typename M::acc a0 = {T(0), T(0), T(0), T(0)}, a1 = {T(0), T(0), T(0), T(0)};
   bool any = false;
   for (int i = 0; i < TCF_RL_PANEL; ++i) {
     const int kb = rl_kb(jb, s, i, fwd);
@@ -998,79 +926,11 @@ __global__ void __launch_bounds__(256) k_trsm_rl_update(const TrsmJob* jobs, con
   if (!any || !colok) return;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    B[(j * TCF_NB + lk + 4 * e) + (int64_t)col * ldb] += a0[e];
-    B[(j * TCF_NB + 16 + lk + 4 * e) + (int64_t)col * ldb] += a1[e];
+    B[(j * TCF_NB + M::row(lk, e)) + (int64_t)col * ldb] += a0[e];
+    B[(j * TCF_NB + 16 + M::row(lk, e)) + (int64_t)col * ldb] += a1[e];
   }
 }
 
-// Solve L^T X = B (backward substitution with the transposed lower block).
-template <class T>
-__global__ void k_trsm_bwd(const TrsmJob* jobs, const int* prefix, int njobs, const T* Lb, T* Bb) {
-  const int jx = find_job(prefix, njobs, blockIdx.x);
-  const TrsmJob jb = jobs[jx];
-  const int c0 = (blockIdx.x - prefix[jx]) * 64;
-  __shared__ T Ls[TCF_NB][TCF_NB + 1];
-  __shared__ T Xs[TCF_NB][64 + 1];
-  __shared__ T Acc[TCF_NB][64 + 1];
-  const T* L = Lb + jb.l_off;
-  T* B = Bb + jb.b_off;
-  const int tr = threadIdx.x % TCF_NB, cg = threadIdx.x / TCF_NB;
-  const int nblk = jb.n / TCF_NB;
-  const int64_t ldl = jb.ldl, ldb = jb.ldb;
-  // identity right-hand sides: L^-T I is upper triangular, so the rows below
-  // this column block stay zero and contribute nothing
-  const int kmax = (c0 + 64 <= jb.tri) ? min(nblk - 1, (c0 + 63) / TCF_NB) : nblk - 1;
-  for (int kb = kmax; kb >= 0; --kb) {
-    T acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int col = c0 + cg + 8 * q;
-      acc[q] = (col < jb.ncols) ? B[(kb * TCF_NB + tr) + col * ldb] : T(0);
-    }
-    for (int jblk = kb + 1; jblk <= kmax; ++jblk) {
-      __syncthreads();
-      // Ls[l][r] = L[jblk*NB + l, kb*NB + r]
-      for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
-        const int l = idx % TCF_NB, r = idx / TCF_NB;
-        Ls[l][r] = L[(jb.l_row0 + jblk * TCF_NB + l) + (int64_t)(jb.l_row0 + kb * TCF_NB + r) * ldl];
-      }
-      for (int idx = threadIdx.x; idx < TCF_NB * 64; idx += blockDim.x) {
-        const int r = idx % TCF_NB, c = idx / TCF_NB;
-        const int col = c0 + c;
-        Xs[r][c] = (col < jb.ncols) ? B[(jblk * TCF_NB + r) + col * ldb] : T(0);
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int l = 0; l < TCF_NB; ++l) {
-        const T lv = Ls[l][tr];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] -= lv * Xs[l][cg + 8 * q];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) Acc[tr][cg + 8 * q] = acc[q];
-    for (int idx = threadIdx.x; idx < TCF_NB * TCF_NB; idx += blockDim.x) {
-      const int l = idx % TCF_NB, r = idx / TCF_NB;
-      Ls[l][r] = L[(jb.l_row0 + kb * TCF_NB + l) + (int64_t)(jb.l_row0 + kb * TCF_NB + r) * ldl];
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int c = threadIdx.x;
-      for (int r = TCF_NB - 1; r >= 0; --r) {
-        T v = Acc[r][c];
-        for (int l = r + 1; l < TCF_NB; ++l) v -= Ls[l][r] * Acc[l][c];
-        Acc[r][c] = v / Ls[r][r];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int col = c0 + cg + 8 * q;
-      if (col < jb.ncols) B[(kb * TCF_NB + tr) + col * ldb] = Acc[tr][cg + 8 * q];
-    }
-  }
-}
 
 // ===========================================================================
 // Per-step matrix-vector products (FP64 vectors, T-typed matrices)
@@ -1852,33 +1712,26 @@ void launch_identity_pad(double* M, int ld, int n0, int n, hipStream_t st) {
   if (n <= n0) return;
   hipLaunchKernelGGL(k_set_identity_pad, TCF_GRID(n - n0, 256), dim3(256), 0, st, M, ld, n0, n);
 }
-void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total,
-                      const double* L, double* D, hipStream_t st) {
+template <class T>
+void launch_trsm_dinv(const TrsmJob* jobs, const int* dprefix, int njobs, int total, const T* L,
+                      T* D, hipStream_t st) {
   if (total == 0) return;
-  hipLaunchKernelGGL(k_trsm_dinv, dim3(total), dim3(64), 0, st, jobs, dprefix, njobs, L, D);
+  hipLaunchKernelGGL(k_trsm_dinv<T>, dim3(total), dim3(64), 0, st, jobs, dprefix, njobs, L, D);
 }
 int trsm_rl_panel() { return TCF_RL_PANEL; }
+template <class T>
 void launch_trsm_rl_diag(const TrsmJob* jobs, const int* cprefix, const int* dprefix, int njobs,
-                         int total, int s, int fwd, const double* L, const double* D, double* B,
-                         hipStream_t st) {
+                         int total, int s, int fwd, const T* L, const T* D, T* B, hipStream_t st) {
   if (total == 0) return;
-  hipLaunchKernelGGL(k_trsm_rl_diag, dim3(total), dim3(256), 0, st, jobs, cprefix, dprefix, njobs,
-                     s, fwd, L, D, B);
-}
-void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
-                           int fwd, const double* L, double* B, hipStream_t st) {
-  if (total == 0) return;
-  hipLaunchKernelGGL(k_trsm_rl_update, dim3(total), dim3(256), 0, st, jobs, tprefix, njobs, s, fwd,
-                     L, B);
+  hipLaunchKernelGGL(k_trsm_rl_diag<T>, dim3(total), dim3(256), 0, st, jobs, cprefix, dprefix,
+                     njobs, s, fwd, L, D, B);
 }
 template <class T>
-void launch_trsm(int fwd, const TrsmJob* jobs, const int* prefix, int njobs, int total,
-                 const T* L, T* B, hipStream_t st) {
+void launch_trsm_rl_update(const TrsmJob* jobs, const int* tprefix, int njobs, int total, int s,
+                           int fwd, const T* L, T* B, hipStream_t st) {
   if (total == 0) return;
-  if (fwd)
-    hipLaunchKernelGGL(k_trsm_fwd<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, L, B);
-  else
-    hipLaunchKernelGGL(k_trsm_bwd<T>, dim3(total), dim3(256), 0, st, jobs, prefix, njobs, L, B);
+  hipLaunchKernelGGL(k_trsm_rl_update<T>, dim3(total), dim3(256), 0, st, jobs, tprefix, njobs, s,
+                     fwd, L, B);
 }
 // Optional timing events for the next timed launch of this thread: attached
 // to the dispatch packet itself (hipExtLaunchKernelGGL), so their interval
@@ -2057,7 +1910,8 @@ void launch_to_global(int64_t n, const int64_t* gid, const double* a, double* ou
   template void launch_potrf<T>(const FactorJob*, int, int, T*, int*, hipStream_t);              \
   template void launch_trsm_panel<T>(const FactorJob*, const int*, int, int, int, T*,            \
                                      hipStream_t);                                               \
-  template void launch_syrk<T>(const FactorJob*, const int*, int, int, int, int, T*, hipStream_t);    \
+  template void launch_syrk<T>(const FactorJob*, const int*, int, int, int, int, T*,             \
+                               hipStream_t);                                                     \
   template void launch_copy_sbb<T>(const DevPatch*, const int*, int, int, const T*, T*,          \
                                    hipStream_t);                                                 \
   template void launch_fill_G<T>(const DevPatch*, const int*, int, int, const T*, T*,            \
@@ -2066,8 +1920,12 @@ void launch_to_global(int64_t n, const int64_t* gid, const double* a, double* ou
                                  hipStream_t);                                                   \
   template void launch_coarse_add<T>(const DevPatch*, int, int, const int*, const T*, double*,   \
                                      int, hipStream_t);                                          \
-  template void launch_trsm<T>(int, const TrsmJob*, const int*, int, int, const T*, T*,          \
-                               hipStream_t);                                                     \
+  template void launch_trsm_dinv<T>(const TrsmJob*, const int*, int, int, const T*, T*,         \
+                                    hipStream_t);                                                \
+  template void launch_trsm_rl_diag<T>(const TrsmJob*, const int*, const int*, int, int, int,    \
+                                       int, const T*, const T*, T*, hipStream_t);                \
+  template void launch_trsm_rl_update<T>(const TrsmJob*, const int*, int, int, int, int,         \
+                                         const T*, T*, hipStream_t);                             \
   template void launch_dotcols<T>(const DotJob*, const int*, int, int, int, const T*, int,       \
                                   const double*, const int*, const signed char*, double,         \
                                   double*, const int*, hipStream_t);                             \
