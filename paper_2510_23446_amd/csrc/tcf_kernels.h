@@ -108,7 +108,6 @@ void launch_build_z(int64_t n, const signed char* is_int, const double* y, const
 namespace tcf {
 void launch_asm_norm2(int n, const int* ptr, const int* idx, const double* x, int first_copy,
                       double* partial, double* out, hipStream_t st);
-void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t st);
 }  // namespace tcf
 namespace tcf {
 void launch_to_float(int64_t n, const double* a, float* b, hipStream_t st);

@@ -1979,21 +1979,12 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double* partial, int
   const double s = sum_partials(partial, npart, sh);
   if (threadIdx.x == 0) *out = s;
 }
-// out = a - b (elementwise)
-__global__ void k_sub(int64_t n, const double* a, const double* b, double* out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = a[i] - b[i];
-}
 void launch_asm_norm2(int n, const int* ptr, const int* idx, const double* x, int first_copy,
                       double* partial, double* out, hipStream_t st) {
   const int nb = (n + 255) / 256;
   if (n == 0) return;
   hipLaunchKernelGGL(k_asm_norm2, dim3(nb), dim3(256), 0, st, n, ptr, idx, x, first_copy, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, nb, out);
-}
-void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t st) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_sub, TCF_GRID(n, 256), dim3(256), 0, st, n, a, b, out);
 }
 }  // namespace tcf
 
