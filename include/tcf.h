@@ -3,7 +3,10 @@
  *
  * The library advances the time-domain A*-formulation
  *     curl(nu curl A) + sigma dA/dt = J,   n x A = 0 on the outer boundary
- * (Sec. 2, A*-formulation with PEC boundary) discretised by curl-conforming
+ * (Sec. 2, A*-formulation with PEC boundary; inhomogeneous n x A data is
+ * posed through a lifting, i.e. as the homogenised problem with the volume
+ * source jvol and the initial value ainit of tcf_problem_desc, Sec. 2.1)
+ * discretised by curl-conforming
  * spline patches (Sec. 2.2) with implicit Euler (Sec. 2.2, implicit Euler
  * system W = M + dt K, f = M a^(l) + dt j^(l+1)).  Every step is solved by the
  * dual-primal tearing of Sec. 3: per-patch remainder solves, a signed jump
@@ -57,8 +60,10 @@ enum tcf_precision {
                         /* applied in FP32; PCG, coarse solve and refinement   */
                         /* residual in FP64                                    */
   TCF_FP32_FULL_IR = 2  /* as TCF_FP32_IR but the local factorisation is FP32 */
-                        /* too (converges only where the local blocks are well */
-                        /* conditioned, e.g. conductors)                       */
+                        /* too, on the FP32 matrix cores with FP32             */
+                        /* accumulation (converges only where the local blocks */
+                        /* are well conditioned, e.g. conductors; see          */
+                        /* tcf_get_cond_est)                                   */
 };
 
 /*
