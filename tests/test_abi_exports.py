@@ -2,6 +2,8 @@
 import os
 import re
 
+import pytest
+
 from paper_2510_23446_amd import tcf
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -32,3 +34,35 @@ def test_default_options_and_error_string():
     o = tcf.default_options()
     assert o.precision == tcf.TCF_FP64 and o.pcg_rtol == 1e-10
     assert isinstance(tcf.lib().tcf_last_error(None), bytes)
+
+
+def test_c_program_uses_the_abi_without_a_gpu(tmp_path):
+    """A plain C program includes tcf.h, links libtcf.so, describes the
+    2x2x2-patch cube and creates the handle (host work only): its topology
+    counts and footprints equal the binding's, and the error paths return
+    the documented codes."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2510_23446_amd")
+    exe = str(tmp_path / "c_abi_host")
+    cmd = [gcc, "-std=c99", "-O1", os.path.join(root, "tests", "c_abi_host.c"),
+           "-I", os.path.join(root, "include"), "-L", pkg, "-ltcf", "-lm",
+           "-Wl,-rpath," + pkg, "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    lines = dict(l.split(" ", 1) for l in r.stdout.strip().splitlines())
+    import workloads as W
+    from paper_2510_23446_amd import tcf
+    p = tcf.Problem(W.plain_fp64())
+    want = [int(v) for v in p.tcf_get_topology(tcf.TCF_TOPO_COUNTS)]
+    assert [int(v) for v in lines["counts"].split()] == want
+    b64, b32 = p.tcf_footprint()
+    assert [int(v) for v in lines["footprint"].split()] == [b64, b32]
+    assert int(lines["step_before_setup"]) == tcf.TCF_ESTATE
+    assert lines["negative_sigma"].split() == [str(tcf.TCF_EINVAL), "null"]
