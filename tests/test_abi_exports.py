@@ -1,4 +1,5 @@
-"""The C-ABI library loads without a GPU and exports every declared symbol."""
+"""The C-ABI library loads without a GPU, exports every declared symbol, and
+serves a plain C program (host-side calls)."""
 import os
 import re
 
