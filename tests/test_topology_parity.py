@@ -148,3 +148,21 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stdout
+
+
+def test_full_size_checkerboard_plan():
+    """Host plan of the 256-patch checkerboard at full size (8 x 8 x 4 patches,
+    p = 3, n = 12).  The edge count is the control-grid closed form over the
+    three edge directions, with N_x = N_y = 8 (12 + 2) + 1 and
+    N_z = 4 (12 + 2) + 1 nodes.  The gauged, dual and primal counts are the
+    sizes derived from the gauge and split rules (every Gamma-face tree is
+    primal)."""
+    prob = W.largest_multirhs(n=12, n_steps=1)
+    c = tcf.Problem(prob).counts()
+    Nx = Ny = 8 * (12 + 3 - 1) + 1
+    Nz = 4 * (12 + 3 - 1) + 1
+    edges = (Nx - 1) * Ny * Nz + Nx * (Ny - 1) * Nz + Nx * Ny * (Nz - 1)
+    assert c["n_edges"] == edges == 2157848
+    assert c["n_kept"] == 1776280
+    assert c["n_lambda"] == 124800
+    assert c["n_primal"] == 115608
