@@ -11,6 +11,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/tcf.h"
@@ -59,16 +60,24 @@ struct tcf_server {
   bool stopping = false;
   double t_first_admit = -1, t_last_done = -1;
   std::thread dispatcher;
-  std::vector<std::thread> workers;
+  // worker threads of admitted requests not yet joined; finished ones are
+  // joined at the next admission, so at most about 2 max_slots stay here
+  std::vector<std::pair<Request*, std::thread>> workers;
 
   void run_request(Request* r);
   void dispatch_loop();
+  void reap_finished(std::unique_lock<std::mutex>& lk);
 };
 
 void tcf_server::run_request(Request* r) {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
-  int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? TCF_OK : TCF_EHIP;
+  const hipError_t se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  int rc = se == hipSuccess ? TCF_OK : TCF_EHIP;
+  if (rc != TCF_OK) {
+    st = nullptr;
+    r->err = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
+  }
   if (rc == TCF_OK) rc = tcf_setup(r->h, st);
   if (rc == TCF_OK) {
     rc = tcf_step(r->h, 1 << 30, st);
@@ -88,7 +97,7 @@ void tcf_server::run_request(Request* r) {
       if (tcf_get_field(r->h, k, f.data(), f.size(), 0, st) != TCF_OK) break;
       r->fields.push_back(std::move(f));
     }
-  } else {
+  } else if (r->err.empty()) {
     r->err = std::string("status ") + std::to_string(rc) + ": " + tcf_last_error(r->h);
   }
   tcf_destroy(r->h);  // releases the request's device memory
@@ -104,6 +113,27 @@ void tcf_server::run_request(Request* r) {
   cv.notify_all();
 }
 
+// Joins the threads of finished requests, outside the lock.  A worker marks
+// its request DONE or FAILED as its last action under the lock and takes the
+// lock no more, so each join here waits only for the thread's own exit.
+void tcf_server::reap_finished(std::unique_lock<std::mutex>& lk) {
+  std::vector<std::thread> done;
+  for (size_t i = 0; i < workers.size();) {
+    const int st = workers[i].first->state;
+    if (st == TCF_REQ_DONE || st == TCF_REQ_FAILED) {
+      done.push_back(std::move(workers[i].second));
+      if (i + 1 != workers.size()) workers[i] = std::move(workers.back());
+      workers.pop_back();
+    } else {
+      ++i;
+    }
+  }
+  if (done.empty()) return;
+  lk.unlock();
+  for (auto& t : done) t.join();
+  lk.lock();
+}
+
 void tcf_server::dispatch_loop() {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
@@ -117,6 +147,7 @@ void tcf_server::dispatch_loop() {
       if (stopping) break;
       continue;
     }
+    reap_finished(lk);
     Request* r = reqs[queue.front()].get();
     queue.pop_front();
     r->state = TCF_REQ_RUNNING;
@@ -125,7 +156,7 @@ void tcf_server::dispatch_loop() {
     used += r->footprint;
     peak = std::max(peak, used);
     ++running;
-    workers.emplace_back([this, r] { run_request(r); });
+    workers.emplace_back(r, std::thread([this, r] { run_request(r); }));
   }
 }
 
@@ -254,7 +285,7 @@ void tcf_server_destroy(tcf_server* srv) {
   }
   if (srv->dispatcher.joinable()) srv->dispatcher.join();
   for (auto& w : srv->workers)
-    if (w.joinable()) w.join();
+    if (w.second.joinable()) w.second.join();
   for (auto& r : srv->reqs)
     if (r->h) tcf_destroy(r->h);
   delete srv;

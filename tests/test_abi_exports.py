@@ -67,3 +67,42 @@ def test_c_program_uses_the_abi_without_a_gpu(tmp_path):
     assert [int(v) for v in lines["footprint"].split()] == [b64, b32]
     assert int(lines["step_before_setup"]) == tcf.TCF_ESTATE
     assert lines["negative_sigma"].split() == [str(tcf.TCF_EINVAL), "null"]
+
+
+def _vm_size_mib():
+    with open("/proc/self/status") as f:
+        for line in f:
+            if line.startswith("VmSize"):
+                return int(line.split()[1]) / 1024.0
+    pytest.skip("no /proc/self/status")
+
+
+def test_server_lifecycle_without_a_device():
+    """With no HIP device every request fails at its worker's first HIP call.
+    The server must still admit, fail and count each one with a message, and
+    join finished workers as it goes: before that fix every finished worker
+    kept its thread stack (about 8 MiB of address space) until the server was
+    destroyed."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("checks the host-side path taken when no device is present")
+    import workloads as W
+
+    prob = W.plain_fp64().with_steps(1)
+    srv = tcf.Server(max_bytes=64 << 30, max_slots=4)
+    try:
+        first = [srv.tcf_server_submit(prob) for _ in range(32)]
+        assert all(srv.tcf_server_wait(i) == tcf.TCF_EHIP for i in first)
+        v0 = _vm_size_mib()
+        more = [srv.tcf_server_submit(prob) for _ in range(256)]
+        assert all(srv.tcf_server_wait(i) == tcf.TCF_EHIP for i in more)
+        grown = _vm_size_mib() - v0
+        assert grown < 64.0, f"address space grew by {grown:.0f} MiB over 256 requests"
+        assert "hipStreamCreateWithFlags" in srv.tcf_server_error(more[-1])
+        assert srv.tcf_server_poll(more[0]) == tcf.TCF_REQ_FAILED
+        st = srv.tcf_server_stats()
+        assert st["submitted"] == st["admitted"] == st["failed"] == 288
+        assert st["completed"] == st["running"] == st["queued"] == 0
+    finally:
+        srv.tcf_server_destroy()
