@@ -248,9 +248,12 @@ class Server:
 
     def tcf_server_submit(self, prob, **kw):
         d, o, keep = marshal(prob, **kw)
-        rid = C.c_int32()
+        rid = C.c_int32(-1)
         rc = lib().tcf_server_submit(self.s, C.byref(d), C.byref(o), C.byref(rid))
-        self._keep[rid.value] = (d, o, keep, prob)
+        # a description that tcf_create rejects gets no id; the callbacks of
+        # an admitted request must outlive its worker's setup
+        if rid.value >= 0:
+            self._keep[rid.value] = (d, o, keep, prob)
         if rc != TCF_OK:
             raise TcfError(rc, lib().tcf_last_error(None).decode())
         return rid.value

@@ -3,6 +3,7 @@ serves a plain C program (host-side calls)."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2510_23446_amd import tcf
@@ -101,6 +102,14 @@ def test_server_lifecycle_without_a_device():
         assert grown < 64.0, f"address space grew by {grown:.0f} MiB over 256 requests"
         assert "hipStreamCreateWithFlags" in srv.tcf_server_error(more[-1])
         assert srv.tcf_server_poll(more[0]) == tcf.TCF_REQ_FAILED
+        # a rejected description gets no id and leaves the other requests'
+        # callbacks in place
+        bad = W.plain_fp64().with_steps(1)
+        bad.sigma = -np.ones_like(np.asarray(bad.sigma, dtype=float))
+        with pytest.raises(tcf.TcfError) as err:
+            srv.tcf_server_submit(bad)
+        assert err.value.code == tcf.TCF_EINVAL
+        assert srv._keep[first[0]][3] is prob and len(srv._keep) == 288
         st = srv.tcf_server_stats()
         assert st["submitted"] == st["admitted"] == st["failed"] == 288
         assert st["completed"] == st["running"] == st["queued"] == 0
