@@ -1,0 +1,134 @@
+"""Reduced primal set (the outlook of Sec. 5): a CPU design study.
+
+Sec. 3 makes the tree edges T_G of every conductor-insulator interface face
+primal.  The outlook asks to drop them from the primal set while the local
+matrices stay nonsingular.  These tests check, against the oracle:
+
+* dropping them alone fails: on each insulator patch next to the interface,
+  moving its T_G edges from primal to remainder adds exactly |T_G| dimensions
+  to the kernel of the local remainder block;
+* the loop split of ``tests/feti_loop_ref.py`` drops them and stays exact.
+  The insulator eliminates T_G, the conductor keeps them as remainder, and
+  the cotree multipliers tie the insulator value to the conductor's loop
+  circulation.  Its field, mapped back to the oracle's gauge, equals the
+  oracle's element by element on every tiny layout (floating conductors
+  included) and on the Sec. 4 problem, whose volume source crosses the
+  interface;
+* the load correction on the conductor's T_G rows is needed: planted out, the
+  Sec. 4 field is wrong.
+
+The PCG iteration counts of both splits are printed, not asserted.  The loop
+split is exact, but with the unscaled Dirichlet preconditioner it needs more
+iterations (7-9 against 9-49 on the Sec. 4 problem, h = 1/4 and 1/8).  The
+preconditioner for the loop rows is the open part of this design.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import workloads as W
+from oracle import assemble, gauge, grid as G, solve
+from paper_2510_23446_amd import tcf
+from tests.feti_loop_ref import LoopFETI
+from tests.feti_ref import DenseFETI
+from tests.test_oracle_gauge import CASES, tiny
+
+LOOP_CASES = ["cond_bottom", "cond_bottom_p2", "checker", "two_subdomains", "floating_p2"]
+
+
+def _parts(prob):
+    g = G.build_grid(prob)
+    return g, assemble.assemble_global(prob, g), gauge.compute_topology(prob, g)
+
+
+@pytest.mark.parametrize("name", LOOP_CASES)
+def test_dropping_the_interface_tree_alone_leaves_a_kernel(name):
+    P, n, p, sig = CASES[name]
+    prob = tiny(P, n, p, sig)
+    g, sysm, topo = _parts(prob)
+    tg = set(int(e) for e in topo.tree_gamma)
+    checked = 0
+    for s, pm in enumerate(sysm.patches):
+        if prob.sigma[s] > 0:
+            continue
+        loc = topo.local[s]
+        gam = [int(e) for e in loc["p"] if int(e) in tg]
+        if not gam:
+            continue
+        pos = {int(x): k for k, x in enumerate(pm.gid)}
+        keep = [pos[int(e)] for e in np.concatenate([loc["i"], loc["b"]])]
+        W_ = (pm.M + prob.dt * pm.K).toarray()
+        with_fixed = np.linalg.eigvalsh(W_[np.ix_(keep, keep)])
+        r = keep + [pos[e] for e in gam]
+        moved = np.linalg.eigvalsh(W_[np.ix_(r, r)])
+        tol = 1e-10 * moved.max()
+        assert np.sum(with_fixed < tol) == 0
+        assert np.sum(moved < tol) == len(gam), (s, len(gam))
+        checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("name", LOOP_CASES)
+def test_loop_split_matches_the_oracle(name):
+    P, n, p, sig = CASES[name]
+    prob = tiny(P, n, p, sig)
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob)
+    lf = LoopFETI(prob, sysm, topo)
+    assert lf.nP == len(topo.primal) - len(topo.tree_gamma)
+    for d in lf.pat:  # every local remainder block is SPD
+        r = np.concatenate([d["i"], d["b"]])
+        sla.cholesky(d["W"][np.ix_(r, r)])
+    if lf.nP:
+        sla.cholesky(lf.SPi)
+    fe = DenseFETI(prob, sysm, topo)
+    a = np.zeros(g.n_edges)
+    worst, it_loop, it_tree = 0.0, [], []
+    for l in range(prob.n_steps):
+        fields, it = lf.step_local(a, prob.amp[0, l], first=(l == 0))
+        it_tree.append(fe.step(a, prob.amp[0, l])[1])
+        a = lf.conforming(fields)
+        r = ref.fields[l][:, 0]
+        worst = max(worst, np.linalg.norm(a - r) / np.linalg.norm(r))
+        it_loop.append(it)
+    print(f"[loop split] {name}: primal {len(topo.primal)} -> {lf.nP}, "
+          f"iterations {it_tree} -> {it_loop}, vs oracle {worst:.2e}")
+    assert worst <= 1e-9
+
+
+@pytest.mark.parametrize("n,p", [(2, 2), (2, 3)])
+def test_loop_split_on_the_sec4_problem(n, p):
+    prob = W.paper_manufactured(n=n, p=p, n_t=3)
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob)
+    fe = DenseFETI(prob, sysm, topo)
+    for corr in (True, False):
+        lf = LoopFETI(prob, sysm, topo, load_correction=corr)
+        assert lf.nP == 0  # two subdomains: every primal edge was interface tree
+        a = np.zeros(g.n_edges)
+        worst, its = 0.0, []
+        for l in range(prob.n_steps):
+            fields, it = lf.step_local(a, prob.amp[0, l], first=(l == 0))
+            a = lf.conforming(fields)
+            r = ref.fields[l][:, 0]
+            worst = max(worst, np.linalg.norm(a - r) / np.linalg.norm(r))
+            its.append(it)
+        if corr:
+            it_tree = [fe.step(ref.fields[l - 1][:, 0], prob.amp[0, l])[1]
+                       for l in range(1, prob.n_steps)]
+            print(f"[loop split] Sec. 4, h = 1/{2 * n}, p = {p}: primal {len(topo.primal)} -> 0, "
+                  f"iterations {it_tree} -> {its[1:]}, vs oracle {worst:.2e}")
+            assert worst <= 1e-9
+        else:
+            assert worst > 1e-2, worst
+
+
+def test_loop_split_size_of_the_full_checkerboard():
+    """What the loop split leaves of the primal set of the 256-patch
+    checkerboard at full size (host plan only): the wirebasket part."""
+    prob = W.largest_multirhs(n=12, n_steps=1)
+    h = tcf.Problem(prob)
+    c = h.counts()
+    tg = h.tcf_get_topology(tcf.TCF_TOPO_TREE_GAMMA)
+    assert c["n_primal"] == 115608 and len(tg) == 108160
+    assert c["n_primal"] - len(tg) == 7448
