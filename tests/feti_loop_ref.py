@@ -31,6 +31,13 @@ that does drop them, and checks it against the oracle.
 The primal set shrinks by |T_G|.  Mapping the result back,
 a_I - G psi(a_C), gives the conforming field in the oracle's gauge, so the
 check against the oracle is element by element.
+
+Preconditioner: the Dirichlet preconditioner sum_s B_D,s S_bb,s B_D,s^T
+needs weights with sum_s B_D,s B_s^T = I (a partition of unity over the
+multipliers).  Here the Boolean rows take 1/2 per side.  A loop row takes
+weight 1 on the insulator's single entry and 0 on the conductor's loop, so
+it is preconditioned by the insulator's Schur complement alone.  Unweighted,
+the long loop rows dominate, and the iterations grow with 1/h.
 """
 from __future__ import annotations
 
@@ -88,7 +95,7 @@ def _face_edges_and_boundary(grid, s, d, ecls):
 class LoopFETI(DenseFETI):
     """FETI-DP on the loop split; same operators and PCG as DenseFETI."""
 
-    def __init__(self, prob, sysm, topo, load_correction=True):
+    def __init__(self, prob, sysm, topo, load_correction=True, scaled=True):
         grid = sysm.grid
         nE = grid.n_edges
         eids = np.arange(nE)
@@ -219,11 +226,30 @@ class LoopFETI(DenseFETI):
             SPi[np.ix_(d["N"], d["N"])] += d["Spp"]
         self.SPi = SPi
         self.cond = cond
+        # Dirichlet preconditioner sum_s B_D,s S_bb,s B_D,s^T with weights that
+        # satisfy sum_s B_D,s B_s^T = I: 1/2 per side on the Boolean rows; on
+        # a loop row weight 1 on the insulator's single entry and 0 on the
+        # conductor's loop.  scaled=False keeps the unweighted B.
+        loop_mask = np.zeros(self.nL, dtype=bool)
+        loop_mask[[rankL[e] for e in loop_rows]] = True
+        self.loop_mask = loop_mask
+        for s, d in enumerate(self.pat):
+            if not scaled:
+                d["BD"] = d["B"]
+                continue
+            w = np.where(loop_mask, 0.0 if cond[s] else 1.0, 0.5)
+            d["BD"] = w[:, None] * d["B"]
         self.tail, self.head = tail, head
         self.insul_only = ~np.zeros(nE, dtype=bool)
         for s in range(prob.n_patches):
             if cond[s]:
                 self.insul_only[gauge._box_edges(grid, s)] = False
+
+    def precond(self, r):
+        z = np.zeros(self.nL)
+        for d in self.pat:
+            z += d["BD"] @ (d["Sbb"] @ (d["BD"].T @ r))
+        return z
 
     def _add_patch(self, pm, order, B, Ns, jhat):
         dt = self.dt
