@@ -34,10 +34,8 @@ check against the oracle is element by element.
 
 Preconditioner: the Dirichlet preconditioner sum_s B_D,s S_bb,s B_D,s^T
 needs weights with sum_s B_D,s B_s^T = I (a partition of unity over the
-multipliers).  Here the Boolean rows take 1/2 per side.  A loop row takes
-weight 1 on the insulator's single entry and 0 on the conductor's loop, so
-it is preconditioned by the insulator's Schur complement alone.  Unweighted,
-the long loop rows dominate, and the iterations grow with 1/h.
+multipliers); ``_set_weights`` gives three choices.  Unweighted, the long
+loop rows dominate, and the iterations grow with 1/h.
 """
 from __future__ import annotations
 
@@ -95,7 +93,7 @@ def _face_edges_and_boundary(grid, s, d, ecls):
 class LoopFETI(DenseFETI):
     """FETI-DP on the loop split; same operators and PCG as DenseFETI."""
 
-    def __init__(self, prob, sysm, topo, load_correction=True, scaled=True):
+    def __init__(self, prob, sysm, topo, load_correction=True, weights="stiffness"):
         grid = sysm.grid
         nE = grid.n_edges
         eids = np.arange(nE)
@@ -201,8 +199,10 @@ class LoopFETI(DenseFETI):
                      "p": np.array([pos[int(x)] for x in p_ids], dtype=np.int64)}
             bpos = {int(x): k for k, x in enumerate(b_ids)}
             B = np.zeros((self.nL, len(b_ids)))
+            own = np.full(self.nL, -1, dtype=np.int64)  # column of the row's own edge
             for e in loc["b"]:
                 r = rankL[int(e)]
+                own[r] = bpos[int(e)]
                 if int(e) in loop_rows:
                     cs, is_ = loop_rows[int(e)]
                     if s == is_:
@@ -221,35 +221,75 @@ class LoopFETI(DenseFETI):
                 jh = jh + corr[pm.gid]
             self._add_patch(pm, order, B, np.array([rankP[int(x)] for x in p_ids],
                                                    dtype=np.int64), jh)
+            self.pat[-1]["own"] = own
         SPi = np.zeros((self.nP, self.nP))
         for d in self.pat:
             SPi[np.ix_(d["N"], d["N"])] += d["Spp"]
         self.SPi = SPi
         self.cond = cond
-        # Dirichlet preconditioner sum_s B_D,s S_bb,s B_D,s^T with weights that
-        # satisfy sum_s B_D,s B_s^T = I: 1/2 per side on the Boolean rows; on
-        # a loop row weight 1 on the insulator's single entry and 0 on the
-        # conductor's loop.  scaled=False keeps the unweighted B.
         loop_mask = np.zeros(self.nL, dtype=bool)
         loop_mask[[rankL[e] for e in loop_rows]] = True
         self.loop_mask = loop_mask
-        for s, d in enumerate(self.pat):
-            if not scaled:
-                d["BD"] = d["B"]
-                continue
-            w = np.where(loop_mask, 0.0 if cond[s] else 1.0, 0.5)
-            d["BD"] = w[:, None] * d["B"]
+        self._set_weights(weights)
         self.tail, self.head = tail, head
         self.insul_only = ~np.zeros(nE, dtype=bool)
         for s in range(prob.n_patches):
             if cond[s]:
                 self.insul_only[gauge._box_edges(grid, s)] = False
 
+    def _set_weights(self, weights):
+        """B_D per patch for the Dirichlet preconditioner
+        sum_s B_D,s S_bb,s B_D,s^T, with sum_s B_D,s B_s^T = I.
+
+        * "none": B_D = B (unweighted).
+        * "insulator": 1/2 per side on Boolean rows; a loop row weight 1 on
+          the insulator's single entry, 0 on the conductor's loop.
+        * "stiffness": with k_s the diagonal of patch s's W at the row's own
+          edge, the side s of a Boolean row gets k_o / (k_s + k_o) (the
+          other side's share).  A loop row gives its insulator entry
+          w_I = k_C / (k_I + k_C), and the conductor the rest,
+          (1 - w_I) (B_C B_C^T)^-1 B_C over that patch's loop rows (B_C B_C^T
+          is SPD: each loop row holds its own edge, which no other row does).
+        """
+        nL, cond, loop = self.nL, self.cond, self.loop_mask
+        if weights == "none":
+            for d in self.pat:
+                d["BD"] = d["B"]
+            return
+        k = []
+        for d in self.pat:
+            kd = np.diag(d["W"])[d["b"]]
+            k.append(np.where(d["own"] >= 0, kd[np.maximum(d["own"], 0)], 0.0))
+        tot = sum(k)
+        kC = sum(kk for kk, c in zip(k, cond) if c)
+        kI = sum(kk for kk, c in zip(k, cond) if not c)
+        for s, d in enumerate(self.pat):
+            part = d["own"] >= 0
+            if weights == "insulator":
+                w_bool = np.where(part, 0.5, 0.0)
+                w_I = np.ones(nL)
+            elif weights == "stiffness":
+                w_bool = np.where(part, (tot - k[s]) / np.where(tot > 0, tot, 1.0), 0.0)
+                w_I = kC / np.where(kI + kC > 0, kI + kC, 1.0)
+            else:
+                raise ValueError(weights)
+            BD = np.where(loop, 0.0, w_bool)[:, None] * d["B"]
+            mine = loop & part
+            if mine.any():
+                if cond[s]:
+                    if weights == "stiffness":
+                        Bl = d["B"][mine]
+                        BD[mine] = (1.0 - w_I[mine])[:, None] * np.linalg.solve(Bl @ Bl.T, Bl)
+                else:
+                    BD[mine] = w_I[mine][:, None] * d["B"][mine]
+            d["BD"] = BD
+
     def precond(self, r):
         z = np.zeros(self.nL)
         for d in self.pat:
             z += d["BD"] @ (d["Sbb"] @ (d["BD"].T @ r))
         return z
+
 
     def _add_patch(self, pm, order, B, Ns, jhat):
         dt = self.dt
@@ -329,3 +369,27 @@ class LoopFETI(DenseFETI):
             loc[d["p"]] = ap
             fields.append(loc)
         return fields, it
+
+
+def stiffness_weighted(fe):
+    """The stiffness-scaled Dirichlet preconditioner on the published (tree)
+    split of a DenseFETI: side s of a multiplier gets k_o / (k_s + k_o)."""
+    nL = fe.nL
+    k = []
+    for d in fe.pat:
+        kd = np.diag(d["W"])[d["b"]]
+        kr = np.zeros(nL)
+        rows, cols = np.nonzero(d["B"])
+        kr[rows] = kd[cols]
+        k.append(kr)
+    tot = sum(k)
+    BD = [np.where(kk > 0, (tot - kk) / np.where(tot > 0, tot, 1.0), 0.0)[:, None] * d["B"]
+          for kk, d in zip(k, fe.pat)]
+
+    def precond(r):
+        z = np.zeros(nL)
+        for bd, d in zip(BD, fe.pat):
+            z += bd @ (d["Sbb"] @ (bd.T @ r))
+        return z
+    fe.precond = precond
+    return fe

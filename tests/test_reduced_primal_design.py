@@ -17,10 +17,13 @@ matrices stay nonsingular.  These tests check, against the oracle:
 * the load correction on the conductor's T_G rows is needed: planted out, the
   Sec. 4 field is wrong;
 * the iteration counts.  The Dirichlet preconditioner is weighted so that
-  sum_s B_D,s B_s^T = I: 1/2 per side on Boolean rows, and the insulator
-  side alone on a loop row.  With it, the loop split needs no more PCG
-  iterations than the tree split on every case here, and fewer on most:
-  9 against 17 in the timed configuration of Sec. 4.
+  sum_s B_D,s B_s^T = I.  With stiffness weights (loop rows split between
+  the insulator's entry and a pseudo-inverse of the conductor's loop rows),
+  the loop split needs no more PCG iterations than the tree split on every
+  case here, and fewer on most:
+  * 7 against 17 in the timed configuration of Sec. 4;
+  * 12 against 17 (tree split, stiffness-scaled) and 48 (unscaled) on a
+    high-contrast checkerboard.
   Unweighted, the long loop rows dominate and the iterations grow with 1/h
   (printed only).
 """
@@ -31,7 +34,7 @@ import scipy.linalg as sla
 import workloads as W
 from oracle import assemble, gauge, grid as G, solve
 from paper_2510_23446_amd import tcf
-from tests.feti_loop_ref import LoopFETI
+from tests.feti_loop_ref import LoopFETI, stiffness_weighted
 from tests.feti_ref import DenseFETI
 from tests.test_oracle_gauge import CASES, tiny
 
@@ -83,10 +86,12 @@ def test_loop_split_matches_the_oracle(name):
         sla.cholesky(d["W"][np.ix_(r, r)])
     if lf.nP:
         sla.cholesky(lf.SPi)
-    pu = sum(d["BD"] @ d["B"].T for d in lf.pat)
-    assert np.abs(pu - np.eye(lf.nL)).max() <= 1e-14
+    for w in ("stiffness", "insulator"):
+        other = lf if w == "stiffness" else LoopFETI(prob, sysm, topo, weights=w)
+        pu = sum(d["BD"] @ d["B"].T for d in other.pat)
+        assert np.abs(pu - np.eye(lf.nL)).max() <= 1e-12, w
     fe = DenseFETI(prob, sysm, topo)
-    plain = LoopFETI(prob, sysm, topo, scaled=False)
+    plain = LoopFETI(prob, sysm, topo, weights="none")
     a = np.zeros(g.n_edges)
     worst, it_loop, it_tree, it_plain = 0.0, [], [], []
     for l in range(prob.n_steps):
@@ -153,6 +158,28 @@ def test_loop_split_iterations_at_the_papers_step():
     print(f"[loop split] p = 3, n_t = 32, (n, primal, tree iters, loop iters): {rows}")
     (_, _, t4, l4), (_, _, t8, l8) = rows
     assert t8 > t4 and l8 <= l4 and l8 < t8
+
+
+def test_loop_split_with_material_contrast():
+    """Checkerboard with sigma 1e3 and nu varying by 200 between patches:
+    the stiffness-weighted loop split against the tree split with and
+    without stiffness scaling (one step from the oracle's previous field)."""
+    P, n, p, sig = CASES["checker"]
+    prob = tiny(P, n, p, np.asarray(sig, float) * 1e3)
+    prob.nu = np.array([1.0, 50.0, 3.0, 1.0, 200.0, 1.0, 7.0, 1.0])
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob, n_steps=2)
+    a0, amp, r = ref.fields[0][:, 0], prob.amp[0, 1], ref.fields[1][:, 0]
+    fe = DenseFETI(prob, sysm, topo)
+    t_plain = fe.step(a0, amp)[1]
+    t_stiff = stiffness_weighted(fe).step(a0, amp)[1]
+    lf = LoopFETI(prob, sysm, topo)
+    fields, l_stiff = lf.step_local(a0, amp)
+    a = lf.conforming(fields)
+    assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
+    print(f"[loop split] contrast: tree {t_plain}, tree stiffness-scaled {t_stiff}, "
+          f"loop stiffness-weighted {l_stiff}")
+    assert l_stiff < t_stiff < t_plain
 
 
 def test_loop_split_size_of_the_full_checkerboard():
