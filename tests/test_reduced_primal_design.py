@@ -182,12 +182,37 @@ def test_loop_split_with_material_contrast():
     assert l_stiff < t_stiff < t_plain
 
 
-def test_loop_split_size_of_the_full_checkerboard():
-    """What the loop split leaves of the primal set of the 256-patch
-    checkerboard at full size (host plan only): the wirebasket part."""
-    prob = W.largest_multirhs(n=12, n_steps=1)
-    h = tcf.Problem(prob)
-    c = h.counts()
-    tg = h.tcf_get_topology(tcf.TCF_TOPO_TREE_GAMMA)
-    assert c["n_primal"] == 115608 and len(tg) == 108160
-    assert c["n_primal"] - len(tg) == 7448
+def test_loop_split_on_the_benchmark_layout_reduced():
+    """The uneven 64-patch layout's materials and degrees (sigma 1e5-1e7,
+    nu = 1/mu_0, dt = 1e-4) on 3x3x3 patches with at most 3 elements per row:
+    exact, with the iterations of the stiffness-scaled tree split and a
+    smaller coarse problem."""
+    prob = W.uneven_fp64(seed=1, n_steps=2, P=(3, 3, 3))
+    prob.nel = [np.minimum(np.asarray(v), 3).astype(np.int32) for v in prob.nel]
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob, n_steps=2)
+    a0, amp, r = ref.fields[0][:, 0], prob.amp[0, 1], ref.fields[1][:, 0]
+    fe = DenseFETI(prob, sysm, topo)
+    t_plain = fe.step(a0, amp)[1]
+    t_stiff = stiffness_weighted(fe).step(a0, amp)[1]
+    lf = LoopFETI(prob, sysm, topo)
+    fields, l_stiff = lf.step_local(a0, amp)
+    a = lf.conforming(fields)
+    assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
+    print(f"[loop split] uneven layout, reduced: primal {fe.nP} -> {lf.nP}; iterations tree "
+          f"{t_plain}, tree stiffness-scaled {t_stiff}, loop stiffness-weighted {l_stiff}")
+    assert lf.nP < fe.nP / 2
+    assert l_stiff <= t_stiff < t_plain
+
+
+def test_loop_split_primal_sizes_at_full_size():
+    """What the loop split leaves of the primal set at full size (host plan
+    only): the 256-patch checkerboard and the 64-patch uneven benchmark."""
+    for prob, n_primal, n_tree, left in [
+            (W.largest_multirhs(n=12, n_steps=1), 115608, 108160, 7448),
+            (W.uneven_fp64(seed=1, n_steps=1), 5416, 4421, 995)]:
+        h = tcf.Problem(prob)
+        c = h.counts()
+        tg = h.tcf_get_topology(tcf.TCF_TOPO_TREE_GAMMA)
+        assert (c["n_primal"], len(tg)) == (n_primal, n_tree), prob.name
+        assert c["n_primal"] - len(tg) == left
