@@ -107,6 +107,8 @@ class LoopFETI(DenseFETI):
         # psi(n) = sum_t coef[n][t] a_C(t) on the face interior nodes
         coef = {}
         cotree = []  # (edge, conductor patch, insulator patch)
+        is_dual = np.zeros(nE, dtype=bool)
+        is_dual[np.asarray(topo.dual, dtype=np.int64)] = True
         for s, d, t in _gamma_faces(prob, grid):
             edges, on_boundary = _face_edges_and_boundary(grid, s, d, ecls)
             tree = [int(e) for e in edges if in_tg[e]]
@@ -133,7 +135,7 @@ class LoopFETI(DenseFETI):
             assert all(on_boundary(n) or n in coef for n in adj)
             c_s, i_s = (s, t) if cond[s] else (t, s)
             for e in edges:
-                if not in_tg[e] and e in set(topo.dual.tolist()):
+                if not in_tg[e] and is_dual[e]:
                     cotree.append((int(e), c_s, i_s))
 
         # extension along T_I, away from grounded nodes
