@@ -90,91 +90,104 @@ def _face_edges_and_boundary(grid, s, d, ecls):
     return edges, on_boundary
 
 
+def loop_structure(prob, sysm, topo):
+    """The loop split's data: psi coefficients per node (face trees, then
+    constant along T_I), the cotree rows (edge, conductor patch, insulator
+    patch), and the load correction on the conductor's T_G rows per
+    excitation (corr, indexed by global edge)."""
+    grid = sysm.grid
+    nE = grid.n_edges
+    eids = np.arange(nE)
+    tail, head = grid.edge_nodes(eids)
+    ecls = grid.edge_class(eids)
+    cond = np.asarray(prob.sigma) > 0
+    tg = np.asarray(topo.tree_gamma, dtype=np.int64)
+    in_tg = np.zeros(nE, dtype=bool)
+    in_tg[tg] = True
+
+    # psi(n) = sum_t coef[n][t] a_C(t) on the face interior nodes
+    coef = {}
+    cotree = []  # (edge, conductor patch, insulator patch)
+    is_dual = np.zeros(nE, dtype=bool)
+    is_dual[np.asarray(topo.dual, dtype=np.int64)] = True
+    for s, d, t in _gamma_faces(prob, grid):
+        edges, on_boundary = _face_edges_and_boundary(grid, s, d, ecls)
+        tree = [int(e) for e in edges if in_tg[e]]
+        adj = {}
+        for e in tree:
+            a, b = int(tail[e]), int(head[e])
+            adj.setdefault(a, []).append(e)
+            adj.setdefault(b, []).append(e)
+        seeds = [n for n in adj if on_boundary(n)]
+        seen = set(seeds)
+        q = deque(seeds)
+        while q:
+            x = q.popleft()
+            for e in adj[x]:
+                y = int(head[e]) if int(tail[e]) == x else int(tail[e])
+                if y in seen:
+                    continue
+                seen.add(y)
+                c = dict(coef.get(x, {}))
+                # psi(head) = psi(tail) - a(e)
+                c[e] = c.get(e, 0.0) + (-1.0 if int(tail[e]) == x else 1.0)
+                coef[y] = c
+                q.append(y)
+        assert all(on_boundary(n) or n in coef for n in adj)
+        c_s, i_s = (s, t) if cond[s] else (t, s)
+        for e in edges:
+            if not in_tg[e] and is_dual[e]:
+                cotree.append((int(e), c_s, i_s))
+
+    # extension along T_I, away from grounded nodes
+    grounded = np.asarray(grid.node_on_boundary(np.arange(grid.n_nodes)), dtype=bool).copy()
+    for s in range(prob.n_patches):
+        if cond[s]:
+            grounded[gauge._box_nodes(grid, s)] = True
+    adjI = {}
+    for e in topo.tree_I:
+        a, b = int(tail[e]), int(head[e])
+        adjI.setdefault(a, []).append(b)
+        adjI.setdefault(b, []).append(a)
+    seed = {n: n for n in coef}
+    q = deque(n for n in list(coef) if n in adjI)
+    while q:
+        x = q.popleft()
+        for y in adjI.get(x, ()):
+            if grounded[y]:
+                continue
+            if y in seed:
+                # T_I is a tree: a subtree hangs from one interface node
+                assert seed[y] == seed[x], "subtree reached from two interface nodes"
+                continue
+            seed[y] = seed[x]
+            coef[y] = coef[x]
+            q.append(y)
+
+    # load correction from the insulator load, per excitation
+    GI = incidence_G(grid).tocsr()
+    fI = np.zeros((nE, prob.n_rhs))
+    for s, pm in enumerate(sysm.patches):
+        if not cond[s]:
+            np.add.at(fI, pm.gid, pm.jhat)
+    g = GI.T @ fI  # (n_nodes, n_rhs)
+    corr = np.zeros((nE, prob.n_rhs))
+    for n, c in coef.items():
+        for t, w in c.items():
+            corr[t] -= g[n] * w
+
+    return dict(grid=grid, nE=nE, tail=tail, head=head, cond=cond, tg=tg, in_tg=in_tg,
+                coef=coef, cotree=cotree, corr=corr)
+
+
 class LoopFETI(DenseFETI):
     """FETI-DP on the loop split; same operators and PCG as DenseFETI."""
 
     def __init__(self, prob, sysm, topo, load_correction=True, weights="stiffness"):
-        grid = sysm.grid
-        nE = grid.n_edges
-        eids = np.arange(nE)
-        tail, head = grid.edge_nodes(eids)
-        ecls = grid.edge_class(eids)
-        cond = np.asarray(prob.sigma) > 0
-        tg = np.asarray(topo.tree_gamma, dtype=np.int64)
-        in_tg = np.zeros(nE, dtype=bool)
-        in_tg[tg] = True
-
-        # psi(n) = sum_t coef[n][t] a_C(t) on the face interior nodes
-        coef = {}
-        cotree = []  # (edge, conductor patch, insulator patch)
-        is_dual = np.zeros(nE, dtype=bool)
-        is_dual[np.asarray(topo.dual, dtype=np.int64)] = True
-        for s, d, t in _gamma_faces(prob, grid):
-            edges, on_boundary = _face_edges_and_boundary(grid, s, d, ecls)
-            tree = [int(e) for e in edges if in_tg[e]]
-            adj = {}
-            for e in tree:
-                a, b = int(tail[e]), int(head[e])
-                adj.setdefault(a, []).append(e)
-                adj.setdefault(b, []).append(e)
-            seeds = [n for n in adj if on_boundary(n)]
-            seen = set(seeds)
-            q = deque(seeds)
-            while q:
-                x = q.popleft()
-                for e in adj[x]:
-                    y = int(head[e]) if int(tail[e]) == x else int(tail[e])
-                    if y in seen:
-                        continue
-                    seen.add(y)
-                    c = dict(coef.get(x, {}))
-                    # psi(head) = psi(tail) - a(e)
-                    c[e] = c.get(e, 0.0) + (-1.0 if int(tail[e]) == x else 1.0)
-                    coef[y] = c
-                    q.append(y)
-            assert all(on_boundary(n) or n in coef for n in adj)
-            c_s, i_s = (s, t) if cond[s] else (t, s)
-            for e in edges:
-                if not in_tg[e] and is_dual[e]:
-                    cotree.append((int(e), c_s, i_s))
-
-        # extension along T_I, away from grounded nodes
-        grounded = np.asarray(grid.node_on_boundary(np.arange(grid.n_nodes)), dtype=bool).copy()
-        for s in range(prob.n_patches):
-            if cond[s]:
-                grounded[gauge._box_nodes(grid, s)] = True
-        adjI = {}
-        for e in topo.tree_I:
-            a, b = int(tail[e]), int(head[e])
-            adjI.setdefault(a, []).append(b)
-            adjI.setdefault(b, []).append(a)
-        seed = {n: n for n in coef}
-        q = deque(n for n in list(coef) if n in adjI)
-        while q:
-            x = q.popleft()
-            for y in adjI.get(x, ()):
-                if grounded[y]:
-                    continue
-                if y in seed:
-                    # T_I is a tree: a subtree hangs from one interface node
-                    assert seed[y] == seed[x], "subtree reached from two interface nodes"
-                    continue
-                seed[y] = seed[x]
-                coef[y] = coef[x]
-                q.append(y)
+        L = loop_structure(prob, sysm, topo)
+        grid, nE, tail, head, cond = L["grid"], L["nE"], L["tail"], L["head"], L["cond"]
+        tg, in_tg, coef, cotree, corr = L["tg"], L["in_tg"], L["coef"], L["cotree"], L["corr"]
         self.coef = coef
-
-        # load correction from the insulator load, per excitation
-        GI = incidence_G(grid).tocsr()
-        fI = np.zeros((nE, prob.n_rhs))
-        for s, pm in enumerate(sysm.patches):
-            if not cond[s]:
-                np.add.at(fI, pm.gid, pm.jhat)
-        g = GI.T @ fI  # (n_nodes, n_rhs)
-        corr = np.zeros((nE, prob.n_rhs))
-        for n, c in coef.items():
-            for t, w in c.items():
-                corr[t] -= g[n] * w
 
         # the split
         primal = np.setdiff1d(topo.primal, tg)

@@ -216,3 +216,26 @@ def test_loop_split_primal_sizes_at_full_size():
         tg = h.tcf_get_topology(tcf.TCF_TOPO_TREE_GAMMA)
         assert (c["n_primal"], len(tg)) == (n_primal, n_tree), prob.name
         assert c["n_primal"] - len(tg) == left
+
+
+@pytest.mark.parametrize("name", ["checker", "floating_p2", "two_subdomains"])
+def test_sparse_prototype_agrees_with_the_dense_ones(name):
+    """tests/feti_sparse.py (sparse LU per patch, for full-size layouts)
+    against the dense prototypes: same PCG iteration counts for the tree
+    split (unweighted and stiffness-scaled) and the loop split, and fields
+    within the solver tolerance of the oracle."""
+    from tests.feti_sparse import SparseFETI
+
+    P, n, p, sig = CASES[name]
+    prob = tiny(P, n, p, sig)
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob, n_steps=2)
+    a0, amp, r = ref.fields[0][:, 0], prob.amp[0, 1], ref.fields[1][:, 0]
+    fe = DenseFETI(prob, sysm, topo)
+    dense = {("tree", "none"): fe.step(a0, amp, rtol=1e-10)[1],
+             ("tree", "stiffness"): stiffness_weighted(fe).step(a0, amp, rtol=1e-10)[1],
+             ("loop", "stiffness"): LoopFETI(prob, sysm, topo).step_local(a0, amp, rtol=1e-10)[1]}
+    for (split, w), it_dense in dense.items():
+        a, it = SparseFETI(prob, sysm, topo, split=split, weights=w).step(a0, amp, rtol=1e-10)
+        assert it == it_dense, (split, w, it, it_dense)
+        assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
