@@ -269,7 +269,7 @@ class SparseFETI:
 
 
 def main():
-    """Full-size comparison on the benchmark's layout (about 7 minutes, 4 GB):
+    """Full-size comparison on the benchmark's layout (about 7 minutes):
     one implicit Euler step from zero, then the second step from that field,
     for each split and weighting; the residual is the oracle's gauged global
     system's."""
