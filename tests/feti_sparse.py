@@ -268,17 +268,26 @@ class SparseFETI:
         return a
 
 
-def main():
-    """Full-size comparison on the benchmark's layout (about 7 minutes):
-    one implicit Euler step from zero, then the second step from that field,
-    for each split and weighting; the residual is the oracle's gauged global
-    system's."""
+def main(workload="uneven"):
+    """Full-size comparison of the splits: one implicit Euler step from
+    zero, then the second step from that field, for each split and
+    weighting; the residual is the oracle's gauged global system's.
+
+    * ``uneven``: the benchmark's 64-patch layout (about 7 minutes);
+    * ``checkerboard``: the 256-patch checkerboard at n = 4, one excitation
+      (the multi-excitation workload's operator).
+    """
     import time
 
     import workloads as W
     from oracle import assemble, grid as G, solve
 
-    prob = W.uneven_fp64(seed=1, n_steps=3)
+    if workload == "uneven":
+        prob = W.uneven_fp64(seed=1, n_steps=3)
+    elif workload == "checkerboard":
+        prob = W.largest_multirhs(n=4, n_rhs=1, n_steps=3)
+    else:
+        raise ValueError(workload)
     g = G.build_grid(prob)
     sysm = assemble.assemble_global(prob, g)
     topo = gauge.compute_topology(prob, g)
@@ -300,4 +309,6 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    import sys
+
+    main(*sys.argv[1:2])
