@@ -189,12 +189,19 @@ class SparseFETI:
             z += d["BD"] @ y
         return z
 
-    def pcg(self, dvec, rtol, maxit):
-        lam = np.zeros_like(dvec)
+    def pcg(self, dvec, rtol, maxit, lam0=None, r0=None):
+        """PCG from lam0 (r0 = d - F lam0 given with it); stops at
+        ||r|| <= rtol ||d||.  Returns (lam, iterations)."""
         nd = np.linalg.norm(dvec)
         if nd == 0:
-            return lam, 0
-        r = dvec.copy()
+            return np.zeros_like(dvec), 0
+        if lam0 is None:
+            lam, r = np.zeros_like(dvec), dvec.copy()
+        else:
+            lam, r = lam0.copy(), r0.copy()
+            if np.linalg.norm(r) <= rtol * nd:
+                self.last_r = r
+                return lam, 0
         z = self.precond(r)
         p = z.copy()
         rz = r @ z
@@ -204,16 +211,23 @@ class SparseFETI:
             lam += alpha * p
             r -= alpha * q
             if np.linalg.norm(r) <= rtol * nd:
+                self.last_r = r
                 return lam, it
             z = self.precond(r)
             rz_new = r @ z
             p = z + (rz_new / rz) * p
             rz = rz_new
+        self.last_r = r
         return lam, maxit
 
     # ---- one implicit Euler step ------------------------------------------
-    def step(self, a_prev, amp, first=False, rtol=1e-10, maxit=2000):
-        """Returns (field in the oracle's gauge, PCG iterations)."""
+    def step(self, a_prev, amp, first=False, rtol=1e-10, maxit=2000, window=0):
+        """Returns (field in the oracle's gauge, PCG iterations).
+
+        window > 0 starts the PCG from the Galerkin projection onto the span
+        of the newest ``window`` solutions of earlier calls,
+        lam0 = L (L^T F L)^-1 L^T d, with F L kept from each solve as d - r.
+        """
         dt = self.dt
         h = np.zeros(self.nP)
         dvec = np.zeros(self.nL)
@@ -230,7 +244,21 @@ class SparseFETI:
         q0 = self._coarse(h)
         for d, u in zip(self.pat, w0):
             dvec += d["B"] @ (u - d["Z"] @ q0[d["N"]])[d["nI"]:]
-        lam, it = self.pcg(dvec, rtol, maxit)
+        hist = getattr(self, "_hist", [])
+        if window and hist:
+            Lm = np.stack([h_[0] for h_ in hist], 1)
+            FL = np.stack([h_[1] for h_ in hist], 1)
+            G = Lm.T @ FL
+            G = 0.5 * (G + G.T)
+            w_, V = np.linalg.eigh(G)
+            keep = w_ > 1e-12 * w_.max()
+            coef = V[:, keep] @ ((V[:, keep].T @ (Lm.T @ dvec)) / w_[keep])
+            lam0, r0 = Lm @ coef, dvec - FL @ coef
+            lam, it = self.pcg(dvec, rtol, maxit, lam0, r0)
+        else:
+            lam, it = self.pcg(dvec, rtol, maxit)
+        if window:
+            self._hist = (hist + [(lam.copy(), dvec - self.last_r)])[-window:]
         c = np.zeros(self.nP)
         for d in self.pat:
             rhs = np.zeros(d["nI"] + len(d["b"]))
@@ -308,7 +336,36 @@ def main(workload="uneven"):
               f"residual {resid(a2, a1, prob.amp[0, 1]):.1e}, {time.time() - t0:.0f} s", flush=True)
 
 
+def main_projection(n_steps=12):
+    """Both splits, stiffness-weighted, with the projection start from the
+    newest 8 solutions, over the first n_steps steps of the benchmark's
+    64-patch layout (about 15 minutes)."""
+    import time
+
+    import workloads as W
+    from oracle import assemble, grid as G
+
+    prob = W.uneven_fp64(seed=1, n_steps=n_steps)
+    g = G.build_grid(prob)
+    sysm = assemble.assemble_global(prob, g)
+    topo = gauge.compute_topology(prob, g)
+    for split in ("tree", "loop"):
+        t0 = time.time()
+        sf = SparseFETI(prob, sysm, topo, split=split, weights="stiffness")
+        a = np.zeros(g.n_edges)
+        its = []
+        for l in range(n_steps):
+            a, it = sf.step(a, prob.amp[0, l], window=8)
+            its.append(it)
+            print(f"{split}: step {l + 1} PCG iterations {it}", flush=True)
+        print(f"{split}/stiffness + projection start: iterations {its}, "
+              f"{time.time() - t0:.0f} s", flush=True)
+
+
 if __name__ == "__main__":
     import sys
 
-    main(*sys.argv[1:2])
+    if sys.argv[1:2] == ["projection"]:
+        main_projection()
+    else:
+        main(*sys.argv[1:2])

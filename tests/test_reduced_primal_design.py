@@ -239,3 +239,26 @@ def test_sparse_prototype_agrees_with_the_dense_ones(name):
         a, it = SparseFETI(prob, sysm, topo, split=split, weights=w).step(a0, amp, rtol=1e-10)
         assert it == it_dense, (split, w, it, it_dense)
         assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r)
+
+
+@pytest.mark.parametrize("split", ["tree", "loop"])
+def test_sparse_prototype_projection_start(split):
+    """The projection start (newest 8 solutions) in the sparse prototype:
+    every step's field within the solver tolerance of the oracle, and the
+    later steps need fewer iterations than the first."""
+    from tests.feti_sparse import SparseFETI
+
+    P, n, p, sig = CASES["floating_p2"]
+    prob = tiny(P, n, p, sig, steps=6)
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob)
+    sf = SparseFETI(prob, sysm, topo, split=split, weights="stiffness")
+    a = np.zeros(g.n_edges)
+    its = []
+    for l in range(prob.n_steps):
+        a, it = sf.step(a, prob.amp[0, l], window=8)
+        r = ref.fields[l][:, 0]
+        assert np.linalg.norm(a - r) <= 1e-9 * np.linalg.norm(r), l
+        its.append(it)
+    print(f"[loop split] projection start, {split}: iterations {its}")
+    assert max(its[2:]) < its[0]
