@@ -339,7 +339,7 @@ def main(workload="uneven"):
 def main_projection(n_steps=12):
     """Both splits, stiffness-weighted, with the projection start from the
     newest 8 solutions, over the first n_steps steps of the benchmark's
-    64-patch layout (about 15 minutes)."""
+    64-patch layout (about 12 minutes)."""
     import time
 
     import workloads as W
