@@ -213,8 +213,17 @@ enum tcf_topology_kind {
   TCF_TOPO_DUAL = 5,       /* sorted dual edge ids; index = multiplier row       */
   TCF_TOPO_INTERIOR = 6,   /* sorted patch-interior kept edge ids                */
   TCF_TOPO_MULT = 7,       /* int64[n_lambda][3]: edge id, patch (+1), patch(-1) */
-  TCF_TOPO_N = 8           /* int64[sum_s n_p^(s)][3]: patch, edge id, primal    */
+  TCF_TOPO_N = 8,          /* int64[sum_s n_p^(s)][3]: patch, edge id, primal    */
                            /* rank; per patch in increasing edge id              */
+  TCF_TOPO_LOOP = 9        /* int64[n][3]: multiplier row, edge id, +1 / -1.     */
+                           /* Host plan of a reduced primal split that drops the */
+                           /* interface trees from the primal set (the outlook   */
+                           /* of Sec. 5): the conductor-side terms of the row of */
+                           /* each cotree edge e of a conductor/insulator face,  */
+                           /* a_C(e) + psi(head e) - psi(tail e), psi the signed */
+                           /* sum of a_C along the face-tree path from the face  */
+                           /* boundary.  Rows ascending, then edge ids.  Not     */
+                           /* used by the solver.                                */
 };
 
 /*

@@ -582,6 +582,9 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
         }
       }
       break;
+    case TCF_TOPO_LOOP:
+      tmp = loop_rows(h->g, h->topo, h->plans);
+      break;
     default:
       return TCF_EINVAL;
   }

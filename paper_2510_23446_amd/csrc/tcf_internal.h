@@ -80,5 +80,9 @@ Grid build_grid(const tcf_problem_desc& d);
 std::string validate_desc(const tcf_problem_desc& d);
 std::string compute_topology(const tcf_problem_desc& d, const Grid& g, Topology& t,
                              std::vector<PatchPlan>& plans);
+// Conductor-side terms (row, edge, +-1) of the loop rows of the reduced
+// primal split; see the definition.
+std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
+                               const std::vector<PatchPlan>& plans);
 
 }  // namespace tcf

@@ -14,7 +14,9 @@
 // face-interior edges of interior faces (one multiplier each, ordered by edge
 // id, +1 on the lower patch id).
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
 #include <numeric>
 #include <sstream>
 
@@ -410,6 +412,107 @@ std::string compute_topology(const tcf_problem_desc& d, const Grid& g, Topology&
     }
   }
   return "";
+}
+
+// Loop rows of the reduced primal split (the outlook of Sec. 5 asks for a
+// split without the interface trees in the primal set).  There the insulator
+// eliminates the tree edges of every conductor/insulator face, the conductor
+// keeps them as remainder unknowns, and the multiplier of each cotree edge e
+// of the face ties the insulator's a_I(e) to the conductor's circulation
+// a_C(e) + psi(head e) - psi(tail e).  psi is a nodal function on the face:
+// zero on the face boundary, and on the face's tree edges
+// a_C(t) + psi(head t) - psi(tail t) = 0, so psi at a face node is a signed
+// sum of a_C along its tree path.  Returns the conductor-side terms as
+// (multiplier row, edge id, +1 / -1) triples, by row, then by edge id.
+std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
+                               const std::vector<PatchPlan>& plans) {
+  const int64_t nE = g.n_edges();
+  std::vector<uint8_t> in_tg(nE, 0);
+  for (int64_t e : t.tree_gamma) in_tg[e] = 1;
+  std::vector<int64_t> row(nE, -1);
+  for (size_t r = 0; r < t.dual.size(); ++r) row[t.dual[r]] = (int64_t)r;
+  const int P0 = g.P[0], P1 = g.P[1];
+  const int np = P0 * P1 * g.P[2];
+  std::vector<std::array<int64_t, 3>> out;
+  for (int s = 0; s < np; ++s) {
+    const int* ijk = plans[s].ijk;
+    for (int dd = 0; dd < 3; ++dd) {
+      if (ijk[dd] + 1 >= g.P[dd]) continue;
+      int n2[3] = {ijk[0], ijk[1], ijk[2]};
+      n2[dd] += 1;
+      const int t2 = n2[0] + P0 * (n2[1] + P1 * n2[2]);
+      if ((plans[s].sigma > 0) == (plans[t2].sigma > 0)) continue;
+      Box f = patch_box(g, ijk[0], ijk[1], ijk[2]);
+      f.lo[dd] = f.hi[dd];
+      const int u = (dd + 1) % 3, v = (dd + 2) % 3;
+      const int64_t nu_ = f.hi[u] - f.lo[u] + 1, nv_ = f.hi[v] - f.lo[v] + 1;
+      // face vertex: 0 = the whole face boundary, else one interior node
+      auto fnode = [&](int64_t I, int64_t J, int64_t K) -> int64_t {
+        const int64_t c[3] = {I, J, K};
+        const int64_t cu = c[u] - f.lo[u], cv = c[v] - f.lo[v];
+        if (cu == 0 || cv == 0 || cu == nu_ - 1 || cv == nv_ - 1) return 0;
+        return 1 + (cu - 1) + (nu_ - 2) * (cv - 1);
+      };
+      const int64_t nfv =
+          1 + std::max<int64_t>(0, nu_ - 2) * std::max<int64_t>(0, nv_ - 2);
+      std::vector<int64_t> tree, cotree;
+      for (int dirn : {u, v}) {
+        int64_t hi[3] = {f.hi[0], f.hi[1], f.hi[2]};
+        hi[dirn] -= 1;
+        for (int64_t K = f.lo[2]; K <= hi[2]; ++K)
+          for (int64_t J = f.lo[1]; J <= hi[1]; ++J)
+            for (int64_t I = f.lo[0]; I <= hi[0]; ++I) {
+              const int64_t e = g.edge_id(dirn, I, J, K);
+              if (in_tg[e]) tree.push_back(e);
+              else if (row[e] >= 0) cotree.push_back(e);
+            }
+      }
+      std::sort(tree.begin(), tree.end());
+      std::sort(cotree.begin(), cotree.end());
+      auto ends = [&](int64_t e, int64_t& a, int64_t& b) {
+        int d2; int64_t I, J, K;
+        g.edge_decode(e, d2, I, J, K);
+        a = fnode(I, J, K);
+        b = fnode(I + (d2 == 0), J + (d2 == 1), K + (d2 == 2));
+      };
+      std::vector<int64_t> va(tree.size()), vb(tree.size()), start, ne, nv;
+      for (size_t k = 0; k < tree.size(); ++k) ends(tree[k], va[k], vb[k]);
+      build_adjacency(nfv, tree, va, vb, start, ne, nv);
+      // psi per face vertex as signed tree edges, grown from the boundary
+      std::vector<std::vector<std::pair<int64_t, int>>> psi(nfv);
+      std::vector<uint8_t> vis(nfv, 0);
+      vis[0] = 1;
+      std::vector<int64_t> queue{0};
+      for (size_t qh = 0; qh < queue.size(); ++qh) {
+        const int64_t x = queue[qh];
+        for (int64_t k = start[x]; k < start[x + 1]; ++k) {
+          const int64_t y = nv[k], e = ne[k];
+          if (vis[y]) continue;
+          vis[y] = 1;
+          int64_t a, b;
+          ends(e, a, b);
+          psi[y] = psi[x];
+          psi[y].push_back({e, a == x ? -1 : 1});  // psi(head) = psi(tail) - a(e)
+          queue.push_back(y);
+        }
+      }
+      for (int64_t e : cotree) {
+        int64_t a, b;
+        ends(e, a, b);
+        std::map<int64_t, int> terms;
+        terms[e] += 1;
+        for (const auto& tc : psi[b]) terms[tc.first] += tc.second;
+        for (const auto& tc : psi[a]) terms[tc.first] -= tc.second;
+        for (const auto& tc : terms)
+          if (tc.second != 0) out.push_back({row[e], tc.first, (int64_t)tc.second});
+      }
+    }
+  }
+  std::sort(out.begin(), out.end());
+  std::vector<int64_t> flat;
+  flat.reserve(out.size() * 3);
+  for (const auto& o : out) flat.insert(flat.end(), o.begin(), o.end());
+  return flat;
 }
 
 }  // namespace tcf

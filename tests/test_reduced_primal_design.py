@@ -262,3 +262,47 @@ def test_sparse_prototype_projection_start(split):
         its.append(it)
     print(f"[loop split] projection start, {split}: iterations {its}")
     assert max(its[2:]) < its[0]
+
+
+def _python_loop_terms(prob, sysm, topo):
+    from tests.feti_loop_ref import loop_structure
+
+    L = loop_structure(prob, sysm, topo)
+    rank = {int(e): r for r, e in enumerate(topo.dual)}
+    out = []
+    for e, _, _ in L["cotree"]:
+        terms = {e: 1.0}
+        x, y = int(L["tail"][e]), int(L["head"][e])
+        for t, w in L["coef"].get(y, {}).items():
+            terms[t] = terms.get(t, 0.0) + w
+        for t, w in L["coef"].get(x, {}).items():
+            terms[t] = terms.get(t, 0.0) - w
+        out += [(rank[e], t, int(c)) for t, c in terms.items() if c != 0]
+    return np.array(sorted(out), dtype=np.int64).reshape(-1, 3)
+
+
+def _loop_host_cases():
+    for name in LOOP_CASES:
+        P, n, p, sig = CASES[name]
+        yield name, tiny(P, n, p, sig)
+    pr = W.uneven_fp64(seed=1, n_steps=1, P=(3, 3, 3))
+    pr.nel = [np.minimum(np.asarray(v), 3).astype(np.int32) for v in pr.nel]
+    yield "uneven_reduced", pr
+    yield "sec4_n4_p3", W.paper_manufactured(n=4, p=3, n_t=2)
+
+
+@pytest.mark.parametrize("case", list(_loop_host_cases()), ids=lambda c: c[0])
+def test_loop_rows_host_plan_matches_the_prototype(case):
+    """The library's host plan of the loop rows (TCF_TOPO_LOOP, C++) against
+    the prototype's, bit-exact: same rows, edges and +-1 coefficients."""
+    _, prob = case
+    g, sysm, topo = _parts(prob)
+    want = _python_loop_terms(prob, sysm, topo)
+    got = tcf.Problem(prob).tcf_get_topology(tcf.TCF_TOPO_LOOP).reshape(-1, 3)
+    assert len(want) > 0
+    assert np.array_equal(got, want)
+    # every row holds its own cotree edge with +1, and only +-1 entries
+    rows = np.unique(got[:, 0])
+    own = {(int(r), int(topo.dual[r])) for r in rows}
+    assert own <= {(int(r), int(e)) for r, e, c in got if c == 1}
+    assert set(np.unique(got[:, 2])) <= {-1, 1}
