@@ -215,7 +215,7 @@ enum tcf_topology_kind {
   TCF_TOPO_MULT = 7,       /* int64[n_lambda][3]: edge id, patch (+1), patch(-1) */
   TCF_TOPO_N = 8,          /* int64[sum_s n_p^(s)][3]: patch, edge id, primal    */
                            /* rank; per patch in increasing edge id              */
-  TCF_TOPO_LOOP = 9        /* int64[n][3]: multiplier row, edge id, +1 / -1.     */
+  TCF_TOPO_LOOP = 9,       /* int64[n][3]: multiplier row, edge id, +1 / -1.     */
                            /* Host plan of a reduced primal split that drops the */
                            /* interface trees from the primal set (the outlook   */
                            /* of Sec. 5): the conductor-side terms of the row of */
@@ -224,6 +224,16 @@ enum tcf_topology_kind {
                            /* sum of a_C along the face-tree path from the face  */
                            /* boundary.  Rows ascending, then edge ids.  Not     */
                            /* used by the solver.                                */
+  TCF_TOPO_LOOP_PSI = 10   /* int64[n][3]: node id, edge id, +1 / -1.  psi of   */
+                           /* the same split as a function of a_C on the face-  */
+                           /* tree edges, at every node where it can be nonzero: */
+                           /* face-interior nodes, then continued as a constant  */
+                           /* along the gauge tree into the insulator (so the    */
+                           /* gauge is kept), stopping at grounded nodes.  The   */
+                           /* load correction of a face-tree edge t is           */
+                           /* -sum_n (G^T f_I)(n) c(n, t).  Nodes ascending,     */
+                           /* then edge ids.  TCF_EINVAL if a gauge subtree hangs */
+                           /* from two face nodes.  Not used by the solver.      */
 };
 
 /*

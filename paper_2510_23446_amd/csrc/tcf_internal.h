@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/tcf.h"
@@ -80,9 +81,17 @@ Grid build_grid(const tcf_problem_desc& d);
 std::string validate_desc(const tcf_problem_desc& d);
 std::string compute_topology(const tcf_problem_desc& d, const Grid& g, Topology& t,
                              std::vector<PatchPlan>& plans);
+// psi of one face node of the loop split: node id, signed face-tree edges
+using NodePsi = std::pair<int64_t, std::vector<std::pair<int64_t, int>>>;
 // Conductor-side terms (row, edge, +-1) of the loop rows of the reduced
-// primal split; see the definition.
+// primal split; see the definition.  With face_psi, also appends psi of
+// every face-interior node that the face trees reach.
 std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
-                               const std::vector<PatchPlan>& plans);
+                               const std::vector<PatchPlan>& plans,
+                               std::vector<NodePsi>* face_psi = nullptr);
+// psi coefficients (node, edge, +-1) of the loop split on the face nodes and
+// along the gauge tree into the insulator; err is set if T_I is inconsistent.
+std::vector<int64_t> loop_psi(const Grid& g, const Topology& t,
+                              const std::vector<PatchPlan>& plans, std::string& err);
 
 }  // namespace tcf

@@ -425,7 +425,7 @@ std::string compute_topology(const tcf_problem_desc& d, const Grid& g, Topology&
 // sum of a_C along its tree path.  Returns the conductor-side terms as
 // (multiplier row, edge id, +1 / -1) triples, by row, then by edge id.
 std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
-                               const std::vector<PatchPlan>& plans) {
+                               const std::vector<PatchPlan>& plans, std::vector<NodePsi>* face_psi) {
   const int64_t nE = g.n_edges();
   std::vector<uint8_t> in_tg(nE, 0);
   for (int64_t e : t.tree_gamma) in_tg[e] = 1;
@@ -494,6 +494,11 @@ std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
           psi[y] = psi[x];
           psi[y].push_back({e, a == x ? -1 : 1});  // psi(head) = psi(tail) - a(e)
           queue.push_back(y);
+          if (face_psi) {
+            int64_t tl, hd;
+            g.edge_nodes(e, tl, hd);
+            face_psi->push_back({a == x ? hd : tl, psi[y]});
+          }
         }
       }
       for (int64_t e : cotree) {
@@ -512,6 +517,84 @@ std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
   std::vector<int64_t> flat;
   flat.reserve(out.size() * 3);
   for (const auto& o : out) flat.insert(flat.end(), o.begin(), o.end());
+  return flat;
+}
+
+// psi of the loop split as a function of a_C on the face-tree edges, at every
+// node where it can be nonzero.  On the interior nodes of each conductor /
+// insulator face it is the signed tree-path sum that loop_rows builds.  Into
+// the insulator it is continued as a constant along the gauge tree T_I (so
+// G psi vanishes on T_I and the gauge is kept), away from grounded nodes:
+// those on the domain boundary or in the closed box of a conductor patch.
+// A subtree of T_I hangs from one face node, since T_I is a tree of the graph
+// in which every conductor closure is one vertex.  The load correction of a
+// face-tree edge t is then -sum_n (G^T f_I)(n) c(n, t) over these terms.
+// Returns (node id, edge id, +1 / -1) triples, by node, then by edge id.
+std::vector<int64_t> loop_psi(const Grid& g, const Topology& t,
+                              const std::vector<PatchPlan>& plans, std::string& err) {
+  std::vector<NodePsi> fp;
+  loop_rows(g, t, plans, &fp);
+  const int64_t nN = g.n_nodes();
+  std::vector<uint8_t> grounded(nN, 0);
+  for (int64_t K = 0; K < g.N[2]; ++K)
+    for (int64_t J = 0; J < g.N[1]; ++J)
+      for (int64_t I = 0; I < g.N[0]; ++I)
+        if (g.node_boundary(I, J, K)) grounded[g.node_id(I, J, K)] = 1;
+  for (const PatchPlan& pp : plans) {
+    if (!(pp.sigma > 0)) continue;
+    const Box b = patch_box(g, pp.ijk[0], pp.ijk[1], pp.ijk[2]);
+    for (int64_t K = b.lo[2]; K <= b.hi[2]; ++K)
+      for (int64_t J = b.lo[1]; J <= b.hi[1]; ++J)
+        for (int64_t I = b.lo[0]; I <= b.hi[0]; ++I) grounded[g.node_id(I, J, K)] = 1;
+  }
+  // T_I as node adjacency (CSR)
+  std::vector<int64_t> start(nN + 1, 0), nbr(2 * t.tree_I.size());
+  for (int64_t e : t.tree_I) {
+    int64_t a, b;
+    g.edge_nodes(e, a, b);
+    ++start[a + 1];
+    ++start[b + 1];
+  }
+  for (int64_t n = 0; n < nN; ++n) start[n + 1] += start[n];
+  {
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t e : t.tree_I) {
+      int64_t a, b;
+      g.edge_nodes(e, a, b);
+      nbr[fill[a]++] = b;
+      nbr[fill[b]++] = a;
+    }
+  }
+  // src[n]: index into fp of the face node whose psi n carries, or -1
+  std::vector<int64_t> src(nN, -1), queue;
+  for (size_t k = 0; k < fp.size(); ++k) {
+    src[fp[k].first] = (int64_t)k;
+    queue.push_back(fp[k].first);
+  }
+  for (size_t qh = 0; qh < queue.size(); ++qh) {
+    const int64_t x = queue[qh];
+    for (int64_t k = start[x]; k < start[x + 1]; ++k) {
+      const int64_t y = nbr[k];
+      if (grounded[y]) continue;
+      if (src[y] >= 0) {
+        if (src[y] != src[x]) {
+          err = "loop split: a gauge subtree is reached from two interface nodes";
+          return {};
+        }
+        continue;
+      }
+      src[y] = src[x];
+      queue.push_back(y);
+    }
+  }
+  std::vector<int64_t> flat;
+  for (int64_t n = 0; n < nN; ++n) {
+    if (src[n] < 0) continue;
+    std::map<int64_t, int> terms;
+    for (const auto& tc : fp[src[n]].second) terms[tc.first] += tc.second;
+    for (const auto& tc : terms)
+      if (tc.second != 0) flat.insert(flat.end(), {n, tc.first, (int64_t)tc.second});
+  }
   return flat;
 }
 

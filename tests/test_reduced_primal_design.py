@@ -306,3 +306,36 @@ def test_loop_rows_host_plan_matches_the_prototype(case):
     own = {(int(r), int(topo.dual[r])) for r in rows}
     assert own <= {(int(r), int(e)) for r, e, c in got if c == 1}
     assert set(np.unique(got[:, 2])) <= {-1, 1}
+
+
+@pytest.mark.parametrize("case", list(_loop_host_cases()), ids=lambda c: c[0])
+def test_loop_psi_host_plan_matches_the_prototype(case):
+    """The library's psi coefficients of the loop split (TCF_TOPO_LOOP_PSI,
+    C++) against the prototype's, bit-exact: the same nodes, face-tree edges
+    and +-1 coefficients, on the face interiors and along the gauge tree into
+    the insulator.  The load correction on the conductor's T_G rows, built
+    from them and G^T of the insulator load, equals the prototype's."""
+    from oracle.grid import incidence_G
+    from tests.feti_loop_ref import loop_structure
+
+    _, prob = case
+    g, sysm, topo = _parts(prob)
+    L = loop_structure(prob, sysm, topo)
+    want = sorted((int(n), int(t), int(w)) for n, c in L["coef"].items()
+                  for t, w in c.items() if w != 0)
+    want = np.array(want, dtype=np.int64).reshape(-1, 3)
+    got = tcf.Problem(prob).tcf_get_topology(tcf.TCF_TOPO_LOOP_PSI).reshape(-1, 3)
+    assert len(want) > 0
+    assert np.array_equal(got, want)
+    # psi lives on face-tree edges only
+    assert set(np.unique(got[:, 1])) <= set(int(e) for e in topo.tree_gamma)
+    # load correction from the host plan against the prototype's
+    fI = np.zeros((g.n_edges, prob.n_rhs))
+    for s, pm in enumerate(sysm.patches):
+        if not prob.sigma[s] > 0:
+            np.add.at(fI, pm.gid, pm.jhat)
+    gn = incidence_G(g).tocsr().T @ fI
+    corr = np.zeros((g.n_edges, prob.n_rhs))
+    np.add.at(corr, got[:, 1], -gn[got[:, 0]] * got[:, 2:3])
+    scale = max(np.abs(L["corr"]).max(), 1e-300)
+    assert np.abs(corr - L["corr"]).max() <= 1e-12 * scale
