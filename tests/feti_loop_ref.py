@@ -180,11 +180,58 @@ def loop_structure(prob, sysm, topo):
                 coef=coef, cotree=cotree, corr=corr)
 
 
-class LoopFETI(DenseFETI):
-    """FETI-DP on the loop split; same operators and PCG as DenseFETI."""
+def loop_structure_from_host_plan(prob, sysm, topo, loop_terms, psi_terms):
+    """The same data as loop_structure, built only from the library's host
+    plan: loop_terms (multiplier row, edge, +-1) are the conductor-side terms
+    of every loop row, psi_terms (node, edge, +-1) the coefficients of psi.
+    The cotree rows come from the multiplier table, the load correction from
+    psi and G^T of the insulator load.  Also returns the rows' terms
+    (row_terms: multiplier row -> [(edge, +-1)])."""
+    grid = sysm.grid
+    nE = grid.n_edges
+    tail, head = grid.edge_nodes(np.arange(nE))
+    cond = np.asarray(prob.sigma) > 0
+    tg = np.asarray(topo.tree_gamma, dtype=np.int64)
+    in_tg = np.zeros(nE, dtype=bool)
+    in_tg[tg] = True
+    coef = {}
+    for n, t, w in np.asarray(psi_terms, dtype=np.int64).reshape(-1, 3):
+        coef.setdefault(int(n), {})[int(t)] = float(w)
+    row_terms = {}
+    for r, t, w in np.asarray(loop_terms, dtype=np.int64).reshape(-1, 3):
+        row_terms.setdefault(int(r), []).append((int(t), float(w)))
+    cotree = []
+    for r in sorted(row_terms):
+        e, sp, sm = (int(v) for v in topo.mult[r])
+        cotree.append((e, sp, sm) if cond[sp] else (e, sm, sp))
+    GI = incidence_G(grid).tocsr()
+    fI = np.zeros((nE, prob.n_rhs))
+    for s, pm in enumerate(sysm.patches):
+        if not cond[s]:
+            np.add.at(fI, pm.gid, pm.jhat)
+    g = GI.T @ fI
+    corr = np.zeros((nE, prob.n_rhs))
+    for n, c in coef.items():
+        for t, w in c.items():
+            corr[t] -= g[n] * w
+    return dict(grid=grid, nE=nE, tail=tail, head=head, cond=cond, tg=tg, in_tg=in_tg,
+                coef=coef, cotree=cotree, corr=corr, row_terms=row_terms)
 
-    def __init__(self, prob, sysm, topo, load_correction=True, weights="stiffness"):
-        L = loop_structure(prob, sysm, topo)
+
+class LoopFETI(DenseFETI):
+    """FETI-DP on the loop split; same operators and PCG as DenseFETI.
+
+    With host_plan = (loop_terms, psi_terms), the library's arrays of the
+    loop rows and of psi replace this file's own construction: the conductor
+    side of each loop row takes the row's terms as given."""
+
+    def __init__(self, prob, sysm, topo, load_correction=True, weights="stiffness",
+                 host_plan=None):
+        if host_plan is None:
+            L = loop_structure(prob, sysm, topo)
+        else:
+            L = loop_structure_from_host_plan(prob, sysm, topo, *host_plan)
+        row_terms = L.get("row_terms")
         grid, nE, tail, head, cond = L["grid"], L["nE"], L["tail"], L["head"], L["cond"]
         tg, in_tg, coef, cotree, corr = L["tg"], L["in_tg"], L["coef"], L["cotree"], L["corr"]
         self.coef = coef
@@ -222,6 +269,9 @@ class LoopFETI(DenseFETI):
                     cs, is_ = loop_rows[int(e)]
                     if s == is_:
                         B[r, bpos[int(e)]] = -1.0
+                    elif row_terms is not None:
+                        for t, w in row_terms[r]:
+                            B[r, bpos[t]] += w
                     else:
                         B[r, bpos[int(e)]] += 1.0
                         x, y = int(tail[e]), int(head[e])

@@ -16,6 +16,9 @@ matrices stay nonsingular.  These tests check, against the oracle:
   interface;
 * the load correction on the conductor's T_G rows is needed: planted out, the
   Sec. 4 field is wrong;
+* the library's host plan of the loop split (TCF_TOPO_LOOP, TCF_TOPO_LOOP_PSI)
+  matches the prototype bit for bit, and the split driven by it alone gives
+  the oracle's field;
 * the iteration counts.  The Dirichlet preconditioner is weighted so that
   sum_s B_D,s B_s^T = I.  With stiffness weights (loop rows split between
   the insulator's entry and a pseudo-inverse of the conductor's loop rows),
@@ -339,3 +342,31 @@ def test_loop_psi_host_plan_matches_the_prototype(case):
     np.add.at(corr, got[:, 1], -gn[got[:, 0]] * got[:, 2:3])
     scale = max(np.abs(L["corr"]).max(), 1e-300)
     assert np.abs(corr - L["corr"]).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("case", list(_loop_host_cases())[:5] + [
+    ("sec4_n2_p2", W.paper_manufactured(n=2, p=2, n_t=3))], ids=lambda c: c[0])
+def test_loop_split_runs_from_the_library_host_plan(case):
+    """The loop split driven only by the library's host plan (TCF_TOPO_LOOP
+    for the conductor side of every loop row, TCF_TOPO_LOOP_PSI for psi, the
+    recovery and the load correction): its field, mapped back to the
+    oracle's gauge, equals the oracle's element by element, with the same
+    PCG iterations as the prototype's own construction."""
+    _, prob = case
+    g, sysm, topo = _parts(prob)
+    ref = solve.run(prob)
+    h = tcf.Problem(prob)
+    plan = (h.tcf_get_topology(tcf.TCF_TOPO_LOOP), h.tcf_get_topology(tcf.TCF_TOPO_LOOP_PSI))
+    lf = LoopFETI(prob, sysm, topo, host_plan=plan)
+    own = LoopFETI(prob, sysm, topo)
+    for a, b in zip(lf.pat, own.pat):
+        assert np.array_equal(a["B"], b["B"])
+    a, worst = np.zeros(g.n_edges), 0.0
+    for l in range(prob.n_steps):
+        fields, it = lf.step_local(a, prob.amp[0, l], first=(l == 0))
+        _, it_own = own.step_local(a, prob.amp[0, l], first=(l == 0))
+        assert it == it_own
+        a = lf.conforming(fields)
+        r = ref.fields[l][:, 0]
+        worst = max(worst, np.linalg.norm(a - r) / np.linalg.norm(r))
+    assert worst <= 1e-9, worst
