@@ -370,3 +370,40 @@ def test_loop_split_runs_from_the_library_host_plan(case):
         r = ref.fields[l][:, 0]
         worst = max(worst, np.linalg.norm(a - r) / np.linalg.norm(r))
     assert worst <= 1e-9, worst
+
+
+@pytest.mark.parametrize("case", list(_loop_host_cases()), ids=lambda c: c[0])
+def test_loop_split_operators_in_multiplier_row_space(case):
+    """The GPU plan of the loop split keeps today's per-iteration kernels by
+    storing each patch's operators over the multiplier rows it touches,
+    R_s: T_s = B_s S_bb^-1 B_s^T, P_s = B_s Phi_b and D_s = B_D,s S_bb
+    B_D,s^T.  The loop rows of a face reach only the conductor of that face,
+    so R_s is the patch's own dual rows and the tiles are no larger than
+    today's (n_b x n_b, n_b x n_p).  F and the preconditioner assembled from
+    these tiles equal the loop split's own on random multipliers."""
+    _, prob = case
+    g, sysm, topo = _parts(prob)
+    lf = LoopFETI(prob, sysm, topo)
+    rankL = {int(e): r for r, e in enumerate(topo.dual)}
+    dt, tiles = lf.dt, []
+    for s, d in enumerate(lf.pat):
+        rows = np.flatnonzero(np.any(d["B"] != 0, axis=1) | np.any(d["BD"] != 0, axis=1))
+        own = np.sort([rankL[int(e)] for e in topo.local[s]["b"]])
+        assert np.array_equal(rows, own), s
+        assert len(d["N"]) <= len(topo.local[s]["p"])
+        B, BD = d["B"][rows], d["BD"][rows]
+        tiles.append((rows, d["N"], B @ d["Sbbinv"] @ B.T, B @ d["Phi"], BD @ d["Sbb"] @ BD.T))
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        lam = rng.standard_normal(lf.nL)
+        c = np.zeros(lf.nP)
+        for R, N, T, P, D in tiles:
+            np.add.at(c, N, dt * P.T @ lam[R])
+        q = np.linalg.solve(lf.SPi, c) if lf.nP else c
+        y, z = np.zeros(lf.nL), np.zeros(lf.nL)
+        for R, N, T, P, D in tiles:
+            np.add.at(y, R, dt * (dt * T @ lam[R] + P @ q[N]))
+            np.add.at(z, R, D @ lam[R])
+        Fl, Ml = lf.F(lam), lf.precond(lam)
+        assert np.abs(y - Fl).max() <= 1e-12 * np.abs(Fl).max()
+        assert np.abs(z - Ml).max() <= 1e-12 * np.abs(Ml).max()
