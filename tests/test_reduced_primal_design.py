@@ -407,3 +407,13 @@ def test_loop_split_operators_in_multiplier_row_space(case):
         Fl, Ml = lf.F(lam), lf.precond(lam)
         assert np.abs(y - Fl).max() <= 1e-12 * np.abs(Fl).max()
         assert np.abs(z - Ml).max() <= 1e-12 * np.abs(Ml).max()
+
+
+@pytest.mark.parametrize("name", ["all_insulator", "all_conductor", "single_insulator"])
+def test_loop_host_plan_empty_without_an_interface_face(name):
+    """With no conductor/insulator face there are no loop rows and psi is
+    zero: both host-plan queries return empty arrays, not an error."""
+    P, n, p, sig = CASES[name]
+    h = tcf.Problem(tiny(P, n, p, sig))
+    assert h.tcf_get_topology(tcf.TCF_TOPO_LOOP).size == 0
+    assert h.tcf_get_topology(tcf.TCF_TOPO_LOOP_PSI).size == 0
