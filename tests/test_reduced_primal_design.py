@@ -417,3 +417,40 @@ def test_loop_host_plan_empty_without_an_interface_face(name):
     h = tcf.Problem(tiny(P, n, p, sig))
     assert h.tcf_get_topology(tcf.TCF_TOPO_LOOP).size == 0
     assert h.tcf_get_topology(tcf.TCF_TOPO_LOOP_PSI).size == 0
+
+
+def test_loop_split_bytes_per_iteration_estimate():
+    """The estimate of FP64 operator bytes streamed per PCG iteration on the
+    benchmark layout (64 uneven patches), from the library's host plan, for
+    the published tree split and for the loop split with operators in
+    multiplier-row space.  Per patch, the F apply reads packed S_bb^-1
+    (n_b(n_b+1)/2) and Phi_b (n_b n_p), the Phi pass reads Phi_b again and
+    the preconditioner packed S_bb; the coarse apply reads packed S_Pi^-1
+    (n_Pi(n_Pi+1)/2).  The loop split keeps n_b (each patch touches its own
+    dual rows), takes a patch's face-tree edges out of its n_p and the
+    interface trees out of n_Pi.  An estimate from counts, not a measurement."""
+    prob = W.uneven_fp64(seed=1, n_steps=1)
+    h = tcf.Problem(prob)
+    mult = h.tcf_get_topology(tcf.TCF_TOPO_MULT).reshape(-1, 3)
+    ntab = h.tcf_get_topology(tcf.TCF_TOPO_N).reshape(-1, 3)
+    tg = np.zeros(h.counts()["n_edges"], dtype=bool)
+    tg[h.tcf_get_topology(tcf.TCF_TOPO_TREE_GAMMA)] = True
+    S = prob.n_patches
+    nb = np.bincount(mult[:, 1], minlength=S) + np.bincount(mult[:, 2], minlength=S)
+    npp = np.bincount(ntab[:, 0], minlength=S)
+    ng = np.bincount(ntab[tg[ntab[:, 1]], 0], minlength=S)
+    nP = h.counts()["n_primal"]
+    nPl = nP - int(tg.sum())
+
+    def mb(nb, npp, nP):
+        F = np.sum(nb * (nb + 1) / 2 + nb * npp) * 8
+        return np.array([F, nP * (nP + 1) / 2 * 8, np.sum(nb * npp) * 8,
+                         np.sum(nb * (nb + 1) / 2) * 8]) / 1e6
+
+    tree, loop = mb(nb, npp, nP), mb(nb, npp - ng, nPl)
+    print(f"[loop split] MB per PCG iteration (F, coarse, Phi, precond): tree "
+          f"{np.round(tree, 1)} = {tree.sum():.1f}, loop {np.round(loop, 1)} = {loop.sum():.1f}")
+    assert (nP, nPl) == (5416, 995)
+    assert abs(tree.sum() - 443.4) < 0.1 and abs(loop.sum() - 242.8) < 0.1
+    assert np.allclose(tree[:3], [163.0, 117.4, 64.7], atol=0.1)
+    assert np.allclose(loop[:3], [119.4, 4.0, 21.1], atol=0.1)
