@@ -224,7 +224,7 @@ enum tcf_topology_kind {
                            /* sum of a_C along the face-tree path from the face  */
                            /* boundary.  Rows ascending, then edge ids.  Not     */
                            /* used by the solver.                                */
-  TCF_TOPO_LOOP_PSI = 10   /* int64[n][3]: node id, edge id, +1 / -1.  psi of   */
+  TCF_TOPO_LOOP_PSI = 10,  /* int64[n][3]: node id, edge id, +1 / -1.  psi of   */
                            /* the same split as a function of a_C on the face-  */
                            /* tree edges, at every node where it can be nonzero: */
                            /* face-interior nodes, then continued as a constant  */
@@ -234,6 +234,19 @@ enum tcf_topology_kind {
                            /* -sum_n (G^T f_I)(n) c(n, t).  Nodes ascending,     */
                            /* then edge ids.  TCF_EINVAL if a gauge subtree hangs */
                            /* from two face nodes.  Not used by the solver.      */
+  TCF_TOPO_LOOP_PLAN = 11  /* int64[n][5]: per-patch plan of the same split,    */
+                           /* patches in order.  The interface-tree edges leave  */
+                           /* the primal set: a conductor appends its own to its */
+                           /* b block (by edge id), an insulator eliminates them;*/
+                           /* the i block is unchanged; coarse ranks renumber    */
+                           /* the primal edges left.  Records:                   */
+                           /*  (s, 0, b index, edge id, 0): b block, in order;   */
+                           /*  (s, 1, p index, edge id, coarse rank): p block;   */
+                           /*  (s, 2, row, b index, +1 / -1): entries of B_s, by */
+                           /*  row then b index.  On a loop row the insulator's  */
+                           /*  entry is -1 and the conductor's are the row's     */
+                           /*  TCF_TOPO_LOOP terms; other rows keep the          */
+                           /*  multiplier table's signs.  Not used by the solver.*/
 };
 
 /*

@@ -585,6 +585,9 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
     case TCF_TOPO_LOOP:
       tmp = loop_rows(h->g, h->topo, h->plans);
       break;
+    case TCF_TOPO_LOOP_PLAN:
+      tmp = loop_plan(h->g, h->topo, h->plans);
+      break;
     case TCF_TOPO_LOOP_PSI: {
       std::string err;
       tmp = loop_psi(h->g, h->topo, h->plans, err);

@@ -94,4 +94,9 @@ std::vector<int64_t> loop_rows(const Grid& g, const Topology& t,
 std::vector<int64_t> loop_psi(const Grid& g, const Topology& t,
                               const std::vector<PatchPlan>& plans, std::string& err);
 
+// Per-patch plan of the loop split as 5-wide records (patch, kind, ...):
+// kind 0 b block, kind 1 p block with coarse ranks, kind 2 entries of B_s.
+std::vector<int64_t> loop_plan(const Grid& g, const Topology& t,
+                               const std::vector<PatchPlan>& plans);
+
 }  // namespace tcf

@@ -598,4 +598,64 @@ std::vector<int64_t> loop_psi(const Grid& g, const Topology& t,
   return flat;
 }
 
+// Per-patch plan of the loop split, in the layout the device setup would take.
+// The interface trees leave the primal set: a conductor keeps its face-tree
+// edges as remainder, appended to its b block (by edge id); an insulator
+// eliminates them.  The i block is unchanged.  Coarse ranks are renumbered
+// over the primal edges left.  Each own b edge carries its multiplier row:
+// on a loop row the insulator's entry is -1 and the conductor's entries are
+// the row's loop terms (own edge and face-tree path); on any other row the
+// entry is today's +1 on the lower patch id, -1 on the other.
+// Returns 5-wide records, per patch in order:
+//   (s, 0, b index, edge id, 0)       b block, in order
+//   (s, 1, p index, edge id, rank)    p block, in order, coarse rank
+//   (s, 2, row, b index, +1 / -1)     entries of B_s, by row, then b index
+std::vector<int64_t> loop_plan(const Grid& g, const Topology& t,
+                               const std::vector<PatchPlan>& plans) {
+  const int64_t nE = g.n_edges();
+  std::vector<uint8_t> in_tg(nE, 0);
+  for (int64_t e : t.tree_gamma) in_tg[e] = 1;
+  std::vector<int64_t> rank(nE, -1);
+  int64_t nP = 0;
+  for (int64_t e : t.primal)
+    if (!in_tg[e]) rank[e] = nP++;
+  const std::vector<int64_t> lr = loop_rows(g, t, plans);
+  std::map<int64_t, std::vector<std::pair<int64_t, int>>> terms;
+  for (size_t k = 0; k + 2 < lr.size(); k += 3) terms[lr[k]].push_back({lr[k + 1], (int)lr[k + 2]});
+  std::vector<int64_t> out;
+  for (size_t s = 0; s < plans.size(); ++s) {
+    const PatchPlan& pp = plans[s];
+    const bool cond = pp.sigma > 0;
+    std::vector<int64_t> b_gid(pp.r_gid.begin() + pp.n_i, pp.r_gid.begin() + pp.n_i + pp.n_b);
+    std::vector<int64_t> p_gid;
+    for (int j = 0; j < pp.n_p; ++j) {
+      const int64_t e = pp.r_gid[pp.n_i + pp.n_b + j];
+      if (!in_tg[e]) p_gid.push_back(e);
+      else if (cond) b_gid.push_back(e);
+    }
+    std::map<int64_t, int64_t> bpos;
+    for (size_t k = 0; k < b_gid.size(); ++k) {
+      bpos[b_gid[k]] = (int64_t)k;
+      out.insert(out.end(), {(int64_t)s, 0, (int64_t)k, b_gid[k], 0});
+    }
+    for (size_t k = 0; k < p_gid.size(); ++k)
+      out.insert(out.end(), {(int64_t)s, 1, (int64_t)k, p_gid[k], rank[p_gid[k]]});
+    std::vector<std::array<int64_t, 3>> ent;
+    for (int k = 0; k < pp.n_b; ++k) {
+      const int64_t r = pp.b_row[k];
+      auto it = terms.find(r);
+      if (it == terms.end()) {
+        ent.push_back({r, k, pp.b_sgn[k]});
+      } else if (!cond) {
+        ent.push_back({r, k, -1});
+      } else {
+        for (const auto& tc : it->second) ent.push_back({r, bpos.at(tc.first), tc.second});
+      }
+    }
+    std::sort(ent.begin(), ent.end());
+    for (const auto& x : ent) out.insert(out.end(), {(int64_t)s, 2, x[0], x[1], x[2]});
+  }
+  return out;
+}
+
 }  // namespace tcf

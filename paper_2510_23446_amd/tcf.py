@@ -22,7 +22,7 @@ TCF_FP64, TCF_FP32_IR, TCF_FP32_FULL_IR = 0, 1, 2
 PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32_FULL_IR}
 (TCF_TOPO_COUNTS, TCF_TOPO_DIRICHLET, TCF_TOPO_TREE_I, TCF_TOPO_TREE_GAMMA, TCF_TOPO_PRIMAL,
  TCF_TOPO_DUAL, TCF_TOPO_INTERIOR, TCF_TOPO_MULT, TCF_TOPO_N, TCF_TOPO_LOOP,
- TCF_TOPO_LOOP_PSI) = range(11)
+ TCF_TOPO_LOOP_PSI, TCF_TOPO_LOOP_PLAN) = range(12)
 
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
            "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",

@@ -7,8 +7,8 @@ import pytest
 
 
 def test_topology_code_is_clean_under_sanitizers(tmp_path):
-    """The host topology code and the loop-split host plan (loop rows, psi),
-    built with AddressSanitizer and UBSan (any finding aborts), run on four
+    """The host topology code and the loop-split host plan (loop rows, psi,
+    per-patch plan), built with AddressSanitizer and UBSan (any finding aborts), run on four
     layouts (a floating conductor and two checkerboards among them) without
     a report."""
     import shutil
@@ -34,4 +34,5 @@ def test_topology_code_is_clean_under_sanitizers(tmp_path):
     for line in lines:
         f = line.split()
         assert int(f[f.index("loop") + 2]) > 0 and int(f[f.index("psi") + 2]) > 0, line
+        assert int(f[f.index("plan") + 2]) > 0, line
         assert line.endswith("err ''"), line

@@ -454,3 +454,34 @@ def test_loop_split_bytes_per_iteration_estimate():
     assert abs(tree.sum() - 443.4) < 0.1 and abs(loop.sum() - 242.8) < 0.1
     assert np.allclose(tree[:3], [163.0, 117.4, 64.7], atol=0.1)
     assert np.allclose(loop[:3], [119.4, 4.0, 21.1], atol=0.1)
+
+
+@pytest.mark.parametrize("case", list(_loop_host_cases()), ids=lambda c: c[0])
+def test_loop_plan_per_patch_matches_the_prototype(case):
+    """The library's per-patch plan of the loop split (TCF_TOPO_LOOP_PLAN):
+    b block, p block with reduced coarse ranks and the entries of B_s equal
+    the prototype's, bit for bit, patch by patch.  The prototype's field
+    equals the oracle's, so this is the layout a device setup of the split
+    would take."""
+    _, prob = case
+    g, sysm, topo = _parts(prob)
+    lf = LoopFETI(prob, sysm, topo)
+    rec = tcf.Problem(prob).tcf_get_topology(tcf.TCF_TOPO_LOOP_PLAN).reshape(-1, 5)
+    assert rec.size > 0
+    for s, d in enumerate(lf.pat):
+        mine = rec[rec[:, 0] == s]
+        b = mine[mine[:, 1] == 0]
+        p = mine[mine[:, 1] == 1]
+        ent = mine[mine[:, 1] == 2]
+        assert np.array_equal(b[:, 2], np.arange(len(b)))
+        assert np.array_equal(b[:, 3], d["gid"][d["b"]]), s
+        assert np.array_equal(p[:, 2], np.arange(len(p)))
+        assert np.array_equal(p[:, 3], d["gid"][d["p"]]), s
+        assert np.array_equal(p[:, 4], d["N"]), s
+        B = np.zeros((lf.nL, len(b)))
+        B[ent[:, 2], ent[:, 3]] = ent[:, 4]
+        assert np.array_equal(B, d["B"]), s
+        # B_s has entries only on the patch's own dual rows
+        own = {int(r) for r, e in enumerate(topo.dual) if int(e) in set(d["gid"][d["b"]].tolist())}
+        assert set(ent[:, 2].tolist()) <= own
+    assert lf.nP == len(np.unique(rec[rec[:, 1] == 1, 4]))

@@ -1,9 +1,9 @@
 /*
  * Host-only driver of the topology code (gauge tree, primal/dual split,
- * multiplier table) and of the loop-split host plan (loop rows, psi), built
- * with AddressSanitizer and UBSan by the test that runs it.  Four layouts:
- * conductors below, an uneven checkerboard, a floating conductor and a flat
- * 4x4x2 checkerboard; each prints its sizes.
+ * multiplier table) and of the loop-split host plan (loop rows, psi, per-patch
+ * plan), built with AddressSanitizer and UBSan by the test that runs it.  Four
+ * layouts: conductors below, an uneven checkerboard, a floating conductor and a
+ * flat 4x4x2 checkerboard; each prints its sizes.
  */
 #include <cstdio>
 #include <vector>
@@ -36,8 +36,9 @@ static int run(const char* name, int P0, int P1, int P2, std::vector<double> sig
   auto lr = loop_rows(g, t, plans);
   std::string err;
   auto lp = loop_psi(g, t, plans, err);
-  printf("%s: edges %lld loop terms %zu psi terms %zu err '%s'\n", name, (long long)g.n_edges(),
-         lr.size() / 3, lp.size() / 3, err.c_str());
+  auto pl = loop_plan(g, t, plans);
+  printf("%s: edges %lld plan records %zu loop terms %zu psi terms %zu err '%s'\n", name,
+         (long long)g.n_edges(), pl.size() / 5, lr.size() / 3, lp.size() / 3, err.c_str());
   return err.empty() ? 0 : 1;
 }
 
