@@ -24,6 +24,8 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -583,14 +585,21 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
       }
       break;
     case TCF_TOPO_LOOP:
-      tmp = loop_rows(h->g, h->topo, h->plans);
-      break;
     case TCF_TOPO_LOOP_PLAN:
-      tmp = loop_plan(h->g, h->topo, h->plans);
-      break;
     case TCF_TOPO_LOOP_PSI: {
+      // host plans of the loop split: built on demand, so allocation or a
+      // lookup can fail here; no exception crosses the C-ABI
       std::string err;
-      tmp = loop_psi(h->g, h->topo, h->plans, err);
+      try {
+        if (kind == TCF_TOPO_LOOP) tmp = loop_rows(h->g, h->topo, h->plans);
+        else if (kind == TCF_TOPO_LOOP_PLAN) tmp = loop_plan(h->g, h->topo, h->plans);
+        else tmp = loop_psi(h->g, h->topo, h->plans, err);
+      } catch (const std::bad_alloc&) {
+        const_cast<tcf_problem*>(h)->err = "out of host memory in the loop-split plan";
+        return TCF_ENOMEM;
+      } catch (const std::exception& ex) {
+        err = std::string("loop-split plan: ") + ex.what();
+      }
       if (!err.empty()) {
         const_cast<tcf_problem*>(h)->err = err;
         return TCF_EINVAL;
