@@ -540,12 +540,12 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   try {
     h->g = build_grid(d);
     e = compute_topology(d, h->g, h->topo, h->plans);
+    if (e.empty()) build_plan(h.get());
   } catch (const std::bad_alloc&) {
-    g_create_error = "out of host memory in topology";
+    g_create_error = "out of host memory in topology or device plan";
     return TCF_ENOMEM;
   }
   if (!e.empty()) { g_create_error = e; return TCF_EINVAL; }
-  build_plan(h.get());
   *out = h.release();
   return TCF_OK;
 }
@@ -1532,14 +1532,19 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   HIPCHK(hipGetDevice(&h->device));
   const double t0 = now_ms();
   int rc;
-  if (h->precision == TCF_FP32_FULL_IR) {
-    rc = setup_impl<float>(h, st);
-  } else {
-    rc = setup_impl<double>(h, st);
-    if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
+  try {
+    if (h->precision == TCF_FP32_FULL_IR) {
+      rc = setup_impl<float>(h, st);
+    } else {
+      rc = setup_impl<double>(h, st);
+      if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
+    }
+    if (!rc && h->use_tiles)
+      rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
+  } catch (const std::bad_alloc&) {
+    h->err = "out of host memory in setup";
+    return TCF_ENOMEM;
   }
-  if (!rc && h->use_tiles)
-    rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
   if (rc) return rc;
   h->setup_ms = now_ms() - t0;
   h->is_setup = true;
@@ -2193,8 +2198,13 @@ int tcf_step(tcf_problem* h, int32_t nsteps, void* stream) {
   nsteps = std::min(nsteps, h->n_steps - h->steps_done);
   if (nsteps <= 0) return TCF_OK;
   hipStream_t st = (hipStream_t)stream;
-  return h->precision == TCF_FP64 ? step_impl<double>(h, nsteps, st)
-                                  : step_impl<float>(h, nsteps, st);  // FP32 operators
+  try {
+    return h->precision == TCF_FP64 ? step_impl<double>(h, nsteps, st)
+                                    : step_impl<float>(h, nsteps, st);  // FP32 operators
+  } catch (const std::bad_alloc&) {
+    h->err = "out of host memory in step";
+    return TCF_ENOMEM;
+  }
 }
 
 int tcf_sync(tcf_problem* h, void* stream) {

@@ -84,20 +84,29 @@ void tcf_server::run_request(Request* r) {
     if (rc == TCF_ENOCONV) rc = TCF_OK;  // flagged in the stats, results kept
   }
   if (rc == TCF_OK) {
-    tcf_get_stats(r->h, &r->stats);
-    const int n = r->stats.steps_done;
-    r->step_ms.resize(n);
-    tcf_get_step_log(r->h, n, nullptr, nullptr, r->step_ms.data());
-    int64_t cnt[8];
-    size_t len = 8;
-    tcf_get_topology(r->h, TCF_TOPO_COUNTS, cnt, &len);
-    // number of excitations: fetch until the library refuses the index
-    for (int k = 0;; ++k) {
-      std::vector<double> f((size_t)cnt[0]);
-      if (tcf_get_field(r->h, k, f.data(), f.size(), 0, st) != TCF_OK) break;
-      r->fields.push_back(std::move(f));
+    // an exception must not leave this thread: a failed allocation fails
+    // the request instead
+    try {
+      tcf_get_stats(r->h, &r->stats);
+      const int n = r->stats.steps_done;
+      r->step_ms.resize(n);
+      tcf_get_step_log(r->h, n, nullptr, nullptr, r->step_ms.data());
+      int64_t cnt[8];
+      size_t len = 8;
+      tcf_get_topology(r->h, TCF_TOPO_COUNTS, cnt, &len);
+      // number of excitations: fetch until the library refuses the index
+      for (int k = 0;; ++k) {
+        std::vector<double> f((size_t)cnt[0]);
+        if (tcf_get_field(r->h, k, f.data(), f.size(), 0, st) != TCF_OK) break;
+        r->fields.push_back(std::move(f));
+      }
+    } catch (const std::bad_alloc&) {
+      rc = TCF_ENOMEM;
+      r->fields.clear();
+      r->err = "out of host memory while fetching the results";
     }
-  } else if (r->err.empty()) {
+  }
+  if (rc != TCF_OK && r->err.empty()) {
     r->err = std::string("status ") + std::to_string(rc) + ": " + tcf_last_error(r->h);
   }
   tcf_destroy(r->h);  // releases the request's device memory
@@ -156,7 +165,23 @@ void tcf_server::dispatch_loop() {
     used += r->footprint;
     peak = std::max(peak, used);
     ++running;
-    workers.emplace_back(r, std::thread([this, r] { run_request(r); }));
+    // room first, so that a started thread is always stored (a joinable
+    // std::thread destroyed unjoined ends the process); if no thread can be
+    // started, the request fails here and gives its slot back
+    try {
+      workers.reserve(workers.size() + 1);
+      workers.emplace_back(r, std::thread([this, r] { run_request(r); }));
+    } catch (const std::exception&) {
+      used -= r->footprint;
+      --running;
+      r->status = TCF_ENOMEM;
+      r->state = TCF_REQ_FAILED;
+      r->err = "could not start a worker thread for the request";
+      r->t_done = now_ms();
+      tcf_destroy(r->h);
+      r->h = nullptr;
+      cv.notify_all();
+    }
   }
 }
 
@@ -169,7 +194,12 @@ int tcf_server_create(size_t max_bytes, int32_t max_slots, tcf_server** out) {
   s->max_bytes = max_bytes;
   s->max_slots = max_slots;
   if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
-  s->dispatcher = std::thread([s] { s->dispatch_loop(); });
+  try {
+    s->dispatcher = std::thread([s] { s->dispatch_loop(); });
+  } catch (const std::exception&) {
+    delete s;
+    return TCF_ENOMEM;
+  }
   *out = s;
   return TCF_OK;
 }
@@ -183,24 +213,34 @@ int tcf_server_submit(tcf_server* srv, const tcf_problem_desc* desc, const tcf_o
   size_t b64 = 0, b32 = 0;
   tcf_footprint(h, &b64, &b32);
   const int prec = opts ? opts->precision : TCF_FP64;
-  auto r = std::make_unique<Request>();
-  r->h = h;
-  r->footprint = prec == TCF_FP64 ? b64 : b32;
-  r->t_submit = now_ms();
+  const size_t footprint = prec == TCF_FP64 ? b64 : b32;
+  const bool fits = footprint <= srv->max_bytes;
   std::lock_guard<std::mutex> lk(srv->mu);
-  r->id = (int)srv->reqs.size();
-  *req_id = r->id;
-  if (r->footprint > srv->max_bytes) {
-    r->state = TCF_REQ_FAILED;
-    r->status = TCF_ENOMEM;
-    r->err = "request footprint exceeds the server memory budget";
-    tcf_destroy(r->h);
-    r->h = nullptr;
-    srv->reqs.push_back(std::move(r));
+  // everything that can throw comes first, before the request is visible:
+  // the record, room in the request list and the queue entry
+  std::unique_ptr<Request> r;
+  try {
+    r = std::make_unique<Request>();
+    if (!fits) r->err = "request footprint exceeds the server memory budget";
+    srv->reqs.reserve(srv->reqs.size() + 1);
+    if (fits) srv->queue.push_back((int)srv->reqs.size());
+  } catch (const std::bad_alloc&) {
+    tcf_destroy(h);
     return TCF_ENOMEM;
   }
-  srv->queue.push_back(r->id);
-  srv->reqs.push_back(std::move(r));
+  r->h = h;
+  r->footprint = footprint;
+  r->t_submit = now_ms();
+  r->id = (int)srv->reqs.size();
+  *req_id = r->id;
+  if (!fits) {
+    r->state = TCF_REQ_FAILED;
+    r->status = TCF_ENOMEM;
+    tcf_destroy(r->h);
+    r->h = nullptr;
+  }
+  srv->reqs.push_back(std::move(r));  // room reserved above
+  if (!fits) return TCF_ENOMEM;
   srv->cv.notify_all();
   return TCF_OK;
 }

@@ -115,3 +115,32 @@ def test_server_lifecycle_without_a_device():
         assert st["completed"] == st["running"] == st["queued"] == 0
     finally:
         srv.tcf_server_destroy()
+
+
+def test_server_rejects_an_oversize_request_without_a_device():
+    """Admission by footprint is host work: a request larger than the budget
+    is refused with TCF_ENOMEM at submission, keeps an id of its own (so the
+    ids of later requests stay consistent) and does not block the queue."""
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("checks the host-side path taken when no device is present")
+    import workloads as W
+
+    prob = W.plain_fp64().with_steps(1)
+    fp = tcf.Problem(prob).tcf_footprint()[0]
+    srv = tcf.Server(max_bytes=fp // 2, max_slots=2)
+    try:
+        with pytest.raises(tcf.TcfError) as err:
+            srv.tcf_server_submit(prob, precision="fp64")
+        assert err.value.code == tcf.TCF_ENOMEM
+        small = W.plain_fp64().with_steps(1)
+        small.nel = [np.minimum(np.asarray(v), 2).astype(np.int32) for v in small.nel]
+        assert tcf.Problem(small).tcf_footprint()[0] <= fp // 2
+        i = srv.tcf_server_submit(small, precision="fp64")
+        assert i == 1  # id 0 is the rejected request
+        assert srv.tcf_server_poll(0) == tcf.TCF_REQ_FAILED
+        assert "budget" in srv.tcf_server_error(0)
+        assert srv.tcf_server_wait(i) == tcf.TCF_EHIP
+    finally:
+        srv.tcf_server_destroy()
