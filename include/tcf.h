@@ -252,7 +252,8 @@ enum tcf_topology_kind {
 /*
  * Topology of the split, for bit-exact checks.  With out == NULL, *len
  * receives the number of int64 values; otherwise *len is the capacity on
- * entry and the count written on return (TCF_EINVAL if too small).
+ * entry and the count written on return (TCF_EINVAL if too small).  The
+ * loop-split kinds are built on each call and can fail with TCF_ENOMEM.
  */
 int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* len);
 
