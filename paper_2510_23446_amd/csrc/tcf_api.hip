@@ -561,6 +561,7 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
   if (!h || !len) return TCF_EINVAL;
   std::vector<int64_t> tmp;
   const std::vector<int64_t>* src = &tmp;
+  try {
   switch (kind) {
     case TCF_TOPO_COUNTS:
       tmp = {h->g.n_edges(), h->g.n_nodes(), h->topo.n_vertices_H, h->topo.n_plain,
@@ -608,6 +609,10 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
     }
     default:
       return TCF_EINVAL;
+  }
+  } catch (const std::bad_alloc&) {
+    const_cast<tcf_problem*>(h)->err = "out of host memory in the topology query";
+    return TCF_ENOMEM;
   }
   if (!out) { *len = src->size(); return TCF_OK; }
   if (*len < src->size()) {
