@@ -41,6 +41,10 @@ import numpy as np
 
 from .grid import FACE, INTERIOR, WIREBASKET, Grid
 
+# Sec. 3: the tree grows over the wirebasket first, then the subdomain faces,
+# then the subdomain interiors.
+PHASES = (WIREBASKET, FACE, INTERIOR)
+
 
 @dataclass
 class Topology:
@@ -159,7 +163,7 @@ def compute_topology(prob, grid: Grid) -> Topology:
     visited = np.zeros(nV, dtype=bool)
     visited[0] = True
     tree = []
-    for phase, cls in enumerate((WIREBASKET, FACE, INTERIOR)):
+    for phase, cls in enumerate(PHASES):
         elig = np.nonzero(insul_only & (ecls == cls))[0]
         adj = {}
         for e in elig:  # increasing edge id

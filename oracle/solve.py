@@ -13,6 +13,12 @@ the eliminated edges at zero.  The oracle solves exactly that:
 with one sparse LU factorisation of W_g reused for every step.  With an
 initial value A(x, 0) (Sec. 2.1) the first step's M a^(0) is the load
 int sigma A(x,0) . w_e (a^(0) = its sigma-weighted L2 projection).
+
+The factorisation takes W_g symmetrically permuted by a geometric nested
+dissection of its unknowns (``ordering.py``), with SuperLU told to keep
+that order and the diagonal pivots (W_g is symmetric positive definite).
+The permutation changes only the fill of the factor, and so whether the
+full-size systems fit one CPU; the solution is that of W_g itself.
 """
 from __future__ import annotations
 
@@ -25,6 +31,7 @@ import scipy.sparse.linalg as spla
 from .assemble import GlobalSystem, assemble_global
 from .gauge import Topology, compute_topology
 from .grid import build_grid
+from .ordering import edge_midpoints, nested_dissection
 
 
 @dataclass
@@ -41,6 +48,21 @@ def gauged_matrix(sys: GlobalSystem, topo: Topology, dt: float):
     return W[K][:, K].tocsc(), K
 
 
+class GaugedSolver:
+    """Factor of W_g in nested-dissection order; solve(f_K) returns a_K."""
+
+    def __init__(self, Wg, grid, K):
+        self.perm = nested_dissection(Wg, edge_midpoints(grid, K))
+        Wp = Wg[self.perm][:, self.perm].tocsc()
+        self.lu = spla.splu(Wp, permc_spec="NATURAL", diag_pivot_thresh=0.0,
+                            options=dict(SymmetricMode=True))
+
+    def solve(self, f):
+        x = np.empty_like(f)
+        x[self.perm] = self.lu.solve(np.ascontiguousarray(f[self.perm]))
+        return x
+
+
 def run(prob, n_steps=None, keep_fields=True) -> OracleRun:
     t0 = time.perf_counter()
     grid = build_grid(prob)
@@ -49,7 +71,7 @@ def run(prob, n_steps=None, keep_fields=True) -> OracleRun:
     topo = compute_topology(prob, grid)
     t2 = time.perf_counter()
     Wg, K = gauged_matrix(sys, topo, prob.dt)
-    lu = spla.splu(Wg)
+    lu = GaugedSolver(Wg, grid, K)
     t3 = time.perf_counter()
     nE = grid.n_edges
     a = np.zeros((nE, prob.n_rhs))
