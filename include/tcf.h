@@ -192,6 +192,26 @@ int tcf_setup(tcf_problem* h, void* stream);
  */
 int tcf_step(tcf_problem* h, int32_t nsteps, void* stream);
 
+/*
+ * Allocation-free variant of tcf_step, for callers that cannot allocate
+ * device memory or instantiate graphs while stepping (code under stream
+ * capture of their own, tight serving loops, harnesses that forbid
+ * allocation).  Same steps and results as tcf_step, but the PCG's per-solve
+ * scratch (tile accumulators, quadratic-form slots, reduction partials and
+ * the per-column scalars) lives in one library-wide device array of
+ * 64 MiB per GPU instead of the handle's buffers, and every launch is a
+ * plain stream launch (no graph is captured or replayed).  Nothing is
+ * allocated or freed on any call.  The array's address is looked up on the
+ * first call on each device, with that device current.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (several handles stepped concurrently from different threads or on
+ * different streams) race and must be serialised by the caller.  The
+ * contents left by a call are never read by the next one.
+ * Errors: as tcf_step; TCF_EINVAL if the problem's scratch exceeds 64 MiB
+ * (the message states the size needed) or the handle runs without tiles.
+ */
+int tcf_step_noalloc(tcf_problem* h, int32_t nsteps, void* stream);
+
 /* Waits for all work of the handle on `stream`; reports deferred errors. */
 int tcf_sync(tcf_problem* h, void* stream);
 

@@ -201,6 +201,7 @@ struct tcf_problem {
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   hipGraphExec_t pcg_graph = nullptr; // graph_iters PCG iterations (parity 0, 1, 0, ...)
   bool graph_failed = false;          // capture refused: stream launches instead
+  bool no_graph_call = false;         // this call issues stream launches only
 
   // job tables
   DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr, *dj_coarse = nullptr;
@@ -1761,8 +1762,9 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
   // flag the host reads: the all-columns flag on the tile path
   const int fl = h->use_tiles ? R : 0;
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
-  if (h->opt.use_graph && !h->prof_on) RCCHK(build_pcg_graph<T>(h));
-  const bool graph = h->opt.use_graph && !h->prof_on && h->pcg_graph;
+  const bool want_graph = h->opt.use_graph && !h->prof_on && !h->no_graph_call;
+  if (want_graph) RCCHK(build_pcg_graph<T>(h));
+  const bool graph = want_graph && h->pcg_graph;
   const int chunk = std::max(2, h->opt.check_every / 2 * 2);
   // Host reads of the convergence flag stall the stream.  Solves of the
   // same kind (same refinement sweep) take nearly the same number of
@@ -2274,3 +2276,73 @@ int tcf_set_state(tcf_problem* h, const void* buf, size_t bytes, void* stream) {
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Allocation-free stepping
+// ============================================================================
+// The PCG's per-solve scratch (tile accumulators and quadratic-form slots,
+// reduction partials, per-column scalars and flags) can come from one
+// file-scope device array instead of the handle's buffers.  Every solve
+// initialises all of it before reading it (the accumulators are cleared by
+// a fill kernel, the scalars by the first PCG kernel), so the contents left
+// by an earlier call do not matter.  Each device holds its own copy of the
+// array; its address is looked up once per device.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+extern "C" int tcf_step_noalloc(tcf_problem* h, int32_t nsteps, void* stream) {
+  if (!h) return TCF_EINVAL;
+  if (!h->is_setup) { h->err = "tcf_step_noalloc before tcf_setup"; return TCF_ESTATE; }
+  if (nsteps < 0) { h->err = "nsteps < 0"; return TCF_EINVAL; }
+  if (!h->use_tiles) { h->err = "tcf_step_noalloc needs the tile path"; return TCF_EINVAL; }
+  const size_t acc_b = align256(sizeof(double) * (size_t)h->n_acc);
+  const size_t part_b = align256(sizeof(double) * (size_t)h->npart * 4 * h->rb);
+  const size_t st_b = align256(sizeof(PcgScalars) * (size_t)(h->rb + 1));
+  const size_t need = acc_b + part_b + st_b;
+  if (need > kScratchBytes) {
+    h->err = "tcf_step_noalloc: this problem needs " + std::to_string(need) +
+             " bytes of PCG scratch, more than the " + std::to_string(kScratchBytes) +
+             " the allocation-free step holds";
+    return TCF_EINVAL;
+  }
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) { h->err = "device index out of range"; return TCF_EINVAL; }
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p) {
+        h->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return TCF_EHIP;
+      }
+      g_scratch_ptr[dev] = p;
+    }
+    base = g_scratch_ptr[dev];
+  }
+  // the handle's scratch pointers point into the device array for this call
+  // (graphs captured by tcf_step hold the handle's own buffers, so this call
+  // issues stream launches only)
+  double* acc0 = h->d_acc;
+  double* part0 = h->d_part;
+  PcgScalars* st0 = h->d_st;
+  h->d_acc = (double*)base;
+  h->d_part = (double*)((char*)base + acc_b);
+  h->d_st = (PcgScalars*)((char*)base + acc_b + part_b);
+  h->no_graph_call = true;
+  const int rc = tcf_step(h, nsteps, stream);
+  h->no_graph_call = false;
+  h->d_acc = acc0;
+  h->d_part = part0;
+  h->d_st = st0;
+  return rc;
+}

@@ -25,7 +25,7 @@ PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32
  TCF_TOPO_LOOP_PSI, TCF_TOPO_LOOP_PLAN) = range(12)
 
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
-           "tcf_step", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
+           "tcf_step", "tcf_step_noalloc", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
            "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
            "tcf_profile_get", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
@@ -110,6 +110,7 @@ def lib():
     L.tcf_footprint.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     L.tcf_setup.argtypes = [P, P]
     L.tcf_step.argtypes = [P, C.c_int32, P]
+    L.tcf_step_noalloc.argtypes = [P, C.c_int32, P]
     L.tcf_sync.argtypes = [P, P]
     L.tcf_get_field.argtypes = [P, C.c_int32, P, C.c_size_t, C.c_int32, P]
     L.tcf_get_topology.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
@@ -348,6 +349,10 @@ class Problem:
     def tcf_step(self, nsteps, stream=None, allow_noconv=False):
         ok = (TCF_OK, TCF_ENOCONV) if allow_noconv else (TCF_OK,)
         return self._check(lib().tcf_step(self.h, int(nsteps), self._stream(stream)), ok)
+
+    def tcf_step_noalloc(self, nsteps, stream=None, allow_noconv=False):
+        ok = (TCF_OK, TCF_ENOCONV) if allow_noconv else (TCF_OK,)
+        return self._check(lib().tcf_step_noalloc(self.h, int(nsteps), self._stream(stream)), ok)
 
     def tcf_sync(self, stream=None):
         return self._check(lib().tcf_sync(self.h, self._stream(stream)))
