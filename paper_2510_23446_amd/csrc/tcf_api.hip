@@ -176,7 +176,6 @@ struct tcf_problem {
   int* d_cmap = nullptr;    // local primal entry -> position of its coarse unknown in d_acc
   int64_t n_acc = 0;
   int *d_posp_bp = nullptr, *d_posm_bp = nullptr;
-  bool use_tiles = true;
   int rb = 1;  // excitations per PCG (columns of every PCG vector and accumulator)
   bool bp_gaps = false;  // some patch has primal but no dual unknowns
   // warm starts: lambda of the first solve of the last two steps per
@@ -498,8 +497,6 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   {
     const char* tr = std::getenv("TCF_TRACE");
     h->trace = tr && tr[0] == '1';
-    const char* nt = std::getenv("TCF_NO_TILES");
-    h->use_tiles = !(nt && nt[0] == '1');
     const char* fi = std::getenv("TCF_FP64_IR");
     h->fp64_ir = fi && fi[0] == '1';
     const char* gi = std::getenv("TCF_GRAPH_ITERS");
@@ -517,9 +514,8 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   h->nu.assign(desc->nu, desc->nu + np);
   h->src.assign(desc->src_mask, desc->src_mask + np);
   h->n_rhs = desc->n_rhs;
-  // excitations per batched PCG (the tile path only)
-  h->rb = h->use_tiles ? std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 4) : 4)
-                       : 1;
+  // excitations per batched PCG
+  h->rb = std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 4) : 4);
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
   h->jvol = desc->jvol;
@@ -1164,7 +1160,7 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     if (d.ni_pad > 0) ja.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, 0, d.ni_pad, s});
     if (d.nb_pad > 0) jbv.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, d.ni_pad, d.ni_pad + d.nb_pad, s});
   }
-  if (h->opt.precond_scaling == 1 && h->n_lambda > 0 && h->use_tiles) {
+  if (h->opt.precond_scaling == 1 && h->n_lambda > 0) {
     // stiffness scaling: the copy of a dual unknown in patch s is weighted
     // by the other copy's share k_other / (k_s + k_other) of the two local
     // diagonal entries (taken before factorisation)
@@ -1322,11 +1318,11 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   h->npart = (nl + 255) / 256;
   RCCHK(h->alloc(&h->d_part, (size_t)h->npart * 4 * rb));
   RCCHK(h->alloc(&h->d_st, (size_t)rb + 1));  // per column, plus the all-done flag
-  if ((h->opt.pcg_warm == 1 || h->opt.pcg_warm == 2) && h->use_tiles) {
+  if ((h->opt.pcg_warm == 1 || h->opt.pcg_warm == 2)) {
     RCCHK(h->alloc(&h->d_lamh, (size_t)nl * 2 * h->n_rhs));
     h->lamh_n.assign(h->n_rhs, 0);
   }
-  if (h->opt.pcg_warm == 3 && h->use_tiles) {
+  if (h->opt.pcg_warm == 3) {
     const size_t kb = (size_t)tcf_problem::kProjMax * nl * h->n_rhs;
     RCCHK(h->alloc(&h->d_ph, kb));
     RCCHK(h->alloc(&h->d_pfh, kb));
@@ -1545,7 +1541,7 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
       rc = setup_impl<double>(h, st);
       if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
     }
-    if (!rc && h->use_tiles)
+    if (!rc)
       rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
   } catch (const std::bad_alloc&) {
     h->err = "out of host memory in setup";
@@ -1584,32 +1580,6 @@ static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, 
   });
 }
 
-// Fp = F p = sum Bhat [S_bb^-1 x + Phi N S_Pi^-1 sum N^T Phi^T x], x = Bhat^T p;
-// partial sums of p.Fp
-template <class T>
-static void apply_F(tcf_problem* h, const double* p, double* Fp, double* part, const int* done,
-                    hipStream_t st) {
-  if (h->bp_gaps) launch_zero(h->n_bptot, h->d_vc, st);
-  timed(h, TCF_KG_APPLY, st, [&] {
-    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, (const T*)h->d_G,
-                      1, p, h->d_brow, h->d_bsgn, h->dt, h->d_vc, done, st);
-  });
-  coarse_solve(h, h->d_vc, nullptr, h->d_q, done, st);
-  phi_apply<T>(h, h->d_vc, 1.0, h->d_q, h->d_wb, done, st);
-  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, Fp, p, part, done, st);
-}
-
-// z = sum B S_bb B^T r (unscaled Dirichlet preconditioner); partial sums of r.z
-template <class T>
-static void apply_M(tcf_problem* h, const double* r, double* z, double* part, const int* done,
-                    hipStream_t st) {
-  timed(h, TCF_KG_PRECOND, st, [&] {
-    launch_dotcols<T>(h->dj_pre, h->dp_pre, h->nj_pre, h->nt_pre, h->max_nb, (const T*)h->d_S, 1,
-                      r, h->d_brow, h->d_bsgn, 1.0, h->d_tb, done, st);
-  });
-  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_tb, 1.0, z, r, part, done, st);
-}
-
 // Views into the tile path's accumulator block (see pcg_iteration).
 struct TileAcc {
   double *vc, *q, *pq, *tb, *rz;
@@ -1634,7 +1604,7 @@ static TileAcc tile_acc(tcf_problem* h) {
 // One PCG iteration with the given parity (launch sequence only).
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
-  if (h->use_tiles) {
+  {
     // Tile path, 6 launches, rb columns (excitations) at once.  Accumulators
     // (each block rb columns wide): [vc | cv] per column (vc gets S_bb^-1 x
     // and Phi_b N q, cv = sum_s N_s^T Phi_b^T x_s), q the coarse solution,
@@ -1670,19 +1640,7 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
     });
     launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                          a.rz, p_rr, npt, stv, par, tol2, h->d_p, a.vc, a.n_head, st);
-    return;
   }
-  const int nl = h->n_lambda, npt = h->npart;
-  const int* done = &h->d_st->done;
-  double* p_pq = h->d_part;
-  double* p_rr = h->d_part + npt;
-  double* p_rz = h->d_part + 2 * npt;
-  const double tol2 = h->pcg_tol * h->pcg_tol;
-  apply_F<T>(h, h->d_p, h->d_Fp, p_pq, done, st);
-  launch_pcg_update(nl, p_pq, npt, h->d_st, par, h->d_lam, h->d_r, h->d_p, h->d_Fp, p_rr, st);
-  launch_pcg_check(p_rr, npt, h->d_st, tol2, st);
-  apply_M<T>(h, h->d_r, h->d_z, p_rz, done, st);
-  launch_pcg_pupdate(nl, p_rz, npt, h->d_st, par, h->d_p, h->d_z, st);
 }
 
 // Captures graph_iters iterations (parity 0, 1, 0, ...) into a graph replayed per chunk.
@@ -1727,7 +1685,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
   h->last_rel = 0.0;
   if (nl == 0) return TCF_OK;
   const int npt = h->npart;
-  if (h->use_tiles) {
+  {
     const TileAcc a = tile_acc(h);
     double* p_dd = h->d_part + (int64_t)npt * R;
     launch_zero(h->n_acc, h->d_acc, st);
@@ -1752,15 +1710,9 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
                     h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
     launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                        a.rz, p_dd, npt, h->d_st, h->d_p, st);
-  } else {
-    double* p_rz = h->d_part + 2 * npt;
-    double* p_dd = h->d_part + 3 * npt;
-    launch_pcg_init(nl, h->d_d, h->d_lam, h->d_r, p_dd, st);
-    apply_M<T>(h, h->d_r, h->d_z, p_rz, nullptr, st);
-    launch_pcg_init2(nl, h->d_z, h->d_p, p_dd, p_rz, npt, h->d_st, st);
   }
   // flag the host reads: the all-columns flag on the tile path
-  const int fl = h->use_tiles ? R : 0;
+  const int fl = R;
   const int maxit = h->opt.pcg_maxit > 0 ? h->opt.pcg_maxit : std::max(1000, nl);
   const bool want_graph = h->opt.use_graph && !h->prof_on && !h->no_graph_call;
   if (want_graph) RCCHK(build_pcg_graph<T>(h));
@@ -1802,7 +1754,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     if (h->prof_on) h->prof_flush(finished ? max_iters() : INT32_MAX);
   }
   h->cur_it = -1;
-  const int ncol = h->use_tiles ? R : 1;
+  const int ncol = R;
   double rel = 0.0;
   for (int j = 0; j < ncol; ++j) {
     iters[j] = h->h_st[j].iters;
@@ -2301,7 +2253,6 @@ extern "C" int tcf_step_noalloc(tcf_problem* h, int32_t nsteps, void* stream) {
   if (!h) return TCF_EINVAL;
   if (!h->is_setup) { h->err = "tcf_step_noalloc before tcf_setup"; return TCF_ESTATE; }
   if (nsteps < 0) { h->err = "nsteps < 0"; return TCF_EINVAL; }
-  if (!h->use_tiles) { h->err = "tcf_step_noalloc needs the tile path"; return TCF_EINVAL; }
   const size_t acc_b = align256(sizeof(double) * (size_t)h->n_acc);
   const size_t part_b = align256(sizeof(double) * (size_t)h->npart * 4 * h->rb);
   const size_t st_b = align256(sizeof(PcgScalars) * (size_t)(h->rb + 1));

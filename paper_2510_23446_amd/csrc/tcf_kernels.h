@@ -67,16 +67,6 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
                      hipStream_t st);
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
                  const double* dotw, double* partial, const int* done, hipStream_t st);
-void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
-                     hipStream_t st);
-void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, const double* prz,
-                      int npart, PcgScalars* stt, hipStream_t st);
-void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
-                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st);
-void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
-                      hipStream_t st);
-void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
-                        const double* z, hipStream_t st);
 void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
                           const int* ib, const double* srcB, double sb, const double* extra,
                           double* out, const int* done, hipStream_t st);

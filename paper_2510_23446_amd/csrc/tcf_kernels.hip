@@ -1273,70 +1273,6 @@ __device__ inline double sum_partials(const double* p, int n, double* sh) {
   return sh[0];
 }
 
-// lambda = 0, r = d, partial = d.d
-__global__ void __launch_bounds__(256) k_pcg_init(int n, const double* d, double* lam, double* r,
-                                                  double* partial) {
-  __shared__ double sh[4];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double v = 0.0;
-  if (i < n) {
-    lam[i] = 0.0;
-    r[i] = d[i];
-    v = d[i] * d[i];
-  }
-  const double s = block_sum256(v, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-}
-
-// p = z; rz[0] = sum partial_rz; dd = sum partial_dd; done = (dd == 0)
-__global__ void __launch_bounds__(256) k_pcg_init2(int n, const double* z, double* p,
-                                                   const double* part_dd, const double* part_rz,
-                                                   int npart, PcgScalars* st) {
-  __shared__ double sh[1];
-  const double dd = sum_partials(part_dd, npart, sh);
-  __syncthreads();
-  const double rz = sum_partials(part_rz, npart, sh);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->dd = dd;
-    st->rz[0] = rz;
-    st->rz[1] = 0.0;
-    st->rr = dd;
-    st->done = (dd == 0.0) ? 1 : 0;
-    st->iters = 0;
-  }
-}
-
-// alpha = rz[par] / (p.Fp); lambda += alpha p; r -= alpha Fp; partial = r.r
-__global__ void __launch_bounds__(256) k_pcg_update(int n, const double* part_pq, int npart,
-                                                    PcgScalars* st, int par, double* lam,
-                                                    double* r, const double* p, const double* Fp,
-                                                    double* part_rr) {
-  if (st->done) return;
-  __shared__ double sh[1];
-  __shared__ double sh4[4];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  double pi = 0.0, fi = 0.0, ri = 0.0, li = 0.0;
-  if (i < n) {  // independent of the reduction: in flight while it runs
-    pi = p[i];
-    fi = Fp[i];
-    ri = r[i];
-    li = lam[i];
-  }
-  const double pq = sum_partials(part_pq, npart, sh);
-  const double alpha = st->rz[par] / pq;
-  double v = 0.0;
-  if (i < n) {
-    lam[i] = li + alpha * pi;
-    ri -= alpha * fi;
-    r[i] = ri;
-    v = ri * ri;
-  }
-  const double s = block_sum256(v, sh4);
-  if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
-}
-
 // Sum of the TCF_QSLOTS quadratic-form slots (256-thread blocks), the same
 // fixed order in every block.
 __device__ inline double sum_slots(const double* slots, double* sh) {
@@ -1559,31 +1495,6 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, 
   }
 }
 
-
-__global__ void __launch_bounds__(256) k_pcg_check(const double* part_rr, int npart,
-                                                   PcgScalars* st, double tol2) {
-  if (st->done) return;
-  __shared__ double sh[1];
-  const double rr = sum_partials(part_rr, npart, sh);
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    st->iters += 1;
-    if (rr <= tol2 * st->dd) st->done = 1;
-  }
-}
-
-// beta = (r.z)_new / rz[par]; p = z + beta p; rz[par^1] = (r.z)_new
-__global__ void __launch_bounds__(256) k_pcg_pupdate(int n, const double* part_rz, int npart,
-                                                     PcgScalars* st, int par, double* p,
-                                                     const double* z) {
-  if (st->done) return;
-  __shared__ double sh[1];
-  const double rz_new = sum_partials(part_rz, npart, sh);
-  const double beta = rz_new / st->rz[par];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = z[i] + beta * p[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->rz[par ^ 1] = rz_new;
-}
 
 // out[k] = extra[k] + sa * sum srcA[ia[t]] + sb * sum srcB[ib[t]] over owners t of k
 __global__ void __launch_bounds__(256) k_coarse_gather(int n, const int* ptr, const int* ia,
@@ -1828,29 +1739,6 @@ void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const doub
                           double tol2, double* p, double* zero, int64_t nzero, hipStream_t st) {
   TCF_R_DISPATCH(R, k_pcg_pupdate_t, TCF_GRID(max(n, 1), 256), n, pp, pm, tb, tld, wp, wm,
                  rz_slots, part_rr, npart, stt, par, tol2, p, zero, nzero);
-}
-void launch_pcg_init(int n, const double* d, double* lam, double* r, double* partial,
-                     hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_init, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, d, lam, r, partial);
-}
-void launch_pcg_init2(int n, const double* z, double* p, const double* pdd, const double* prz,
-                      int npart, PcgScalars* stt, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_init2, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, z, p, pdd, prz,
-                     npart, stt);
-}
-void launch_pcg_update(int n, const double* ppq, int npart, PcgScalars* stt, int par, double* lam,
-                       double* r, const double* p, const double* Fp, double* prr, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_update, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, ppq, npart, stt,
-                     par, lam, r, p, Fp, prr);
-}
-void launch_pcg_check(const double* prr, int npart, PcgScalars* stt, double tol2,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(256), 0, st, prr, npart, stt, tol2);
-}
-void launch_pcg_pupdate(int n, const double* prz, int npart, PcgScalars* stt, int par, double* p,
-                        const double* z, hipStream_t st) {
-  hipLaunchKernelGGL(k_pcg_pupdate, TCF_GRID(max(n, 1), 256), dim3(256), 0, st, n, prz, npart, stt,
-                     par, p, z);
 }
 void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
                           const int* ib, const double* srcB, double sb, const double* extra,

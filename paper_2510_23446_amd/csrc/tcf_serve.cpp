@@ -70,13 +70,19 @@ struct tcf_server {
 };
 
 void tcf_server::run_request(Request* r) {
+  // The error text is built locally and moved into the request together with
+  // the state change, under the lock that tcf_server_error reads it with.
+  std::string err;
+  std::vector<std::vector<double>> fields;
+  std::vector<double> step_ms;
+  tcf_stats stats{};
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
   const hipError_t se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   int rc = se == hipSuccess ? TCF_OK : TCF_EHIP;
   if (rc != TCF_OK) {
     st = nullptr;
-    r->err = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
+    err = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(se);
   }
   if (rc == TCF_OK) rc = tcf_setup(r->h, st);
   if (rc == TCF_OK) {
@@ -84,35 +90,45 @@ void tcf_server::run_request(Request* r) {
     if (rc == TCF_ENOCONV) rc = TCF_OK;  // flagged in the stats, results kept
   }
   if (rc == TCF_OK) {
-    // an exception must not leave this thread: a failed allocation fails
-    // the request instead
+    // no exception may leave this thread: any failure fails the request
     try {
-      tcf_get_stats(r->h, &r->stats);
-      const int n = r->stats.steps_done;
-      r->step_ms.resize(n);
-      tcf_get_step_log(r->h, n, nullptr, nullptr, r->step_ms.data());
-      int64_t cnt[8];
+      rc = tcf_get_stats(r->h, &stats);
+      const int n = stats.steps_done;
+      if (rc == TCF_OK) {
+        step_ms.resize(n);
+        rc = tcf_get_step_log(r->h, n, nullptr, nullptr, step_ms.data());
+      }
+      int64_t cnt[8] = {0};
       size_t len = 8;
-      tcf_get_topology(r->h, TCF_TOPO_COUNTS, cnt, &len);
+      if (rc == TCF_OK) rc = tcf_get_topology(r->h, TCF_TOPO_COUNTS, cnt, &len);
+      if (rc == TCF_OK && (len < 1 || cnt[0] <= 0)) rc = TCF_EINVAL;
       // number of excitations: fetch until the library refuses the index
-      for (int k = 0;; ++k) {
+      for (int k = 0; rc == TCF_OK; ++k) {
         std::vector<double> f((size_t)cnt[0]);
         if (tcf_get_field(r->h, k, f.data(), f.size(), 0, st) != TCF_OK) break;
-        r->fields.push_back(std::move(f));
+        fields.push_back(std::move(f));
       }
-    } catch (const std::bad_alloc&) {
+      if (rc != TCF_OK) err = std::string("reading the results: ") + tcf_last_error(r->h);
+    } catch (const std::exception& ex) {
       rc = TCF_ENOMEM;
-      r->fields.clear();
-      r->err = "out of host memory while fetching the results";
+      fields.clear();
+      err = std::string("while fetching the results: ") + ex.what();
     }
   }
-  if (rc != TCF_OK && r->err.empty()) {
-    r->err = std::string("status ") + std::to_string(rc) + ": " + tcf_last_error(r->h);
+  if (rc != TCF_OK && err.empty()) {
+    try {
+      err = std::string("status ") + std::to_string(rc) + ": " + tcf_last_error(r->h);
+    } catch (const std::exception&) {
+    }
   }
   tcf_destroy(r->h);  // releases the request's device memory
   r->h = nullptr;
   if (st) (void)hipStreamDestroy(st);
   std::lock_guard<std::mutex> lk(mu);
+  r->stats = stats;
+  r->step_ms = std::move(step_ms);
+  r->fields = std::move(fields);
+  r->err = std::move(err);
   r->status = rc;
   r->state = rc == TCF_OK ? TCF_REQ_DONE : TCF_REQ_FAILED;
   r->t_done = now_ms();

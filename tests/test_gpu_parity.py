@@ -276,15 +276,6 @@ def test_warm_start_fp32_ir_multirhs(warm):
     assert st["nonconverged_steps"] == 0
 
 
-def test_column_dot_path_plain(monkeypatch):
-    """The operators applied from the dense per-patch blocks instead of tiles
-    (TCF_NO_TILES=1, read when the handle is created): same field."""
-    monkeypatch.setenv("TCF_NO_TILES", "1")
-    prob = W.plain_fp64().with_steps(5)
-    worst, st = _run_and_compare(prob, 1e-9)
-    assert st["nonconverged_steps"] == 0
-
-
 # ---- stiffness-scaled Dirichlet preconditioner (same solution, fewer iterations)
 @pytest.mark.parametrize("case", ["uneven", "floating_fp32_ir", "largest_batched", "plain_warm"])
 def test_scaled_preconditioner(case):
