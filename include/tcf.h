@@ -152,6 +152,20 @@ typedef struct tcf_options {
                             /* published), 1 stiffness-scaled: each copy of a */
                             /* dual unknown weighted by the other copy's share*/
                             /* of the two local diagonal entries              */
+  int32_t coarse_mode;      /* coarse solve S_Pi^-1 (Sec. 3: the second Schur  */
+                            /* complement): 0 automatic (the cheaper per apply */
+                            /* of the two below, by streamed bytes and        */
+                            /* launches), 1 one dense FP64 inverse, 2 the     */
+                            /* FP64 Cholesky factor in a nested dissection of */
+                            /* the patch grid (dense blocks per separator,    */
+                            /* explicit inverses of the diagonal blocks, the  */
+                            /* top separator's Schur complement inverted      */
+                            /* densely); both give S_Pi^-1 to rounding        */
+  int32_t setup_group_mb;   /* setup assembles and factors the patches in     */
+                            /* groups whose dense [i|b|p] blocks together      */
+                            /* take at most this many MiB (FP64); a larger     */
+                            /* patch forms a group of its own.  <= 0: 16384.   */
+                            /* Bounds the setup's transient device memory      */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
@@ -254,7 +268,7 @@ enum tcf_topology_kind {
                            /* -sum_n (G^T f_I)(n) c(n, t).  Nodes ascending,     */
                            /* then edge ids.  TCF_EINVAL if a gauge subtree hangs */
                            /* from two face nodes.  Not used by the solver.      */
-  TCF_TOPO_LOOP_PLAN = 11  /* int64[n][5]: per-patch plan of the same split,    */
+  TCF_TOPO_LOOP_PLAN = 11, /* int64[n][5]: per-patch plan of the same split,    */
                            /* patches in order.  The interface-tree edges leave  */
                            /* the primal set: a conductor appends its own to its */
                            /* b block (by edge id), an insulator eliminates them;*/
@@ -267,6 +281,15 @@ enum tcf_topology_kind {
                            /*  entry is -1 and the conductor's are the row's     */
                            /*  TCF_TOPO_LOOP terms; other rows keep the          */
                            /*  multiplier table's signs.  Not used by the solver.*/
+  TCF_TOPO_COARSE = 12     /* The coarse solver's plan: n_Pi values, the index  */
+                           /* of each coarse unknown (TCF_TOPO_PRIMAL order) in  */
+                           /* the factor's elimination order; then per node of   */
+                           /* its elimination tree, in postorder: j0, n_J,       */
+                           /* parent (-1 for a root), height, n_S, then the n_S  */
+                           /* ascending indices of its structure S (ancestor     */
+                           /* unknowns its factor columns reach).  The node owns */
+                           /* indices [j0, j0 + n_J); the last node is inverted  */
+                           /* densely.  One node: the dense inverse of S_Pi.     */
 };
 
 /*
@@ -309,13 +332,24 @@ typedef struct tcf_stats {
                                /* n_i (n_b + n_p)^2 (interior elimination),      */
                                /* n_b^3/3 + n_b^2 n_p + n_b n_p^2 (dual block),  */
                                /* n_b^3/3 + n_b^2 (n_b + n_p) (S_bb^-1, Phi_b),  */
-                               /* n_i^3/3 + n_i^2 (n_b + n_p) (Q^T); coarse      */
-                               /* 5 n_Pi^3/3 (Cholesky, triangular inverse, and  */
+                               /* n_i^3/3 + n_i^2 (n_b + n_p) (Q^T); coarse: per */
+                               /* node of its factor below the top block         */
+                               /* 2 n_J^3/3 + 2 n_J^2 n_S + n_J n_S^2 (partial    */
+                               /* Cholesky, L_JJ^-1, L_JJ^-T L_SJ^T), the top    */
+                               /* block 5 n^3/3 (Cholesky, triangular inverse,   */
                                /* one full triangular solve); triangular         */
                                /* right-hand sides counted by their nonzeros     */
   double cond_est_max;         /* largest per-patch pivot ratio (see            */
   int32_t cond_est_patch;      /* tcf_get_cond_est) and its patch; -1 before    */
                                /* setup                                         */
+  int32_t coarse_nodes;        /* nodes of the coarse factor (1: dense inverse)  */
+  int32_t coarse_launches;     /* tile launches per coarse solve (the kernel    */
+                               /* group TCF_KG_COARSE; with the factor, one     */
+                               /* more small reduction for p.Fp)                */
+  int32_t coarse_root;         /* unknowns of the densely inverted top block    */
+  int32_t setup_chunks;        /* patch groups the setup factorised in turn     */
+  double coarse_bytes;         /* algorithmic bytes of one coarse solve         */
+  size_t device_bytes_peak;    /* high-water mark of the handle's device memory */
 } tcf_stats;
 
 int tcf_get_stats(const tcf_problem* h, tcf_stats* st);
@@ -349,7 +383,9 @@ enum tcf_kernel_group {
   TCF_KG_APPLY = 0,    /* [S_bb^-1 | Phi_b]^T x over all patches (F apply)   */
   TCF_KG_PRECOND = 1,  /* S_bb x over all patches (Dirichlet preconditioner) */
   TCF_KG_PHI = 2,      /* Phi_b N q over all patches                         */
-  TCF_KG_COARSE = 3,   /* S_Pi^-1 c                                          */
+  TCF_KG_COARSE = 3,   /* S_Pi^-1 c in the PCG: tcf_stats.coarse_launches    */
+                       /* launches per solve (1 for the dense inverse); its  */
+                       /* bytes are those of one whole solve                 */
   TCF_KG_CONDENSE = 4, /* per-step condensation of conductor patches         */
   TCF_KG_RECOVER = 5,  /* interior recovery of all patches                   */
   TCF_KG_COUNT = 6

@@ -27,6 +27,7 @@ HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", 
 
 SOURCES = [
     ("tcf_topology.cpp", False),
+    ("tcf_coarse.cpp", False),
     ("tcf_kernels.hip", True),
     ("tcf_api.hip", True),
     ("tcf_serve.cpp", False),

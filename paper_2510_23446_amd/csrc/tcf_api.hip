@@ -25,6 +25,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <numeric>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -47,6 +48,12 @@ thread_local std::string g_create_error;
 std::mutex g_capture_mu;
 
 inline int pad32(int n) { return (n + TCF_NB - 1) / TCF_NB * TCF_NB; }
+// Setup factorises the patches in groups whose dense [i|b|p] blocks
+// together take at most this many bytes (in FP64).
+constexpr int64_t kSetupGroupBytes = (int64_t)16 << 30;
+// Below the top separator the coarse nested dissection stops cutting a
+// region of at most this many primal unknowns.
+constexpr int kCoarseLeafMax = 256;
 inline double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
@@ -136,7 +143,26 @@ struct tcf_problem {
   bool is_setup = false;
   int device = 0;
   std::vector<DevBuf> bufs;
-  size_t dev_bytes = 0;
+  size_t dev_bytes = 0, dev_bytes_peak = 0;
+  // setup in patch groups: patches [chunk_begin[c], chunk_begin[c + 1]) are
+  // assembled and factored together; A_off is relative to the group
+  std::vector<int> chunk_begin;
+  int64_t A_chunk_max = 0, G_chunk_max = 0, S_chunk_max = 0, Q_chunk_max = 0;
+  // coarse factor: nested dissection of the primal unknowns over the patch
+  // grid (one node = the dense inverse); the last node is inverted densely
+  CoarsePlan cplan;
+  std::vector<CoarseNodeDev> cnodes;      // host copy of the node table
+  int c_root = -1;                        // node inverted densely (-1: no coarse)
+  int c_levels = 0;                       // heights of the other nodes: 0 .. c_levels - 1
+  int64_t c_front_elems = 0, c_lop_elems = 0;
+  double c_bytes = 0.0;                   // algorithmic bytes of one coarse solve
+  int c_launches = 0;                     // tile launches per coarse solve
+  std::vector<int> c_fwd_pre, c_bwd_pre;  // per level: job prefix into tj_cfwd / tj_cbwd
+  TileJob *tj_cfwd = nullptr, *tj_cbwd = nullptr;
+  int* d_cT = nullptr;    // index table of the sweeps: identity over [b | y | x], then the
+                          // structure lists as b and as x positions
+  double* d_cw1 = nullptr;  // one-column coarse work vector [b | y | x] (n_Pi each)
+  double* d_cL = nullptr;   // per node below the top: [L_JJ^-1 | -L_JJ^-T L_SJ^T]
 
   DevPatch* dP = nullptr;
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
@@ -203,9 +229,9 @@ struct tcf_problem {
   bool no_graph_call = false;         // this call issues stream launches only
 
   // job tables
-  DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr, *dj_coarse = nullptr;
-  int *dp_app = nullptr, *dp_pre = nullptr, *dp_coarse = nullptr;
-  int nj_app = 0, nt_app = 0, nj_pre = 0, nt_pre = 0, nt_coarse = 0;
+  DotJob *dj_app_g = nullptr, *dj_app_v = nullptr, *dj_pre = nullptr;
+  int *dp_app = nullptr, *dp_pre = nullptr;
+  int nj_app = 0, nt_app = 0, nj_pre = 0, nt_pre = 0;
   AxpyJob *aj_phi = nullptr, *aj_ab = nullptr, *aj_ai = nullptr;
   int *ap_phi = nullptr, *ap_ai = nullptr, *a_boff_bp = nullptr, *a_boff_b = nullptr;
   int *a_boff_ai = nullptr, *a_boff_ab = nullptr;
@@ -286,6 +312,7 @@ struct tcf_problem {
     }
     bufs.push_back({p, bytes});
     dev_bytes += bytes;
+    dev_bytes_peak = std::max(dev_bytes_peak, dev_bytes);
     *out = (T*)p;
     return TCF_OK;
   }
@@ -370,26 +397,150 @@ static void compute_alg_bytes(tcf_problem* h) {
   h->prof_bytes[TCF_KG_APPLY] = app;
   h->prof_bytes[TCF_KG_PRECOND] = pre;
   h->prof_bytes[TCF_KG_PHI] = phi;
-  h->prof_bytes[TCF_KG_COARSE] = nP * (nP + 1) / 2 * 8 + 2 * nP * 8;
+  h->prof_bytes[TCF_KG_COARSE] = nP > 0 ? h->c_bytes : 0.0;  // per coarse solve
   h->prof_bytes[TCF_KG_CONDENSE] = cond;
   h->prof_bytes[TCF_KG_RECOVER] = rec;
 }
 
+// Device bytes the handle needs at its peak: the resident set (operators in
+// their stored precision, their tiles, vectors) plus the largest transient
+// of setup (one patch group's dense blocks with the coarse fronts, the
+// coarse factor's operators, or the coarse operators while they are tiled).
 size_t tcf_problem::footprint(int prec) const {
-  const size_t w = prec == TCF_FP64 ? 8 : 4;
-  size_t b = (size_t)(A_elems + G_elems + S_elems + Q_elems) * w;
-  b += (size_t)nPi_pad * nPi_pad * 8 * 2;
-  b += (size_t)n_rtot * n_rhs * 8 * 6 + (size_t)n_rtot * rb * 8 * 3;
-  b += ((size_t)n_bptot * 16 + (size_t)n_btot * 16 + (size_t)n_lambda * 8 * 8) * rb;
-  b += (size_t)rb * (n_bptot + n_btot + 2 * TCF_QSLOTS) * 8 + (size_t)(tab_elems + ptab_elems) * 8;
-  b += (size_t)n_rtot * 24 + (size_t)n_loctot * 4;
-  if (ainit && !cond_list.empty()) b += (size_t)n_rtot * n_rhs * 8;  // initial load
-  return b;
+  const double w = prec == TCF_FP64 ? 8 : 4;          // stored operators
+  const double wf = prec == TCF_FP32_FULL_IR ? 4 : 8;  // factorisation
+  double ops = (double)(G_elems + S_elems + Q_elems) * w;
+  double tiles = 0.0, ctiles = 0.0;
+  for (const DevPatch& d : hp) {
+    const double Tb = (d.n_b + 63) / 64, Tp = (d.n_p + 63) / 64;
+    tiles += (Tb * (Tb + 1) + Tb * Tp) * 4096.0 * w;
+  }
+  double root_inv = 0.0;
+  for (size_t i = 0; i < cnodes.size(); ++i) {
+    const CoarseNodeDev& c = cnodes[i];
+    const double Tj = (c.nj + 63) / 64, Ts = (c.ns + 63) / 64;
+    if ((int)i == c_root) {
+      ctiles += Tj * (Tj + 1) / 2 * 4096.0 * 8;
+      root_inv = (double)c.nj_pad * c.nj_pad * 8;
+    } else {
+      ctiles += (Tj * (Tj + 1) / 2 + Tj * Ts) * 4096.0 * 8;
+    }
+  }
+  const double npm = std::max(n_primal, 1);
+  double vec = (double)n_rtot * n_rhs * 8 * 6 + (double)n_rtot * rb * 8 * 3;
+  vec += ((double)n_bptot * 16 + (double)n_btot * 16 + (double)n_lambda * 8 * 8) * rb;
+  vec += (double)rb * (n_bptot + 3 * npm + n_btot + 2 * TCF_QSLOTS) * 8 + npm * 8 * (4 + rb);
+  vec += (double)(tab_elems + ptab_elems) * 8 + (double)n_rtot * 24 + (double)n_loctot * 4;
+  vec += (double)g.n_edges() * 8 + (double)n_rtot * 8;  // field, copy maps
+  if (ainit && !cond_list.empty()) vec += (double)n_rtot * n_rhs * 8;  // initial load
+  if (opt.pcg_warm == 1 || opt.pcg_warm == 2) vec += (double)n_lambda * 2 * n_rhs * 8;
+  if (opt.pcg_warm == 3) vec += (double)tcf_problem::kProjMax * 4 * n_lambda * n_rhs * 8;
+  const double fronts = (double)c_front_elems * 8, lops = (double)c_lop_elems * 8;
+  // a group's dense blocks, plus the inverted 32 x 32 diagonal blocks of
+  // its triangular solves
+  double grp = (double)A_chunk_max * wf * (1.0 + 32.0 / 1024) + fronts;
+  if (prec == TCF_FP32_IR) grp += (double)(G_chunk_max + S_chunk_max + Q_chunk_max) * 8;
+  const double coarse = fronts + lops + root_inv;
+  const double pack = tiles + ctiles + lops + root_inv;
+  const double peak = ops + vec + std::max(grp, std::max(coarse, pack));
+  // the tiles stay resident after setup
+  const double resident = ops + vec + tiles + ctiles;
+  return (size_t)(std::max(peak, resident) * 1.02) + ((size_t)8 << 20);
 }
 
 // ============================================================================
 // Plan: sizes, offsets and index tables (host only)
 // ============================================================================
+// Algorithmic bytes and launches of one coarse solve under a plan: the
+// dense top block's lower triangle once (it serves both triangles), every
+// other node's L_JJ^-1 triangle and its structure block twice (forward and
+// backward sweep), FP64.
+static void coarse_cost(const CoarsePlan& cp, double& bytes, int& levels) {
+  bytes = 0.0;
+  levels = 0;
+  const int nn = (int)cp.nodes.size();
+  for (int i = 0; i < nn; ++i) {
+    const CoarseNode& c = cp.nodes[i];
+    const double nj = c.nj, ns = (double)c.S.size();
+    if (i == nn - 1) {
+      bytes += nj * (nj + 1) / 2 * 8 + 2 * nj * 8;
+    } else {
+      bytes += 2 * (nj * (nj + 1) / 2 + nj * ns) * 8 + 4 * (nj + ns) * 8;
+      levels = std::max(levels, c.height + 1);
+    }
+  }
+}
+
+// Chooses between the dense inverse of S_Pi and the nested-dissection
+// factor (coarse_mode 0: whichever a simple model of one solve, streamed
+// bytes at 5 TB/s plus 3 us per launch, finds cheaper; the dense inverse
+// is also ruled out when its setup would need more than 64 GiB), and lays
+// out the fronts, operator blocks and node table.
+static void plan_coarse_solver(tcf_problem* h) {
+  const int n = h->n_primal;
+  h->cnodes.clear();
+  h->c_root = -1;
+  h->c_levels = 0;
+  h->c_front_elems = h->c_lop_elems = 0;
+  h->c_bytes = 0.0;
+  h->c_launches = 0;
+  if (n == 0) return;
+  CoarsePlan dense;
+  dense.nd.resize(n);
+  std::iota(dense.nd.begin(), dense.nd.end(), 0);
+  dense.nodes.resize(1);
+  dense.nodes[0].nj = n;
+  int mode = h->opt.coarse_mode;
+  if (mode != 1) {
+    CoarsePlan nd = plan_coarse(h->plans, h->np, n, 0, kCoarseLeafMax);
+    double bd, bn;
+    int ld, ln;
+    coarse_cost(dense, bd, ld);
+    coarse_cost(nd, bn, ln);
+    const double td = bd / 5e12 + 3e-6;
+    const double tn = bn / 5e12 + 3e-6 * (2 * ln + 2);
+    const double dense_setup = 2.0 * pad32(n) * (double)pad32(n) * 8;
+    if (mode == 2 || (nd.nodes.size() > 1 && (tn < td || dense_setup > 64.0 * (1 << 30)))) {
+      h->cplan = std::move(nd);
+      mode = 2;
+    } else {
+      mode = 1;
+    }
+  }
+  if (mode == 1) h->cplan = std::move(dense);
+  const CoarsePlan& cp = h->cplan;
+  const int nn = (int)cp.nodes.size();
+  h->cnodes.resize(nn);
+  int64_t fo = 0, lo = 0;
+  int s_off = 0;
+  for (int i = 0; i < nn; ++i) {
+    const CoarseNode& c = cp.nodes[i];
+    CoarseNodeDev& d = h->cnodes[i];
+    d.j0 = c.j0;
+    d.nj = c.nj;
+    d.nj_pad = pad32(c.nj);
+    d.ns = (int)c.S.size();
+    d.nf = d.nj_pad + pad32(d.ns);
+    d.s_off = s_off;
+    s_off += d.ns;
+    d.parent = c.parent;
+    d.pad = 0;
+    d.f_off = fo;
+    fo += (int64_t)d.nf * d.nf;
+    d.l_off = lo;
+    if (i < nn - 1) {
+      lo += (int64_t)d.nj_pad * (d.nj + d.ns);
+      h->c_levels = std::max(h->c_levels, c.height + 1);
+    }
+  }
+  h->c_root = nn - 1;
+  h->c_front_elems = fo;
+  h->c_lop_elems = lo;
+  int lev;
+  coarse_cost(cp, h->c_bytes, lev);
+  h->c_launches = nn > 1 ? 2 * h->c_levels + 1 : 1;  // tile launches (timed group)
+}
+
 static void build_plan(tcf_problem* h) {
   const int np = h->np_tot;
   h->hp.assign(np, DevPatch());
@@ -415,7 +566,7 @@ static void build_plan(tcf_problem* h) {
     d.src = pp.src ? 1 : 0;
     d.cond = pp.sigma > 0 ? 1 : 0;
     if (d.cond) h->cond_list.push_back(s);
-    d.A_off = A; A += (int64_t)d.nr_pad * d.nr_pad;
+    d.A_off = A; A += (int64_t)d.nr_pad * d.nr_pad;  // made group-relative below
     d.G_off = G; G += (int64_t)d.nb_pad * (d.n_b + d.n_p);
     d.S_off = S; S += (int64_t)d.nb_pad * d.n_b;
     d.Q_off = Q; Q += (int64_t)d.ni_pad * d.n_r;
@@ -447,6 +598,33 @@ static void build_plan(tcf_problem* h) {
   h->n_primal = (int)h->topo.primal.size();
   h->nPi_pad = pad32(h->n_primal);
   for (int n = 1, o = 0; n <= 16; o += n, ++n) gauss_legendre(n, h->gx + o, h->gw + o);
+  // setup groups: consecutive patches whose dense [i|b|p] blocks together
+  // stay within the budget (a single larger patch forms its own group)
+  const int64_t budget =
+      (h->opt.setup_group_mb > 0 ? ((int64_t)h->opt.setup_group_mb << 20) : kSetupGroupBytes) / 8;
+  h->chunk_begin.assign(1, 0);
+  h->A_chunk_max = h->G_chunk_max = h->S_chunk_max = h->Q_chunk_max = 0;
+  auto close = [&](int c0, int c1) {
+    const DevPatch &f = h->hp[c0], &l = h->hp[c1 - 1];
+    h->A_chunk_max = std::max(h->A_chunk_max, l.A_off + (int64_t)l.nr_pad * l.nr_pad - f.A_off);
+    h->G_chunk_max = std::max(h->G_chunk_max, l.G_off + (int64_t)l.nb_pad * (l.n_b + l.n_p) - f.G_off);
+    h->S_chunk_max = std::max(h->S_chunk_max, l.S_off + (int64_t)l.nb_pad * l.n_b - f.S_off);
+    h->Q_chunk_max = std::max(h->Q_chunk_max, l.Q_off + (int64_t)l.ni_pad * l.n_r - f.Q_off);
+    const int64_t base = f.A_off;
+    for (int t = c0; t < c1; ++t) h->hp[t].A_off -= base;
+    h->chunk_begin.push_back(c1);
+  };
+  int c0 = 0;
+  for (int s = 0; s < np; ++s) {
+    const int64_t end = h->hp[s].A_off + (int64_t)h->hp[s].nr_pad * h->hp[s].nr_pad;
+    if (s > c0 && end - h->hp[c0].A_off > budget) {
+      close(c0, s);
+      c0 = s;
+    }
+  }
+  if (np > 0) close(c0, np);
+  h->A_elems = h->A_chunk_max;
+  plan_coarse_solver(h);
 }
 
 // ============================================================================
@@ -465,6 +643,8 @@ void tcf_default_options(tcf_options* o) {
   o->rhs_batch = 0;
   o->pcg_warm = 0;
   o->precond_scaling = 0;
+  o->coarse_mode = 0;
+  o->setup_group_mb = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -490,6 +670,10 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   if (h->opt.pcg_warm < 0 || h->opt.pcg_warm > 3) { g_create_error = "pcg_warm not in 0..3"; return TCF_EINVAL; }
   if (h->opt.precond_scaling < 0 || h->opt.precond_scaling > 1) {
     g_create_error = "precond_scaling not in 0..1";
+    return TCF_EINVAL;
+  }
+  if (h->opt.coarse_mode < 0 || h->opt.coarse_mode > 2) {
+    g_create_error = "coarse_mode not in 0..2";
     return TCF_EINVAL;
   }
   h->precision = h->opt.precision;
@@ -582,6 +766,13 @@ int tcf_get_topology(const tcf_problem* h, int32_t kind, int64_t* out, size_t* l
         }
       }
       break;
+    case TCF_TOPO_COARSE:
+      tmp.assign(h->cplan.nd.begin(), h->cplan.nd.end());
+      for (const CoarseNode& c : h->cplan.nodes) {
+        tmp.insert(tmp.end(), {c.j0, c.nj, c.parent, c.height, (int64_t)c.S.size()});
+        tmp.insert(tmp.end(), c.S.begin(), c.S.end());
+      }
+      break;
     case TCF_TOPO_LOOP:
     case TCF_TOPO_LOOP_PLAN:
     case TCF_TOPO_LOOP_PSI: {
@@ -652,9 +843,21 @@ int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
       f += nb * nb * nb / 3 + nb * nb * (nb + np_);             // S_bb^-1 and Phi_b
       f += ni * ni * ni / 3 + ni * ni * nbp;                    // Q^T
     }
-    const double nP = h->n_primal;
-    st->setup_flops = f + 5 * nP * nP * nP / 3;  // coarse Cholesky and inverse
+    // coarse: per node below the top its partial Cholesky, L_JJ^-1 and
+    // L_JJ^-T L_SJ^T; the top block's Cholesky and inverse
+    for (size_t i = 0; i < h->cnodes.size(); ++i) {
+      const double nj = h->cnodes[i].nj, ns = h->cnodes[i].ns;
+      if ((int)i == h->c_root) f += 5 * nj * nj * nj / 3;
+      else f += 2 * nj * nj * nj / 3 + 2 * nj * nj * ns + nj * ns * ns;
+    }
+    st->setup_flops = f;
   }
+  st->coarse_nodes = (int32_t)h->cnodes.size();
+  st->coarse_launches = h->c_launches;
+  st->coarse_root = h->c_root >= 0 ? h->cnodes[h->c_root].nj : 0;
+  st->setup_chunks = (int32_t)h->chunk_begin.size() - 1;
+  st->coarse_bytes = h->c_bytes;
+  st->device_bytes_peak = h->dev_bytes_peak;
   st->cond_est_max = 0.0;
   st->cond_est_patch = -1;
   for (size_t s = 0; s < h->cond_est.size(); ++s)
@@ -892,8 +1095,9 @@ static int build_index_tables(tcf_problem* h) {
         posm_r[pp.b_row[k]] = d.r_off + pp.n_i + k;
       }
     }
+    // coarse unknowns are numbered in the order of the coarse factor
     for (int j = 0; j < pp.n_p; ++j) {
-      prank.push_back(pp.p_rank[j]);
+      prank.push_back(h->cplan.nd[pp.p_rank[j]]);
       p2r.push_back(d.r_off + pp.n_i + pp.n_b + j);
     }
     for (int j = 0; j < pp.n_r(); ++j) isint.push_back(j < pp.n_i ? 1 : 0);
@@ -904,7 +1108,7 @@ static int build_index_tables(tcf_problem* h) {
     const PatchPlan& pp = h->plans[s];
     const DevPatch& d = h->hp[s];
     for (int j = 0; j < pp.n_p; ++j)
-      own[pp.p_rank[j]].push_back({d.bp_off + pp.n_b + j, d.r_off + pp.n_i + pp.n_b + j});
+      own[h->cplan.nd[pp.p_rank[j]]].push_back({d.bp_off + pp.n_b + j, d.r_off + pp.n_i + pp.n_b + j});
   }
   std::vector<int> cptr(1, 0), cbp, cr;
   for (int k = 0; k < h->n_primal; ++k) {
@@ -1003,17 +1207,6 @@ static int build_index_tables(tcf_problem* h) {
   }
   RCCHK(h->upload(&h->aj_ab, ab));
   RCCHK(h->upload(&h->a_boff_ab, boff_ab));
-  // coarse GEMV
-  std::vector<DotJob> cj;
-  std::vector<int> cc;
-  if (h->n_primal > 0) {
-    cj.push_back(DotJob{0, h->nPi_pad, h->n_primal, h->n_primal, 0, 0});
-    cc.push_back((h->n_primal + kDotCpb - 1) / kDotCpb);
-  }
-  auto p_c = prefix_of(cc);
-  h->nt_coarse = p_c.back();
-  RCCHK(h->upload(&h->dj_coarse, cj));
-  RCCHK(h->upload(&h->dp_coarse, p_c));
   // conductor patch lists
   std::vector<int> ccnt, rcnt;
   for (int s : h->cond_list) {
@@ -1029,11 +1222,91 @@ static int build_index_tables(tcf_problem* h) {
   return TCF_OK;
 }
 
-template <class T>
+// Coarse factor from its assembled fronts: per height of the elimination
+// tree (leaves first) a batched partial Cholesky of the fronts' own columns,
+// then each front's update matrix is added into its parent's front; last
+// the top block is factored completely.  Then the explicit operators:
+// L_JJ^-1 and -L_JJ^-T L_SJ^T per node, and the dense inverse of the top
+// block's Schur complement.
+static int coarse_factor(tcf_problem* h, double* F, const CoarseNodeDev* dnodes, const int* d_cpos,
+                         hipStream_t st) {
+  const int nn = (int)h->cnodes.size();
+  const int root = h->c_root;
+  for (int lv = 0; lv <= h->c_levels; ++lv) {
+    std::vector<FactorJob> jobs;
+    std::vector<int> done;
+    for (int i = 0; i < nn; ++i) {
+      const bool here = lv < h->c_levels ? (i != root && h->cplan.nodes[i].height == lv) : i == root;
+      if (!here) continue;
+      const CoarseNodeDev& c = h->cnodes[i];
+      jobs.push_back(FactorJob{c.f_off, c.nf, c.nf, 0, c.nj_pad, -1});
+      done.push_back(i);
+    }
+    RCCHK(run_factor_phase<double>(h, jobs, F, st));
+    for (int i : done) {
+      const CoarseNodeDev& c = h->cnodes[i];
+      if (c.parent >= 0) launch_extend_add(dnodes, i, c.ns, d_cpos, F, st);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  // L_JJ^-1 | -L_JJ^-T L_SJ^T of every node below the top block
+  if (nn > 1) {
+    double* L;
+    RCCHK(h->alloc(&L, (size_t)h->c_lop_elems));
+    h->d_cL = L;
+    std::vector<int> ids, cnt;
+    std::vector<TrsmJob> tf, tb;
+    for (int i = 0; i < nn; ++i) {
+      if (i == root) continue;
+      const CoarseNodeDev& c = h->cnodes[i];
+      ids.push_back(i);
+      cnt.push_back(c.nj + c.ns);
+      tf.push_back(TrsmJob{c.f_off, c.nf, 0, c.nj_pad, c.l_off, c.nj_pad, c.nj, c.nj, 0});
+      if (c.ns > 0)
+        tb.push_back(TrsmJob{c.f_off, c.nf, 0, c.nj_pad, c.l_off + (int64_t)c.nj * c.nj_pad,
+                             c.nj_pad, c.ns, 0, 0});
+    }
+    auto pre = prefix_of(cnt);
+    int *dids, *dpre;
+    RCCHK(h->upload(&dids, ids));
+    RCCHK(h->upload(&dpre, pre));
+    launch_front_rhs(dnodes, dids, dpre, (int)ids.size(), pre.back(), F, L, st);
+    HIPCHK(hipGetLastError());
+    RCCHK(run_trsm<double>(h, 1, tf, F, L, st));
+    RCCHK(run_trsm<double>(h, 0, tb, F, L, st));
+    h->release(dids);
+    h->release(dpre);
+  }
+  // dense inverse of the top block: L X = I, then L^T Y = X
+  {
+    const CoarseNodeDev& c = h->cnodes[root];
+    const int ld = c.nj_pad;
+    double* Sinv;
+    RCCHK(h->alloc(&Sinv, (size_t)ld * ld));
+    HIPCHK(hipMemsetAsync(Sinv, 0, sizeof(double) * ld * ld, st));
+    launch_identity_pad(Sinv, ld, 0, c.nj, st);
+    std::vector<TrsmJob> t1{TrsmJob{c.f_off, c.nf, 0, ld, 0, ld, c.nj, c.nj, 0}};
+    std::vector<TrsmJob> t0{TrsmJob{c.f_off, c.nf, 0, ld, 0, ld, c.nj, 0, 0}};
+    RCCHK(run_trsm<double>(h, 1, t1, F, Sinv, st));
+    RCCHK(run_trsm<double>(h, 0, t0, F, Sinv, st));
+    h->d_SPinv = Sinv;
+  }
+  return TCF_OK;
+}
+
+// Setup.  T: precision of the factorisation; TO: precision in which the
+// explicit operators (G, S, Q^T) are kept.  The patches are factored in
+// groups (chunk_begin); within a group the kernels see a copy of the patch
+// table whose A, G, S and Q^T offsets are relative to the group, so that
+// only one group's dense blocks (and, when TO is narrower than T, its
+// operators in T) exist at a time; the group's operators are then written
+// to their final storage in TO.
+template <class T, class TO>
 static int setup_impl(tcf_problem* h, hipStream_t st) {
   const int np = h->np_tot;
   const int nrhs = h->n_rhs;
   const int64_t ldv = h->n_rtot;
+  constexpr bool kSame = std::is_same<T, TO>::value;
   RCCHK(h->upload(&h->dP, h->hp));
   RCCHK(build_index_tables(h));
   std::vector<double> gx(h->gx, h->gx + 136), gw(h->gw, h->gw + 136);
@@ -1044,17 +1317,6 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   RCCHK(h->alloc(&h->d_fail, 1));
   HIPCHK(hipMemsetAsync(h->d_fail, 0, sizeof(int), st));
   launch_tables(h->dP, np, h->d_gx, h->d_gw, h->d_tabs, h->d_ptab, st);
-
-  // dense patch matrices
-  T* A = nullptr;
-  RCCHK(h->alloc(&A, h->A_elems));
-  std::vector<int> colcnt(np);
-  for (int s = 0; s < np; ++s) colcnt[s] = h->hp[s].nr_pad;
-  auto colpre = prefix_of(colcnt);
-  int* d_colpre;
-  RCCHK(h->upload(&d_colpre, colpre));
-  launch_assemble<T>(h->dP, d_colpre, np, colpre.back(), h->d_rloc, h->d_tabs, h->dt, A, st);
-  HIPCHK(hipGetLastError());
 
   // source loads: the curl form (phi) and/or the volume form (jvol) on
   // source patches, and the initial load int sigma A(x,0) . w (ainit) on
@@ -1153,20 +1415,184 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     if (stage) h->release(stage);
   }
 
-  // factor the interior columns, keep S_bb, factor the dual columns
-  std::vector<FactorJob> ja, jbv;
-  for (int s = 0; s < np; ++s) {
-    const DevPatch& d = h->hp[s];
-    if (d.ni_pad > 0) ja.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, 0, d.ni_pad, s});
-    if (d.nb_pad > 0) jbv.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, d.ni_pad, d.ni_pad + d.nb_pad, s});
+  h->d_jr = jr;
+  // final operator storage, the condensed source, and per-patch diagnostics
+  TO *G, *S, *Q;
+  RCCHK(h->alloc(&S, h->S_elems));
+  RCCHK(h->alloc(&G, h->G_elems));
+  RCCHK(h->alloc(&Q, h->Q_elems));
+  h->d_G = G;
+  h->d_S = S;
+  h->d_Q = Q;
+  RCCHK(h->alloc(&h->d_yggs, (size_t)ldv * nrhs));
+  HIPCHK(hipMemsetAsync(h->d_yggs, 0, sizeof(double) * ldv * nrhs, st));
+  const bool scaled = h->opt.precond_scaling == 1 && h->n_lambda > 0;
+  double* kd = nullptr;
+  if (scaled) RCCHK(h->alloc(&kd, (size_t)std::max<int64_t>(h->n_btot, 1)));
+  double* dr;
+  RCCHK(h->alloc(&dr, (size_t)2 * np));
+  // coarse fronts, assembled patch by patch while the groups are factored
+  double* F = nullptr;
+  CoarseNodeDev* dnodes = nullptr;
+  int *d_nodeof = nullptr, *d_slist = nullptr, *d_cpos = nullptr;
+  if (h->c_root >= 0) {
+    const int nn = (int)h->cnodes.size();
+    std::vector<int> nodeof(h->n_primal), slist, cpos;
+    for (int i = 0; i < nn; ++i) {
+      const CoarseNode& c = h->cplan.nodes[i];
+      for (int g = c.j0; g < c.j0 + c.nj; ++g) nodeof[g] = i;
+      slist.insert(slist.end(), c.S.begin(), c.S.end());
+    }
+    // parent front position of every structure entry
+    for (int i = 0; i < nn; ++i) {
+      const CoarseNode& c = h->cplan.nodes[i];
+      for (int g : c.S) {
+        if (c.parent < 0) { cpos.push_back(0); continue; }
+        const CoarseNode& p = h->cplan.nodes[c.parent];
+        const CoarseNodeDev& pd = h->cnodes[c.parent];
+        if (g >= p.j0 && g < p.j0 + p.nj) {
+          cpos.push_back(g - p.j0);
+        } else {
+          const auto it = std::lower_bound(p.S.begin(), p.S.end(), g);
+          if (it == p.S.end() || *it != g) {
+            h->err = "coarse plan: a structure entry is missing from its parent";
+            return TCF_EINVAL;
+          }
+          cpos.push_back(pd.nj_pad + (int)(it - p.S.begin()));
+        }
+      }
+    }
+    slist.push_back(0);
+    cpos.push_back(0);
+    RCCHK(h->upload(&dnodes, h->cnodes));
+    RCCHK(h->upload(&d_nodeof, nodeof));
+    RCCHK(h->upload(&d_slist, slist));
+    RCCHK(h->upload(&d_cpos, cpos));
+    RCCHK(h->alloc(&F, (size_t)h->c_front_elems));
+    HIPCHK(hipMemsetAsync(F, 0, sizeof(double) * h->c_front_elems, st));
+    launch_front_pad(dnodes, nn, F, st);
   }
-  if (h->opt.precond_scaling == 1 && h->n_lambda > 0) {
+  T* A = nullptr;
+  RCCHK(h->alloc(&A, h->A_chunk_max));
+  T *Gt = nullptr, *St = nullptr, *Qt = nullptr;
+  if (!kSame) {
+    RCCHK(h->alloc(&Gt, (size_t)std::max<int64_t>(h->G_chunk_max, 1)));
+    RCCHK(h->alloc(&St, (size_t)std::max<int64_t>(h->S_chunk_max, 1)));
+    RCCHK(h->alloc(&Qt, (size_t)std::max<int64_t>(h->Q_chunk_max, 1)));
+  }
+  DevPatch* dPc;
+  RCCHK(h->alloc(&dPc, (size_t)np));
+  const int nchunks = (int)h->chunk_begin.size() - 1;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int s0 = h->chunk_begin[ch], s1 = h->chunk_begin[ch + 1], nc = s1 - s0;
+    const int64_t gb = h->hp[s0].G_off, sb = h->hp[s0].S_off, qb = h->hp[s0].Q_off;
+    std::vector<DevPatch> tab(h->hp.begin() + s0, h->hp.begin() + s1);
+    for (DevPatch& d : tab) {
+      d.G_off -= gb;
+      d.S_off -= sb;
+      d.Q_off -= qb;
+    }
+    HIPCHK(hipMemcpyAsync(dPc, tab.data(), sizeof(DevPatch) * nc, hipMemcpyHostToDevice, st));
+    T* Gw = kSame ? (T*)(G + gb) : Gt;
+    T* Sw = kSame ? (T*)(S + sb) : St;
+    T* Qw = kSame ? (T*)(Q + qb) : Qt;
+    std::vector<int> colcnt(nc), sbc(nc), cg(nc), cq(nc), cc(nc), plist(nc);
+    for (int t = 0; t < nc; ++t) {
+      const DevPatch& d = tab[t];
+      colcnt[t] = d.nr_pad;
+      sbc[t] = d.n_b;
+      cg[t] = d.n_b > 0 ? d.n_b + d.n_p : 0;
+      cq[t] = d.n_i > 0 ? d.n_r : 0;
+      cc[t] = (d.n_r + 15) / 16;
+      plist[t] = t;
+    }
+    auto colpre = prefix_of(colcnt), sbpre = prefix_of(sbc), pg = prefix_of(cg),
+         pq = prefix_of(cq), cpre = prefix_of(cc);
+    int *d_colpre, *d_sbpre, *dpg, *dpq, *dcp, *dpl;
+    RCCHK(h->upload(&d_colpre, colpre));
+    RCCHK(h->upload(&d_sbpre, sbpre));
+    RCCHK(h->upload(&dpg, pg));
+    RCCHK(h->upload(&dpq, pq));
+    RCCHK(h->upload(&dcp, cpre));
+    RCCHK(h->upload(&dpl, plist));
+    launch_assemble<T>(dPc, d_colpre, nc, colpre.back(), h->d_rloc, h->d_tabs, h->dt, A, st);
+    HIPCHK(hipGetLastError());
+    // stiffness scaling takes the dual diagonal before factorisation
+    if (kd) launch_bdiag<T>(dPc, nc, A, kd, st);
+    // factor the interior columns, keep S_bb, factor the dual columns
+    std::vector<FactorJob> ja, jbv;
+    for (int t = 0; t < nc; ++t) {
+      const DevPatch& d = tab[t];
+      if (d.ni_pad > 0) ja.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, 0, d.ni_pad, s0 + t});
+      if (d.nb_pad > 0)
+        jbv.push_back(FactorJob{d.A_off, d.nr_pad, d.nr_pad, d.ni_pad, d.ni_pad + d.nb_pad, s0 + t});
+    }
+    RCCHK(run_factor_phase<T>(h, ja, A, st));
+    launch_copy_sbb<T>(dPc, d_sbpre, nc, sbpre.back(), A, Sw, st);
+    RCCHK(run_factor_phase<T>(h, jbv, A, st));
+    // per-patch pivot range of the factored [i|b] block
+    launch_diag_range<T>(dPc, nc, A, dr + 2 * s0, st);
+    // this group's primal Schur complements into the coarse fronts, patch
+    // by patch in id order
+    if (F)
+      for (int t = 0; t < nc; ++t)
+        launch_front_add<T>(dPc, t, tab[t].n_p, h->d_prank, A, dnodes, d_nodeof, d_slist, F, st);
+    // G = [S_bb^-1 | Phi_b] and Q^T
+    launch_fill_G<T>(dPc, dpg, nc, pg.back(), A, Gw, st);
+    launch_fill_Q<T>(dPc, dpq, nc, pq.back(), A, Qw, st);
+    HIPCHK(hipGetLastError());
+    std::vector<TrsmJob> gf, gbk, qbk;
+    for (int t = 0; t < nc; ++t) {
+      const DevPatch& d = tab[t];
+      if (d.n_b > 0) {
+        gf.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b,
+                             d.n_b, 0});
+        gbk.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad,
+                              d.n_b + d.n_p, 0, 0});
+      }
+      if (d.n_i > 0)
+        qbk.push_back(TrsmJob{d.A_off, d.nr_pad, 0, d.ni_pad, d.Q_off, d.ni_pad, d.n_r, d.n_i, 0});
+    }
+    RCCHK(run_trsm<T>(h, 1, gf, A, Gw, st));
+    RCCHK(run_trsm<T>(h, 0, gbk, A, Gw, st));
+    RCCHK(run_trsm<T>(h, 0, qbk, A, Qw, st));
+    // the source condenses once (time separable), with the factorisation's
+    // own Q^T: yggs = cond(jhat)
+    launch_condense<T>(dPc, dpl, dcp, nc, cpre.back(), nrhs, h->max_ni, Qw, h->d_jr, h->d_yggs,
+                       ldv, st);
+    HIPCHK(hipGetLastError());
+    if (!kSame) {
+      const DevPatch& l = h->hp[s1 - 1];
+      launch_to_float((l.G_off + (int64_t)l.nb_pad * (l.n_b + l.n_p)) - gb, (const double*)Gt,
+                      (float*)(G + gb), st);
+      launch_to_float((l.S_off + (int64_t)l.nb_pad * l.n_b) - sb, (const double*)St,
+                      (float*)(S + sb), st);
+      launch_to_float((l.Q_off + (int64_t)l.ni_pad * l.n_r) - qb, (const double*)Qt,
+                      (float*)(Q + qb), st);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int* b : {d_colpre, d_sbpre, dpg, dpq, dcp, dpl}) h->release(b);
+  }
+  h->release(A);
+  h->release(dPc);
+  if (Gt) h->release(Gt);
+  if (St) h->release(St);
+  if (Qt) h->release(Qt);
+  {
+    int fail = 0;
+    HIPCHK(hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (fail) {
+      h->fail_patch = fail - 2;
+      h->err = "non-positive pivot in patch " + std::to_string(fail - 2);
+      return TCF_ENOTSPD;
+    }
+  }
+  if (kd) {
     // stiffness scaling: the copy of a dual unknown in patch s is weighted
     // by the other copy's share k_other / (k_s + k_other) of the two local
     // diagonal entries (taken before factorisation)
-    double* kd;
-    RCCHK(h->alloc(&kd, (size_t)h->n_btot));
-    launch_bdiag<T>(h->dP, np, A, kd, st);
     std::vector<double> k(h->n_btot);
     HIPCHK(hipMemcpyAsync(k.data(), kd, sizeof(double) * h->n_btot, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1188,30 +1614,7 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     RCCHK(h->upload(&h->d_zwp, wp));
     RCCHK(h->upload(&h->d_zwm, wm));
   }
-  RCCHK(run_factor_phase<T>(h, ja, A, st));
-  T *G, *S, *Q;
-  RCCHK(h->alloc(&S, h->S_elems));
-  RCCHK(h->alloc(&G, h->G_elems));
-  RCCHK(h->alloc(&Q, h->Q_elems));
-  h->d_G = G;
-  h->d_S = S;
-  h->d_Q = Q;
   {
-    std::vector<int> cnt(np);
-    for (int s = 0; s < np; ++s) cnt[s] = h->hp[s].n_b;
-    auto pre = prefix_of(cnt);
-    int* dpre;
-    RCCHK(h->upload(&dpre, pre));
-    launch_copy_sbb<T>(h->dP, dpre, np, pre.back(), A, S, st);
-    HIPCHK(hipStreamSynchronize(st));
-    h->release(dpre);
-  }
-  RCCHK(run_factor_phase<T>(h, jbv, A, st));
-  {
-    // per-patch pivot-ratio condition estimate of the factored [i|b] block
-    double* dr;
-    RCCHK(h->alloc(&dr, (size_t)2 * np));
-    launch_diag_range<T>(h->dP, np, A, dr, st);
     std::vector<double> r(2 * (size_t)np);
     HIPCHK(hipMemcpyAsync(r.data(), dr, sizeof(double) * 2 * np, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1221,83 +1624,31 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
       if (h->hp[s].n_i + h->hp[s].n_b > 0 && r[2 * s] > 0)
         h->cond_est[s] = (r[2 * s + 1] / r[2 * s]) * (r[2 * s + 1] / r[2 * s]);
   }
-
-  // coarse matrix S_Pi = sum N^T S_pp N, its Cholesky factor and inverse (FP64)
-  if (h->n_primal > 0) {
-    const int ldc = h->nPi_pad;
-    double *SPi, *SPinv;
-    RCCHK(h->alloc(&SPi, (size_t)ldc * ldc));
-    RCCHK(h->alloc(&SPinv, (size_t)ldc * ldc));
-    HIPCHK(hipMemsetAsync(SPi, 0, sizeof(double) * ldc * ldc, st));
-    for (int s = 0; s < np; ++s)
-      launch_coarse_add<T>(h->dP, s, h->hp[s].n_p, h->d_prank, A, SPi, ldc, st);
-    launch_identity_pad(SPi, ldc, h->n_primal, ldc, st);
-    std::vector<FactorJob> jc{FactorJob{0, ldc, ldc, 0, ldc, -1}};
-    RCCHK(run_factor_phase<double>(h, jc, SPi, st));
-    // SPinv = I, then solve L X = I and L^T Y = X
-    HIPCHK(hipMemsetAsync(SPinv, 0, sizeof(double) * ldc * ldc, st));
-    launch_identity_pad(SPinv, ldc, 0, h->n_primal, st);
-    std::vector<TrsmJob> tj{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal, h->n_primal, 0}};
-    std::vector<TrsmJob> tjb{TrsmJob{0, ldc, 0, ldc, 0, ldc, h->n_primal, 0, 0}};
-    RCCHK(run_trsm<double>(h, 1, tj, SPi, SPinv, st));
-    RCCHK(run_trsm<double>(h, 0, tjb, SPi, SPinv, st));
-    h->release(SPi);
-    h->d_SPinv = SPinv;
-  }
-
-  // G = [S_bb^-1 | Phi_b] and Q^T
-  {
-    std::vector<int> cg(np), cq(np);
-    for (int s = 0; s < np; ++s) {
-      cg[s] = h->hp[s].n_b > 0 ? h->hp[s].n_b + h->hp[s].n_p : 0;
-      cq[s] = h->hp[s].n_i > 0 ? h->hp[s].n_r : 0;
-    }
-    auto pg = prefix_of(cg), pq = prefix_of(cq);
-    int *dpg, *dpq;
-    RCCHK(h->upload(&dpg, pg));
-    RCCHK(h->upload(&dpq, pq));
-    launch_fill_G<T>(h->dP, dpg, np, pg.back(), A, G, st);
-    launch_fill_Q<T>(h->dP, dpq, np, pq.back(), A, Q, st);
+  // the coarse factor and its explicit operators (FP64)
+  if (F) {
+    RCCHK(coarse_factor(h, F, dnodes, d_cpos, st));
+    int fail = 0;
+    HIPCHK(hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    h->release(dpg);
-    h->release(dpq);
-    std::vector<TrsmJob> gf, gb, qb;
-    for (int s = 0; s < np; ++s) {
-      const DevPatch& d = h->hp[s];
-      if (d.n_b > 0) {
-        gf.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad, d.n_b,
-                             d.n_b, 0});
-        gb.push_back(TrsmJob{d.A_off, d.nr_pad, d.ni_pad, d.nb_pad, d.G_off, d.nb_pad,
-                             d.n_b + d.n_p, 0, 0});
-      }
-      if (d.n_i > 0)
-        qb.push_back(TrsmJob{d.A_off, d.nr_pad, 0, d.ni_pad, d.Q_off, d.ni_pad, d.n_r, d.n_i, 0});
+    h->release(F);
+    h->release(dnodes);
+    h->release(d_nodeof);
+    h->release(d_slist);
+    h->release(d_cpos);
+    if (fail) {
+      h->fail_patch = -1;
+      h->err = "non-positive pivot in the coarse matrix";
+      return TCF_ENOTSPD;
     }
-    RCCHK(run_trsm<T>(h, 1, gf, A, G, st));
-    RCCHK(run_trsm<T>(h, 0, gb, A, G, st));
-    RCCHK(run_trsm<T>(h, 0, qb, A, Q, st));
-  }
-  int fail = 0;
-  HIPCHK(hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  h->release(A);
-  h->release(d_colpre);
-  if (fail) {
-    h->fail_patch = fail - 2;
-    h->err = "non-positive pivot in " +
-             (fail - 2 >= 0 ? "patch " + std::to_string(fail - 2) : std::string("coarse matrix"));
-    return TCF_ENOTSPD;
   }
 
   // state and work vectors
   RCCHK(h->alloc(&h->d_a, (size_t)ldv * nrhs));
   RCCHK(h->alloc(&h->d_fM, (size_t)ldv * nrhs));
   RCCHK(h->alloc(&h->d_ygg, (size_t)ldv * nrhs));
-  RCCHK(h->alloc(&h->d_yggs, (size_t)ldv * nrhs));
   RCCHK(h->alloc(&h->d_zr, (size_t)ldv));
   HIPCHK(hipMemsetAsync(h->d_a, 0, sizeof(double) * ldv * nrhs, st));
   HIPCHK(hipMemsetAsync(h->d_fM, 0, sizeof(double) * ldv * nrhs, st));
-  HIPCHK(hipMemsetAsync(h->d_yggs, 0, sizeof(double) * ldv * nrhs, st));
   const int rb = h->rb;
   RCCHK(h->alloc(&h->d_uc, (size_t)h->n_bptot * rb));
   RCCHK(h->alloc(&h->d_vc, h->n_bptot));
@@ -1341,16 +1692,13 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   }
   HIPCHK(hipMemsetAsync(h->d_lam, 0, sizeof(double) * nl, st));
 
-  // source condensation (time separable): yggs = cond(jhat)
+  // every patch, for the condensation of a general right-hand side
   std::vector<int> all(np), acnt(np);
   for (int s = 0; s < np; ++s) { all[s] = s; acnt[s] = (h->hp[s].n_r + 15) / 16; }
   auto apre = prefix_of(acnt);
   int *d_all, *d_apre;
   RCCHK(h->upload(&d_all, all));
   RCCHK(h->upload(&d_apre, apre));
-  launch_condense<T>(h->dP, d_all, d_apre, np, apre.back(), nrhs, h->max_ni, Q, jr, h->d_yggs, ldv, st);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
   h->d_all = d_all;
   h->d_all_cprefix = d_apre;
   h->nt_all_c = apre.back();
@@ -1361,7 +1709,6 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     h->nt_all_r = rp.back();
     RCCHK(h->upload(&h->d_all_rprefix, rp));
   }
-  h->d_jr = jr;
   // refinement work vectors and the kept-unknown -> local-copies map
   RCCHK(h->alloc(&h->d_floc, (size_t)ldv * rb));
   RCCHK(h->alloc(&h->d_res, (size_t)ldv * rb));
@@ -1414,9 +1761,10 @@ static void add_tile(std::vector<PackJob>& pk, std::vector<TileJob>& tj, int64_t
   off += 64 * (int64_t)jb.nc;
 }
 
-// Phi tiles are read by two job lists (the apply's T part and the coarse
-// correction's N part): one packing, two jobs with the same orientation.
-static void add_phi_tile(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
+// A tile read by two job lists (Phi: the apply's T part and the coarse
+// correction's N part; coarse factor blocks: the forward and the backward
+// sweep): one packing, two jobs with the same orientation.
+static void add_tile_twice(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
                          std::vector<TileJob>& jphi, int64_t& off, int64_t src_off, int ld,
                          int row0, int col0, TileJob japp, TileJob jphi_) {
   const int64_t off0 = off;
@@ -1458,38 +1806,107 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
     for (int K = 0; K < Tp; ++K)
       for (int I = 0; I < Tb; ++I) {
         const int nr = std::min(64, d.n_b - 64 * I), nc = std::min(64, d.n_p - 64 * K);
-        add_phi_tile(pa, ja, jphi, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K,
+        add_tile_twice(pa, ja, jphi, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K,
                      TileJob{0, d.b_off + 64 * I, 0, 0, d.p_off + 64 * K, nr, nc, 2 | 4, 0},
                      TileJob{0, 0, d.p_off + 64 * K, d.bp_off + 64 * I, 0, nr, nc, 1, 0});
       }
   }
-  const int nP = h->n_primal;
-  const int Tc = (nP + 63) / 64;
-  for (int J = 0; J < Tc; ++J)
-    for (int I = J; I < Tc; ++I) {
-      const int nr = std::min(64, nP - 64 * I), nc = std::min(64, nP - 64 * J);
-      add_tile(pc, jc, oc, 0, h->nPi_pad, 64 * I, 64 * J,
-               TileJob{0, 64 * I, 64 * J, 64 * I, 64 * J, nr, nc, 1 | (I != J ? 2 | 32 : 0) | 16,
-                       0});
+  // coarse solve: lower tiles of the top block's dense inverse (both
+  // triangles, one launch, inputs and outputs by offset), and per node below
+  // it the tiles of L_JJ^-1 and -L_JJ^-T L_SJ^T, each read by a forward job
+  // (y_J = L_JJ^-1 b_J, b_S -= L_SJ y_J) and a backward job (x_J = L_JJ^-T
+  // y_J - L_JJ^-T L_SJ^T x_S), grouped by the node's height.  Work block per
+  // column: b (the right-hand side, updated in place), y, x (the solution),
+  // n_Pi entries each; the index table maps tile rows and columns to them.
+  const int nP = h->n_primal, npm = std::max(nP, 1);
+  std::vector<PackJob> pl;
+  std::vector<std::vector<TileJob>> fw(h->c_levels), bw(h->c_levels);
+  std::vector<int> ctab(3 * (size_t)npm);
+  std::iota(ctab.begin(), ctab.end(), 0);
+  if (h->c_root >= 0) {
+    const CoarseNodeDev& r = h->cnodes[h->c_root];
+    const int Tc = (r.nj + 63) / 64;
+    for (int J = 0; J < Tc; ++J)
+      for (int I = J; I < Tc; ++I) {
+        const int nr = std::min(64, r.nj - 64 * I), nc = std::min(64, r.nj - 64 * J);
+        add_tile(pc, jc, oc, 0, r.nj_pad, 64 * I, 64 * J,
+                 TileJob{0, r.j0 + 64 * I, r.j0 + 64 * J, r.j0 + 64 * I, r.j0 + 64 * J, nr, nc,
+                         1 | (I != J ? 2 | 32 : 0) | 16, 0});
+      }
+    int stot = 0;
+    for (const CoarseNodeDev& c : h->cnodes) stot += c.ns;
+    const int sb0 = 3 * npm, sx0 = 3 * npm + stot;
+    ctab.resize((size_t)sx0 + stot);
+    for (size_t i = 0; i < h->cnodes.size(); ++i) {
+      const CoarseNodeDev& c = h->cnodes[i];
+      const std::vector<int>& S = h->cplan.nodes[i].S;
+      for (int a = 0; a < c.ns; ++a) {
+        ctab[sb0 + c.s_off + a] = S[a];
+        ctab[sx0 + c.s_off + a] = 2 * npm + S[a];
+      }
+      if ((int)i == h->c_root) continue;
+      const int lv = h->cplan.nodes[i].height;
+      const int Tj = (c.nj + 63) / 64, Ts = (c.ns + 63) / 64;
+      for (int K = 0; K < Tj; ++K)
+        for (int I = K; I < Tj; ++I) {
+          const int nr = std::min(64, c.nj - 64 * I), nc = std::min(64, c.nj - 64 * K);
+          add_tile_twice(pl, fw[lv], bw[lv], oc, c.l_off, c.nj_pad, 64 * I, 64 * K,
+                         TileJob{0, 0, c.j0 + 64 * K, npm + c.j0 + 64 * I, 0, nr, nc, 1 | 8, 0},
+                         TileJob{0, npm + c.j0 + 64 * I, 0, 0, 2 * npm + c.j0 + 64 * K, nr, nc,
+                                 2 | 4, 0});
+        }
+      for (int K = 0; K < Tj; ++K)
+        for (int a = 0; a < Ts; ++a) {
+          const int nr = std::min(64, c.nj - 64 * K), nc = std::min(64, c.ns - 64 * a);
+          add_tile_twice(pl, fw[lv], bw[lv], oc, c.l_off + (int64_t)c.nj * c.nj_pad, c.nj_pad,
+                         64 * K, 64 * a,
+                         TileJob{0, c.j0 + 64 * K, 0, 0, sb0 + c.s_off + 64 * a, nr, nc, 2 | 4, 0},
+                         TileJob{0, 0, sx0 + c.s_off + 64 * a, 2 * npm + c.j0 + 64 * K, 0, nr, nc,
+                                 1 | 8, 0});
+        }
     }
+  }
   T *tA, *tB;
   RCCHK(h->alloc(&tA, (size_t)oa));
   RCCHK(h->alloc(&tB, (size_t)ob));
   RCCHK(h->alloc(&h->d_tC, (size_t)oc));
   h->d_tA = tA;
   h->d_tB = tB;
-  PackJob *dpa, *dpb, *dpc;
+  PackJob *dpa, *dpb, *dpc, *dpl;
   RCCHK(h->upload(&dpa, pa));
   RCCHK(h->upload(&dpb, pb));
   RCCHK(h->upload(&dpc, pc));
+  RCCHK(h->upload(&dpl, pl));
   launch_pack_tiles<T, T>(dpa, (int)pa.size(), (const T*)h->d_G, tA, st);
   launch_pack_tiles<T, T>(dpb, (int)pb.size(), (const T*)h->d_S, tB, st);
-  if (nP > 0) launch_pack_tiles<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_tC, st);
+  if (!pc.empty()) launch_pack_tiles<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_tC, st);
+  if (!pl.empty()) launch_pack_tiles<double, double>(dpl, (int)pl.size(), h->d_cL, h->d_tC, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   h->release(dpa);
   h->release(dpb);
   h->release(dpc);
+  h->release(dpl);
+  // the coarse operators live on as tiles only
+  if (h->d_SPinv) h->release(h->d_SPinv);
+  if (h->d_cL) h->release(h->d_cL);
+  h->d_SPinv = nullptr;
+  h->d_cL = nullptr;
+  {
+    std::vector<TileJob> f, b;
+    h->c_fwd_pre.assign(1, 0);
+    h->c_bwd_pre.assign(1, 0);
+    for (int lv = 0; lv < h->c_levels; ++lv) {
+      f.insert(f.end(), fw[lv].begin(), fw[lv].end());
+      b.insert(b.end(), bw[lv].begin(), bw[lv].end());
+      h->c_fwd_pre.push_back((int)f.size());
+      h->c_bwd_pre.push_back((int)b.size());
+    }
+    RCCHK(h->upload(&h->tj_cfwd, f));
+    RCCHK(h->upload(&h->tj_cbwd, b));
+    RCCHK(h->upload(&h->d_cT, ctab));
+    RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm));
+  }
   RCCHK(h->upload(&h->tj_apply, ja));
   RCCHK(h->upload(&h->tj_phi, jphi));
   RCCHK(h->upload(&h->tj_pre, jpre));
@@ -1502,28 +1919,12 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
   std::vector<int> cmap((size_t)std::max<int64_t>(h->n_ptot, 1), 0);
   for (int s = 0; s < h->np_tot; ++s)
     for (int j = 0; j < h->hp[s].n_p; ++j)
-      cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->plans[s].p_rank[j];
+      cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->cplan.nd[h->plans[s].p_rank[j]];
   RCCHK(h->upload(&h->d_cmap, cmap));
-  // per column j of rb: [vc | cv] (stride n_bptot + n_Pi), then q, p.Fp
-  // slots, tb, r.z slots, each block rb columns wide
-  h->n_acc = (int64_t)h->rb * (h->n_bptot + 2 * std::max(nP, 1) + 2 * TCF_QSLOTS + h->n_btot);
+  // per column j of rb: [vc | cv = b | y | x = q] (stride n_bptot + 3 n_Pi),
+  // then p.Fp slots, tb, r.z slots, each block rb columns wide
+  h->n_acc = (int64_t)h->rb * (h->n_bptot + 3 * npm + 2 * TCF_QSLOTS + h->n_btot);
   RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
-  return TCF_OK;
-}
-
-// FP32_IR: the Schur operators were built in FP64; keep FP32 copies only.
-static int demote_operators(tcf_problem* h, hipStream_t st) {
-  void** bufs[3] = {&h->d_G, &h->d_S, &h->d_Q};
-  const int64_t counts[3] = {h->G_elems, h->S_elems, h->Q_elems};
-  for (int i = 0; i < 3; ++i) {
-    float* f = nullptr;
-    RCCHK(h->alloc(&f, (size_t)counts[i]));
-    launch_to_float(counts[i], (const double*)*bufs[i], f, st);
-    HIPCHK(hipStreamSynchronize(st));
-    h->release(*bufs[i]);
-    *bufs[i] = f;
-  }
-  HIPCHK(hipGetLastError());
   return TCF_OK;
 }
 
@@ -1535,12 +1936,12 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   const double t0 = now_ms();
   int rc;
   try {
-    if (h->precision == TCF_FP32_FULL_IR) {
-      rc = setup_impl<float>(h, st);
-    } else {
-      rc = setup_impl<double>(h, st);
-      if (!rc && h->precision == TCF_FP32_IR) rc = demote_operators(h, st);
-    }
+    if (h->precision == TCF_FP32_FULL_IR)
+      rc = setup_impl<float, float>(h, st);
+    else if (h->precision == TCF_FP32_IR)
+      rc = setup_impl<double, float>(h, st);
+    else
+      rc = setup_impl<double, double>(h, st);
     if (!rc)
       rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
   } catch (const std::bad_alloc&) {
@@ -1568,35 +1969,79 @@ static void phi_apply(tcf_problem* h, const double* base_bp, double alpha, const
     });
 }
 
+// x = S_Pi^-1 b on R columns of a coarse work block [b | y | x] (n_Pi
+// entries each, column stride ld, all cleared beforehand): forward sweep
+// over the heights of the factor's elimination tree (b is updated in place,
+// y_J = L_JJ^-1 b_J), the top block's dense inverse, backward sweep.  With
+// slots, adds b^T S_Pi^-1 b per column: |y|^2 over the lower nodes plus the
+// top block's quadratic form.
+static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* slots,
+                          const int* done, hipStream_t st) {
+  if (h->c_root < 0) return;
+  const int npm = std::max(h->n_primal, 1);
+  // kernel timing covers the PCG's coarse solves (the ones with slots) only
+  auto timed = [&](int g, hipStream_t s, auto&& f) {
+    if (slots) ::timed(h, g, s, f);
+    else f();
+  };
+  for (int lv = 0; lv < h->c_levels; ++lv) {
+    const int j0 = h->c_fwd_pre[lv], nj = h->c_fwd_pre[lv + 1] - j0;
+    timed(TCF_KG_COARSE, st, [&] {
+      launch_tiles<double>(1, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+                           base, ld, h->d_cT, nullptr, done, st);
+    });
+  }
+  const CoarseNodeDev& r = h->cnodes[h->c_root];
+  if (slots && r.j0 > 0) launch_sumsq_slots(R, r.j0, base + npm, ld, slots, done, st);
+  timed(TCF_KG_COARSE, st, [&] {
+    launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, base, ld, nullptr, nullptr,
+                         1.0, base + 2 * npm, ld, nullptr, slots, done, st);
+  });
+  for (int lv = h->c_levels - 1; lv >= 0; --lv) {
+    const int j0 = h->c_bwd_pre[lv], nj = h->c_bwd_pre[lv + 1] - j0;
+    timed(TCF_KG_COARSE, st, [&] {
+      launch_tiles<double>(1, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+                           base, ld, h->d_cT, nullptr, done, st);
+    });
+  }
+}
+
+// out = S_Pi^-1 in (one column, through the one-column work block)
+static void coarse_solve1(tcf_problem* h, const double* in, double* out, hipStream_t st) {
+  if (h->n_primal == 0) return;
+  const int npm = std::max(h->n_primal, 1);
+  launch_zero(3 * (int64_t)npm, h->d_cw1, st);
+  launch_axpby(h->n_primal, 1.0, in, 0.0, h->d_cw1, st);
+  coarse_sweeps(h, 1, h->d_cw1, 3 * npm, nullptr, nullptr, st);
+  launch_axpby(h->n_primal, 1.0, h->d_cw1 + 2 * npm, 0.0, out, st);
+}
+
 // out = S_Pi^-1 (extra + sum_s N_s^T c_s), c_s = the primal part of a bp-vector
 static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, double* out,
-                         const int* done, hipStream_t st) {
+                         hipStream_t st) {
   if (h->n_primal == 0) return;
   launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, bp, 1.0,
-                       extra, h->d_cv, done, st);
-  timed(h, TCF_KG_COARSE, st, [&] {
-    launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv,
-                           0, h->d_cv, nullptr, nullptr, 1.0, out, done, st);
-  });
+                       extra, h->d_cv, nullptr, st);
+  coarse_solve1(h, h->d_cv, out, st);
 }
 
 // Views into the tile path's accumulator block (see pcg_iteration).
 struct TileAcc {
   double *vc, *q, *pq, *tb, *rz;
-  int lf, npm;              // column strides of [vc | cv] and of q
+  int lf, npm;              // column stride of [vc | b | y | x], and n_Pi (at least 1)
   int64_t n_head, n_tail;   // [vc .. p.Fp slots] and [tb .. r.z slots] lengths
 };
 static TileAcc tile_acc(tcf_problem* h) {
   TileAcc a;
   const int R = h->rb;
   a.npm = std::max(h->n_primal, 1);
-  a.lf = (int)h->n_bptot + a.npm;
+  a.lf = (int)h->n_bptot + 3 * a.npm;
   a.vc = h->d_acc;
-  a.q = a.vc + (int64_t)a.lf * R;
-  a.pq = a.q + (int64_t)a.npm * R;
+  a.q = a.vc + h->n_bptot + 2 * a.npm;
+  a.pq = a.vc + (int64_t)a.lf * R;
   a.tb = a.pq + (int64_t)TCF_QSLOTS * R;
   a.rz = a.tb + h->n_btot * R;
-  a.n_head = (int64_t)(a.lf + a.npm + TCF_QSLOTS) * R;
+  a.n_head = (int64_t)(a.lf + TCF_QSLOTS) * R;
   a.n_tail = (h->n_btot + TCF_QSLOTS) * R;
   return a;
 }
@@ -1623,12 +2068,9 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
                       h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, alldone, st);
     });
     if (h->n_primal > 0) {
-      timed(h, TCF_KG_COARSE, st, [&] {
-        launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, a.vc + h->n_bptot, a.lf,
-                             nullptr, nullptr, 1.0, a.q, a.npm, nullptr, a.pq, alldone, st);
-      });
+      coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, alldone, st);
       timed(h, TCF_KG_PHI, st, [&] {
-        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.npm, h->d_prank,
+        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
                         nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, alldone, st);
       });
     }
@@ -1694,9 +2136,8 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
       launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_lam, nl, h->d_brow,
                       h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, nullptr, st);
       if (h->n_primal > 0) {
-        launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, a.vc + h->n_bptot, a.lf,
-                             nullptr, nullptr, 1.0, a.q, a.npm, nullptr, a.pq, nullptr, st);
-        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.npm, h->d_prank,
+        coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, nullptr, st);
+        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
                         nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, nullptr, st);
       }
       launch_pcg_init_w(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, h->d_d, h->d_r,
@@ -1813,8 +2254,7 @@ static void solve_pre(tcf_problem* h, int k, int l, const double* rhs, const dou
   if (h->n_primal > 0) {
     launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, uc, -1.0,
                          nullptr, hv, nullptr, st);
-    launch_dotcols<double>(h->dj_coarse, h->dp_coarse, 1, h->nt_coarse, h->n_primal, h->d_SPinv,
-                           0, hv, nullptr, nullptr, 1.0, h->d_q0, nullptr, st);
+    coarse_solve1(h, hv, h->d_q0, st);
   }
   phi_apply<T>(h, uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
   launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, dv, nullptr, nullptr, nullptr,
@@ -1838,7 +2278,7 @@ static void solve_post(tcf_problem* h, int k, int j, double* x_out, hipStream_t 
   if (h->n_lambda > 0)
     launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, lam,
                       h->d_brow, h->d_bsgn, h->dt, h->d_vc, nullptr, st);
-  coarse_solve(h, h->d_vc, hv, h->d_q, nullptr, st);
+  coarse_solve(h, h->d_vc, hv, h->d_q, st);
   launch_sub_gather((int)h->n_btot, h->d_b2bp, uc, h->d_b2bp, h->d_vc, h->d_tb, st);
   launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, x_out, nullptr, st);
   if (h->n_primal > 0) {

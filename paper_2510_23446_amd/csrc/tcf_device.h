@@ -101,6 +101,17 @@ struct PackJob {
   int trans;
 };
 
+// One node of the coarse factor's elimination tree as the kernels see it.
+// Its front is dense, column-major, order nf = nj_pad + ns_pad: the node's
+// own nj unknowns (padded to TCF_NB with an identity diagonal), then its
+// structure S (ns ND indices, ascending, at slist + s_off).
+struct CoarseNodeDev {
+  int64_t f_off;     // front offset in the front buffer
+  int64_t l_off;     // [L_JJ^-1 | -L_JJ^-T L_SJ^T] offset in the operator buffer
+  int j0, nj, nj_pad, ns, nf, s_off;
+  int parent, pad;
+};
+
 struct PcgScalars {
   double dd;         // ||d||^2
   double rz[2];      // r.z of the current / next iteration (parity)

@@ -1,6 +1,7 @@
 // Internal host-side structures of libtcf (not part of the C-ABI).
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -98,5 +99,23 @@ std::vector<int64_t> loop_psi(const Grid& g, const Topology& t,
 // kind 0 b block, kind 1 p block with coarse ranks, kind 2 entries of B_s.
 std::vector<int64_t> loop_plan(const Grid& g, const Topology& t,
                                const std::vector<PatchPlan>& plans);
+
+// Nested-dissection plan of the coarse Cholesky factor (tcf_coarse.cpp).
+struct CoarseNode {
+  int j0 = 0, nj = 0;       // its own unknowns: ND indices [j0, j0 + nj)
+  int parent = -1;          // -1: a root of the elimination forest
+  int height = 0;           // 0 for a leaf, else 1 + the highest child
+  std::vector<int> S;       // structure: ascending ND indices of the ancestor
+                            // unknowns its factor columns reach
+};
+struct CoarsePlan {
+  std::vector<int> nd;             // coarse unknown (primal rank) -> ND index
+  std::vector<CoarseNode> nodes;   // postorder (children before parents)
+};
+// Regions of more than dense_max (top) / leaf_max (below) unknowns are cut
+// at the middle patch plane of their longest extent, down to single patch
+// rows.  dense_max >= n_primal gives one node: the dense inverse.
+CoarsePlan plan_coarse(const std::vector<PatchPlan>& plans, const int P[3], int n_primal,
+                       int dense_max, int leaf_max);
 
 }  // namespace tcf

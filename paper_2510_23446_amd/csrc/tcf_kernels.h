@@ -150,5 +150,17 @@ void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const doub
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
 void launch_copy_probe(int64_t n32, const void* a, void* b, hipStream_t st);
+// Coarse factor fronts (nested dissection over the patch grid).
+template <class T>
+void launch_front_add(const DevPatch* P, int s, int n_p, const int* p_nd, const T* A,
+                      const CoarseNodeDev* nodes, const int* node_of, const int* slist, double* F,
+                      hipStream_t st);
+void launch_extend_add(const CoarseNodeDev* nodes, int c, int ns, const int* cpos, double* F,
+                       hipStream_t st);
+void launch_front_pad(const CoarseNodeDev* nodes, int nn, double* F, hipStream_t st);
+void launch_front_rhs(const CoarseNodeDev* nodes, const int* jobs, const int* prefix, int njobs,
+                      int total, const double* F, double* L, hipStream_t st);
+void launch_sumsq_slots(int R, int n, const double* y, int ld, double* slots, const int* done,
+                        hipStream_t st);
 void launch_zero(int64_t n, double* a, hipStream_t st);
 }  // namespace tcf

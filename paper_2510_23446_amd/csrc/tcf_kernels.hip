@@ -2104,7 +2104,9 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   __shared__ double Tp[R][64][TPW + 1];
   __shared__ double Np[R][4][64];
   const int t = threadIdx.x;
-  const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = jb.flags & 16;
+  // the quadratic form is accumulated only when the caller passes its slots
+  // (the one-column coarse solves of the per-step setup pass none)
+  const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = (jb.flags & 16) && qslot != nullptr;
   const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
   // inputs, step 1: gather indices (threads 0..63 the row side, 64..127 the
   // column side).  Issued before the matrix loads: memory counters retire in
@@ -2352,6 +2354,136 @@ void launch_zero(int64_t n, double* a, hipStream_t st) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_zero, TCF_GRID(n, 256), dim3(256), 0, st, n, a);
 }
+// ===========================================================================
+// Coarse factor: fronts of the nested-dissection elimination tree
+// ===========================================================================
+// Position of ND index g in the front of node c (g in its own range or in
+// its structure; the structure is searched by bisection).
+__device__ inline int front_pos(const CoarseNodeDev& c, const int* slist, int g) {
+  if (g < c.j0 + c.nj) return g - c.j0;
+  int lo = 0, hi = c.ns - 1;
+  const int* S = slist + c.s_off;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (S[mid] < g) lo = mid + 1; else hi = mid;
+  }
+  return c.nj_pad + lo;
+}
+
+// Original entries of S_Pi = sum_s N_s^T S_pp N_s from one patch (launched
+// per patch in sequence, so every entry sums its patches in one order):
+// entry (gi, gj), gi >= gj, goes to the front of the node owning gj (the one
+// eliminated first), lower triangle.
+template <class T>
+__global__ void k_front_add(const DevPatch* P, int s, const int* p_nd, const T* A,
+                            const CoarseNodeDev* nodes, const int* node_of, const int* slist,
+                            double* F) {
+  const DevPatch& pp = P[s];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= pp.n_p * pp.n_p) return;
+  const int i = idx % pp.n_p, j = idx / pp.n_p;
+  const int gi = p_nd[pp.p_off + i], gj = p_nd[pp.p_off + j];
+  if (gi < gj) return;
+  const int R = pp.ni_pad + pp.nb_pad + max(i, j), C = pp.ni_pad + pp.nb_pad + min(i, j);
+  const double v = (double)A[pp.A_off + R + (int64_t)C * pp.nr_pad];
+  const CoarseNodeDev c = nodes[node_of[gj]];
+  const int row = front_pos(c, slist, gi), col = gj - c.j0;
+  if (row < c.nf && col < c.nj) F[c.f_off + row + (int64_t)col * c.nf] += v;
+}
+
+// Extend-add of child c's update matrix (the Schur complement left in the
+// trailing S x S block of its factored front) into its parent's front.
+// cpos[s_off + a] is the parent front position of the child's structure
+// entry a; both are ascending, so the lower triangle maps to the lower
+// triangle.  One launch per child, in postorder.
+__global__ void k_extend_add(const CoarseNodeDev* nodes, int c, const int* cpos, double* F) {
+  const CoarseNodeDev ch = nodes[c];
+  const CoarseNodeDev pa = nodes[ch.parent];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ch.ns * ch.ns) return;
+  const int a = (int)(idx % ch.ns), b = (int)(idx / ch.ns);
+  if (a < b) return;
+  const double v = F[ch.f_off + (ch.nj_pad + a) + (int64_t)(ch.nj_pad + b) * ch.nf];
+  const int* cp = cpos + ch.s_off;
+  F[pa.f_off + cp[a] + (int64_t)cp[b] * pa.nf] += v;
+}
+
+// Identity diagonal on the padding of each node's own block.
+__global__ void k_front_pad(const CoarseNodeDev* nodes, double* F) {
+  const CoarseNodeDev c = nodes[blockIdx.x];
+  for (int r = c.nj + threadIdx.x; r < c.nj_pad; r += blockDim.x)
+    F[c.f_off + r + (int64_t)r * c.nf] = 1.0;
+}
+
+// Right-hand sides of the explicit operators of non-root nodes, ld nj_pad:
+// columns [0, nj) the identity (for L_JJ^-1), columns nj .. nj + ns the
+// negated transpose of L_SJ (for -L_JJ^-T L_SJ^T).  One block per column.
+__global__ void k_front_rhs(const CoarseNodeDev* nodes, const int* jobs, const int* prefix,
+                            int njobs, const double* F, double* L) {
+  const int j = find_job(prefix, njobs, blockIdx.x);
+  const CoarseNodeDev c = nodes[jobs[j]];
+  const int col = blockIdx.x - prefix[j];
+  double* o = L + c.l_off + (int64_t)col * c.nj_pad;
+  for (int r = threadIdx.x; r < c.nj_pad; r += blockDim.x) {
+    double v;
+    if (col < c.nj) v = (r == col) ? 1.0 : 0.0;
+    else v = -F[c.f_off + (c.nj_pad + (col - c.nj)) + (int64_t)r * c.nf];
+    o[r] = v;
+  }
+}
+
+// slots[j * TCF_QSLOTS + k] += sum of squares of part of column j of y
+// (y[j * ld + i], i < n).  Blocks of 256 threads, grid (chunks, R).
+__global__ void __launch_bounds__(256) k_sumsq_slots(int n, const double* y, int ld,
+                                                     double* slots, const int* done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  const int j = blockIdx.y;
+  double v = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double t = y[(int64_t)j * ld + i];
+    v += t * t;
+  }
+  v = block_sum256(v, sh);
+  if (threadIdx.x == 0) atomicAdd(slots + j * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)), v);
+}
+
+template <class T>
+void launch_front_add(const DevPatch* P, int s, int n_p, const int* p_nd, const T* A,
+                      const CoarseNodeDev* nodes, const int* node_of, const int* slist, double* F,
+                      hipStream_t st) {
+  if (n_p == 0) return;
+  hipLaunchKernelGGL(k_front_add<T>, TCF_GRID(n_p * n_p, 256), dim3(256), 0, st, P, s, p_nd, A,
+                     nodes, node_of, slist, F);
+}
+template void launch_front_add<double>(const DevPatch*, int, int, const int*, const double*,
+                                       const CoarseNodeDev*, const int*, const int*, double*,
+                                       hipStream_t);
+template void launch_front_add<float>(const DevPatch*, int, int, const int*, const float*,
+                                      const CoarseNodeDev*, const int*, const int*, double*,
+                                      hipStream_t);
+void launch_extend_add(const CoarseNodeDev* nodes, int c, int ns, const int* cpos, double* F,
+                       hipStream_t st) {
+  if (ns == 0) return;
+  hipLaunchKernelGGL(k_extend_add, TCF_GRID((int64_t)ns * ns, 256), dim3(256), 0, st, nodes, c,
+                     cpos, F);
+}
+void launch_front_pad(const CoarseNodeDev* nodes, int nn, double* F, hipStream_t st) {
+  if (nn == 0) return;
+  hipLaunchKernelGGL(k_front_pad, dim3(nn), dim3(64), 0, st, nodes, F);
+}
+void launch_front_rhs(const CoarseNodeDev* nodes, const int* jobs, const int* prefix, int njobs,
+                      int total, const double* F, double* L, hipStream_t st) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_front_rhs, dim3(total), dim3(256), 0, st, nodes, jobs, prefix, njobs, F, L);
+}
+void launch_sumsq_slots(int R, int n, const double* y, int ld, double* slots, const int* done,
+                        hipStream_t st) {
+  if (n == 0) return;
+  const int chunks = std::min(256, (n + 2047) / 2048);
+  hipLaunchKernelGGL(k_sumsq_slots, dim3(chunks, R), dim3(256), 0, st, n, y, ld, slots, done);
+}
+
 template void launch_pack_tiles<double, double>(const PackJob*, int, const double*, double*,
                                                 hipStream_t);
 template void launch_pack_tiles<float, float>(const PackJob*, int, const float*, float*,

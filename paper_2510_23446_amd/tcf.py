@@ -22,7 +22,7 @@ TCF_FP64, TCF_FP32_IR, TCF_FP32_FULL_IR = 0, 1, 2
 PRECISIONS = {"fp64": TCF_FP64, "fp32_ir": TCF_FP32_IR, "fp32_full_ir": TCF_FP32_FULL_IR}
 (TCF_TOPO_COUNTS, TCF_TOPO_DIRICHLET, TCF_TOPO_TREE_I, TCF_TOPO_TREE_GAMMA, TCF_TOPO_PRIMAL,
  TCF_TOPO_DUAL, TCF_TOPO_INTERIOR, TCF_TOPO_MULT, TCF_TOPO_N, TCF_TOPO_LOOP,
- TCF_TOPO_LOOP_PSI, TCF_TOPO_LOOP_PLAN) = range(12)
+ TCF_TOPO_LOOP_PSI, TCF_TOPO_LOOP_PLAN, TCF_TOPO_COARSE) = range(13)
 
 EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint", "tcf_setup",
            "tcf_step", "tcf_step_noalloc", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
@@ -66,7 +66,8 @@ class tcf_options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("pcg_rtol", C.c_double), ("pcg_maxit", C.c_int32),
                 ("ir_rtol", C.c_double), ("ir_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32),
-                ("precond_scaling", C.c_int32)]
+                ("precond_scaling", C.c_int32), ("coarse_mode", C.c_int32),
+                ("setup_group_mb", C.c_int32)]
 
 
 class tcf_stats(C.Structure):
@@ -79,7 +80,10 @@ class tcf_stats(C.Structure):
                 ("last_ir_residual", C.c_double), ("setup_ms", C.c_double),
                 ("step_ms_total", C.c_double), ("device_bytes", C.c_size_t),
                 ("setup_flops", C.c_double), ("cond_est_max", C.c_double),
-                ("cond_est_patch", C.c_int32)]
+                ("cond_est_patch", C.c_int32), ("coarse_nodes", C.c_int32),
+                ("coarse_launches", C.c_int32), ("coarse_root", C.c_int32),
+                ("setup_chunks", C.c_int32), ("coarse_bytes", C.c_double),
+                ("device_bytes_peak", C.c_size_t)]
 
 
 class tcf_server_report(C.Structure):
@@ -163,7 +167,8 @@ def default_options(**kw) -> tcf_options:
 
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
-            use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0):
+            use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0, coarse_mode=0,
+            setup_group_mb=0):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -227,7 +232,8 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         pcg_rtol=float(pcg_rtol if pcg_rtol is not None else prob.pcg_rtol),
         pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
         check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch),
-        pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling))
+        pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling),
+        coarse_mode=int(coarse_mode), setup_group_mb=int(setup_group_mb))
     return d, o, keep
 
 
@@ -310,11 +316,13 @@ class Problem:
     again by tcf_setup)."""
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
-                 check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0):
+                 check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0,
+                 coarse_mode=0, setup_group_mb=0):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
-                                   use_graph, rhs_batch, pcg_warm, precond_scaling)
+                                   use_graph, rhs_batch, pcg_warm, precond_scaling, coarse_mode,
+                                   setup_group_mb)
         self._desc = d
         self.opts = o
         h = C.c_void_p()
