@@ -33,10 +33,18 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="uneven",
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 3 for the largest workload, else 40)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default 1 for the largest workload, else 5)")
+    ap.add_argument("--workload", default="largest",
                     choices=["uneven", "plain", "mixed", "largest", "multirhs", "serving"])
+    ap.add_argument("--legs", action="store_true",
+                    help="largest workload: also run the option legs (warm/projection "
+                         "start, scaled preconditioner), which the smaller workloads run "
+                         "by default")
+    ap.add_argument("--no-fp32-leg", action="store_true",
+                    help="largest workload: skip the FP32-operator + FP64-refinement leg")
     ap.add_argument("--rhs-batch", type=int, default=0,
                     help="excitations per batched PCG (0: automatic, up to 4)")
     ap.add_argument("--pcg-warm", type=int, default=0, choices=[0, 1, 2, 3],
@@ -53,7 +61,7 @@ def parse():
                          "capacity (the last one is the headline line)")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_ir", "fp32_full_ir"])
-    ap.add_argument("--profile-steps", type=int, default=3,
+    ap.add_argument("--profile-steps", type=int, default=None,
                     help="steps after the timed run with per-kernel HIP-event timing")
     ap.add_argument("--check-steps", type=int, default=5,
                     help="oracle leg: steps of the sample compared against the oracle")
@@ -128,38 +136,27 @@ def oracle_check(sub, prec, rhs_batch, check_steps):
     return rel_err, small.name
 
 
-def cpu_baseline(prob, budget_s, full_kept):
-    """Time the oracle (as it is) on a bounded sample of the same workload.
-
-    The oracle factorises the global gauged system once with SuperLU and
-    solves once per step; at the full size of the 64-patch workloads that
-    factorisation alone runs for far over an hour on one core.  The sample
-    is the same seeded problem restricted to its first 2x2x2 block of patches
-    (same rows, materials, source, time step): it is assembled, factorised,
-    and stepped until the budget is spent.  `value` scales the sample's
-    steps/s by (sample unknowns / full unknowns), i.e. assumes the oracle's
-    per-step cost grows only linearly with size, which flatters it.
-    """
-    import workloads as W
+def _oracle_rate(sub, budget_s):
+    """The oracle as it is (assembly, gauge, one nested-dissection SuperLU
+    factorisation, one solve per step for all excitations) on one sample;
+    steps are timed until the budget is spent (amplitudes repeated)."""
+    import scipy.sparse.linalg  # noqa: F401  (imported before timing)
     from oracle import solve as osolve
-    import scipy.sparse.linalg as spla
     from oracle.assemble import assemble_global
     from oracle.gauge import compute_topology
     from oracle.grid import build_grid
 
-    sub = W.subproblem(prob, (0, 0, 0), (2, 2, 2))
     t0 = time.perf_counter()
     g = build_grid(sub)
     sysm = assemble_global(sub, g, keep_patches=False)
     topo = compute_topology(sub, g)
     Wg, K = osolve.gauged_matrix(sysm, topo, sub.dt)
     t1 = time.perf_counter()
-    lu = spla.splu(Wg)
+    lu = osolve.GaugedSolver(Wg, g, K)
     t2 = time.perf_counter()
     a = np.zeros((g.n_edges, sub.n_rhs))
     steps = 0
     ts = time.perf_counter()
-    # the amplitude sequence repeats until the budget is spent
     while steps < 1_000_000:
         f = sysm.M @ a + sub.dt * sysm.jhat * sub.amp[:, steps % sub.n_steps][None, :]
         a = np.zeros_like(a)
@@ -168,7 +165,37 @@ def cpu_baseline(prob, budget_s, full_kept):
         if time.perf_counter() - ts > budget_s:
             break
     t3 = time.perf_counter()
-    sub_rate = steps / (t3 - ts)
+    return {"name": sub.name, "unknowns": int(len(K)), "n_rhs": int(sub.n_rhs),
+            "steps_per_s": steps / (t3 - ts), "steps_timed": steps,
+            "assembly_s": t1 - t0, "factor_s": t2 - t1}
+
+
+def cpu_baseline(prob, budget_s, full_kept, samples):
+    """The oracle, unmodified, timed on the host on bounded samples of the
+    workload, and its per-step rate extrapolated to the full size.
+
+    The full-size direct factorisation is out of the bench's time budget
+    (the 64-patch workload takes about 15 minutes to assemble and factorise
+    on one core; the 256-patch one far longer), so the oracle runs on
+    samples of increasing size: the same seeded problem restricted to
+    sub-blocks of patches (for the largest workload, its reduced instance:
+    n = 4 elements per direction, 4 of the 32 excitations).  A least-squares
+    fit of log(steps/s) against log(gauged unknowns) over the samples gives
+    the size exponent; `value` is the fitted rate at the full size, scaled
+    to all of the workload's excitations (the solve cost is linear in the
+    number of right-hand sides).  Assembly and factorisation are timed
+    separately and are not in `value`.
+    """
+    per = budget_s / max(len(samples), 1)
+    rows = []
+    for sub in samples:
+        rows.append(_oracle_rate(sub, per * 0.6))
+        print(f"[bench] oracle sample {rows[-1]['name']}: {rows[-1]['unknowns']} unknowns, "
+              f"{rows[-1]['steps_per_s']:.2f} steps/s", file=sys.stderr, flush=True)
+    x = np.log([r["unknowns"] for r in rows])
+    y = np.log([r["steps_per_s"] * r["n_rhs"] for r in rows])  # excitation-steps/s
+    slope, icpt = np.polyfit(x, y, 1) if len(rows) > 1 else (-1.0, y[0] + x[0])
+    rate_full = float(np.exp(icpt + slope * np.log(full_kept))) / prob.n_rhs
     cores = len(os.sched_getaffinity(0))
     model = ""
     try:
@@ -180,26 +207,28 @@ def cpu_baseline(prob, budget_s, full_kept):
     except OSError:
         pass
     return {
-        "value": sub_rate * len(K) / full_kept, "unit": "time-steps/s", "cores": 1,
-        "kind": "oracle",
-        "sample": (f"{sub.name}: first 2x2x2 patches of the same seeded workload, "
-                   f"{len(K)} gauged unknowns (full problem {full_kept}); assembly+gauge "
-                   f"{t1 - t0:.1f} s and one SuperLU factorisation {t2 - t1:.1f} s (not in value), "
-                   f"then {steps} implicit-Euler solves (amplitudes repeated after "
-                   f"{sub.n_steps}) at {sub_rate:.2f} steps/s; value = that rate "
-                   f"x sample/full unknowns (linear scaling); SuperLU runs on 1 core, "
-                   f"{cores} cores visible"),
-        "sample_steps_per_s": sub_rate, "sample_unknowns": len(K), "factor_s": t2 - t1,
-        "assembly_s": t1 - t0, "steps_timed": steps,
-        # the same rate with assembly, gauge and factorisation spread over the
-        # workload's own number of steps (same linear scaling to full size)
-        "value_setup_amortised": (prob.n_steps / (prob.n_steps / sub_rate + (t2 - t0)))
-                                 * len(K) / full_kept,
-        "amortised_over_steps": int(prob.n_steps),
+        "value": rate_full, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (global FP64 assembly, gauge, nested-dissection SuperLU, one "
+                   f"solve per step) on {len(rows)} samples of the workload "
+                   f"({', '.join(r['name'] for r in rows)}; "
+                   f"{', '.join(str(r['unknowns']) for r in rows)} gauged unknowns), each "
+                   f"stepped for ~{per * 0.6:.0f} s; value = the fitted rate "
+                   f"(steps/s ~ unknowns^{slope:.2f}) at the full {full_kept} unknowns and "
+                   f"{prob.n_rhs} excitations; SuperLU on 1 core, {cores} cores visible"),
+        "fit_exponent": float(slope), "samples": rows,
         "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity": cores,
                  "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
                  "direct_solve_threads": 1},
     }
+
+
+def oracle_samples(args, prob):
+    """Samples of the workload the oracle can factorise within the budget."""
+    import workloads as W
+    if args.workload in ("largest", "multirhs"):
+        base = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=4, n_steps=8)
+        return [W.subproblem(base, (0, 0, 0), P) for P in ((2, 2, 1), (2, 2, 2), (4, 2, 2))]
+    return [W.subproblem(prob, (0, 0, 0), P) for P in ((2, 2, 1), (2, 2, 2), (3, 2, 2))]
 
 
 def serving(args):
@@ -281,6 +310,20 @@ def serving(args):
     print(json.dumps(out))
 
 
+def timed_run(p, warmup, steps):
+    """warmup untimed steps, then `steps` timed ones bracketed by syncs."""
+    if warmup:
+        p.tcf_step(warmup)
+    st0 = p.tcf_get_stats()
+    p.tcf_sync()
+    t0 = time.perf_counter()
+    p.tcf_step(steps)
+    p.tcf_sync()
+    wall = time.perf_counter() - t0
+    st1 = p.tcf_get_stats()
+    return wall, int(st1["total_pcg_iters"] - st0["total_pcg_iters"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -292,34 +335,38 @@ def main():
         return
     from paper_2510_23446_amd import tcf
 
+    big = args.workload == "largest"
+    if args.steps is None:
+        args.steps = 3 if big else 40
+    if args.warmup is None:
+        args.warmup = 1 if big else 5
+    if args.profile_steps is None:
+        args.profile_steps = 1 if big else 3
     if args.copy_probe_mb:
         tcf.tcf_copy_probe(args.copy_probe_mb << 20)
     n_steps = args.warmup + args.steps + args.profile_steps
     prob = make_problem(args.workload, max(n_steps, args.check_steps))
-    prec = args.precision or prob.precision
+    # the largest workload's headline runs in FP64; its FP32-operator path
+    # (the configuration's precision pattern) is the leg below
+    prec = args.precision or ("fp64" if big else prob.precision)
     p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
                     rhs_batch=args.rhs_batch, pcg_warm=args.pcg_warm)
     counts = p.counts()
     t0 = time.perf_counter()
     p.tcf_setup()
     setup_s = time.perf_counter() - t0
-    print(f"[bench] {prob.name}: setup {setup_s:.2f} s, counts {counts}", file=sys.stderr, flush=True)
+    st_setup = p.tcf_get_stats()
+    print(f"[bench] {prob.name}: setup {setup_s:.2f} s ({st_setup['setup_chunks']} patch groups, "
+          f"coarse factor {st_setup['coarse_nodes']} nodes), counts {counts}",
+          file=sys.stderr, flush=True)
 
-    # warmup
-    if args.warmup:
-        p.tcf_step(args.warmup)
-    st0 = p.tcf_get_stats()
-    p.tcf_sync()
-    t0 = time.perf_counter()
-    p.tcf_step(args.steps)
-    p.tcf_sync()
-    t1 = time.perf_counter()
-    st1 = p.tcf_get_stats()
-    wall = t1 - t0
+    wall, applies = timed_run(p, args.warmup, args.steps)
     iters, _, ms = p.tcf_get_step_log(args.steps)
-    applies = int(st1["total_pcg_iters"] - st0["total_pcg_iters"])
     print(f"[bench] timed {args.steps} steps in {wall:.3f} s; PCG iterations {applies}",
           file=sys.stderr, flush=True)
+    # fields after the timed steps, for the FP32 leg's error (a few excitations)
+    ks = sorted({0, prob.n_rhs // 2, prob.n_rhs - 1})
+    ref_fields = {k: p.tcf_get_field(k) for k in ks} if big else None
     # per-kernel durations: HIP events around every launch of each kernel
     # group, on the launch stream, over the next steps (stream launches; the
     # timed run above replays captured graphs, which take no events)
@@ -328,24 +375,57 @@ def main():
     p.tcf_sync()
     prof = p.tcf_profile_get()
     p.tcf_profile_enable(False)
+    st_end = p.tcf_get_stats()
 
-    # dominant kernel by measured time
+    # kernel groups: launches per unit (the coarse solve is several launches
+    # when it runs through the nested-dissection factor; its bytes are those
+    # of one whole solve)
+    per_unit = {k: (st_end["coarse_launches"] if k == "coarse" else 1) for k in prof}
+
+    def unit_s(k):
+        tot_ms, nl, _ = prof[k]
+        return tot_ms / 1e3 / max(nl / per_unit[k], 1e-30)
+
     dom = max(prof, key=lambda k: prof[k][0])
-    tot_ms, nl, alg_bytes = prof[dom]
-    avg_s = tot_ms / 1e3 / max(nl, 1)
-    achieved = alg_bytes / avg_s / 1e9 if nl else 0.0
+    alg_bytes = prof[dom][2]
+    achieved = alg_bytes / unit_s(dom) / 1e9 if prof[dom][1] else 0.0
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
         tj = json.load(open(args.traffic))
         same_kernel = tj.get("kernel_source_sha256") == kernel_digest("template <class T, int Group, int R>")
         if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
-                and prec == "fp64"):
+                and tj.get("precision", "fp64") == prec):
             traffic = tj.get("hbm_bytes_per_launch")
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
-                     "avg_us": round(v[0] * 1e3 / max(v[1], 1), 2),
-                     "alg_MB_per_launch": round(v[2] / 1e6, 3),
-                     "alg_GBs": round(v[2] / (v[0] / 1e3 / max(v[1], 1)) / 1e9, 1) if v[1] else 0.0}
+                     "launches_per_unit": per_unit[k],
+                     "avg_us_per_unit": round(unit_s(k) * 1e6, 2) if v[1] else 0.0,
+                     "alg_MB_per_unit": round(v[2] / 1e6, 3),
+                     "alg_GBs": round(v[2] / unit_s(k) / 1e9, 1) if v[1] else 0.0}
                  for k, v in prof.items()}
+
+    # the FP32-operator path with FP64 refinement on the same workload (the
+    # largest configuration's own precision pattern), its error stated
+    # against the FP64 run above after the same steps
+    fp32_leg = None
+    if big and not args.no_fp32_leg:
+        q = tcf.Problem(prob, precision="fp32_ir", use_graph=0 if args.no_graph else 1,
+                        rhs_batch=args.rhs_batch)
+        tq = time.perf_counter()
+        q.tcf_setup()
+        q_setup = time.perf_counter() - tq
+        q_wall, q_app = timed_run(q, args.warmup, args.steps)
+        err = max(float(np.linalg.norm(q.tcf_get_field(k) - ref_fields[k])
+                        / np.linalg.norm(ref_fields[k])) for k in ks)
+        sq = q.tcf_get_stats()
+        fp32_leg = {"precision": "fp32_ir", "value": args.steps / q_wall, "unit": "time-steps/s",
+                    "setup_s": q_setup, "pcg_iters_per_step": q_app / args.steps,
+                    "ir_sweeps_last_step": sq["last_ir_sweeps"],
+                    "ir_residual_last_step": sq["last_ir_residual"],
+                    "rel_error_vs_fp64_run": err, "error_excitations": ks,
+                    "device_bytes_peak": sq["device_bytes_peak"]}
+        q.tcf_destroy()
+        print(f"[bench] fp32_ir leg {fp32_leg['value']:.3f} steps/s, error vs the FP64 run "
+              f"{err:.2e}", file=sys.stderr, flush=True)
 
     # the same timed run with options beyond the published method: the first
     # solve of each step from the extrapolated multipliers of the last two
@@ -355,7 +435,8 @@ def main():
     # recommends), and combinations (same stopping test, same solution; the
     # value above is the method as published)
     legs = {}
-    if not args.no_warm_leg and args.pcg_warm == 0:
+    want_legs = (args.legs or not big) and not args.no_warm_leg
+    if want_legs and args.pcg_warm == 0:
         for name, kw in (("warm_start", {"pcg_warm": 2}),
                          ("projection_start", {"pcg_warm": 3}),
                          ("scaled_precond", {"precond_scaling": 1}),
@@ -364,18 +445,9 @@ def main():
             pw = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
                              rhs_batch=args.rhs_batch, **kw)
             pw.tcf_setup()
-            if args.warmup:
-                pw.tcf_step(args.warmup)
-            w0 = pw.tcf_get_stats()
-            pw.tcf_sync()
-            tw0 = time.perf_counter()
-            pw.tcf_step(args.steps)
-            pw.tcf_sync()
-            tw = time.perf_counter() - tw0
-            w1 = pw.tcf_get_stats()
+            tw, wi = timed_run(pw, args.warmup, args.steps)
             legs[name] = dict(kw, value=args.steps / tw, unit="time-steps/s",
-                              pcg_iters_per_step=(w1["total_pcg_iters"] - w0["total_pcg_iters"])
-                              / args.steps)
+                              pcg_iters_per_step=wi / args.steps)
             pw.tcf_destroy()
             print(f"[bench] {name} leg {legs[name]['value']:.2f} steps/s, "
                   f"{legs[name]['pcg_iters_per_step']:.1f} iterations per step",
@@ -408,19 +480,20 @@ def main():
         print(f"[bench] paper configuration end to end {paper['total_s']:.3f} s",
               file=sys.stderr, flush=True)
 
-    # the oracle leg, the only one that runs the oracle: the field check and
-    # the CPU baseline, both on the same sample (the seeded workload
-    # restricted to its first 2x2x2 patches)
+    # the oracle leg, the only one that runs the oracle: the field check on a
+    # sample and the CPU baseline
     cpu, rel_err, check_name = None, None, None
     if not args.no_cpu_baseline:
         import workloads as W
-        sub = W.subproblem(prob, (0, 0, 0), (2, 2, 2))
+        samples = oracle_samples(args, prob)
         if args.check_steps > 0:
-            rel_err, check_name = oracle_check(sub, prec, args.rhs_batch, args.check_steps)
-        print("[bench] oracle baseline on a sub-sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(prob, args.cpu_budget_s, counts["n_kept"])
-        print(f"[bench] oracle {cpu['value']:.3f} steps/s", file=sys.stderr, flush=True)
+            rel_err, check_name = oracle_check(samples[1], prec, args.rhs_batch, args.check_steps)
+        print("[bench] oracle baseline on samples", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob, args.cpu_budget_s, counts["n_kept"], samples)
+        print(f"[bench] oracle {cpu['value']:.4g} steps/s (fitted exponent "
+              f"{cpu['fit_exponent']:.2f})", file=sys.stderr, flush=True)
 
+    setup_flops = st_setup["setup_flops"]
     out = {
         "metric": "time-steps/sec",
         "value": args.steps / wall,
@@ -439,23 +512,26 @@ def main():
                    "n_edges": counts["n_edges"], "gauged_dofs": counts["n_kept"],
                    "n_lambda": counts["n_lambda"], "n_primal": counts["n_primal"],
                    "graphs": not args.no_graph, "rhs_batch": args.rhs_batch or "auto",
-                   "pcg_warm": args.pcg_warm},
+                   "pcg_warm": args.pcg_warm, "coarse_nodes": st_setup["coarse_nodes"],
+                   "setup_groups": st_setup["setup_chunks"]},
         "rhs_steps_per_s": args.steps * prob.n_rhs / wall,
         "pcg_applies_per_s": applies / wall,
         "pcg_iters_per_step": applies / args.steps,
         "p50_step_ms": float(np.percentile(ms, 50)),
         "p99_step_ms": float(np.percentile(ms, 99)),
         "setup_s": setup_s,
-        # setup factorisations on the FP64/FP32 vector units (on this GPU the
-        # FP64 and FP32 matrix-core peaks equal the vector peaks)
-        "setup_tflops": p.tcf_get_stats()["setup_flops"] / setup_s / 1e12,
-        "setup_frac_of_fp64_peak": p.tcf_get_stats()["setup_flops"] / setup_s / 78.6e12,
+        # algorithmic flops of the setup factorisations over the setup's wall
+        # time (which includes assembly, loads and the host plan)
+        "setup_tflops": setup_flops / setup_s / 1e12,
+        "setup_frac_of_fp64_peak": setup_flops / setup_s / 78.6e12,
+        "device_bytes_peak": st_end["device_bytes_peak"],
         "rel_error_vs_oracle": rel_err,
         "rel_error_steps": args.check_steps if rel_err is not None else 0,
         "rel_error_sample": check_name,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": breakdown,
+        "fp32_operator_leg": fp32_leg,
         "options_beyond_published": legs or None,
         "paper_timed_configuration": paper,
         "cpu_baseline": cpu,
