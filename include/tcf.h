@@ -135,8 +135,12 @@ typedef struct tcf_options {
   int32_t use_graph;        /* 1: replay captured hipGraphs for PCG chunks    */
   int32_t rhs_batch;        /* excitations solved together (one PCG over      */
                             /* several columns, each operator tile read once  */
-                            /* per iteration for all of them): 1..4, <= 0:    */
-                            /* min(n_rhs, 4)                                  */
+                            /* per iteration for all of them): 1..32.  Up to  */
+                            /* 4 on the vector units; wider batches run the   */
+                            /* tile products on the matrix cores in widths of */
+                            /* 8, 16 or 32 (a batch is rounded up; its idle   */
+                            /* columns carry zero right-hand sides).  <= 0:   */
+                            /* min(n_rhs, 32), rounded the same way           */
   int32_t pcg_warm;         /* first solve of a step starts from: 0 lambda =  */
                             /* 0; 1 the previous step's lambda; 2 the linear  */
                             /* extrapolation of the last two; 3 the Galerkin  */
@@ -169,8 +173,29 @@ typedef struct tcf_options {
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
- * rhs_batch 0 (automatic), pcg_warm 0, precond_scaling 0. */
+ * rhs_batch 0 (automatic), pcg_warm 0, precond_scaling 0, coarse_mode 0,
+ * setup_group_mb 0. */
 void tcf_default_options(tcf_options* opts);
+
+/*
+ * Device memory of a handle.  Every device buffer the handle holds (setup
+ * transients, operators, tiles, vectors) is taken from alloc and given back
+ * through free, each on the stream of the call that needs it (the stream of
+ * tcf_setup or tcf_step; tcf_destroy returns what is left on the stream of
+ * the handle's last call).  alloc returns NULL when it cannot serve a
+ * request; the call then fails with TCF_ENOMEM.  The callbacks are called
+ * on the calling thread (for serving: the request's worker thread) and must
+ * stay valid for the handle's lifetime; ctx is passed through.  A NULL
+ * allocator, or one with a NULL alloc, selects stream-ordered allocation
+ * (hipMallocAsync / hipFreeAsync on the call's stream), so that giving
+ * memory back does not synchronise the device.  The tcf_allocator struct is
+ * copied by tcf_create.
+ */
+typedef struct tcf_allocator {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* stream);
+  void (*free)(void* ctx, void* ptr, void* stream);
+} tcf_allocator;
 
 typedef struct tcf_problem tcf_problem;
 
@@ -181,9 +206,11 @@ typedef struct tcf_problem tcf_problem;
  * return; the phi callback and its context are kept until tcf_setup.
  * Errors: TCF_EINVAL (bad sizes, sigma < 0, nu <= 0, dt <= 0, non-increasing
  * breaks, deg < 1, nel < 1, n_rhs < 1), TCF_ENOMEM.  On error *out is NULL and
- * tcf_last_error(NULL) holds the message.
+ * tcf_last_error(NULL) holds the message.  allocator may be NULL (see
+ * tcf_allocator).
  */
-int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_problem** out);
+int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts,
+               const tcf_allocator* allocator, tcf_problem** out);
 
 /* Device bytes the setup will allocate for the FP64 and FP32 paths. */
 int tcf_footprint(const tcf_problem* h, size_t* bytes_fp64, size_t* bytes_fp32);
@@ -402,6 +429,11 @@ int tcf_profile_get(const tcf_problem* h, int32_t group, double* total_ms, int64
  */
 int tcf_copy_probe(size_t bytes, void* stream);
 
+/*
+ * Releases the handle.  Its device memory goes back to its allocator on the
+ * stream of the handle's last stream call, which must still exist (or be
+ * the null stream); work already queued there finishes first.
+ */
 void tcf_destroy(tcf_problem* h);
 
 /*

@@ -144,6 +144,8 @@ struct tcf_problem {
   int device = 0;
   std::vector<DevBuf> bufs;
   size_t dev_bytes = 0, dev_bytes_peak = 0;
+  tcf_allocator allocator{nullptr, nullptr, nullptr};  // alloc == NULL: stream-ordered HIP
+  hipStream_t mem_stream = nullptr;  // stream of the current (or last) call
   // setup in patch groups: patches [chunk_begin[c], chunk_begin[c + 1]) are
   // assembled and factored together; A_off is relative to the group
   std::vector<int> chunk_begin;
@@ -238,6 +240,10 @@ struct tcf_problem {
   int nj_phi = 0, nt_phi = 0, nj_ai = 0, nt_ai = 0;
   int *d_cond = nullptr, *d_cond_cprefix = nullptr, *d_cond_rprefix = nullptr;
   int nt_cond_c = 0, nt_cond_r = 0;
+  // 64-wide blocks of the matrix-core condensation (columns) and recovery
+  // (interior rows)
+  int *d_cond_wprefix = nullptr, *d_all_wprefix = nullptr, *d_all_iprefix = nullptr;
+  int nt_cond_w = 0, nt_all_w = 0, nt_all_i = 0;
 
   // ---- kernel timing -------------------------------------------------------------
   struct Pend { int g, it; hipEvent_t a, b; };
@@ -292,23 +298,45 @@ struct tcf_problem {
     for (auto& p : pend) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto& b : bufs)
-      if (b.p) (void)hipFree(b.p);
+      if (b.p) give_back(b.p);
     if (h_st) (void)hipHostFree(h_st);
     if (h_nrm) (void)hipHostFree(h_nrm);
   }
 
+  // one buffer back to its allocator, on the current call's stream
+  void give_back(void* p) {
+    if (allocator.alloc) allocator.free(allocator.ctx, p, (void*)mem_stream);
+    else (void)hipFreeAsync(p, mem_stream);
+  }
   template <class T>
   int alloc(T** out, size_t count) {
     void* p = nullptr;
-    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e;
+    // whole multiples of 256 bytes: every buffer starts on a 256-byte boundary
+    // whichever allocator serves it
+    const size_t bytes = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+    bool ok;
     {
       std::lock_guard<std::mutex> lk(g_capture_mu);
-      e = hipMalloc(&p, bytes);
+      if (allocator.alloc) {
+        p = allocator.alloc(allocator.ctx, bytes, (void*)mem_stream);
+        ok = p != nullptr;
+      } else {
+        ok = hipMallocAsync(&p, bytes, mem_stream) == hipSuccess;
+        if (!ok) (void)hipGetLastError();
+      }
     }
-    if (e != hipSuccess) {
-      err = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+    if (!ok) {
+      err = "device allocation of " + std::to_string(bytes) + " bytes failed";
       return TCF_ENOMEM;
+    }
+    // the block may have been given back on this stream by work still in
+    // flight, and the handle fills some buffers with blocking copies (the
+    // null stream): let that work finish first
+    if (hipStreamSynchronize(mem_stream) != hipSuccess) {
+      (void)hipGetLastError();
+      give_back(p);
+      err = "stream synchronisation after a device allocation failed";
+      return TCF_EHIP;
     }
     bufs.push_back({p, bytes});
     dev_bytes += bytes;
@@ -320,7 +348,7 @@ struct tcf_problem {
     for (auto& b : bufs)
       if (b.p == p) {
         std::lock_guard<std::mutex> lk(g_capture_mu);
-        (void)hipFree(b.p);
+        give_back(b.p);
         dev_bytes -= b.bytes;
         b.p = nullptr;
         b.bytes = 0;
@@ -427,7 +455,7 @@ size_t tcf_problem::footprint(int prec) const {
     }
   }
   const double npm = std::max(n_primal, 1);
-  double vec = (double)n_rtot * n_rhs * 8 * 6 + (double)n_rtot * rb * 8 * 3;
+  double vec = (double)n_rtot * n_rhs * 8 * 6 + (double)n_rtot * rb * 8 * 4;
   vec += ((double)n_bptot * 16 + (double)n_btot * 16 + (double)n_lambda * 8 * 8) * rb;
   vec += (double)rb * (n_bptot + 3 * npm + n_btot + 2 * TCF_QSLOTS) * 8 + npm * 8 * (4 + rb);
   vec += (double)(tab_elems + ptab_elems) * 8 + (double)n_rtot * 24 + (double)n_loctot * 4;
@@ -651,7 +679,8 @@ const char* tcf_last_error(const tcf_problem* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }
 
-int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_problem** out) {
+int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts,
+               const tcf_allocator* allocator, tcf_problem** out) {
   if (!out) { g_create_error = "null output handle"; return TCF_EINVAL; }
   *out = nullptr;
   if (!desc) { g_create_error = "null description"; return TCF_EINVAL; }
@@ -660,6 +689,10 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   std::unique_ptr<tcf_problem> h(new (std::nothrow) tcf_problem());
   if (!h) { g_create_error = "out of host memory"; return TCF_ENOMEM; }
   if (opts) h->opt = *opts; else tcf_default_options(&h->opt);
+  if (allocator && allocator->alloc) {
+    if (!allocator->free) { g_create_error = "allocator without a free function"; return TCF_EINVAL; }
+    h->allocator = *allocator;
+  }
   if (h->opt.precision != TCF_FP64 && h->opt.precision != TCF_FP32_IR &&
       h->opt.precision != TCF_FP32_FULL_IR) {
     g_create_error = "unknown precision"; return TCF_EINVAL;
@@ -699,7 +732,12 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts, tcf_proble
   h->src.assign(desc->src_mask, desc->src_mask + np);
   h->n_rhs = desc->n_rhs;
   // excitations per batched PCG
-  h->rb = std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 4) : 4);
+  // up to 4 columns on the vector tile kernels; more on the matrix cores,
+  // in widths of 8, 16 or 32 (idle columns carry zero right-hand sides)
+  {
+    const int want = std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 32) : 32);
+    h->rb = want <= 4 ? want : (want <= 8 ? 8 : (want <= 16 ? 16 : 32));
+  }
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
   h->jvol = desc->jvol;
@@ -1219,6 +1257,21 @@ static int build_index_tables(tcf_problem* h) {
   RCCHK(h->upload(&h->d_cond, h->cond_list));
   RCCHK(h->upload(&h->d_cond_cprefix, cpre));
   RCCHK(h->upload(&h->d_cond_rprefix, rpre));
+  {
+    std::vector<int> cw, aw, ai64;
+    for (int s : h->cond_list) cw.push_back((h->hp[s].n_r + 63) / 64);
+    for (int s = 0; s < np; ++s) {
+      aw.push_back((h->hp[s].n_r + 63) / 64);
+      ai64.push_back((h->hp[s].n_i + 63) / 64);
+    }
+    auto pcw = prefix_of(cw), paw = prefix_of(aw), pai = prefix_of(ai64);
+    h->nt_cond_w = pcw.back();
+    h->nt_all_w = paw.back();
+    h->nt_all_i = pai.back();
+    RCCHK(h->upload(&h->d_cond_wprefix, pcw));
+    RCCHK(h->upload(&h->d_all_wprefix, paw));
+    RCCHK(h->upload(&h->d_all_iprefix, pai));
+  }
   return TCF_OK;
 }
 
@@ -1503,7 +1556,8 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
       sbc[t] = d.n_b;
       cg[t] = d.n_b > 0 ? d.n_b + d.n_p : 0;
       cq[t] = d.n_i > 0 ? d.n_r : 0;
-      cc[t] = (d.n_r + 15) / 16;
+      // condensation blocks: 16 columns (vector form) or 64 (matrix cores)
+      cc[t] = nrhs > 2 ? (d.n_r + 63) / 64 : (d.n_r + 15) / 16;
       plist[t] = t;
     }
     auto colpre = prefix_of(colcnt), sbpre = prefix_of(sbc), pg = prefix_of(cg),
@@ -1558,8 +1612,13 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     RCCHK(run_trsm<T>(h, 0, qbk, A, Qw, st));
     // the source condenses once (time separable), with the factorisation's
     // own Q^T: yggs = cond(jhat)
-    launch_condense<T>(dPc, dpl, dcp, nc, cpre.back(), nrhs, h->max_ni, Qw, h->d_jr, h->d_yggs,
-                       ldv, st);
+    if (nrhs > 2)
+      for (int r0 = 0; r0 < nrhs; r0 += 32)
+        launch_condense_w<T>(dPc, dpl, dcp, nc, cpre.back(), std::min(32, nrhs - r0), Qw,
+                             h->d_jr + (int64_t)r0 * ldv, h->d_yggs + (int64_t)r0 * ldv, ldv, st);
+    else
+      launch_condense<T>(dPc, dpl, dcp, nc, cpre.back(), nrhs, h->max_ni, Qw, h->d_jr, h->d_yggs,
+                         ldv, st);
     HIPCHK(hipGetLastError());
     if (!kSame) {
       const DevPatch& l = h->hp[s1 - 1];
@@ -1646,7 +1705,7 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   RCCHK(h->alloc(&h->d_a, (size_t)ldv * nrhs));
   RCCHK(h->alloc(&h->d_fM, (size_t)ldv * nrhs));
   RCCHK(h->alloc(&h->d_ygg, (size_t)ldv * nrhs));
-  RCCHK(h->alloc(&h->d_zr, (size_t)ldv));
+  RCCHK(h->alloc(&h->d_zr, (size_t)ldv * h->rb));
   HIPCHK(hipMemsetAsync(h->d_a, 0, sizeof(double) * ldv * nrhs, st));
   HIPCHK(hipMemsetAsync(h->d_fM, 0, sizeof(double) * ldv * nrhs, st));
   const int rb = h->rb;
@@ -1712,6 +1771,7 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   // refinement work vectors and the kept-unknown -> local-copies map
   RCCHK(h->alloc(&h->d_floc, (size_t)ldv * rb));
   RCCHK(h->alloc(&h->d_res, (size_t)ldv * rb));
+  HIPCHK(hipMemsetAsync(h->d_res, 0, sizeof(double) * ldv * rb, st));
   RCCHK(h->alloc(&h->d_delta, (size_t)ldv * rb));
   {
     std::vector<std::vector<int>> copies;
@@ -1932,6 +1992,7 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   if (!h) return TCF_EINVAL;
   if (h->is_setup) { h->err = "setup already done"; return TCF_ESTATE; }
   hipStream_t st = (hipStream_t)stream;
+  h->mem_stream = st;
   HIPCHK(hipGetDevice(&h->device));
   const double t0 = now_ms();
   int rc;
@@ -1987,7 +2048,7 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
   for (int lv = 0; lv < h->c_levels; ++lv) {
     const int j0 = h->c_fwd_pre[lv], nj = h->c_fwd_pre[lv + 1] - j0;
     timed(TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(1, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+      launch_tiles<double>(4, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
                            base, ld, h->d_cT, nullptr, done, st);
     });
   }
@@ -2000,7 +2061,7 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
   for (int lv = h->c_levels - 1; lv >= 0; --lv) {
     const int j0 = h->c_bwd_pre[lv], nj = h->c_bwd_pre[lv + 1] - j0;
     timed(TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(1, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+      launch_tiles<double>(4, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
                            base, ld, h->d_cT, nullptr, done, st);
     });
   }
@@ -2217,37 +2278,69 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
 //
 // solve_pre: [u; c0] = G^T g_b, h = sum N^T (g_p - c0), q0 = S_Pi^-1 h,
 // d = jump(u - Phi N q0) into column j.
+// Condensation of the right-hand sides of excitations k0 .. k0 + nc - 1
+// into ygg (columns k0 .. of d_ygg).  rhs == nullptr: the time-step form
+// f = M a_k + dt g_k(t_{l+1}) jhat_k, whose source part was condensed at
+// setup, so only the conductor patches' M a_k is condensed; else rhs
+// holds the nc right-hand sides (column j at rhs + j * ldv, all patches).
+// Batches wider than two go through the matrix-core form, which reads Q^T
+// once for all of them.
 template <class T>
-static void solve_pre(tcf_problem* h, int k, int l, const double* rhs, const double* base, int j,
-                      hipStream_t st) {
+static void condense_batch(tcf_problem* h, int k0, int nc, int l, const double* rhs,
+                           hipStream_t st) {
+  const int64_t ldv = h->n_rtot;
+  const T* Q = (const T*)h->d_Q;
+  double* ygg = h->d_ygg + (int64_t)k0 * ldv;
+  const bool wide = nc > 2;
+  if (!rhs) {
+    for (int j = 0; j < nc; ++j) {
+      const int k = k0 + j;
+      const double gk = h->amp[(size_t)k * h->n_steps + l];
+      launch_axpby(ldv, h->dt * gk, h->d_yggs + (int64_t)k * ldv, 0.0, ygg + (int64_t)j * ldv, st);
+    }
+    if (h->cond_list.empty()) return;
+    double* a = h->d_a + (int64_t)k0 * ldv;
+    double* fM = h->d_fM + (int64_t)k0 * ldv;
+    launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, nc,
+                  h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
+    // the initial value enters the first step as M a^(0) = int sigma A_0 . w
+    if (l == 0 && h->d_m0)
+      launch_axpby(ldv * nc, 1.0, h->d_m0 + (int64_t)k0 * ldv, 1.0, fM, st);
+    timed(h, TCF_KG_CONDENSE, st, [&] {
+      if (wide)
+        launch_condense_w<T>(h->dP, h->d_cond, h->d_cond_wprefix, (int)h->cond_list.size(),
+                             h->nt_cond_w, nc, Q, fM, ygg, ldv, st);
+      else
+        launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
+                           h->nt_cond_c, nc, h->max_ni, Q, fM, ygg, ldv, st);
+    });
+  } else {
+    launch_zero(ldv * nc, ygg, st);
+    if (wide)
+      launch_condense_w<T>(h->dP, h->d_all, h->d_all_wprefix, h->np_tot, h->nt_all_w, nc, Q, rhs,
+                           ygg, ldv, st);
+    else
+      launch_condense<T>(h->dP, h->d_all, h->d_all_cprefix, h->np_tot, h->nt_all_c, nc,
+                         h->max_ni, Q, rhs, ygg, ldv, st);
+  }
+}
+
+// Dual-primal solve of W x = f, split around the (batched) PCG, with f
+// condensed into ygg of excitation k beforehand (condense_batch).  If
+// base != nullptr the solution is a correction to base and the interface
+// constraint is Bhat (base + x) = 0, i.e. the dual right-hand side becomes
+// d + Bhat base.  Column j of the PCG vectors carries it.
+//
+// solve_pre: [u; c0] = G^T g_b, h = sum N^T (g_p - c0), q0 = S_Pi^-1 h,
+// d = jump(u - Phi N q0) into column j.
+template <class T>
+static void solve_pre(tcf_problem* h, int k, const double* base, int j, hipStream_t st) {
   const int64_t ldv = h->n_rtot;
   double* ygg = h->d_ygg + (int64_t)k * ldv;
   const T* G = (const T*)h->d_G;
-  const T* Q = (const T*)h->d_Q;
   double* uc = h->d_uc + (int64_t)j * h->n_bptot;
   double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
   double* dv = h->d_d + (int64_t)j * h->n_lambda;
-  if (!rhs) {
-    double* a = h->d_a + (int64_t)k * ldv;
-    double* fM = h->d_fM + (int64_t)k * ldv;
-    const double* yggs = h->d_yggs + (int64_t)k * ldv;
-    const double gk = h->amp[(size_t)k * h->n_steps + l];
-    launch_axpby(ldv, h->dt * gk, yggs, 0.0, ygg, st);
-    if (!h->cond_list.empty()) {
-      launch_wapply(h->dP, h->d_cond, h->d_cond_rprefix, (int)h->cond_list.size(), h->nt_cond_r, 1,
-                    h->d_rloc, h->d_loc2r, h->d_tabs, h->dt, 1, a, fM, ldv, st);
-      // the initial value enters the first step as M a^(0) = int sigma A_0 . w
-      if (l == 0 && h->d_m0) launch_axpby(ldv, 1.0, h->d_m0 + (int64_t)k * ldv, 1.0, fM, st);
-      timed(h, TCF_KG_CONDENSE, st, [&] {
-        launch_condense<T>(h->dP, h->d_cond, h->d_cond_cprefix, (int)h->cond_list.size(),
-                           h->nt_cond_c, 1, h->max_ni, Q, fM, ygg, ldv, st);
-      });
-    }
-  } else {
-    launch_axpby(ldv, 0.0, rhs, 0.0, ygg, st);
-    launch_condense<T>(h->dP, h->d_all, h->d_all_cprefix, h->np_tot, h->nt_all_c, 1, h->max_ni, Q,
-                       rhs, ygg, ldv, st);
-  }
   if (h->bp_gaps) launch_zero(h->n_bptot, uc, st);
   launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
                     nullptr, 1.0, uc, nullptr, st);
@@ -2263,14 +2356,15 @@ static void solve_pre(tcf_problem* h, int k, int l, const double* rhs, const dou
 }
 
 // solve_post (column j, lambda from the PCG): p = S_Pi^-1 (h + sum N^T Phi^T
-// x) with x = Bhat^T lambda; x_b = (u - v) - Phi N p; x_p = N p; x_i from
-// Q^T [y; -x_b; -x_p].  Writes the solution to x_out (kept order).
+// x) with x = Bhat^T lambda; x_b = (u - v) - Phi N p; x_p = N p; and the
+// right-hand side of the interior recovery, z = [y; -x_b; -x_p], into column
+// j of d_zr.  The interior unknowns follow for the whole batch in
+// recover_batch.  Writes into x_out (kept order).
 template <class T>
 static void solve_post(tcf_problem* h, int k, int j, double* x_out, hipStream_t st) {
   const int64_t ldv = h->n_rtot;
   double* ygg = h->d_ygg + (int64_t)k * ldv;
   const T* G = (const T*)h->d_G;
-  const T* Q = (const T*)h->d_Q;
   const double* uc = h->d_uc + (int64_t)j * h->n_bptot;
   const double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
   const double* lam = h->d_lam + (int64_t)j * h->n_lambda;
@@ -2287,11 +2381,29 @@ static void solve_post(tcf_problem* h, int k, int j, double* x_out, hipStream_t 
                          h->d_prank, x_out, h->a_boff_ab, -1.0, x_out, 0, nullptr, st);
     launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, x_out, nullptr, st);
   }
-  launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr, st);
-  timed(h, TCF_KG_RECOVER, st, [&] {
-    launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q, h->d_zr, nullptr,
-                       nullptr, h->a_boff_ai, 1.0, x_out, 1, nullptr, st);
-  });
+  launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr + (int64_t)j * ldv, st);
+}
+
+// Interior recovery x_i = Q^T z of the nc columns of a batch (column j of
+// z at d_zr + j ldv, of x at x_out + j ldv): the matrix-core form reads Q^T
+// once for the batch; up to two columns use the row-stripe product.
+template <class T>
+static void recover_batch(tcf_problem* h, int nc, double* x_out, hipStream_t st) {
+  const int64_t ldv = h->n_rtot;
+  const T* Q = (const T*)h->d_Q;
+  if (nc > 2) {
+    timed(h, TCF_KG_RECOVER, st, [&] {
+      launch_qapply_w<T>(h->dP, h->d_all, h->d_all_iprefix, h->np_tot, h->nt_all_i, nc, Q,
+                         h->d_zr, x_out, ldv, st);
+    });
+    return;
+  }
+  for (int j = 0; j < nc; ++j)
+    timed(h, TCF_KG_RECOVER, st, [&] {
+      launch_axpyrows<T>(h->aj_ai, h->ap_ai, h->nj_ai, h->nt_ai, h->max_nr, Q,
+                         h->d_zr + (int64_t)j * ldv, nullptr, nullptr, h->a_boff_ai, 1.0,
+                         x_out + (int64_t)j * ldv, 1, nullptr, st);
+    });
 }
 
 // Relative interface jump ||Bhat x|| (diagnostics with TCF_TRACE=1; syncs).
@@ -2384,7 +2496,8 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   const int R = h->rb, nl = h->n_lambda;
   std::vector<int> it(R);
   std::vector<char> cv(R);
-  bool cvb[4];
+  std::vector<int> itv(R);
+  std::unique_ptr<bool[]> cvb(new bool[R]);
   for (int j = 0; j < nc; ++j) {
     iters[j] = 0;
     sweeps[j] = 0;
@@ -2402,8 +2515,7 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
       }
   };
   auto run_pcg = [&]() -> int {
-    int itv[4];
-    RCCHK(pcg_solve<T>(h, st, itv, cvb));
+    RCCHK(pcg_solve<T>(h, st, itv.data(), cvb.get()));
     for (int j = 0; j < R; ++j) {
       it[j] = itv[j];
       cv[j] = cvb[j];
@@ -2414,7 +2526,8 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   for (int j = 0; j < nc; ++j) all[j] = 1;
   // first solve: the time-step right-hand side of every excitation
   h->cur_sweep = 0;
-  for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, l, nullptr, nullptr, j, st);
+  condense_batch<T>(h, k0, nc, l, nullptr, st);
+  for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, nullptr, j, st);
   zero_idle(all);
   if (h->d_px) {
     for (int j = 0; j < R; ++j) {
@@ -2459,6 +2572,7 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   if (h->d_px)
     for (int j = 0; j < nc; ++j) proj_update(h, k0 + j, j, st);
   for (int j = 0; j < nc; ++j) solve_post<T>(h, k0 + j, j, h->d_a + (int64_t)(k0 + j) * ldv, st);
+  recover_batch<T>(h, nc, h->d_a + (int64_t)k0 * ldv, st);
   collect(all);
   for (int j = 0; j < nc; ++j) sweeps[j] = 1;
   if (h->precision == TCF_FP64 && !h->fp64_ir) return TCF_OK;
@@ -2506,20 +2620,23 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
     // its dual right-hand side is as small as the true residual and the PCG
     // tolerance also resolves the interface jump carried over from a
     h->cur_sweep = sweep;
-    for (int j = 0; j < nc; ++j) {
-      if (!active[j]) continue;
-      double* res = h->d_res + (int64_t)j * ldv;
-      launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, res, st);
-      solve_pre<T>(h, k0 + j, l, res, h->d_a + (int64_t)(k0 + j) * ldv, j, st);
-    }
+    for (int j = 0; j < nc; ++j)
+      if (active[j])
+        launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, h->d_res + (int64_t)j * ldv, st);
+    // (columns of settled excitations are condensed too and left unused)
+    condense_batch<T>(h, k0, nc, l, h->d_res, st);
+    for (int j = 0; j < nc; ++j)
+      if (active[j]) solve_pre<T>(h, k0 + j, h->d_a + (int64_t)(k0 + j) * ldv, j, st);
     zero_idle(active);
     RCCHK(run_pcg());
+    for (int j = 0; j < nc; ++j)
+      if (active[j]) solve_post<T>(h, k0 + j, j, h->d_delta + (int64_t)j * ldv, st);
+    recover_batch<T>(h, nc, h->d_delta, st);
     for (int j = 0; j < nc; ++j) {
       if (!active[j]) continue;
       const int k = k0 + j;
       double* a = h->d_a + (int64_t)k * ldv;
       double* delta = h->d_delta + (int64_t)j * ldv;
-      solve_post<T>(h, k, j, delta, st);
       launch_axpby(ldv, 1.0, delta, 1.0, a, st);
       RCCHK(asm_norm2(h, delta, 1, 2, st));
       RCCHK(asm_norm2(h, a, 1, 3, st));
@@ -2551,8 +2668,8 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
 template <class T>
 static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
   int status = TCF_OK;
-  int iters[4], sweeps[4];
-  bool conv[4];
+  std::vector<int> iters(h->rb), sweeps(h->rb);
+  std::unique_ptr<bool[]> conv(new bool[h->rb]);
   for (int s = 0; s < nsteps; ++s) {
     const int l = h->steps_done;
     const double t0 = now_ms();
@@ -2560,7 +2677,7 @@ static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
     bool all_conv = true;
     for (int k0 = 0; k0 < h->n_rhs; k0 += h->rb) {
       const int nc = std::min(h->rb, h->n_rhs - k0);
-      RCCHK(step_batch<T>(h, k0, nc, l, st, iters, sweeps, conv));
+      RCCHK(step_batch<T>(h, k0, nc, l, st, iters.data(), sweeps.data(), conv.get()));
       for (int j = 0; j < nc; ++j) {
         it_sum += iters[j];
         ir_sum += sweeps[j];
@@ -2597,6 +2714,7 @@ int tcf_step(tcf_problem* h, int32_t nsteps, void* stream) {
   nsteps = std::min(nsteps, h->n_steps - h->steps_done);
   if (nsteps <= 0) return TCF_OK;
   hipStream_t st = (hipStream_t)stream;
+  h->mem_stream = st;
   try {
     return h->precision == TCF_FP64 ? step_impl<double>(h, nsteps, st)
                                     : step_impl<float>(h, nsteps, st);  // FP32 operators

@@ -65,6 +65,16 @@ template <class T>
 void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int nlist, int total,
                      int nrhs, int max_ni, const T* Q, const double* f, double* ygg, int64_t ldv,
                      hipStream_t st);
+// The condensation and the interior recovery for R <= 32 columns at once
+// (matrix cores); prefixes over ceil(n_r / 64) resp. ceil(n_i / 64) blocks.
+template <class T>
+void launch_condense_w(const DevPatch* P, const int* plist, const int* prefix, int nlist,
+                       int total, int R, const T* Q, const double* f, double* ygg, int64_t ldv,
+                       hipStream_t st);
+template <class T>
+void launch_qapply_w(const DevPatch* P, const int* plist, const int* prefix, int nlist, int total,
+                     int R, const T* Q, const double* z, double* out, int64_t ldv,
+                     hipStream_t st);
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
                  const double* dotw, double* partial, const int* done, hipStream_t st);
 void launch_coarse_gather(int n, const int* ptr, const int* ia, const double* srcA, double sa,
@@ -119,7 +129,8 @@ template <class TS, class TD>
 void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st);
 template <class T>
 // group: 0 F apply, 2 preconditioner (signed gather inputs), 1 Phi_b N q
-// (plain gather), 3 coarse (direct inputs)
+// and 4 coarse factor sweeps (plain gather), 3 coarse top block (direct
+// inputs)
 // R (1..4) right-hand sides at once: inputs xv[j * xld + i], outputs
 // y[j * yld + i], quadratic-form slots qslot[j * TCF_QSLOTS + k].
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,

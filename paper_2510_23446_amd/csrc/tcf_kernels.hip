@@ -1158,6 +1158,122 @@ __global__ void __launch_bounds__(256) k_condense(const DevPatch* P, const int* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same products for many right-hand sides at once on the matrix cores
+// (v_mfma_f64_16x16x4, FP64 accumulation; up to 32 columns, two 16-wide
+// accumulators per wave), so that Q^T is read once per step for a whole
+// batch of excitations instead of once per excitation.  A block takes a
+// 64 x 64 block of Q^T (rows = interior unknowns, columns = kept
+// unknowns) and the matching 64 rows of the right-hand sides through LDS
+// per step of 64 along the contracted index.
+// ---------------------------------------------------------------------------
+// stage Q^T[r0 .. r0 + 64, c0 .. c0 + 64) (zero outside rows < nr, cols < nc)
+template <class T>
+__device__ inline void stage_q(const T* Mq, int64_t ld, int r0, int c0, int nr, int nc,
+                               double (*Qs)[65]) {
+  const int t = threadIdx.x;
+  const int c = t >> 2, rq = (t & 3) * 16;  // column c, rows rq .. rq + 15
+  const bool cok = c0 + c < nc;
+  const T* src = Mq + (int64_t)(c0 + (cok ? c : 0)) * ld + r0 + rq;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int r = r0 + rq + u;
+    Qs[rq + u][c] = (cok && r < nr) ? (double)src[u] : 0.0;
+  }
+}
+
+// Condensation of R right-hand sides (columns j of f and ygg at j * ldv):
+// ygg[c] += (c < n_i) ? (Q^T[:, c] . f_i) : (f[c] - Q^T[:, c] . f_i).  One
+// block per 64 columns of a listed patch (prefix over ceil(n_r / 64)).
+template <class T>
+__global__ void __launch_bounds__(256) k_condense_w(const DevPatch* P, const int* plist,
+                                                    const int* prefix, int nlist, const T* Q,
+                                                    const double* f, double* ygg, int64_t ldv,
+                                                    int R) {
+  typedef Mfma16<double> M;
+  const int li_ = find_job(prefix, nlist, blockIdx.x);
+  const DevPatch& pp = P[plist[li_]];
+  const int c0 = (blockIdx.x - prefix[li_]) * 64;
+  __shared__ double Qs[64][65];
+  __shared__ double Fs[64][33];
+  const T* Mq = Q + pp.Q_off;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  // Q^T[:, c] for c < n_i has nonzeros only in rows <= c
+  const int rmax = c0 < pp.n_i ? min(pp.n_i, c0 + 64) : pp.n_i;
+  M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < rmax; r0 += 64) {
+    __syncthreads();
+    stage_q(Mq, pp.ni_pad, r0, c0, pp.n_i, pp.n_r, Qs);
+    for (int idx = t; idx < 64 * 32; idx += 256) {
+      const int r = idx & 63, j = idx >> 6;
+      Fs[r][j] = (j < R && r0 + r < pp.n_i) ? f[(int64_t)j * ldv + pp.r_off + r0 + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k4 = 0; k4 < 16; ++k4) {
+      const double a = Qs[4 * k4 + lk][16 * w + li];
+      a0 = M::mma(a, Fs[4 * k4 + lk][li], a0);
+      if (R > 16) a1 = M::mma(a, Fs[4 * k4 + lk][16 + li], a1);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = c0 + 16 * w + M::row(lk, e);
+    if (c >= pp.n_r) continue;
+    for (int h = 0; h < 2; ++h) {
+      const int j = 16 * h + li;
+      if (j >= R) continue;
+      const double v = h ? a1[e] : a0[e];
+      const int64_t o = (int64_t)j * ldv + pp.r_off + c;
+      ygg[o] += (c < pp.n_i) ? v : (f[o] - v);
+    }
+  }
+}
+
+// Interior recovery of R columns: out[r_off + r] = sum_c Q^T[r, c] z[r_off + c]
+// for r < n_i (column j of z and out at j * ldv); Q^T's leading block is
+// upper triangular, so column blocks before the row block are skipped.  One
+// block per 64 interior rows of a listed patch (prefix over ceil(n_i / 64)).
+template <class T>
+__global__ void __launch_bounds__(256) k_qapply_w(const DevPatch* P, const int* plist,
+                                                  const int* prefix, int nlist, const T* Q,
+                                                  const double* z, double* out, int64_t ldv,
+                                                  int R) {
+  typedef Mfma16<double> M;
+  const int li_ = find_job(prefix, nlist, blockIdx.x);
+  const DevPatch& pp = P[plist[li_]];
+  const int r0 = (blockIdx.x - prefix[li_]) * 64;
+  __shared__ double Qs[64][65];
+  __shared__ double Zs[64][33];
+  const T* Mq = Q + pp.Q_off;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = r0 / 64 * 64; c0 < pp.n_r; c0 += 64) {
+    __syncthreads();
+    stage_q(Mq, pp.ni_pad, r0, c0, pp.n_i, pp.n_r, Qs);
+    for (int idx = t; idx < 64 * 32; idx += 256) {
+      const int c = idx & 63, j = idx >> 6;
+      Zs[c][j] = (j < R && c0 + c < pp.n_r) ? z[(int64_t)j * ldv + pp.r_off + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k4 = 0; k4 < 16; ++k4) {
+      const double a = Qs[16 * w + li][4 * k4 + lk];
+      a0 = M::mma(a, Zs[4 * k4 + lk][li], a0);
+      if (R > 16) a1 = M::mma(a, Zs[4 * k4 + lk][16 + li], a1);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = r0 + 16 * w + M::row(lk, e);
+    if (r >= pp.n_i) continue;
+    for (int h = 0; h < 2; ++h) {
+      const int j = 16 * h + li;
+      if (j < R) out[(int64_t)j * ldv + pp.r_off + r] = h ? a1[e] : a0[e];
+    }
+  }
+}
+
 // ===========================================================================
 // Small vector kernels
 // ===========================================================================
@@ -1398,20 +1514,31 @@ __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, c
   __shared__ double sh4[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int a = 0, b = 0;
-  double pi[R], ri[R], li[R];
+  // up to 4 columns the vectors are loaded ahead (in flight during the slot
+  // reductions); wider batches load each column in its turn
+  constexpr int RC = R <= 4 ? R : 1;
+  double pi[RC], ri[RC], li[RC];
   if (i < n) {
     a = pos_p[i];
     b = pos_m[i];
   }
+  if (R <= 4) {
 #pragma unroll
-  for (int j = 0; j < R; ++j) {
-    pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
-    ri[j] = i < n ? r[(int64_t)j * n + i] : 0.0;
-    li[j] = i < n ? lam[(int64_t)j * n + i] : 0.0;
+    for (int j = 0; j < RC; ++j) {
+      pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
+      ri[j] = i < n ? r[(int64_t)j * n + i] : 0.0;
+      li[j] = i < n ? lam[(int64_t)j * n + i] : 0.0;
+    }
   }
   for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
+    const int jc = R <= 4 ? j : 0;
+    if (R > 4) {
+      pi[0] = i < n ? p[(int64_t)j * n + i] : 0.0;
+      ri[0] = i < n ? r[(int64_t)j * n + i] : 0.0;
+      li[0] = i < n ? lam[(int64_t)j * n + i] : 0.0;
+    }
     const double pq = sum_slots(pq_slots + j * TCF_QSLOTS, sh);
     const bool live = !st[j].done;
     double v = 0.0;
@@ -1419,11 +1546,11 @@ __global__ void __launch_bounds__(256) k_pcg_update_t(int n, const int* pos_p, c
       if (live) {
         const double alpha = st[j].rz[par] / pq;
         const double fi = dt * (w[(int64_t)j * wld + a] - w[(int64_t)j * wld + b]);
-        lam[(int64_t)j * n + i] = li[j] + alpha * pi[j];
-        ri[j] -= alpha * fi;
-        r[(int64_t)j * n + i] = ri[j];
+        lam[(int64_t)j * n + i] = li[jc] + alpha * pi[jc];
+        ri[jc] -= alpha * fi;
+        r[(int64_t)j * n + i] = ri[jc];
       }
-      v = ri[j] * ri[j];
+      v = ri[jc] * ri[jc];
     }
     const double s = block_sum256(v, sh4);
     if (threadIdx.x == 0) part_rr[j * npart + blockIdx.x] = s;
@@ -1451,24 +1578,29 @@ __global__ void __launch_bounds__(256) k_pcg_pupdate_t(int n, const int* pos_p, 
   __shared__ double rzs[R];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   int a = 0, b = 0;
-  double pi[R], ca = 1.0, cb = 1.0;
+  constexpr int RC = R <= 4 ? R : 1;
+  double pi[RC], ca = 1.0, cb = 1.0;
   if (i < n) {
     a = pos_p[i];
     b = pos_m[i];
     if (wp) ca = wp[i];
     if (wm) cb = wm[i];
   }
+  if (R <= 4) {
 #pragma unroll
-  for (int j = 0; j < R; ++j) pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
+    for (int j = 0; j < RC; ++j) pi[j] = i < n ? p[(int64_t)j * n + i] : 0.0;
+  }
   for (int64_t k = i; k < nzero; k += (int64_t)gridDim.x * blockDim.x) zero[k] = 0.0;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
+    const int jc = R <= 4 ? j : 0;
+    if (R > 4) pi[0] = i < n ? p[(int64_t)j * n + i] : 0.0;
     const double rz_new = sum_slots(rz_slots + j * TCF_QSLOTS, sh);
     if (threadIdx.x == 0) rzs[j] = rz_new;
     if (i < n && !st[j].done) {
       const double beta = rz_new / st[j].rz[par];
       p[(int64_t)j * n + i] =
-          (ca * tb[(int64_t)j * tld + a] - cb * tb[(int64_t)j * tld + b]) + beta * pi[j];
+          (ca * tb[(int64_t)j * tld + a] - cb * tb[(int64_t)j * tld + b]) + beta * pi[jc];
     }
     __syncthreads();
   }
@@ -1696,6 +1828,34 @@ void launch_condense(const DevPatch* P, const int* plist, const int* prefix, int
                      f, ygg, ldv);
 }
 
+template <class T>
+void launch_condense_w(const DevPatch* P, const int* plist, const int* prefix, int nlist,
+                       int total, int R, const T* Q, const double* f, double* ygg, int64_t ldv,
+                       hipStream_t st) {
+  if (total == 0 || R == 0) return;
+  TCF_TIMED_LAUNCH(k_condense_w<T>, dim3(total), dim3(256), 0, st, P, plist, prefix, nlist, Q, f,
+                   ygg, ldv, R);
+}
+template <class T>
+void launch_qapply_w(const DevPatch* P, const int* plist, const int* prefix, int nlist, int total,
+                     int R, const T* Q, const double* z, double* out, int64_t ldv,
+                     hipStream_t st) {
+  if (total == 0 || R == 0) return;
+  TCF_TIMED_LAUNCH(k_qapply_w<T>, dim3(total), dim3(256), 0, st, P, plist, prefix, nlist, Q, z,
+                   out, ldv, R);
+}
+template void launch_condense_w<double>(const DevPatch*, const int*, const int*, int, int, int,
+                                        const double*, const double*, double*, int64_t,
+                                        hipStream_t);
+template void launch_condense_w<float>(const DevPatch*, const int*, const int*, int, int, int,
+                                       const float*, const double*, double*, int64_t,
+                                       hipStream_t);
+template void launch_qapply_w<double>(const DevPatch*, const int*, const int*, int, int, int,
+                                      const double*, const double*, double*, int64_t,
+                                      hipStream_t);
+template void launch_qapply_w<float>(const DevPatch*, const int*, const int*, int, int, int,
+                                     const float*, const double*, double*, int64_t, hipStream_t);
+
 void launch_jump(int n, const int* pp, const int* pm, const double* w, double scale, double* y,
                  const double* dotw, double* partial, const int* done, hipStream_t st) {
   if (n == 0) return;
@@ -1707,7 +1867,10 @@ void launch_jump(int n, const int* pp, const int* pm, const double* w, double sc
     case 1: hipLaunchKernelGGL(KERNEL<1>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
     case 2: hipLaunchKernelGGL(KERNEL<2>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
     case 3: hipLaunchKernelGGL(KERNEL<3>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
-    default: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    case 16: hipLaunchKernelGGL(KERNEL<16>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
+    default: hipLaunchKernelGGL(KERNEL<32>, GRID, dim3(256), 0, st, __VA_ARGS__); break; \
   }
 void launch_pcg_init_t(int R, int n, const double* d, double* lam, double* r, double* part_dd,
                        int npart, hipStream_t st) {
@@ -2072,14 +2235,16 @@ struct TileVec<float> {
 // Group (the operator) fixes the input mode: 0 (F apply) and 2 (Dirichlet
 // preconditioner) take the signed gather scale * gsw[i] * xv[gidx[i]] (gsw:
 // the +-1 entries of Bhat, or for a scaled preconditioner those of D Bhat),
-// 1 (Phi_b N q) the plain gather xv[gidx[i]], 3 (coarse) reads xv[i].
+// 1 (Phi_b N q) and 4 (the coarse factor's sweeps; a separate instance so
+// that profiles tell the two apart) the plain gather xv[gidx[i]], 3 (the
+// coarse top block) reads xv[i].
 template <class T, int Group, int R>
 __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
                                                const double* xv, int xld, const int* gidx,
                                                const double* gsw, double scale,
                                                double* y, int yld, const int* ymap,
                                                double* qslot, const int* done) {
-  constexpr int XM = Group == 3 ? 0 : (Group == 1 ? 2 : 1);
+  constexpr int XM = Group == 3 ? 0 : ((Group == 1 || Group == 4) ? 2 : 1);
   // Blocks are dealt to the 8 XCDs round-robin (block b on XCD b % 8); give
   // each XCD a contiguous run of jobs, so that the tiles of a patch, which
   // share inputs and outputs, stay within one L2.
@@ -2219,6 +2384,121 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   }
 }
 
+// The same tile products for many right-hand sides (5 <= R <= 32) on the
+// matrix cores: v_mfma_f64_16x16x4 with FP64 accumulation (FP32 tiles are
+// widened as they are staged), so every tile is read from HBM once per
+// apply for all R columns.  The tile goes to LDS once; the right-hand sides
+// are taken 16 at a time: both sides' inputs for those 16 columns into LDS,
+// then wave w forms the N part of rows 16w.. (D = A[16w.., :] X_c) and the
+// T part of columns 16w.. (D = A[:, 16w..]^T X_r), each as 16 k-steps of
+// 4 over the tile's 64 columns (rows).  Results go to y with FP64 atomics,
+// as in k_tiles; the quadratic form x_r^T A x_c of each column is summed
+// over the tile's rows and added to its slot.
+template <class T, int Group>
+__global__ void __launch_bounds__(256) k_tiles_w(const TileJob* jobs, const T* Mb,
+                                                 const double* xv, int xld, const int* gidx,
+                                                 const double* gsw, double scale,
+                                                 double* y, int yld, const int* ymap,
+                                                 double* qslot, const int* done, int R) {
+  typedef Mfma16<double> M;
+  constexpr int XM = Group == 3 ? 0 : ((Group == 1 || Group == 4) ? 2 : 1);
+  const int nb = gridDim.x, per = nb >> 3, rem = nb & 7;
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
+  typedef typename TileVec<T>::v VT;
+  constexpr int V = TileVec<T>::n;
+  constexpr int RPC = 64 / V;
+  constexpr int L = 64 * 64 / V / 256;
+  constexpr int CPL = 256 / RPC;
+  const TileJob jb = jobs[job];
+  if ((done ? *done : 0) | (jb.nc < 0) | (jb.m_off < 0)) return;
+  __shared__ double As[64][65];      // the tile, As[row][col]
+  __shared__ double Xs[2][64][17];   // inputs of 16 columns: [0] row side, [1] column side
+  __shared__ double Qs[4][16];       // per-wave quadratic-form partials
+  const int t = threadIdx.x;
+  const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = (jb.flags & 16) && qslot != nullptr;
+  // input gather: thread t serves side t >> 7, entry t & 63, columns of
+  // parity (t >> 6) & 1
+  const int side = t >> 7, ie = t & 63, jpar = (t >> 6) & 1;
+  const bool xon = side == 0 ? ((doT || qf) && ie < jb.nr) : (doN && ie < jb.nc);
+  const int xo = xon ? (side == 0 ? jb.xr_off : jb.xc_off) + ie : 0;
+  int gi = xo;
+  double sw = 1.0;
+  if (XM != 0) gi = gidx[xo];
+  if (XM == 1) sw = gsw[xo];
+  const double f = XM == 1 ? scale * sw : 1.0;
+  // the tile, coalesced as in k_tiles, into LDS (columns past nc as zeros)
+  const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
+  const int h = t / RPC, lr = t % RPC;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int cc = k * CPL + h;
+    const bool ok = cc < jb.nc;
+    const VT v = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
+#pragma unroll
+    for (int u = 0; u < V; ++u) As[V * lr + u][cc] = ok ? (double)v[u] : 0.0;
+  }
+  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const bool wN = doN && 16 * w < jb.nr;  // this wave's 16 rows exist
+  const bool wT = doT && 16 * w < jb.nc;  // this wave's 16 columns exist
+  const int kN = (jb.nc + 3) >> 2, kT = (jb.nr + 3) >> 2;  // k-steps that see data
+  for (int c0 = 0; c0 < R; c0 += 16) {
+    __syncthreads();  // As staged (first pass) / previous columns consumed
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int j = c0 + jpar + 2 * m;
+      const double xg = (xon && j < R) ? xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
+      Xs[side][ie][jpar + 2 * m] = f * xg;
+    }
+    __syncthreads();
+    if (wN) {
+      M::acc a4 = {0.0, 0.0, 0.0, 0.0};
+      for (int k4 = 0; k4 < kN; ++k4)
+        a4 = M::mma(As[16 * w + li][4 * k4 + lk], Xs[1][4 * k4 + lk][li], a4);
+      const int j = c0 + li;
+      double q = 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = 16 * w + M::row(lk, e);
+        if (row < jb.nr && j < R) {
+          const int yi = (jb.flags & 8) ? ymap[jb.yr_off + row] : jb.yr_off + row;
+          atomicAdd(y + (int64_t)j * yld + yi, a4[e]);
+        }
+        q += Xs[0][row][li] * a4[e];  // rows past nr carry zero inputs
+      }
+      if (qf) {
+        q = xor16_sum(q);
+        q = xor32_sum(q);
+        if (lk == 0) Qs[w][li] = q;
+      }
+    } else if (qf && lk == 0) {
+      Qs[w][li] = 0.0;
+    }
+    if (wT) {
+      M::acc a4 = {0.0, 0.0, 0.0, 0.0};
+      for (int k4 = 0; k4 < kT; ++k4)
+        a4 = M::mma(As[4 * k4 + lk][16 * w + li], Xs[0][4 * k4 + lk][li], a4);
+      const int j = c0 + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int col = 16 * w + M::row(lk, e);
+        if (col < jb.nc && j < R) {
+          const int yi = (jb.flags & 4) ? ymap[jb.yc_off + col] : jb.yc_off + col;
+          atomicAdd(y + (int64_t)j * yld + yi, a4[e]);
+        }
+      }
+    }
+    if (qf) {
+      __syncthreads();
+      if (t < 16 && c0 + t < R) {
+        const double v = (Qs[0][t] + Qs[1][t]) + (Qs[2][t] + Qs[3][t]);
+        atomicAdd(qslot + (c0 + t) * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
+                  (jb.flags & 32) ? 2.0 * v : v);
+      }
+    }
+  }
+}
+
 __global__ void k_zero(int64_t n, double* a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0;
@@ -2255,11 +2535,45 @@ static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, co
       break;
   }
 }
+template <class T, int G>
+static void launch_tiles_wide(int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
+                              int xld, const int* gidx, const double* gsgn, double scale,
+                              double* y, int yld, const int* ymap, double* qslot, const int* done,
+                              hipStream_t st) {
+  TCF_TIMED_LAUNCH((k_tiles_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx, gsgn,
+                   scale, y, yld, ymap, qslot, done, R);
+}
+
 template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
                   int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
+  if (R > 4) {  // many right-hand sides: the matrix-core form
+    switch (group) {
+      case 0:
+        launch_tiles_wide<T, 0>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
+                                qslot, done, st);
+        break;
+      case 1:
+        launch_tiles_wide<T, 1>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
+                                qslot, done, st);
+        break;
+      case 2:
+        launch_tiles_wide<T, 2>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
+                                qslot, done, st);
+        break;
+      case 3:
+        launch_tiles_wide<T, 3>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
+                                qslot, done, st);
+        break;
+      default:
+        launch_tiles_wide<T, 4>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
+                                qslot, done, st);
+        break;
+    }
+    return;
+  }
   switch (group) {
     case 0:
       launch_tiles_g<T, 0>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
@@ -2273,8 +2587,12 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
       launch_tiles_g<T, 2>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
                            done, st);
       break;
-    default:
+    case 3:
       launch_tiles_g<T, 3>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
+                           done, st);
+      break;
+    default:
+      launch_tiles_g<T, 4>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,
                            done, st);
       break;
   }

@@ -121,9 +121,12 @@ void tcf_server::run_request(Request* r) {
     } catch (const std::exception&) {
     }
   }
-  tcf_destroy(r->h);  // releases the request's device memory
+  tcf_destroy(r->h);  // gives the request's device memory back on its stream
   r->h = nullptr;
-  if (st) (void)hipStreamDestroy(st);
+  if (st) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
   std::lock_guard<std::mutex> lk(mu);
   r->stats = stats;
   r->step_ms = std::move(step_ms);
@@ -224,7 +227,7 @@ int tcf_server_submit(tcf_server* srv, const tcf_problem_desc* desc, const tcf_o
                       int32_t* req_id) {
   if (!srv || !desc || !req_id) return TCF_EINVAL;
   tcf_problem* h = nullptr;
-  int rc = tcf_create(desc, opts, &h);
+  int rc = tcf_create(desc, opts, nullptr, &h);
   if (rc != TCF_OK) return rc;
   size_t b64 = 0, b32 = 0;
   tcf_footprint(h, &b64, &b32);

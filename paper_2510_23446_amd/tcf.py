@@ -70,6 +70,33 @@ class tcf_options(C.Structure):
                 ("setup_group_mb", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class tcf_allocator(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+def torch_allocator():
+    """A tcf_allocator that takes the handle's device memory from PyTorch's
+    caching allocator (on the stream of each call) and gives it back there.
+    Returns (struct, keep-alive list); keep both for the handle's lifetime."""
+    import torch
+
+    def _alloc(ctx, nbytes, stream):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0)))
+        except RuntimeError:
+            return None
+
+    def _free(ctx, ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    return tcf_allocator(None, fa, ff), [fa, ff]
+
+
 class tcf_stats(C.Structure):
     _fields_ = [("n_patches", C.c_int64), ("n_edges", C.c_int64), ("n_kept", C.c_int64),
                 ("n_lambda", C.c_int64), ("n_primal", C.c_int64), ("n_tree_I", C.c_int64),
@@ -110,7 +137,8 @@ def lib():
     L.tcf_default_options.restype = None
     L.tcf_last_error.argtypes = [P]
     L.tcf_last_error.restype = C.c_char_p
-    L.tcf_create.argtypes = [C.POINTER(tcf_problem_desc), C.POINTER(tcf_options), C.POINTER(P)]
+    L.tcf_create.argtypes = [C.POINTER(tcf_problem_desc), C.POINTER(tcf_options),
+                             C.POINTER(tcf_allocator), C.POINTER(P)]
     L.tcf_footprint.argtypes = [P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
     L.tcf_setup.argtypes = [P, P]
     L.tcf_step.argtypes = [P, C.c_int32, P]
@@ -317,7 +345,7 @@ class Problem:
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
                  check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0,
-                 coarse_mode=0, setup_group_mb=0):
+                 coarse_mode=0, setup_group_mb=0, allocator=None):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
@@ -325,8 +353,12 @@ class Problem:
                                    setup_group_mb)
         self._desc = d
         self.opts = o
+        # allocator: None (stream-ordered HIP allocation) or a (tcf_allocator,
+        # keep-alive) pair such as torch_allocator() returns
+        self._alloc = allocator
         h = C.c_void_p()
-        rc = L.tcf_create(C.byref(d), C.byref(o), C.byref(h))
+        rc = L.tcf_create(C.byref(d), C.byref(o),
+                          C.byref(allocator[0]) if allocator is not None else None, C.byref(h))
         if rc != TCF_OK:
             raise TcfError(rc, L.tcf_last_error(None).decode())
         self.h = h

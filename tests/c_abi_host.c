@@ -52,7 +52,7 @@ int main(void) {
   tcf_options o;
   tcf_default_options(&o);
   tcf_problem* h = NULL;
-  int rc = tcf_create(&d, &o, &h);
+  int rc = tcf_create(&d, &o, NULL, &h);
   if (rc != TCF_OK) {
     printf("create failed %d: %s\n", rc, tcf_last_error(NULL));
     return 1;
@@ -72,7 +72,7 @@ int main(void) {
   /* an invalid description is rejected with a message */
   sigma[3] = -1.0;
   tcf_problem* bad = NULL;
-  rc = tcf_create(&d, &o, &bad);
+  rc = tcf_create(&d, &o, NULL, &bad);
   printf("negative_sigma %d %s\n", rc, bad == NULL ? "null" : "handle");
   tcf_destroy(h);
   return 0;

@@ -134,3 +134,65 @@ def test_condition_estimates(case):
     assert np.allclose(got, want, rtol=1e-9, atol=0)
     assert st["cond_est_patch"] == int(np.argmax(got))
     assert abs(st["cond_est_max"] - got.max()) <= 1e-12 * got.max()
+
+
+_ALLOC_CASE = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import workloads as W
+from oracle import solve
+from paper_2510_23446_amd import tcf
+
+which = sys.argv[2]
+# PyTorch's ROCm build carries its own HIP runtime: its device is brought
+# up before the library's first device call in this process
+stream = torch.cuda.Stream()
+torch.cuda.synchronize()
+prob = W.plain_fp64().with_steps(3)
+ref = solve.run(prob)
+alloc = tcf.torch_allocator() if which == "torch_caching" else None
+before = torch.cuda.memory_allocated()
+p = tcf.Problem(prob, allocator=alloc)
+p.tcf_setup(stream)
+held = p.tcf_get_stats()["device_bytes"]
+grown = torch.cuda.memory_allocated() - before
+errs = []
+for l in range(prob.n_steps):
+    p.tcf_step(1, stream)
+    a = p.tcf_get_field(0, stream=stream)
+    r = ref.fields[l][:, 0]
+    errs.append(float(np.linalg.norm(a - r) / np.linalg.norm(r)))
+p.tcf_destroy()
+torch.cuda.synchronize()
+print(json.dumps({"held": held, "grown": grown, "errs": errs,
+                  "after": torch.cuda.memory_allocated() - before}))
+"""
+
+
+@pytest.mark.parametrize("which", ["torch_caching", "stream_ordered_default"])
+def test_allocator_through_the_boundary(which):
+    """tcf_create's allocator: PyTorch's caching allocator passed through
+    ctypes (every buffer of the handle comes from torch, on the call's
+    stream, and goes back to it on destroy), or NULL (stream-ordered HIP
+    allocation).  Both give the oracle's field.  Runs in a fresh process
+    in which torch's device comes up first (its ROCm build carries its own
+    HIP runtime)."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _ALLOC_CASE, root, which], capture_output=True,
+                         text=True, timeout=600)
+    assert out.returncode == 0, out.stderr[-2000:]
+    res = json.loads(out.stdout.strip().splitlines()[-1])
+    print(f"[allocator] {which}: {res}", flush=True)
+    if which == "torch_caching":
+        assert res["grown"] >= res["held"] > 0
+    else:
+        assert res["grown"] == 0
+    assert res["after"] == 0
+    assert max(res["errs"]) <= 1e-9
