@@ -53,18 +53,26 @@ class _NoLoad:
         return getattr(self._p, name)
 
 
+def local_operator(prob, s, grid=None):
+    """Patch s's local (M, K), without its loads."""
+    pm = assemble_patch(_NoLoad(prob), grid or build_grid(prob), s)
+    return pm.M.tocsr(), pm.K.tocsr()
+
+
+def shape_representatives(prob):
+    """The key of every patch, and the first patch of each distinct key."""
+    keys = [shape_key(prob, s) for s in range(prob.n_patches)]
+    reps = {}
+    for s, k in enumerate(keys):
+        reps.setdefault(k, s)
+    return keys, reps
+
+
 def local_operators(prob, grid=None):
     """{shape key: (M_local, K_local)} and the key of every patch."""
     grid = grid or build_grid(prob)
-    bare = _NoLoad(prob)
-    ops, keys = {}, []
-    for s in range(prob.n_patches):
-        k = shape_key(prob, s)
-        keys.append(k)
-        if k not in ops:
-            pm = assemble_patch(bare, grid, s)
-            ops[k] = (pm.M.tocsr(), pm.K.tocsr())
-    return ops, keys
+    keys, reps = shape_representatives(prob)
+    return {k: local_operator(prob, s, grid) for k, s in reps.items()}, keys
 
 
 def patch_load(prob, s, ks):
