@@ -170,6 +170,10 @@ typedef struct tcf_options {
                             /* take at most this many MiB (FP64); a larger     */
                             /* patch forms a group of its own.  <= 0: 16384.   */
                             /* Bounds the setup's transient device memory      */
+  int32_t panel_chunk;      /* matrix-core path (batches of more than 4       */
+                            /* columns): a row panel of an operator is split  */
+                            /* into jobs of at most this many 64 x 64 tiles,  */
+                            /* whose partial rows add atomically.  <= 0: 16   */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,

@@ -165,6 +165,14 @@ struct tcf_problem {
                           // structure lists as b and as x positions
   double* d_cw1 = nullptr;  // one-column coarse work vector [b | y | x] (n_Pi each)
   double* d_cL = nullptr;   // per node below the top: [L_JJ^-1 | -L_JJ^-T L_SJ^T]
+  // matrix-core path (rb > 4): operators as row panels (symmetric ones whole)
+  bool wide = false;
+  void *d_pA = nullptr, *d_pB = nullptr;  // apply + Phi panels, preconditioner panels (T)
+  double* d_pC = nullptr;                 // coarse panels (FP64)
+  PanelTile* d_ptile = nullptr;           // the tiles of every panel
+  PanelJob *pj_apply = nullptr, *pj_phi = nullptr, *pj_pre = nullptr, *pj_root = nullptr,
+           *pj_cfwd = nullptr, *pj_cbwd = nullptr;
+  int n_papply = 0, n_pphi = 0, n_ppre = 0, n_proot = 0;
 
   DevPatch* dP = nullptr;
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
@@ -439,19 +447,22 @@ size_t tcf_problem::footprint(int prec) const {
   const double wf = prec == TCF_FP32_FULL_IR ? 4 : 8;  // factorisation
   double ops = (double)(G_elems + S_elems + Q_elems) * w;
   double tiles = 0.0, ctiles = 0.0;
+  // narrow batches: lower tiles of the symmetric blocks, each tile of Phi_b
+  // once; wide batches (row panels): the symmetric blocks whole, Phi_b and
+  // the coarse factor's blocks once per sweep that reads them
   for (const DevPatch& d : hp) {
     const double Tb = (d.n_b + 63) / 64, Tp = (d.n_p + 63) / 64;
-    tiles += (Tb * (Tb + 1) + Tb * Tp) * 4096.0 * w;
+    tiles += (wide ? 2 * (Tb * Tb + Tb * Tp) : Tb * (Tb + 1) + Tb * Tp) * 4096.0 * w;
   }
   double root_inv = 0.0;
   for (size_t i = 0; i < cnodes.size(); ++i) {
     const CoarseNodeDev& c = cnodes[i];
     const double Tj = (c.nj + 63) / 64, Ts = (c.ns + 63) / 64;
     if ((int)i == c_root) {
-      ctiles += Tj * (Tj + 1) / 2 * 4096.0 * 8;
+      ctiles += (wide ? Tj * Tj : Tj * (Tj + 1) / 2) * 4096.0 * 8;
       root_inv = (double)c.nj_pad * c.nj_pad * 8;
     } else {
-      ctiles += (Tj * (Tj + 1) / 2 + Tj * Ts) * 4096.0 * 8;
+      ctiles += (wide ? 2 : 1) * (Tj * (Tj + 1) / 2 + Tj * Ts) * 4096.0 * 8;
     }
   }
   const double npm = std::max(n_primal, 1);
@@ -673,6 +684,7 @@ void tcf_default_options(tcf_options* o) {
   o->precond_scaling = 0;
   o->coarse_mode = 0;
   o->setup_group_mb = 0;
+  o->panel_chunk = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -737,6 +749,7 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts,
   {
     const int want = std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 32) : 32);
     h->rb = want <= 4 ? want : (want <= 8 ? 8 : (want <= 16 ? 16 : 32));
+    h->wide = h->rb > 4;
   }
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
@@ -1840,10 +1853,224 @@ static void add_tile_twice(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
   jphi.push_back(jphi_);
 }
 
+// One tile of a row panel: the nrB x ncB block at (row0, col0) of a
+// column-major source, stored as is (trans 0: the block's ncB columns) or
+// transposed (trans 1: its nrB rows become the tile's columns).
+static void add_panel_tile(std::vector<PackJob>& pk, std::vector<PanelTile>& tl, int64_t& off,
+                           int64_t src_off, int ld, int row0, int col0, int nrB, int ncB,
+                           int trans, int xc_off) {
+  pk.push_back(PackJob{src_off, off, ld, row0, col0, nrB, ncB, trans});
+  const int nc = trans ? nrB : ncB;
+  tl.push_back(PanelTile{xc_off, nc});
+  off += 64 * (int64_t)nc;
+}
+
+// Row panels of the per-iteration operators for the matrix-core path:
+// S_bb^-1 and S_bb whole (one panel per 64 dual rows of a patch), Phi_b^T
+// (rows: the patch's primal entries) for the F apply and Phi_b for the
+// coarse correction; for the coarse solve the top block's inverse whole,
+// and per lower node L_JJ^-1 and (L_SJ L_JJ^-1) = -(-L_JJ^-T L_SJ^T)^T for
+// the forward sweep, L_JJ^-T together with -L_JJ^-T L_SJ^T for the
+// backward sweep.  Shared outputs: the coarse right-hand side (several
+// patches hold a primal unknown) and the forward sweep's updates of
+// ancestor unknowns (several nodes of one height update one ancestor).
+template <class T>
+static int build_panels(tcf_problem* h, hipStream_t st) {
+  const int npm = std::max(h->n_primal, 1);
+  std::vector<PackJob> pa, pb, pc, pl;
+  std::vector<PanelTile> tl;
+  std::vector<PanelJob> japp, jphi, jpre, jroot;
+  std::vector<std::vector<PanelJob>> fw(h->c_levels), bw(h->c_levels);
+  int64_t oa = 0, ob = 0, oc = 0;
+  auto begin = [&](int64_t off, int yr_off, int nr, int xr_off, int flags) {
+    return PanelJob{off, (int)tl.size(), 0, yr_off, nr, xr_off, flags};
+  };
+  // a panel longer than the chunk becomes several jobs of about equal
+  // length (more workgroups in flight); their partial rows add atomically
+  const int chunk = h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16;
+  auto finish = [&](std::vector<PanelJob>& v, PanelJob j) {
+    const int nt = (int)tl.size() - j.t0;
+    if (nt <= 0) return;
+    const int parts = (nt + chunk - 1) / chunk;
+    int64_t off = j.m_off;
+    for (int q = 0, t = j.t0; q < parts; ++q) {
+      const int n = nt / parts + (q < nt % parts ? 1 : 0);
+      PanelJob c = j;
+      c.m_off = off;
+      c.t0 = t;
+      c.nt = n;
+      if (parts > 1) c.flags |= 1;
+      for (int k = 0; k < n; ++k) off += 64 * (int64_t)tl[t + k].nc;
+      t += n;
+      v.push_back(c);
+    }
+  };
+  for (int s = 0; s < h->np_tot; ++s) {
+    const DevPatch& d = h->hp[s];
+    if (d.n_b == 0) continue;
+    const int Tb = (d.n_b + 63) / 64, Tp = (d.n_p + 63) / 64;
+    auto nrb = [&](int I) { return std::min(64, d.n_b - 64 * I); };
+    auto nrp = [&](int K) { return std::min(64, d.n_p - 64 * K); };
+    for (int I = 0; I < Tb; ++I) {
+      // F apply: S_bb^-1 rows (vc, with x^T S_bb^-1 x), Phi_b^T rows (cv)
+      PanelJob j = begin(oa, d.bp_off + 64 * I, nrb(I), d.b_off + 64 * I, 4);
+      for (int J = 0; J < Tb; ++J)
+        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
+                       d.b_off + 64 * J);
+      finish(japp, j);
+      // preconditioner: S_bb rows (tb, with r.z)
+      PanelJob q = begin(ob, d.b_off + 64 * I, nrb(I), d.b_off + 64 * I, 4);
+      for (int J = 0; J < Tb; ++J)
+        add_panel_tile(pb, tl, ob, d.S_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
+                       d.b_off + 64 * J);
+      finish(jpre, q);
+    }
+    for (int K = 0; K < Tp; ++K) {
+      PanelJob j = begin(oa, d.p_off + 64 * K, nrp(K), 0, 1 | 2);
+      for (int I = 0; I < Tb; ++I)
+        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 1,
+                       d.b_off + 64 * I);
+      finish(japp, j);
+    }
+    for (int I = 0; I < Tb && Tp > 0; ++I) {
+      // coarse correction vc += Phi_b N q (inputs q through the primal ranks)
+      PanelJob j = begin(oa, d.bp_off + 64 * I, nrb(I), 0, 0);
+      for (int K = 0; K < Tp; ++K)
+        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 0,
+                       d.p_off + 64 * K);
+      finish(jphi, j);
+    }
+  }
+  std::vector<int> ctab(3 * (size_t)npm);
+  std::iota(ctab.begin(), ctab.end(), 0);
+  if (h->c_root >= 0) {
+    const CoarseNodeDev& r = h->cnodes[h->c_root];
+    const int Tr = (r.nj + 63) / 64;
+    auto nrr = [&](int I) { return std::min(64, r.nj - 64 * I); };
+    for (int I = 0; I < Tr; ++I) {
+      PanelJob j = begin(oc, r.j0 + 64 * I, nrr(I), r.j0 + 64 * I, 4);
+      for (int J = 0; J < Tr; ++J)
+        add_panel_tile(pc, tl, oc, 0, r.nj_pad, 64 * I, 64 * J, nrr(I), nrr(J), 0, r.j0 + 64 * J);
+      finish(jroot, j);
+    }
+    int stot = 0;
+    for (const CoarseNodeDev& c : h->cnodes) stot += c.ns;
+    const int sb0 = 3 * npm, sx0 = 3 * npm + stot;
+    ctab.resize((size_t)sx0 + stot);
+    for (size_t i = 0; i < h->cnodes.size(); ++i) {
+      const CoarseNodeDev& c = h->cnodes[i];
+      const std::vector<int>& S = h->cplan.nodes[i].S;
+      for (int a = 0; a < c.ns; ++a) {
+        ctab[sb0 + c.s_off + a] = S[a];
+        ctab[sx0 + c.s_off + a] = 2 * npm + S[a];
+      }
+      if ((int)i == h->c_root) continue;
+      const int lv = h->cplan.nodes[i].height;
+      const int Tj = (c.nj + 63) / 64, Ts = (c.ns + 63) / 64;
+      auto nrj = [&](int I) { return std::min(64, c.nj - 64 * I); };
+      auto nrs = [&](int a) { return std::min(64, c.ns - 64 * a); };
+      const int64_t mt = c.l_off + (int64_t)c.nj * c.nj_pad;  // -L_JJ^-T L_SJ^T, ld nj_pad
+      for (int I = 0; I < Tj; ++I) {
+        // forward: y_J = L_JJ^-1 b_J (into the y part)
+        PanelJob j = begin(oc, npm + c.j0 + 64 * I, nrj(I), 0, 0);
+        for (int K = 0; K <= I; ++K)
+          add_panel_tile(pl, tl, oc, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 0,
+                         c.j0 + 64 * K);
+        finish(fw[lv], j);
+      }
+      for (int a = 0; a < Ts; ++a) {
+        // forward: b_S -= L_SJ L_JJ^-1 b_J (shared with the other nodes)
+        PanelJob j = begin(oc, sb0 + c.s_off + 64 * a, nrs(a), 0, 1 | 2);
+        for (int K = 0; K < Tj; ++K)
+          add_panel_tile(pl, tl, oc, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 1,
+                         c.j0 + 64 * K);
+        finish(fw[lv], j);
+      }
+      for (int K = 0; K < Tj; ++K) {
+        // backward: x_J = L_JJ^-T y_J - L_JJ^-T L_SJ^T x_S
+        PanelJob j = begin(oc, 2 * npm + c.j0 + 64 * K, nrj(K), 0, 0);
+        for (int I = K; I < Tj; ++I)
+          add_panel_tile(pl, tl, oc, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 1,
+                         npm + c.j0 + 64 * I);
+        for (int a = 0; a < Ts; ++a)
+          add_panel_tile(pl, tl, oc, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 0,
+                         sx0 + c.s_off + 64 * a);
+        finish(bw[lv], j);
+      }
+    }
+  }
+  // the pack jobs of one buffer refer to it from offset 0
+  T *pA, *pB;
+  RCCHK(h->alloc(&pA, (size_t)std::max<int64_t>(oa, 1)));
+  RCCHK(h->alloc(&pB, (size_t)std::max<int64_t>(ob, 1)));
+  RCCHK(h->alloc(&h->d_pC, (size_t)std::max<int64_t>(oc, 1)));
+  h->d_pA = pA;
+  h->d_pB = pB;
+  PackJob *dpa, *dpb, *dpc, *dpl;
+  RCCHK(h->upload(&dpa, pa));
+  RCCHK(h->upload(&dpb, pb));
+  RCCHK(h->upload(&dpc, pc));
+  RCCHK(h->upload(&dpl, pl));
+  launch_pack_tiles<T, T>(dpa, (int)pa.size(), (const T*)h->d_G, pA, st);
+  launch_pack_tiles<T, T>(dpb, (int)pb.size(), (const T*)h->d_S, pB, st);
+  if (!pc.empty()) launch_pack_tiles<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_pC, st);
+  if (!pl.empty()) launch_pack_tiles<double, double>(dpl, (int)pl.size(), h->d_cL, h->d_pC, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  for (PackJob* b : {dpa, dpb, dpc, dpl}) h->release(b);
+  if (h->d_SPinv) h->release(h->d_SPinv);
+  if (h->d_cL) h->release(h->d_cL);
+  h->d_SPinv = nullptr;
+  h->d_cL = nullptr;
+  std::vector<PanelJob> f, b;
+  h->c_fwd_pre.assign(1, 0);
+  h->c_bwd_pre.assign(1, 0);
+  for (int lv = 0; lv < h->c_levels; ++lv) {
+    f.insert(f.end(), fw[lv].begin(), fw[lv].end());
+    b.insert(b.end(), bw[lv].begin(), bw[lv].end());
+    h->c_fwd_pre.push_back((int)f.size());
+    h->c_bwd_pre.push_back((int)b.size());
+  }
+  RCCHK(h->upload(&h->d_ptile, tl));
+  RCCHK(h->upload(&h->pj_apply, japp));
+  RCCHK(h->upload(&h->pj_phi, jphi));
+  RCCHK(h->upload(&h->pj_pre, jpre));
+  RCCHK(h->upload(&h->pj_root, jroot));
+  RCCHK(h->upload(&h->pj_cfwd, f));
+  RCCHK(h->upload(&h->pj_cbwd, b));
+  RCCHK(h->upload(&h->d_cT, ctab));
+  RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm));
+  h->n_papply = (int)japp.size();
+  h->n_pphi = (int)jphi.size();
+  h->n_ppre = (int)jpre.size();
+  h->n_proot = (int)jroot.size();
+  return TCF_OK;
+}
+
 // Tile copies of the per-iteration operators: lower tiles of S_bb^-1 (with
 // the Phi_b tiles), of S_bb and of S_Pi^-1, plus the job lists.
 template <class T>
+static int build_tiles_narrow(tcf_problem* h, hipStream_t st);
+
+template <class T>
 static int build_tiles(tcf_problem* h, hipStream_t st) {
+  RCCHK(h->wide ? build_panels<T>(h, st) : build_tiles_narrow<T>(h, st));
+  const int npm = std::max(h->n_primal, 1);
+  // c = Phi_b^T x goes straight into the coarse vector: cv = sum_s N_s^T c_s
+  std::vector<int> cmap((size_t)std::max<int64_t>(h->n_ptot, 1), 0);
+  for (int s = 0; s < h->np_tot; ++s)
+    for (int j = 0; j < h->hp[s].n_p; ++j)
+      cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->cplan.nd[h->plans[s].p_rank[j]];
+  RCCHK(h->upload(&h->d_cmap, cmap));
+  // per column j of rb: [vc | cv = b | y | x = q] (stride n_bptot + 3 n_Pi),
+  // then p.Fp slots, tb, r.z slots, each block rb columns wide
+  h->n_acc = (int64_t)h->rb * (h->n_bptot + 3 * npm + 2 * TCF_QSLOTS + h->n_btot);
+  RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
+  return TCF_OK;
+}
+
+template <class T>
+static int build_tiles_narrow(tcf_problem* h, hipStream_t st) {
   std::vector<PackJob> pa, pb, pc;
   std::vector<TileJob> ja, jphi, jpre, jc;
   int64_t oa = 0, ob = 0, oc = 0;
@@ -1975,16 +2202,6 @@ static int build_tiles(tcf_problem* h, hipStream_t st) {
   h->n_tphi = (int)jphi.size();
   h->n_tpre = (int)jpre.size();
   h->n_tcoarse = (int)jc.size();
-  // c = Phi_b^T x goes straight into the coarse vector: cv = sum_s N_s^T c_s
-  std::vector<int> cmap((size_t)std::max<int64_t>(h->n_ptot, 1), 0);
-  for (int s = 0; s < h->np_tot; ++s)
-    for (int j = 0; j < h->hp[s].n_p; ++j)
-      cmap[h->hp[s].p_off + j] = (int)h->n_bptot + h->cplan.nd[h->plans[s].p_rank[j]];
-  RCCHK(h->upload(&h->d_cmap, cmap));
-  // per column j of rb: [vc | cv = b | y | x = q] (stride n_bptot + 3 n_Pi),
-  // then p.Fp slots, tb, r.z slots, each block rb columns wide
-  h->n_acc = (int64_t)h->rb * (h->n_bptot + 3 * npm + 2 * TCF_QSLOTS + h->n_btot);
-  RCCHK(h->alloc(&h->d_acc, (size_t)h->n_acc));
   return TCF_OK;
 }
 
@@ -2045,24 +2262,37 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
     if (slots) ::timed(h, g, s, f);
     else f();
   };
+  const bool wide = h->wide;
   for (int lv = 0; lv < h->c_levels; ++lv) {
     const int j0 = h->c_fwd_pre[lv], nj = h->c_fwd_pre[lv + 1] - j0;
     timed(TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(4, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
-                           base, ld, h->d_cT, nullptr, done, st);
+      if (wide)
+        launch_panels<double>(4, R, h->pj_cfwd + j0, h->d_ptile, nj, h->d_pC, base, ld, h->d_cT,
+                              nullptr, 1.0, base, ld, h->d_cT, nullptr, done, st);
+      else
+        launch_tiles<double>(4, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+                             base, ld, h->d_cT, nullptr, done, st);
     });
   }
   const CoarseNodeDev& r = h->cnodes[h->c_root];
   if (slots && r.j0 > 0) launch_sumsq_slots(R, r.j0, base + npm, ld, slots, done, st);
   timed(TCF_KG_COARSE, st, [&] {
-    launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, base, ld, nullptr, nullptr,
-                         1.0, base + 2 * npm, ld, nullptr, slots, done, st);
+    if (wide)
+      launch_panels<double>(3, R, h->pj_root, h->d_ptile, h->n_proot, h->d_pC, base, ld, nullptr,
+                            nullptr, 1.0, base + 2 * npm, ld, nullptr, slots, done, st);
+    else
+      launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, base, ld, nullptr, nullptr,
+                           1.0, base + 2 * npm, ld, nullptr, slots, done, st);
   });
   for (int lv = h->c_levels - 1; lv >= 0; --lv) {
     const int j0 = h->c_bwd_pre[lv], nj = h->c_bwd_pre[lv + 1] - j0;
     timed(TCF_KG_COARSE, st, [&] {
-      launch_tiles<double>(4, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
-                           base, ld, h->d_cT, nullptr, done, st);
+      if (wide)
+        launch_panels<double>(4, R, h->pj_cbwd + j0, h->d_ptile, nj, h->d_pC, base, ld, h->d_cT,
+                              nullptr, 1.0, base, ld, h->d_cT, nullptr, done, st);
+      else
+        launch_tiles<double>(4, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
+                             base, ld, h->d_cT, nullptr, done, st);
     });
   }
 }
@@ -2107,6 +2337,41 @@ static TileAcc tile_acc(tcf_problem* h) {
   return a;
 }
 
+// The F apply, the coarse correction (Phi_b N q) and the preconditioner on
+// R columns, through the tiles or (wide batches) the row panels.
+template <class T>
+static void op_apply(tcf_problem* h, const TileAcc& a, const double* x, const int* done,
+                     hipStream_t st) {
+  const int R = h->rb, nl = h->n_lambda;
+  if (h->wide)
+    launch_panels<T>(0, R, h->pj_apply, h->d_ptile, h->n_papply, (const T*)h->d_pA, x, nl,
+                     h->d_brow, h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+  else
+    launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, x, nl, h->d_brow,
+                    h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+}
+template <class T>
+static void op_phi(tcf_problem* h, const TileAcc& a, const int* done, hipStream_t st) {
+  const int R = h->rb;
+  if (h->wide)
+    launch_panels<T>(1, R, h->pj_phi, h->d_ptile, h->n_pphi, (const T*)h->d_pA, a.q, a.lf,
+                     h->d_prank, nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, done, st);
+  else
+    launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
+                    nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, done, st);
+}
+template <class T>
+static void op_precond(tcf_problem* h, const TileAcc& a, const double* r, const int* done,
+                       hipStream_t st) {
+  const int R = h->rb, nl = h->n_lambda;
+  if (h->wide)
+    launch_panels<T>(2, R, h->pj_pre, h->d_ptile, h->n_ppre, (const T*)h->d_pB, r, nl,
+                     h->d_brow, h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, done, st);
+  else
+    launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, r, nl, h->d_brow,
+                    h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, done, st);
+}
+
 // One PCG iteration with the given parity (launch sequence only).
 template <class T>
 static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
@@ -2124,23 +2389,14 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
     const int* alldone = &h->d_st[R].done;
     double* p_rr = h->d_part;
     const double tol2 = h->pcg_tol * h->pcg_tol;
-    timed(h, TCF_KG_APPLY, st, [&] {
-      launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_p, nl, h->d_brow,
-                      h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, alldone, st);
-    });
+    timed(h, TCF_KG_APPLY, st, [&] { op_apply<T>(h, a, h->d_p, alldone, st); });
     if (h->n_primal > 0) {
       coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, alldone, st);
-      timed(h, TCF_KG_PHI, st, [&] {
-        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
-                        nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, alldone, st);
-      });
+      timed(h, TCF_KG_PHI, st, [&] { op_phi<T>(h, a, alldone, st); });
     }
     launch_pcg_update_t(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, a.pq, stv, par,
                         h->d_lam, h->d_r, h->d_p, p_rr, npt, a.tb, a.n_tail, st);
-    timed(h, TCF_KG_PRECOND, st, [&] {
-      launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
-                      h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, alldone, st);
-    });
+    timed(h, TCF_KG_PRECOND, st, [&] { op_precond<T>(h, a, h->d_r, alldone, st); });
     launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                          a.rz, p_rr, npt, stv, par, tol2, h->d_p, a.vc, a.n_head, st);
   }
@@ -2194,12 +2450,10 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     launch_zero(h->n_acc, h->d_acc, st);
     if (h->warm_init) {
       // r0 = d - F lambda0: one F apply on the lambda columns as set
-      launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, h->d_lam, nl, h->d_brow,
-                      h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, nullptr, st);
+      op_apply<T>(h, a, h->d_lam, nullptr, st);
       if (h->n_primal > 0) {
         coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, nullptr, st);
-        launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
-                        nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, nullptr, st);
+        op_phi<T>(h, a, nullptr, st);
       }
       launch_pcg_init_w(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, h->d_d, h->d_r,
                         p_dd, npt, st);
@@ -2208,8 +2462,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     } else {
       launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
     }
-    launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, h->d_r, nl, h->d_brow,
-                    h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, nullptr, st);
+    op_precond<T>(h, a, h->d_r, nullptr, st);
     launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                        a.rz, p_dd, npt, h->d_st, h->d_p, st);
   }

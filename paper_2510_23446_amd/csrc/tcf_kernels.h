@@ -136,6 +136,13 @@ template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
                   int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st);
+// Row panels on the matrix cores (5 <= R <= 32 right-hand sides); groups
+// and inputs as launch_tiles.
+template <class T>
+void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
+                   const T* M, const double* xv, int xld, const int* gidx, const double* gsgn,
+                   double scale, double* y, int yld, const int* ymap, double* qslot,
+                   const int* done, hipStream_t st);
 template <class T>
 void launch_bdiag(const DevPatch* P, int np, const T* A, double* out, hipStream_t st);
 // Tile-path PCG on R (1..4) right-hand sides, column-major vectors; st[R].done

@@ -2499,6 +2499,135 @@ __global__ void __launch_bounds__(256) k_tiles_w(const TileJob* jobs, const T* M
   }
 }
 
+// Row panels on the matrix cores, for batches of 5..32 right-hand sides.
+// One block per panel: wave w owns rows 16w .. 16w + 15 of the panel for all
+// R columns (two 16-wide v_mfma_f64_16x16x4 accumulators), and the panel's
+// tiles stream through LDS one after the other with their column inputs, so
+// each output row is formed completely in one block: written once (added to
+// what the vector holds), with atomics only where another panel shares the
+// row (an operator that adds into a vector other panels also add into).
+// The symmetric operators are stored whole for this path, so no tile is
+// applied transposed.  Inputs as in k_tiles (Group fixes the gather mode).
+template <class T, int Group>
+__global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const PanelTile* tiles,
+                                                 const T* Mb, const double* xv, int xld,
+                                                 const int* gidx, const double* gsw, double scale,
+                                                 double* y, int yld, const int* ymap,
+                                                 double* qslot, const int* done, int R) {
+  typedef Mfma16<double> M;
+  constexpr int XM = Group == 3 ? 0 : ((Group == 1 || Group == 4) ? 2 : 1);
+  const int nbk = gridDim.x, per = nbk >> 3, rem = nbk & 7;
+  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
+  const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
+  typedef typename TileVec<T>::v VT;
+  constexpr int V = TileVec<T>::n;
+  constexpr int RPC = 64 / V;
+  constexpr int L = 64 * 64 / V / 256;
+  constexpr int CPL = 256 / RPC;
+  const PanelJob jb = jobs[job];
+  if ((done ? *done : 0) | (jb.nt < 0) | (jb.m_off < 0)) return;
+  __shared__ double As[64][65];
+  __shared__ double Xs[64][33];
+  __shared__ double Qs[4][32];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int h = t / RPC, lr = t % RPC;
+  // input staging: thread t serves entry t & 63, columns (t >> 6) + 4 m
+  const int ie = t & 63, jq = t >> 6;
+  M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+  // registers hold the next tile (matrix chunk and gathered inputs) while the
+  // matrix cores work on the current one from the LDS
+  VT raw[L];
+  double xg[8];
+  const PanelTile* tp = tiles + jb.t0;
+  auto fetch = [&](const PanelTile& tl, int64_t off) {
+    const VT* base = reinterpret_cast<const VT*>(Mb + off);
+    const bool xon = ie < tl.nc;
+    const int xo = xon ? tl.xc_off + ie : 0;
+    int gi = xo;
+    double f = 1.0;
+    if (XM != 0) gi = gidx[xo];
+    if (XM == 1) f = scale * gsw[xo];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const bool ok = k * CPL + h < tl.nc;
+      raw[k] = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int j = jq + 4 * m;
+      xg[m] = (xon && j < R) ? f * xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
+    }
+  };
+  PanelTile tl = tp[0];
+  int64_t off = jb.m_off;
+  fetch(tl, off);
+  for (int it = 0; it < jb.nt; ++it) {
+    const int nc = tl.nc;
+    __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const int cc = k * CPL + h;
+      const bool ok = cc < nc;
+#pragma unroll
+      for (int u = 0; u < V; ++u) As[V * lr + u][cc] = ok ? (double)raw[k][u] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) Xs[ie][jq + 4 * m] = xg[m];
+    __syncthreads();
+    off += 64 * (int64_t)nc;
+    if (it + 1 < jb.nt) {
+      tl = tp[it + 1];
+      fetch(tl, off);
+    }
+    const int kN = (nc + 3) >> 2;
+    for (int k4 = 0; k4 < kN; ++k4) {
+      const double a = As[16 * w + li][4 * k4 + lk];
+      a0 = M::mma(a, Xs[4 * k4 + lk][li], a0);
+      if (R > 16) a1 = M::mma(a, Xs[4 * k4 + lk][16 + li], a1);
+    }
+  }
+  // outputs: lane (li, lk), element e is row 16 w + row(lk, e), column li (+16)
+  const bool shared = jb.flags & 1, mapped = jb.flags & 2, qf = (jb.flags & 4) && qslot;
+  double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = 16 * w + M::row(lk, e);
+    if (row >= jb.nr) continue;
+    const int yi = mapped ? ymap[jb.yr_off + row] : jb.yr_off + row;
+    double xr = 1.0;
+    int gr = jb.xr_off + row;
+    if (qf) {
+      if (XM != 0) gr = gidx[jb.xr_off + row];
+      if (XM == 1) xr = scale * gsw[jb.xr_off + row];
+    }
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int j = 16 * hh + li;
+      if (j >= R) continue;
+      const double v = hh ? a1[e] : a0[e];
+      double* dst = y + (int64_t)j * yld + yi;
+      if (shared) atomicAdd(dst, v);
+      else *dst += v;
+      if (qf) {
+        const double xv_r = xr * xv[(size_t)j * (unsigned)xld + (unsigned)gr];
+        if (hh) q1 += xv_r * v; else q0 += xv_r * v;
+      }
+    }
+  }
+  if (qf) {
+    q0 = xor32_sum(xor16_sum(q0));
+    q1 = xor32_sum(xor16_sum(q1));
+    if (lk == 0) {
+      Qs[w][li] = q0;
+      Qs[w][16 + li] = q1;
+    }
+    __syncthreads();
+    if (t < 32 && t < R)
+      atomicAdd(qslot + t * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
+                (Qs[0][t] + Qs[1][t]) + (Qs[2][t] + Qs[3][t]));
+  }
+}
+
 __global__ void k_zero(int64_t n, double* a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0;
@@ -2543,6 +2672,37 @@ static void launch_tiles_wide(int R, const TileJob* jobs, int njobs, const T* M,
   TCF_TIMED_LAUNCH((k_tiles_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx, gsgn,
                    scale, y, yld, ymap, qslot, done, R);
 }
+
+template <class T>
+void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
+                   const T* M, const double* xv, int xld, const int* gidx, const double* gsgn,
+                   double scale, double* y, int yld, const int* ymap, double* qslot,
+                   const int* done, hipStream_t st) {
+  if (njobs == 0) return;
+#define TCF_PANEL_CASE(G)                                                                       \
+  case G:                                                                                       \
+    TCF_TIMED_LAUNCH((k_panel_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld, \
+                     gidx, gsgn, scale, y, yld, ymap, qslot, done, R);                          \
+    break;
+  switch (group) {
+    TCF_PANEL_CASE(0)
+    TCF_PANEL_CASE(1)
+    TCF_PANEL_CASE(2)
+    TCF_PANEL_CASE(3)
+    default:
+      TCF_TIMED_LAUNCH((k_panel_w<T, 4>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld,
+                       gidx, gsgn, scale, y, yld, ymap, qslot, done, R);
+      break;
+  }
+#undef TCF_PANEL_CASE
+}
+template void launch_panels<double>(int, int, const PanelJob*, const PanelTile*, int,
+                                    const double*, const double*, int, const int*,
+                                    const double*, double, double*, int, const int*, double*,
+                                    const int*, hipStream_t);
+template void launch_panels<float>(int, int, const PanelJob*, const PanelTile*, int, const float*,
+                                   const double*, int, const int*, const double*, double, double*,
+                                   int, const int*, double*, const int*, hipStream_t);
 
 template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,

@@ -67,7 +67,7 @@ class tcf_options(C.Structure):
                 ("ir_rtol", C.c_double), ("ir_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32),
                 ("precond_scaling", C.c_int32), ("coarse_mode", C.c_int32),
-                ("setup_group_mb", C.c_int32)]
+                ("setup_group_mb", C.c_int32), ("panel_chunk", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -196,7 +196,7 @@ def default_options(**kw) -> tcf_options:
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
             use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0, coarse_mode=0,
-            setup_group_mb=0):
+            setup_group_mb=0, panel_chunk=0):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -261,7 +261,8 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         pcg_maxit=int(pcg_maxit), ir_rtol=float(ir_rtol if ir_rtol is not None else prob.ir_rtol),
         check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch),
         pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling),
-        coarse_mode=int(coarse_mode), setup_group_mb=int(setup_group_mb))
+        coarse_mode=int(coarse_mode), setup_group_mb=int(setup_group_mb),
+        panel_chunk=int(panel_chunk))
     return d, o, keep
 
 
@@ -345,12 +346,12 @@ class Problem:
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
                  check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0,
-                 coarse_mode=0, setup_group_mb=0, allocator=None):
+                 coarse_mode=0, setup_group_mb=0, allocator=None, panel_chunk=0):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
                                    use_graph, rhs_batch, pcg_warm, precond_scaling, coarse_mode,
-                                   setup_group_mb)
+                                   setup_group_mb, panel_chunk)
         self._desc = d
         self.opts = o
         # allocator: None (stream-ordered HIP allocation) or a (tcf_allocator,
