@@ -170,6 +170,7 @@ struct tcf_problem {
   void *d_pA = nullptr, *d_pB = nullptr;  // apply + Phi panels, preconditioner panels (T)
   double* d_pC = nullptr;                 // coarse panels (FP64)
   PanelTile* d_ptile = nullptr;           // the tiles of every panel
+  double* d_xg = nullptr;                 // gathered panel inputs, max(n_b, n_p) x rb
   PanelJob *pj_apply = nullptr, *pj_phi = nullptr, *pj_pre = nullptr, *pj_root = nullptr,
            *pj_cfwd = nullptr, *pj_cbwd = nullptr;
   int n_papply = 0, n_pphi = 0, n_ppre = 0, n_proot = 0;
@@ -469,6 +470,7 @@ size_t tcf_problem::footprint(int prec) const {
   double vec = (double)n_rtot * n_rhs * 8 * 6 + (double)n_rtot * rb * 8 * 4;
   vec += ((double)n_bptot * 16 + (double)n_btot * 16 + (double)n_lambda * 8 * 8) * rb;
   vec += (double)rb * (n_bptot + 3 * npm + n_btot + 2 * TCF_QSLOTS) * 8 + npm * 8 * (4 + rb);
+  if (wide) vec += (double)std::max(n_btot, n_ptot) * rb * 8;  // gathered panel inputs
   vec += (double)(tab_elems + ptab_elems) * 8 + (double)n_rtot * 24 + (double)n_loctot * 4;
   vec += (double)g.n_edges() * 8 + (double)n_rtot * 8;  // field, copy maps
   if (ainit && !cond_list.empty()) vec += (double)n_rtot * n_rhs * 8;  // initial load
@@ -2040,6 +2042,7 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   RCCHK(h->upload(&h->pj_cbwd, b));
   RCCHK(h->upload(&h->d_cT, ctab));
   RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm));
+  RCCHK(h->alloc(&h->d_xg, (size_t)std::max<int64_t>(std::max(h->n_btot, h->n_ptot), 1) * h->rb));
   h->n_papply = (int)japp.size();
   h->n_pphi = (int)jphi.size();
   h->n_ppre = (int)jpre.size();
@@ -2268,7 +2271,7 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
     timed(TCF_KG_COARSE, st, [&] {
       if (wide)
         launch_panels<double>(4, R, h->pj_cfwd + j0, h->d_ptile, nj, h->d_pC, base, ld, h->d_cT,
-                              nullptr, 1.0, base, ld, h->d_cT, nullptr, done, st);
+                              base, ld, h->d_cT, nullptr, done, st);
       else
         launch_tiles<double>(4, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
                              base, ld, h->d_cT, nullptr, done, st);
@@ -2279,7 +2282,7 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
   timed(TCF_KG_COARSE, st, [&] {
     if (wide)
       launch_panels<double>(3, R, h->pj_root, h->d_ptile, h->n_proot, h->d_pC, base, ld, nullptr,
-                            nullptr, 1.0, base + 2 * npm, ld, nullptr, slots, done, st);
+                            base + 2 * npm, ld, nullptr, slots, done, st);
     else
       launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, base, ld, nullptr, nullptr,
                            1.0, base + 2 * npm, ld, nullptr, slots, done, st);
@@ -2289,7 +2292,7 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
     timed(TCF_KG_COARSE, st, [&] {
       if (wide)
         launch_panels<double>(4, R, h->pj_cbwd + j0, h->d_ptile, nj, h->d_pC, base, ld, h->d_cT,
-                              nullptr, 1.0, base, ld, h->d_cT, nullptr, done, st);
+                              base, ld, h->d_cT, nullptr, done, st);
       else
         launch_tiles<double>(4, R, h->tj_cbwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
                              base, ld, h->d_cT, nullptr, done, st);
@@ -2338,38 +2341,63 @@ static TileAcc tile_acc(tcf_problem* h) {
 }
 
 // The F apply, the coarse correction (Phi_b N q) and the preconditioner on
-// R columns, through the tiles or (wide batches) the row panels.
-template <class T>
-static void op_apply(tcf_problem* h, const TileAcc& a, const double* x, const int* done,
-                     hipStream_t st) {
-  const int R = h->rb, nl = h->n_lambda;
-  if (h->wide)
-    launch_panels<T>(0, R, h->pj_apply, h->d_ptile, h->n_papply, (const T*)h->d_pA, x, nl,
-                     h->d_brow, h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, done, st);
-  else
-    launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, x, nl, h->d_brow,
-                    h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+// R columns, through the tiles or (wide batches) the row panels, whose
+// inputs are gathered first into d_xg.  tm: time the product as its kernel
+// group.
+template <class F>
+static void maybe_timed(tcf_problem* h, bool tm, int g, hipStream_t st, F&& f) {
+  if (tm) timed(h, g, st, f);
+  else f();
 }
 template <class T>
-static void op_phi(tcf_problem* h, const TileAcc& a, const int* done, hipStream_t st) {
-  const int R = h->rb;
-  if (h->wide)
-    launch_panels<T>(1, R, h->pj_phi, h->d_ptile, h->n_pphi, (const T*)h->d_pA, a.q, a.lf,
-                     h->d_prank, nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, done, st);
-  else
-    launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
-                    nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, done, st);
+static void op_apply(tcf_problem* h, const TileAcc& a, const double* x, const int* done,
+                     hipStream_t st, bool tm) {
+  const int R = h->rb, nl = h->n_lambda, nb = (int)h->n_btot;
+  if (h->wide) {
+    launch_gather_cols(R, nb, h->d_brow, h->d_bsgn_d, h->dt, x, nl, h->d_xg, nb, done, st);
+    maybe_timed(h, tm, TCF_KG_APPLY, st, [&] {
+      launch_panels<T>(0, R, h->pj_apply, h->d_ptile, h->n_papply, (const T*)h->d_pA, h->d_xg,
+                       nb, nullptr, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+    });
+  } else {
+    maybe_timed(h, tm, TCF_KG_APPLY, st, [&] {
+      launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, x, nl, h->d_brow,
+                      h->d_bsgn_d, h->dt, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+    });
+  }
+}
+template <class T>
+static void op_phi(tcf_problem* h, const TileAcc& a, const int* done, hipStream_t st, bool tm) {
+  const int R = h->rb, np = (int)h->n_ptot;
+  if (h->wide) {
+    launch_gather_cols(R, np, h->d_prank, nullptr, 1.0, a.q, a.lf, h->d_xg, np, done, st);
+    maybe_timed(h, tm, TCF_KG_PHI, st, [&] {
+      launch_panels<T>(1, R, h->pj_phi, h->d_ptile, h->n_pphi, (const T*)h->d_pA, h->d_xg, np,
+                       nullptr, a.vc, a.lf, nullptr, nullptr, done, st);
+    });
+  } else {
+    maybe_timed(h, tm, TCF_KG_PHI, st, [&] {
+      launch_tiles<T>(1, R, h->tj_phi, h->n_tphi, (const T*)h->d_tA, a.q, a.lf, h->d_prank,
+                      nullptr, 1.0, a.vc, a.lf, nullptr, nullptr, done, st);
+    });
+  }
 }
 template <class T>
 static void op_precond(tcf_problem* h, const TileAcc& a, const double* r, const int* done,
-                       hipStream_t st) {
-  const int R = h->rb, nl = h->n_lambda;
-  if (h->wide)
-    launch_panels<T>(2, R, h->pj_pre, h->d_ptile, h->n_ppre, (const T*)h->d_pB, r, nl,
-                     h->d_brow, h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, done, st);
-  else
-    launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, r, nl, h->d_brow,
-                    h->d_pre_w, 1.0, a.tb, (int)h->n_btot, nullptr, a.rz, done, st);
+                       hipStream_t st, bool tm) {
+  const int R = h->rb, nl = h->n_lambda, nb = (int)h->n_btot;
+  if (h->wide) {
+    launch_gather_cols(R, nb, h->d_brow, h->d_pre_w, 1.0, r, nl, h->d_xg, nb, done, st);
+    maybe_timed(h, tm, TCF_KG_PRECOND, st, [&] {
+      launch_panels<T>(2, R, h->pj_pre, h->d_ptile, h->n_ppre, (const T*)h->d_pB, h->d_xg, nb,
+                       nullptr, a.tb, nb, nullptr, a.rz, done, st);
+    });
+  } else {
+    maybe_timed(h, tm, TCF_KG_PRECOND, st, [&] {
+      launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, r, nl, h->d_brow,
+                      h->d_pre_w, 1.0, a.tb, nb, nullptr, a.rz, done, st);
+    });
+  }
 }
 
 // One PCG iteration with the given parity (launch sequence only).
@@ -2389,14 +2417,14 @@ static void pcg_iteration(tcf_problem* h, int par, hipStream_t st) {
     const int* alldone = &h->d_st[R].done;
     double* p_rr = h->d_part;
     const double tol2 = h->pcg_tol * h->pcg_tol;
-    timed(h, TCF_KG_APPLY, st, [&] { op_apply<T>(h, a, h->d_p, alldone, st); });
+    op_apply<T>(h, a, h->d_p, alldone, st, true);
     if (h->n_primal > 0) {
       coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, alldone, st);
-      timed(h, TCF_KG_PHI, st, [&] { op_phi<T>(h, a, alldone, st); });
+      op_phi<T>(h, a, alldone, st, true);
     }
     launch_pcg_update_t(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, a.pq, stv, par,
                         h->d_lam, h->d_r, h->d_p, p_rr, npt, a.tb, a.n_tail, st);
-    timed(h, TCF_KG_PRECOND, st, [&] { op_precond<T>(h, a, h->d_r, alldone, st); });
+    op_precond<T>(h, a, h->d_r, alldone, st, true);
     launch_pcg_pupdate_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                          a.rz, p_rr, npt, stv, par, tol2, h->d_p, a.vc, a.n_head, st);
   }
@@ -2450,10 +2478,10 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     launch_zero(h->n_acc, h->d_acc, st);
     if (h->warm_init) {
       // r0 = d - F lambda0: one F apply on the lambda columns as set
-      op_apply<T>(h, a, h->d_lam, nullptr, st);
+      op_apply<T>(h, a, h->d_lam, nullptr, st, false);
       if (h->n_primal > 0) {
         coarse_sweeps(h, R, a.vc + h->n_bptot, a.lf, a.pq, nullptr, st);
-        op_phi<T>(h, a, nullptr, st);
+        op_phi<T>(h, a, nullptr, st, false);
       }
       launch_pcg_init_w(R, nl, h->d_posp_bp, h->d_posm_bp, a.vc, a.lf, h->dt, h->d_d, h->d_r,
                         p_dd, npt, st);
@@ -2462,7 +2490,7 @@ static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
     } else {
       launch_pcg_init_t(R, nl, h->d_d, h->d_lam, h->d_r, p_dd, npt, st);
     }
-    op_precond<T>(h, a, h->d_r, nullptr, st);
+    op_precond<T>(h, a, h->d_r, nullptr, st, false);
     launch_pcg_init2_t(R, nl, h->d_posp, h->d_posm, a.tb, (int)h->n_btot, h->d_zwp, h->d_zwm,
                        a.rz, p_dd, npt, h->d_st, h->d_p, st);
   }

@@ -136,13 +136,16 @@ template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
                   int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st);
-// Row panels on the matrix cores (5 <= R <= 32 right-hand sides); groups
-// and inputs as launch_tiles.
+// Row panels on the matrix cores (R <= 32 right-hand sides): group names
+// the operator as for launch_tiles; groups 0 to 3 read their inputs
+// directly, xv[j * xld + i] (gathered beforehand by launch_gather_cols),
+// group 4 (the coarse factor's sweeps) through gidx.  A job owns its
+// output rows (y[j * yld + i] += v) unless its flags mark them shared
+// (atomic adds); outputs are mapped through ymap where its flags say so.
 template <class T>
 void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
-                   const T* M, const double* xv, int xld, const int* gidx, const double* gsgn,
-                   double scale, double* y, int yld, const int* ymap, double* qslot,
-                   const int* done, hipStream_t st);
+                   const T* M, const double* xv, int xld, const int* gidx, double* y, int yld,
+                   const int* ymap, double* qslot, const int* done, hipStream_t st);
 template <class T>
 void launch_bdiag(const DevPatch* P, int np, const T* A, double* out, hipStream_t st);
 // Tile-path PCG on R (1..4) right-hand sides, column-major vectors; st[R].done
@@ -178,6 +181,12 @@ void launch_extend_add(const CoarseNodeDev* nodes, int c, int ns, const int* cpo
 void launch_front_pad(const CoarseNodeDev* nodes, int nn, double* F, hipStream_t st);
 void launch_front_rhs(const CoarseNodeDev* nodes, const int* jobs, const int* prefix, int njobs,
                       int total, const double* F, double* L, hipStream_t st);
+// dst[j * dld + i] = scale * (w ? w[i] : 1) * src[j * sld + idx[i]], i < n,
+// j < R: the gathered (and signed) inputs of the row-panel products, so that
+// the panels read them as contiguous blocks.
+void launch_gather_cols(int R, int n, const int* idx, const double* w, double scale,
+                        const double* src, int sld, double* dst, int dld, const int* done,
+                        hipStream_t st);
 void launch_sumsq_slots(int R, int n, const double* y, int ld, double* slots, const int* done,
                         hipStream_t st);
 void launch_zero(int64_t n, double* a, hipStream_t st);

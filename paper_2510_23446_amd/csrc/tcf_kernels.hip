@@ -2511,11 +2511,14 @@ __global__ void __launch_bounds__(256) k_tiles_w(const TileJob* jobs, const T* M
 template <class T, int Group>
 __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const PanelTile* tiles,
                                                  const T* Mb, const double* xv, int xld,
-                                                 const int* gidx, const double* gsw, double scale,
-                                                 double* y, int yld, const int* ymap,
-                                                 double* qslot, const int* done, int R) {
+                                                 const int* gidx, double* y, int yld,
+                                                 const int* ymap, double* qslot, const int* done,
+                                                 int R) {
   typedef Mfma16<double> M;
-  constexpr int XM = Group == 3 ? 0 : ((Group == 1 || Group == 4) ? 2 : 1);
+  // the F apply, the preconditioner and the coarse correction read inputs
+  // gathered beforehand (contiguous per tile); the coarse sweeps gather
+  // through their index table
+  constexpr int XM = Group == 4 ? 2 : 0;
   const int nbk = gridDim.x, per = nbk >> 3, rem = nbk & 7;
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
   const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
@@ -2543,10 +2546,7 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
     const VT* base = reinterpret_cast<const VT*>(Mb + off);
     const bool xon = ie < tl.nc;
     const int xo = xon ? tl.xc_off + ie : 0;
-    int gi = xo;
-    double f = 1.0;
-    if (XM != 0) gi = gidx[xo];
-    if (XM == 1) f = scale * gsw[xo];
+    const int gi = XM != 0 ? gidx[xo] : xo;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
       const bool ok = k * CPL + h < tl.nc;
@@ -2555,7 +2555,7 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int j = jq + 4 * m;
-      xg[m] = (xon && j < R) ? f * xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
+      xg[m] = (xon && j < R) ? xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
     }
   };
   PanelTile tl = tp[0];
@@ -2594,12 +2594,8 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
     const int row = 16 * w + M::row(lk, e);
     if (row >= jb.nr) continue;
     const int yi = mapped ? ymap[jb.yr_off + row] : jb.yr_off + row;
-    double xr = 1.0;
     int gr = jb.xr_off + row;
-    if (qf) {
-      if (XM != 0) gr = gidx[jb.xr_off + row];
-      if (XM == 1) xr = scale * gsw[jb.xr_off + row];
-    }
+    if (qf && XM != 0) gr = gidx[gr];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int j = 16 * hh + li;
@@ -2609,7 +2605,7 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
       if (shared) atomicAdd(dst, v);
       else *dst += v;
       if (qf) {
-        const double xv_r = xr * xv[(size_t)j * (unsigned)xld + (unsigned)gr];
+        const double xv_r = xv[(size_t)j * (unsigned)xld + (unsigned)gr];
         if (hh) q1 += xv_r * v; else q0 += xv_r * v;
       }
     }
@@ -2675,14 +2671,13 @@ static void launch_tiles_wide(int R, const TileJob* jobs, int njobs, const T* M,
 
 template <class T>
 void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
-                   const T* M, const double* xv, int xld, const int* gidx, const double* gsgn,
-                   double scale, double* y, int yld, const int* ymap, double* qslot,
-                   const int* done, hipStream_t st) {
+                   const T* M, const double* xv, int xld, const int* gidx, double* y, int yld,
+                   const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
 #define TCF_PANEL_CASE(G)                                                                       \
   case G:                                                                                       \
     TCF_TIMED_LAUNCH((k_panel_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld, \
-                     gidx, gsgn, scale, y, yld, ymap, qslot, done, R);                          \
+                     gidx, y, yld, ymap, qslot, done, R);                                       \
     break;
   switch (group) {
     TCF_PANEL_CASE(0)
@@ -2691,18 +2686,17 @@ void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tile
     TCF_PANEL_CASE(3)
     default:
       TCF_TIMED_LAUNCH((k_panel_w<T, 4>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld,
-                       gidx, gsgn, scale, y, yld, ymap, qslot, done, R);
+                       gidx, y, yld, ymap, qslot, done, R);
       break;
   }
 #undef TCF_PANEL_CASE
 }
 template void launch_panels<double>(int, int, const PanelJob*, const PanelTile*, int,
-                                    const double*, const double*, int, const int*,
-                                    const double*, double, double*, int, const int*, double*,
-                                    const int*, hipStream_t);
+                                    const double*, const double*, int, const int*, double*, int,
+                                    const int*, double*, const int*, hipStream_t);
 template void launch_panels<float>(int, int, const PanelJob*, const PanelTile*, int, const float*,
-                                   const double*, int, const int*, const double*, double, double*,
-                                   int, const int*, double*, const int*, hipStream_t);
+                                   const double*, int, const int*, double*, int, const int*,
+                                   double*, const int*, hipStream_t);
 
 template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
@@ -2955,6 +2949,26 @@ void launch_front_rhs(const CoarseNodeDev* nodes, const int* jobs, const int* pr
   if (total == 0) return;
   hipLaunchKernelGGL(k_front_rhs, dim3(total), dim3(256), 0, st, nodes, jobs, prefix, njobs, F, L);
 }
+__global__ void __launch_bounds__(256) k_gather_cols(int n, int R, const int* idx,
+                                                     const double* w, double scale,
+                                                     const double* src, int sld, double* dst,
+                                                     int dld, const int* done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int g = idx[i];
+  const double f = w ? scale * w[i] : scale;
+  for (int j = 0; j < R; ++j)
+    dst[(int64_t)j * dld + i] = f * src[(int64_t)j * sld + g];
+}
+void launch_gather_cols(int R, int n, const int* idx, const double* w, double scale,
+                        const double* src, int sld, double* dst, int dld, const int* done,
+                        hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_gather_cols, dim3((n + 255) / 256), dim3(256), 0, st, n, R, idx, w, scale,
+                     src, sld, dst, dld, done);
+}
+
 void launch_sumsq_slots(int R, int n, const double* y, int ld, double* slots, const int* done,
                         hipStream_t st) {
   if (n == 0) return;
