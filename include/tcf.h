@@ -381,6 +381,10 @@ typedef struct tcf_stats {
   int32_t setup_chunks;        /* patch groups the setup factorised in turn     */
   double coarse_bytes;         /* algorithmic bytes of one coarse solve         */
   size_t device_bytes_peak;    /* high-water mark of the handle's device memory */
+  int32_t rhs_batch;           /* excitations per batched PCG after rounding    */
+                               /* (more than 4: the matrix-core row panels)     */
+  int32_t panel_jobs;          /* row-panel jobs of the F apply (0: the vector  */
+                               /* tile path)                                    */
 } tcf_stats;
 
 int tcf_get_stats(const tcf_problem* h, tcf_stats* st);
@@ -424,6 +428,15 @@ enum tcf_kernel_group {
 int tcf_profile_enable(tcf_problem* h, int32_t on);
 int tcf_profile_get(const tcf_problem* h, int32_t group, double* total_ms, int64_t* launches,
                     double* alg_bytes_per_launch);
+/*
+ * Algorithmic flops of one launch of group g (per coarse solve for
+ * TCF_KG_COARSE): 2 per matrix entry and column of the batch (rhs_batch
+ * after rounding), symmetric matrices counted whole, triangular ones as
+ * triangles; the matrix-core fraction of a batched product is these flops
+ * over its time.  0 for the condensation and recovery groups.  Host only;
+ * TCF_EINVAL for a bad group or a NULL output.
+ */
+int tcf_profile_get_flops(const tcf_problem* h, int32_t group, double* alg_flops_per_launch);
 
 /*
  * Measurement reference: one launch of a plain streaming copy that reads and

@@ -262,6 +262,7 @@ struct tcf_problem {
   double prof_ms[TCF_KG_COUNT] = {0};
   int64_t prof_n[TCF_KG_COUNT] = {0};
   double prof_bytes[TCF_KG_COUNT] = {0};
+  double prof_flops[TCF_KG_COUNT] = {0};
   int cur_it = -1;  // PCG iteration of the launches being issued (-1: outside PCG)
   int cur_sweep = 0;  // refinement sweep of the solve being issued (0: first solve)
 #define TCF_PRED_KINDS 8
@@ -431,6 +432,25 @@ static void compute_alg_bytes(tcf_problem* h) {
     rec += qb + (d.n_r + ni) * 8;
   }
   const double nP = h->n_primal;
+  // algorithmic flops: 2 per matrix entry and batch column, symmetric
+  // matrices whole, triangles as triangles
+  double fa = 0, fp = 0, fphi = 0, fc = 0;
+  for (int s = 0; s < h->np_tot; ++s) {
+    const DevPatch& d = h->hp[s];
+    const double nb = d.n_b, np_ = d.n_p;
+    fa += 2 * (nb * nb + nb * np_);
+    fp += 2 * nb * nb;
+    fphi += 2 * nb * np_;
+  }
+  for (size_t i = 0; i < h->cnodes.size(); ++i) {
+    const double nj = h->cnodes[i].nj, ns = h->cnodes[i].ns;
+    fc += (int)i == h->c_root ? 2 * nj * nj : 2 * (nj * (nj + 1) + 2 * nj * ns);
+  }
+  const double R = h->rb;
+  h->prof_flops[TCF_KG_APPLY] = R * fa;
+  h->prof_flops[TCF_KG_PRECOND] = R * fp;
+  h->prof_flops[TCF_KG_PHI] = R * fphi;
+  h->prof_flops[TCF_KG_COARSE] = R * fc;
   h->prof_bytes[TCF_KG_APPLY] = app;
   h->prof_bytes[TCF_KG_PRECOND] = pre;
   h->prof_bytes[TCF_KG_PHI] = phi;
@@ -911,6 +931,8 @@ int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
   st->setup_chunks = (int32_t)h->chunk_begin.size() - 1;
   st->coarse_bytes = h->c_bytes;
   st->device_bytes_peak = h->dev_bytes_peak;
+  st->rhs_batch = h->rb;
+  st->panel_jobs = h->n_papply;
   st->cond_est_max = 0.0;
   st->cond_est_patch = -1;
   for (size_t s = 0; s < h->cond_est.size(); ++s)
@@ -986,6 +1008,12 @@ int tcf_profile_get(const tcf_problem* h, int32_t g, double* total_ms, int64_t* 
   if (total_ms) *total_ms = h->prof_ms[g];
   if (launches) *launches = h->prof_n[g];
   if (alg_bytes) *alg_bytes = h->prof_bytes[g];
+  return TCF_OK;
+}
+
+int tcf_profile_get_flops(const tcf_problem* h, int32_t g, double* alg_flops) {
+  if (!h || g < 0 || g >= TCF_KG_COUNT || !alg_flops) return TCF_EINVAL;
+  *alg_flops = h->prof_flops[g];
   return TCF_OK;
 }
 
@@ -1858,13 +1886,19 @@ static void add_tile_twice(std::vector<PackJob>& pk, std::vector<TileJob>& ja,
 // One tile of a row panel: the nrB x ncB block at (row0, col0) of a
 // column-major source, stored as is (trans 0: the block's ncB columns) or
 // transposed (trans 1: its nrB rows become the tile's columns).
+// Elements one stored panel tile of nc columns takes: columns padded to the
+// quantum of the matrix-core operand order, 4 x (16 bytes / element size).
+static int64_t panel_tile_elems(int nc, int elem_bytes) {
+  const int q = 4 * (16 / elem_bytes);
+  return 64 * (int64_t)((nc + q - 1) / q * q);
+}
 static void add_panel_tile(std::vector<PackJob>& pk, std::vector<PanelTile>& tl, int64_t& off,
-                           int64_t src_off, int ld, int row0, int col0, int nrB, int ncB,
-                           int trans, int xc_off) {
+                           int elem_bytes, int64_t src_off, int ld, int row0, int col0, int nrB,
+                           int ncB, int trans, int xc_off) {
   pk.push_back(PackJob{src_off, off, ld, row0, col0, nrB, ncB, trans});
   const int nc = trans ? nrB : ncB;
   tl.push_back(PanelTile{xc_off, nc});
-  off += 64 * (int64_t)nc;
+  off += panel_tile_elems(nc, elem_bytes);
 }
 
 // Row panels of the per-iteration operators for the matrix-core path:
@@ -1890,7 +1924,8 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   // a panel longer than the chunk becomes several jobs of about equal
   // length (more workgroups in flight); their partial rows add atomically
   const int chunk = h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16;
-  auto finish = [&](std::vector<PanelJob>& v, PanelJob j) {
+  const int wT = (int)sizeof(T), wD = (int)sizeof(double);
+  auto finish = [&](std::vector<PanelJob>& v, PanelJob j, int eb) {
     const int nt = (int)tl.size() - j.t0;
     if (nt <= 0) return;
     const int parts = (nt + chunk - 1) / chunk;
@@ -1902,7 +1937,7 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       c.t0 = t;
       c.nt = n;
       if (parts > 1) c.flags |= 1;
-      for (int k = 0; k < n; ++k) off += 64 * (int64_t)tl[t + k].nc;
+      for (int k = 0; k < n; ++k) off += panel_tile_elems(tl[t + k].nc, eb);
       t += n;
       v.push_back(c);
     }
@@ -1917,30 +1952,30 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       // F apply: S_bb^-1 rows (vc, with x^T S_bb^-1 x), Phi_b^T rows (cv)
       PanelJob j = begin(oa, d.bp_off + 64 * I, nrb(I), d.b_off + 64 * I, 4);
       for (int J = 0; J < Tb; ++J)
-        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
+        add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
                        d.b_off + 64 * J);
-      finish(japp, j);
+      finish(japp, j, wT);
       // preconditioner: S_bb rows (tb, with r.z)
       PanelJob q = begin(ob, d.b_off + 64 * I, nrb(I), d.b_off + 64 * I, 4);
       for (int J = 0; J < Tb; ++J)
-        add_panel_tile(pb, tl, ob, d.S_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
+        add_panel_tile(pb, tl, ob, wT, d.S_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
                        d.b_off + 64 * J);
-      finish(jpre, q);
+      finish(jpre, q, wT);
     }
     for (int K = 0; K < Tp; ++K) {
       PanelJob j = begin(oa, d.p_off + 64 * K, nrp(K), 0, 1 | 2);
       for (int I = 0; I < Tb; ++I)
-        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 1,
+        add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 1,
                        d.b_off + 64 * I);
-      finish(japp, j);
+      finish(japp, j, wT);
     }
     for (int I = 0; I < Tb && Tp > 0; ++I) {
       // coarse correction vc += Phi_b N q (inputs q through the primal ranks)
       PanelJob j = begin(oa, d.bp_off + 64 * I, nrb(I), 0, 0);
       for (int K = 0; K < Tp; ++K)
-        add_panel_tile(pa, tl, oa, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 0,
+        add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 0,
                        d.p_off + 64 * K);
-      finish(jphi, j);
+      finish(jphi, j, wT);
     }
   }
   std::vector<int> ctab(3 * (size_t)npm);
@@ -1952,8 +1987,8 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
     for (int I = 0; I < Tr; ++I) {
       PanelJob j = begin(oc, r.j0 + 64 * I, nrr(I), r.j0 + 64 * I, 4);
       for (int J = 0; J < Tr; ++J)
-        add_panel_tile(pc, tl, oc, 0, r.nj_pad, 64 * I, 64 * J, nrr(I), nrr(J), 0, r.j0 + 64 * J);
-      finish(jroot, j);
+        add_panel_tile(pc, tl, oc, wD, 0, r.nj_pad, 64 * I, 64 * J, nrr(I), nrr(J), 0, r.j0 + 64 * J);
+      finish(jroot, j, wD);
     }
     int stot = 0;
     for (const CoarseNodeDev& c : h->cnodes) stot += c.ns;
@@ -1976,28 +2011,28 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
         // forward: y_J = L_JJ^-1 b_J (into the y part)
         PanelJob j = begin(oc, npm + c.j0 + 64 * I, nrj(I), 0, 0);
         for (int K = 0; K <= I; ++K)
-          add_panel_tile(pl, tl, oc, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 0,
+          add_panel_tile(pl, tl, oc, wD, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 0,
                          c.j0 + 64 * K);
-        finish(fw[lv], j);
+        finish(fw[lv], j, wD);
       }
       for (int a = 0; a < Ts; ++a) {
         // forward: b_S -= L_SJ L_JJ^-1 b_J (shared with the other nodes)
         PanelJob j = begin(oc, sb0 + c.s_off + 64 * a, nrs(a), 0, 1 | 2);
         for (int K = 0; K < Tj; ++K)
-          add_panel_tile(pl, tl, oc, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 1,
+          add_panel_tile(pl, tl, oc, wD, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 1,
                          c.j0 + 64 * K);
-        finish(fw[lv], j);
+        finish(fw[lv], j, wD);
       }
       for (int K = 0; K < Tj; ++K) {
         // backward: x_J = L_JJ^-T y_J - L_JJ^-T L_SJ^T x_S
         PanelJob j = begin(oc, 2 * npm + c.j0 + 64 * K, nrj(K), 0, 0);
         for (int I = K; I < Tj; ++I)
-          add_panel_tile(pl, tl, oc, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 1,
+          add_panel_tile(pl, tl, oc, wD, c.l_off, c.nj_pad, 64 * I, 64 * K, nrj(I), nrj(K), 1,
                          npm + c.j0 + 64 * I);
         for (int a = 0; a < Ts; ++a)
-          add_panel_tile(pl, tl, oc, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 0,
+          add_panel_tile(pl, tl, oc, wD, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 0,
                          sx0 + c.s_off + 64 * a);
-        finish(bw[lv], j);
+        finish(bw[lv], j, wD);
       }
     }
   }
@@ -2013,10 +2048,10 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   RCCHK(h->upload(&dpb, pb));
   RCCHK(h->upload(&dpc, pc));
   RCCHK(h->upload(&dpl, pl));
-  launch_pack_tiles<T, T>(dpa, (int)pa.size(), (const T*)h->d_G, pA, st);
-  launch_pack_tiles<T, T>(dpb, (int)pb.size(), (const T*)h->d_S, pB, st);
-  if (!pc.empty()) launch_pack_tiles<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_pC, st);
-  if (!pl.empty()) launch_pack_tiles<double, double>(dpl, (int)pl.size(), h->d_cL, h->d_pC, st);
+  launch_pack_panel<T, T>(dpa, (int)pa.size(), (const T*)h->d_G, pA, st);
+  launch_pack_panel<T, T>(dpb, (int)pb.size(), (const T*)h->d_S, pB, st);
+  if (!pc.empty()) launch_pack_panel<double, double>(dpc, (int)pc.size(), h->d_SPinv, h->d_pC, st);
+  if (!pl.empty()) launch_pack_panel<double, double>(dpl, (int)pl.size(), h->d_cL, h->d_pC, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   for (PackJob* b : {dpa, dpb, dpc, dpl}) h->release(b);

@@ -125,6 +125,9 @@ namespace tcf {
 void launch_assemble_split(int n, const int* ptr, const int* idx, double* x, hipStream_t st);
 }  // namespace tcf
 namespace tcf {
+// Row-panel tiles in the matrix cores' operand order (k_pack_panel).
+template <class TS, class TD>
+void launch_pack_panel(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st);
 template <class TS, class TD>
 void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st);
 template <class T>

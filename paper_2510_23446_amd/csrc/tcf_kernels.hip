@@ -2165,6 +2165,35 @@ __global__ void k_pack_tiles(const PackJob* jobs, const TS* src, TD* dst) {
   }
 }
 
+// One tile of a row panel in the matrix cores' operand order (read by
+// k_panel_w): the 64 x nc tile (the block at (row0, col0), or its transpose
+// when trans) is stored as 4 wave blocks of 16 rows; in wave block w,
+// vector g of lane l holds, for e < V = 16 / sizeof(TD), the entry
+// (16 w + l % 16, 4 (V g + e) + l / 16).  Columns are padded with zeros to a
+// multiple of 4 V: the tile takes 64 * roundup(nc, 4 V) elements.
+template <class TS, class TD>
+__global__ void k_pack_panel(const PackJob* jobs, const TS* src, TD* dst) {
+  constexpr int V = 16 / sizeof(TD), Q = 4 * V;
+  const PackJob jb = jobs[blockIdx.x];
+  TD* o = dst + jb.dst_off;
+  const TS* s = src + jb.src_off;
+  const int ncs = jb.trans ? jb.nr : jb.nc;  // stored columns
+  const int nrs = jb.trans ? jb.nc : jb.nr;  // filled rows
+  const int ncq = (ncs + Q - 1) / Q;
+  const int wblk = 16 * Q * ncq;             // elements of one wave block
+  for (int idx = threadIdx.x; idx < 4 * wblk; idx += blockDim.x) {
+    const int w = idx / wblk, r1 = idx % wblk;
+    const int g = r1 / (64 * V), r2 = r1 % (64 * V);
+    const int l = r2 / V, e = r2 % V;
+    const int r = 16 * w + (l & 15), c = 4 * (V * g + e) + (l >> 4);
+    TD v = TD(0);
+    if (r < nrs && c < ncs) {
+      const int br = jb.trans ? c : r, bc = jb.trans ? r : c;
+      v = (TD)s[(int64_t)(jb.row0 + br) + (int64_t)(jb.col0 + bc) * jb.ld];
+    }
+    o[idx] = v;
+  }
+}
 
 // Lane exchanges inside a wave without the LDS crossbar: DPP moves of the two
 // 32-bit halves of a double.  CTRL is a DPP control word: quad_perm 0xB1 (lane
@@ -2384,206 +2413,116 @@ __global__ void __launch_bounds__(256) k_tiles(const TileJob* jobs, const T* Mb,
   }
 }
 
-// The same tile products for many right-hand sides (5 <= R <= 32) on the
-// matrix cores: v_mfma_f64_16x16x4 with FP64 accumulation (FP32 tiles are
-// widened as they are staged), so every tile is read from HBM once per
-// apply for all R columns.  The tile goes to LDS once; the right-hand sides
-// are taken 16 at a time: both sides' inputs for those 16 columns into LDS,
-// then wave w forms the N part of rows 16w.. (D = A[16w.., :] X_c) and the
-// T part of columns 16w.. (D = A[:, 16w..]^T X_r), each as 16 k-steps of
-// 4 over the tile's 64 columns (rows).  Results go to y with FP64 atomics,
-// as in k_tiles; the quadratic form x_r^T A x_c of each column is summed
-// over the tile's rows and added to its slot.
-template <class T, int Group>
-__global__ void __launch_bounds__(256) k_tiles_w(const TileJob* jobs, const T* Mb,
-                                                 const double* xv, int xld, const int* gidx,
-                                                 const double* gsw, double scale,
-                                                 double* y, int yld, const int* ymap,
-                                                 double* qslot, const int* done, int R) {
-  typedef Mfma16<double> M;
-  constexpr int XM = Group == 3 ? 0 : ((Group == 1 || Group == 4) ? 2 : 1);
-  const int nb = gridDim.x, per = nb >> 3, rem = nb & 7;
-  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
-  const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
-  typedef typename TileVec<T>::v VT;
-  constexpr int V = TileVec<T>::n;
-  constexpr int RPC = 64 / V;
-  constexpr int L = 64 * 64 / V / 256;
-  constexpr int CPL = 256 / RPC;
-  const TileJob jb = jobs[job];
-  if ((done ? *done : 0) | (jb.nc < 0) | (jb.m_off < 0)) return;
-  __shared__ double As[64][65];      // the tile, As[row][col]
-  __shared__ double Xs[2][64][17];   // inputs of 16 columns: [0] row side, [1] column side
-  __shared__ double Qs[4][16];       // per-wave quadratic-form partials
-  const int t = threadIdx.x;
-  const bool doN = jb.flags & 1, doT = jb.flags & 2, qf = (jb.flags & 16) && qslot != nullptr;
-  // input gather: thread t serves side t >> 7, entry t & 63, columns of
-  // parity (t >> 6) & 1
-  const int side = t >> 7, ie = t & 63, jpar = (t >> 6) & 1;
-  const bool xon = side == 0 ? ((doT || qf) && ie < jb.nr) : (doN && ie < jb.nc);
-  const int xo = xon ? (side == 0 ? jb.xr_off : jb.xc_off) + ie : 0;
-  int gi = xo;
-  double sw = 1.0;
-  if (XM != 0) gi = gidx[xo];
-  if (XM == 1) sw = gsw[xo];
-  const double f = XM == 1 ? scale * sw : 1.0;
-  // the tile, coalesced as in k_tiles, into LDS (columns past nc as zeros)
-  const VT* base = reinterpret_cast<const VT*>(Mb + jb.m_off);
-  const int h = t / RPC, lr = t % RPC;
-#pragma unroll
-  for (int k = 0; k < L; ++k) {
-    const int cc = k * CPL + h;
-    const bool ok = cc < jb.nc;
-    const VT v = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
-#pragma unroll
-    for (int u = 0; u < V; ++u) As[V * lr + u][cc] = ok ? (double)v[u] : 0.0;
-  }
-  const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
-  const bool wN = doN && 16 * w < jb.nr;  // this wave's 16 rows exist
-  const bool wT = doT && 16 * w < jb.nc;  // this wave's 16 columns exist
-  const int kN = (jb.nc + 3) >> 2, kT = (jb.nr + 3) >> 2;  // k-steps that see data
-  for (int c0 = 0; c0 < R; c0 += 16) {
-    __syncthreads();  // As staged (first pass) / previous columns consumed
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int j = c0 + jpar + 2 * m;
-      const double xg = (xon && j < R) ? xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
-      Xs[side][ie][jpar + 2 * m] = f * xg;
-    }
-    __syncthreads();
-    if (wN) {
-      M::acc a4 = {0.0, 0.0, 0.0, 0.0};
-      for (int k4 = 0; k4 < kN; ++k4)
-        a4 = M::mma(As[16 * w + li][4 * k4 + lk], Xs[1][4 * k4 + lk][li], a4);
-      const int j = c0 + li;
-      double q = 0.0;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = 16 * w + M::row(lk, e);
-        if (row < jb.nr && j < R) {
-          const int yi = (jb.flags & 8) ? ymap[jb.yr_off + row] : jb.yr_off + row;
-          atomicAdd(y + (int64_t)j * yld + yi, a4[e]);
-        }
-        q += Xs[0][row][li] * a4[e];  // rows past nr carry zero inputs
-      }
-      if (qf) {
-        q = xor16_sum(q);
-        q = xor32_sum(q);
-        if (lk == 0) Qs[w][li] = q;
-      }
-    } else if (qf && lk == 0) {
-      Qs[w][li] = 0.0;
-    }
-    if (wT) {
-      M::acc a4 = {0.0, 0.0, 0.0, 0.0};
-      for (int k4 = 0; k4 < kT; ++k4)
-        a4 = M::mma(As[4 * k4 + lk][16 * w + li], Xs[0][4 * k4 + lk][li], a4);
-      const int j = c0 + li;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int col = 16 * w + M::row(lk, e);
-        if (col < jb.nc && j < R) {
-          const int yi = (jb.flags & 4) ? ymap[jb.yc_off + col] : jb.yc_off + col;
-          atomicAdd(y + (int64_t)j * yld + yi, a4[e]);
-        }
-      }
-    }
-    if (qf) {
-      __syncthreads();
-      if (t < 16 && c0 + t < R) {
-        const double v = (Qs[0][t] + Qs[1][t]) + (Qs[2][t] + Qs[3][t]);
-        atomicAdd(qslot + (c0 + t) * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
-                  (jb.flags & 32) ? 2.0 * v : v);
-      }
-    }
-  }
-}
-
-// Row panels on the matrix cores, for batches of 5..32 right-hand sides.
-// One block per panel: wave w owns rows 16w .. 16w + 15 of the panel for all
-// R columns (two 16-wide v_mfma_f64_16x16x4 accumulators), and the panel's
-// tiles stream through LDS one after the other with their column inputs, so
-// each output row is formed completely in one block: written once (added to
-// what the vector holds), with atomics only where another panel shares the
-// row (an operator that adds into a vector other panels also add into).
-// The symmetric operators are stored whole for this path, so no tile is
-// applied transposed.  Inputs as in k_tiles (Group fixes the gather mode).
-template <class T, int Group>
+// Row panels on the matrix cores, for batches of up to 32 right-hand sides.
+// One block per panel job: wave w owns rows 16w .. 16w + 15 of the panel for
+// all R columns (one 16-wide v_mfma_f64_16x16x4 accumulator, two when W32:
+// R > 16; FP64 accumulation, FP32 tiles widened as they are used), and the job's
+// tiles stream by one after the other, so each output row is formed in one
+// block: added once to what the vector holds, with atomics only where another
+// job shares the row (a split panel, or an operator whose rows several
+// panels add into).  The symmetric operators are stored whole for this path.
+//
+// Tiles are stored in the matrix cores' operand order (see k_pack_panel):
+// the 16 rows of wave w come as consecutive 16-byte vectors, lane l holding
+// the entries (16w + l % 16, 4k + l / 16) of V = 16 / sizeof(T) consecutive
+// k-steps k, so a wave's loads are contiguous and need no LDS.  They go to
+// registers one tile ahead: the next tile is in flight while the matrix
+// cores work on the current one.  The column inputs of a tile (64 entries x R)
+// are staged in LDS, column-major with a column stride of 66 doubles, which
+// keeps both the staging stores (lanes along entries) and the operand reads
+// of a half-wave (16 columns x 2 entries) on distinct banks, and lets every
+// operand read use one base address plus a constant offset; two buffers,
+// one barrier per tile.  Inputs: groups 0 to 3 read
+// xv[j * xld + i] directly, group 4 (the coarse factor's sweeps) through
+// gidx.
+template <class T, int Group, bool W32>
 __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const PanelTile* tiles,
                                                  const T* Mb, const double* xv, int xld,
                                                  const int* gidx, double* y, int yld,
                                                  const int* ymap, double* qslot, const int* done,
                                                  int R) {
   typedef Mfma16<double> M;
-  // the F apply, the preconditioner and the coarse correction read inputs
-  // gathered beforehand (contiguous per tile); the coarse sweeps gather
-  // through their index table
   constexpr int XM = Group == 4 ? 2 : 0;
+  typedef typename TileVec<T>::v VT;
+  constexpr int V = TileVec<T>::n;  // k-steps per 16-byte vector
+  constexpr int Q = 4 * V;          // column quantum of the stored tiles
+  constexpr int GM = 64 / Q;        // vectors per lane of a full tile
   const int nbk = gridDim.x, per = nbk >> 3, rem = nbk & 7;
   const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
   const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
-  typedef typename TileVec<T>::v VT;
-  constexpr int V = TileVec<T>::n;
-  constexpr int RPC = 64 / V;
-  constexpr int L = 64 * 64 / V / 256;
-  constexpr int CPL = 256 / RPC;
   const PanelJob jb = jobs[job];
   if ((done ? *done : 0) | (jb.nt < 0) | (jb.m_off < 0)) return;
-  __shared__ double As[64][65];
-  __shared__ double Xs[64][33];
-  __shared__ double Qs[4][32];
+  constexpr int XP = 66;  // column stride of the staged inputs
+  __shared__ double Xs[2][32 * XP];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
-  const int h = t / RPC, lr = t % RPC;
   // input staging: thread t serves entry t & 63, columns (t >> 6) + 4 m
   const int ie = t & 63, jq = t >> 6;
   M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-  // registers hold the next tile (matrix chunk and gathered inputs) while the
-  // matrix cores work on the current one from the LDS
-  VT raw[L];
+  VT ra[GM];
   double xg[8];
   const PanelTile* tp = tiles + jb.t0;
   auto fetch = [&](const PanelTile& tl, int64_t off) {
-    const VT* base = reinterpret_cast<const VT*>(Mb + off);
+    // the index load goes first: the input loads wait for it, and the
+    // tile's loads issued after it stay in flight meanwhile
     const bool xon = ie < tl.nc;
-    const int xo = xon ? tl.xc_off + ie : 0;
+    const int xo = tl.xc_off + (xon ? ie : 0);
     const int gi = XM != 0 ? gidx[xo] : xo;
+    const int ncq = (tl.nc + Q - 1) / Q;  // vectors per lane
+    // wave block w: 16 rows x Q ncq columns = 64 ncq vectors
+    const VT* base = reinterpret_cast<const VT*>(Mb + off) + w * 64 * ncq + lane;
+    // every load is issued, from a clamped address where it has nothing to
+    // read, so that the number in flight is fixed and the waits are exact.
+    // An input past the tile's columns meets zero columns of the stored tile
+    // and one past the batch feeds an output column that is dropped, so
+    // both may hold any finite value: they are not masked
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-      const bool ok = k * CPL + h < tl.nc;
-      raw[k] = __builtin_nontemporal_load(base + (ok ? k * 256 + t : lr));
-    }
+    for (int g = 0; g < GM; ++g) ra[g] = __builtin_nontemporal_load(base + (g < ncq ? g : 0) * 64);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int j = jq + 4 * m;
-      xg[m] = (xon && j < R) ? xv[(size_t)j * (unsigned)xld + (unsigned)gi] : 0.0;
+      xg[m] = xv[(size_t)(j < R ? j : 0) * (unsigned)xld + (unsigned)gi];
     }
   };
   PanelTile tl = tp[0];
   int64_t off = jb.m_off;
   fetch(tl, off);
   for (int it = 0; it < jb.nt; ++it) {
-    const int nc = tl.nc;
-    __syncthreads();  // the previous tile's LDS reads are done
+    const int buf = it & 1;
+    const int ncq = (tl.nc + Q - 1) / Q;
+    VT rc[GM];
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-      const int cc = k * CPL + h;
-      const bool ok = cc < nc;
+    for (int g = 0; g < GM; ++g) rc[g] = ra[g];
 #pragma unroll
-      for (int u = 0; u < V; ++u) As[V * lr + u][cc] = ok ? (double)raw[k][u] : 0.0;
+    for (int m = 0; m < 8; ++m) {
+      const int j = jq + 4 * m;
+      Xs[buf][j * XP + ie] = xg[m];
     }
-#pragma unroll
-    for (int m = 0; m < 8; ++m) Xs[ie][jq + 4 * m] = xg[m];
+    // the tile's inputs are staged; every wave is past the reads of this
+    // buffer two tiles ago
     __syncthreads();
-    off += 64 * (int64_t)nc;
+    off += 64 * (int64_t)(ncq * Q);
     if (it + 1 < jb.nt) {
       tl = tp[it + 1];
       fetch(tl, off);
     }
-    const int kN = (nc + 3) >> 2;
-    for (int k4 = 0; k4 < kN; ++k4) {
-      const double a = As[16 * w + li][4 * k4 + lk];
-      a0 = M::mma(a, Xs[4 * k4 + lk][li], a0);
-      if (R > 16) a1 = M::mma(a, Xs[4 * k4 + lk][16 + li], a1);
+    const double* xs = Xs[buf] + li * XP + lk;
+#pragma unroll
+    for (int g = 0; g < GM; ++g) {
+      if (g < ncq) {
+        // the group's operand reads first, then its products
+        double b0[V], b1[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          b0[e] = xs[4 * (V * g + e)];
+          if (W32) b1[e] = xs[16 * XP + 4 * (V * g + e)];
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const double a = (double)rc[g][e];
+          a0 = M::mma(a, b0[e], a0);
+          if (W32) a1 = M::mma(a, b1[e], a1);
+        }
+      }
     }
   }
   // outputs: lane (li, lk), element e is row 16 w + row(lk, e), column li (+16)
@@ -2613,14 +2552,16 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
   if (qf) {
     q0 = xor32_sum(xor16_sum(q0));
     q1 = xor32_sum(xor16_sum(q1));
+    __syncthreads();  // every wave is done with the staged inputs
+    double* Qs = Xs[0];  // 4 x 32
     if (lk == 0) {
-      Qs[w][li] = q0;
-      Qs[w][16 + li] = q1;
+      Qs[w * 32 + li] = q0;
+      Qs[w * 32 + 16 + li] = q1;
     }
     __syncthreads();
     if (t < 32 && t < R)
       atomicAdd(qslot + t * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
-                (Qs[0][t] + Qs[1][t]) + (Qs[2][t] + Qs[3][t]));
+                (Qs[t] + Qs[32 + t]) + (Qs[64 + t] + Qs[96 + t]));
   }
 }
 
@@ -2634,6 +2575,15 @@ void launch_pack_tiles(const PackJob* jobs, int njobs, const TS* src, TD* dst, h
   if (njobs == 0) return;
   hipLaunchKernelGGL((k_pack_tiles<TS, TD>), dim3(njobs), dim3(256), 0, st, jobs, src, dst);
 }
+template <class TS, class TD>
+void launch_pack_panel(const PackJob* jobs, int njobs, const TS* src, TD* dst, hipStream_t st) {
+  if (njobs == 0) return;
+  hipLaunchKernelGGL((k_pack_panel<TS, TD>), dim3(njobs), dim3(256), 0, st, jobs, src, dst);
+}
+template void launch_pack_panel<double, double>(const PackJob*, int, const double*, double*,
+                                                hipStream_t);
+template void launch_pack_panel<float, float>(const PackJob*, int, const float*, float*,
+                                              hipStream_t);
 // group only names the kernel instance (apply / phi / precond / coarse) so
 // that traces attribute each operator separately
 template <class T, int G>
@@ -2660,33 +2610,28 @@ static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, co
       break;
   }
 }
-template <class T, int G>
-static void launch_tiles_wide(int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
-                              int xld, const int* gidx, const double* gsgn, double scale,
-                              double* y, int yld, const int* ymap, double* qslot, const int* done,
-                              hipStream_t st) {
-  TCF_TIMED_LAUNCH((k_tiles_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, M, xv, xld, gidx, gsgn,
-                   scale, y, yld, ymap, qslot, done, R);
-}
 
 template <class T>
 void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
                    const T* M, const double* xv, int xld, const int* gidx, double* y, int yld,
                    const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
-#define TCF_PANEL_CASE(G)                                                                       \
-  case G:                                                                                       \
-    TCF_TIMED_LAUNCH((k_panel_w<T, G>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld, \
-                     gidx, y, yld, ymap, qslot, done, R);                                       \
+#define TCF_PANEL_CASE(G)                                                                     \
+  case G:                                                                                     \
+    if (R > 16)                                                                               \
+      TCF_TIMED_LAUNCH((k_panel_w<T, G, true>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, \
+                       xv, xld, gidx, y, yld, ymap, qslot, done, R);                          \
+    else                                                                                      \
+      TCF_TIMED_LAUNCH((k_panel_w<T, G, false>), dim3(njobs), dim3(256), 0, st, jobs, tiles,  \
+                       M, xv, xld, gidx, y, yld, ymap, qslot, done, R);                       \
     break;
   switch (group) {
     TCF_PANEL_CASE(0)
     TCF_PANEL_CASE(1)
     TCF_PANEL_CASE(2)
     TCF_PANEL_CASE(3)
+    TCF_PANEL_CASE(4)
     default:
-      TCF_TIMED_LAUNCH((k_panel_w<T, 4>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, xv, xld,
-                       gidx, y, yld, ymap, qslot, done, R);
       break;
   }
 #undef TCF_PANEL_CASE
@@ -2703,31 +2648,6 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
                   int xld, const int* gidx, const double* gsgn, double scale, double* y,
                   int yld, const int* ymap, double* qslot, const int* done, hipStream_t st) {
   if (njobs == 0) return;
-  if (R > 4) {  // many right-hand sides: the matrix-core form
-    switch (group) {
-      case 0:
-        launch_tiles_wide<T, 0>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
-                                qslot, done, st);
-        break;
-      case 1:
-        launch_tiles_wide<T, 1>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
-                                qslot, done, st);
-        break;
-      case 2:
-        launch_tiles_wide<T, 2>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
-                                qslot, done, st);
-        break;
-      case 3:
-        launch_tiles_wide<T, 3>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
-                                qslot, done, st);
-        break;
-      default:
-        launch_tiles_wide<T, 4>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap,
-                                qslot, done, st);
-        break;
-    }
-    return;
-  }
   switch (group) {
     case 0:
       launch_tiles_g<T, 0>(R, jobs, njobs, M, xv, xld, gidx, gsgn, scale, y, yld, ymap, qslot,

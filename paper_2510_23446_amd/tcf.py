@@ -28,7 +28,7 @@ EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint
            "tcf_step", "tcf_step_noalloc", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
            "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
-           "tcf_profile_get", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
+           "tcf_profile_get", "tcf_profile_get_flops", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
            "tcf_server_poll", "tcf_server_wait", "tcf_server_fetch", "tcf_server_stats",
            "tcf_server_error", "tcf_server_destroy"]
 TCF_REQ_QUEUED, TCF_REQ_RUNNING, TCF_REQ_DONE, TCF_REQ_FAILED = range(4)
@@ -110,7 +110,8 @@ class tcf_stats(C.Structure):
                 ("cond_est_patch", C.c_int32), ("coarse_nodes", C.c_int32),
                 ("coarse_launches", C.c_int32), ("coarse_root", C.c_int32),
                 ("setup_chunks", C.c_int32), ("coarse_bytes", C.c_double),
-                ("device_bytes_peak", C.c_size_t)]
+                ("device_bytes_peak", C.c_size_t), ("rhs_batch", C.c_int32),
+                ("panel_jobs", C.c_int32)]
 
 
 class tcf_server_report(C.Structure):
@@ -154,6 +155,7 @@ def lib():
     L.tcf_profile_enable.argtypes = [P, C.c_int32]
     L.tcf_profile_get.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double)]
+    L.tcf_profile_get_flops.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
     L.tcf_copy_probe.argtypes = [C.c_size_t, P]
     L.tcf_destroy.argtypes = [P]
     L.tcf_destroy.restype = None
@@ -467,6 +469,15 @@ class Problem:
             ms, n, b = C.c_double(), C.c_int64(), C.c_double()
             self._check(lib().tcf_profile_get(self.h, g, C.byref(ms), C.byref(n), C.byref(b)))
             out[name] = (ms.value, n.value, b.value)
+        return out
+
+    def tcf_profile_get_flops(self):
+        """{group: algorithmic flops per launch}"""
+        out = {}
+        for g, name in enumerate(KERNEL_GROUPS):
+            f = C.c_double()
+            self._check(lib().tcf_profile_get_flops(self.h, g, C.byref(f)))
+            out[name] = f.value
         return out
 
     def tcf_destroy(self):
