@@ -163,7 +163,7 @@ struct tcf_problem {
   TileJob *tj_cfwd = nullptr, *tj_cbwd = nullptr;
   int* d_cT = nullptr;    // index table of the sweeps: identity over [b | y | x], then the
                           // structure lists as b and as x positions
-  double* d_cw1 = nullptr;  // one-column coarse work vector [b | y | x] (n_Pi each)
+  double* d_cw1 = nullptr;  // coarse work block, rb columns [b | y | x] (n_Pi each)
   double* d_cL = nullptr;   // per node below the top: [L_JJ^-1 | -L_JJ^-T L_SJ^T]
   // matrix-core path (rb > 4): operators as row panels (symmetric ones whole)
   bool wide = false;
@@ -172,8 +172,8 @@ struct tcf_problem {
   PanelTile* d_ptile = nullptr;           // the tiles of every panel
   double* d_xg = nullptr;                 // gathered panel inputs, max(n_b, n_p) x rb
   PanelJob *pj_apply = nullptr, *pj_phi = nullptr, *pj_pre = nullptr, *pj_root = nullptr,
-           *pj_cfwd = nullptr, *pj_cbwd = nullptr;
-  int n_papply = 0, n_pphi = 0, n_ppre = 0, n_proot = 0;
+           *pj_cfwd = nullptr, *pj_cbwd = nullptr, *pj_gt = nullptr;
+  int n_papply = 0, n_pphi = 0, n_ppre = 0, n_proot = 0, n_pgt = 0;
 
   DevPatch* dP = nullptr;
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
@@ -193,7 +193,7 @@ struct tcf_problem {
   int *d_all = nullptr, *d_all_cprefix = nullptr, *d_all_rprefix = nullptr;
   int nt_all_c = 0, nt_all_r = 0;
   double *d_uc = nullptr, *d_vc = nullptr, *d_wb = nullptr, *d_tb = nullptr;
-  double *d_h = nullptr, *d_q0 = nullptr, *d_cv = nullptr, *d_q = nullptr;
+  double *d_h = nullptr, *d_q0 = nullptr;
   double *d_d = nullptr, *d_lam = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr,
          *d_Fp = nullptr;
   double *d_part = nullptr;  // 3 partial arrays
@@ -491,6 +491,7 @@ size_t tcf_problem::footprint(int prec) const {
   vec += ((double)n_bptot * 16 + (double)n_btot * 16 + (double)n_lambda * 8 * 8) * rb;
   vec += (double)rb * (n_bptot + 3 * npm + n_btot + 2 * TCF_QSLOTS) * 8 + npm * 8 * (4 + rb);
   if (wide) vec += (double)std::max(n_btot, n_ptot) * rb * 8;  // gathered panel inputs
+  vec += ((double)n_bptot + 3 * npm) * rb * 8;  // per-column v and coarse work block
   vec += (double)(tab_elems + ptab_elems) * 8 + (double)n_rtot * 24 + (double)n_loctot * 4;
   vec += (double)g.n_edges() * 8 + (double)n_rtot * 8;  // field, copy maps
   if (ainit && !cond_list.empty()) vec += (double)n_rtot * n_rhs * 8;  // initial load
@@ -1753,14 +1754,12 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   HIPCHK(hipMemsetAsync(h->d_fM, 0, sizeof(double) * ldv * nrhs, st));
   const int rb = h->rb;
   RCCHK(h->alloc(&h->d_uc, (size_t)h->n_bptot * rb));
-  RCCHK(h->alloc(&h->d_vc, h->n_bptot));
+  RCCHK(h->alloc(&h->d_vc, (size_t)h->n_bptot * rb));
   RCCHK(h->alloc(&h->d_wb, h->n_btot));
   RCCHK(h->alloc(&h->d_tb, h->n_btot));
   const int nP = std::max(h->n_primal, 1);
   RCCHK(h->alloc(&h->d_h, (size_t)nP * rb));
   RCCHK(h->alloc(&h->d_q0, nP));
-  RCCHK(h->alloc(&h->d_cv, nP));
-  RCCHK(h->alloc(&h->d_q, nP));
   const int nl = std::max(h->n_lambda, 1);
   RCCHK(h->alloc(&h->d_d, (size_t)nl * rb));
   RCCHK(h->alloc(&h->d_lam, (size_t)nl * rb));
@@ -1915,7 +1914,7 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   const int npm = std::max(h->n_primal, 1);
   std::vector<PackJob> pa, pb, pc, pl;
   std::vector<PanelTile> tl;
-  std::vector<PanelJob> japp, jphi, jpre, jroot;
+  std::vector<PanelJob> japp, jphi, jpre, jroot, jgt;
   std::vector<std::vector<PanelJob>> fw(h->c_levels), bw(h->c_levels);
   int64_t oa = 0, ob = 0, oc = 0;
   auto begin = [&](int64_t off, int yr_off, int nr, int xr_off, int flags) {
@@ -1954,7 +1953,15 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       for (int J = 0; J < Tb; ++J)
         add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, 64 * J, nrb(I), nrb(J), 0,
                        d.b_off + 64 * J);
+      const size_t a0 = japp.size();
       finish(japp, j, wT);
+      // G^T x unassembled (the dual-primal solve's pre and post phases):
+      // the same tiles into the patch's bp block, no quadratic form
+      for (size_t q = a0; q < japp.size(); ++q) {
+        PanelJob g = japp[q];
+        g.flags = japp.size() - a0 > 1 ? 1 : 0;
+        jgt.push_back(g);
+      }
       // preconditioner: S_bb rows (tb, with r.z)
       PanelJob q = begin(ob, d.b_off + 64 * I, nrb(I), d.b_off + 64 * I, 4);
       for (int J = 0; J < Tb; ++J)
@@ -1967,7 +1974,14 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       for (int I = 0; I < Tb; ++I)
         add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 1,
                        d.b_off + 64 * I);
+      const size_t a0 = japp.size();
       finish(japp, j, wT);
+      for (size_t q = a0; q < japp.size(); ++q) {
+        PanelJob g = japp[q];
+        g.yr_off = d.bp_off + d.n_b + 64 * K;
+        g.flags = japp.size() - a0 > 1 ? 1 : 0;
+        jgt.push_back(g);
+      }
     }
     for (int I = 0; I < Tb && Tp > 0; ++I) {
       // coarse correction vc += Phi_b N q (inputs q through the primal ranks)
@@ -2070,13 +2084,15 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   }
   RCCHK(h->upload(&h->d_ptile, tl));
   RCCHK(h->upload(&h->pj_apply, japp));
+  RCCHK(h->upload(&h->pj_gt, jgt));
+  h->n_pgt = (int)jgt.size();
   RCCHK(h->upload(&h->pj_phi, jphi));
   RCCHK(h->upload(&h->pj_pre, jpre));
   RCCHK(h->upload(&h->pj_root, jroot));
   RCCHK(h->upload(&h->pj_cfwd, f));
   RCCHK(h->upload(&h->pj_cbwd, b));
   RCCHK(h->upload(&h->d_cT, ctab));
-  RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm));
+  RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm * h->rb));
   RCCHK(h->alloc(&h->d_xg, (size_t)std::max<int64_t>(std::max(h->n_btot, h->n_ptot), 1) * h->rb));
   h->n_papply = (int)japp.size();
   h->n_pphi = (int)jphi.size();
@@ -2230,7 +2246,7 @@ static int build_tiles_narrow(tcf_problem* h, hipStream_t st) {
     RCCHK(h->upload(&h->tj_cfwd, f));
     RCCHK(h->upload(&h->tj_cbwd, b));
     RCCHK(h->upload(&h->d_cT, ctab));
-    RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm));
+    RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm * h->rb));
   }
   RCCHK(h->upload(&h->tj_apply, ja));
   RCCHK(h->upload(&h->tj_phi, jphi));
@@ -2279,10 +2295,8 @@ static void phi_apply(tcf_problem* h, const double* base_bp, double alpha, const
                       double* wb, const int* done, hipStream_t st) {
   launch_scatter((int)h->n_btot, nullptr, h->d_b2bp, base_bp, 1.0, wb, done, st);
   if (h->n_primal > 0)
-    timed(h, TCF_KG_PHI, st, [&] {
-      launch_axpyrows<T>(h->aj_phi, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, (const T*)h->d_G,
-                         q, h->d_prank, wb, h->a_boff_b, alpha, wb, 0, done, st);
-    });
+    launch_axpyrows<T>(h->aj_phi, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, (const T*)h->d_G, q,
+                       h->d_prank, wb, h->a_boff_b, alpha, wb, 0, done, st);
 }
 
 // x = S_Pi^-1 b on R columns of a coarse work block [b | y | x] (n_Pi
@@ -2335,23 +2349,13 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
   }
 }
 
-// out = S_Pi^-1 in (one column, through the one-column work block)
-static void coarse_solve1(tcf_problem* h, const double* in, double* out, hipStream_t st) {
-  if (h->n_primal == 0) return;
+// Coarse solves of a batch's columns at once: column j of the coarse work
+// block (stride 3 n_Pi) holds its right-hand side in its b part, with y and
+// x cleared; the solutions land in the x parts.
+static void coarse_solve_cols(tcf_problem* h, int ncols, hipStream_t st) {
+  if (h->n_primal == 0 || ncols == 0) return;
   const int npm = std::max(h->n_primal, 1);
-  launch_zero(3 * (int64_t)npm, h->d_cw1, st);
-  launch_axpby(h->n_primal, 1.0, in, 0.0, h->d_cw1, st);
-  coarse_sweeps(h, 1, h->d_cw1, 3 * npm, nullptr, nullptr, st);
-  launch_axpby(h->n_primal, 1.0, h->d_cw1 + 2 * npm, 0.0, out, st);
-}
-
-// out = S_Pi^-1 (extra + sum_s N_s^T c_s), c_s = the primal part of a bp-vector
-static void coarse_solve(tcf_problem* h, const double* bp, const double* extra, double* out,
-                         hipStream_t st) {
-  if (h->n_primal == 0) return;
-  launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, bp, 1.0,
-                       extra, h->d_cv, nullptr, st);
-  coarse_solve1(h, h->d_cv, out, st);
+  coarse_sweeps(h, ncols, h->d_cw1, 3 * npm, nullptr, nullptr, st);
 }
 
 // Views into the tile path's accumulator block (see pcg_iteration).
@@ -2641,63 +2645,146 @@ static void condense_batch(tcf_problem* h, int k0, int nc, int l, const double* 
   }
 }
 
-// Dual-primal solve of W x = f, split around the (batched) PCG, with f
-// condensed into ygg of excitation k beforehand (condense_batch).  If
-// base != nullptr the solution is a correction to base and the interface
-// constraint is Bhat (base + x) = 0, i.e. the dual right-hand side becomes
-// d + Bhat base.  Column j of the PCG vectors carries it.
+// Dual-primal solves of W x = f, split around the batched PCG, for the
+// columns cols of a batch whose excitations start at k0 (column j carries
+// excitation k0 + j), with f condensed into ygg beforehand (condense_batch).
+// With corr the solutions are corrections to the fields a and the interface
+// constraint is Bhat (a + x) = 0, i.e. the dual right-hand side becomes
+// d + Bhat a.  The coarse solves of all columns run as one batch.
 //
 // solve_pre: [u; c0] = G^T g_b, h = sum N^T (g_p - c0), q0 = S_Pi^-1 h,
-// d = jump(u - Phi N q0) into column j.
+// d = jump(u - Phi N q0) into column j of the PCG's right-hand sides.
 template <class T>
-static void solve_pre(tcf_problem* h, int k, const double* base, int j, hipStream_t st) {
+static void solve_pre(tcf_problem* h, int k0, const std::vector<int>& cols, bool corr,
+                      hipStream_t st) {
   const int64_t ldv = h->n_rtot;
-  double* ygg = h->d_ygg + (int64_t)k * ldv;
+  const int npm = std::max(h->n_primal, 1);
   const T* G = (const T*)h->d_G;
-  double* uc = h->d_uc + (int64_t)j * h->n_bptot;
-  double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
-  double* dv = h->d_d + (int64_t)j * h->n_lambda;
-  if (h->bp_gaps) launch_zero(h->n_bptot, uc, st);
-  launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg, nullptr,
-                    nullptr, 1.0, uc, nullptr, st);
-  if (h->n_primal > 0) {
-    launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, uc, -1.0,
-                         nullptr, hv, nullptr, st);
-    coarse_solve1(h, hv, h->d_q0, st);
+  if (cols.empty()) return;
+  const int ncols = cols.back() + 1;
+  const int nb = (int)h->n_btot, np = (int)h->n_ptot;
+  if (h->n_primal > 0) launch_zero((int64_t)3 * npm * ncols, h->d_cw1, st);
+  if (h->wide) {
+    // [u; c0] of every column at once through the row panels of G^T
+    launch_gather_cols(ncols, nb, h->d_b2r, nullptr, 1.0, h->d_ygg + (int64_t)k0 * ldv, (int)ldv,
+                       h->d_xg, nb, nullptr, st);
+    launch_zero(h->n_bptot * ncols, h->d_uc, st);
+    launch_panels<T>(0, ncols, h->pj_gt, h->d_ptile, h->n_pgt, (const T*)h->d_pA, h->d_xg, nb,
+                     nullptr, h->d_uc, (int)h->n_bptot, nullptr, nullptr, nullptr, st);
   }
-  phi_apply<T>(h, uc, -1.0, h->d_q0, h->d_wb, nullptr, st);
-  launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, dv, nullptr, nullptr, nullptr,
-              st);
-  if (base) launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, base, h->dt, dv, st);
+  for (int j : cols) {
+    const double* ygg = h->d_ygg + (int64_t)(k0 + j) * ldv;
+    double* uc = h->d_uc + (int64_t)j * h->n_bptot;
+    double* hv = h->d_h + (int64_t)j * npm;
+    if (!h->wide) {
+      if (h->bp_gaps) launch_zero(h->n_bptot, uc, st);
+      launch_dotcols<T>(h->dj_app_v, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 0, ygg,
+                        nullptr, nullptr, 1.0, uc, nullptr, st);
+    }
+    if (h->n_primal > 0) {
+      launch_coarse_gather(h->n_primal, h->d_cptr, h->d_cidx_r, ygg, 1.0, h->d_cidx_bp, uc, -1.0,
+                           nullptr, hv, nullptr, st);
+      launch_axpby(h->n_primal, 1.0, hv, 0.0, h->d_cw1 + (int64_t)j * 3 * npm, st);
+    }
+  }
+  coarse_solve_cols(h, ncols, st);
+  if (h->wide) {
+    // v = u - Phi_b N q0 of every column (bp space) through the Phi panels
+    launch_axpby(h->n_bptot * ncols, 1.0, h->d_uc, 0.0, h->d_vc, st);
+    if (h->n_primal > 0) {
+      launch_gather_cols(ncols, np, h->d_prank, nullptr, -1.0, h->d_cw1 + 2 * npm, 3 * npm,
+                         h->d_xg, np, nullptr, st);
+      launch_panels<T>(1, ncols, h->pj_phi, h->d_ptile, h->n_pphi, (const T*)h->d_pA, h->d_xg, np,
+                       nullptr, h->d_vc, (int)h->n_bptot, nullptr, nullptr, nullptr, st);
+    }
+  }
+  for (int j : cols) {
+    const double* uc = h->d_uc + (int64_t)j * h->n_bptot;
+    const double* q0 = h->n_primal > 0 ? h->d_cw1 + (int64_t)j * 3 * npm + 2 * npm : h->d_q0;
+    double* dv = h->d_d + (int64_t)j * h->n_lambda;
+    if (h->wide)
+      launch_scatter(nb, nullptr, h->d_b2bp, h->d_vc + (int64_t)j * h->n_bptot, 1.0, h->d_wb,
+                     nullptr, st);
+    else
+      phi_apply<T>(h, uc, -1.0, q0, h->d_wb, nullptr, st);
+    launch_jump(h->n_lambda, h->d_posp, h->d_posm, h->d_wb, h->dt, dv, nullptr, nullptr, nullptr,
+                st);
+    if (corr)
+      launch_jump_add(h->n_lambda, h->d_posp_r, h->d_posm_r, h->d_a + (int64_t)(k0 + j) * ldv,
+                      h->dt, dv, st);
+  }
 }
 
-// solve_post (column j, lambda from the PCG): p = S_Pi^-1 (h + sum N^T Phi^T
-// x) with x = Bhat^T lambda; x_b = (u - v) - Phi N p; x_p = N p; and the
-// right-hand side of the interior recovery, z = [y; -x_b; -x_p], into column
-// j of d_zr.  The interior unknowns follow for the whole batch in
-// recover_batch.  Writes into x_out (kept order).
+// solve_post (lambda of column j from the PCG): p = S_Pi^-1 (h + sum N^T
+// Phi^T x) with x = Bhat^T lambda; x_b = (u - v) - Phi N p; x_p = N p; and
+// the right-hand side of the interior recovery, z = [y; -x_b; -x_p], into
+// column j of d_zr.  The interior unknowns follow for the whole batch in
+// recover_batch.  Writes column j's solution (kept order) at
+// out + j * n_rtot.
 template <class T>
-static void solve_post(tcf_problem* h, int k, int j, double* x_out, hipStream_t st) {
+static void solve_post(tcf_problem* h, int k0, const std::vector<int>& cols, double* out,
+                       hipStream_t st) {
   const int64_t ldv = h->n_rtot;
-  double* ygg = h->d_ygg + (int64_t)k * ldv;
+  const int npm = std::max(h->n_primal, 1);
   const T* G = (const T*)h->d_G;
-  const double* uc = h->d_uc + (int64_t)j * h->n_bptot;
-  const double* hv = h->d_h + (int64_t)j * std::max(h->n_primal, 1);
-  const double* lam = h->d_lam + (int64_t)j * h->n_lambda;
-  if (h->n_lambda == 0 || h->bp_gaps) launch_zero(std::max<int64_t>(h->n_bptot, 1), h->d_vc, st);
-  if (h->n_lambda > 0)
-    launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, lam,
-                      h->d_brow, h->d_bsgn, h->dt, h->d_vc, nullptr, st);
-  coarse_solve(h, h->d_vc, hv, h->d_q, st);
-  launch_sub_gather((int)h->n_btot, h->d_b2bp, uc, h->d_b2bp, h->d_vc, h->d_tb, st);
-  launch_scatter((int)h->n_btot, h->d_b2r, nullptr, h->d_tb, 1.0, x_out, nullptr, st);
-  if (h->n_primal > 0) {
-    if (h->nj_phi > 0)
-      launch_axpyrows<T>(h->aj_ab, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, G, h->d_q,
-                         h->d_prank, x_out, h->a_boff_ab, -1.0, x_out, 0, nullptr, st);
-    launch_scatter((int)h->n_ptot, h->d_p2r, h->d_prank, h->d_q, 1.0, x_out, nullptr, st);
+  if (cols.empty()) return;
+  const int ncols = cols.back() + 1;
+  const int nb = (int)h->n_btot, np = (int)h->n_ptot;
+  if (h->n_primal > 0) launch_zero((int64_t)3 * npm * ncols, h->d_cw1, st);
+  if (h->wide) {
+    // G^T x of every column at once, x = dt Bhat^T lambda
+    launch_zero(h->n_bptot * ncols, h->d_vc, st);
+    if (h->n_lambda > 0) {
+      launch_gather_cols(ncols, nb, h->d_brow, h->d_bsgn_d, h->dt, h->d_lam, h->n_lambda,
+                         h->d_xg, nb, nullptr, st);
+      launch_panels<T>(0, ncols, h->pj_gt, h->d_ptile, h->n_pgt, (const T*)h->d_pA, h->d_xg, nb,
+                       nullptr, h->d_vc, (int)h->n_bptot, nullptr, nullptr, nullptr, st);
+    }
   }
-  launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr + (int64_t)j * ldv, st);
+  for (int j : cols) {
+    double* vc = h->d_vc + (int64_t)j * h->n_bptot;
+    const double* lam = h->d_lam + (int64_t)j * h->n_lambda;
+    if (!h->wide) {
+      if (h->n_lambda == 0 || h->bp_gaps) launch_zero(std::max<int64_t>(h->n_bptot, 1), vc, st);
+      if (h->n_lambda > 0)
+        launch_dotcols<T>(h->dj_app_g, h->dp_app, h->nj_app, h->nt_app, h->max_nb, G, 1, lam,
+                          h->d_brow, h->d_bsgn, h->dt, vc, nullptr, st);
+    }
+    if (h->n_primal > 0)
+      launch_coarse_gather(h->n_primal, h->d_cptr, nullptr, nullptr, 0.0, h->d_cidx_bp, vc, 1.0,
+                           h->d_h + (int64_t)j * npm, h->d_cw1 + (int64_t)j * 3 * npm, nullptr,
+                           st);
+  }
+  coarse_solve_cols(h, ncols, st);
+  if (h->wide) {
+    // x_b = (u - v) - Phi_b N p of every column, in bp space
+    launch_axpby(h->n_bptot * ncols, 1.0, h->d_uc, -1.0, h->d_vc, st);
+    if (h->n_primal > 0) {
+      launch_gather_cols(ncols, np, h->d_prank, nullptr, -1.0, h->d_cw1 + 2 * npm, 3 * npm,
+                         h->d_xg, np, nullptr, st);
+      launch_panels<T>(1, ncols, h->pj_phi, h->d_ptile, h->n_pphi, (const T*)h->d_pA, h->d_xg, np,
+                       nullptr, h->d_vc, (int)h->n_bptot, nullptr, nullptr, nullptr, st);
+    }
+  }
+  for (int j : cols) {
+    const double* ygg = h->d_ygg + (int64_t)(k0 + j) * ldv;
+    const double* uc = h->d_uc + (int64_t)j * h->n_bptot;
+    const double* vc = h->d_vc + (int64_t)j * h->n_bptot;
+    const double* q = h->d_cw1 + (int64_t)j * 3 * npm + 2 * npm;
+    double* x_out = out + (int64_t)j * ldv;
+    if (h->wide) {
+      launch_scatter(nb, h->d_b2r, h->d_b2bp, vc, 1.0, x_out, nullptr, st);
+    } else {
+      launch_sub_gather(nb, h->d_b2bp, uc, h->d_b2bp, vc, h->d_tb, st);
+      launch_scatter(nb, h->d_b2r, nullptr, h->d_tb, 1.0, x_out, nullptr, st);
+      if (h->n_primal > 0 && h->nj_phi > 0)
+        launch_axpyrows<T>(h->aj_ab, h->ap_phi, h->nj_phi, h->nt_phi, h->max_np, G, q,
+                           h->d_prank, x_out, h->a_boff_ab, -1.0, x_out, 0, nullptr, st);
+    }
+    if (h->n_primal > 0)
+      launch_scatter(np, h->d_p2r, h->d_prank, q, 1.0, x_out, nullptr, st);
+    launch_build_z(ldv, h->d_isint, ygg, x_out, h->d_zr + (int64_t)j * ldv, st);
+  }
 }
 
 // Interior recovery x_i = Q^T z of the nc columns of a batch (column j of
@@ -2843,7 +2930,9 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   // first solve: the time-step right-hand side of every excitation
   h->cur_sweep = 0;
   condense_batch<T>(h, k0, nc, l, nullptr, st);
-  for (int j = 0; j < nc; ++j) solve_pre<T>(h, k0 + j, nullptr, j, st);
+  std::vector<int> cols_all(nc);
+  std::iota(cols_all.begin(), cols_all.end(), 0);
+  solve_pre<T>(h, k0, cols_all, false, st);
   zero_idle(all);
   if (h->d_px) {
     for (int j = 0; j < R; ++j) {
@@ -2887,7 +2976,7 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   }
   if (h->d_px)
     for (int j = 0; j < nc; ++j) proj_update(h, k0 + j, j, st);
-  for (int j = 0; j < nc; ++j) solve_post<T>(h, k0 + j, j, h->d_a + (int64_t)(k0 + j) * ldv, st);
+  solve_post<T>(h, k0, cols_all, h->d_a + (int64_t)k0 * ldv, st);
   recover_batch<T>(h, nc, h->d_a + (int64_t)k0 * ldv, st);
   collect(all);
   for (int j = 0; j < nc; ++j) sweeps[j] = 1;
@@ -2941,12 +3030,13 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
         launch_assemble_split(h->n_kept_i, h->d_kptr, h->d_kidx, h->d_res + (int64_t)j * ldv, st);
     // (columns of settled excitations are condensed too and left unused)
     condense_batch<T>(h, k0, nc, l, h->d_res, st);
+    std::vector<int> cols_act;
     for (int j = 0; j < nc; ++j)
-      if (active[j]) solve_pre<T>(h, k0 + j, h->d_a + (int64_t)(k0 + j) * ldv, j, st);
+      if (active[j]) cols_act.push_back(j);
+    solve_pre<T>(h, k0, cols_act, true, st);
     zero_idle(active);
     RCCHK(run_pcg());
-    for (int j = 0; j < nc; ++j)
-      if (active[j]) solve_post<T>(h, k0 + j, j, h->d_delta + (int64_t)j * ldv, st);
+    solve_post<T>(h, k0, cols_act, h->d_delta, st);
     recover_batch<T>(h, nc, h->d_delta, st);
     for (int j = 0; j < nc; ++j) {
       if (!active[j]) continue;
