@@ -1517,7 +1517,9 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   TO *G, *S, *Q;
   RCCHK(h->alloc(&S, h->S_elems));
   RCCHK(h->alloc(&G, h->G_elems));
-  RCCHK(h->alloc(&Q, h->Q_elems));
+  // 64 elements of slack: the matrix-core Q^T products read up to 63 rows
+  // past a patch's last column (and discard them)
+  RCCHK(h->alloc(&Q, h->Q_elems + 64));
   h->d_G = G;
   h->d_S = S;
   h->d_Q = Q;
@@ -1575,7 +1577,7 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   if (!kSame) {
     RCCHK(h->alloc(&Gt, (size_t)std::max<int64_t>(h->G_chunk_max, 1)));
     RCCHK(h->alloc(&St, (size_t)std::max<int64_t>(h->S_chunk_max, 1)));
-    RCCHK(h->alloc(&Qt, (size_t)std::max<int64_t>(h->Q_chunk_max, 1)));
+    RCCHK(h->alloc(&Qt, (size_t)std::max<int64_t>(h->Q_chunk_max, 1) + 64));
   }
   DevPatch* dPc;
   RCCHK(h->alloc(&dPc, (size_t)np));

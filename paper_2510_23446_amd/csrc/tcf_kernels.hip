@@ -48,6 +48,20 @@ struct Mfma16<float> {
 
 namespace tcf {
 
+// 16-byte vector of stored matrix entries (2 doubles or 4 floats)
+template <class T>
+struct TileVec;
+template <>
+struct TileVec<double> {
+  typedef double v __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+template <>
+struct TileVec<float> {
+  typedef float v __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+
 // ===========================================================================
 // 1-D splines on one patch row (open uniform knots)
 // ===========================================================================
@@ -319,28 +333,34 @@ __global__ void k_assemble(const DevPatch* P, const int* col_prefix, int np, con
 
 // Matrix-free y = W x (full) or y = sigma M x (mass only) on the kept
 // unknowns of each listed patch, FP64.  x, y are kept-ordered vectors.
+template <int C>
 __global__ void k_wapply(const DevPatch* P, const int* plist, const int* row_prefix, int nlist,
                          const int* r_loc, const int* loc2r, const double* tabs, double dt,
-                         int mass_only, const double* x, double* y, int64_t ldv) {
+                         int mass_only, int nrhs, const double* x, double* y, int64_t ldv) {
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= row_prefix[nlist]) return;
   const int li = find_job(row_prefix, nlist, gi);
   const int s = plist[li];
   const DevPatch& pp = P[s];
   const int j = gi - row_prefix[li];
-  const int rhs = blockIdx.y;
+  // columns rhs0 .. rhs0 + C - 1 (those below nrhs): each matrix entry is
+  // formed once and applied to all of them
+  const int rhs0 = blockIdx.y * C;
+  const int nc = min(C, nrhs - rhs0);
   const Tab1 X = make_tab(pp, tabs, 0), Y = make_tab(pp, tabs, 1), Z = make_tab(pp, tabs, 2);
   const EdgeCode u = decode_local(pp, r_loc[pp.r_off + j]);
-  const double* xs = x + (int64_t)rhs * ldv + pp.r_off;
+  const double* xs = x + (int64_t)rhs0 * ldv + pp.r_off;
   const int* l2r = loc2r + pp.loc_off;
-  double acc = 0.0;
+  double acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = 0.0;
   const int px = pp.deg[0], py = pp.deg[1], pz = pp.deg[2];
   for (int dir = 0; dir < 3; ++dir) {
     if (mass_only && dir != u.dir) continue;
-    const int na = pp.m[0] - (dir == 0), nb = pp.m[1] - (dir == 1), nc = pp.m[2] - (dir == 2);
+    const int na = pp.m[0] - (dir == 0), nb = pp.m[1] - (dir == 1), nc3 = pp.m[2] - (dir == 2);
     const int a0 = max(0, u.a - px), a1 = min(na - 1, u.a + px);
     const int b0 = max(0, u.b - py), b1 = min(nb - 1, u.b + py);
-    const int c0 = max(0, u.c - pz), c1 = min(nc - 1, u.c + pz);
+    const int c0 = max(0, u.c - pz), c1 = min(nc3 - 1, u.c + pz);
     for (int c = c0; c <= c1; ++c)
       for (int b = b0; b <= b1; ++b)
         for (int a = a0; a <= a1; ++a) {
@@ -349,10 +369,14 @@ __global__ void k_wapply(const DevPatch* P, const int* plist, const int* row_pre
           double M, K;
           mk_entry(X, Y, Z, u, EdgeCode{dir, a, b, c}, M, K);
           const double wv = mass_only ? pp.sigma * M : pp.sigma * M + pp.nu * dt * K;
-          acc += wv * xs[r2];
+#pragma unroll
+          for (int q = 0; q < C; ++q)
+            if (q < nc) acc[q] += wv * xs[(int64_t)q * ldv + r2];
         }
   }
-  y[(int64_t)rhs * ldv + pp.r_off + j] = acc;
+#pragma unroll
+  for (int q = 0; q < C; ++q)
+    if (q < nc) y[(int64_t)(rhs0 + q) * ldv + pp.r_off + j] = acc[q];
 }
 
 // Curl-form load of one patch: jhat_e = int phi (curl w_e)_z, with
@@ -1162,59 +1186,81 @@ __global__ void __launch_bounds__(256) k_condense(const DevPatch* P, const int* 
 // The same products for many right-hand sides at once on the matrix cores
 // (v_mfma_f64_16x16x4, FP64 accumulation; up to 32 columns, two 16-wide
 // accumulators per wave), so that Q^T is read once per step for a whole
-// batch of excitations instead of once per excitation.  A block takes a
-// 64 x 64 block of Q^T (rows = interior unknowns, columns = kept
-// unknowns) and the matching 64 rows of the right-hand sides through LDS
-// per step of 64 along the contracted index.
+// batch of excitations instead of once per excitation.  A block owns 64
+// output rows (interior unknowns for the recovery, kept unknowns for the
+// condensation) and streams the 64 x 64 blocks of Q^T along the contracted
+// index: each lane loads its matrix operands straight from Q^T's column-major
+// storage into registers, one block ahead, and only the right-hand sides go
+// through LDS (two buffers, one barrier per block).  Loads are issued
+// unconditionally, from clamped addresses where they have nothing to read
+// (the Q buffers carry 64 elements of slack at their end for the rows past a
+// patch's last column), so the waits stay exact.
 // ---------------------------------------------------------------------------
-// stage Q^T[r0 .. r0 + 64, c0 .. c0 + 64) (zero outside rows < nr, cols < nc)
-template <class T>
-__device__ inline void stage_q(const T* Mq, int64_t ld, int r0, int c0, int nr, int nc,
-                               double (*Qs)[65]) {
-  const int t = threadIdx.x;
-  const int c = t >> 2, rq = (t & 3) * 16;  // column c, rows rq .. rq + 15
-  const bool cok = c0 + c < nc;
-  const T* src = Mq + (int64_t)(c0 + (cok ? c : 0)) * ld + r0 + rq;
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int r = r0 + rq + u;
-    Qs[rq + u][c] = (cok && r < nr) ? (double)src[u] : 0.0;
-  }
-}
 
 // Condensation of R right-hand sides (columns j of f and ygg at j * ldv):
 // ygg[c] += (c < n_i) ? (Q^T[:, c] . f_i) : (f[c] - Q^T[:, c] . f_i).  One
-// block per 64 columns of a listed patch (prefix over ceil(n_r / 64)).
+// block per 64 columns of a listed patch (prefix over ceil(n_r / 64)).  The
+// contraction runs over interior rows, in an order of its own (the k order
+// of a product is free as long as both operands follow it): vector g of
+// lane (li, lk) holds the rows 4 V g + V lk .. + V - 1 of the 64-row block
+// in column li, so the 4 lanes of one column read 4 V consecutive entries
+// per load instruction (64 contiguous bytes per column).
 template <class T>
 __global__ void __launch_bounds__(256) k_condense_w(const DevPatch* P, const int* plist,
                                                     const int* prefix, int nlist, const T* Q,
                                                     const double* f, double* ygg, int64_t ldv,
                                                     int R) {
   typedef Mfma16<double> M;
+  typedef typename TileVec<T>::v VT;
+  constexpr int V = TileVec<T>::n, NV = 16 / V;  // vectors per lane per block
+  constexpr int XP = 65;                         // column stride of the staged f
   const int li_ = find_job(prefix, nlist, blockIdx.x);
   const DevPatch& pp = P[plist[li_]];
   const int c0 = (blockIdx.x - prefix[li_]) * 64;
-  __shared__ double Qs[64][65];
-  __shared__ double Fs[64][33];
+  __shared__ double Fs[2][32 * XP];
   const T* Mq = Q + pp.Q_off;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int ie = t & 63, jq = t >> 6;
   // Q^T[:, c] for c < n_i has nonzeros only in rows <= c
   const int rmax = c0 < pp.n_i ? min(pp.n_i, c0 + 64) : pp.n_i;
+  const int cl = min(c0 + 16 * w + li, pp.n_r - 1);  // this lane's column (clamped)
   M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-  for (int r0 = 0; r0 < rmax; r0 += 64) {
-    __syncthreads();
-    stage_q(Mq, pp.ni_pad, r0, c0, pp.n_i, pp.n_r, Qs);
-    for (int idx = t; idx < 64 * 32; idx += 256) {
-      const int r = idx & 63, j = idx >> 6;
-      Fs[r][j] = (j < R && r0 + r < pp.n_i) ? f[(int64_t)j * ldv + pp.r_off + r0 + r] : 0.0;
+  VT ra[NV];
+  double xg[8];
+  auto fetch = [&](int r0) {
+    const VT* src = reinterpret_cast<const VT*>(Mq + (int64_t)cl * pp.ni_pad + r0) + lk;
+#pragma unroll
+    for (int g = 0; g < NV; ++g) ra[g] = __builtin_nontemporal_load(src + 4 * g);
+    const int r = min(r0 + ie, pp.n_r - 1);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int j = jq + 4 * m;
+      xg[m] = f[(int64_t)(j < R ? j : 0) * ldv + pp.r_off + r];
     }
+  };
+  if (rmax > 0) fetch(0);
+  for (int r0 = 0, it = 0; r0 < rmax; r0 += 64, ++it) {
+    const int buf = it & 1;
+    VT rc[NV];
+#pragma unroll
+    for (int g = 0; g < NV; ++g) rc[g] = ra[g];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) Fs[buf][(jq + 4 * m) * XP + ie] = xg[m];
     __syncthreads();
-#pragma unroll 4
-    for (int k4 = 0; k4 < 16; ++k4) {
-      const double a = Qs[4 * k4 + lk][16 * w + li];
-      a0 = M::mma(a, Fs[4 * k4 + lk][li], a0);
-      if (R > 16) a1 = M::mma(a, Fs[4 * k4 + lk][16 + li], a1);
-    }
+    if (r0 + 64 < rmax) fetch(r0 + 64);
+    const double* fs = Fs[buf] + li * XP + V * lk;
+    const int rl = r0 + V * lk;  // row of this lane's first k-step
+#pragma unroll
+    for (int g = 0; g < NV; ++g)
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int k = 4 * V * g + e;  // row offset of this k-step from rl
+        // rows past n_i contract with zero (their storage may hold the next
+        // column's entries)
+        const double a = rl + k < pp.n_i ? (double)rc[g][e] : 0.0;
+        a0 = M::mma(a, fs[k], a0);
+        if (R > 16) a1 = M::mma(a, fs[16 * XP + k], a1);
+      }
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -1234,38 +1280,64 @@ __global__ void __launch_bounds__(256) k_condense_w(const DevPatch* P, const int
 // for r < n_i (column j of z and out at j * ldv); Q^T's leading block is
 // upper triangular, so column blocks before the row block are skipped.  One
 // block per 64 interior rows of a listed patch (prefix over ceil(n_i / 64)).
+// Lane (li, lk) loads Q^T[r0 + 16 w + li, c0 + 4 k + lk] for its 16 k-steps:
+// per load, 16 consecutive rows of 4 columns.
 template <class T>
 __global__ void __launch_bounds__(256) k_qapply_w(const DevPatch* P, const int* plist,
                                                   const int* prefix, int nlist, const T* Q,
                                                   const double* z, double* out, int64_t ldv,
                                                   int R) {
   typedef Mfma16<double> M;
+  constexpr int XP = 66;  // column stride of the staged z
   const int li_ = find_job(prefix, nlist, blockIdx.x);
   const DevPatch& pp = P[plist[li_]];
   const int r0 = (blockIdx.x - prefix[li_]) * 64;
-  __shared__ double Qs[64][65];
-  __shared__ double Zs[64][33];
-  const T* Mq = Q + pp.Q_off;
+  __shared__ double Zs[2][32 * XP];
+  const T* Mq = Q + pp.Q_off + r0 + 16 * ((threadIdx.x >> 6)) + (threadIdx.x & 15);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int ie = t & 63, jq = t >> 6;
+  (void)w;
   M::acc a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-  for (int c0 = r0 / 64 * 64; c0 < pp.n_r; c0 += 64) {
-    __syncthreads();
-    stage_q(Mq, pp.ni_pad, r0, c0, pp.n_i, pp.n_r, Qs);
-    for (int idx = t; idx < 64 * 32; idx += 256) {
-      const int c = idx & 63, j = idx >> 6;
-      Zs[c][j] = (j < R && c0 + c < pp.n_r) ? z[(int64_t)j * ldv + pp.r_off + c0 + c] : 0.0;
+  T ra[16];
+  double xg[8];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = min(c0 + 4 * k + lk, pp.n_r - 1);
+      ra[k] = __builtin_nontemporal_load(Mq + (int64_t)c * pp.ni_pad);
     }
+    const int c = c0 + ie;
+    const int cc = min(c, pp.n_r - 1);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int j = jq + 4 * m;
+      const double v = z[(int64_t)(j < R ? j : 0) * ldv + pp.r_off + cc];
+      // columns past n_r meet clamped (nonzero) matrix columns: zero inputs
+      xg[m] = c < pp.n_r ? v : 0.0;
+    }
+  };
+  const int cbeg = r0 / 64 * 64;
+  if (cbeg < pp.n_r) fetch(cbeg);
+  for (int c0 = cbeg, it = 0; c0 < pp.n_r; c0 += 64, ++it) {
+    const int buf = it & 1;
+    T rc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) rc[k] = ra[k];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) Zs[buf][(jq + 4 * m) * XP + ie] = xg[m];
     __syncthreads();
-#pragma unroll 4
-    for (int k4 = 0; k4 < 16; ++k4) {
-      const double a = Qs[16 * w + li][4 * k4 + lk];
-      a0 = M::mma(a, Zs[4 * k4 + lk][li], a0);
-      if (R > 16) a1 = M::mma(a, Zs[4 * k4 + lk][16 + li], a1);
+    if (c0 + 64 < pp.n_r) fetch(c0 + 64);
+    const double* zs = Zs[buf] + li * XP + lk;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double a = (double)rc[k];
+      a0 = M::mma(a, zs[4 * k], a0);
+      if (R > 16) a1 = M::mma(a, zs[16 * XP + 4 * k], a1);
     }
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int r = r0 + 16 * w + M::row(lk, e);
+    const int r = r0 + 16 * (t >> 6) + M::row(lk, e);
     if (r >= pp.n_i) continue;
     for (int h = 0; h < 2; ++h) {
       const int j = 16 * h + li;
@@ -1695,9 +1767,15 @@ void launch_wapply(const DevPatch* P, const int* plist, const int* row_prefix, i
                    int total_rows, int nrhs, const int* r_loc, const int* loc2r,
                    const double* tabs, double dt, int mass_only, const double* x, double* y,
                    int64_t ldv, hipStream_t st) {
-  if (total_rows == 0) return;
-  hipLaunchKernelGGL(k_wapply, dim3((total_rows + 127) / 128, nrhs), dim3(128), 0, st, P, plist,
-                     row_prefix, nlist, r_loc, loc2r, tabs, dt, mass_only, x, y, ldv);
+  if (total_rows == 0 || nrhs <= 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_wapply<1>, dim3((total_rows + 127) / 128, 1), dim3(128), 0, st, P,
+                       plist, row_prefix, nlist, r_loc, loc2r, tabs, dt, mass_only, nrhs, x, y,
+                       ldv);
+  else
+    hipLaunchKernelGGL(k_wapply<8>, dim3((total_rows + 127) / 128, (nrhs + 7) / 8), dim3(128), 0,
+                       st, P, plist, row_prefix, nlist, r_loc, loc2r, tabs, dt, mass_only, nrhs,
+                       x, y, ldv);
 }
 
 
@@ -2248,18 +2326,6 @@ __device__ inline double wave_sum_dpp(double v) {
 // V rows go through LDS and are summed by 4 threads per column.  Results are
 // added to y with FP64 atomics (a tile of a symmetric operator serves A_IJ
 // and A_IJ^T).
-template <class T>
-struct TileVec;
-template <>
-struct TileVec<double> {
-  typedef double v __attribute__((ext_vector_type(2)));
-  static constexpr int n = 2;
-};
-template <>
-struct TileVec<float> {
-  typedef float v __attribute__((ext_vector_type(4)));
-  static constexpr int n = 4;
-};
 
 // Group (the operator) fixes the input mode: 0 (F apply) and 2 (Dirichlet
 // preconditioner) take the signed gather scale * gsw[i] * xv[gidx[i]] (gsw:
