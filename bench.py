@@ -50,6 +50,12 @@ def parse():
                     help="excitations per batched PCG (0: automatic, up to 4)")
     ap.add_argument("--panel-chunk", type=int, default=0,
                     help="matrix-core path: tiles per job of a split row panel (0: default)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="matrix-core path: keep the fixed split length instead of timing "
+                         "the candidates at setup (or taking them from the tune table)")
+    ap.add_argument("--tune-table", default=os.path.join(ROOT, "paper_2510_23446_amd", "tune",
+                                                         "panels_mi355x.txt"),
+                    help="tuned split lengths by problem shape (read; new entries appended)")
     ap.add_argument("--pcg-warm", type=int, default=0, choices=[0, 1, 2, 3],
                     help="timed run: first solve of a step from the previous (1) or "
                          "extrapolated (2) multipliers, or from the projection onto the "
@@ -313,6 +319,23 @@ def serving(args):
     print(json.dumps(out))
 
 
+def panel_split(st):
+    """The row panels' split lengths per operator, where they came from, and
+    (when timed at setup) each operator's time per launch at the chosen
+    length next to the fixed default of 16 tiles."""
+    if st["rhs_batch"] <= 4:
+        return None
+    names = ["apply", "precond", "phi", "coarse"]
+    cands = [4, 8, 16, 32, "whole"]
+    src = {0: "fixed", 1: "tune table", 2: "timed at setup"}[st["panel_chunk_src"]]
+    out = {"source": src, "chunks": dict(zip(names, st["panel_chunk"]))}
+    t = st["panel_tune_us"]
+    if st["panel_chunk_src"] == 2:
+        out["us_per_launch"] = {n: dict(zip(map(str, cands), [round(v, 1) for v in t[5 * g:5 * g + 5]]))
+                                for g, n in enumerate(names)}
+    return out
+
+
 def timed_run(p, warmup, steps):
     """warmup untimed steps, then `steps` timed ones bracketed by syncs."""
     if warmup:
@@ -354,9 +377,11 @@ def main():
     # the largest workload's headline runs in FP64; its FP32-operator path
     # (the configuration's precision pattern) is the leg below
     prec = args.precision or ("fp64" if big else prob.precision)
+    tune = dict(autotune=0 if args.no_autotune else 1,
+                tune_table=None if args.no_autotune or not args.tune_table else args.tune_table)
     p = tcf.Problem(prob, precision=prec, use_graph=0 if args.no_graph else 1,
                     rhs_batch=args.rhs_batch, pcg_warm=args.pcg_warm,
-                    panel_chunk=args.panel_chunk)
+                    panel_chunk=args.panel_chunk, **tune)
     counts = p.counts()
     t0 = time.perf_counter()
     p.tcf_setup()
@@ -430,7 +455,7 @@ def main():
     fp32_leg = None
     if big and not args.no_fp32_leg:
         q = tcf.Problem(prob, precision="fp32_ir", use_graph=0 if args.no_graph else 1,
-                        rhs_batch=args.rhs_batch, panel_chunk=args.panel_chunk)
+                        rhs_batch=args.rhs_batch, panel_chunk=args.panel_chunk, **tune)
         tq = time.perf_counter()
         q.tcf_setup()
         q_setup = time.perf_counter() - tq
@@ -535,6 +560,7 @@ def main():
                    "graphs": not args.no_graph, "rhs_batch": args.rhs_batch or "auto",
                    "pcg_warm": args.pcg_warm, "coarse_nodes": st_setup["coarse_nodes"],
                    "setup_groups": st_setup["setup_chunks"]},
+        "panel_split": panel_split(st_setup),
         "rhs_steps_per_s": args.steps * prob.n_rhs / wall,
         "pcg_applies_per_s": applies / wall,
         "pcg_iters_per_step": applies / args.steps,

@@ -174,6 +174,17 @@ typedef struct tcf_options {
                             /* columns): a row panel of an operator is split  */
                             /* into jobs of at most this many 64 x 64 tiles,  */
                             /* whose partial rows add atomically.  <= 0: 16   */
+  int32_t autotune;         /* matrix-core path: 1 times every operator at the */
+                            /* end of setup for split lengths 4, 8, 16, 32 and */
+                            /* unsplit, and keeps the fastest per operator (F  */
+                            /* apply, preconditioner, coarse correction,       */
+                            /* coarse solve); 0 keeps panel_chunk              */
+  const char* tune_table;   /* NULL, or a text file of tuned split lengths     */
+                            /* keyed by the problem's shape: an entry for this */
+                            /* shape is used without timing; with autotune = 1 */
+                            /* a new result is appended (the file is created   */
+                            /* if missing; a file that cannot be opened is     */
+                            /* skipped).  Read during tcf_setup only           */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
@@ -385,6 +396,13 @@ typedef struct tcf_stats {
                                /* (more than 4: the matrix-core row panels)     */
   int32_t panel_jobs;          /* row-panel jobs of the F apply (0: the vector  */
                                /* tile path)                                    */
+  int32_t panel_chunk[4];      /* split lengths in use: F apply, preconditioner,*/
+                               /* coarse correction, coarse solve (0: tiles)    */
+  int32_t panel_chunk_src;     /* 0 default or panel_chunk, 1 tune table, 2     */
+                               /* timed at setup                                */
+  double panel_tune_us[20];    /* when timed: microseconds per launch of each   */
+                               /* operator (4, in the order above) at split     */
+                               /* lengths 4, 8, 16, 32 and unsplit              */
 } tcf_stats;
 
 int tcf_get_stats(const tcf_problem* h, tcf_stats* st);

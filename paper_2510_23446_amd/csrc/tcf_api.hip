@@ -174,6 +174,16 @@ struct tcf_problem {
   PanelJob *pj_apply = nullptr, *pj_phi = nullptr, *pj_pre = nullptr, *pj_root = nullptr,
            *pj_cfwd = nullptr, *pj_cbwd = nullptr, *pj_gt = nullptr;
   int n_papply = 0, n_pphi = 0, n_ppre = 0, n_proot = 0, n_pgt = 0;
+  // the row panels before they are split into jobs, the tiles they read,
+  // and the split length per operator: 0 F apply (and G^T), 1
+  // preconditioner, 2 coarse correction, 3 coarse solve
+  std::vector<PanelTile> h_ptile;
+  std::vector<PanelJob> w_apply, w_gt, w_pre, w_phi, w_root;
+  std::vector<std::vector<PanelJob>> w_fwd, w_bwd;
+  int p_eb = 8;  // element bytes of the F apply / preconditioner panels
+  int chunk[4] = {16, 16, 16, 16};
+  int chunk_src = 0;  // 0 default or option, 1 tune table, 2 timed at setup
+  double tune_us[4][5] = {};  // per operator and candidate: one launch, timed
 
   DevPatch* dP = nullptr;
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
@@ -708,6 +718,8 @@ void tcf_default_options(tcf_options* o) {
   o->coarse_mode = 0;
   o->setup_group_mb = 0;
   o->panel_chunk = 0;
+  o->autotune = 0;
+  o->tune_table = nullptr;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -934,6 +946,10 @@ int tcf_get_stats(const tcf_problem* h, tcf_stats* st) {
   st->device_bytes_peak = h->dev_bytes_peak;
   st->rhs_batch = h->rb;
   st->panel_jobs = h->n_papply;
+  for (int g = 0; g < 4; ++g) st->panel_chunk[g] = h->wide ? h->chunk[g] : 0;
+  st->panel_chunk_src = h->chunk_src;
+  for (int g = 0; g < 4; ++g)
+    for (int c = 0; c < 5; ++c) st->panel_tune_us[g * 5 + c] = h->tune_us[g][c];
   st->cond_est_max = 0.0;
   st->cond_est_patch = -1;
   for (size_t s = 0; s < h->cond_est.size(); ++s)
@@ -1902,6 +1918,67 @@ static void add_panel_tile(std::vector<PackJob>& pk, std::vector<PanelTile>& tl,
   off += panel_tile_elems(nc, elem_bytes);
 }
 
+// A panel longer than the split length becomes several jobs of about equal
+// length (more workgroups in flight); their partial rows add atomically.
+static std::vector<PanelJob> split_jobs(const std::vector<PanelJob>& whole, int chunk,
+                                        const std::vector<PanelTile>& tl, int eb) {
+  std::vector<PanelJob> v;
+  for (const PanelJob& j : whole) {
+    const int parts = (j.nt + chunk - 1) / chunk;
+    int64_t off = j.m_off;
+    for (int q = 0, t = j.t0; q < parts; ++q) {
+      const int n = j.nt / parts + (q < j.nt % parts ? 1 : 0);
+      PanelJob c = j;
+      c.m_off = off;
+      c.t0 = t;
+      c.nt = n;
+      if (parts > 1) c.flags |= 1;
+      for (int k = 0; k < n; ++k) off += panel_tile_elems(tl[t + k].nc, eb);
+      t += n;
+      v.push_back(c);
+    }
+  }
+  return v;
+}
+
+// Uploads the job lists of operator group g split at the handle's length
+// for it (replacing the previous lists).
+static int emit_panels(tcf_problem* h, int g) {
+  auto up = [&](PanelJob*& dst, int* n, const std::vector<PanelJob>& v) -> int {
+    if (dst) h->release(dst);
+    dst = nullptr;
+    RCCHK(h->upload(&dst, v));
+    if (n) *n = (int)v.size();
+    return TCF_OK;
+  };
+  const int c = h->chunk[g];
+  const std::vector<PanelTile>& tl = h->h_ptile;
+  if (g == 0) {
+    RCCHK(up(h->pj_apply, &h->n_papply, split_jobs(h->w_apply, c, tl, h->p_eb)));
+    RCCHK(up(h->pj_gt, &h->n_pgt, split_jobs(h->w_gt, c, tl, h->p_eb)));
+  } else if (g == 1) {
+    RCCHK(up(h->pj_pre, &h->n_ppre, split_jobs(h->w_pre, c, tl, h->p_eb)));
+  } else if (g == 2) {
+    RCCHK(up(h->pj_phi, &h->n_pphi, split_jobs(h->w_phi, c, tl, h->p_eb)));
+  } else {
+    RCCHK(up(h->pj_root, &h->n_proot, split_jobs(h->w_root, c, tl, 8)));
+    std::vector<PanelJob> f, b;
+    h->c_fwd_pre.assign(1, 0);
+    h->c_bwd_pre.assign(1, 0);
+    for (int lv = 0; lv < h->c_levels; ++lv) {
+      const std::vector<PanelJob> fl = split_jobs(h->w_fwd[lv], c, tl, 8);
+      const std::vector<PanelJob> bl = split_jobs(h->w_bwd[lv], c, tl, 8);
+      f.insert(f.end(), fl.begin(), fl.end());
+      b.insert(b.end(), bl.begin(), bl.end());
+      h->c_fwd_pre.push_back((int)f.size());
+      h->c_bwd_pre.push_back((int)b.size());
+    }
+    RCCHK(up(h->pj_cfwd, nullptr, f));
+    RCCHK(up(h->pj_cbwd, nullptr, b));
+  }
+  return TCF_OK;
+}
+
 // Row panels of the per-iteration operators for the matrix-core path:
 // S_bb^-1 and S_bb whole (one panel per 64 dual rows of a patch), Phi_b^T
 // (rows: the patch's primal entries) for the F apply and Phi_b for the
@@ -1914,6 +1991,14 @@ static void add_panel_tile(std::vector<PackJob>& pk, std::vector<PanelTile>& tl,
 template <class T>
 static int build_panels(tcf_problem* h, hipStream_t st) {
   const int npm = std::max(h->n_primal, 1);
+  {
+    // the panel kernel addresses its column inputs by 32-bit byte offsets
+    const int64_t ld = std::max<int64_t>({h->n_bptot + 3 * (int64_t)npm, h->n_btot, h->n_ptot});
+    if (ld * h->rb * 8 >= ((int64_t)1 << 32)) {
+      h->err = "problem too large for the matrix-core path (inputs beyond 4 GiB)";
+      return TCF_EINVAL;
+    }
+  }
   std::vector<PackJob> pa, pb, pc, pl;
   std::vector<PanelTile> tl;
   std::vector<PanelJob> japp, jphi, jpre, jroot, jgt;
@@ -1922,26 +2007,11 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   auto begin = [&](int64_t off, int yr_off, int nr, int xr_off, int flags) {
     return PanelJob{off, (int)tl.size(), 0, yr_off, nr, xr_off, flags};
   };
-  // a panel longer than the chunk becomes several jobs of about equal
-  // length (more workgroups in flight); their partial rows add atomically
-  const int chunk = h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16;
   const int wT = (int)sizeof(T), wD = (int)sizeof(double);
-  auto finish = [&](std::vector<PanelJob>& v, PanelJob j, int eb) {
-    const int nt = (int)tl.size() - j.t0;
-    if (nt <= 0) return;
-    const int parts = (nt + chunk - 1) / chunk;
-    int64_t off = j.m_off;
-    for (int q = 0, t = j.t0; q < parts; ++q) {
-      const int n = nt / parts + (q < nt % parts ? 1 : 0);
-      PanelJob c = j;
-      c.m_off = off;
-      c.t0 = t;
-      c.nt = n;
-      if (parts > 1) c.flags |= 1;
-      for (int k = 0; k < n; ++k) off += panel_tile_elems(tl[t + k].nc, eb);
-      t += n;
-      v.push_back(c);
-    }
+  // a whole panel (split into jobs later, emit_panels)
+  auto finish = [&](std::vector<PanelJob>& v, PanelJob j, int) {
+    j.nt = (int)tl.size() - j.t0;
+    if (j.nt > 0) v.push_back(j);
   };
   for (int s = 0; s < h->np_tot; ++s) {
     const DevPatch& d = h->hp[s];
@@ -1961,7 +2031,7 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       // the same tiles into the patch's bp block, no quadratic form
       for (size_t q = a0; q < japp.size(); ++q) {
         PanelJob g = japp[q];
-        g.flags = japp.size() - a0 > 1 ? 1 : 0;
+        g.flags = 0;
         jgt.push_back(g);
       }
       // preconditioner: S_bb rows (tb, with r.z)
@@ -1981,7 +2051,7 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       for (size_t q = a0; q < japp.size(); ++q) {
         PanelJob g = japp[q];
         g.yr_off = d.bp_off + d.n_b + 64 * K;
-        g.flags = japp.size() - a0 > 1 ? 1 : 0;
+        g.flags = 0;
         jgt.push_back(g);
       }
     }
@@ -2075,31 +2145,24 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   if (h->d_cL) h->release(h->d_cL);
   h->d_SPinv = nullptr;
   h->d_cL = nullptr;
-  std::vector<PanelJob> f, b;
-  h->c_fwd_pre.assign(1, 0);
-  h->c_bwd_pre.assign(1, 0);
-  for (int lv = 0; lv < h->c_levels; ++lv) {
-    f.insert(f.end(), fw[lv].begin(), fw[lv].end());
-    b.insert(b.end(), bw[lv].begin(), bw[lv].end());
-    h->c_fwd_pre.push_back((int)f.size());
-    h->c_bwd_pre.push_back((int)b.size());
+  h->h_ptile = tl;
+  h->w_apply = std::move(japp);
+  h->w_gt = std::move(jgt);
+  h->w_pre = std::move(jpre);
+  h->w_phi = std::move(jphi);
+  h->w_root = std::move(jroot);
+  h->w_fwd = std::move(fw);
+  h->w_bwd = std::move(bw);
+  h->p_eb = wT;
+  const int c0 = h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16;
+  for (int g = 0; g < 4; ++g) {
+    h->chunk[g] = c0;
+    RCCHK(emit_panels(h, g));
   }
   RCCHK(h->upload(&h->d_ptile, tl));
-  RCCHK(h->upload(&h->pj_apply, japp));
-  RCCHK(h->upload(&h->pj_gt, jgt));
-  h->n_pgt = (int)jgt.size();
-  RCCHK(h->upload(&h->pj_phi, jphi));
-  RCCHK(h->upload(&h->pj_pre, jpre));
-  RCCHK(h->upload(&h->pj_root, jroot));
-  RCCHK(h->upload(&h->pj_cfwd, f));
-  RCCHK(h->upload(&h->pj_cbwd, b));
   RCCHK(h->upload(&h->d_cT, ctab));
   RCCHK(h->alloc(&h->d_cw1, (size_t)3 * npm * h->rb));
   RCCHK(h->alloc(&h->d_xg, (size_t)std::max<int64_t>(std::max(h->n_btot, h->n_ptot), 1) * h->rb));
-  h->n_papply = (int)japp.size();
-  h->n_pphi = (int)jphi.size();
-  h->n_ppre = (int)jpre.size();
-  h->n_proot = (int)jroot.size();
   return TCF_OK;
 }
 
@@ -2261,6 +2324,9 @@ static int build_tiles_narrow(tcf_problem* h, hipStream_t st) {
   return TCF_OK;
 }
 
+template <class T>
+static int tune_panels(tcf_problem* h, hipStream_t st);
+
 extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   if (!h) return TCF_EINVAL;
   if (h->is_setup) { h->err = "setup already done"; return TCF_ESTATE; }
@@ -2278,6 +2344,8 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
       rc = setup_impl<double, double>(h, st);
     if (!rc)
       rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
+    if (!rc && h->wide)
+      rc = h->precision == TCF_FP64 ? tune_panels<double>(h, st) : tune_panels<float>(h, st);
   } catch (const std::bad_alloc&) {
     h->err = "out of host memory in setup";
     return TCF_ENOMEM;
@@ -2439,6 +2507,111 @@ static void op_precond(tcf_problem* h, const TileAcc& a, const double* r, const 
                       h->d_pre_w, 1.0, a.tb, nb, nullptr, a.rz, done, st);
     });
   }
+}
+
+// Split lengths of the row panels per operator.  A tune table (a text file,
+// one line per problem shape: the shape's key, then the four lengths) is
+// consulted first; without an entry and with autotune set, each operator
+// is timed at setup for every candidate length (one untimed and two timed
+// launches on inputs cleared to zero) and the fastest is kept, and written
+// to the table when one is named.
+static std::string tune_key(const tcf_problem* h) {
+  int nb = 0, np = 0;
+  for (const DevPatch& d : h->hp) {
+    nb = std::max(nb, d.n_b);
+    np = std::max(np, d.n_p);
+  }
+  char buf[256];
+  snprintf(buf, sizeof buf, "panels-v1 patches=%d nb_max=%d np_max=%d primal=%d nodes=%d rb=%d prec=%d",
+           h->np_tot, nb, np, h->n_primal, (int)h->cnodes.size(), h->rb, h->precision);
+  return buf;
+}
+
+template <class T>
+static int tune_panels(tcf_problem* h, hipStream_t st) {
+  const std::string key = tune_key(h);
+  if (h->opt.tune_table) {
+    FILE* f = fopen(h->opt.tune_table, "r");
+    if (f) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        int c[4];
+        const size_t n = key.size();
+        if (strncmp(line, key.c_str(), n) == 0 && line[n] == ' ' &&
+            sscanf(line + n, " chunks %d %d %d %d", &c[0], &c[1], &c[2], &c[3]) == 4 &&
+            c[0] > 0 && c[1] > 0 && c[2] > 0 && c[3] > 0) {
+          for (int g = 0; g < 4; ++g) {
+            h->chunk[g] = c[g];
+            RCCHK(emit_panels(h, g));
+          }
+          h->chunk_src = 1;
+        }
+      }
+      fclose(f);
+      if (h->chunk_src == 1) return TCF_OK;
+    }
+  }
+  if (!h->opt.autotune) return TCF_OK;
+  const TileAcc a = tile_acc(h);
+  launch_zero((int64_t)h->n_lambda * h->rb, h->d_p, st);
+  launch_zero((int64_t)h->n_lambda * h->rb, h->d_r, st);
+  launch_zero(h->n_acc, h->d_acc, st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto run = [&](int g) {
+    if (g == 0) op_apply<T>(h, a, h->d_p, nullptr, st, false);
+    else if (g == 1) op_precond<T>(h, a, h->d_r, nullptr, st, false);
+    else if (g == 2) op_phi<T>(h, a, nullptr, st, false);
+    else coarse_sweeps(h, h->rb, a.vc + h->n_bptot, a.lf, nullptr, nullptr, st);
+  };
+  int rc = TCF_OK;
+  for (int g = 0; g < 4 && !rc; ++g) {
+    if ((g == 2 && h->n_pphi == 0) || (g == 3 && h->c_root < 0)) continue;
+    const int cands[] = {4, 8, 16, 32, 1 << 20};
+    float best = 1e30f;
+    int bestc = h->chunk[g];
+    for (int ci = 0; ci < 5; ++ci) {
+      const int c = cands[ci];
+      h->chunk[g] = c;
+      if ((rc = emit_panels(h, g))) break;
+      run(g);
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = TCF_EHIP; break; }
+      run(g);
+      run(g);
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = TCF_EHIP;
+        break;
+      }
+      h->tune_us[g][ci] = ms * 500.0;  // two launches, ms -> us per launch
+      if (ms < best) {
+        best = ms;
+        bestc = c;
+      }
+    }
+    h->chunk[g] = bestc;
+    if (!rc) rc = emit_panels(h, g);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    if (h->err.empty()) h->err = "panel tuning failed";
+    return rc;
+  }
+  launch_zero(h->n_acc, h->d_acc, st);
+  HIPCHK(hipGetLastError());
+  h->chunk_src = 2;
+  if (h->opt.tune_table) {
+    FILE* f = fopen(h->opt.tune_table, "a");
+    if (f) {
+      fprintf(f, "%s chunks %d %d %d %d\n", key.c_str(), h->chunk[0], h->chunk[1], h->chunk[2],
+              h->chunk[3]);
+      fclose(f);
+    }
+  }
+  return TCF_OK;
 }
 
 // One PCG iteration with the given parity (launch sequence only).

@@ -2534,19 +2534,25 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
     const int xo = tl.xc_off + (xon ? ie : 0);
     const int gi = XM != 0 ? gidx[xo] : xo;
     const int ncq = (tl.nc + Q - 1) / Q;  // vectors per lane
-    // wave block w: 16 rows x Q ncq columns = 64 ncq vectors
-    const VT* base = reinterpret_cast<const VT*>(Mb + off) + w * 64 * ncq + lane;
+    // wave block w: 16 rows x Q ncq columns = 64 ncq vectors.  Addresses are
+    // a block-uniform base plus 32-bit byte offsets (one register each).
+    const char* base = reinterpret_cast<const char*>(Mb + off);
+    const unsigned lo = (unsigned)(w * 64 * ncq + lane) * 16u;
     // every load is issued, from a clamped address where it has nothing to
     // read, so that the number in flight is fixed and the waits are exact.
     // An input past the tile's columns meets zero columns of the stored tile
     // and one past the batch feeds an output column that is dropped, so
     // both may hold any finite value: they are not masked
 #pragma unroll
-    for (int g = 0; g < GM; ++g) ra[g] = __builtin_nontemporal_load(base + (g < ncq ? g : 0) * 64);
+    for (int g = 0; g < GM; ++g)
+      ra[g] = __builtin_nontemporal_load(
+          reinterpret_cast<const VT*>(base + lo + (unsigned)(g < ncq ? g : 0) * 1024u));
+    const char* xb = reinterpret_cast<const char*>(xv);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int j = jq + 4 * m;
-      xg[m] = xv[(size_t)(j < R ? j : 0) * (unsigned)xld + (unsigned)gi];
+      xg[m] = *reinterpret_cast<const double*>(
+          xb + ((unsigned)(j < R ? j : 0) * (unsigned)xld + (unsigned)gi) * 8u);
     }
   };
   PanelTile tl = tp[0];

@@ -67,7 +67,8 @@ class tcf_options(C.Structure):
                 ("ir_rtol", C.c_double), ("ir_maxit", C.c_int32), ("check_every", C.c_int32),
                 ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32),
                 ("precond_scaling", C.c_int32), ("coarse_mode", C.c_int32),
-                ("setup_group_mb", C.c_int32), ("panel_chunk", C.c_int32)]
+                ("setup_group_mb", C.c_int32), ("panel_chunk", C.c_int32),
+                ("autotune", C.c_int32), ("tune_table", C.c_char_p)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -111,7 +112,8 @@ class tcf_stats(C.Structure):
                 ("coarse_launches", C.c_int32), ("coarse_root", C.c_int32),
                 ("setup_chunks", C.c_int32), ("coarse_bytes", C.c_double),
                 ("device_bytes_peak", C.c_size_t), ("rhs_batch", C.c_int32),
-                ("panel_jobs", C.c_int32)]
+                ("panel_jobs", C.c_int32), ("panel_chunk", C.c_int32 * 4),
+                ("panel_chunk_src", C.c_int32), ("panel_tune_us", C.c_double * 20)]
 
 
 class tcf_server_report(C.Structure):
@@ -198,7 +200,7 @@ def default_options(**kw) -> tcf_options:
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
             use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0, coarse_mode=0,
-            setup_group_mb=0, panel_chunk=0):
+            setup_group_mb=0, panel_chunk=0, autotune=0, tune_table=None):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -264,7 +266,11 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch),
         pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling),
         coarse_mode=int(coarse_mode), setup_group_mb=int(setup_group_mb),
-        panel_chunk=int(panel_chunk))
+        panel_chunk=int(panel_chunk), autotune=int(autotune))
+    if tune_table is not None:
+        tt = os.fsencode(tune_table)
+        keep.append(tt)
+        o.tune_table = tt
     return d, o, keep
 
 
@@ -273,6 +279,15 @@ def tcf_copy_probe(nbytes, stream=None):
     rc = lib().tcf_copy_probe(int(nbytes), Problem._stream(stream))
     if rc != TCF_OK:
         raise TcfError(rc, "tcf_copy_probe")
+
+
+def _fields_dict(s):
+    """A ctypes structure as a dict (arrays as lists)."""
+    out = {}
+    for f, _ in type(s)._fields_:
+        v = getattr(s, f)
+        out[f] = list(v) if isinstance(v, C.Array) else v
+    return out
 
 
 class Server:
@@ -318,7 +333,7 @@ class Server:
                                     None)
         if rc != TCF_OK:
             raise TcfError(rc, "fetch")
-        return out, {f: getattr(st, f) for f, _ in tcf_stats._fields_}
+        return out, _fields_dict(st)
 
     def tcf_server_error(self, rid):
         return lib().tcf_server_error(self.s, int(rid)).decode()
@@ -348,12 +363,13 @@ class Problem:
 
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
                  check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0,
-                 coarse_mode=0, setup_group_mb=0, allocator=None, panel_chunk=0):
+                 coarse_mode=0, setup_group_mb=0, allocator=None, panel_chunk=0, autotune=0,
+                 tune_table=None):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
                                    use_graph, rhs_batch, pcg_warm, precond_scaling, coarse_mode,
-                                   setup_group_mb, panel_chunk)
+                                   setup_group_mb, panel_chunk, autotune, tune_table)
         self._desc = d
         self.opts = o
         # allocator: None (stream-ordered HIP allocation) or a (tcf_allocator,
@@ -436,7 +452,7 @@ class Problem:
     def tcf_get_stats(self):
         s = tcf_stats()
         self._check(lib().tcf_get_stats(self.h, C.byref(s)))
-        return {f: getattr(s, f) for f, _ in tcf_stats._fields_}
+        return _fields_dict(s)
 
     def tcf_get_step_log(self, n):
         it = np.zeros(max(n, 1), np.int32)

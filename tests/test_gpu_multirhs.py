@@ -43,3 +43,32 @@ def test_wide_batch_with_each_coarse_solver(coarse_mode):
     prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=16, n_steps=2, precision="fp64")
     worst, st = _run_and_compare(prob, 1e-9, coarse_mode=coarse_mode)
     assert st["nonconverged_steps"] == 0
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 1000])
+def test_panel_split_lengths_keep_the_solution(chunk):
+    """Row panels split into jobs of 1 tile (every output row added by many
+    jobs), 3, or not at all: the same solution as the oracle."""
+    prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=8, n_steps=2, precision="fp64")
+    worst, st = _run_and_compare(prob, 1e-9, panel_chunk=chunk, coarse_mode=2)
+    assert st["panel_chunk"] == [chunk] * 4 and st["panel_chunk_src"] == 0
+
+
+def test_autotuned_split_and_tune_table(tmp_path):
+    """Timing the split lengths at setup keeps the solution; the result goes
+    to the tune table, and a second handle of the same shape takes it from
+    there without timing."""
+    table = str(tmp_path / "panels.txt")
+    prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=16, n_steps=2, precision="fp64")
+    worst, st = _run_and_compare(prob, 1e-9, autotune=1, tune_table=table, coarse_mode=2)
+    assert st["panel_chunk_src"] == 2
+    cands = (4, 8, 16, 32, 1 << 20)
+    assert all(c in cands for c in st["panel_chunk"])
+    assert all(t > 0 for t in st["panel_tune_us"])
+    lines = open(table).read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(" ".join(map(str, st["panel_chunk"])))
+    q = tcf.Problem(prob, autotune=1, tune_table=table, coarse_mode=2)
+    q.tcf_setup()
+    s2 = q.tcf_get_stats()
+    assert s2["panel_chunk_src"] == 1 and s2["panel_chunk"] == st["panel_chunk"]
+    assert open(table).read().splitlines() == lines
