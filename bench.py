@@ -372,6 +372,9 @@ def main():
     # taken here by a small copy launch, so that the setup timed below is the
     # setup alone
     tcf.tcf_copy_probe(max(args.copy_probe_mb, 1) << 20)
+    # the device's practical HBM ceilings (streaming read, copy), reported
+    # beside the roofline, which is quoted against the 8 TB/s peak
+    probe_read, probe_copy = tcf.tcf_bandwidth_probe(4 << 30)
     n_steps = args.warmup + args.steps + args.profile_steps
     prob = make_problem(args.workload, max(n_steps, args.check_steps))
     # the largest workload's headline runs in FP64; its FP32-operator path
@@ -577,7 +580,9 @@ def main():
         "rel_error_sample": check_name,
         "roofline": {"bound": bound, "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": frac, "hbm_frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "mfma": mfma},
+                     "traffic": traffic, "mfma": mfma,
+                     "measured_ceiling_GBs": {"stream_read": round(probe_read, 1),
+                                              "copy": round(probe_copy, 1)}},
         "kernels": breakdown,
         "fp32_operator_leg": fp32_leg,
         "options_beyond_published": legs or None,

@@ -185,6 +185,15 @@ typedef struct tcf_options {
                             /* a new result is appended (the file is created   */
                             /* if missing; a file that cannot be opened is     */
                             /* skipped).  Read during tcf_setup only           */
+  int32_t deterministic;    /* 1: bitwise reproducible runs.  Every batch      */
+                            /* width takes the row panels, unsplit; rows that  */
+                            /* several panels add into, and the quadratic      */
+                            /* forms, are staged and summed in a fixed order   */
+                            /* (no atomics): reruns, resumed checkpoints and   */
+                            /* requests served alongside others give the same  */
+                            /* bits.  Costs the panels' storage of the         */
+                            /* symmetric blocks whole (twice the bytes of the  */
+                            /* tiles for batches of up to 4)                   */
 } tcf_options;
 
 /* Fills defaults: FP64, rtol 1e-10, maxit auto, ir_rtol 1e-8, check 8, graph 1,
@@ -274,7 +283,10 @@ int tcf_sync(tcf_problem* h, void* stream);
 /*
  * Copies the current field of excitation k (global edge vector, length
  * n_edges, FP64) into `out`: host memory if on_device == 0, else device
- * memory of the current device.  len must be >= n_edges.
+ * memory of the current device.  len must be >= n_edges.  An interface
+ * unknown held by several patches (their copies agree to the PCG
+ * tolerance) is read from its lowest-numbered patch; eliminated and
+ * Dirichlet edges are zero.
  */
 int tcf_get_field(tcf_problem* h, int32_t k, double* out, size_t len, int32_t on_device,
                   void* stream);
@@ -463,6 +475,16 @@ int tcf_profile_get_flops(const tcf_problem* h, int32_t group, double* alg_flops
  * the same counters report for this launch.
  */
 int tcf_copy_probe(size_t bytes, void* stream);
+
+/*
+ * Practical HBM ceilings of the device: a streaming read of `bytes` (16-byte
+ * non-temporal loads, 8 in flight per thread) and a copy of `bytes`, each
+ * the best of 3 event-timed launches after a warm one, in GB/s (bytes moved:
+ * read, and read + written).  Allocates and frees its buffers; synchronises
+ * the stream.  TCF_EINVAL for bytes < 32 or NULL outputs, TCF_ENOMEM when the
+ * buffers do not fit.
+ */
+int tcf_bandwidth_probe(size_t bytes, void* stream, double* read_gbs, double* copy_gbs);
 
 /*
  * Releases the handle.  Its device memory goes back to its allocator on the

@@ -183,12 +183,26 @@ struct tcf_problem {
   int p_eb = 8;  // element bytes of the F apply / preconditioner panels
   int chunk[4] = {16, 16, 16, 16};
   int chunk_src = 0;  // 0 default or option, 1 tune table, 2 timed at setup
+  // deterministic sums (opt.deterministic): rows that several panels add
+  // into are staged and summed in a fixed order, per-job quadratic forms
+  // likewise; the F apply's coarse rows (sa_*) and the forward sweep's
+  // ancestor rows per height (sf_*) as target -> staged-row lists
+  bool determ = false;
+  double* d_stage = nullptr;
+  int stage_ld = 0;
+  double* d_qjob = nullptr;
+  int *sa_tgt = nullptr, *sa_ptr = nullptr, *sa_idx = nullptr;
+  int n_sa = 0;
+  std::vector<int*> sf_tgt, sf_ptr, sf_idx;
+  std::vector<int> n_sf;
   double tune_us[4][5] = {};  // per operator and candidate: one launch, timed
 
   DevPatch* dP = nullptr;
   int *d_rloc = nullptr, *d_loc2r = nullptr, *d_brow = nullptr, *d_prank = nullptr;
   signed char *d_bsgn = nullptr, *d_isint = nullptr;
-  int64_t* d_rgid = nullptr;
+  // global edge of each local remainder unknown that is its edge's first
+  // copy (lowest patch id), -1 for the other copies: the field's readout
+  int64_t* d_rgid1 = nullptr;
   int *d_posp_r = nullptr, *d_posm_r = nullptr;  // multiplier -> kept-order position of its copies
   int *d_posp = nullptr, *d_posm = nullptr, *d_cptr = nullptr, *d_cidx_bp = nullptr,
       *d_cidx_r = nullptr, *d_b2bp = nullptr, *d_p2r = nullptr, *d_b2r = nullptr;
@@ -720,6 +734,7 @@ void tcf_default_options(tcf_options* o) {
   o->panel_chunk = 0;
   o->autotune = 0;
   o->tune_table = nullptr;
+  o->deterministic = 0;
 }
 
 const char* tcf_last_error(const tcf_problem* h) {
@@ -784,7 +799,8 @@ int tcf_create(const tcf_problem_desc* desc, const tcf_options* opts,
   {
     const int want = std::min(h->n_rhs, h->opt.rhs_batch > 0 ? std::min(h->opt.rhs_batch, 32) : 32);
     h->rb = want <= 4 ? want : (want <= 8 ? 8 : (want <= 16 ? 16 : 32));
-    h->wide = h->rb > 4;
+    h->determ = h->opt.deterministic != 0;
+    h->wide = h->rb > 4 || h->determ;
   }
   h->phi = desc->phi;
   h->phi_ctx = desc->phi_ctx;
@@ -1019,6 +1035,61 @@ int tcf_copy_probe(size_t bytes, void* stream) {
   return rc;
 }
 
+int tcf_bandwidth_probe(size_t bytes, void* stream, double* read_gbs, double* copy_gbs) {
+  const size_t n32 = bytes / 32;
+  if (n32 == 0 || !read_gbs || !copy_gbs) return TCF_EINVAL;
+  void *a = nullptr, *b = nullptr, *o = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_capture_mu);
+    if (hipMalloc(&a, n32 * 32) != hipSuccess) return TCF_ENOMEM;
+    if (hipMalloc(&b, n32 * 32) != hipSuccess || hipMalloc(&o, 8) != hipSuccess) {
+      (void)hipFree(a);
+      if (b) (void)hipFree(b);
+      return TCF_ENOMEM;
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int rc = TCF_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = TCF_EHIP;
+  if (!rc && (hipMemsetAsync(a, 0, n32 * 32, st) != hipSuccess ||
+              hipMemsetAsync(b, 0, n32 * 32, st) != hipSuccess))
+    rc = TCF_EHIP;
+  // best of 3 after one warm launch each, timed by events on the stream
+  auto best = [&](auto launch) -> float {
+    launch();
+    float m = 1e30f;
+    for (int r = 0; r < 3 && !rc; ++r) {
+      float ms = 0.f;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = TCF_EHIP; break; }
+      launch();
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = TCF_EHIP;
+        break;
+      }
+      m = std::min(m, ms);
+    }
+    return m;
+  };
+  if (!rc) {
+    const float mr = best([&] { launch_read_probe((int64_t)(n32 * 2), a, (double*)o, st); });
+    const float mc = best([&] { launch_copy_probe((int64_t)n32, a, b, st); });
+    if (!rc) {
+      *read_gbs = (double)n32 * 32 / (mr * 1e6);
+      *copy_gbs = 2.0 * n32 * 32 / (mc * 1e6);
+    }
+  }
+  if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) rc = TCF_EHIP;
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  (void)hipFree(a);
+  (void)hipFree(b);
+  (void)hipFree(o);
+  return rc;
+}
+
 int tcf_profile_get(const tcf_problem* h, int32_t g, double* total_ms, int64_t* launches,
                     double* alg_bytes) {
   if (!h || g < 0 || g >= TCF_KG_COUNT) return TCF_EINVAL;
@@ -1171,13 +1242,11 @@ static int build_index_tables(tcf_problem* h) {
   std::vector<int> posp_r(h->n_lambda), posm_r(h->n_lambda);
   std::vector<int> posp_bp(h->n_lambda), posm_bp(h->n_lambda);
   std::vector<signed char> bsgn, isint;
-  std::vector<int64_t> rgid;
   for (int s = 0; s < np; ++s) {
     const PatchPlan& pp = h->plans[s];
     const DevPatch& d = h->hp[s];
     rloc.insert(rloc.end(), pp.r_loc.begin(), pp.r_loc.end());
     loc2r.insert(loc2r.end(), pp.loc2r.begin(), pp.loc2r.end());
-    rgid.insert(rgid.end(), pp.r_gid.begin(), pp.r_gid.end());
     for (int k = 0; k < pp.n_b; ++k) {
       brow.push_back(pp.b_row[k]);
       bsgn.push_back((signed char)pp.b_sgn[k]);
@@ -1215,7 +1284,6 @@ static int build_index_tables(tcf_problem* h) {
   }
   RCCHK(h->upload(&h->d_rloc, rloc));
   RCCHK(h->upload(&h->d_loc2r, loc2r));
-  RCCHK(h->upload(&h->d_rgid, rgid));
   RCCHK(h->upload(&h->d_brow, brow));
   RCCHK(h->upload(&h->d_bsgn, bsgn));
   RCCHK(h->upload(&h->d_isint, isint));
@@ -1848,6 +1916,20 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
     std::vector<int> kp(1, 0), ki;
     for (auto& c : copies) { ki.insert(ki.end(), c.begin(), c.end()); kp.push_back((int)ki.size()); }
     h->n_kept_i = (int)copies.size();
+    // the field is read out from each edge's first copy: the copies of an
+    // interface unknown agree only to the PCG tolerance, and writing all of
+    // them would leave whichever copy's store landed last
+    {
+      std::vector<int64_t> g1((size_t)std::max<int64_t>(ldv, 1), -1);
+      for (int s = 0; s < np; ++s) {
+        const PatchPlan& pp = h->plans[s];
+        for (int j = 0; j < pp.n_r(); ++j) {
+          const int64_t e = pp.r_gid[j];
+          if (copies[where[e]][0] == h->hp[s].r_off + j) g1[h->hp[s].r_off + j] = e;
+        }
+      }
+      RCCHK(h->upload(&h->d_rgid1, g1));
+    }
     RCCHK(h->upload(&h->d_kptr, kp));
     RCCHK(h->upload(&h->d_kidx, ki));
     RCCHK(h->alloc(&h->d_nrm_part, (size_t)(h->n_kept_i + 255) / 256 + 1));
@@ -2003,6 +2085,12 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   std::vector<PanelTile> tl;
   std::vector<PanelJob> japp, jphi, jpre, jroot, jgt;
   std::vector<std::vector<PanelJob>> fw(h->c_levels), bw(h->c_levels);
+  // deterministic sums: (target, staged row) pairs of the F apply's coarse
+  // rows and of each height's ancestor rows, and the staged row counts
+  std::vector<std::array<int, 2>> spa;
+  std::vector<std::vector<std::array<int, 2>>> spf(h->c_levels);
+  int sa = 0;
+  std::vector<int> sl(h->c_levels, 0);
   int64_t oa = 0, ob = 0, oc = 0;
   auto begin = [&](int64_t off, int yr_off, int nr, int xr_off, int flags) {
     return PanelJob{off, (int)tl.size(), 0, yr_off, nr, xr_off, flags};
@@ -2043,6 +2131,15 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
     }
     for (int K = 0; K < Tp; ++K) {
       PanelJob j = begin(oa, d.p_off + 64 * K, nrp(K), 0, 1 | 2);
+      if (h->determ) {
+        // staged: rows sa .. sa + nr of the staging block, each summed into
+        // its coarse unknown afterwards
+        j.yr_off = sa;
+        j.flags = 8;
+        for (int r = 0; r < nrp(K); ++r)
+          spa.push_back({(int)h->n_bptot + h->cplan.nd[h->plans[s].p_rank[64 * K + r]], sa + r});
+        sa += nrp(K);
+      }
       for (int I = 0; I < Tb; ++I)
         add_panel_tile(pa, tl, oa, wT, d.G_off, d.nb_pad, 64 * I, d.n_b + 64 * K, nrb(I), nrp(K), 1,
                        d.b_off + 64 * I);
@@ -2104,6 +2201,12 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
       for (int a = 0; a < Ts; ++a) {
         // forward: b_S -= L_SJ L_JJ^-1 b_J (shared with the other nodes)
         PanelJob j = begin(oc, sb0 + c.s_off + 64 * a, nrs(a), 0, 1 | 2);
+        if (h->determ) {
+          j.yr_off = sl[lv];
+          j.flags = 8;
+          for (int r = 0; r < nrs(a); ++r) spf[lv].push_back({S[64 * a + r], sl[lv] + r});
+          sl[lv] += nrs(a);
+        }
         for (int K = 0; K < Tj; ++K)
           add_panel_tile(pl, tl, oc, wD, mt, c.nj_pad, 64 * K, 64 * a, nrj(K), nrs(a), 1,
                          c.j0 + 64 * K);
@@ -2154,10 +2257,46 @@ static int build_panels(tcf_problem* h, hipStream_t st) {
   h->w_fwd = std::move(fw);
   h->w_bwd = std::move(bw);
   h->p_eb = wT;
-  const int c0 = h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16;
+  // deterministic sums need whole panels (a split panel adds its parts)
+  const int c0 = h->determ ? (1 << 20) : (h->opt.panel_chunk > 0 ? h->opt.panel_chunk : 16);
   for (int g = 0; g < 4; ++g) {
     h->chunk[g] = c0;
     RCCHK(emit_panels(h, g));
+  }
+  if (h->determ) {
+    auto csr = [&](std::vector<std::array<int, 2>> pr, int*& tgt, int*& ptr, int*& idx,
+                   int& n) -> int {
+      std::sort(pr.begin(), pr.end());
+      std::vector<int> t, pt(1, 0), ix;
+      for (size_t i = 0; i < pr.size(); ++i) {
+        if (i == 0 || pr[i][0] != pr[i - 1][0]) {
+          if (i) pt.push_back((int)ix.size());
+          t.push_back(pr[i][0]);
+        }
+        ix.push_back(pr[i][1]);
+      }
+      if (!pr.empty()) pt.push_back((int)ix.size());
+      n = (int)t.size();
+      RCCHK(h->upload(&tgt, t));
+      RCCHK(h->upload(&ptr, pt));
+      RCCHK(h->upload(&idx, ix));
+      return TCF_OK;
+    };
+    RCCHK(csr(spa, h->sa_tgt, h->sa_ptr, h->sa_idx, h->n_sa));
+    const int L = h->c_levels;
+    h->sf_tgt.assign(L, nullptr);
+    h->sf_ptr.assign(L, nullptr);
+    h->sf_idx.assign(L, nullptr);
+    h->n_sf.assign(L, 0);
+    int rows = std::max(sa, 1);
+    for (int lv = 0; lv < L; ++lv) {
+      RCCHK(csr(spf[lv], h->sf_tgt[lv], h->sf_ptr[lv], h->sf_idx[lv], h->n_sf[lv]));
+      rows = std::max(rows, sl[lv]);
+    }
+    h->stage_ld = rows;
+    RCCHK(h->alloc(&h->d_stage, (size_t)rows * h->rb));
+    const int jmax = std::max({h->n_papply, h->n_ppre, h->n_proot, 1});
+    RCCHK(h->alloc(&h->d_qjob, (size_t)jmax * h->rb));
   }
   RCCHK(h->upload(&h->d_ptile, tl));
   RCCHK(h->upload(&h->d_cT, ctab));
@@ -2390,22 +2529,27 @@ static void coarse_sweeps(tcf_problem* h, int R, double* base, int ld, double* s
     timed(TCF_KG_COARSE, st, [&] {
       if (wide)
         launch_panels<double>(4, R, h->pj_cfwd + j0, h->d_ptile, nj, h->d_pC, base, ld, h->d_cT,
-                              base, ld, h->d_cT, nullptr, done, st);
+                              base, ld, h->d_cT, nullptr, done, st, h->d_stage, h->stage_ld);
       else
         launch_tiles<double>(4, R, h->tj_cfwd + j0, nj, h->d_tC, base, ld, h->d_cT, nullptr, 1.0,
                              base, ld, h->d_cT, nullptr, done, st);
     });
+    if (h->determ)
+      launch_stage_add(h->n_sf[lv], h->sf_tgt[lv], h->sf_ptr[lv], h->sf_idx[lv], h->d_stage,
+                       h->stage_ld, R, base, ld, done, st);
   }
   const CoarseNodeDev& r = h->cnodes[h->c_root];
   if (slots && r.j0 > 0) launch_sumsq_slots(R, r.j0, base + npm, ld, slots, done, st);
   timed(TCF_KG_COARSE, st, [&] {
     if (wide)
       launch_panels<double>(3, R, h->pj_root, h->d_ptile, h->n_proot, h->d_pC, base, ld, nullptr,
-                            base + 2 * npm, ld, nullptr, slots, done, st);
+                            base + 2 * npm, ld, nullptr, slots, done, st, nullptr, 0,
+                            h->determ && slots ? h->d_qjob : nullptr);
     else
       launch_tiles<double>(3, R, h->tj_coarse, h->n_tcoarse, h->d_tC, base, ld, nullptr, nullptr,
                            1.0, base + 2 * npm, ld, nullptr, slots, done, st);
   });
+  if (h->determ && slots) launch_qjob_add(R, h->n_proot, h->d_qjob, slots, done, st);
   for (int lv = h->c_levels - 1; lv >= 0; --lv) {
     const int j0 = h->c_bwd_pre[lv], nj = h->c_bwd_pre[lv + 1] - j0;
     timed(TCF_KG_COARSE, st, [&] {
@@ -2466,8 +2610,14 @@ static void op_apply(tcf_problem* h, const TileAcc& a, const double* x, const in
     launch_gather_cols(R, nb, h->d_brow, h->d_bsgn_d, h->dt, x, nl, h->d_xg, nb, done, st);
     maybe_timed(h, tm, TCF_KG_APPLY, st, [&] {
       launch_panels<T>(0, R, h->pj_apply, h->d_ptile, h->n_papply, (const T*)h->d_pA, h->d_xg,
-                       nb, nullptr, a.vc, a.lf, h->d_cmap, a.pq, done, st);
+                       nb, nullptr, a.vc, a.lf, h->d_cmap, a.pq, done, st, h->d_stage,
+                       h->stage_ld, h->d_qjob);
     });
+    if (h->determ) {
+      launch_stage_add(h->n_sa, h->sa_tgt, h->sa_ptr, h->sa_idx, h->d_stage, h->stage_ld, R,
+                       a.vc, a.lf, done, st);
+      launch_qjob_add(R, h->n_papply, h->d_qjob, a.pq, done, st);
+    }
   } else {
     maybe_timed(h, tm, TCF_KG_APPLY, st, [&] {
       launch_tiles<T>(0, R, h->tj_apply, h->n_tapply, (const T*)h->d_tA, x, nl, h->d_brow,
@@ -2499,8 +2649,9 @@ static void op_precond(tcf_problem* h, const TileAcc& a, const double* r, const 
     launch_gather_cols(R, nb, h->d_brow, h->d_pre_w, 1.0, r, nl, h->d_xg, nb, done, st);
     maybe_timed(h, tm, TCF_KG_PRECOND, st, [&] {
       launch_panels<T>(2, R, h->pj_pre, h->d_ptile, h->n_ppre, (const T*)h->d_pB, h->d_xg, nb,
-                       nullptr, a.tb, nb, nullptr, a.rz, done, st);
+                       nullptr, a.tb, nb, nullptr, a.rz, done, st, nullptr, 0, h->d_qjob);
     });
+    if (h->determ) launch_qjob_add(R, h->n_ppre, h->d_qjob, a.rz, done, st);
   } else {
     maybe_timed(h, tm, TCF_KG_PRECOND, st, [&] {
       launch_tiles<T>(2, R, h->tj_pre, h->n_tpre, (const T*)h->d_tB, r, nl, h->d_brow,
@@ -2530,7 +2681,7 @@ static std::string tune_key(const tcf_problem* h) {
 template <class T>
 static int tune_panels(tcf_problem* h, hipStream_t st) {
   const std::string key = tune_key(h);
-  if (h->opt.tune_table) {
+  if (h->opt.tune_table && !h->determ) {
     FILE* f = fopen(h->opt.tune_table, "r");
     if (f) {
       char line[512];
@@ -2551,7 +2702,7 @@ static int tune_panels(tcf_problem* h, hipStream_t st) {
       if (h->chunk_src == 1) return TCF_OK;
     }
   }
-  if (!h->opt.autotune) return TCF_OK;
+  if (!h->opt.autotune || h->determ) return TCF_OK;
   const TileAcc a = tile_acc(h);
   launch_zero((int64_t)h->n_lambda * h->rb, h->d_p, st);
   launch_zero((int64_t)h->n_lambda * h->rb, h->d_r, st);
@@ -3322,7 +3473,7 @@ int tcf_get_field(tcf_problem* h, int32_t k, double* out, size_t len, int32_t on
   hipStream_t st = (hipStream_t)stream;
   double* dst = on_device ? out : h->d_field;
   HIPCHK(hipMemsetAsync(dst, 0, sizeof(double) * nE, st));
-  launch_to_global(h->n_rtot, h->d_rgid, h->d_a + (int64_t)k * h->n_rtot, dst, st);
+  launch_to_global(h->n_rtot, h->d_rgid1, h->d_a + (int64_t)k * h->n_rtot, dst, st);
   HIPCHK(hipGetLastError());
   if (!on_device)
     HIPCHK(hipMemcpyAsync(out, h->d_field, sizeof(double) * nE, hipMemcpyDeviceToHost, st));

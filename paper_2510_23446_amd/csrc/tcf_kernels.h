@@ -144,11 +144,20 @@ void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, 
 // directly, xv[j * xld + i] (gathered beforehand by launch_gather_cols),
 // group 4 (the coarse factor's sweeps) through gidx.  A job owns its
 // output rows (y[j * yld + i] += v) unless its flags mark them shared
-// (atomic adds); outputs are mapped through ymap where its flags say so.
+// (atomic adds) or staged (stored into its rows of stage, column stride
+// sld); outputs are mapped through ymap where its flags say so.  With qjob
+// the quadratic forms go to qjob[j * njobs + job] instead of the slots.
 template <class T>
 void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
                    const T* M, const double* xv, int xld, const int* gidx, double* y, int yld,
-                   const int* ymap, double* qslot, const int* done, hipStream_t st);
+                   const int* ymap, double* qslot, const int* done, hipStream_t st,
+                   double* stage = nullptr, int sld = 0, double* qjob = nullptr);
+// Deterministic sums: staged rows into their targets (fixed order per
+// target), per-job quadratic forms into slot 0 of each column.
+void launch_stage_add(int n, const int* tgt, const int* ptr, const int* idx, const double* stage,
+                      int sld, int R, double* y, int yld, const int* done, hipStream_t st);
+void launch_qjob_add(int R, int njobs, const double* qjob, double* slots, const int* done,
+                     hipStream_t st);
 template <class T>
 void launch_bdiag(const DevPatch* P, int np, const T* A, double* out, hipStream_t st);
 // Tile-path PCG on R (1..4) right-hand sides, column-major vectors; st[R].done
@@ -174,6 +183,7 @@ void launch_pcg_pupdate_t(int R, int n, const int* pp, const int* pm, const doub
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
 void launch_copy_probe(int64_t n32, const void* a, void* b, hipStream_t st);
+void launch_read_probe(int64_t n16, const void* a, double* out, hipStream_t st);
 // Coarse factor fronts (nested dissection over the patch grid).
 template <class T>
 void launch_front_add(const DevPatch* P, int s, int n_p, const int* p_nd, const T* A,

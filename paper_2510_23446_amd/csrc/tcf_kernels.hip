@@ -1738,10 +1738,10 @@ __global__ void k_scatter(int n, const int* dst, const int* sidx, const double* 
   if (i < n) out[dst ? dst[i] : i] = scale * src[sidx ? sidx[i] : i];
 }
 
-// global field: out[gid[i]] = a[i] (zero elsewhere beforehand)
+// global field: out[gid[i]] = a[i] where gid[i] >= 0 (zero elsewhere beforehand)
 __global__ void k_to_global(int64_t n, const int64_t* gid, const double* a, double* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[gid[i]] = a[i];
+  if (i < n && gid[i] >= 0) out[gid[i]] = a[i];
 }
 
 // ===========================================================================
@@ -2506,7 +2506,7 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
                                                  const T* Mb, const double* xv, int xld,
                                                  const int* gidx, double* y, int yld,
                                                  const int* ymap, double* qslot, const int* done,
-                                                 int R) {
+                                                 int R, double* stage, int sld, double* qjob) {
   typedef Mfma16<double> M;
   constexpr int XM = Group == 4 ? 2 : 0;
   typedef typename TileVec<T>::v VT;
@@ -2597,14 +2597,18 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
       }
     }
   }
-  // outputs: lane (li, lk), element e is row 16 w + row(lk, e), column li (+16)
-  const bool shared = jb.flags & 1, mapped = jb.flags & 2, qf = (jb.flags & 4) && qslot;
+  // outputs: lane (li, lk), element e is row 16 w + row(lk, e), column li (+16).
+  // A staged job (flag 8) stores its rows into its own rows of the staging
+  // block, summed into their targets afterwards in a fixed order; with qjob
+  // the quadratic form of each job goes to its own entry (summed likewise).
+  const bool shared = jb.flags & 1, mapped = jb.flags & 2, staged = jb.flags & 8;
+  const bool qf = (jb.flags & 4) && (qslot || qjob);
   double q0 = 0.0, q1 = 0.0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int row = 16 * w + M::row(lk, e);
     if (row >= jb.nr) continue;
-    const int yi = mapped ? ymap[jb.yr_off + row] : jb.yr_off + row;
+    const int yi = staged ? jb.yr_off + row : (mapped ? ymap[jb.yr_off + row] : jb.yr_off + row);
     int gr = jb.xr_off + row;
     if (qf && XM != 0) gr = gidx[gr];
 #pragma unroll
@@ -2612,9 +2616,13 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
       const int j = 16 * hh + li;
       if (j >= R) continue;
       const double v = hh ? a1[e] : a0[e];
-      double* dst = y + (int64_t)j * yld + yi;
-      if (shared) atomicAdd(dst, v);
-      else *dst += v;
+      if (staged) {
+        stage[(int64_t)j * sld + yi] = v;
+      } else {
+        double* dst = y + (int64_t)j * yld + yi;
+        if (shared) atomicAdd(dst, v);
+        else *dst += v;
+      }
       if (qf) {
         const double xv_r = xv[(size_t)j * (unsigned)xld + (unsigned)gr];
         if (hh) q1 += xv_r * v; else q0 += xv_r * v;
@@ -2631,10 +2639,44 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
       Qs[w * 32 + 16 + li] = q1;
     }
     __syncthreads();
-    if (t < 32 && t < R)
-      atomicAdd(qslot + t * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)),
-                (Qs[t] + Qs[32 + t]) + (Qs[64 + t] + Qs[96 + t]));
+    if (t < 32 && t < R) {
+      const double qv = (Qs[t] + Qs[32 + t]) + (Qs[64 + t] + Qs[96 + t]);
+      if (qjob) qjob[(int64_t)t * nbk + job] = qv;
+      else atomicAdd(qslot + t * TCF_QSLOTS + (blockIdx.x & (TCF_QSLOTS - 1)), qv);
+    }
+  } else if (qjob && t < 32 && t < R) {
+    qjob[(int64_t)t * nbk + job] = 0.0;
   }
+}
+
+// Fixed-order sums of staged rows: y[j * yld + tgt[i]] += sum over
+// p in [ptr[i], ptr[i+1]) of stage[j * sld + idx[p]], for R columns (the
+// entries of each target in the order the plan lists them).
+__global__ void k_stage_add(int n, const int* tgt, const int* ptr, const int* idx,
+                            const double* stage, int sld, int R, double* y, int yld,
+                            const int* done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = ptr[i], p1 = ptr[i + 1], t = tgt[i];
+  for (int j = 0; j < R; ++j) {
+    double v = 0.0;
+    for (int p = p0; p < p1; ++p) v += stage[(int64_t)j * sld + idx[p]];
+    y[(int64_t)j * yld + t] += v;
+  }
+}
+
+// slots[j * TCF_QSLOTS] += the sum of the njobs per-job quadratic forms of
+// column j (one block per column, a fixed summation order).
+__global__ void __launch_bounds__(256) k_qjob_add(int njobs, const double* qjob, double* slots,
+                                                  const int* done) {
+  if (done && *done) return;
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < njobs; k += 256) v += qjob[(int64_t)j * njobs + k];
+  v = block_sum256(v, sh);
+  if (threadIdx.x == 0) slots[(int64_t)j * TCF_QSLOTS] += v;
 }
 
 __global__ void k_zero(int64_t n, double* a) {
@@ -2686,16 +2728,17 @@ static void launch_tiles_g(int R, const TileJob* jobs, int njobs, const T* M, co
 template <class T>
 void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tiles, int njobs,
                    const T* M, const double* xv, int xld, const int* gidx, double* y, int yld,
-                   const int* ymap, double* qslot, const int* done, hipStream_t st) {
+                   const int* ymap, double* qslot, const int* done, hipStream_t st,
+                   double* stage, int sld, double* qjob) {
   if (njobs == 0) return;
 #define TCF_PANEL_CASE(G)                                                                     \
   case G:                                                                                     \
     if (R > 16)                                                                               \
       TCF_TIMED_LAUNCH((k_panel_w<T, G, true>), dim3(njobs), dim3(256), 0, st, jobs, tiles, M, \
-                       xv, xld, gidx, y, yld, ymap, qslot, done, R);                          \
+                       xv, xld, gidx, y, yld, ymap, qslot, done, R, stage, sld, qjob);        \
     else                                                                                      \
       TCF_TIMED_LAUNCH((k_panel_w<T, G, false>), dim3(njobs), dim3(256), 0, st, jobs, tiles,  \
-                       M, xv, xld, gidx, y, yld, ymap, qslot, done, R);                       \
+                       M, xv, xld, gidx, y, yld, ymap, qslot, done, R, stage, sld, qjob);     \
     break;
   switch (group) {
     TCF_PANEL_CASE(0)
@@ -2710,10 +2753,22 @@ void launch_panels(int group, int R, const PanelJob* jobs, const PanelTile* tile
 }
 template void launch_panels<double>(int, int, const PanelJob*, const PanelTile*, int,
                                     const double*, const double*, int, const int*, double*, int,
-                                    const int*, double*, const int*, hipStream_t);
+                                    const int*, double*, const int*, hipStream_t, double*, int,
+                                    double*);
 template void launch_panels<float>(int, int, const PanelJob*, const PanelTile*, int, const float*,
                                    const double*, int, const int*, double*, int, const int*,
-                                   double*, const int*, hipStream_t);
+                                   double*, const int*, hipStream_t, double*, int, double*);
+void launch_stage_add(int n, const int* tgt, const int* ptr, const int* idx, const double* stage,
+                      int sld, int R, double* y, int yld, const int* done, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_stage_add, dim3((n + 255) / 256), dim3(256), 0, st, n, tgt, ptr, idx, stage,
+                     sld, R, y, yld, done);
+}
+void launch_qjob_add(int R, int njobs, const double* qjob, double* slots, const int* done,
+                     hipStream_t st) {
+  if (njobs == 0 || R == 0) return;
+  hipLaunchKernelGGL(k_qjob_add, dim3(R), dim3(256), 0, st, njobs, qjob, slots, done);
+}
 
 template <class T>
 void launch_tiles(int group, int R, const TileJob* jobs, int njobs, const T* M, const double* xv,
@@ -2813,6 +2868,31 @@ __global__ void k_copy_probe(int64_t n, const double4* a, double4* b) {
 void launch_copy_probe(int64_t n32, const void* a, void* b, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_probe, dim3(8192), dim3(256), 0, st, n32, (const double4*)a,
                      (double4*)b);
+}
+
+// Streaming read of n 16-byte vectors, 8 non-temporal loads in flight per
+// thread (the read ceiling the bandwidth probe measures); the sum is kept
+// only to keep the loads.
+__global__ void __launch_bounds__(256) k_read_probe(int64_t n, const TileVec<double>::v* a,
+                                                    double* out) {
+  typedef TileVec<double>::v V2;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256 * 8;
+  for (int64_t base = (int64_t)blockIdx.x * 256 * 8 + threadIdx.x; base < n; base += stride) {
+    V2 r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = base + (int64_t)u * 256;
+      r[u] = i < n ? __builtin_nontemporal_load(a + i) : V2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += r[u][0] + r[u][1];
+  }
+  if (acc == 1.0e300) out[0] = acc;
+}
+void launch_read_probe(int64_t n16, const void* a, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_read_probe, dim3(8192), dim3(256), 0, st, n16,
+                     (const TileVec<double>::v*)a, out);
 }
 void launch_zero(int64_t n, double* a, hipStream_t st) {
   if (n == 0) return;

@@ -28,7 +28,7 @@ EXPORTS = ["tcf_default_options", "tcf_last_error", "tcf_create", "tcf_footprint
            "tcf_step", "tcf_step_noalloc", "tcf_sync", "tcf_get_field", "tcf_get_topology", "tcf_get_cond_est",
            "tcf_get_stats",
            "tcf_get_step_log", "tcf_get_state", "tcf_set_state", "tcf_profile_enable",
-           "tcf_profile_get", "tcf_profile_get_flops", "tcf_copy_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
+           "tcf_profile_get", "tcf_profile_get_flops", "tcf_copy_probe", "tcf_bandwidth_probe", "tcf_destroy", "tcf_server_create", "tcf_server_submit",
            "tcf_server_poll", "tcf_server_wait", "tcf_server_fetch", "tcf_server_stats",
            "tcf_server_error", "tcf_server_destroy"]
 TCF_REQ_QUEUED, TCF_REQ_RUNNING, TCF_REQ_DONE, TCF_REQ_FAILED = range(4)
@@ -68,7 +68,8 @@ class tcf_options(C.Structure):
                 ("use_graph", C.c_int32), ("rhs_batch", C.c_int32), ("pcg_warm", C.c_int32),
                 ("precond_scaling", C.c_int32), ("coarse_mode", C.c_int32),
                 ("setup_group_mb", C.c_int32), ("panel_chunk", C.c_int32),
-                ("autotune", C.c_int32), ("tune_table", C.c_char_p)]
+                ("autotune", C.c_int32), ("tune_table", C.c_char_p),
+                ("deterministic", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -159,6 +160,7 @@ def lib():
                                   C.POINTER(C.c_double)]
     L.tcf_profile_get_flops.argtypes = [P, C.c_int32, C.POINTER(C.c_double)]
     L.tcf_copy_probe.argtypes = [C.c_size_t, P]
+    L.tcf_bandwidth_probe.argtypes = [C.c_size_t, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.tcf_destroy.argtypes = [P]
     L.tcf_destroy.restype = None
     L.tcf_server_create.argtypes = [C.c_size_t, C.c_int32, C.POINTER(P)]
@@ -200,7 +202,7 @@ def default_options(**kw) -> tcf_options:
 
 def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, check_every=8,
             use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0, coarse_mode=0,
-            setup_group_mb=0, panel_chunk=0, autotune=0, tune_table=None):
+            setup_group_mb=0, panel_chunk=0, autotune=0, tune_table=None, deterministic=0):
     """(desc, options, keep-alive list) for a workloads.Problem."""
     keep = []
     d = tcf_problem_desc()
@@ -266,7 +268,7 @@ def marshal(prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None, chec
         check_every=int(check_every), use_graph=int(use_graph), rhs_batch=int(rhs_batch),
         pcg_warm=int(pcg_warm), precond_scaling=int(precond_scaling),
         coarse_mode=int(coarse_mode), setup_group_mb=int(setup_group_mb),
-        panel_chunk=int(panel_chunk), autotune=int(autotune))
+        panel_chunk=int(panel_chunk), autotune=int(autotune), deterministic=int(deterministic))
     if tune_table is not None:
         tt = os.fsencode(tune_table)
         keep.append(tt)
@@ -288,6 +290,15 @@ def _fields_dict(s):
         v = getattr(s, f)
         out[f] = list(v) if isinstance(v, C.Array) else v
     return out
+
+
+def tcf_bandwidth_probe(nbytes, stream=None):
+    """(read GB/s, copy GB/s): the device's practical HBM ceilings."""
+    r, c = C.c_double(), C.c_double()
+    rc = lib().tcf_bandwidth_probe(int(nbytes), Problem._stream(stream), C.byref(r), C.byref(c))
+    if rc != TCF_OK:
+        raise TcfError(rc, "tcf_bandwidth_probe")
+    return r.value, c.value
 
 
 class Server:
@@ -364,12 +375,13 @@ class Problem:
     def __init__(self, prob, precision=None, pcg_rtol=None, pcg_maxit=0, ir_rtol=None,
                  check_every=8, use_graph=1, rhs_batch=0, pcg_warm=0, precond_scaling=0,
                  coarse_mode=0, setup_group_mb=0, allocator=None, panel_chunk=0, autotune=0,
-                 tune_table=None):
+                 tune_table=None, deterministic=0):
         L = lib()
         self.prob = prob
         d, o, self._keep = marshal(prob, precision, pcg_rtol, pcg_maxit, ir_rtol, check_every,
                                    use_graph, rhs_batch, pcg_warm, precond_scaling, coarse_mode,
-                                   setup_group_mb, panel_chunk, autotune, tune_table)
+                                   setup_group_mb, panel_chunk, autotune, tune_table,
+                                   deterministic)
         self._desc = d
         self.opts = o
         # allocator: None (stream-ordered HIP allocation) or a (tcf_allocator,

@@ -44,6 +44,36 @@ def test_checkpoint_resume_matches_uninterrupted_run():
     assert err.value.code == tcf.TCF_EINVAL
 
 
+def test_checkpoint_resume_is_bitwise_with_deterministic_sums():
+    """With deterministic sums (no atomics, fixed summation orders) a resumed
+    run gives the same bits as the uninterrupted one, and a rerun the same
+    bits again; the field still matches the oracle."""
+    prob = W.plain_fp64().with_steps(8)
+    a = tcf.Problem(prob, deterministic=1)
+    a.tcf_setup()
+    a.tcf_step(4)
+    state = a.tcf_get_state()
+    a.tcf_step(4)
+    straight = _field(a)
+    b = tcf.Problem(prob, deterministic=1)
+    b.tcf_setup()
+    b.tcf_set_state(state)
+    b.tcf_step(4)
+    resumed = _field(b)
+    c = tcf.Problem(prob, deterministic=1)
+    c.tcf_setup()
+    c.tcf_step(8)
+    rerun = _field(c)
+    ref = solve.run(prob).fields[-1][:, 0]
+    e = np.linalg.norm(straight - ref) / np.linalg.norm(ref)
+    print(f"[api] deterministic: vs oracle {e:.2e}, resumed bitwise "
+          f"{np.array_equal(resumed, straight)}, rerun bitwise {np.array_equal(rerun, straight)}",
+          flush=True)
+    assert np.array_equal(resumed, straight)
+    assert np.array_equal(rerun, straight)
+    assert e <= 1e-9
+
+
 def test_call_order_and_limits():
     prob = W.plain_fp64().with_steps(3)
     p = tcf.Problem(prob)

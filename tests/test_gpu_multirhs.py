@@ -72,3 +72,22 @@ def test_autotuned_split_and_tune_table(tmp_path):
     s2 = q.tcf_get_stats()
     assert s2["panel_chunk_src"] == 1 and s2["panel_chunk"] == st["panel_chunk"]
     assert open(table).read().splitlines() == lines
+
+
+@pytest.mark.parametrize("batch,prec", [(1, "fp64"), (4, "fp64"), (32, "fp64"), (8, "fp32_ir")])
+def test_deterministic_sums_match_the_oracle_and_rerun_bitwise(batch, prec):
+    """deterministic = 1 (row panels at every batch width, staged shared rows,
+    per-job quadratic forms): the oracle's fields, and a second handle gives
+    the same bits."""
+    n_rhs = max(batch, 2)
+    prob = W.largest_multirhs(P=(4, 4, 2), n=4, p=3, n_rhs=n_rhs, n_steps=2, precision=prec)
+    tol = 1e-9 if prec == "fp64" else 1e-8
+    worst, st = _run_and_compare(prob, tol, rhs_batch=batch, deterministic=1, coarse_mode=2)
+    assert st["rhs_batch"] == batch and st["panel_jobs"] > 0
+    fields = []
+    for _ in range(2):
+        p = tcf.Problem(prob, rhs_batch=batch, deterministic=1, coarse_mode=2)
+        p.tcf_setup()
+        p.tcf_step(prob.n_steps)
+        fields.append(np.stack([p.tcf_get_field(k) for k in range(prob.n_rhs)]))
+    assert np.array_equal(fields[0], fields[1])

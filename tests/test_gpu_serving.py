@@ -54,6 +54,49 @@ def test_alone_equals_mix(precision):
     srv.tcf_server_destroy()
 
 
+def test_alone_equals_mix_on_the_served_draws():
+    """The served workload's own draws (256 seeded requests, k in {2, 3, 4},
+    per-row n in {4..10}): the first three 4 x 4 x 4 requests and two
+    smaller ones, 3 steps each, in one mix of 3 slots, each against its run
+    alone."""
+    draws = W.serving_requests(n_req=256, seed=3, n_steps=50)
+    big = [r for r in draws if r.np[0] == 4][:3]
+    small = [r for r in draws if r.np[0] < 4][:2]
+    reqs = [r.with_steps(3) for r in big + small]
+    assert max(int(max(n.max() for n in r.nel)) for r in big) >= 8
+    srv = tcf.Server(max_bytes=128 << 30, max_slots=3)
+    ids = [srv.tcf_server_submit(r, precision="fp32_ir") for r in reqs]
+    for i in ids:
+        assert srv.tcf_server_wait(i) == tcf.TCF_OK
+    for i, r in zip(ids, reqs):
+        mix, _ = srv.tcf_server_fetch(i)
+        alone = _alone(r, "fp32_ir")
+        d = np.linalg.norm(mix - alone) / np.linalg.norm(alone)
+        print(f"[serving] {r.name} nel {[[int(v) for v in n] for n in r.nel]} alone-vs-mix {d:.2e}", flush=True)
+        assert d <= 1e-8
+    srv.tcf_server_destroy()
+
+
+def test_alone_equals_mix_bitwise_with_deterministic_sums():
+    """Requests served three at a time give the same bits as each run alone
+    when the library sums deterministically."""
+    reqs = _requests(n=5, steps=3)
+    srv = tcf.Server(max_bytes=64 << 30, max_slots=3)
+    ids = [srv.tcf_server_submit(r, precision="fp32_ir", deterministic=1) for r in reqs]
+    for i in ids:
+        assert srv.tcf_server_wait(i) == tcf.TCF_OK
+    for i, r in zip(ids, reqs):
+        mix, _ = srv.tcf_server_fetch(i)
+        p = tcf.Problem(r, precision="fp32_ir", deterministic=1)
+        p.tcf_setup()
+        p.tcf_step(r.n_steps)
+        alone = p.tcf_get_field(0)
+        print(f"[serving] {r.name} deterministic alone-vs-mix bitwise {np.array_equal(mix, alone)}",
+              flush=True)
+        assert np.array_equal(mix, alone)
+    srv.tcf_server_destroy()
+
+
 def test_admission_by_memory():
     reqs = _requests(n=4)
     fps = []
