@@ -2513,11 +2513,12 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
   constexpr int V = TileVec<T>::n;  // k-steps per 16-byte vector
   constexpr int Q = 4 * V;          // column quantum of the stored tiles
   constexpr int GM = 64 / Q;        // vectors per lane of a full tile
-  const int nbk = gridDim.x, per = nbk >> 3, rem = nbk & 7;
-  const int xcd = blockIdx.x & 7, kb = blockIdx.x >> 3;
-  const int job = xcd < rem ? xcd * (per + 1) + kb : rem * (per + 1) + (xcd - rem) * per + kb;
+  // block b takes job b: the hardware deals consecutive blocks to the 8 XCDs
+  // in turn, which spreads each XCD's streams over the whole buffer (a
+  // contiguous run of jobs per XCD streamed measurably slower)
+  const int nbk = gridDim.x, job = blockIdx.x;
   const PanelJob jb = jobs[job];
-  if ((done ? *done : 0) | (jb.nt < 0) | (jb.m_off < 0)) return;
+  if ((done ? *done : 0) | (jb.nt <= 0) | (jb.m_off < 0)) return;
   constexpr int XP = 66;  // column stride of the staged inputs
   __shared__ double Xs[2][32 * XP];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
@@ -2555,10 +2556,38 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
           xb + ((unsigned)(j < R ? j : 0) * (unsigned)xld + (unsigned)gi) * 8u);
     }
   };
+  // Operands of the epilogue: the output rows' current values (rows no other
+  // job adds into) and the quadratic form's inputs.  They are loaded during
+  // the job's last tile, in place of a next tile, so that their latency
+  // hides behind that tile's products instead of following them.
+  const bool shared = jb.flags & 1, mapped = jb.flags & 2, staged = jb.flags & 8;
+  const bool qf = (jb.flags & 4) && (qslot || qjob);
+  int yix[4];
+  double yv[4][2], xq[4][2];
+  auto load_epilogue = [&] {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * w + M::row(lk, e);
+      const bool ok = row < jb.nr;
+      const int yi = (mapped && !staged) ? (ok ? ymap[jb.yr_off + row] : 0) : jb.yr_off + row;
+      yix[e] = yi;
+      int gr = jb.xr_off + row;
+      if (qf && XM != 0 && ok) gr = gidx[gr];
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int j = 16 * hh + li;
+        const bool okj = ok && j < R;
+        yv[e][hh] = (okj && !staged && !shared) ? y[(int64_t)j * yld + yi] : 0.0;
+        xq[e][hh] = (okj && qf) ? xv[(size_t)j * (unsigned)xld + (unsigned)gr] : 0.0;
+      }
+    }
+  };
   PanelTile tl = tp[0];
   int64_t off = jb.m_off;
   fetch(tl, off);
-  for (int it = 0; it < jb.nt; ++it) {
+  // one tile: its inputs staged, the next tile (or, for the last one, the
+  // epilogue's operands) requested, then its products
+  auto step = [&](int it, auto last) {
     const int buf = it & 1;
     const int ncq = (tl.nc + Q - 1) / Q;
     VT rc[GM];
@@ -2572,8 +2601,10 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
     // the tile's inputs are staged; every wave is past the reads of this
     // buffer two tiles ago
     __syncthreads();
-    off += 64 * (int64_t)(ncq * Q);
-    if (it + 1 < jb.nt) {
+    if constexpr (decltype(last)::value) {
+      load_epilogue();
+    } else {
+      off += 64 * (int64_t)(ncq * Q);
       tl = tp[it + 1];
       fetch(tl, off);
     }
@@ -2596,21 +2627,19 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
         }
       }
     }
-  }
+  };
+  for (int it = 0; it + 1 < jb.nt; ++it) step(it, std::false_type());
+  step(jb.nt - 1, std::true_type());
   // outputs: lane (li, lk), element e is row 16 w + row(lk, e), column li (+16).
   // A staged job (flag 8) stores its rows into its own rows of the staging
   // block, summed into their targets afterwards in a fixed order; with qjob
   // the quadratic form of each job goes to its own entry (summed likewise).
-  const bool shared = jb.flags & 1, mapped = jb.flags & 2, staged = jb.flags & 8;
-  const bool qf = (jb.flags & 4) && (qslot || qjob);
   double q0 = 0.0, q1 = 0.0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int row = 16 * w + M::row(lk, e);
     if (row >= jb.nr) continue;
-    const int yi = staged ? jb.yr_off + row : (mapped ? ymap[jb.yr_off + row] : jb.yr_off + row);
-    int gr = jb.xr_off + row;
-    if (qf && XM != 0) gr = gidx[gr];
+    const int yi = yix[e];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) {
       const int j = 16 * hh + li;
@@ -2621,11 +2650,10 @@ __global__ void __launch_bounds__(256) k_panel_w(const PanelJob* jobs, const Pan
       } else {
         double* dst = y + (int64_t)j * yld + yi;
         if (shared) atomicAdd(dst, v);
-        else *dst += v;
+        else *dst = yv[e][hh] + v;
       }
       if (qf) {
-        const double xv_r = xv[(size_t)j * (unsigned)xld + (unsigned)gr];
-        if (hh) q1 += xv_r * v; else q0 += xv_r * v;
+        if (hh) q1 += xq[e][hh] * v; else q0 += xq[e][hh] * v;
       }
     }
   }
