@@ -77,9 +77,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (field check and CPU baseline)")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
-                                                      "apply_tiles_uneven_fp64_traffic.json"),
-                    help="JSON with the counter-measured HBM bytes per launch of a kernel")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles"),
+                    help="JSON with the counter-measured HBM bytes per unit of a kernel group, "
+                         "or a folder of them (*_traffic.json; the one for this workload, "
+                         "precision, kernel group and kernel source is used)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every PCG iteration on the stream instead of replaying graphs")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -440,11 +441,16 @@ def main():
             bound, frac = "mfma", tf / MFMA_F64_PEAK_TFS
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
-        tj = json.load(open(args.traffic))
-        same_kernel = tj.get("kernel_source_sha256") == kernel_digest(tj.get("kernel_marker", ""))
-        if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
-                and tj.get("precision", "fp64") == prec):
-            traffic = tj.get("hbm_bytes_per_launch")
+        import glob
+        cands = (sorted(glob.glob(os.path.join(args.traffic, "*_traffic.json")))
+                 if os.path.isdir(args.traffic) else [args.traffic])
+        for path in cands:
+            tj = json.load(open(path))
+            same_kernel = tj.get("kernel_source_sha256") == kernel_digest(
+                tj.get("kernel_marker", ""))
+            if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
+                    and tj.get("precision", "fp64") == prec):
+                traffic = tj.get("hbm_bytes_per_launch")
     breakdown = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                      "launches_per_unit": per_unit[k],
                      "avg_us_per_unit": round(unit_s(k) * 1e6, 2) if v[1] else 0.0,
