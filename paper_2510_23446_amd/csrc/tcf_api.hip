@@ -15,6 +15,7 @@
 //   d = sum Bhat (u - Phi N q0);  PCG on F lambda = d with the unscaled
 //   Dirichlet preconditioner sum B S_bb B^T;  recover p, a_b, a_i.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -58,6 +59,16 @@ inline double now_ms() {
   using namespace std::chrono;
   return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
+// A named range of the ROCm marker timeline (rocprofv3 --marker-trace) for
+// the lifetime of the object: setup and its phases, each time step, each
+// PCG solve and each refinement sweep.  The ranges are host intervals; the
+// calls that synchronise (setup, a step) span their device work.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Gauss-Legendre rule on [-1, 1] by Newton iteration on P_n.
 void gauss_legendre(int n, double* x, double* w) {
@@ -1815,7 +1826,10 @@ static int setup_impl(tcf_problem* h, hipStream_t st) {
   }
   // the coarse factor and its explicit operators (FP64)
   if (F) {
-    RCCHK(coarse_factor(h, F, dnodes, d_cpos, st));
+    {
+      Range rg("tcf setup: coarse factor");
+      RCCHK(coarse_factor(h, F, dnodes, d_cpos, st));
+    }
     int fail = 0;
     HIPCHK(hipMemcpyAsync(&fail, h->d_fail, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -2474,17 +2488,25 @@ extern "C" int tcf_setup(tcf_problem* h, void* stream) {
   HIPCHK(hipGetDevice(&h->device));
   const double t0 = now_ms();
   int rc;
+  Range rg("tcf setup");
   try {
-    if (h->precision == TCF_FP32_FULL_IR)
-      rc = setup_impl<float, float>(h, st);
-    else if (h->precision == TCF_FP32_IR)
-      rc = setup_impl<double, float>(h, st);
-    else
-      rc = setup_impl<double, double>(h, st);
-    if (!rc)
+    {
+      Range r1("tcf setup: assembly, local factors, coarse factor");
+      if (h->precision == TCF_FP32_FULL_IR)
+        rc = setup_impl<float, float>(h, st);
+      else if (h->precision == TCF_FP32_IR)
+        rc = setup_impl<double, float>(h, st);
+      else
+        rc = setup_impl<double, double>(h, st);
+    }
+    if (!rc) {
+      Range r2("tcf setup: operator tiles");
       rc = h->precision == TCF_FP64 ? build_tiles<double>(h, st) : build_tiles<float>(h, st);
-    if (!rc && h->wide)
+    }
+    if (!rc && h->wide) {
+      Range r3("tcf setup: panel split lengths");
       rc = h->precision == TCF_FP64 ? tune_panels<double>(h, st) : tune_panels<float>(h, st);
+    }
   } catch (const std::bad_alloc&) {
     h->err = "out of host memory in setup";
     return TCF_ENOMEM;
@@ -2829,6 +2851,7 @@ static int build_pcg_graph(tcf_problem* h) {
 // iteration count and whether it converged within maxit.
 template <class T>
 static int pcg_solve(tcf_problem* h, hipStream_t st, int* iters, bool* conv) {
+  Range rg("PCG solve");
   const int nl = h->n_lambda, R = h->rb;
   for (int j = 0; j < R; ++j) {
     iters[j] = 0;
@@ -3326,6 +3349,7 @@ static int step_batch(tcf_problem* h, int k0, int nc, int l, hipStream_t st, int
   }
   std::vector<char> active(R, 0), settled(nc, 0);
   for (int sweep = 1;; ++sweep) {
+    Range rg("refinement sweep");
     int n_active = 0;
     for (int j = 0; j < nc; ++j) {
       active[j] = 0;
@@ -3403,6 +3427,7 @@ static int step_impl(tcf_problem* h, int nsteps, hipStream_t st) {
   std::vector<int> iters(h->rb), sweeps(h->rb);
   std::unique_ptr<bool[]> conv(new bool[h->rb]);
   for (int s = 0; s < nsteps; ++s) {
+    Range rg("tcf step: one time step");
     const int l = h->steps_done;
     const double t0 = now_ms();
     int it_sum = 0, ir_sum = 0;

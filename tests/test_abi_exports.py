@@ -96,14 +96,17 @@ def test_server_lifecycle_without_a_device():
         first = [srv.tcf_server_submit(prob) for _ in range(32)]
         assert all(srv.tcf_server_wait(i) == tcf.TCF_EHIP for i in first)
         # a leak grows with every batch; a one-off reservation (a new malloc
-        # arena reserves 64 MiB of address space) shows in one batch only
+        # arena reserves 64 MiB of address space) shows in one batch only, so
+        # of four batches all but the largest together stay under 64 MiB (a
+        # kept thread stack per request would add about 1 GiB per batch)
         grown = []
-        for _ in range(2):
+        for _ in range(4):
             v0 = _vm_size_mib()
-            more = [srv.tcf_server_submit(prob) for _ in range(256)]
+            more = [srv.tcf_server_submit(prob) for _ in range(128)]
             assert all(srv.tcf_server_wait(i) == tcf.TCF_EHIP for i in more)
             grown.append(_vm_size_mib() - v0)
-        assert min(grown) < 64.0, f"address space grew by {grown} MiB over two batches of 256"
+        assert sum(sorted(grown)[:-1]) < 64.0, \
+            f"address space grew by {grown} MiB over four batches of 128"
         assert "hipStreamCreateWithFlags" in srv.tcf_server_error(more[-1])
         assert srv.tcf_server_poll(more[0]) == tcf.TCF_REQ_FAILED
         # a rejected description gets no id and leaves the other requests'
@@ -113,9 +116,9 @@ def test_server_lifecycle_without_a_device():
         with pytest.raises(tcf.TcfError) as err:
             srv.tcf_server_submit(bad)
         assert err.value.code == tcf.TCF_EINVAL
-        assert srv._keep[first[0]][3] is prob and len(srv._keep) == 32 + 2 * 256
+        assert srv._keep[first[0]][3] is prob and len(srv._keep) == 32 + 4 * 128
         st = srv.tcf_server_stats()
-        assert st["submitted"] == st["admitted"] == st["failed"] == 32 + 2 * 256
+        assert st["submitted"] == st["admitted"] == st["failed"] == 32 + 4 * 128
         assert st["completed"] == st["running"] == st["queued"] == 0
     finally:
         srv.tcf_server_destroy()
@@ -187,3 +190,16 @@ def test_server_concurrent_submissions_without_a_device():
         assert "hipStreamCreateWithFlags" in srv.tcf_server_error(ids[-1])
     finally:
         srv.tcf_server_destroy()
+
+
+def test_marker_ranges_are_linked():
+    """Setup, steps, PCG solves and refinement sweeps open named ranges on
+    the ROCm marker timeline: the library imports the marker API."""
+    import subprocess
+    so = os.path.join(ROOT, "paper_2510_23446_amd", "libtcf.so")
+    out = subprocess.run(["nm", "-D", "--undefined-only", so], capture_output=True, text=True,
+                         check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+    src = open(os.path.join(ROOT, "paper_2510_23446_amd", "csrc", "tcf_api.hip")).read()
+    for name in ("tcf setup", "tcf step: one time step", "PCG solve", "refinement sweep"):
+        assert f'Range rg("{name}")' in src or f'("{name}' in src, name
