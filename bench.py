@@ -88,19 +88,30 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_digest(marker):
+def kernel_digest(marker, host_markers=()):
     """sha256 of a kernel's source text (from the line starting with marker to
-    the closing brace in column 0): counters taken for another text are stale."""
+    the closing brace in column 0), followed by the text of the host functions
+    named in host_markers (in the API source: the order the jobs are
+    dispatched in, which also moves the traffic): counters taken for another
+    text are stale."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2510_23446_amd", "csrc", "tcf_kernels.hip")
-    lines = open(path).read().splitlines()
-    i = next((n for n, l in enumerate(lines) if l.startswith(marker)), None)
-    if i is None:
+    csrc = os.path.join(ROOT, "paper_2510_23446_amd", "csrc")
+
+    def block(path, mk):
+        lines = open(path).read().splitlines()
+        i = next((n for n, l in enumerate(lines) if l.startswith(mk)), None)
+        if i is None:
+            return None
+        j = i
+        while j < len(lines) and not lines[j].startswith("}"):
+            j += 1
+        return "\n".join(lines[i:j + 1])
+
+    parts = [block(os.path.join(csrc, "tcf_kernels.hip"), marker)]
+    parts += [block(os.path.join(csrc, "tcf_api.hip"), m) for m in host_markers]
+    if any(p is None for p in parts):
         return None
-    j = i
-    while j < len(lines) and not lines[j].startswith("}"):
-        j += 1
-    return hashlib.sha256("\n".join(lines[i:j + 1]).encode()).hexdigest()
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
 
 
 def make_problem(name, n_steps):
@@ -447,7 +458,7 @@ def main():
         for path in cands:
             tj = json.load(open(path))
             same_kernel = tj.get("kernel_source_sha256") == kernel_digest(
-                tj.get("kernel_marker", ""))
+                tj.get("kernel_marker", ""), tj.get("host_markers", ()))
             if (tj.get("kernel_group") == dom and tj.get("workload") == prob.name and same_kernel
                     and tj.get("precision", "fp64") == prec):
                 traffic = tj.get("hbm_bytes_per_launch")

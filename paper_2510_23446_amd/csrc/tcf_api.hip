@@ -2037,9 +2037,32 @@ static std::vector<PanelJob> split_jobs(const std::vector<PanelJob>& whole, int 
   return v;
 }
 
+// Dispatch order of one coarse-sweep launch's jobs (block b takes entry b;
+// the hardware deals consecutive blocks to the 8 XCDs in turn): runs of
+// kXcdRun consecutive jobs (panels of one node, which take the same inputs)
+// go to one XCD, whose L2 then serves their inputs, and the runs are dealt
+// to the XCDs in turn, so that the blocks in flight still stream one window
+// of the buffer.  Measured against the plain order on one GPU: the coarse
+// solve 4% faster, the per-patch operators (F apply, coarse correction)
+// 7-10% slower, so those keep the plain order.
+constexpr int kXcdRun = 16;
+static std::vector<PanelJob> xcd_order(const std::vector<PanelJob>& v) {
+  const int n = (int)v.size();
+  std::vector<std::vector<int>> q(8);
+  for (int r = 0; r * kXcdRun < n; ++r)
+    for (int k = r * kXcdRun; k < std::min(n, (r + 1) * kXcdRun); ++k) q[r % 8].push_back(k);
+  std::vector<PanelJob> out;
+  out.reserve(n);
+  for (size_t k = 0; (int)out.size() < n; ++k)
+    for (int x = 0; x < 8; ++x)
+      if (k < q[x].size()) out.push_back(v[q[x][k]]);
+  return out;
+}
+
 // Uploads the job lists of operator group g split at the handle's length
 // for it (replacing the previous lists).
 static int emit_panels(tcf_problem* h, int g) {
+  // v: one launch's jobs in dispatch order
   auto up = [&](PanelJob*& dst, int* n, const std::vector<PanelJob>& v) -> int {
     if (dst) h->release(dst);
     dst = nullptr;
@@ -2057,13 +2080,14 @@ static int emit_panels(tcf_problem* h, int g) {
   } else if (g == 2) {
     RCCHK(up(h->pj_phi, &h->n_pphi, split_jobs(h->w_phi, c, tl, h->p_eb)));
   } else {
-    RCCHK(up(h->pj_root, &h->n_proot, split_jobs(h->w_root, c, tl, 8)));
+    RCCHK(up(h->pj_root, &h->n_proot, xcd_order(split_jobs(h->w_root, c, tl, 8))));
     std::vector<PanelJob> f, b;
     h->c_fwd_pre.assign(1, 0);
     h->c_bwd_pre.assign(1, 0);
     for (int lv = 0; lv < h->c_levels; ++lv) {
-      const std::vector<PanelJob> fl = split_jobs(h->w_fwd[lv], c, tl, 8);
-      const std::vector<PanelJob> bl = split_jobs(h->w_bwd[lv], c, tl, 8);
+      // one launch per height: each height's jobs ordered on their own
+      const std::vector<PanelJob> fl = xcd_order(split_jobs(h->w_fwd[lv], c, tl, 8));
+      const std::vector<PanelJob> bl = xcd_order(split_jobs(h->w_bwd[lv], c, tl, 8));
       f.insert(f.end(), fl.begin(), fl.end());
       b.insert(b.end(), bl.begin(), bl.end());
       h->c_fwd_pre.push_back((int)f.size());
