@@ -91,9 +91,9 @@ def parse():
 def kernel_digest(marker, host_markers=()):
     """sha256 of a kernel's source text (from the line starting with marker to
     the closing brace in column 0), followed by the text of the host functions
-    named in host_markers (in the API source: the order the jobs are
-    dispatched in, which also moves the traffic): counters taken for another
-    text are stale."""
+    named in host_markers (in the API source or the panel plan: the order
+    the jobs are dispatched in, which also moves the traffic): counters taken
+    for another text are stale."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2510_23446_amd", "csrc")
 
@@ -107,8 +107,11 @@ def kernel_digest(marker, host_markers=()):
             j += 1
         return "\n".join(lines[i:j + 1])
 
+    host = [os.path.join(csrc, f) for f in ("tcf_api.hip", "tcf_panel_plan.h")]
     parts = [block(os.path.join(csrc, "tcf_kernels.hip"), marker)]
-    parts += [block(os.path.join(csrc, "tcf_api.hip"), m) for m in host_markers]
+    for m in host_markers:
+        found = [b for b in (block(f, m) for f in host) if b is not None]
+        parts.append(found[0] if found else None)
     if any(p is None for p in parts):
         return None
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()
