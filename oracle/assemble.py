@@ -99,7 +99,10 @@ def _local_index_blocks(m, rng_x, rng_y, rng_z, d):
     return nX + nY + a + mx * (b + my * c)
 
 
-def assemble_patch(prob, grid: Grid, s: int) -> PatchMatrices:
+def assemble_patch(prob, grid: Grid, s: int, nu_elem=None) -> PatchMatrices:
+    """Local matrices of patch s.  ``nu_elem`` (optional, shape (nz, ny, nx))
+    gives nu per element in place of the patch's constant nu (a
+    field-dependent reluctivity, evaluated per element)."""
     rows = patch_rows(prob, s)
     (bx, nx, px), (by, ny, py), (bz, nz, pz) = rows
     m = (nx + px, ny + py, nz + pz)
@@ -162,7 +165,8 @@ def assemble_patch(prob, grid: Grid, s: int) -> PatchMatrices:
         Cq = C.transpose(0, 1, 3, 2).reshape(E, nq3 * 3, nl)
         Vq = V.transpose(0, 1, 3, 2).reshape(E, nq3 * 3, nl)
         wr = np.repeat(wq, 3, axis=1)[:, :, None]
-        Ke = nu * np.matmul((Cq * wr).transpose(0, 2, 1), Cq)
+        nu_l = nu if nu_elem is None else np.asarray(nu_elem, dtype=np.float64)[ez].ravel()[:, None, None]
+        Ke = nu_l * np.matmul((Cq * wr).transpose(0, 2, 1), Cq)
         Me = sig * np.matmul((Vq * wr).transpose(0, 2, 1), Vq)
         Mr.append(np.repeat(idx[:, :, None], nl, axis=2).ravel())
         Mc.append(np.repeat(idx[:, None, :], nl, axis=1).ravel())
