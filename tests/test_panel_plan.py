@@ -1,5 +1,6 @@
 """Host planning of the row-panel jobs (paper_2510_23446_amd/csrc/
-tcf_panel_plan.h), built with g++ and checked on seeded job lists:
+tcf_panel_plan.h), built with g++ (with AddressSanitizer and UBSan where
+the host has them) and checked on seeded job lists:
 split_jobs covers every tile once, in order, at the offsets the stored
 tiles take, in parts of nearly equal length that add atomically when a
 panel is split; xcd_order is a permutation that keeps each run of
@@ -107,7 +108,14 @@ def test_split_and_dispatch_order(tmp_path):
     src.write_text(PROGRAM)
     exe = tmp_path / "plan_test"
     csrc = os.path.join(ROOT, "paper_2510_23446_amd", "csrc")
-    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", csrc, str(src), "-o", str(exe)],
-                   check=True, capture_output=True, text=True)
+    # host code only: AddressSanitizer and UBSan catch an out-of-range tile
+    # or job index in the planning
+    flags = ["-std=c++17", "-O1", "-Wall", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=all"]
+    b = subprocess.run([gxx, *flags, "-I", csrc, str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    if b.returncode != 0:  # no sanitizer runtime here: plain build
+        subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", csrc, str(src), "-o", str(exe)],
+                       check=True, capture_output=True, text=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:]
