@@ -119,3 +119,18 @@ def test_split_and_dispatch_order(tmp_path):
                        check=True, capture_output=True, text=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout[-2000:]
+
+
+def test_committed_tune_table_matches_the_key_format():
+    """Every entry of the committed tune table carries the key the library
+    builds (same version tag and fields), so the bench finds it instead of
+    re-timing at setup."""
+    import re
+    src = open(os.path.join(ROOT, "paper_2510_23446_amd", "csrc", "tcf_api.hip")).read()
+    fmt = re.search(r'snprintf\(buf, sizeof buf, "(panels-v\d+[^"]*)"', src).group(1)
+    pat = "^" + re.escape(fmt).replace("%d", r"-?\d+") + r" chunks( \d+){4}$"
+    table = os.path.join(ROOT, "paper_2510_23446_amd", "tune", "panels_mi355x.txt")
+    lines = [l.rstrip("\n") for l in open(table) if l.strip()]
+    assert lines
+    for l in lines:
+        assert re.match(pat, l), l
