@@ -99,10 +99,13 @@ def _local_index_blocks(m, rng_x, rng_y, rng_z, d):
     return nX + nY + a + mx * (b + my * c)
 
 
-def assemble_patch(prob, grid: Grid, s: int, nu_elem=None) -> PatchMatrices:
+def assemble_patch(prob, grid: Grid, s: int, nu_elem=None, elements=None) -> PatchMatrices:
     """Local matrices of patch s.  ``nu_elem`` (optional, shape (nz, ny, nx))
     gives nu per element in place of the patch's constant nu (a
-    field-dependent reluctivity, evaluated per element)."""
+    field-dependent reluctivity, evaluated per element).  ``elements``
+    (optional list) receives, per layer of elements in z, the local indices
+    (E, nl) and the curl-curl element matrices with nu = 1 (E, nl, nl),
+    elements x-fastest."""
     rows = patch_rows(prob, s)
     (bx, nx, px), (by, ny, py), (bz, nz, pz) = rows
     m = (nx + px, ny + py, nz + pz)
@@ -166,7 +169,10 @@ def assemble_patch(prob, grid: Grid, s: int, nu_elem=None) -> PatchMatrices:
         Vq = V.transpose(0, 1, 3, 2).reshape(E, nq3 * 3, nl)
         wr = np.repeat(wq, 3, axis=1)[:, :, None]
         nu_l = nu if nu_elem is None else np.asarray(nu_elem, dtype=np.float64)[ez].ravel()[:, None, None]
-        Ke = nu_l * np.matmul((Cq * wr).transpose(0, 2, 1), Cq)
+        K1 = np.matmul((Cq * wr).transpose(0, 2, 1), Cq)
+        Ke = nu_l * K1
+        if elements is not None:
+            elements.append((idx.copy(), K1))
         Me = sig * np.matmul((Vq * wr).transpose(0, 2, 1), Vq)
         Mr.append(np.repeat(idx[:, :, None], nl, axis=2).ravel())
         Mc.append(np.repeat(idx[:, None, :], nl, axis=1).ravel())

@@ -141,3 +141,132 @@ def nonlinear_residual(prob, curve, nonlinear, a_now, a_prev, l, k=0):
     r = (sys.M + prob.dt * Kg) @ a_now[:, k] - f
     K = topo.kept
     return float(np.linalg.norm(r[K]) / np.linalg.norm(f[K]))
+
+
+# --------------------------------------------------------------------------
+# Newton's method for the same nonlinear step.
+#
+# With nu constant per element at b2_e = (1/|e|) int_e |curl a|^2 =
+# a_e^T K1_e a_e / |e| (K1_e the element's curl-curl matrix for nu = 1), the
+# step's residual is R(a) = (M + dt K(nu(a))) a - f and its Jacobian is
+#   J(a) = M + dt [ K(nu(a)) + sum_e (2 nu'(b2_e) / |e|) g_e g_e^T ],
+# g_e = K1_e a_e (the derivative of nu_e K1_e a_e with respect to a brings
+# K1_e a_e times the derivative of nu_e, which is nu'(b2_e) 2 g_e^T / |e|).
+# --------------------------------------------------------------------------
+
+def brauer_dnu(b2, k1, k2, k3):
+    """d nu / d(|B|^2) of the exponential curve."""
+    return k1 * k2 * np.exp(k2 * np.asarray(b2, dtype=np.float64))
+
+
+def element_data(prob, grid, s):
+    """(global edge ids per element (E, nl), K1 (E, nl, nl), element volume)
+    of patch s, elements in (z, y, x) order with x fastest."""
+    els = []
+    pm = assemble_patch(prob, grid, s, elements=els)
+    idx = np.concatenate([e[0] for e in els])
+    K1 = np.concatenate([e[1] for e in els])
+    ijk = prob.patch_ijk(s)
+    vol = 1.0
+    for d in range(3):
+        r = ijk[d]
+        vol *= (float(prob.breaks[d][r + 1]) - float(prob.breaks[d][r])) / int(prob.nel[d][r])
+    return pm.gid[idx], K1, vol
+
+
+def _element_state(x, edata, curve):
+    """b2, nu, nu' and g_e = K1_e a_e per element of one nonlinear patch."""
+    gidx, K1, vol = edata
+    ae = x[gidx]                                   # (E, nl)
+    g = np.einsum("eij,ej->ei", K1, ae)
+    b2 = np.einsum("ei,ei->e", ae, g) / vol
+    return b2, brauer_nu(b2, *curve), brauer_dnu(b2, *curve), g
+
+
+def _k_nu(prob, grid, x, curve, nonlinear, edatas, cache):
+    nu_e = [None] * prob.n_patches
+    for s in range(prob.n_patches):
+        if nonlinear[s]:
+            _, nu, _, _ = _element_state(x, edatas[s], curve)
+            nel = [int(prob.nel[d][prob.patch_ijk(s)[d]]) for d in range(3)]
+            nu_e[s] = nu.reshape(nel[2], nel[1], nel[0])
+    return assemble_K(prob, grid, nu_e, cache)
+
+
+def step_residual(prob, grid, sys, x, f, curve, nonlinear, edatas, cache=None):
+    """R(x) = (M + dt K(nu(x))) x - f (all edges)."""
+    return (sys.M + prob.dt * _k_nu(prob, grid, x, curve, nonlinear, edatas, cache)) @ x - f
+
+
+def step_jacobian(prob, grid, sys, x, curve, nonlinear, edatas, cache=None):
+    """J(x) of the step residual (all edges, sparse)."""
+    Kg = _k_nu(prob, grid, x, curve, nonlinear, edatas, cache)
+    rows, cols, vals = [], [], []
+    for s in range(prob.n_patches):
+        if not nonlinear[s]:
+            continue
+        gidx, _, vol = edatas[s]
+        _, _, dnu, g = _element_state(x, edatas[s], curve)
+        w = 2.0 * dnu / vol
+        nl = gidx.shape[1]
+        rows.append(np.repeat(gidx[:, :, None], nl, axis=2).ravel())
+        cols.append(np.repeat(gidx[:, None, :], nl, axis=1).ravel())
+        vals.append((w[:, None, None] * g[:, :, None] * g[:, None, :]).ravel())
+    nE = grid.n_edges
+    D = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nE, nE)) if rows else sp.csr_matrix((nE, nE))
+    return (sys.M + prob.dt * (Kg + D)).tocsr()
+
+
+@dataclass
+class NewtonRun:
+    fields: list        # a^(l+1) per step, (n_edges, n_rhs)
+    iterations: list    # per step and excitation: Newton iterations taken
+    residuals: list     # per step, excitation 0: |R|_K / |f|_K before each iteration
+
+
+def run_newton(prob, curve, nonlinear, n_steps=None, tol=1e-12, maxit=40) -> NewtonRun:
+    """Implicit Euler with nu(|B|) solved per step by Newton's method from
+    the previous step's field; stops when the update is below ``tol``
+    relative to the field."""
+    grid = build_grid(prob)
+    sys = assemble_global(prob, grid)
+    topo = compute_topology(prob, grid)
+    Kk = topo.kept
+    edatas = [element_data(prob, grid, s) if nonlinear[s] else None
+              for s in range(prob.n_patches)]
+    cache = {}
+    nE = grid.n_edges
+    steps = prob.n_steps if n_steps is None else int(n_steps)
+    a = np.zeros((nE, prob.n_rhs))
+    fields, iters, res = [], [], []
+    for l in range(steps):
+        f = sys.M @ a + prob.dt * sys.jhat * prob.amp[:, l][None, :]
+        if l == 0 and sys.m0 is not None:
+            f = f + sys.m0
+        a_new = np.zeros_like(a)
+        it_l, res_l = [], []
+        for k in range(prob.n_rhs):
+            x = a[:, k].copy()
+            fk = f[:, k]
+            fn = np.linalg.norm(fk[Kk])
+            for it in range(1, maxit + 1):
+                R = step_residual(prob, grid, sys, x, fk, curve, nonlinear, edatas, cache)
+                if k == 0:
+                    res_l.append(float(np.linalg.norm(R[Kk]) / fn))
+                J = step_jacobian(prob, grid, sys, x, curve, nonlinear, edatas, cache)
+                Jg = J[Kk][:, Kk].tocsc()
+                d = np.zeros(nE)
+                d[Kk] = -GaugedSolver(Jg, grid, Kk).solve(np.ascontiguousarray(R[Kk]))
+                x = x + d
+                if np.linalg.norm(d) <= tol * np.linalg.norm(x):
+                    break
+            else:
+                raise RuntimeError(f"Newton did not converge in {maxit} iterations (step {l})")
+            a_new[:, k] = x
+            it_l.append(it)
+        a = a_new
+        fields.append(a.copy())
+        iters.append(it_l)
+        res.append(res_l)
+    return NewtonRun(fields=fields, iterations=iters, residuals=res)

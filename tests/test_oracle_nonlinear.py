@@ -7,7 +7,10 @@ against something other than the oracle's own formula:
   projection onto the spline space is exact);
 * a constant curve reduces every step to the linear oracle's;
 * the converged iterate is a fixed point: nu re-evaluated from it and the
-  step's nonlinear residual vanish to the iteration's tolerance.
+  step's nonlinear residual vanish to the iteration's tolerance;
+* Newton's method: its Jacobian matches central differences of the step
+  residual (and fails without the terms of nu's own dependence on a), and
+  it reaches the fixed-point iteration's field, superlinearly.
 A planted mistake (nu of the wrong element order) fails the energy pin."""
 import numpy as np
 import pytest
@@ -122,3 +125,54 @@ def test_fixed_point_and_a_real_nonlinearity():
 def test_brauer_curve_values():
     assert brauer_nu(0.0, 2.0, 3.0, 5.0) == 7.0
     assert np.isclose(brauer_nu(1.0, 2.0, np.log(3.0), 5.0), 11.0)
+
+
+def _strong_case():
+    prob = small(n_steps=3)
+    nu0 = float(prob.nu[0])
+    lin = solve.run(prob)
+    grid = build_grid(prob)
+    b2max = max(float(element_b2(prob, grid, 0, lin.fields[l][:, 0]).max())
+                for l in range(prob.n_steps))
+    return prob, lin, grid, (0.5 * nu0, 3.0 / b2max, 0.5 * nu0), [True, False]
+
+
+def test_newton_jacobian_matches_central_differences():
+    """The step Jacobian (including the rank-one terms of nu's dependence
+    on the element mean of |B|^2) against central differences of the step
+    residual along a random direction."""
+    from oracle.nonlinear import element_data, step_jacobian, step_residual
+    prob, lin, grid, curve, nonl = _strong_case()
+    sysg = assemble_global(prob, grid)
+    ed = [element_data(prob, grid, s) if nonl[s] else None for s in range(prob.n_patches)]
+    rng = np.random.default_rng(11)
+    x = 1.3 * lin.fields[-1][:, 0]
+    f = rng.standard_normal(grid.n_edges)
+    v = rng.standard_normal(grid.n_edges)
+    Jv = step_jacobian(prob, grid, sysg, x, curve, nonl, ed) @ v
+    eps = 1e-6 * np.linalg.norm(x) / np.linalg.norm(v)
+    fd = (step_residual(prob, grid, sysg, x + eps * v, f, curve, nonl, ed)
+          - step_residual(prob, grid, sysg, x - eps * v, f, curve, nonl, ed)) / (2 * eps)
+    assert np.linalg.norm(fd - Jv) <= 1e-5 * np.linalg.norm(Jv)
+    # without the rank-one terms (the Picard matrix M + dt K(nu(x))) the
+    # check fails: they are not negligible here
+    from oracle.nonlinear import _k_nu
+    J0 = sysg.M + prob.dt * _k_nu(prob, grid, x, curve, nonl, ed, None)
+    assert np.linalg.norm(fd - J0 @ v) > 1e-3 * np.linalg.norm(Jv)
+
+
+def test_newton_reaches_the_fixed_point_quadratically():
+    from oracle.nonlinear import run_newton
+    prob, lin, grid, curve, nonl = _strong_case()
+    nr = run_newton(prob, curve, nonl, tol=1e-13)
+    pr = run_picard(prob, curve, nonl, tol=1e-13)
+    for l in range(prob.n_steps):
+        ref = pr.fields[l]
+        assert np.linalg.norm(nr.fields[l] - ref) <= 1e-10 * np.linalg.norm(ref)
+        assert nr.iterations[l][0] <= 8
+        # superlinear decrease of the residual once it is small
+        r = [x for x in nr.residuals[l] if x > 0]
+        for a, b in zip(r, r[1:]):
+            if a < 1e-2 and b > 1e-14:
+                assert b <= a ** 1.5, (a, b)
+    assert sum(max(it) for it in pr.iterations) > sum(max(it) for it in nr.iterations)
